@@ -1,0 +1,170 @@
+"""Structured-mesh geometry for the oracle: neighbour access, finite-element
+first derivatives, physical gradients, and blending-function mesh motion.
+Test infrastructure only.
+
+Fields are arrays [nj, ni] on node (i, j), i fastest.
+
+Gradients (Sec. II.B, FE derivative d_X C = J^{-1} sum_s C_s d_xi N_s): at a
+node of the structured mesh the derivative of the quadratic Lagrange element
+centred on that node is the centred difference (C_{+1} - C_{-1}) / 2 in index
+space; on a non-periodic end row the element is one-sided and its derivative
+at the end node is (-3 C_0 + 4 C_1 - C_2) / 2.  Physical derivatives follow
+from the chain rule with the mesh metrics computed the same way (Sec. II.B,
+J^{-1} and det J).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+TOPO_PERIODIC2 = 0
+TOPO_OGRID = 1
+
+
+class Grid:
+    """Index topology of a structured mesh.
+
+    periodic_i / periodic_j: wrap in that index.  shift_i / shift_j: vectors
+    added to coordinates when a neighbour is taken across the periodic seam
+    (zero for an O-grid's azimuthal seam, the period for a doubly periodic box).
+    """
+
+    def __init__(self, ni, nj, topo, shift_i=(0.0, 0.0), shift_j=(0.0, 0.0)):
+        self.ni, self.nj, self.topo = int(ni), int(nj), int(topo)
+        self.periodic_i = True
+        self.periodic_j = topo == TOPO_PERIODIC2
+        self.shift_i = np.asarray(shift_i, dtype=np.float64)
+        self.shift_j = np.asarray(shift_j, dtype=np.float64)
+        self.jj, self.ii = np.meshgrid(np.arange(self.nj), np.arange(self.ni),
+                                       indexing="ij")
+
+    @classmethod
+    def from_mesh(cls, mesh):
+        return cls(mesh.ni, mesh.nj, mesh.topo, mesh.shift_i, mesh.shift_j)
+
+    # ---- neighbour access -------------------------------------------------
+    def neighbour(self, F, di, dj):
+        """F at (i + di, j + dj); NaN where the neighbour does not exist."""
+        ii = self.ii + di
+        jj = self.jj + dj
+        ii = ii % self.ni
+        valid = np.ones(F.shape, dtype=bool)
+        if self.periodic_j:
+            jj = jj % self.nj
+        else:
+            valid = (jj >= 0) & (jj < self.nj)
+            jj = np.clip(jj, 0, self.nj - 1)
+        out = F[jj, ii].astype(np.float64)
+        return np.where(valid, out, np.nan)
+
+    def neighbour_pos(self, X, Y, di, dj):
+        """Coordinates of node (i + di, j + dj) as seen from node (i, j), with
+        the periodic shift applied across a seam."""
+        xs = self.neighbour(X, di, dj)
+        ys = self.neighbour(Y, di, dj)
+        wrap_i = np.floor_divide(self.ii + di, self.ni)
+        xs = xs + wrap_i * self.shift_i[0]
+        ys = ys + wrap_i * self.shift_i[1]
+        if self.periodic_j:
+            wrap_j = np.floor_divide(self.jj + dj, self.nj)
+            xs = xs + wrap_j * self.shift_j[0]
+            ys = ys + wrap_j * self.shift_j[1]
+        return xs, ys
+
+    # ---- index-space derivatives -------------------------------------------
+    def d_i(self, F):
+        """dF/d(i): centred difference (i is periodic)."""
+        return 0.5 * (self.neighbour(F, 1, 0) - self.neighbour(F, -1, 0))
+
+    def d_j(self, F):
+        """dF/d(j): centred inside, one-sided 3-point on non-periodic end rows."""
+        if self.periodic_j:
+            return 0.5 * (self.neighbour(F, 0, 1) - self.neighbour(F, 0, -1))
+        out = np.empty_like(F, dtype=np.float64)
+        out[1:-1] = 0.5 * (F[2:] - F[:-2])
+        out[0] = 0.5 * (-3.0 * F[0] + 4.0 * F[1] - F[2])
+        out[-1] = 0.5 * (3.0 * F[-1] - 4.0 * F[-2] + F[-3])
+        return out
+
+    def metrics(self, x, y):
+        """(x_xi, x_eta, y_xi, y_eta) of a coordinate field, with seams shifted."""
+        xp, yp = self.neighbour_pos(x, y, 1, 0)
+        xm, ym = self.neighbour_pos(x, y, -1, 0)
+        x_xi = 0.5 * (xp - xm)
+        y_xi = 0.5 * (yp - ym)
+        if self.periodic_j:
+            xp, yp = self.neighbour_pos(x, y, 0, 1)
+            xm, ym = self.neighbour_pos(x, y, 0, -1)
+            x_eta = 0.5 * (xp - xm)
+            y_eta = 0.5 * (yp - ym)
+        else:
+            x_eta = self.d_j(x)
+            y_eta = self.d_j(y)
+        return x_xi, x_eta, y_xi, y_eta
+
+    def grad(self, C, x, y):
+        """Physical gradient (dC/dx, dC/dy) on the mesh with coordinates (x, y):
+
+            dC/dx = ( y_eta C_xi - y_xi C_eta) / det J
+            dC/dy = (-x_eta C_xi + x_xi C_eta) / det J
+            det J = x_xi y_eta - y_xi x_eta           (Sec. II.B)
+        """
+        x_xi, x_eta, y_xi, y_eta = self.metrics(x, y)
+        det = x_xi * y_eta - y_xi * x_eta
+        C_xi = self.d_i(C)
+        C_eta = self.d_j(C)
+        return ((y_eta * C_xi - y_xi * C_eta) / det,
+                (-x_eta * C_xi + x_xi * C_eta) / det)
+
+
+# ---- blending-function mesh motion (Sec. II.D) ------------------------------
+
+def r5(s):
+    """Fifth-order blending polynomial r_5(s) = 10 s^3 - 15 s^4 + 6 s^5."""
+    return 10.0 * s ** 3 - 15.0 * s ** 4 + 6.0 * s ** 5
+
+
+def blend_factor(X, Y, body):
+    """r_blend: 0 inside the rigid radius, 1 beyond the blend radius, r_5 of
+    the normalised radial position in between (Sec. II.D).  Radial distance is
+    measured from the body's blending centre in the undeformed frame."""
+    d = np.hypot(X - body.center[0], Y - body.center[1])
+    s = (d - body.r_rigid) / (body.r_blend - body.r_rigid)
+    return np.where(s < 0.0, 0.0, np.where(s > 1.0, 1.0, r5(np.clip(s, 0.0, 1.0))))
+
+
+def rigid_map(X, Y, body, h, alpha):
+    """G'_x(X): rigid motion of the body, translation h along y and a
+    counter-clockwise rotation alpha about the elastic axis."""
+    ex, ey = body.ea
+    c, s = np.cos(alpha), np.sin(alpha)
+    dx = X - ex
+    dy = Y - ey
+    return ex + c * dx - s * dy, ey + h + s * dx + c * dy
+
+
+def rigid_displacement(X, Y, body, h, alpha):
+    """G'_x(X) - X = (0, h) + (R(alpha) - I)(X - X_EA), evaluated without
+    forming G' so that a body at rest gives exactly zero."""
+    ex, ey = body.ea
+    c, s = np.cos(alpha), np.sin(alpha)
+    dx = X - ex
+    dy = Y - ey
+    return (c - 1.0) * dx - s * dy, h + s * dx + (c - 1.0) * dy
+
+
+def deformed_positions(X, Y, bodies, states):
+    """x = r_blend X + (1 - r_blend) G'_x(X, t) (Sec. II.D), evaluated as
+    x = X + (1 - r_blend)(G'_x(X) - X), which is the same expression.
+
+    ``states`` holds (h, alpha, hdot, alphadot) per body.  A single body per
+    mesh is supported; with no body x = X.
+    """
+    if not bodies:
+        return X.copy(), Y.copy()
+    assert len(bodies) == 1, "one moving body per mesh"
+    body = bodies[0]
+    h, alpha = states[0][0], states[0][1]
+    r = blend_factor(X, Y, body)
+    ux, uy = rigid_displacement(X, Y, body, h, alpha)
+    return X + (1.0 - r) * ux, Y + (1.0 - r) * uy

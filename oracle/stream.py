@@ -1,0 +1,210 @@
+"""ALE semi-Lagrangian streaming in float64 (paper Sec. II.A and II.B).
+Test infrastructure only.
+
+For every node and every moving velocity c_i:
+
+1. transformed velocity  c^_i = g^{-1} (c_i - V_G), with g = dx/dX the
+   Jacobian of the ALE map.  Reading of the printed "g^{-T} c_i - V_G": by the
+   chain rule the advection velocity in the undeformed frame is
+   (dx/dX)^{-1}(c - V_G) (the printed g^{-1} matrix is the inverse transpose of
+   dx_k/dX_l, and V_G is a physical velocity).  g is taken at t^{n+1}:
+   g = (dx^{n+1}/dxi)(dX/dxi)^{-1} from FE derivatives, V_G = (x^{n+1}-x^n)/dt.
+2. departure point  X_dp = X - dt c^_i  (Sec. II.B, Eq. for X_dp),
+3. its reference coordinates from the first-order (bilinear, 4-node) element
+   map, solved by Newton among the cells that touch the node
+   (Sec. II.B, Eq. for X_dp = sum_s X_s N'_s),
+4. the population at the node is the second-order (9-node) Lagrange
+   interpolant of the post-collision populations at the departure point
+   (Sec. II.B, Eq. for f_i(X, t)).
+
+Reading for the structured mesh: the 9-node element is the 3 x 3 block of
+nodes centred on the arriving node (shifted inward by one row on a
+non-periodic end row), with tensor-product quadratic Lagrange shape functions
+of the offsets of xi_dp from the block centre.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .lattice import CX, CY, Q
+
+
+class CFLViolation(ValueError):
+    """A departure point lies outside the cells that touch its node."""
+
+
+# candidate cells touching a node, by the index offset of their lower-left corner
+CANDIDATE_CELLS = ((-1, -1), (0, -1), (-1, 0), (0, 0))
+CELL_TOL = 1e-12
+
+
+def bilinear_inverse(P00, P10, P01, P11, Px, Py, iters=60):
+    """Solve X(s, t) = P for the bilinear map of one cell (Newton, float64).
+
+    X(s, t) = P00 (1-s)(1-t) + P10 s (1-t) + P01 (1-s) t + P11 s t, with each
+    corner a pair (x, y) of arrays.  Returns (s, t, residual).
+    """
+    s = np.full(np.shape(Px), 0.5)
+    t = np.full(np.shape(Px), 0.5)
+    for _ in range(iters):
+        Xs = P00[0] * (1 - s) * (1 - t) + P10[0] * s * (1 - t) + P01[0] * (1 - s) * t + P11[0] * s * t
+        Ys = P00[1] * (1 - s) * (1 - t) + P10[1] * s * (1 - t) + P01[1] * (1 - s) * t + P11[1] * s * t
+        rx = Xs - Px
+        ry = Ys - Py
+        a_x = (P10[0] - P00[0]) * (1 - t) + (P11[0] - P01[0]) * t
+        a_y = (P10[1] - P00[1]) * (1 - t) + (P11[1] - P01[1]) * t
+        b_x = (P01[0] - P00[0]) * (1 - s) + (P11[0] - P10[0]) * s
+        b_y = (P01[1] - P00[1]) * (1 - s) + (P11[1] - P10[1]) * s
+        det = a_x * b_y - a_y * b_x
+        ds = (b_y * rx - b_x * ry) / det
+        dtt = (-a_y * rx + a_x * ry) / det
+        with np.errstate(invalid="ignore"):
+            s = s - ds
+            t = t - dtt
+            if np.all(~np.isfinite(ds) | (np.abs(ds) + np.abs(dtt) < 1e-15)):
+                break
+    Xs = P00[0] * (1 - s) * (1 - t) + P10[0] * s * (1 - t) + P01[0] * (1 - s) * t + P11[0] * s * t
+    Ys = P00[1] * (1 - s) * (1 - t) + P10[1] * s * (1 - t) + P01[1] * (1 - s) * t + P11[1] * s * t
+    return s, t, np.hypot(Xs - Px, Ys - Py)
+
+
+def transformed_velocities(grid, X, Y, x1, y1, VGx, VGy):
+    """c^_i = g^{-1}(c_i - V_G) for i = 0..8, with g = (dx^{n+1}/dxi)(dX/dxi)^{-1}.
+
+    Returns a list of (c^x, c^y) pairs, one per velocity.
+    """
+    A = grid.metrics(x1, y1)            # x_xi, x_eta, y_xi, y_eta at t^{n+1}
+    B = grid.metrics(X, Y)              # the same for the undeformed mesh
+    # g = A B^{-1}
+    detB = B[0] * B[3] - B[2] * B[1]
+    Binv = (B[3] / detB, -B[1] / detB, -B[2] / detB, B[0] / detB)  # (11, 12, 21, 22)
+    g11 = A[0] * Binv[0] + A[1] * Binv[2]
+    g12 = A[0] * Binv[1] + A[1] * Binv[3]
+    g21 = A[2] * Binv[0] + A[3] * Binv[2]
+    g22 = A[2] * Binv[1] + A[3] * Binv[3]
+    detg = g11 * g22 - g12 * g21
+    out = []
+    for i in range(Q):
+        wx = CX[i] - VGx
+        wy = CY[i] - VGy
+        out.append(((g22 * wx - g12 * wy) / detg, (-g21 * wx + g11 * wy) / detg))
+    return out
+
+
+def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
+    """Reference coordinates of X_dp = X - dt c^ relative to each node.
+
+    Returns (a, b, missing): a, b are the index-space offsets of xi_dp from the
+    node; ``missing`` marks departure points that leave the mesh through the
+    wall row j = 0 (only when ``wall_row``).  Raises CFLViolation if a
+    departure point lies in none of the four cells touching its node.
+    """
+    Pdx = -dt * chx                      # X_dp - X, relative to the node
+    Pdy = -dt * chy
+    a = np.full(X.shape, np.nan)
+    b = np.full(X.shape, np.nan)
+    found = np.zeros(X.shape, dtype=bool)
+    missing = np.zeros(X.shape, dtype=bool)
+    for (di0, dj0) in CANDIDATE_CELLS:
+        corners = []
+        for (ci, cj) in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            px, py = grid.neighbour_pos(X, Y, di0 + ci, dj0 + cj)
+            corners.append((px - X, py - Y))
+        with np.errstate(invalid="ignore", divide="ignore"):
+            s, t, _ = bilinear_inverse(*corners, Pdx, Pdy)
+        inside = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL)
+                  & (t >= -CELL_TOL) & (t <= 1 + CELL_TOL))
+        take = inside & ~found
+        a = np.where(take, di0 + s, a)
+        b = np.where(take, dj0 + t, b)
+        found |= take
+        if wall_row and dj0 == 0:
+            # a wall-row departure point below the first cell row lies in the body
+            below = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL) & (t < -CELL_TOL)
+                     & (grid.jj == 0))
+            missing |= below & ~found
+    missing &= ~found
+    bad = ~found & ~missing
+    if np.any(bad):
+        k = int(np.flatnonzero(bad.ravel())[0])
+        raise CFLViolation(f"departure point outside the node's cells at flat node {k}")
+    return a, b, missing
+
+
+def lagrange_1d(p, a):
+    """Quadratic Lagrange basis on the nodes {-1, 0, +1}: L_p(a) =
+    prod_{m != p} (a - m) / (p - m)."""
+    out = np.ones_like(a)
+    for m in (-1, 0, 1):
+        if m != p:
+            out = out * (a - m) / (p - m)
+    return out
+
+
+def stencil_centre_rows(grid):
+    """Row index of the 3x3 element centre for every node: the node's own row,
+    moved inward by one on a non-periodic end row."""
+    jc = grid.jj.copy()
+    if not grid.periodic_j:
+        jc[0] = 1
+        jc[-1] = grid.nj - 2
+    return jc
+
+
+def interpolate(grid, fstar_i, a, b):
+    """f_i(node) = sum_s N_s(xi_dp) f*_i(xi_s) over the 3 x 3 element
+    (Sec. II.B, Eq. for f_i(X, t))."""
+    jc = stencil_centre_rows(grid)
+    bc = b + (grid.jj - jc)
+    out = np.zeros(a.shape)
+    for p in (-1, 0, 1):
+        La = lagrange_1d(p, a)
+        for q in (-1, 0, 1):
+            Lb = lagrange_1d(q, bc)
+            jj = jc + q
+            if grid.periodic_j:
+                jj = jj % grid.nj
+            ii = (grid.ii + p) % grid.ni
+            out = out + La * Lb * fstar_i[jj, ii]
+    return out
+
+
+def stream(grid, X, Y, x1, y1, VGx, VGy, dt, fpost, gpost, skip_rows=()):
+    """Interpolating ALE streaming of both population sets.
+
+    Returns (f_new, g_new, missing[9]); rows in ``skip_rows`` (the far-field
+    row, whose populations the boundary condition replaces) are left NaN,
+    as are populations flagged missing at the wall.
+    """
+    chat = transformed_velocities(grid, X, Y, x1, y1, VGx, VGy)
+    f_new = np.full(fpost.shape, np.nan)
+    g_new = np.full(gpost.shape, np.nan)
+    missing = np.zeros(fpost.shape, dtype=bool)
+    active = np.ones(X.shape, dtype=bool)
+    for r in skip_rows:
+        active[r] = False
+    wall = not grid.periodic_j
+    for i in range(Q):
+        if i == 0:
+            f_new[0] = fpost[0]
+            g_new[0] = gpost[0]
+            continue
+        chx, chy = chat[i]
+        a, b, miss = _offsets_on_active(grid, X, Y, chx, chy, dt, active, wall)
+        fi = interpolate(grid, fpost[i], np.where(np.isnan(a), 0.0, a),
+                         np.where(np.isnan(b), 0.0, b))
+        gi = interpolate(grid, gpost[i], np.where(np.isnan(a), 0.0, a),
+                         np.where(np.isnan(b), 0.0, b))
+        keep = active & ~miss
+        f_new[i] = np.where(keep, fi, np.nan)
+        g_new[i] = np.where(keep, gi, np.nan)
+        missing[i] = miss & active
+    return f_new, g_new, missing
+
+
+def _offsets_on_active(grid, X, Y, chx, chy, dt, active, wall):
+    # inactive rows get a zero offset (never used) so they cannot raise
+    chx = np.where(active, chx, 0.0)
+    chy = np.where(active, chy, 0.0)
+    return departure_offsets(grid, X, Y, chx, chy, dt, wall_row=wall)
