@@ -1,0 +1,213 @@
+"""Throughput of the coupled ALE lattice Boltzmann FSI step on one MI355X.
+
+One step = the whole coupled update of one instance: collision + ALE
+semi-Lagrangian streaming of both population sets at every node, far-field
+and Grad wall boundaries, the traction reduction and the body update.
+
+Default workload: cylinder in compressible flow (Ma 0.5, Re 1000) on a
+2048 (radial) x 4096 (azimuthal) O-grid, 8,388,608 nodes, with blending
+mesh motion from a prescribed heave of amplitude 0.2 D, FP32 populations.
+Metric: MLUPS, one lattice update = both f and g (18 populations) at one node.
+
+Prints ONE JSON line.  Inputs are synthetic and resident in HBM before the
+timed region starts.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "MLUPS (f+g, D2Q9) and % HBM roofline; batched/FP16 vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2107_01370_amd", "csrc", "fsilbm_kernels.hip")
+
+
+def algorithmic_bytes_per_node(storage: int) -> int:
+    """Populations read once and written once (18 values each way) plus the
+    FP64 node coordinates (16 B) needed to recompute the departure points."""
+    per_pop = 2 if storage == 1 else 4
+    return 2 * 18 * per_pop + 16
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, storage: int, n_nodes: int):
+    """HBM bytes per launch of the collision-streaming kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_collide_stream_{workload}_"
+                                          f"{'fp16' if storage else 'fp32'}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def workload_case(name: str, storage: int):
+    if name == "cylinder_heave_2048x4096":
+        return synth.large_heave_case(storage=storage)
+    if name == "cylinder_viv_256x512":
+        c = synth.cylinder_viv_case()
+        c.fluid.storage = storage
+        return c
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_gpu(case, steps: int, warmup: int, kernel_reps: int = 20):
+    import torch
+
+    from paper_2107_01370_amd.fsilbm import Simulation
+
+    sim = Simulation(case.mesh, case.fluid, case.bodies, device="cuda:0")
+    sim.init_equilibrium(case.rho, case.ux, case.uy, case.T)
+    sim.step(warmup)
+    sim.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(sim.stream)
+    sim.step(steps)
+    stop.record(sim.stream)
+    stop.synchronize()
+    sim.synchronize()                 # also checks the device error word
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    # per-kernel mean launch durations, HIP events on the simulation stream
+    kms = sim.time_kernels(kernel_reps)
+    rho, ux, uy, T = sim.macro()
+    finite = bool(np.all(np.isfinite(rho)) and np.all(np.isfinite(T)))
+    sim.close()
+    return total_ms, kms, finite
+
+
+def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
+    """Oracle (plain FP64 NumPy) timed on a strip of the same workload: the
+    first `rows` radial rows of the O-grid (wall included) with the same
+    physics, stepped until about `target_s` seconds of CPU work."""
+    from dataclasses import replace
+
+    from oracle.solver import OracleSolver
+
+    m = case.mesh
+    strip = replace(m, nj=rows, X=m.X[:rows].copy(), Y=m.Y[:rows].copy())
+    ora = OracleSolver(strip, case.fluid, case.bodies)
+    ora.step()                         # warm-up (first-call overheads)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        ora.step()
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or n >= 50:
+            break
+    nodes = strip.ni * strip.nj
+    threads = os.environ.get("OMP_NUM_THREADS", "1")
+    return {
+        "value": nodes * n / el / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n} steps of a {strip.ni}x{rows} strip (rows 0..{rows - 1}, wall included) "
+                  f"of the same mesh and physics, {el:.1f} s, single-threaded NumPy "
+                  f"(OMP_NUM_THREADS={threads}), host {platform.processor() or platform.machine()}, "
+                  f"os.cpu_count()={os.cpu_count()}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cylinder_heave_2048x4096")
+    ap.add_argument("--storage", choices=("fp32", "fp16"), default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    storage = 1 if args.storage == "fp16" else 0
+    case = workload_case(args.workload, storage)
+    N = case.mesh.n_nodes
+    total_ms, kms, finite = time_gpu(case, args.steps, args.warmup)
+    ms_per_step = total_ms / args.steps
+    mlups = N * args.steps / (total_ms * 1e-3) / 1e6
+    bpn = algorithmic_bytes_per_node(storage)
+    k1_ms = float(kms[0])
+    achieved = bpn * N / (k1_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, storage, N)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: O-grid cylinder, Ma 0.5, Re 1000, blended mesh "
+                        f"with prescribed heave 0.2 D, {args.storage} population storage",
+            "nodes": N,
+            "storage": args.storage,
+            "kernel_ms": {"collide_stream": round(k1_ms, 5),
+                          "wall_targets_farfield": round(float(kms[1]), 5),
+                          "wall_grad_traction": round(float(kms[2]), 5),
+                          "body": round(float(kms[3]), 5)},
+            "finite_state": finite,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_collide_stream",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_node": bpn,
+        },
+    }
+    if not args.no_variants and args.workload == "cylinder_heave_2048x4096" and storage == 0:
+        case16 = workload_case(args.workload, 1)
+        t16, k16, fin16 = time_gpu(case16, args.steps, args.warmup)
+        out["variants"] = [{
+            "storage": "fp16_shifted",
+            "value": round(N * args.steps / (t16 * 1e-3) / 1e6, 1),
+            "unit": "MLUPS",
+            "ms_per_step": round(t16 / args.steps, 5),
+            "collide_stream_ms": round(float(k16[0]), 5),
+            "achieved_GBs": round(algorithmic_bytes_per_node(1) * N / (float(k16[0]) * 1e-3) / 1e9, 1),
+            "finite_state": fin16,
+        }]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

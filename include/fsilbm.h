@@ -1,0 +1,195 @@
+/*
+ * fsilbm.h -- C ABI of the MI355X (gfx950) library for the two-population
+ * compressible lattice Boltzmann fluid-structure step of Bhadauria, Dorschner
+ * and Karlin (arXiv 2107.01370).
+ *
+ * What one step computes (paper Sec. II-IV; staggered weak coupling, Sec. III):
+ *   1. surface force F^n and moment M_EA^n from the populations at t^n
+ *      (sigma = -p I - (1 - omega/2) P^(1), Sec. III);
+ *   2. rigid-body state s^{n+1}: RK4 of the 1DOF / 2DOF spring-mass ODEs with
+ *      the load frozen (Sec. IV), or a prescribed motion;
+ *   3. blended mesh x^{n+1} = r X + (1 - r) G'(X) (Sec. II.D) and its velocity
+ *      V_G = (x^{n+1} - x^n) / dt;
+ *   4. collision of f and g with the momentum correction phi and the energy
+ *      correction Psi (Sec. II.C, kinetic equations);
+ *   5. ALE semi-Lagrangian streaming: departure points X - dt c^ with
+ *      c^ = (dx/dX)^{-1}(c - V_G), bilinear inverse map, 9-node quadratic
+ *      Lagrange interpolation (Sec. II.A-B);
+ *   6. Grad wall populations and far-field equilibria (Sec. III.A).
+ *
+ * Conventions
+ *   - Lattice units, gas constant R = 1, C_v = 1/(gamma - 1).
+ *   - Node (i, j), i fastest; host arrays are row-major [nj][ni].
+ *   - Velocity order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1)
+ *     6:(-1,1) 7:(-1,-1) 8:(1,-1); population arrays are [9][nj][ni].
+ *   - Every call returns fsi_status (0 = OK, < 0 = error); nothing throws
+ *     across the ABI.  On error, fsi_last_error() holds a message.
+ *
+ * Ownership
+ *   - Host inputs are copied during the call that receives them.
+ *   - Device memory is owned by the caller: fsi_workspace_bytes() says how
+ *     much, fsi_bind_workspace() lends it to the context.  It must stay
+ *     allocated, and untouched by the caller, until fsi_destroy().
+ *   - Host outputs go to caller-owned buffers of the stated sizes.
+ *   - All device work is enqueued on the HIP stream given at creation.
+ *     fsi_step() is asynchronous; a sticky device error word is checked and
+ *     reported by the next synchronising call (fsi_synchronize, fsi_get_*,
+ *     fsi_dump_macro, fsi_save).
+ *
+ * Threading: a context may be used from one host thread at a time.
+ */
+#ifndef FSILBM_H
+#define FSILBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSI_OK = 0,
+    FSI_E_ARG = -1,     /* invalid argument or size */
+    FSI_E_MESH = -2,    /* det(dX/dxi) <= 0, bad topology, wall cell thinner than dt */
+    FSI_E_CFL = -3,     /* a departure point left the cells around its node */
+    FSI_E_STATE = -4,   /* rho <= 0, T <= 0, T + u_a^2 >= 1, or NaN */
+    FSI_E_HIP = -5,     /* HIP runtime error */
+    FSI_E_NOMEM = -6,   /* host allocation failed */
+    FSI_E_UNBOUND = -7  /* workspace not bound / state not initialised */
+} fsi_status;
+
+typedef struct fsi_ctx fsi_ctx;
+
+/* Storage precision of the populations (arithmetic is FP32 in both). */
+enum { FSI_STORE_FP32 = 0, FSI_STORE_FP16_SHIFTED = 1 };
+
+/* Fluid parameters (Sec. II.C): mu = (1/omega - 1/2) p dt with constant mu,
+ * Pr = (1/omega - 1/2)/(1/omega_1 - 1/2); free-stream state for the far field. */
+typedef struct {
+    double gamma;       /* adiabatic exponent (> 1) */
+    double Pr;          /* Prandtl number */
+    double mu;          /* dynamic viscosity (lattice units) */
+    double rho_inf;     /* free-stream density */
+    double T_inf;       /* free-stream temperature */
+    double u_inf[2];    /* free-stream velocity */
+    double dt;          /* time step */
+    int storage;        /* FSI_STORE_FP32 or FSI_STORE_FP16_SHIFTED */
+} fsi_fluid_params;
+
+/* Mesh topologies.
+ *   PERIODIC2: periodic in i and j; crossing a seam adds shift_i / shift_j to
+ *              the coordinates.  No wall, no far field.
+ *   OGRID:     periodic in i (no shift); row j = 0 is the body wall, row
+ *              j = nj - 1 the far field.  dX/dxi must have a positive
+ *              determinant (i runs clockwise when j points outward).        */
+typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1 } fsi_topo;
+
+typedef struct {
+    int ni, nj;             /* nodes in i (fast) and j; ni >= 8, nj >= 8 */
+    int topo;               /* fsi_topo */
+    const double *X;        /* host, [nj][ni][2] undeformed coordinates, FP64; copied */
+    double shift_i[2];      /* PERIODIC2 only */
+    double shift_j[2];      /* PERIODIC2 only */
+} fsi_mesh_desc;
+
+/* Rigid-body degrees of freedom (Sec. IV). */
+enum { FSI_DOF_PRESCRIBED = 0, FSI_DOF_HEAVE = 1, FSI_DOF_PITCH_PLUNGE = 2,
+       FSI_DOF_FIXED = 3 };
+
+/* One body: spring-mass parameters (m h'' + S_a a'' + k_h h = F_y,
+ * S_a h'' + I_a a'' + k_a a = M_EA), the blending region of influence
+ * (rigid inside r_rigid, r_5 blend out to r_blend, Sec. II.D, radial from
+ * `center`), the elastic axis `ea` (rotation centre), the initial state and,
+ * for FSI_DOF_PRESCRIBED, h(t) = heave_amp sin(2 pi heave_freq t),
+ * alpha(t) = pitch_amp sin(2 pi pitch_freq t).  h is along +y, alpha is
+ * counter-clockwise. */
+typedef struct {
+    int dof;
+    double m, S_a, I_a, k_h, k_a;
+    double center[2], ea[2];
+    double r_rigid, r_blend;
+    double h0, a0, hd0, ad0;
+    double heave_amp, heave_freq, pitch_amp, pitch_freq;
+} fsi_body_desc;
+
+/* Create a context for one structured mesh with at most one moving body
+ * (nbodies = 0 or 1).  `hip_stream` is a hipStream_t (NULL = default stream).
+ * Validates the mesh (FSI_E_MESH) and precomputes the static boundary
+ * geometry on the host.  No device memory is allocated. */
+fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
+                      const fsi_body_desc *bodies, int nbodies, void *hip_stream,
+                      fsi_ctx **out);
+
+/* Bytes of device workspace the context needs (populations ping-pong,
+ * coordinates, boundary and body buffers). */
+fsi_status fsi_workspace_bytes(const fsi_ctx *ctx, size_t *bytes);
+
+/* Lend `bytes` of device memory at `dev_ptr` (256-byte aligned) to the
+ * context and upload the static data.  Synchronises the stream. */
+fsi_status fsi_bind_workspace(fsi_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Initial populations = equilibria (f^eq, g^eq with Psi) of the given host
+ * fields [nj][ni] (NULL = free-stream values), body state from the body
+ * description, step counter 0; computes the initial load F^0 and s^1.
+ * Synchronises. */
+fsi_status fsi_init_equilibrium(fsi_ctx *ctx, const double *rho, const double *ux,
+                                const double *uy, const double *T);
+
+/* Enqueue `nsteps` coupled steps (replays of a captured HIP graph of one
+ * step).  Asynchronous. */
+fsi_status fsi_step(fsi_ctx *ctx, int nsteps);
+
+/* Wait for the stream and report the sticky device error word
+ * (FSI_E_CFL, FSI_E_STATE, FSI_E_MESH). */
+fsi_status fsi_synchronize(fsi_ctx *ctx);
+
+/* Number of completed steps (synchronises). */
+fsi_status fsi_get_step(fsi_ctx *ctx, int64_t *step);
+
+/* History records of body `body` for steps first .. first+count-1, each
+ * {n, F_x, F_y, M_EA, h, alpha} at the start of step n (F from f^n).  The
+ * library keeps the last `fsi_history_capacity()` records.  Synchronises. */
+fsi_status fsi_get_forces(fsi_ctx *ctx, int body, int64_t first, int count, double *out);
+int64_t fsi_history_capacity(void);
+
+/* Current body state {h, alpha, hdot, alphadot}.  Synchronises. */
+fsi_status fsi_get_body_state(fsi_ctx *ctx, int body, double out[4]);
+
+/* Macroscopic fields of the current populations, host [nj][ni] each
+ * (any pointer may be NULL).  Synchronises. */
+fsi_status fsi_dump_macro(fsi_ctx *ctx, double *rho, double *ux, double *uy, double *T);
+
+/* Current populations as FP32 host arrays [9][nj][ni] (decoded from the
+ * storage precision).  Synchronises. */
+fsi_status fsi_get_populations(fsi_ctx *ctx, float *f, float *g);
+
+/* Overwrite the current populations from FP32 host arrays [9][nj][ni]
+ * (encoded to the storage precision).  Does not change the body state. */
+fsi_status fsi_set_populations(fsi_ctx *ctx, const float *f, const float *g);
+
+/* Checkpoint: populations (storage precision), body states, step counter and
+ * parameters.  fsi_state_bytes() gives the buffer size. */
+fsi_status fsi_state_bytes(const fsi_ctx *ctx, size_t *bytes);
+fsi_status fsi_save(fsi_ctx *ctx, void *host_buf, size_t bytes);
+fsi_status fsi_load(fsi_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Time each kernel of one coupled step with HIP events on the context's
+ * stream: `reps` back-to-back launches of the collision-streaming kernel, of
+ * the two wall kernels and of the body kernel, at the current step (every
+ * launch recomputes the same values, so the state is unchanged).  out_ms[4]
+ * receives the mean milliseconds per launch, in that order (0 for kernels the
+ * topology does not use).  Synchronises. */
+fsi_status fsi_time_kernels(fsi_ctx *ctx, int reps, double out_ms[4]);
+
+/* Message of the last error on this context (static storage of the context). */
+const char *fsi_last_error(const fsi_ctx *ctx);
+
+/* Release the context (not the caller's workspace). */
+void fsi_destroy(fsi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSILBM_H */

@@ -1,0 +1,739 @@
+// Host runtime of the C ABI declared in include/fsilbm.h: validation, static
+// boundary geometry, workspace layout, graph capture of one coupled step, and
+// host <-> device transfers.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/fsilbm.h"
+#include "fsilbm_internal.h"
+
+using fsi::Inst;
+
+struct fsi_ctx {
+    fsi_fluid_params fluid{};
+    int ni = 0, nj = 0, topo = 0;
+    double shift_i[2] = {0, 0}, shift_j[2] = {0, 0};
+    std::vector<double> X;          // [nj][ni][2]
+    fsi_body_desc body{};
+    bool has_body = false;
+    hipStream_t stream = nullptr;
+    Inst inst{};
+    // workspace layout (byte offsets)
+    size_t off_pop[2]{}, off_X = 0, off_mask = 0, off_tgt = 0, off_B = 0, off_inflow = 0,
+           off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
+           off_wk1 = 0, off_wbnd = 0, off_wwall = 0, total = 0;
+    char *ws = nullptr;
+    std::vector<float2> wallB;
+    std::vector<uint8_t> inflow;
+    std::vector<int2> wk1, wbnd, wwall;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t host_step = 0;
+    bool initialized = false;
+    std::string err;
+};
+
+namespace {
+
+constexpr int64_t kMagic = 0x46534c424d303031LL;   // checkpoint tag
+
+fsi_status fail(fsi_ctx *c, fsi_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+fsi_status hip_fail(fsi_ctx *c, hipError_t e, const char *what) {
+    return fail(c, FSI_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                   \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
+    } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+int wrapi(int a, int n) { return ((a % n) + n) % n; }
+
+// coordinate of node (i, j) seen from an unwrapped index, with periodic shifts
+void coord(const fsi_ctx *c, int i, int j, double &x, double &y) {
+    const int wi = (int)floor((double)i / c->ni), wj = (int)floor((double)j / c->nj);
+    const int ii = i - wi * c->ni;
+    const int jj = c->topo == FSI_TOPO_PERIODIC2 ? j - wj * c->nj : j;
+    x = c->X[2 * ((size_t)jj * c->ni + ii)];
+    y = c->X[2 * ((size_t)jj * c->ni + ii) + 1];
+    x += wi * c->shift_i[0];
+    y += wi * c->shift_i[1];
+    if (c->topo == FSI_TOPO_PERIODIC2) {
+        x += wj * c->shift_j[0];
+        y += wj * c->shift_j[1];
+    }
+}
+
+// bilinear inverse of cell with corners (relative) c00, c10, c01, c11 -> (s, t)
+bool bilinear_inverse(const double c[4][2], double px, double py, double &s, double &t) {
+    s = 0.5;
+    t = 0.5;
+    for (int it = 0; it < 60; ++it) {
+        const double ax = c[1][0] - c[0][0], ay = c[1][1] - c[0][1];
+        const double bx = c[2][0] - c[0][0], by = c[2][1] - c[0][1];
+        const double ex = c[3][0] - c[1][0] - c[2][0] + c[0][0], ey = c[3][1] - c[1][1] - c[2][1] + c[0][1];
+        const double rx = c[0][0] + ax * s + bx * t + ex * s * t - px;
+        const double ry = c[0][1] + ay * s + by * t + ey * s * t - py;
+        const double jsx = ax + ex * t, jsy = ay + ey * t, jtx = bx + ex * s, jty = by + ey * s;
+        const double det = jsx * jty - jsy * jtx;
+        if (!(fabs(det) > 0)) return false;
+        const double ds = (jty * rx - jtx * ry) / det, dt = (-jsy * rx + jsx * ry) / det;
+        s -= ds;
+        t -= dt;
+        if (fabs(ds) + fabs(dt) < 1e-15) break;
+    }
+    return isfinite(s) && isfinite(t);
+}
+
+double blend_r(const fsi_body_desc &b, double X, double Y) {
+    const double d = hypot(X - b.center[0], Y - b.center[1]);
+    const double s = (d - b.r_rigid) / (b.r_blend - b.r_rigid);
+    if (s <= 0) return 0;
+    if (s >= 1) return 1;
+    return s * s * s * (10 + s * (-15 + 6 * s));
+}
+
+fsi::BodySlot slot_of(double h, double a, double hd, double ad) {
+    fsi::BodySlot s{};
+    s.h = h; s.a = a; s.hd = hd; s.ad = ad;
+    const double sh = sin(0.5 * a);
+    s.cm1 = -2.0 * sh * sh;
+    s.sa = sin(a);
+    return s;
+}
+
+fsi_status validate_and_precompute(fsi_ctx *c) {
+    const int ni = c->ni, nj = c->nj;
+    // det(dX/dxi) > 0 everywhere (FE metric: centred, one-sided on O-grid end rows)
+    for (int j = 0; j < nj; ++j) {
+        for (int i = 0; i < ni; ++i) {
+            double xp, yp, xm, ym, x0, y0, x1, y1, x2, y2;
+            coord(c, i + 1, j, xp, yp);
+            coord(c, i - 1, j, xm, ym);
+            double xe, ye;
+            if (c->topo == FSI_TOPO_OGRID && (j == 0 || j == nj - 1)) {
+                const int s = j == 0 ? 1 : -1;
+                coord(c, i, j, x0, y0);
+                coord(c, i, j + s, x1, y1);
+                coord(c, i, j + 2 * s, x2, y2);
+                xe = s * (2.0 * (x1 - x0) - 0.5 * (x2 - x0));
+                ye = s * (2.0 * (y1 - y0) - 0.5 * (y2 - y0));
+            } else {
+                coord(c, i, j + 1, x1, y1);
+                coord(c, i, j - 1, x0, y0);
+                xe = 0.5 * (x1 - x0);
+                ye = 0.5 * (y1 - y0);
+            }
+            const double det = 0.5 * (xp - xm) * ye - 0.5 * (yp - ym) * xe;
+            if (!(det > 0))
+                return fail(c, FSI_E_MESH, "det(dX/dxi) <= 0 at node (" + std::to_string(i) + ", " +
+                                               std::to_string(j) + "): mesh must be right-handed");
+        }
+    }
+    if (c->has_body) {
+        const fsi_body_desc &b = c->body;
+        if (!(b.r_blend > b.r_rigid) || !(b.r_rigid >= 0))
+            return fail(c, FSI_E_ARG, "body needs 0 <= r_rigid < r_blend");
+        if (b.dof == FSI_DOF_HEAVE && !(b.m > 0)) return fail(c, FSI_E_ARG, "heave body needs m > 0");
+        if (b.dof == FSI_DOF_PITCH_PLUNGE && !(b.m * b.I_a - b.S_a * b.S_a > 0))
+            return fail(c, FSI_E_ARG, "pitch-plunge body needs a positive-definite mass matrix");
+        if (c->topo == FSI_TOPO_PERIODIC2) {
+            // the blended region must not reach the periodic seams
+            for (int j = 0; j < nj; ++j)
+                for (int i = 0; i < ni; ++i) {
+                    if (i > 3 && i < ni - 4 && j > 3 && j < nj - 4) continue;
+                    const double *p = &c->X[2 * ((size_t)j * ni + i)];
+                    if (blend_r(b, p[0], p[1]) < 1.0)
+                        return fail(c, FSI_E_MESH, "blending region reaches a periodic seam");
+                }
+        }
+    }
+    if (c->topo == FSI_TOPO_OGRID) {
+        const double dt = c->fluid.dt;
+        c->wallB.assign(ni, make_float2(0, 0));
+        c->inflow.assign(ni, 0);
+        for (int i = 0; i < ni; ++i) {
+            double xp, yp, xm, ym, x0, y0;
+            coord(c, i + 1, 0, xp, yp);
+            coord(c, i - 1, 0, xm, ym);
+            coord(c, i, 0, x0, y0);
+            const double tx = xp - xm, ty = yp - ym, tn = hypot(tx, ty);
+            const double bx = -ty / tn * dt, by = tx / tn * dt;   // B - X_A
+            bool found = false;
+            for (int di0 = -1; di0 <= 0 && !found; ++di0) {
+                double cc[4][2];
+                const int off[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+                for (int k = 0; k < 4; ++k) {
+                    double x, y;
+                    coord(c, i + di0 + off[k][0], off[k][1], x, y);
+                    cc[k][0] = x - x0;
+                    cc[k][1] = y - y0;
+                }
+                double s, t;
+                if (bilinear_inverse(cc, bx, by, s, t) && s >= -1e-12 && s <= 1 + 1e-12 &&
+                    t >= -1e-12 && t <= 1 + 1e-12) {
+                    c->wallB[i] = make_float2((float)(di0 + s), (float)t);
+                    found = true;
+                }
+            }
+            if (!found)
+                return fail(c, FSI_E_MESH, "wall point B (distance dt along the normal) leaves the "
+                                           "first cell row at wall node " + std::to_string(i));
+            // far-field inlet flag: u_inf . n_out < 0, n_out = rot90(tangent)
+            double fxp, fyp, fxm, fym;
+            coord(c, i + 1, nj - 1, fxp, fyp);
+            coord(c, i - 1, nj - 1, fxm, fym);
+            const double ftx = fxp - fxm, fty = fyp - fym;
+            const double nx = -fty, ny = ftx;
+            c->inflow[i] = (c->fluid.u_inf[0] * nx + c->fluid.u_inf[1] * ny) < 0.0 ? 1 : 0;
+        }
+    }
+    return FSI_OK;
+}
+
+void fill_params(fsi_ctx *c) {
+    Inst &P = c->inst;
+    const fsi_fluid_params &fl = c->fluid;
+    P.ni = c->ni;
+    P.nj = c->nj;
+    P.periodic_j = c->topo == FSI_TOPO_PERIODIC2;
+    P.storage = fl.storage;
+    P.tiles_i = (c->ni + fsi::TILE_X - 1) / fsi::TILE_X;
+    P.tiles_j = (c->nj + fsi::TILE_Y - 1) / fsi::TILE_Y;
+    P.tile_base = 0;
+    P.n_nodes = (long long)c->ni * c->nj;
+    P.shift_ix = c->shift_i[0];
+    P.shift_iy = c->shift_i[1];
+    P.shift_jx = c->shift_j[0];
+    P.shift_jy = c->shift_j[1];
+    P.dt_d = fl.dt;
+    P.gamma = (float)fl.gamma;
+    const double Cv = 1.0 / (fl.gamma - 1.0);
+    P.Cv = (float)Cv;
+    P.Cp = (float)(Cv + 1.0);
+    P.mu = (float)fl.mu;
+    P.Pr = (float)fl.Pr;
+    P.dt = (float)fl.dt;
+    P.rho_inf = (float)fl.rho_inf;
+    P.T_inf = (float)fl.T_inf;
+    P.ux_inf = (float)fl.u_inf[0];
+    P.uy_inf = (float)fl.u_inf[1];
+    // FP16 shifted storage: reference = free-stream equilibrium populations
+    {
+        const double rho = fl.rho_inf, ux = fl.u_inf[0], uy = fl.u_inf[1], T = fl.T_inf;
+        const double E = Cv * T + 0.5 * (ux * ux + uy * uy);
+        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        auto phi = [&](int cc, double u) { return cc == 0 ? 1 - (u * u + T) : 0.5 * (cc * u + u * u + T); };
+        auto w1 = [&](int cc) { return cc == 0 ? 1 - T : 0.5 * T; };
+        for (int k = 0; k < 9; ++k) {
+            P.ref[k] = (float)(rho * phi(cx[k], ux) * phi(cy[k], uy));
+            P.ref[9 + k] = (float)(2.0 * rho * E * w1(cx[k]) * w1(cy[k]));
+        }
+        P.scale[0] = 1.0f / 64.0f;
+        P.scale[1] = 1.0f / 16.0f;
+        P.inv_scale[0] = 64.0f;
+        P.inv_scale[1] = 16.0f;
+    }
+    fsi::Body &B = P.body;
+    B = fsi::Body{};
+    B.present = c->has_body ? 1 : 0;
+    B.dof = c->has_body ? c->body.dof : fsi::DOF_FIXED;
+    if (c->has_body) {
+        const fsi_body_desc &b = c->body;
+        B.m = b.m; B.S_a = b.S_a; B.I_a = b.I_a; B.k_h = b.k_h; B.k_a = b.k_a;
+        B.cx = b.center[0]; B.cy = b.center[1]; B.ex = b.ea[0]; B.ey = b.ea[1];
+        B.r_rigid = b.r_rigid;
+        B.inv_width = 1.0 / (b.r_blend - b.r_rigid);
+        B.heave_amp = b.heave_amp; B.heave_omega = 2.0 * M_PI * b.heave_freq;
+        B.pitch_amp = b.pitch_amp; B.pitch_omega = 2.0 * M_PI * b.pitch_freq;
+    }
+    // work lists
+    const int ntiles = P.tiles_i * P.tiles_j;
+    c->wk1.resize(ntiles);
+    for (int t = 0; t < ntiles; ++t) c->wk1[t] = make_int2(0, t);
+    c->wbnd.clear();
+    c->wwall.clear();
+    if (c->topo == FSI_TOPO_OGRID) {
+        const int nb = (c->ni + 63) / 64;
+        for (int b = 0; b < nb; ++b) {
+            c->wbnd.push_back(make_int2(0, 2 * b));
+            c->wbnd.push_back(make_int2(0, 2 * b + 1));
+            c->wwall.push_back(make_int2(0, b));
+        }
+    }
+}
+
+void layout(fsi_ctx *c) {
+    const size_t N = (size_t)c->ni * c->nj;
+    const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
+    c->off_pop[0] = take(fsi::NPOP * N * bpp);
+    c->off_pop[1] = take(fsi::NPOP * N * bpp);
+    c->off_X = take(N * 16);
+    c->off_mask = take(c->ni * 2);
+    c->off_tgt = take(c->ni * 16);
+    c->off_B = take(c->ni * 8);
+    c->off_inflow = take(c->ni);
+    c->off_force = take(c->ni * 32);
+    c->off_slots = take(3 * sizeof(fsi::BodySlot));
+    c->off_hist = take((size_t)fsi::HIST_CAP * 6 * 8);
+    c->off_step = take(8);
+    c->off_err = take(4);
+    c->off_inst = take(sizeof(Inst));
+    c->off_wk1 = take(c->wk1.size() * sizeof(int2));
+    c->off_wbnd = take(c->wbnd.size() * sizeof(int2));
+    c->off_wwall = take(c->wwall.size() * sizeof(int2));
+    c->total = o;
+}
+
+fsi_status check_ready(fsi_ctx *c, bool need_init) {
+    if (!c) return FSI_E_ARG;
+    if (!c->ws) return fail(c, FSI_E_UNBOUND, "workspace not bound");
+    if (need_init && !c->initialized) return fail(c, FSI_E_UNBOUND, "state not initialised");
+    return FSI_OK;
+}
+
+const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c->off_inst); }
+
+fsi_status enqueue_step(fsi_ctx *c) {
+    const int st = c->fluid.storage;
+    HIP_TRY(c, fsi::launch_collide_stream(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
+                                          (int)c->wk1.size(), st, c->stream));
+    if (c->topo == FSI_TOPO_OGRID) {
+        HIP_TRY(c, fsi::launch_wall_targets(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
+                                            (int)c->wbnd.size(), st, c->stream));
+        HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
+                                               reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
+                                               (int)c->wwall.size(), st, 1, c->stream));
+    }
+    HIP_TRY(c, fsi::launch_body(d_inst(c), 1, 1, c->stream));
+    return FSI_OK;
+}
+
+// force of the current level and the next body state (no boundary update)
+fsi_status enqueue_load_update(fsi_ctx *c) {
+    if (c->topo == FSI_TOPO_OGRID)
+        HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
+                                               reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
+                                               (int)c->wwall.size(), c->fluid.storage, 0, c->stream));
+    HIP_TRY(c, fsi::launch_body(d_inst(c), 1, 0, c->stream));
+    return FSI_OK;
+}
+
+fsi_status sync_check(fsi_ctx *c) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned e = 0;
+    HIP_TRY(c, hipMemcpy(&e, c->ws + c->off_err, 4, hipMemcpyDeviceToHost));
+    if (e & fsi::ERR_STATE) return fail(c, FSI_E_STATE, "non-physical state (rho<=0, T<=0, T+u^2>=1 or NaN)");
+    if (e & fsi::ERR_CFL) return fail(c, FSI_E_CFL, "departure point outside the cells around its node");
+    if (e & fsi::ERR_MESH) return fail(c, FSI_E_MESH, "inverted cell after mesh blending");
+    return FSI_OK;
+}
+
+void drop_graph(fsi_ctx *c) {
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t fsi_history_capacity(void) { return fsi::HIST_CAP; }
+
+fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
+                      const fsi_body_desc *bodies, int nbodies, void *hip_stream, fsi_ctx **out) {
+    if (!out) return FSI_E_ARG;
+    *out = nullptr;
+    if (!fluid || !mesh || !mesh->X) return FSI_E_ARG;
+    fsi_ctx *c = new (std::nothrow) fsi_ctx();
+    if (!c) return FSI_E_NOMEM;
+    *out = c;
+    c->fluid = *fluid;
+    c->ni = mesh->ni;
+    c->nj = mesh->nj;
+    c->topo = mesh->topo;
+    c->stream = (hipStream_t)hip_stream;
+    if (c->ni < 8 || c->nj < 8) return fail(c, FSI_E_ARG, "mesh needs ni >= 8 and nj >= 8");
+    if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_OGRID)
+        return fail(c, FSI_E_ARG, "unsupported topology");
+    if (nbodies < 0 || nbodies > 1 || (nbodies == 1 && !bodies))
+        return fail(c, FSI_E_ARG, "nbodies must be 0 or 1");
+    if (!(fluid->gamma > 1) || !(fluid->mu > 0) || !(fluid->dt > 0) || !(fluid->Pr > 0) ||
+        !(fluid->rho_inf > 0) || !(fluid->T_inf > 0 && fluid->T_inf < 1))
+        return fail(c, FSI_E_ARG, "fluid parameters out of range");
+    if (fluid->storage != FSI_STORE_FP32 && fluid->storage != FSI_STORE_FP16_SHIFTED)
+        return fail(c, FSI_E_ARG, "unknown storage mode");
+    if ((long long)c->ni * c->nj > (1LL << 31) / fsi::NPOP)
+        return fail(c, FSI_E_ARG, "mesh too large for 32-bit population offsets");
+    for (int k = 0; k < 2; ++k) {
+        c->shift_i[k] = mesh->shift_i[k];
+        c->shift_j[k] = mesh->shift_j[k];
+    }
+    if (c->topo == FSI_TOPO_OGRID) c->shift_i[0] = c->shift_i[1] = c->shift_j[0] = c->shift_j[1] = 0;
+    c->X.assign(mesh->X, mesh->X + 2 * (size_t)c->ni * c->nj);
+    for (double v : c->X)
+        if (!isfinite(v)) return fail(c, FSI_E_MESH, "non-finite mesh coordinate");
+    if (nbodies == 1) {
+        c->body = bodies[0];
+        c->has_body = true;
+        if (c->body.dof < 0 || c->body.dof > 3) return fail(c, FSI_E_ARG, "unknown body dof");
+    }
+    fsi_status st = validate_and_precompute(c);
+    if (st != FSI_OK) return st;
+    fill_params(c);
+    layout(c);
+    return FSI_OK;
+}
+
+fsi_status fsi_workspace_bytes(const fsi_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return FSI_E_ARG;
+    *bytes = c->total;
+    return FSI_OK;
+}
+
+fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
+    if (!c || !dev_ptr) return FSI_E_ARG;
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(c, FSI_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < c->total) return fail(c, FSI_E_ARG, "workspace too small");
+    drop_graph(c);
+    c->ws = static_cast<char *>(dev_ptr);
+    c->initialized = false;
+    Inst &P = c->inst;
+    P.pop[0] = c->ws + c->off_pop[0];
+    P.pop[1] = c->ws + c->off_pop[1];
+    P.X = reinterpret_cast<const double2 *>(c->ws + c->off_X);
+    P.wall_mask = reinterpret_cast<uint16_t *>(c->ws + c->off_mask);
+    P.wall_tgt = reinterpret_cast<float4 *>(c->ws + c->off_tgt);
+    P.wall_B = reinterpret_cast<const float2 *>(c->ws + c->off_B);
+    P.inflow = reinterpret_cast<const uint8_t *>(c->ws + c->off_inflow);
+    P.wall_force = reinterpret_cast<double4 *>(c->ws + c->off_force);
+    P.slots = reinterpret_cast<fsi::BodySlot *>(c->ws + c->off_slots);
+    P.history = reinterpret_cast<double *>(c->ws + c->off_hist);
+    P.step = reinterpret_cast<long long *>(c->ws + c->off_step);
+    P.err = reinterpret_cast<unsigned *>(c->ws + c->off_err);
+    P.scratch = nullptr;
+    const size_t N = (size_t)c->ni * c->nj;
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_X, c->X.data(), N * 16, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_mask, 0, c->ni * 2, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_force, 0, c->ni * 32, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_hist, 0, (size_t)fsi::HIST_CAP * 48, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_step, 0, 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
+    if (c->topo == FSI_TOPO_OGRID) {
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_B, c->wallB.data(), c->ni * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inflow, c->inflow.data(), c->ni, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wbnd, c->wbnd.data(), c->wbnd.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wwall, c->wwall.data(), c->wwall.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk1, c->wk1.data(), c->wk1.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FSI_OK;
+}
+
+fsi_status fsi_init_equilibrium(fsi_ctx *c, const double *rho, const double *ux, const double *uy,
+                                const double *T) {
+    fsi_status st = check_ready(c, false);
+    if (st != FSI_OK) return st;
+    const size_t N = (size_t)c->ni * c->nj;
+    std::vector<double> macro(4 * N);
+    const double dflt[4] = {c->fluid.rho_inf, c->fluid.u_inf[0], c->fluid.u_inf[1], c->fluid.T_inf};
+    const double *src[4] = {rho, ux, uy, T};
+    for (int k = 0; k < 4; ++k)
+        for (size_t i = 0; i < N; ++i) macro[k * N + i] = src[k] ? src[k][i] : dflt[k];
+    for (size_t i = 0; i < N; ++i) {
+        const double r = macro[i], u = macro[N + i], v = macro[2 * N + i], t = macro[3 * N + i];
+        if (!(r > 0) || !(t > 0) || !(1 - t - u * u > 0) || !(1 - t - v * v > 0))
+            return fail(c, FSI_E_STATE, "initial state outside the D2Q9 positivity domain at node " +
+                                            std::to_string(i));
+    }
+    double *scratch = reinterpret_cast<double *>(c->ws + c->off_pop[1]);
+    HIP_TRY(c, hipMemcpyAsync(scratch, macro.data(), 4 * N * 8, hipMemcpyHostToDevice, c->stream));
+    fsi::BodySlot slots[3];
+    if (c->has_body) {
+        const fsi_body_desc &b = c->body;
+        if (b.dof == FSI_DOF_PRESCRIBED)
+            slots[0] = slot_of(0.0, 0.0, b.heave_amp * 2 * M_PI * b.heave_freq,
+                               b.pitch_amp * 2 * M_PI * b.pitch_freq);
+        else
+            slots[0] = slot_of(b.h0, b.a0, b.hd0, b.ad0);
+    } else {
+        slots[0] = slot_of(0, 0, 0, 0);
+    }
+    slots[1] = slots[2] = slots[0];
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_slots, slots, sizeof(slots), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_step, 0, 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
+    HIP_TRY(c, fsi::launch_init_equilibrium(d_inst(c), scratch, (long long)N, c->fluid.storage, c->stream));
+    st = enqueue_load_update(c);
+    if (st != FSI_OK) return st;
+    c->host_step = 0;
+    c->initialized = true;
+    return sync_check(c);
+}
+
+fsi_status fsi_step(fsi_ctx *c, int nsteps) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (nsteps < 0) return fail(c, FSI_E_ARG, "nsteps < 0");
+    if (nsteps == 0) return FSI_OK;
+    if (c->stream == nullptr) {
+        // the legacy default stream cannot be captured: launch directly
+        for (int k = 0; k < nsteps; ++k) {
+            st = enqueue_step(c);
+            if (st != FSI_OK) return st;
+        }
+    } else {
+        if (!c->graph_exec) {
+            HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_step(c);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (st != FSI_OK) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+            c->graph = g;
+            HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        }
+        for (int k = 0; k < nsteps; ++k) HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+    }
+    c->host_step += nsteps;
+    return FSI_OK;
+}
+
+fsi_status fsi_synchronize(fsi_ctx *c) {
+    fsi_status st = check_ready(c, false);
+    if (st != FSI_OK) return st;
+    return sync_check(c);
+}
+
+fsi_status fsi_get_step(fsi_ctx *c, int64_t *step) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (!step) return fail(c, FSI_E_ARG, "null output");
+    long long n = 0;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(&n, c->ws + c->off_step, 8, hipMemcpyDeviceToHost));
+    *step = n;
+    return FSI_OK;
+}
+
+fsi_status fsi_get_forces(fsi_ctx *c, int body, int64_t first, int count, double *out) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (body != 0 || count < 0 || (count > 0 && !out)) return fail(c, FSI_E_ARG, "bad history request");
+    const int64_t last = c->host_step;   // record `last` exists once the queue drained
+    const int64_t oldest = std::max<int64_t>(0, last - fsi::HIST_CAP + 1);
+    if (first < oldest || first + count - 1 > last)
+        return fail(c, FSI_E_ARG, "history records available: " + std::to_string(oldest) + " .. " +
+                                      std::to_string(last));
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    for (int k = 0; k < count; ++k) {
+        const int64_t L = first + k;
+        HIP_TRY(c, hipMemcpy(out + 6 * (size_t)k, c->ws + c->off_hist + (size_t)(L % fsi::HIST_CAP) * 48, 48,
+                             hipMemcpyDeviceToHost));
+    }
+    return FSI_OK;
+}
+
+fsi_status fsi_get_body_state(fsi_ctx *c, int body, double out[4]) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (body != 0 || !out) return fail(c, FSI_E_ARG, "bad body index");
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    fsi::BodySlot s;
+    HIP_TRY(c, hipMemcpy(&s, c->ws + c->off_slots + (size_t)(c->host_step % 3) * sizeof(fsi::BodySlot),
+                         sizeof(s), hipMemcpyDeviceToHost));
+    out[0] = s.h; out[1] = s.a; out[2] = s.hd; out[3] = s.ad;
+    return FSI_OK;
+}
+
+fsi_status fsi_dump_macro(fsi_ctx *c, double *rho, double *ux, double *uy, double *T) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    const size_t N = (size_t)c->ni * c->nj;
+    const int cur = (int)(c->host_step & 1);
+    double *scratch = reinterpret_cast<double *>(c->ws + c->off_pop[cur ^ 1]);
+    HIP_TRY(c, fsi::launch_dump_macro(d_inst(c), cur, scratch, (long long)N, c->fluid.storage, c->stream));
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    double *outs[4] = {rho, ux, uy, T};
+    for (int k = 0; k < 4; ++k)
+        if (outs[k]) HIP_TRY(c, hipMemcpy(outs[k], scratch + k * N, N * 8, hipMemcpyDeviceToHost));
+    return FSI_OK;
+}
+
+fsi_status fsi_get_populations(fsi_ctx *c, float *f, float *g) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    const size_t N = (size_t)c->ni * c->nj;
+    const int cur = (int)(c->host_step & 1);
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    float *outs[2] = {f, g};
+    for (int h = 0; h < 2; ++h) {
+        if (!outs[h]) continue;
+        if (c->fluid.storage == FSI_STORE_FP32) {
+            HIP_TRY(c, hipMemcpy(outs[h], c->ws + c->off_pop[cur] + (size_t)h * 9 * N * 4, 9 * N * 4,
+                                 hipMemcpyDeviceToHost));
+        } else {
+            float *tmp = reinterpret_cast<float *>(c->ws + c->off_pop[cur ^ 1]);
+            HIP_TRY(c, fsi::launch_decode(d_inst(c), cur, 9 * h, tmp, (long long)N, 1, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipMemcpy(outs[h], tmp, 9 * N * 4, hipMemcpyDeviceToHost));
+        }
+    }
+    return FSI_OK;
+}
+
+fsi_status fsi_set_populations(fsi_ctx *c, const float *f, const float *g) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (!f || !g) return fail(c, FSI_E_ARG, "null populations");
+    const size_t N = (size_t)c->ni * c->nj;
+    const int cur = (int)(c->host_step & 1);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const float *ins[2] = {f, g};
+    for (int h = 0; h < 2; ++h) {
+        if (c->fluid.storage == FSI_STORE_FP32) {
+            HIP_TRY(c, hipMemcpy(c->ws + c->off_pop[cur] + (size_t)h * 9 * N * 4, ins[h], 9 * N * 4,
+                                 hipMemcpyHostToDevice));
+        } else {
+            float *tmp = reinterpret_cast<float *>(c->ws + c->off_pop[cur ^ 1]);
+            HIP_TRY(c, hipMemcpy(tmp, ins[h], 9 * N * 4, hipMemcpyHostToDevice));
+            HIP_TRY(c, fsi::launch_encode(d_inst(c), cur, 9 * h, tmp, (long long)N, 1, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    // the load of the new populations and the body state it drives
+    st = enqueue_load_update(c);
+    if (st != FSI_OK) return st;
+    return sync_check(c);
+}
+
+fsi_status fsi_state_bytes(const fsi_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return FSI_E_ARG;
+    const size_t N = (size_t)c->ni * c->nj;
+    const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
+    *bytes = 8 * 6 + 3 * sizeof(fsi::BodySlot) + fsi::NPOP * N * bpp;
+    return FSI_OK;
+}
+
+fsi_status fsi_save(fsi_ctx *c, void *host_buf, size_t bytes) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    size_t need = 0;
+    fsi_state_bytes(c, &need);
+    if (!host_buf || bytes < need) return fail(c, FSI_E_ARG, "checkpoint buffer too small");
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    const size_t N = (size_t)c->ni * c->nj;
+    const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
+    int64_t *hdr = static_cast<int64_t *>(host_buf);
+    hdr[0] = kMagic; hdr[1] = c->ni; hdr[2] = c->nj; hdr[3] = c->fluid.storage; hdr[4] = c->host_step;
+    hdr[5] = c->topo;
+    char *p = static_cast<char *>(host_buf) + 48;
+    HIP_TRY(c, hipMemcpy(p, c->ws + c->off_slots, 3 * sizeof(fsi::BodySlot), hipMemcpyDeviceToHost));
+    p += 3 * sizeof(fsi::BodySlot);
+    HIP_TRY(c, hipMemcpy(p, c->ws + c->off_pop[c->host_step & 1], fsi::NPOP * N * bpp, hipMemcpyDeviceToHost));
+    return FSI_OK;
+}
+
+fsi_status fsi_load(fsi_ctx *c, const void *host_buf, size_t bytes) {
+    fsi_status st = check_ready(c, false);
+    if (st != FSI_OK) return st;
+    size_t need = 0;
+    fsi_state_bytes(c, &need);
+    if (!host_buf || bytes < need) return fail(c, FSI_E_ARG, "checkpoint buffer too small");
+    const int64_t *hdr = static_cast<const int64_t *>(host_buf);
+    if (hdr[0] != kMagic || hdr[1] != c->ni || hdr[2] != c->nj || hdr[3] != c->fluid.storage || hdr[5] != c->topo)
+        return fail(c, FSI_E_ARG, "checkpoint does not match this context");
+    const size_t N = (size_t)c->ni * c->nj;
+    const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
+    const int64_t step = hdr[4];
+    const char *p = static_cast<const char *>(host_buf) + 48;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_slots, p, 3 * sizeof(fsi::BodySlot), hipMemcpyHostToDevice));
+    p += 3 * sizeof(fsi::BodySlot);
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_pop[step & 1], p, fsi::NPOP * N * bpp, hipMemcpyHostToDevice));
+    long long s = step;
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_step, &s, 8, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemset(c->ws + c->off_err, 0, 4));
+    c->host_step = step;
+    c->initialized = true;
+    // the history record of the current level
+    st = enqueue_load_update(c);
+    if (st != FSI_OK) return st;
+    return sync_check(c);
+}
+
+fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (reps < 1 || !out_ms) return fail(c, FSI_E_ARG, "reps must be >= 1");
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const int stg = c->fluid.storage;
+    const int2 *wk1 = reinterpret_cast<const int2 *>(c->ws + c->off_wk1);
+    const int2 *wbnd = reinterpret_cast<const int2 *>(c->ws + c->off_wbnd);
+    const int2 *wwall = reinterpret_cast<const int2 *>(c->ws + c->off_wwall);
+    for (int which = 0; which < 4; ++which) {
+        out_ms[which] = 0.0;
+        if (c->topo != FSI_TOPO_OGRID && (which == 1 || which == 2)) continue;
+        // one untimed launch, then `reps` timed ones
+        for (int r = 0; r <= reps; ++r) {
+            if (r == 1) HIP_TRY(c, hipEventRecord(e0, c->stream));
+            hipError_t e = hipSuccess;
+            if (which == 0) e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream);
+            if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
+            // phase 0 of the wall kernel (traction only) and of the body kernel
+            // recompute the current level without advancing it
+            if (which == 2) e = fsi::launch_wall_grad_force(d_inst(c), wwall, (int)c->wwall.size(), stg, 0, c->stream);
+            if (which == 3) e = fsi::launch_body(d_inst(c), 1, 0, c->stream);
+            HIP_TRY(c, e);
+        }
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        out_ms[which] = ms / reps;
+    }
+    HIP_TRY(c, hipEventDestroy(e0));
+    HIP_TRY(c, hipEventDestroy(e1));
+    return sync_check(c);
+}
+
+const char *fsi_last_error(const fsi_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void fsi_destroy(fsi_ctx *c) {
+    if (!c) return;
+    drop_graph(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal data layout shared by the host runtime and the gfx950 kernels.
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace fsi {
+
+constexpr int Q = 9;
+constexpr int NPOP = 18;            // f_0..f_8 then g_0..g_8
+constexpr int TILE_X = 64;          // nodes along i per tile (one wavefront width)
+constexpr int TILE_Y = 8;           // nodes along j per tile
+constexpr int K1_THREADS = 256;
+constexpr int HIST_CAP = 1 << 16;   // force / displacement history records kept
+
+// error bits of the device error word
+constexpr unsigned ERR_CFL = 1u;    // departure point outside the node's cells
+constexpr unsigned ERR_STATE = 2u;  // rho<=0, T<=0, T>=1, Phi_0<=0, NaN
+constexpr unsigned ERR_MESH = 4u;   // det(dx/dxi) <= 0 after blending
+
+enum Dof { DOF_PRESCRIBED = 0, DOF_HEAVE = 1, DOF_PITCH_PLUNGE = 2, DOF_FIXED = 3 };
+
+// Constant description of the (single) body of an instance.
+struct Body {
+    int dof;
+    int present;
+    double m, S_a, I_a, k_h, k_a;
+    double cx, cy;            // blending centre (undeformed frame)
+    double ex, ey;            // elastic axis / rotation centre (undeformed frame)
+    double r_rigid, inv_width;// 1 / (r_blend - r_rigid)
+    double heave_amp, heave_omega, pitch_amp, pitch_omega;
+};
+
+// Body state at one time level, plus the rotation terms the kernels need.
+struct BodySlot {
+    double h, a, hd, ad;      // plunge, pitch (counter-clockwise), rates
+    double cm1, sa;           // cos(a) - 1 (computed as -2 sin^2(a/2)), sin(a)
+    double pad0, pad1;
+};
+
+// Everything one instance (one mesh + body) needs on the device.  Lives in
+// device memory; kernels read it through the scalar cache.
+struct Inst {
+    int ni, nj;
+    int periodic_j;           // 1: PERIODIC2 topology, 0: O-grid (wall + far field)
+    int storage;              // 0 FP32, 1 FP16 shifted
+    int tiles_i, tiles_j;     // tile grid of the fused kernel
+    int tile_base;            // first work item of this instance in a batch
+    int pad0;
+    long long n_nodes;
+    double shift_ix, shift_iy, shift_jx, shift_jy;
+    double dt_d;
+    float gamma, Cv, Cp, mu, Pr, dt;
+    float rho_inf, T_inf, ux_inf, uy_inf;
+    float ref[NPOP];          // FP16 shifted storage: reference populations
+    float scale[2];           // FP16 shifted storage: f, g scales
+    float inv_scale[2];
+    Body body;
+    // device buffers (all inside the caller's workspace)
+    void *pop[2];             // ping-pong [18][nj][ni], float or half
+    const double2 *X;         // [nj][ni] undeformed coordinates
+    uint16_t *wall_mask;      // [ni] bit k: population k missing at the wall node
+    float4 *wall_tgt;         // [ni] (rho, ux, uy, T) targets
+    const float2 *wall_B;     // [ni] index offsets of point B from the wall node
+    const uint8_t *inflow;    // [ni] far-field node is an inlet
+    double4 *wall_force;      // [ni] per-node (Fx, Fy, Mz, 0)
+    BodySlot *slots;          // [3] body states at levels n % 3
+    double *history;          // [HIST_CAP][6]
+    long long *step;          // completed steps
+    unsigned *err;            // sticky error word
+    double *scratch;          // init / dump staging (aliases the idle ping-pong side)
+};
+
+}  // namespace fsi
+
+namespace fsi {
+// host-callable launchers (fsilbm_kernels.hip)
+hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
+                                 hipStream_t s);
+hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,
+                               hipStream_t s);
+hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_work, int storage,
+                                  int phase, hipStream_t s);
+hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
+hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,
+                                   int storage, hipStream_t s);
+hipError_t launch_dump_macro(const Inst *inst, int side, double *out, long long n_nodes, int storage,
+                             hipStream_t s);
+hipError_t launch_decode(const Inst *inst, int side, int q0, float *out, long long n_nodes, int storage,
+                         hipStream_t s);
+hipError_t launch_encode(const Inst *inst, int side, int q0, const float *in, long long n_nodes,
+                         int storage, hipStream_t s);
+}  // namespace fsi

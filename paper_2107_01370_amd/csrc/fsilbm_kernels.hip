@@ -1,0 +1,995 @@
+// gfx950 kernels of the two-population compressible lattice Boltzmann FSI step
+// (Bhadauria, Dorschner & Karlin, arXiv 2107.01370).
+//
+//   k_collide_stream   fused collision (Sec. II.C) + ALE semi-Lagrangian
+//                      streaming (Sec. II.A-B) over 64 x 8 node tiles
+//   k_wall_targets     Grad targets at the wall (Sec. III.A.1) and
+//                      far-field equilibria (Sec. III.A.2)
+//   k_wall_grad_force  Grad populations at the wall and per-node traction
+//                      (Sec. III.A.1, Sec. III force)
+//   k_body             deterministic force reduction + rigid-body RK4 (Sec. IV)
+//   k_init_equilibrium, k_dump_macro, k_decode, k_encode: set-up and I/O
+//
+// Precision: populations are stored in FP32 (or FP16 as shifted deviations)
+// and collided / interpolated in FP32.  Mesh coordinates, blending weights,
+// mesh displacements, the traction sum and the body ODE are FP64; coordinate
+// differences are formed in FP64 and only then rounded to FP32.
+#include "fsilbm_internal.h"
+
+namespace fsi {
+
+__constant__ int c_cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int c_cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+#define CXK(k) ((k) == 1 || (k) == 5 || (k) == 8 ? 1 : ((k) == 3 || (k) == 6 || (k) == 7 ? -1 : 0))
+#define CYK(k) ((k) == 2 || (k) == 5 || (k) == 6 ? 1 : ((k) == 4 || (k) == 7 || (k) == 8 ? -1 : 0))
+
+__device__ __forceinline__ int floor_div(int a, int b) {
+    const int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__device__ __forceinline__ int wrap(int a, int n) { return a - floor_div(a, n) * n; }
+
+// ---------------------------------------------------------------------------
+// population storage codec
+// ---------------------------------------------------------------------------
+template <int STORE>
+__device__ __forceinline__ float pop_load(const Inst &P, const void *base, int q, long long idx) {
+    if constexpr (STORE == 0) {
+        return static_cast<const float *>(base)[q * P.n_nodes + idx];
+    } else {
+        const __half h = static_cast<const __half *>(base)[q * P.n_nodes + idx];
+        return P.ref[q] + P.scale[q >= Q] * __half2float(h);
+    }
+}
+
+template <int STORE>
+__device__ __forceinline__ void pop_store(const Inst &P, void *base, int q, long long idx, float v) {
+    if constexpr (STORE == 0) {
+        static_cast<float *>(base)[q * P.n_nodes + idx] = v;
+    } else {
+        static_cast<__half *>(base)[q * P.n_nodes + idx] =
+            __float2half_rn((v - P.ref[q]) * P.inv_scale[q >= Q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// geometry (FP64): blending factor and rigid displacement (Sec. II.D)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double blend_factor(const Body &b, double X, double Y) {
+    if (!b.present) return 1.0;
+    const double dx = X - b.cx, dy = Y - b.cy;
+    const double s = (sqrt(dx * dx + dy * dy) - b.r_rigid) * b.inv_width;
+    if (s <= 0.0) return 0.0;
+    if (s >= 1.0) return 1.0;
+    return s * s * s * (10.0 + s * (-15.0 + 6.0 * s));
+}
+
+// G'(X) - X = (0, h) + (R(a) - I)(X - X_EA)
+__device__ __forceinline__ void rigid_disp(const Body &b, const BodySlot &s, double X, double Y,
+                                           double &dx, double &dy) {
+    const double rx = X - b.ex, ry = Y - b.ey;
+    dx = s.cm1 * rx - s.sa * ry;
+    dy = s.h + s.sa * rx + s.cm1 * ry;
+}
+
+// ---------------------------------------------------------------------------
+// D2Q9 collision (Sec. II.C).  f, g in registers, overwritten with f*, g*.
+// ---------------------------------------------------------------------------
+struct Moments {
+    float rho, ux, uy, E, T;
+};
+
+__device__ __forceinline__ Moments moments(const float f[9], const float g[9], float Cv) {
+    Moments m;
+    m.rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float ir = 1.0f / m.rho;
+    m.ux = jx * ir;
+    m.uy = jy * ir;
+    m.E = 0.5f * G * ir;
+    m.T = (m.E - 0.5f * (m.ux * m.ux + m.uy * m.uy)) / Cv;
+    return m;
+}
+
+__device__ __forceinline__ bool state_ok(float rho, float ux, float uy, float T) {
+    // also false for NaN
+    return rho > 0.0f && T > 0.0f && (1.0f - T) > 0.0f && (1.0f - T - ux * ux) > 0.0f &&
+           (1.0f - T - uy * uy) > 0.0f;
+}
+
+// f^eq (product form) and g^eq (with the energy correction Psi) of a
+// macroscopic state (Sec. II.C).  R = T for the FP32 hot path, double for
+// initialisation.
+template <typename R>
+__device__ __forceinline__ void equilibria(R rho, R ux, R uy, R T, R E, R feq[9], R geq[9]) {
+    const R half = R(0.5), one = R(1), two = R(2);
+    const R px[3] = {half * (-ux + ux * ux + T), one - (ux * ux + T), half * (ux + ux * ux + T)};
+    const R py[3] = {half * (-uy + uy * uy + T), one - (uy * uy + T), half * (uy + uy * uy + T)};
+    const R w[3] = {half * T, one - T, half * T};
+    const R invT = one / T;
+    const R inv2T2 = half * invT * invT;
+    const R H = E + T;                              // enthalpy (C_v + 1) T + u^2/2
+    const R qx = two * rho * ux * H, qy = two * rho * uy * H;
+    const R e2 = E + two * T;
+    // A = R^eq - 2 rho E T I = 2 rho [(E + 2T) u u + T^2 I]
+    const R Axx = two * rho * (e2 * ux * ux + T * T);
+    const R Ayy = two * rho * (e2 * uy * uy + T * T);
+    const R Axy = two * rho * e2 * ux * uy;
+    // Psi: delta R_a = rho (1 - 3T)(T^2 + 2 u_a^2 T + E u_a^2) / T
+    const R c13 = rho * (one - R(3) * T) * invT;
+    const R dRx = c13 * (T * T + (two * T + E) * ux * ux);
+    const R dRy = c13 * (T * T + (two * T + E) * uy * uy);
+    const R two_rho_E = two * rho * E;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = CXK(k), cy = CYK(k);
+        feq[k] = rho * px[cx + 1] * py[cy + 1];
+        const R W = w[cx + 1] * w[cy + 1];
+        const R contr = Axx * R(cx * cx) + Ayy * R(cy * cy) + two * Axy * R(cx * cy) - T * (Axx + Ayy);
+        R psi = R(0);
+        if (k == 0) psi = dRx + dRy;
+        else if (cy == 0 && cx != 0) psi = -half * dRx;
+        else if (cx == 0 && cy != 0) psi = -half * dRy;
+        geq[k] = W * (two_rho_E + (qx * R(cx) + qy * R(cy)) * invT + contr * inv2T2) + psi;
+    }
+}
+
+template <bool CHECK = true>
+__device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float Fy, const Inst &P,
+                                        unsigned &err) {
+    const Moments m = moments(f, g, P.Cv);
+    const float rho = m.rho, ux = m.ux, uy = m.uy, T = m.T, E = m.E;
+    if (CHECK && !state_ok(rho, ux, uy, T)) err |= ERR_STATE;
+    const float Pxx = (f[1] + f[3]) + (f[5] + f[6]) + (f[7] + f[8]);
+    const float Pyy = (f[2] + f[4]) + (f[5] + f[6]) + (f[7] + f[8]);
+    const float Pxy = (f[5] - f[6]) + (f[7] - f[8]);
+    // omega from mu = (1/omega - 1/2) p dt; Pr = (1/omega - 1/2)/(1/omega_1 - 1/2)
+    const float a = P.mu / (rho * T * P.dt);
+    const float omega = 1.0f / (a + 0.5f);
+    const float omega1 = 1.0f / (a / P.Pr + 0.5f);
+    float feq[9], geq[9];
+    equilibria<float>(rho, ux, uy, T, E, feq, geq);
+    // q* - q^eq = 2 u . (P - P^eq)
+    const float dPxx = Pxx - rho * (T + ux * ux);
+    const float dPyy = Pyy - rho * (T + uy * uy);
+    const float dPxy = Pxy - rho * ux * uy;
+    const float dqx = 2.0f * (ux * dPxx + uy * dPxy);
+    const float dqy = 2.0f * (ux * dPxy + uy * dPyy);
+    const float invT = 1.0f / T;
+    const float w[3] = {0.5f * T, 1.0f - T, 0.5f * T};
+    const float cf = -P.dt * invT;                 // phi_i = -(W_i/T) c_i . F
+    const float cg = (omega1 - omega) * invT;      // g^* - g^eq = W_i dq . c_i / T
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = CXK(k), cy = CYK(k);
+        const float W = w[cx + 1] * w[cy + 1];
+        f[k] = f[k] + omega * (feq[k] - f[k]) + cf * W * (Fx * (float)cx + Fy * (float)cy);
+        g[k] = g[k] + omega1 * (geq[k] - g[k]) + cg * W * (dqx * (float)cx + dqy * (float)cy);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused collision + ALE interpolating streaming.
+//
+// One workgroup owns a TILE_X x TILE_Y block of arrival nodes.  Because the
+// momentum correction needs nested gradients (reach 2) and the interpolation
+// stencil reaches one node, the tile is processed with a halo of 3:
+//   phase 1 (tile+3): load populations -> delta Q, mu/p;  X, r_blend -> LDS
+//   phase 2 (tile+2): D_a = (mu/p) d_a dQ_a on the mesh x^n        -> LDS
+//   phase 3 (tile+1): F_a = d_a D_a; collide                        -> LDS
+//   phase 4 (tile)  : departure points on x^{n+1}, 3x3 Lagrange
+//                     interpolation from LDS, store f^{n+1}, g^{n+1}
+// ---------------------------------------------------------------------------
+constexpr int R3X = TILE_X + 6, R3Y = TILE_Y + 6, R3N = R3X * R3Y;
+constexpr int R2X = TILE_X + 4, R2Y = TILE_Y + 4, R2N = R2X * R2Y;
+constexpr int R1X = TILE_X + 2, R1Y = TILE_Y + 2, R1N = R1X * R1Y;
+
+struct K1Smem {
+    double X[R3N];
+    double Y[R3N];
+    double R[R3N];           // blending factor r
+    float Dx[R2N], Dy[R2N];
+    union {
+        struct {
+            float Qx[R3N], Qy[R3N], S[R3N];
+        } q;
+        float FG[NPOP][R1N];
+    } u;
+};
+
+// index-space derivative along j at relative row v of an R-region column:
+// centred inside, one-sided 3-point on the physical end rows of an O-grid.
+struct JStencil {
+    int o0, o1, o2;          // row offsets
+    float w0, w1, w2;        // weights
+};
+
+__device__ __forceinline__ JStencil jstencil(const Inst &P, int jg) {
+    JStencil s;
+    if (!P.periodic_j && jg == 0) {
+        s.o0 = 0; s.o1 = 1; s.o2 = 2; s.w0 = -1.5f; s.w1 = 2.0f; s.w2 = -0.5f;
+    } else if (!P.periodic_j && jg == P.nj - 1) {
+        s.o0 = 0; s.o1 = -1; s.o2 = -2; s.w0 = 1.5f; s.w1 = -2.0f; s.w2 = 0.5f;
+    } else {
+        s.o0 = -1; s.o1 = 1; s.o2 = 0; s.w0 = -0.5f; s.w1 = 0.5f; s.w2 = 0.0f;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double jstencil_d(const JStencil &s, double a0, double a1, double a2) {
+    return (double)s.w0 * a0 + (double)s.w1 * a1 + (double)s.w2 * a2;
+}
+
+// physical position x(t) of an R3 entry: X + (1 - r) d(X)
+__device__ __forceinline__ void pos_at(const K1Smem &sm, const Body &b, const BodySlot &s, int e,
+                                      double &x, double &y) {
+    const double X = sm.X[e], Y = sm.Y[e], r = sm.R[e];
+    if (r >= 1.0) { x = X; y = Y; return; }
+    double dx, dy;
+    rigid_disp(b, s, X, Y, dx, dy);
+    x = X + (1.0 - r) * dx;
+    y = Y + (1.0 - r) * dy;
+}
+
+// metric (x_xi, x_eta, y_xi, y_eta) at R3 entry (u, v) of the mesh at slot s
+__device__ __forceinline__ void metric_at(const K1Smem &sm, const Body &b, const BodySlot &s,
+                                          const JStencil &js, int u, int v, float J[4]) {
+    double xp, yp, xm, ym;
+    pos_at(sm, b, s, v * R3X + u + 1, xp, yp);
+    pos_at(sm, b, s, v * R3X + u - 1, xm, ym);
+    J[0] = (float)(0.5 * (xp - xm));
+    J[2] = (float)(0.5 * (yp - ym));
+    double x0, y0, x1, y1, x2, y2;
+    pos_at(sm, b, s, (v + js.o0) * R3X + u, x0, y0);
+    pos_at(sm, b, s, (v + js.o1) * R3X + u, x1, y1);
+    if (js.w2 != 0.0f) {
+        pos_at(sm, b, s, (v + js.o2) * R3X + u, x2, y2);
+        // one-sided: form differences first to keep FP64 relative accuracy
+        J[1] = (float)((double)js.w1 * (x1 - x0) + (double)js.w2 * (x2 - x0));
+        J[3] = (float)((double)js.w1 * (y1 - y0) + (double)js.w2 * (y2 - y0));
+    } else {
+        J[1] = (float)(0.5 * (x1 - x0));
+        J[3] = (float)(0.5 * (y1 - y0));
+    }
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(K1_THREADS, 2)
+k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
+    __shared__ K1Smem sm;
+    // XCD-aware work mapping: consecutive dispatch slots go round-robin over the
+    // 8 XCDs, so give each XCD a contiguous run of tiles (shared halos stay in
+    // that XCD's L2).
+    const int nb = gridDim.x;
+    const int per_xcd = (nb + 7) / 8;
+    const int b = blockIdx.x;
+    const int w = (b % 8) * per_xcd + b / 8;
+    if (w >= n_work) return;
+    const int2 item = work[w];
+    const Inst &P = insts[item.x];
+    const int tile = item.y;
+    const int ti = tile % P.tiles_i, tj = tile / P.tiles_i;
+    const int i0 = ti * TILE_X, j0 = tj * TILE_Y;
+    const int ni = P.ni, nj = P.nj;
+    const long long n = *P.step;
+    const void *src = P.pop[n & 1];
+    void *dst = P.pop[(n + 1) & 1];
+    const BodySlot sn = P.slots[n % 3];
+    const BodySlot sn1 = P.slots[(n + 1) % 3];
+    const Body &body = P.body;
+    const int t = threadIdx.x;
+    unsigned err = 0;
+
+    // ---- phase 1: tile+3 --------------------------------------------------
+    for (int e = t; e < R3N; e += K1_THREADS) {
+        const int u = e % R3X, v = e / R3X;
+        int ig = i0 - 3 + u, jg = j0 - 3 + v;
+        // wrap into the mesh; coordinates of a node seen across a periodic seam
+        // are shifted by the period
+        const int wi = floor_div(ig, ni);
+        ig -= wi * ni;
+        double shx = wi * P.shift_ix, shy = wi * P.shift_iy;
+        bool valid = true;
+        if (P.periodic_j) {
+            const int wj = floor_div(jg, nj);
+            jg -= wj * nj;
+            shx += wj * P.shift_jx;
+            shy += wj * P.shift_jy;
+        } else {
+            valid = (jg >= 0 && jg < nj);
+        }
+        if (!valid) {
+            sm.X[e] = 0.0; sm.Y[e] = 0.0; sm.R[e] = 1.0;
+            sm.u.q.Qx[e] = 0.0f; sm.u.q.Qy[e] = 0.0f; sm.u.q.S[e] = 0.0f;
+            continue;
+        }
+        const long long idx = (long long)jg * ni + ig;
+        const double2 Xr = P.X[idx];
+        sm.R[e] = blend_factor(body, Xr.x, Xr.y);   // from the unshifted node
+        sm.X[e] = Xr.x + shx;
+        sm.Y[e] = Xr.y + shy;
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, idx);
+            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+        }
+        const Moments m = moments(f, g, P.Cv);
+        const float one3T = 1.0f - 3.0f * m.T;
+        sm.u.q.Qx[e] = m.rho * m.ux * (one3T - m.ux * m.ux);
+        sm.u.q.Qy[e] = m.rho * m.uy * (one3T - m.uy * m.uy);
+        sm.u.q.S[e] = P.mu / (m.rho * m.T);
+    }
+    __syncthreads();
+
+    // ---- phase 2: tile+2: D_a = (mu/p) d_{x_a} dQ_a --------------------------
+    for (int e = t; e < R2N; e += K1_THREADS) {
+        const int u2 = e % R2X, v2 = e / R2X;
+        const int u = u2 + 1, v = v2 + 1;             // R3 coordinates
+        int jg = j0 - 2 + v2;
+        if (P.periodic_j) jg = wrap(jg, nj);
+        else if (jg < 0 || jg >= nj) { sm.Dx[e] = 0.0f; sm.Dy[e] = 0.0f; continue; }
+        const JStencil js = jstencil(P, jg);
+        float J[4];
+        metric_at(sm, body, sn, js, u, v, J);
+        const float det = J[0] * J[3] - J[2] * J[1];
+        const int c = v * R3X + u;
+        const float qx_xi = 0.5f * (sm.u.q.Qx[c + 1] - sm.u.q.Qx[c - 1]);
+        const float qy_xi = 0.5f * (sm.u.q.Qy[c + 1] - sm.u.q.Qy[c - 1]);
+        const int r0 = (v + js.o0) * R3X + u, r1 = (v + js.o1) * R3X + u, r2 = (v + js.o2) * R3X + u;
+        const float qx_eta = js.w0 * sm.u.q.Qx[r0] + js.w1 * sm.u.q.Qx[r1] + js.w2 * sm.u.q.Qx[r2];
+        const float qy_eta = js.w0 * sm.u.q.Qy[r0] + js.w1 * sm.u.q.Qy[r1] + js.w2 * sm.u.q.Qy[r2];
+        const float s = sm.u.q.S[c] / det;
+        sm.Dx[e] = s * (J[3] * qx_xi - J[2] * qx_eta);
+        sm.Dy[e] = s * (-J[1] * qy_xi + J[0] * qy_eta);
+    }
+    __syncthreads();
+
+    // ---- phase 3: tile+1: F_a = d_{x_a} D_a, collide -> LDS ------------------
+    for (int e = t; e < R1N; e += K1_THREADS) {
+        const int u1 = e % R1X, v1 = e / R1X;
+        int ig = wrap(i0 - 1 + u1, ni), jg = j0 - 1 + v1;
+        if (P.periodic_j) jg = wrap(jg, nj);
+        else if (jg < 0 || jg >= nj) continue;
+        const JStencil js = jstencil(P, jg);
+        float J[4];
+        metric_at(sm, body, sn, js, u1 + 2, v1 + 2, J);
+        const float det = J[0] * J[3] - J[2] * J[1];
+        const int c = (v1 + 1) * R2X + (u1 + 1);     // R2 coordinates
+        const float dx_xi = 0.5f * (sm.Dx[c + 1] - sm.Dx[c - 1]);
+        const float dy_xi = 0.5f * (sm.Dy[c + 1] - sm.Dy[c - 1]);
+        const int r0 = c + js.o0 * R2X, r1 = c + js.o1 * R2X, r2 = c + js.o2 * R2X;
+        const float dx_eta = js.w0 * sm.Dx[r0] + js.w1 * sm.Dx[r1] + js.w2 * sm.Dx[r2];
+        const float dy_eta = js.w0 * sm.Dy[r0] + js.w1 * sm.Dy[r1] + js.w2 * sm.Dy[r2];
+        const float Fx = (J[3] * dx_xi - J[2] * dx_eta) / det;
+        const float Fy = (-J[1] * dy_xi + J[0] * dy_eta) / det;
+        const long long idx = (long long)jg * ni + ig;
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, idx);
+            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+        }
+        collide(f, g, Fx, Fy, P, err);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sm.u.FG[k][e] = f[k];
+            sm.u.FG[Q + k][e] = g[k];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: tile: departure points + interpolation ---------------------
+    const float dtf = P.dt;
+    for (int e = t; e < TILE_X * TILE_Y; e += K1_THREADS) {
+        const int ut = e % TILE_X, vt = e / TILE_X;
+        const int ig = i0 + ut, jg = j0 + vt;
+        if (ig >= ni || jg >= nj) continue;
+        if (!P.periodic_j && jg == nj - 1) continue;   // far-field row: boundary kernel
+        const int u = ut + 3, v = vt + 3;              // R3 coordinates
+        const JStencil js = jstencil(P, jg);
+        // mesh at t^{n+1}
+        float J[4];
+        metric_at(sm, body, sn1, js, u, v, J);
+        const float det = J[0] * J[3] - J[2] * J[1];
+        if (!(det > 0.0f)) err |= ERR_MESH;
+        const float idet = 1.0f / det;
+        // undeformed metric (for the bilinear target) and the mesh velocity
+        const int c3 = v * R3X + u;
+        const double Xc = sm.X[c3], Yc = sm.Y[c3];
+        float VGx = 0.0f, VGy = 0.0f;
+        {
+            const double r = sm.R[c3];
+            if (r < 1.0) {
+                double d1x, d1y, d0x, d0y;
+                rigid_disp(body, sn1, Xc, Yc, d1x, d1y);
+                rigid_disp(body, sn, Xc, Yc, d0x, d0y);
+                VGx = (float)((1.0 - r) * (d1x - d0x) / P.dt_d);
+                VGy = (float)((1.0 - r) * (d1y - d0y) / P.dt_d);
+            }
+        }
+        // relative undeformed coordinates of the 3x3 neighbourhood
+        float RX[3][3], RY[3][3];
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+            for (int di = -1; di <= 1; ++di) {
+                const int ee = (v + dj) * R3X + (u + di);
+                RX[dj + 1][di + 1] = (float)(sm.X[ee] - Xc);
+                RY[dj + 1][di + 1] = (float)(sm.Y[ee] - Yc);
+            }
+        const float BX_xi = 0.5f * (RX[1][2] - RX[1][0]), BY_xi = 0.5f * (RY[1][2] - RY[1][0]);
+        float BX_eta, BY_eta;
+        if (!P.periodic_j && jg == 0) {
+            const int e2 = (v + 2) * R3X + u;
+            const float RX2 = (float)(sm.X[e2] - Xc), RY2 = (float)(sm.Y[e2] - Yc);
+            BX_eta = 2.0f * RX[2][1] - 0.5f * RX2;
+            BY_eta = 2.0f * RY[2][1] - 0.5f * RY2;
+        } else {
+            BX_eta = 0.5f * (RX[2][1] - RX[0][1]);
+            BY_eta = 0.5f * (RY[2][1] - RY[0][1]);
+        }
+        const bool wall = (!P.periodic_j && jg == 0);
+        const int vc = wall ? 1 : 0;                   // stencil centre row offset
+        const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of stencil centre
+        const long long idx = (long long)jg * ni + ig;
+        uint16_t miss = 0;
+        pop_store<STORE>(P, dst, 0, idx, sm.u.FG[0][(vt + 1) * R1X + ut + 1]);
+        pop_store<STORE>(P, dst, Q, idx, sm.u.FG[Q][(vt + 1) * R1X + ut + 1]);
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {
+            const float wx = (float)CXK(k) - VGx, wy = (float)CYK(k) - VGy;
+            // linear estimate of the index-space offset: -dt (dx^{n+1}/dxi)^{-1} (c - V_G)
+            const float dxi = -dtf * idet * (J[3] * wx - J[1] * wy);
+            const float deta = -dtf * idet * (-J[2] * wx + J[0] * wy);
+            // target X_dp - X = (dX/dxi) dxi  (c^ = (dx/dX)^{-1}(c - V_G))
+            const float Px = BX_xi * dxi + BX_eta * deta;
+            const float Py = BY_xi * dxi + BY_eta * deta;
+            int ci = dxi < 0.0f ? -1 : 0;
+            int cj = deta < 0.0f ? -1 : 0;
+            if (wall) cj = 0;
+            float s = dxi - (float)ci, tt = deta - (float)cj;
+            for (int attempt = 0; attempt < 3; ++attempt) {
+                // corners of cell (ci, cj) relative to the node, by selection
+                // (ci, cj in {-1, 0}) so the 3x3 block stays in registers
+                const bool li = ci < 0, lj = cj < 0;
+                const float xa0 = li ? RX[0][0] : RX[0][1], xa1 = li ? RX[0][1] : RX[0][2];
+                const float xb0 = li ? RX[1][0] : RX[1][1], xb1 = li ? RX[1][1] : RX[1][2];
+                const float xc0 = li ? RX[2][0] : RX[2][1], xc1 = li ? RX[2][1] : RX[2][2];
+                const float ya0 = li ? RY[0][0] : RY[0][1], ya1 = li ? RY[0][1] : RY[0][2];
+                const float yb0 = li ? RY[1][0] : RY[1][1], yb1 = li ? RY[1][1] : RY[1][2];
+                const float yc0 = li ? RY[2][0] : RY[2][1], yc1 = li ? RY[2][1] : RY[2][2];
+                const float x00 = lj ? xa0 : xb0, x10 = lj ? xa1 : xb1;
+                const float x01 = lj ? xb0 : xc0, x11 = lj ? xb1 : xc1;
+                const float y00 = lj ? ya0 : yb0, y10 = lj ? ya1 : yb1;
+                const float y01 = lj ? yb0 : yc0, y11 = lj ? yb1 : yc1;
+                const float ax = x10 - x00, ay = y10 - y00;
+                const float bx = x01 - x00, by = y01 - y00;
+                const float cx = x11 - x10 - x01 + x00, cy = y11 - y10 - y01 + y00;
+#pragma unroll
+                for (int it = 0; it < 3; ++it) {
+                    const float rx = x00 + ax * s + bx * tt + cx * s * tt - Px;
+                    const float ry = y00 + ay * s + by * tt + cy * s * tt - Py;
+                    const float jsx = ax + cx * tt, jsy = ay + cy * tt;
+                    const float jtx = bx + cx * s, jty = by + cy * s;
+                    const float id = 1.0f / (jsx * jty - jsy * jtx);
+                    s -= id * (jty * rx - jtx * ry);
+                    tt -= id * (-jsy * rx + jsx * ry);
+                }
+                const float eps = 1e-5f;
+                bool moved = false;
+                if (s < -eps && ci == 0) { ci = -1; s += 1.0f; moved = true; }
+                else if (s > 1.0f + eps && ci == -1) { ci = 0; s -= 1.0f; moved = true; }
+                if (!wall) {
+                    if (tt < -eps && cj == 0) { cj = -1; tt += 1.0f; moved = true; }
+                    else if (tt > 1.0f + eps && cj == -1) { cj = 0; tt -= 1.0f; moved = true; }
+                }
+                if (!moved) break;
+            }
+            const float a = (float)ci + s;
+            float bb = (float)cj + tt;
+            if (wall && tt < -1e-5f) { miss |= (uint16_t)(1u << k); continue; }
+            if (!(fabsf(a) <= 1.0f + 1e-4f) || !(fabsf(bb) <= 1.0f + 1e-4f)) err |= ERR_CFL;
+            bb -= (float)vc;
+            const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
+            const float wbm = 0.5f * bb * (bb - 1.0f), wbp = 0.5f * bb * (bb + 1.0f);
+            // tensor-product quadratic Lagrange, written as centre + weighted
+            // differences so constants are reproduced exactly
+            float outv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float *F = sm.u.FG[h * Q + k];
+                float row[3];
+#pragma unroll
+                for (int dj = -1; dj <= 1; ++dj) {
+                    const int cc = c1 + dj * R1X;
+                    const float fc = F[cc];
+                    row[dj + 1] = fc + wam * (F[cc - 1] - fc) + wap * (F[cc + 1] - fc);
+                }
+                outv[h] = row[1] + wbm * (row[0] - row[1]) + wbp * (row[2] - row[1]);
+            }
+            pop_store<STORE>(P, dst, k, idx, outv[0]);
+            pop_store<STORE>(P, dst, Q + k, idx, outv[1]);
+        }
+        if (wall) P.wall_mask[ig] = miss;
+    }
+    if (err) atomicOr(P.err, err);
+}
+
+
+// ---------------------------------------------------------------------------
+// Boundary kernels (O-grid).  Work items (instance, block): 64 wall or
+// far-field nodes per block.
+// ---------------------------------------------------------------------------
+constexpr int BND = 64;
+
+// quadratic Lagrange basis on the nodes {-1, 0, +1}
+template <typename R>
+__device__ __forceinline__ R lag(int p, R a) {
+    return p < 0 ? R(0.5) * a * (a - R(1)) : (p == 0 ? R(1) - a * a : R(0.5) * a * (a + R(1)));
+}
+
+template <int STORE>
+__device__ __forceinline__ void load_node(const Inst &P, const void *base, long long idx, float f[9],
+                                          float g[9]) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        f[k] = pop_load<STORE>(P, base, k, idx);
+        g[k] = pop_load<STORE>(P, base, Q + k, idx);
+    }
+}
+
+// physical position of node idx at the level of slot s (FP64)
+__device__ __forceinline__ void node_pos(const Inst &P, long long idx, const BodySlot &s, double &x,
+                                         double &y) {
+    const double2 X = P.X[idx];
+    const double r = blend_factor(P.body, X.x, X.y);
+    x = X.x;
+    y = X.y;
+    if (r < 1.0) {
+        double dx, dy;
+        rigid_disp(P.body, s, X.x, X.y, dx, dy);
+        x += (1.0 - r) * dx;
+        y += (1.0 - r) * dy;
+    }
+}
+
+// Wall targets (Grad BC, Sec. III.A.1) for item.y even, far-field
+// equilibria (Sec. III.A.2) for item.y odd.
+//   rho_t, T_t : values at B (distance dt along the wall normal), 9-node
+//                Lagrange element centred on row 1; the wall row of the
+//                element holds the previous step's values
+//   u_t        : mesh velocity of the wall node (no slip on a moving wall)
+template <int STORE>
+__global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ insts,
+                                                      const int2 *__restrict__ work, int n_work) {
+    __shared__ float s_rho[3][BND + 2], s_T[3][BND + 2];
+    if ((int)blockIdx.x >= n_work) return;
+    const int2 item = work[blockIdx.x];
+    const Inst &P = insts[item.x];
+    const int kind = item.y & 1, i0 = (item.y >> 1) * BND;
+    const long long n = *P.step;
+    const void *src = P.pop[n & 1];
+    void *dst = P.pop[(n + 1) & 1];
+    const int ni = P.ni, nj = P.nj, t = threadIdx.x;
+    if (kind == 0) {
+        for (int e = t; e < 3 * (BND + 2); e += BND) {
+            const int r = e / (BND + 2), c = e % (BND + 2);
+            const int ig = wrap(i0 - 1 + c, ni);
+            float f[9], g[9];
+            load_node<STORE>(P, r == 0 ? src : dst, (long long)r * ni + ig, f, g);
+            const Moments m = moments(f, g, P.Cv);
+            s_rho[r][c] = m.rho;
+            s_T[r][c] = m.T;
+        }
+        __syncthreads();
+        const int ig = i0 + t;
+        if (ig >= ni) return;
+        const float2 B = P.wall_B[ig];
+        const float a = B.x, b = B.y - 1.0f;   // offsets from the element centre (i, 1)
+        float rho_t = 0.0f, T_t = 0.0f;
+#pragma unroll
+        for (int q = -1; q <= 1; ++q)
+#pragma unroll
+            for (int p = -1; p <= 1; ++p) {
+                const float w = lag(p, a) * lag(q, b);
+                rho_t += w * s_rho[q + 1][t + 1 + p];
+                T_t += w * s_T[q + 1][t + 1 + p];
+            }
+        float VGx = 0.0f, VGy = 0.0f;
+        const double2 X = P.X[ig];
+        const double r = blend_factor(P.body, X.x, X.y);
+        if (r < 1.0) {
+            double d1x, d1y, d0x, d0y;
+            rigid_disp(P.body, P.slots[(n + 1) % 3], X.x, X.y, d1x, d1y);
+            rigid_disp(P.body, P.slots[n % 3], X.x, X.y, d0x, d0y);
+            VGx = (float)((1.0 - r) * (d1x - d0x) / P.dt_d);
+            VGy = (float)((1.0 - r) * (d1y - d0y) / P.dt_d);
+        }
+        P.wall_tgt[ig] = make_float4(rho_t, VGx, VGy, T_t);
+    } else {
+        const int ig = i0 + t;
+        if (ig >= ni) return;
+        float rho, ux, uy, T;
+        if (P.inflow[ig]) {
+            rho = P.rho_inf; ux = P.ux_inf; uy = P.uy_inf; T = P.T_inf;
+        } else {  // outlet: zero gradient, copy the adjacent interior node
+            float f[9], g[9];
+            load_node<STORE>(P, dst, (long long)(nj - 2) * ni + ig, f, g);
+            const Moments m = moments(f, g, P.Cv);
+            rho = m.rho; ux = m.ux; uy = m.uy; T = m.T;
+        }
+        const float E = P.Cv * T + 0.5f * (ux * ux + uy * uy);
+        float feq[9], geq[9];
+        equilibria<float>(rho, ux, uy, T, E, feq, geq);
+        const long long idx = (long long)(nj - 1) * ni + ig;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            pop_store<STORE>(P, dst, k, idx, feq[k]);
+            pop_store<STORE>(P, dst, Q + k, idx, geq[k]);
+        }
+    }
+}
+
+// Grad populations for the missing wall populations (phase 1 only) and the
+// traction F_k = sigma . (n ds)_k of every wall node at the current level
+// (Sec. III: sigma = -p I - (1 - omega/2) P^(1), P^(1) = sum (f - f^eq) c c;
+// (n ds)_k = 1/2 rot_{+90}(x_{k+1} - x_{k-1})).
+template <int STORE>
+__global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict__ insts,
+                                                         const int2 *__restrict__ work, int n_work,
+                                                         int phase) {
+    if ((int)blockIdx.x >= n_work) return;
+    const int2 item = work[blockIdx.x];
+    const Inst &P = insts[item.x];
+    const int ni = P.ni;
+    const int ig = item.y * BND + threadIdx.x;
+    if (ig >= ni) return;
+    const long long n = *P.step;
+    const long long L = phase ? n + 1 : n;
+    void *buf = P.pop[L & 1];
+    const BodySlot sL = P.slots[L % 3];
+    const int im = wrap(ig - 1, ni), ip = wrap(ig + 1, ni);
+    double xm, ym, xp, yp, x0, y0;
+    node_pos(P, im, sL, xm, ym);
+    node_pos(P, ip, sL, xp, yp);
+    node_pos(P, ig, sL, x0, y0);
+    float f[9], g[9];
+    load_node<STORE>(P, buf, ig, f, g);
+    const float Cv = P.Cv, Cp = P.Cp, dt = P.dt;
+    if (phase) {
+        const uint16_t miss = P.wall_mask[ig];
+        if (miss) {
+            const float4 tm = P.wall_tgt[im], t0 = P.wall_tgt[ig], tp = P.wall_tgt[ip];
+            float f1[9], g1[9], f2[9], g2[9];
+            load_node<STORE>(P, buf, (long long)ni + ig, f1, g1);
+            load_node<STORE>(P, buf, 2LL * ni + ig, f2, g2);
+            const Moments m1 = moments(f1, g1, Cv), m2 = moments(f2, g2, Cv);
+            // metric of the mesh at t^{n+1} at the wall node: centred along the
+            // wall, one-sided into the fluid
+            double x1, y1, x2, y2;
+            node_pos(P, (long long)ni + ig, sL, x1, y1);
+            node_pos(P, 2LL * ni + ig, sL, x2, y2);
+            const float x_xi = (float)(0.5 * (xp - xm)), y_xi = (float)(0.5 * (yp - ym));
+            const float x_eta = (float)(2.0 * (x1 - x0) - 0.5 * (x2 - x0));
+            const float y_eta = (float)(2.0 * (y1 - y0) - 0.5 * (y2 - y0));
+            const float idet = 1.0f / (x_xi * y_eta - y_xi * x_eta);
+            const float rho_t = t0.x, ux_t = t0.y, uy_t = t0.z, T_t = t0.w;
+            const float E_t = Cv * T_t + 0.5f * (ux_t * ux_t + uy_t * uy_t);
+            const float Em = Cv * tm.w + 0.5f * (tm.y * tm.y + tm.z * tm.z);
+            const float Ep = Cv * tp.w + 0.5f * (tp.y * tp.y + tp.z * tp.z);
+            const float E1 = Cv * m1.T + 0.5f * (m1.ux * m1.ux + m1.uy * m1.uy);
+            const float E2 = Cv * m2.T + 0.5f * (m2.ux * m2.ux + m2.uy * m2.uy);
+            // (C_xi, C_eta) -> (dC/dx, dC/dy)
+            auto grad = [&](float cm, float c0, float cp, float c1, float c2, float &gx, float &gy) {
+                const float cxi = 0.5f * (cp - cm);
+                const float ceta = -1.5f * c0 + 2.0f * c1 - 0.5f * c2;
+                gx = idet * (y_eta * cxi - y_xi * ceta);
+                gy = idet * (-x_eta * cxi + x_xi * ceta);
+            };
+            float duxx, duxy, duyx, duyy, dTx, dTy, dEx, dEy;
+            grad(tm.y, ux_t, tp.y, m1.ux, m2.ux, duxx, duxy);
+            grad(tm.z, uy_t, tp.z, m1.uy, m2.uy, duyx, duyy);
+            grad(tm.w, T_t, tp.w, m1.T, m2.T, dTx, dTy);
+            grad(Em, E_t, Ep, E1, E2, dEx, dEy);
+            const float aa = P.mu / (rho_t * T_t * dt);
+            const float omega = 1.0f / (aa + 0.5f);
+            const float omega1 = 1.0f / (aa / P.Pr + 0.5f);
+            // S = grad u + grad u^T, (grad u)_ab = d_a u_b
+            const float Sxx = 2.0f * duxx, Syy = 2.0f * duyy, Sxy = duxy + duyx;
+            const float div = duxx + duyy;
+            const float pref = -rho_t * T_t / omega;
+            const float P1xx = pref * (Sxx - div / Cv);
+            const float P1yy = pref * (Syy - div / Cv);
+            const float P1xy = pref * Sxy;
+            const float q1x = -(2.0f / omega1) * rho_t * Cp * T_t * dTx + 2.0f * (ux_t * P1xx + uy_t * P1xy);
+            const float q1y = -(2.0f / omega1) * rho_t * Cp * T_t * dTy + 2.0f * (ux_t * P1xy + uy_t * P1yy);
+            const float rpref = -(2.0f / omega1) * rho_t * T_t;
+            const float e2 = E_t + 2.0f * T_t;
+            const float R1xx = rpref * (Sxx * e2 + 2.0f * ux_t * dEx);
+            const float R1yy = rpref * (Syy * e2 + 2.0f * uy_t * dEy);
+            const float R1xy = rpref * (Sxy * e2 + ux_t * dEy + uy_t * dEx);
+            float feq[9], geq[9];
+            equilibria<float>(rho_t, ux_t, uy_t, T_t, E_t, feq, geq);
+            const float w[3] = {0.5f * T_t, 1.0f - T_t, 0.5f * T_t};
+            const float invT = 1.0f / T_t, inv2T2 = 0.5f * invT * invT;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                if (!(miss & (1u << k))) continue;
+                const int cx = CXK(k), cy = CYK(k);
+                const float W = w[cx + 1] * w[cy + 1];
+                const float ccx = (float)(cx * cx) - T_t, ccy = (float)(cy * cy) - T_t;
+                const float cxy = 2.0f * (float)(cx * cy);
+                const float fneq = W * (P1xx * ccx + P1yy * ccy + P1xy * cxy) * inv2T2;
+                const float gneq = W * ((q1x * (float)cx + q1y * (float)cy) * invT +
+                                        (R1xx * ccx + R1yy * ccy + R1xy * cxy) * inv2T2);
+                f[k] = feq[k] + dt * fneq;
+                g[k] = geq[k] + dt * gneq;
+                pop_store<STORE>(P, buf, k, ig, f[k]);
+                pop_store<STORE>(P, buf, Q + k, ig, g[k]);
+            }
+        }
+    }
+    // traction of the complete wall node, with the moments formed in FP64
+    // from the stored populations
+    double fd[9], gd[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        fd[k] = f[k];
+        gd[k] = g[k];
+    }
+    double rho = 0, jx = 0, jy = 0, G = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        rho += fd[k];
+        jx += CXK(k) * fd[k];
+        jy += CYK(k) * fd[k];
+        G += gd[k];
+    }
+    const double ux = jx / rho, uy = jy / rho, E = 0.5 * G / rho;
+    const double T = (E - 0.5 * (ux * ux + uy * uy)) / (double)Cv;
+    double feq[9], geq[9];
+    equilibria<double>(rho, ux, uy, T, E, feq, geq);
+    double Pxx = 0.0, Pyy = 0.0, Pxy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double d = fd[k] - feq[k];
+        const int cx = CXK(k), cy = CYK(k);
+        Pxx += d * (double)(cx * cx);
+        Pyy += d * (double)(cy * cy);
+        Pxy += d * (double)(cx * cy);
+    }
+    const double p = rho * T;
+    const double omega = 1.0 / ((double)P.mu / (p * P.dt_d) + 0.5);
+    const double kk = 1.0 - 0.5 * omega;
+    const double sxx = -p - kk * Pxx, syy = -p - kk * Pyy, sxy = -kk * Pxy;
+    const double nx = -0.5 * (yp - ym), ny = 0.5 * (xp - xm);
+    const double Fx = sxx * nx + sxy * ny;
+    const double Fy = sxy * nx + syy * ny;
+    const double rx = x0 - P.body.ex, ry = y0 - (P.body.ey + sL.h);
+    P.wall_force[ig] = make_double4(Fx, Fy, rx * Fy - ry * Fx, 0.0);
+    if (!state_ok((float)rho, (float)ux, (float)uy, (float)T)) atomicOr(P.err, ERR_STATE);
+}
+
+// ---------------------------------------------------------------------------
+// Rigid body (Sec. IV): fixed-order FP64 traction sum, RK4 with the load
+// frozen over the step, or the prescribed motion.  One block per instance.
+// ---------------------------------------------------------------------------
+__device__ void body_accel(const Body &b, double h, double a, double Fy, double M, double &hdd,
+                           double &add) {
+    if (b.dof == DOF_HEAVE) {
+        hdd = (Fy - b.k_h * h) / b.m;
+        add = 0.0;
+    } else {  // pitch-plunge: [m S; S I] [h''; a''] = [Fy - k_h h; M - k_a a]
+        const double r1 = Fy - b.k_h * h, r2 = M - b.k_a * a;
+        const double det = b.m * b.I_a - b.S_a * b.S_a;
+        hdd = (b.I_a * r1 - b.S_a * r2) / det;
+        add = (-b.S_a * r1 + b.m * r2) / det;
+    }
+}
+
+__device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, double M, double t_next,
+                                 double dt) {
+    BodySlot o = s;
+    if (b.present && b.dof == DOF_PRESCRIBED) {
+        o.h = b.heave_amp * sin(b.heave_omega * t_next);
+        o.hd = b.heave_amp * b.heave_omega * cos(b.heave_omega * t_next);
+        o.a = b.pitch_amp * sin(b.pitch_omega * t_next);
+        o.ad = b.pitch_amp * b.pitch_omega * cos(b.pitch_omega * t_next);
+    } else if (b.present && (b.dof == DOF_HEAVE || b.dof == DOF_PITCH_PLUNGE)) {
+        double y[4] = {s.h, s.a, s.hd, s.ad}, k[4][4];
+        for (int st = 0; st < 4; ++st) {
+            const double c = st == 0 ? 0.0 : (st == 3 ? dt : 0.5 * dt);
+            double z[4];
+            for (int q = 0; q < 4; ++q) z[q] = st == 0 ? y[q] : y[q] + c * k[st - 1][q];
+            double hdd, add;
+            body_accel(b, z[0], z[1], Fy, M, hdd, add);
+            k[st][0] = z[2];
+            k[st][1] = z[3];
+            k[st][2] = hdd;
+            k[st][3] = add;
+        }
+        o.h = y[0] + dt / 6.0 * (k[0][0] + 2.0 * k[1][0] + 2.0 * k[2][0] + k[3][0]);
+        o.a = y[1] + dt / 6.0 * (k[0][1] + 2.0 * k[1][1] + 2.0 * k[2][1] + k[3][1]);
+        o.hd = y[2] + dt / 6.0 * (k[0][2] + 2.0 * k[1][2] + 2.0 * k[2][2] + k[3][2]);
+        o.ad = y[3] + dt / 6.0 * (k[0][3] + 2.0 * k[1][3] + 2.0 * k[2][3] + k[3][3]);
+    }
+    const double sh = sin(0.5 * o.a);
+    o.cm1 = -2.0 * sh * sh;
+    o.sa = sin(o.a);
+    return o;
+}
+
+constexpr int BODY_THREADS = 256;
+
+__global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ insts, int phase) {
+    __shared__ double sx[BODY_THREADS], sy[BODY_THREADS], sz[BODY_THREADS];
+    const Inst &P = insts[blockIdx.x];
+    const int t = threadIdx.x;
+    const long long n = *P.step;
+    const long long L = phase ? n + 1 : n;
+    double fx = 0.0, fy = 0.0, mz = 0.0;
+    if (!P.periodic_j) {
+        for (int i = t; i < P.ni; i += BODY_THREADS) {
+            const double4 v = P.wall_force[i];
+            fx += v.x;
+            fy += v.y;
+            mz += v.z;
+        }
+    }
+    sx[t] = fx; sy[t] = fy; sz[t] = mz;
+    __syncthreads();
+    for (int s = BODY_THREADS / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sx[t] += sx[t + s];
+            sy[t] += sy[t + s];
+            sz[t] += sz[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const BodySlot cur = P.slots[L % 3];
+        double *rec = P.history + (L % HIST_CAP) * 6;
+        rec[0] = (double)L; rec[1] = sx[0]; rec[2] = sy[0]; rec[3] = sz[0];
+        rec[4] = cur.h; rec[5] = cur.a;
+        P.slots[(L + 1) % 3] = body_advance(P.body, cur, sy[0], sz[0], (double)(L + 1) * P.dt_d, P.dt_d);
+        if (phase) *P.step = n + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial equilibria, macroscopic dump, storage codec
+// ---------------------------------------------------------------------------
+template <int STORE>
+__global__ void k_init_equilibrium(const Inst *__restrict__ pinst, const double *__restrict__ macro) {
+    const Inst &P = *pinst;
+    const long long N = P.n_nodes;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const double rho = macro[idx], ux = macro[N + idx], uy = macro[2 * N + idx], T = macro[3 * N + idx];
+        const double Cv = 1.0 / ((double)P.gamma - 1.0);
+        const double E = Cv * T + 0.5 * (ux * ux + uy * uy);
+        double feq[9], geq[9];
+        equilibria<double>(rho, ux, uy, T, E, feq, geq);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            pop_store<STORE>(P, P.pop[0], k, idx, (float)feq[k]);
+            pop_store<STORE>(P, P.pop[0], Q + k, idx, (float)geq[k]);
+        }
+    }
+}
+
+template <int STORE>
+__global__ void k_dump_macro(const Inst *__restrict__ pinst, int side, double *__restrict__ out) {
+    const Inst &P = *pinst;
+    const long long N = P.n_nodes;
+    const void *src = P.pop[side];
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        double rho = 0, jx = 0, jy = 0, G = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double fk = pop_load<STORE>(P, src, k, idx);
+            rho += fk;
+            jx += CXK(k) * fk;
+            jy += CYK(k) * fk;
+            G += (double)pop_load<STORE>(P, src, Q + k, idx);
+        }
+        const double ux = jx / rho, uy = jy / rho;
+        const double E = 0.5 * G / rho;
+        const double T = (E - 0.5 * (ux * ux + uy * uy)) * ((double)P.gamma - 1.0);
+        out[idx] = rho;
+        out[N + idx] = ux;
+        out[2 * N + idx] = uy;
+        out[3 * N + idx] = T;
+    }
+}
+
+template <int STORE>
+__global__ void k_decode(const Inst *__restrict__ pinst, int side, int q0, float *__restrict__ out) {
+    const Inst &P = *pinst;
+    const long long N = P.n_nodes;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 9 * N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int q = (int)(e / N);
+        out[e] = pop_load<STORE>(P, P.pop[side], q0 + q, e - q * N);
+    }
+}
+
+template <int STORE>
+__global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const float *__restrict__ in) {
+    const Inst &P = *pinst;
+    const long long N = P.n_nodes;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 9 * N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int q = (int)(e / N);
+        pop_store<STORE>(P, P.pop[side], q0 + q, e - q * N, in[e]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+#define FSI_DISPATCH(storage, KERNEL, GRID, BLOCK, STREAM, ...)                              \
+    do {                                                                                 \
+        if ((storage) == 0) hipLaunchKernelGGL(KERNEL<0>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); \
+        else hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__);          \
+    } while (0)
+
+hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
+                                 hipStream_t s) {
+    const int grid = ((n_work + 7) / 8) * 8;   // multiple of the XCD count
+    FSI_DISPATCH(storage, k_collide_stream, dim3(grid), dim3(K1_THREADS), s, insts, work, n_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,
+                               hipStream_t s) {
+    FSI_DISPATCH(storage, k_wall_targets, dim3(n_work), dim3(BND), s, insts, work, n_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_work, int storage,
+                                  int phase, hipStream_t s) {
+    FSI_DISPATCH(storage, k_wall_grad_force, dim3(n_work), dim3(BND), s, insts, work, n_work, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s) {
+    hipLaunchKernelGGL(k_body, dim3(n_inst), dim3(BODY_THREADS), 0, s, insts, phase);
+    return hipGetLastError();
+}
+
+static int io_grid(long long n) {
+    long long g = (n + 255) / 256;
+    return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,
+                                   int storage, hipStream_t s) {
+    FSI_DISPATCH(storage, k_init_equilibrium, dim3(io_grid(n_nodes)), dim3(256), s, inst, macro);
+    return hipGetLastError();
+}
+
+hipError_t launch_dump_macro(const Inst *inst, int side, double *out, long long n_nodes, int storage,
+                             hipStream_t s) {
+    FSI_DISPATCH(storage, k_dump_macro, dim3(io_grid(n_nodes)), dim3(256), s, inst, side, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const Inst *inst, int side, int q0, float *out, long long n_nodes, int storage,
+                         hipStream_t s) {
+    FSI_DISPATCH(storage, k_decode, dim3(io_grid(9 * n_nodes)), dim3(256), s, inst, side, q0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const Inst *inst, int side, int q0, const float *in, long long n_nodes,
+                         int storage, hipStream_t s) {
+    FSI_DISPATCH(storage, k_encode, dim3(io_grid(9 * n_nodes)), dim3(256), s, inst, side, q0, in);
+    return hipGetLastError();
+}
+
+}  // namespace fsi

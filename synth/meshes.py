@@ -81,7 +81,7 @@ def geometric_ratio(n_cells: int, first: float, span: float) -> float:
     """Ratio q with first * (q**n_cells - 1) / (q - 1) == span (bisection)."""
     if abs(first * n_cells - span) < 1e-12 * span:
         return 1.0
-    lo, hi = 1.0 + 1e-15, 2.0
+    lo, hi = 1.0 + 1e-15, 1.0 + min(1.0, 700.0 / n_cells)   # q**n_cells stays finite
     if first * n_cells > span:
         lo, hi = 1e-6, 1.0 - 1e-15
 
