@@ -12,7 +12,11 @@ constexpr int Q = 9;
 constexpr int NPOP = 18;            // f_0..f_8 then g_0..g_8
 constexpr int TILE_X = 64;          // nodes along i per tile (one wavefront width)
 constexpr int TILE_Y = 8;           // nodes along j per tile
-constexpr int K1_THREADS = 256;
+#ifndef FSI_K1_THREADS
+#define FSI_K1_THREADS 512
+#endif
+constexpr int K1_THREADS = FSI_K1_THREADS;      // threads per fused-kernel tile
+constexpr int K1_WAVES_PER_SIMD = (K1_THREADS / 64) * 2 / 4;   // two tiles per CU
 constexpr int HIST_CAP = 1 << 16;   // force / displacement history records kept
 
 // error bits of the device error word

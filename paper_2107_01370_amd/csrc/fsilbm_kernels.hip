@@ -137,127 +137,201 @@ __device__ __forceinline__ void equilibria(R rho, R ux, R uy, R T, R E, R feq[9]
     }
 }
 
-template <bool CHECK = true>
+// fast reciprocal (hardware v_rcp_f32, ~1 ulp); used where a correctly
+// rounded quotient is not needed
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// loads / stores through the global address space (the pointers live in
+// device memory, so the compiler would otherwise emit flat instructions)
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) const unsigned short gcushort;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) unsigned short gushort;
+
+__device__ __forceinline__ float gld(const float *p) { return *(gcfloat *)p; }
+__device__ __forceinline__ double2 gld(const double2 *p) {
+    gcdouble *q = (gcdouble *)p;
+    return make_double2(q[0], q[1]);
+}
+
+template <int STORE>
+__device__ __forceinline__ float pop_ld(const Inst &P, const void *base, int q, long long idx) {
+    if constexpr (STORE == 0) {
+        return gld(static_cast<const float *>(base) + q * P.n_nodes + idx);
+    } else {
+        const unsigned short h = *(gcushort *)(static_cast<const unsigned short *>(base) + q * P.n_nodes + idx);
+        return P.ref[q] + P.scale[q >= Q] * __half2float(__ushort_as_half(h));
+    }
+}
+
+template <int STORE>
+__device__ __forceinline__ void pop_st(const Inst &P, void *base, int q, long long idx, float v) {
+    if constexpr (STORE == 0) {
+        *(gfloat *)(static_cast<float *>(base) + q * P.n_nodes + idx) = v;
+    } else {
+        *(gushort *)(static_cast<unsigned short *>(base) + q * P.n_nodes + idx) =
+            __half_as_ushort(__float2half_rn((v - P.ref[q]) * P.inv_scale[q >= Q]));
+    }
+}
+
+// Collision at one node (Sec. II.C, kinetic equations):
+//   f* = f + omega (f^eq - f) + dt phi,  phi_i = -(W_i/T) c_i . F
+//   g* = g + omega (g^eq - g) + (omega_1 - omega)(g^* - g)
+//      = g + omega_1 (g^eq - g) + (omega_1 - omega) W_i (q^* - q^eq) . c_i / T
+// with q^* - q^eq = 2 u . (P - P^eq).
 __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float Fy, const Inst &P,
                                         unsigned &err) {
-    const Moments m = moments(f, g, P.Cv);
-    const float rho = m.rho, ux = m.ux, uy = m.uy, T = m.T, E = m.E;
-    if (CHECK && !state_ok(rho, ux, uy, T)) err |= ERR_STATE;
+    const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float ir = rcpf(rho);
+    const float ux = jx * ir, uy = jy * ir;
+    const float E = 0.5f * G * ir;
+    const float T = (E - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
+    if (!state_ok(rho, ux, uy, T)) err |= ERR_STATE;
     const float Pxx = (f[1] + f[3]) + (f[5] + f[6]) + (f[7] + f[8]);
     const float Pyy = (f[2] + f[4]) + (f[5] + f[6]) + (f[7] + f[8]);
     const float Pxy = (f[5] - f[6]) + (f[7] - f[8]);
     // omega from mu = (1/omega - 1/2) p dt; Pr = (1/omega - 1/2)/(1/omega_1 - 1/2)
-    const float a = P.mu / (rho * T * P.dt);
-    const float omega = 1.0f / (a + 0.5f);
-    const float omega1 = 1.0f / (a / P.Pr + 0.5f);
-    float feq[9], geq[9];
-    equilibria<float>(rho, ux, uy, T, E, feq, geq);
-    // q* - q^eq = 2 u . (P - P^eq)
+    const float a = P.mu * rcpf(rho * T * P.dt);
+    const float omega = rcpf(a + 0.5f);
+    const float omega1 = rcpf(a * rcpf(P.Pr) + 0.5f);
+    const float invT = rcpf(T);
+    // equilibria (product-form f^eq; g^eq with Psi)
+    const float px[3] = {0.5f * (-ux + ux * ux + T), 1.0f - (ux * ux + T), 0.5f * (ux + ux * ux + T)};
+    const float py[3] = {0.5f * (-uy + uy * uy + T), 1.0f - (uy * uy + T), 0.5f * (uy + uy * uy + T)};
+    const float w[3] = {0.5f * T, 1.0f - T, 0.5f * T};
+    const float inv2T2 = 0.5f * invT * invT;
+    const float H = E + T;
+    const float qx = 2.0f * rho * ux * H, qy = 2.0f * rho * uy * H;
+    const float e2 = E + 2.0f * T;
+    const float Axx = 2.0f * rho * (e2 * ux * ux + T * T);
+    const float Ayy = 2.0f * rho * (e2 * uy * uy + T * T);
+    const float Axy = 2.0f * rho * e2 * ux * uy;
+    const float c13 = rho * (1.0f - 3.0f * T) * invT;
+    const float dRx = c13 * (T * T + (2.0f * T + E) * ux * ux);
+    const float dRy = c13 * (T * T + (2.0f * T + E) * uy * uy);
+    const float two_rho_E = 2.0f * rho * E;
+    const float trA = T * (Axx + Ayy);
     const float dPxx = Pxx - rho * (T + ux * ux);
     const float dPyy = Pyy - rho * (T + uy * uy);
     const float dPxy = Pxy - rho * ux * uy;
     const float dqx = 2.0f * (ux * dPxx + uy * dPxy);
     const float dqy = 2.0f * (ux * dPxy + uy * dPyy);
-    const float invT = 1.0f / T;
-    const float w[3] = {0.5f * T, 1.0f - T, 0.5f * T};
-    const float cf = -P.dt * invT;                 // phi_i = -(W_i/T) c_i . F
-    const float cg = (omega1 - omega) * invT;      // g^* - g^eq = W_i dq . c_i / T
+    // per-direction vectors: f gets -dt F/T, g gets (omega_1 - omega) dq/T + q^eq/T
+    const float cf = -P.dt * invT, cg = (omega1 - omega) * invT;
+    const float vfx = cf * Fx, vfy = cf * Fy;
+    const float vgx = cg * dqx, vgy = cg * dqy;
+    const float qxT = qx * invT, qyT = qy * invT;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const int cx = CXK(k), cy = CYK(k);
         const float W = w[cx + 1] * w[cy + 1];
-        f[k] = f[k] + omega * (feq[k] - f[k]) + cf * W * (Fx * (float)cx + Fy * (float)cy);
-        g[k] = g[k] + omega1 * (geq[k] - g[k]) + cg * W * (dqx * (float)cx + dqy * (float)cy);
+        const float feq = rho * px[cx + 1] * py[cy + 1];
+        const float contr = Axx * (float)(cx * cx) + Ayy * (float)(cy * cy) +
+                            2.0f * Axy * (float)(cx * cy) - trA;
+        float psi = 0.0f;
+        if (k == 0) psi = dRx + dRy;
+        else if (cy == 0) psi = -0.5f * dRx;
+        else if (cx == 0) psi = -0.5f * dRy;
+        const float geq = W * (two_rho_E + qxT * (float)cx + qyT * (float)cy + contr * inv2T2) + psi;
+        f[k] = f[k] + omega * (feq - f[k]) + W * (vfx * (float)cx + vfy * (float)cy);
+        g[k] = g[k] + omega1 * (geq - g[k]) + W * (vgx * (float)cx + vgy * (float)cy);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Fused collision + ALE interpolating streaming.
 //
-// One workgroup owns a TILE_X x TILE_Y block of arrival nodes.  Because the
-// momentum correction needs nested gradients (reach 2) and the interpolation
-// stencil reaches one node, the tile is processed with a halo of 3:
-//   phase 1 (tile+3): load populations -> delta Q, mu/p;  X, r_blend -> LDS
-//   phase 2 (tile+2): D_a = (mu/p) d_a dQ_a on the mesh x^n        -> LDS
-//   phase 3 (tile+1): F_a = d_a D_a; collide                        -> LDS
+// One workgroup owns a TILE_X x TILE_Y block of arrival nodes.  The momentum
+// correction needs nested gradients (reach 2) and the interpolation stencil
+// reaches one node, so the tile is processed with a halo of 3:
+//   phase 1 (tile+3): populations -> delta Q_a, mu/p;  mesh geometry -> LDS
+//   phase 2 (tile+2): D_a = (mu/p) d_{x_a} dQ_a on the mesh x^n     -> LDS
+//   phase 3 (tile+1): F_a = d_{x_a} D_a; collide                     -> LDS
 //   phase 4 (tile)  : departure points on x^{n+1}, 3x3 Lagrange
 //                     interpolation from LDS, store f^{n+1}, g^{n+1}
+//
+// Geometry in LDS: undeformed coordinates X (FP64, with periodic shifts) and,
+// in FP32, the blended displacement at t^n relative to an FP64 reference
+// displacement of the tile (dn) and its increment over the step (dd).  All
+// coordinate differences are formed in FP64 (X) and FP32 (small relative
+// displacements), so metrics keep FP32 relative accuracy on meshes with large
+// absolute coordinates and displacements.
 // ---------------------------------------------------------------------------
 constexpr int R3X = TILE_X + 6, R3Y = TILE_Y + 6, R3N = R3X * R3Y;
 constexpr int R2X = TILE_X + 4, R2Y = TILE_Y + 4, R2N = R2X * R2Y;
 constexpr int R1X = TILE_X + 2, R1Y = TILE_Y + 2, R1N = R1X * R1Y;
+constexpr int NMOV = 16;     // moving populations kept in LDS (f_1..8, g_1..8)
 
 struct K1Smem {
     double X[R3N];
     double Y[R3N];
-    double R[R3N];           // blending factor r
-    float Dx[R2N], Dy[R2N];
+    float2 dn[R3N];          // (1 - r) d^n(X) - D_ref^n
+    float2 dd[R3N];          // (1 - r)(d^{n+1}(X) - d^n(X))
+    float2 D[R2N];           // nested correction, first level
     union {
         struct {
             float Qx[R3N], Qy[R3N], S[R3N];
         } q;
-        float FG[NPOP][R1N];
+        float FG[NMOV][R1N];
     } u;
 };
 
-// index-space derivative along j at relative row v of an R-region column:
-// centred inside, one-sided 3-point on the physical end rows of an O-grid.
+// index-space derivative along j: centred inside, one-sided 3-point on the
+// physical end rows of an O-grid
 struct JStencil {
-    int o0, o1, o2;          // row offsets
-    float w0, w1, w2;        // weights
+    int o1, o2;              // row offsets of the two other nodes
+    float w1, w2;            // d/dj = w1 (C_o1 - C_0) + w2 (C_o2 - C_0) ...
+    bool centred;            // ... or (C_{+1} - C_{-1}) / 2
 };
 
 __device__ __forceinline__ JStencil jstencil(const Inst &P, int jg) {
     JStencil s;
+    s.centred = true; s.o1 = 1; s.o2 = -1; s.w1 = 0.5f; s.w2 = -0.5f;
     if (!P.periodic_j && jg == 0) {
-        s.o0 = 0; s.o1 = 1; s.o2 = 2; s.w0 = -1.5f; s.w1 = 2.0f; s.w2 = -0.5f;
+        s.centred = false; s.o1 = 1; s.o2 = 2; s.w1 = 2.0f; s.w2 = -0.5f;
     } else if (!P.periodic_j && jg == P.nj - 1) {
-        s.o0 = 0; s.o1 = -1; s.o2 = -2; s.w0 = 1.5f; s.w1 = -2.0f; s.w2 = 0.5f;
-    } else {
-        s.o0 = -1; s.o1 = 1; s.o2 = 0; s.w0 = -0.5f; s.w1 = 0.5f; s.w2 = 0.0f;
+        s.centred = false; s.o1 = -1; s.o2 = -2; s.w1 = -2.0f; s.w2 = 0.5f;
     }
     return s;
 }
 
-__device__ __forceinline__ double jstencil_d(const JStencil &s, double a0, double a1, double a2) {
-    return (double)s.w0 * a0 + (double)s.w1 * a1 + (double)s.w2 * a2;
+// position difference x_a - x_b of two R3 entries: FP64 for X, FP32 for the
+// relative displacement; `level1` adds the step increment (mesh at t^{n+1})
+__device__ __forceinline__ float2 pos_diff(const K1Smem &sm, int a, int b, bool level1) {
+    float2 d;
+    d.x = (float)(sm.X[a] - sm.X[b]) + (sm.dn[a].x - sm.dn[b].x);
+    d.y = (float)(sm.Y[a] - sm.Y[b]) + (sm.dn[a].y - sm.dn[b].y);
+    if (level1) {
+        d.x += sm.dd[a].x - sm.dd[b].x;
+        d.y += sm.dd[a].y - sm.dd[b].y;
+    }
+    return d;
 }
 
-// physical position x(t) of an R3 entry: X + (1 - r) d(X)
-__device__ __forceinline__ void pos_at(const K1Smem &sm, const Body &b, const BodySlot &s, int e,
-                                      double &x, double &y) {
-    const double X = sm.X[e], Y = sm.Y[e], r = sm.R[e];
-    if (r >= 1.0) { x = X; y = Y; return; }
-    double dx, dy;
-    rigid_disp(b, s, X, Y, dx, dy);
-    x = X + (1.0 - r) * dx;
-    y = Y + (1.0 - r) * dy;
-}
-
-// metric (x_xi, x_eta, y_xi, y_eta) at R3 entry (u, v) of the mesh at slot s
-__device__ __forceinline__ void metric_at(const K1Smem &sm, const Body &b, const BodySlot &s,
-                                          const JStencil &js, int u, int v, float J[4]) {
-    double xp, yp, xm, ym;
-    pos_at(sm, b, s, v * R3X + u + 1, xp, yp);
-    pos_at(sm, b, s, v * R3X + u - 1, xm, ym);
-    J[0] = (float)(0.5 * (xp - xm));
-    J[2] = (float)(0.5 * (yp - ym));
-    double x0, y0, x1, y1, x2, y2;
-    pos_at(sm, b, s, (v + js.o0) * R3X + u, x0, y0);
-    pos_at(sm, b, s, (v + js.o1) * R3X + u, x1, y1);
-    if (js.w2 != 0.0f) {
-        pos_at(sm, b, s, (v + js.o2) * R3X + u, x2, y2);
-        // one-sided: form differences first to keep FP64 relative accuracy
-        J[1] = (float)((double)js.w1 * (x1 - x0) + (double)js.w2 * (x2 - x0));
-        J[3] = (float)((double)js.w1 * (y1 - y0) + (double)js.w2 * (y2 - y0));
+// metric (x_xi, x_eta, y_xi, y_eta) at R3 entry c
+__device__ __forceinline__ void metric(const K1Smem &sm, int c, const JStencil &js, bool level1,
+                                       float J[4]) {
+    const float2 di = pos_diff(sm, c + 1, c - 1, level1);
+    J[0] = 0.5f * di.x;
+    J[2] = 0.5f * di.y;
+    if (js.centred) {
+        const float2 dj = pos_diff(sm, c + R3X, c - R3X, level1);
+        J[1] = 0.5f * dj.x;
+        J[3] = 0.5f * dj.y;
     } else {
-        J[1] = (float)(0.5 * (x1 - x0));
-        J[3] = (float)(0.5 * (y1 - y0));
+        const float2 d1 = pos_diff(sm, c + js.o1 * R3X, c, level1);
+        const float2 d2 = pos_diff(sm, c + js.o2 * R3X, c, level1);
+        J[1] = js.w1 * d1.x + js.w2 * d2.x;
+        J[3] = js.w1 * d1.y + js.w2 * d2.y;
     }
 }
 
 template <int STORE>
-__global__ void __launch_bounds__(K1_THREADS, 2)
+__global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
 k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
     __shared__ K1Smem sm;
     // XCD-aware work mapping: consecutive dispatch slots go round-robin over the
@@ -266,9 +340,9 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
     const int nb = gridDim.x;
     const int per_xcd = (nb + 7) / 8;
     const int b = blockIdx.x;
-    const int w = (b % 8) * per_xcd + b / 8;
-    if (w >= n_work) return;
-    const int2 item = work[w];
+    const int wk = (b % 8) * per_xcd + b / 8;
+    if (wk >= n_work) return;
+    const int2 item = work[wk];
     const Inst &P = insts[item.x];
     const int tile = item.y;
     const int ti = tile % P.tiles_i, tj = tile / P.tiles_i;
@@ -283,225 +357,265 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
     const int t = threadIdx.x;
     unsigned err = 0;
 
+    // FP64 reference displacement of the tile: that of its first node
+    double Drx = 0.0, Dry = 0.0;
+    if (body.present) {
+        const double2 Xr = P.X[(long long)min(j0, nj - 1) * ni + i0];
+        const double r = blend_factor(body, Xr.x, Xr.y);
+        double dx, dy;
+        rigid_disp(body, sn, Xr.x, Xr.y, dx, dy);
+        Drx = (1.0 - r) * dx;
+        Dry = (1.0 - r) * dy;
+    }
+
     // ---- phase 1: tile+3 --------------------------------------------------
     for (int e = t; e < R3N; e += K1_THREADS) {
         const int u = e % R3X, v = e / R3X;
         int ig = i0 - 3 + u, jg = j0 - 3 + v;
-        // wrap into the mesh; coordinates of a node seen across a periodic seam
-        // are shifted by the period
-        const int wi = floor_div(ig, ni);
-        ig -= wi * ni;
-        double shx = wi * P.shift_ix, shy = wi * P.shift_iy;
+        // wrap into the mesh; a node seen across a periodic seam has its
+        // coordinates shifted by the period
+        int wi = 0, wj = 0;
+        while (ig < 0) { ig += ni; --wi; }
+        while (ig >= ni) { ig -= ni; ++wi; }
         bool valid = true;
         if (P.periodic_j) {
-            const int wj = floor_div(jg, nj);
-            jg -= wj * nj;
-            shx += wj * P.shift_jx;
-            shy += wj * P.shift_jy;
+            while (jg < 0) { jg += nj; --wj; }
+            while (jg >= nj) { jg -= nj; ++wj; }
         } else {
             valid = (jg >= 0 && jg < nj);
         }
         if (!valid) {
-            sm.X[e] = 0.0; sm.Y[e] = 0.0; sm.R[e] = 1.0;
+            sm.X[e] = 0.0; sm.Y[e] = 0.0;
+            sm.dn[e] = make_float2(0.0f, 0.0f); sm.dd[e] = make_float2(0.0f, 0.0f);
             sm.u.q.Qx[e] = 0.0f; sm.u.q.Qy[e] = 0.0f; sm.u.q.S[e] = 0.0f;
             continue;
         }
         const long long idx = (long long)jg * ni + ig;
-        const double2 Xr = P.X[idx];
-        sm.R[e] = blend_factor(body, Xr.x, Xr.y);   // from the unshifted node
-        sm.X[e] = Xr.x + shx;
-        sm.Y[e] = Xr.y + shy;
+        const double2 Xr = gld(P.X + idx);
+        float2 dn = make_float2((float)(-Drx), (float)(-Dry)), dd = make_float2(0.0f, 0.0f);
+        if (body.present) {
+            // blending factor and displacements from the unshifted node
+            const double r = blend_factor(body, Xr.x, Xr.y);
+            if (r < 1.0) {
+                double d0x, d0y, d1x, d1y;
+                rigid_disp(body, sn, Xr.x, Xr.y, d0x, d0y);
+                rigid_disp(body, sn1, Xr.x, Xr.y, d1x, d1y);
+                const double om = 1.0 - r;
+                dn = make_float2((float)(om * d0x - Drx), (float)(om * d0y - Dry));
+                dd = make_float2((float)(om * (d1x - d0x)), (float)(om * (d1y - d0y)));
+            }
+        }
+        sm.X[e] = Xr.x + (double)wi * P.shift_ix + (double)wj * P.shift_jx;
+        sm.Y[e] = Xr.y + (double)wi * P.shift_iy + (double)wj * P.shift_jy;
+        sm.dn[e] = dn;
+        sm.dd[e] = dd;
         float f[9], g[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_load<STORE>(P, src, k, idx);
-            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+            f[k] = pop_ld<STORE>(P, src, k, idx);
+            g[k] = pop_ld<STORE>(P, src, Q + k, idx);
         }
-        const Moments m = moments(f, g, P.Cv);
-        const float one3T = 1.0f - 3.0f * m.T;
-        sm.u.q.Qx[e] = m.rho * m.ux * (one3T - m.ux * m.ux);
-        sm.u.q.Qy[e] = m.rho * m.uy * (one3T - m.uy * m.uy);
-        sm.u.q.S[e] = P.mu / (m.rho * m.T);
+        const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+        const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+        const float ir = rcpf(rho);
+        const float ux = jx * ir, uy = jy * ir;
+        const float T = (0.5f * G * ir - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
+        const float one3T = 1.0f - 3.0f * T;
+        // delta Q_a = rho u_a (1 - 3T) - rho u_a^3
+        sm.u.q.Qx[e] = jx * (one3T - ux * ux);
+        sm.u.q.Qy[e] = jy * (one3T - uy * uy);
+        sm.u.q.S[e] = P.mu * rcpf(rho * T);       // (1/omega - 1/2) dt = mu / p
     }
     __syncthreads();
 
     // ---- phase 2: tile+2: D_a = (mu/p) d_{x_a} dQ_a --------------------------
     for (int e = t; e < R2N; e += K1_THREADS) {
         const int u2 = e % R2X, v2 = e / R2X;
-        const int u = u2 + 1, v = v2 + 1;             // R3 coordinates
         int jg = j0 - 2 + v2;
-        if (P.periodic_j) jg = wrap(jg, nj);
-        else if (jg < 0 || jg >= nj) { sm.Dx[e] = 0.0f; sm.Dy[e] = 0.0f; continue; }
+        if (P.periodic_j) {
+            while (jg < 0) jg += nj;
+            while (jg >= nj) jg -= nj;
+        } else if (jg < 0 || jg >= nj) {
+            sm.D[e] = make_float2(0.0f, 0.0f);
+            continue;
+        }
         const JStencil js = jstencil(P, jg);
+        const int c = (v2 + 1) * R3X + (u2 + 1);    // R3 index
         float J[4];
-        metric_at(sm, body, sn, js, u, v, J);
-        const float det = J[0] * J[3] - J[2] * J[1];
-        const int c = v * R3X + u;
+        metric(sm, c, js, false, J);
+        const float idet = rcpf(J[0] * J[3] - J[2] * J[1]);
         const float qx_xi = 0.5f * (sm.u.q.Qx[c + 1] - sm.u.q.Qx[c - 1]);
         const float qy_xi = 0.5f * (sm.u.q.Qy[c + 1] - sm.u.q.Qy[c - 1]);
-        const int r0 = (v + js.o0) * R3X + u, r1 = (v + js.o1) * R3X + u, r2 = (v + js.o2) * R3X + u;
-        const float qx_eta = js.w0 * sm.u.q.Qx[r0] + js.w1 * sm.u.q.Qx[r1] + js.w2 * sm.u.q.Qx[r2];
-        const float qy_eta = js.w0 * sm.u.q.Qy[r0] + js.w1 * sm.u.q.Qy[r1] + js.w2 * sm.u.q.Qy[r2];
-        const float s = sm.u.q.S[c] / det;
-        sm.Dx[e] = s * (J[3] * qx_xi - J[2] * qx_eta);
-        sm.Dy[e] = s * (-J[1] * qy_xi + J[0] * qy_eta);
+        float qx_eta, qy_eta;
+        if (js.centred) {
+            qx_eta = 0.5f * (sm.u.q.Qx[c + R3X] - sm.u.q.Qx[c - R3X]);
+            qy_eta = 0.5f * (sm.u.q.Qy[c + R3X] - sm.u.q.Qy[c - R3X]);
+        } else {
+            const int c1 = c + js.o1 * R3X, c2 = c + js.o2 * R3X;
+            qx_eta = js.w1 * (sm.u.q.Qx[c1] - sm.u.q.Qx[c]) + js.w2 * (sm.u.q.Qx[c2] - sm.u.q.Qx[c]);
+            qy_eta = js.w1 * (sm.u.q.Qy[c1] - sm.u.q.Qy[c]) + js.w2 * (sm.u.q.Qy[c2] - sm.u.q.Qy[c]);
+        }
+        const float s = sm.u.q.S[c] * idet;
+        sm.D[e] = make_float2(s * (J[3] * qx_xi - J[2] * qx_eta), s * (-J[1] * qy_xi + J[0] * qy_eta));
     }
     __syncthreads();
 
     // ---- phase 3: tile+1: F_a = d_{x_a} D_a, collide -> LDS ------------------
     for (int e = t; e < R1N; e += K1_THREADS) {
         const int u1 = e % R1X, v1 = e / R1X;
-        int ig = wrap(i0 - 1 + u1, ni), jg = j0 - 1 + v1;
-        if (P.periodic_j) jg = wrap(jg, nj);
-        else if (jg < 0 || jg >= nj) continue;
+        int ig = i0 - 1 + u1, jg = j0 - 1 + v1;
+        while (ig < 0) ig += ni;
+        while (ig >= ni) ig -= ni;
+        if (P.periodic_j) {
+            while (jg < 0) jg += nj;
+            while (jg >= nj) jg -= nj;
+        } else if (jg < 0 || jg >= nj) {
+            continue;
+        }
         const JStencil js = jstencil(P, jg);
         float J[4];
-        metric_at(sm, body, sn, js, u1 + 2, v1 + 2, J);
-        const float det = J[0] * J[3] - J[2] * J[1];
-        const int c = (v1 + 1) * R2X + (u1 + 1);     // R2 coordinates
-        const float dx_xi = 0.5f * (sm.Dx[c + 1] - sm.Dx[c - 1]);
-        const float dy_xi = 0.5f * (sm.Dy[c + 1] - sm.Dy[c - 1]);
-        const int r0 = c + js.o0 * R2X, r1 = c + js.o1 * R2X, r2 = c + js.o2 * R2X;
-        const float dx_eta = js.w0 * sm.Dx[r0] + js.w1 * sm.Dx[r1] + js.w2 * sm.Dx[r2];
-        const float dy_eta = js.w0 * sm.Dy[r0] + js.w1 * sm.Dy[r1] + js.w2 * sm.Dy[r2];
-        const float Fx = (J[3] * dx_xi - J[2] * dx_eta) / det;
-        const float Fy = (-J[1] * dy_xi + J[0] * dy_eta) / det;
+        metric(sm, (v1 + 2) * R3X + (u1 + 2), js, false, J);
+        const float idet = rcpf(J[0] * J[3] - J[2] * J[1]);
+        const int c = (v1 + 1) * R2X + (u1 + 1);     // R2 index
+        const float dx_xi = 0.5f * (sm.D[c + 1].x - sm.D[c - 1].x);
+        const float dy_xi = 0.5f * (sm.D[c + 1].y - sm.D[c - 1].y);
+        float dx_eta, dy_eta;
+        if (js.centred) {
+            dx_eta = 0.5f * (sm.D[c + R2X].x - sm.D[c - R2X].x);
+            dy_eta = 0.5f * (sm.D[c + R2X].y - sm.D[c - R2X].y);
+        } else {
+            const int c1 = c + js.o1 * R2X, c2 = c + js.o2 * R2X;
+            dx_eta = js.w1 * (sm.D[c1].x - sm.D[c].x) + js.w2 * (sm.D[c2].x - sm.D[c].x);
+            dy_eta = js.w1 * (sm.D[c1].y - sm.D[c].y) + js.w2 * (sm.D[c2].y - sm.D[c].y);
+        }
+        const float Fx = idet * (J[3] * dx_xi - J[2] * dx_eta);
+        const float Fy = idet * (-J[1] * dy_xi + J[0] * dy_eta);
         const long long idx = (long long)jg * ni + ig;
         float f[9], g[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_load<STORE>(P, src, k, idx);
-            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+            f[k] = pop_ld<STORE>(P, src, k, idx);
+            g[k] = pop_ld<STORE>(P, src, Q + k, idx);
         }
         collide(f, g, Fx, Fy, P, err);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            sm.u.FG[k][e] = f[k];
-            sm.u.FG[Q + k][e] = g[k];
+        for (int k = 1; k < 9; ++k) {
+            sm.u.FG[k - 1][e] = f[k];
+            sm.u.FG[7 + k][e] = g[k];
+        }
+        // rest populations do not move: store them for the tile's own nodes
+        const bool own = u1 >= 1 && u1 <= TILE_X && v1 >= 1 && v1 <= TILE_Y &&
+                         i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
+        if (own) {
+            pop_st<STORE>(P, dst, 0, idx, f[0]);
+            pop_st<STORE>(P, dst, Q, idx, g[0]);
         }
     }
     __syncthreads();
 
     // ---- phase 4: tile: departure points + interpolation ---------------------
     const float dtf = P.dt;
+    const float inv_dt = rcpf(dtf);
     for (int e = t; e < TILE_X * TILE_Y; e += K1_THREADS) {
         const int ut = e % TILE_X, vt = e / TILE_X;
         const int ig = i0 + ut, jg = j0 + vt;
         if (ig >= ni || jg >= nj) continue;
         if (!P.periodic_j && jg == nj - 1) continue;   // far-field row: boundary kernel
-        const int u = ut + 3, v = vt + 3;              // R3 coordinates
+        const int c3 = (vt + 3) * R3X + (ut + 3);
+        const bool wall = (!P.periodic_j && jg == 0);
         const JStencil js = jstencil(P, jg);
-        // mesh at t^{n+1}
+        // metric of the mesh at t^{n+1} and its inverse
         float J[4];
-        metric_at(sm, body, sn1, js, u, v, J);
+        metric(sm, c3, js, true, J);
         const float det = J[0] * J[3] - J[2] * J[1];
         if (!(det > 0.0f)) err |= ERR_MESH;
-        const float idet = 1.0f / det;
-        // undeformed metric (for the bilinear target) and the mesh velocity
-        const int c3 = v * R3X + u;
-        const double Xc = sm.X[c3], Yc = sm.Y[c3];
-        float VGx = 0.0f, VGy = 0.0f;
-        {
-            const double r = sm.R[c3];
-            if (r < 1.0) {
-                double d1x, d1y, d0x, d0y;
-                rigid_disp(body, sn1, Xc, Yc, d1x, d1y);
-                rigid_disp(body, sn, Xc, Yc, d0x, d0y);
-                VGx = (float)((1.0 - r) * (d1x - d0x) / P.dt_d);
-                VGy = (float)((1.0 - r) * (d1y - d0y) / P.dt_d);
-            }
-        }
-        // relative undeformed coordinates of the 3x3 neighbourhood
+        const float idet = rcpf(det);
+        // undeformed neighbourhood relative to the node: R[dj+1][di+1]
         float RX[3][3], RY[3][3];
+        const double Xc = sm.X[c3], Yc = sm.Y[c3];
 #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
             for (int di = -1; di <= 1; ++di) {
-                const int ee = (v + dj) * R3X + (u + di);
+                const int ee = c3 + dj * R3X + di;
                 RX[dj + 1][di + 1] = (float)(sm.X[ee] - Xc);
                 RY[dj + 1][di + 1] = (float)(sm.Y[ee] - Yc);
             }
-        const float BX_xi = 0.5f * (RX[1][2] - RX[1][0]), BY_xi = 0.5f * (RY[1][2] - RY[1][0]);
-        float BX_eta, BY_eta;
-        if (!P.periodic_j && jg == 0) {
-            const int e2 = (v + 2) * R3X + u;
-            const float RX2 = (float)(sm.X[e2] - Xc), RY2 = (float)(sm.Y[e2] - Yc);
-            BX_eta = 2.0f * RX[2][1] - 0.5f * RX2;
-            BY_eta = 2.0f * RY[2][1] - 0.5f * RY2;
+        // centred metric of X (one-sided into the fluid on the wall row)
+        const float BXxi = 0.5f * (RX[1][2] - RX[1][0]), BYxi = 0.5f * (RY[1][2] - RY[1][0]);
+        float BXeta, BYeta;
+        if (wall) {
+            const int e2 = c3 + 2 * R3X;
+            BXeta = 2.0f * RX[2][1] - 0.5f * (float)(sm.X[e2] - Xc);
+            BYeta = 2.0f * RY[2][1] - 0.5f * (float)(sm.Y[e2] - Yc);
         } else {
-            BX_eta = 0.5f * (RX[2][1] - RX[0][1]);
-            BY_eta = 0.5f * (RY[2][1] - RY[0][1]);
+            BXeta = 0.5f * (RX[2][1] - RX[0][1]);
+            BYeta = 0.5f * (RY[2][1] - RY[0][1]);
         }
-        const bool wall = (!P.periodic_j && jg == 0);
+        // mesh velocity V_G = (x^{n+1} - x^n)/dt
+        const float VGx = sm.dd[c3].x * inv_dt, VGy = sm.dd[c3].y * inv_dt;
+        // linear departure offsets are affine in c_i:
+        //   dxi_i = -dt (dx^{n+1}/dxi)^{-1} (c_i - V_G) = A c_i + B0
+        const float a11 = -dtf * idet * J[3], a12 = dtf * idet * J[1];
+        const float a21 = dtf * idet * J[2], a22 = -dtf * idet * J[0];
+        const float B0x = -(a11 * VGx + a12 * VGy), B0y = -(a21 * VGx + a22 * VGy);
         const int vc = wall ? 1 : 0;                   // stencil centre row offset
-        const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of stencil centre
+        const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
         const long long idx = (long long)jg * ni + ig;
         uint16_t miss = 0;
-        pop_store<STORE>(P, dst, 0, idx, sm.u.FG[0][(vt + 1) * R1X + ut + 1]);
-        pop_store<STORE>(P, dst, Q, idx, sm.u.FG[Q][(vt + 1) * R1X + ut + 1]);
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
-            const float wx = (float)CXK(k) - VGx, wy = (float)CYK(k) - VGy;
-            // linear estimate of the index-space offset: -dt (dx^{n+1}/dxi)^{-1} (c - V_G)
-            const float dxi = -dtf * idet * (J[3] * wx - J[1] * wy);
-            const float deta = -dtf * idet * (-J[2] * wx + J[0] * wy);
-            // target X_dp - X = (dX/dxi) dxi  (c^ = (dx/dX)^{-1}(c - V_G))
-            const float Px = BX_xi * dxi + BX_eta * deta;
-            const float Py = BY_xi * dxi + BY_eta * deta;
-            int ci = dxi < 0.0f ? -1 : 0;
-            int cj = deta < 0.0f ? -1 : 0;
-            if (wall) cj = 0;
-            float s = dxi - (float)ci, tt = deta - (float)cj;
-            for (int attempt = 0; attempt < 3; ++attempt) {
-                // corners of cell (ci, cj) relative to the node, by selection
-                // (ci, cj in {-1, 0}) so the 3x3 block stays in registers
-                const bool li = ci < 0, lj = cj < 0;
-                const float xa0 = li ? RX[0][0] : RX[0][1], xa1 = li ? RX[0][1] : RX[0][2];
-                const float xb0 = li ? RX[1][0] : RX[1][1], xb1 = li ? RX[1][1] : RX[1][2];
-                const float xc0 = li ? RX[2][0] : RX[2][1], xc1 = li ? RX[2][1] : RX[2][2];
-                const float ya0 = li ? RY[0][0] : RY[0][1], ya1 = li ? RY[0][1] : RY[0][2];
-                const float yb0 = li ? RY[1][0] : RY[1][1], yb1 = li ? RY[1][1] : RY[1][2];
-                const float yc0 = li ? RY[2][0] : RY[2][1], yc1 = li ? RY[2][1] : RY[2][2];
-                const float x00 = lj ? xa0 : xb0, x10 = lj ? xa1 : xb1;
-                const float x01 = lj ? xb0 : xc0, x11 = lj ? xb1 : xc1;
-                const float y00 = lj ? ya0 : yb0, y10 = lj ? ya1 : yb1;
-                const float y01 = lj ? yb0 : yc0, y11 = lj ? yb1 : yc1;
-                const float ax = x10 - x00, ay = y10 - y00;
-                const float bx = x01 - x00, by = y01 - y00;
-                const float cx = x11 - x10 - x01 + x00, cy = y11 - y10 - y01 + y00;
+            const float cx = (float)CXK(k), cy = (float)CYK(k);
+            const float dxi = a11 * cx + a12 * cy + B0x;
+            const float deta = a21 * cx + a22 * cy + B0y;
+            // target X_dp - X = (dX/dxi) dxi, since c^ = (dx/dX)^{-1}(c - V_G)
+            const float Px = BXxi * dxi + BXeta * deta;
+            const float Py = BYxi * dxi + BYeta * deta;
+            // quadrant (cell) holding X_dp, decided by which side of the straight
+            // cell edges through the node the target lies on (the linear estimate
+            // only seeds the choice); on the wall row only cells above exist
+            const bool ljg = !wall && deta < 0.0f;
+            float djx = ljg ? -RX[0][1] : RX[2][1], djy = ljg ? -RY[0][1] : RY[2][1];
+            bool li = djx * Py - djy * Px > 0.0f;
+            const float dix = li ? -RX[1][0] : RX[1][2], diy = li ? -RY[1][0] : RY[1][2];
+            const bool lj = !wall && (dix * Py - diy * Px < 0.0f);
+            djx = lj ? -RX[0][1] : RX[2][1];
+            djy = lj ? -RY[0][1] : RY[2][1];
+            li = djx * Py - djy * Px > 0.0f;
+            // bilinear first-order element of that cell: X(u,v) = u e_i + v e_j
+            // + u v tw with (u, v) in [0,1]^2
+            const float eix = li ? RX[1][0] : RX[1][2], eiy = li ? RY[1][0] : RY[1][2];
+            const float ejx = lj ? RX[0][1] : RX[2][1], ejy = lj ? RY[0][1] : RY[2][1];
+            const float ckx = lj ? (li ? RX[0][0] : RX[0][2]) : (li ? RX[2][0] : RX[2][2]);
+            const float cky = lj ? (li ? RY[0][0] : RY[0][2]) : (li ? RY[2][0] : RY[2][2]);
+            const float twx = ckx - eix - ejx, twy = cky - eiy - ejy;
+            const float im = rcpf(eix * ejy - eiy * ejx);
+            const float pu = im * (ejy * Px - ejx * Py), pv = im * (eix * Py - eiy * Px);
+            const float tu = im * (ejy * twx - ejx * twy), tv = im * (eix * twy - eiy * twx);
+            // u + tu u v = pu, v + tv u v = pv: fixed point from the linear
+            // solution (the twist is small for smooth cells)
+            float uu = pu, vv = pv;
 #pragma unroll
-                for (int it = 0; it < 3; ++it) {
-                    const float rx = x00 + ax * s + bx * tt + cx * s * tt - Px;
-                    const float ry = y00 + ay * s + by * tt + cy * s * tt - Py;
-                    const float jsx = ax + cx * tt, jsy = ay + cy * tt;
-                    const float jtx = bx + cx * s, jty = by + cy * s;
-                    const float id = 1.0f / (jsx * jty - jsy * jtx);
-                    s -= id * (jty * rx - jtx * ry);
-                    tt -= id * (-jsy * rx + jsx * ry);
-                }
-                const float eps = 1e-5f;
-                bool moved = false;
-                if (s < -eps && ci == 0) { ci = -1; s += 1.0f; moved = true; }
-                else if (s > 1.0f + eps && ci == -1) { ci = 0; s -= 1.0f; moved = true; }
-                if (!wall) {
-                    if (tt < -eps && cj == 0) { cj = -1; tt += 1.0f; moved = true; }
-                    else if (tt > 1.0f + eps && cj == -1) { cj = 0; tt -= 1.0f; moved = true; }
-                }
-                if (!moved) break;
+            for (int it = 0; it < 4; ++it) {
+                const float uv = uu * vv;
+                uu = pu - tu * uv;
+                vv = pv - tv * uv;
             }
-            const float a = (float)ci + s;
-            float bb = (float)cj + tt;
-            if (wall && tt < -1e-5f) { miss |= (uint16_t)(1u << k); continue; }
+            const float a = li ? -uu : uu;
+            float bb = lj ? -vv : vv;
+            if (wall && vv < -1e-5f) { miss |= (uint16_t)(1u << k); continue; }
             if (!(fabsf(a) <= 1.0f + 1e-4f) || !(fabsf(bb) <= 1.0f + 1e-4f)) err |= ERR_CFL;
             bb -= (float)vc;
             const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
             const float wbm = 0.5f * bb * (bb - 1.0f), wbp = 0.5f * bb * (bb + 1.0f);
-            // tensor-product quadratic Lagrange, written as centre + weighted
-            // differences so constants are reproduced exactly
+            // tensor-product quadratic Lagrange, as centre + weighted differences
+            // so that constants are reproduced exactly
             float outv[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const float *F = sm.u.FG[h * Q + k];
+                const float *F = sm.u.FG[h * 8 + k - 1];
                 float row[3];
 #pragma unroll
                 for (int dj = -1; dj <= 1; ++dj) {
@@ -511,14 +625,13 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
                 }
                 outv[h] = row[1] + wbm * (row[0] - row[1]) + wbp * (row[2] - row[1]);
             }
-            pop_store<STORE>(P, dst, k, idx, outv[0]);
-            pop_store<STORE>(P, dst, Q + k, idx, outv[1]);
+            pop_st<STORE>(P, dst, k, idx, outv[0]);
+            pop_st<STORE>(P, dst, Q + k, idx, outv[1]);
         }
         if (wall) P.wall_mask[ig] = miss;
     }
     if (err) atomicOr(P.err, err);
 }
-
 
 // ---------------------------------------------------------------------------
 // Boundary kernels (O-grid).  Work items (instance, block): 64 wall or

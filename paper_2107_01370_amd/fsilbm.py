@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libfsilbm.so")
+LIB_PATH = os.environ.get("FSILBM_LIB", os.path.join(_HERE, "lib", "libfsilbm.so"))
 
 FSI_OK = 0
 STATUS_NAMES = {0: "FSI_OK", -1: "FSI_E_ARG", -2: "FSI_E_MESH", -3: "FSI_E_CFL",

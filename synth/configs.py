@@ -103,6 +103,38 @@ def uniform_fields(mesh: MeshSpec, rho0: float, u0, T0: float):
             np.full(shape, float(u0[1])), np.full(shape, float(T0)))
 
 
+def cylinder_start_fields(mesh: MeshSpec, D: float, U: float, rho0: float, T0: float,
+                          delta: float, center=(0.0, 0.0), potential: bool = True):
+    """Smooth start for flow past a cylinder of diameter D: incompressible
+    potential flow (or a uniform stream) multiplied by tanh((r - R)/delta), so
+    the velocity rises from zero at the wall over a layer of width delta;
+    uniform density and temperature.  An impulsive start (free-stream velocity
+    on the no-slip wall) drives the Grad wall populations negative when
+    1/omega is large."""
+    R = 0.5 * D
+    dx = mesh.X - center[0]
+    dy = mesh.Y - center[1]
+    r = np.hypot(dx, dy)
+    layer = np.tanh(np.maximum(r - R, 0.0) / delta)
+    if potential:
+        c = dx / r
+        s = dy / r
+        a = (R / r) ** 2
+        ur = U * (1.0 - a) * c
+        ut = -U * (1.0 + a) * s
+        ux = (ur * c - ut * s) * layer
+        uy = (ur * s + ut * c) * layer
+    else:
+        ux = U * layer
+        uy = np.zeros_like(ux)
+    shape = mesh.X.shape
+    return np.full(shape, float(rho0)), ux, uy, np.full(shape, float(T0))
+
+
+def start_layer_width(D: float, first_cell: float) -> float:
+    return max(0.01 * D, 10.0 * first_cell)
+
+
 def acoustic_pulse_case(n: int = 64, amp_mesh: float = 0.05, dt: float = 1.0 / 3.0,
                         nu: float = 0.01, steps: int = 100) -> Case:
     """Static 64x64 periodic sine-deformed mesh, gas at rest, Gaussian pulse.
@@ -150,7 +182,7 @@ def cylinder_viv_case(n_r: int = 256, n_theta: int = 512, D: float = 200.0,
                         u_inf=(U, 0.0), dt=dt)
     body = heave_body_params(D, rho, U, mstar, ustar, r_rigid=0.5 * D,
                              r_blend=blend_D * D, h0=h0_frac * D)
-    r, ux, uy, T = uniform_fields(mesh, rho, (U, 0.0), T_inf)
+    r, ux, uy, T = cylinder_start_fields(mesh, D, U, rho, T_inf, start_layer_width(D, first))
     return Case(name or f"cylinder_viv_{n_r}x{n_theta}", mesh, fluid, [body],
                 r, ux, uy, T, steps,
                 info={"D": D, "U": U, "Ma": Ma, "Re": Re, "mstar": mstar,
@@ -175,7 +207,7 @@ def large_heave_case(n_r: int = 2048, n_theta: int = 4096, D: float = 1600.0,
     body = BodyParams(dof=DOF_PRESCRIBED, m=1.0, center=(0.0, 0.0), ea=(0.0, 0.0),
                       r_rigid=0.5 * D, r_blend=10.0 * D, heave_amp=0.2 * D,
                       heave_freq=0.2 * U / D)
-    r, ux, uy, T = uniform_fields(mesh, rho, (U, 0.0), T_inf)
+    r, ux, uy, T = cylinder_start_fields(mesh, D, U, rho, T_inf, start_layer_width(D, first))
     return Case(f"cylinder_heave_{n_r}x{n_theta}", mesh, fluid, [body], r, ux, uy,
                 T, steps, info={"D": D, "U": U, "Ma": Ma, "Re": Re})
 
