@@ -185,7 +185,8 @@ fsi_status fsi_time_kernels(fsi_ctx *ctx, int reps, double out_ms[4]);
 /* Message of the last error on this context (static storage of the context). */
 const char *fsi_last_error(const fsi_ctx *ctx);
 
-/* Release the context (not the caller's workspace). */
+/* Wait for the work queued on the context's stream, then release the context
+ * (not the caller's workspace, which may be freed once this returns). */
 void fsi_destroy(fsi_ctx *ctx);
 
 #ifdef __cplusplus

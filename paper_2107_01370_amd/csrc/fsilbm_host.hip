@@ -732,6 +732,8 @@ const char *fsi_last_error(const fsi_ctx *c) { return c ? c->err.c_str() : "null
 
 void fsi_destroy(fsi_ctx *c) {
     if (!c) return;
+    // the caller frees the workspace after this returns: drain queued work first
+    if (c->ws) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     delete c;
 }

@@ -43,6 +43,17 @@ __device__ __forceinline__ float pop_load(const Inst &P, const void *base, int q
     }
 }
 
+// the value a population reads back as after being stored
+template <int STORE>
+__device__ __forceinline__ float pop_round(const Inst &P, int q, float v) {
+    if constexpr (STORE == 0) {
+        return v;
+    } else {
+        const __half h = __float2half_rn((v - P.ref[q]) * P.inv_scale[q >= Q]);
+        return P.ref[q] + P.scale[q >= Q] * __half2float(h);
+    }
+}
+
 template <int STORE>
 __device__ __forceinline__ void pop_store(const Inst &P, void *base, int q, long long idx, float v) {
     if constexpr (STORE == 0) {
@@ -839,10 +850,11 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
                 const float fneq = W * (P1xx * ccx + P1yy * ccy + P1xy * cxy) * inv2T2;
                 const float gneq = W * ((q1x * (float)cx + q1y * (float)cy) * invT +
                                         (R1xx * ccx + R1yy * ccy + R1xy * cxy) * inv2T2);
-                f[k] = feq[k] + dt * fneq;
-                g[k] = geq[k] + dt * gneq;
-                pop_store<STORE>(P, buf, k, ig, f[k]);
-                pop_store<STORE>(P, buf, Q + k, ig, g[k]);
+                pop_store<STORE>(P, buf, k, ig, feq[k] + dt * fneq);
+                pop_store<STORE>(P, buf, Q + k, ig, geq[k] + dt * gneq);
+                // the traction below sees the populations as stored
+                f[k] = pop_round<STORE>(P, k, feq[k] + dt * fneq);
+                g[k] = pop_round<STORE>(P, Q + k, geq[k] + dt * gneq);
             }
         }
     }

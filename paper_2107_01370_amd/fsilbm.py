@@ -315,9 +315,11 @@ class Simulation:
         return fsi_time_kernels(self.ctx, reps)
 
     def close(self):
+        # fsi_destroy drains the stream before the workspace can be released
         if self.ctx:
             fsi_destroy(self.ctx)
             self.ctx = None
+        self.workspace = None
 
     def __del__(self):
         try:
