@@ -109,7 +109,8 @@ def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
 
     m = case.mesh
     strip = replace(m, nj=rows, X=m.X[:rows].copy(), Y=m.Y[:rows].copy())
-    ora = OracleSolver(strip, case.fluid, case.bodies)
+    ora = OracleSolver(strip, case.fluid, case.bodies, case.rho[:rows], case.ux[:rows],
+                       case.uy[:rows], case.T[:rows])
     ora.step()                         # warm-up (first-call overheads)
     t0 = time.perf_counter()
     n = 0
@@ -142,12 +143,22 @@ def main():
     ap.add_argument("--storage", choices=("fp32", "fp16"), default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy, the reference "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
     storage = 1 if args.storage == "fp16" else 0
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     case = workload_case(args.workload, storage)
     N = case.mesh.n_nodes
     total_ms, kms, finite = time_gpu(case, args.steps, args.warmup)
