@@ -10,8 +10,8 @@ namespace fsi {
 
 constexpr int Q = 9;
 constexpr int NPOP = 18;            // f_0..f_8 then g_0..g_8
-constexpr int TILE_X = 64;          // nodes along i per tile (one wavefront width)
-constexpr int TILE_Y = 8;           // nodes along j per tile
+constexpr int TILE_X = 32;          // nodes along i per tile
+constexpr int TILE_Y = 16;          // nodes along j per tile
 #ifndef FSI_K1_THREADS
 #define FSI_K1_THREADS 512
 #endif

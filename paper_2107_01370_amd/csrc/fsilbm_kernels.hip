@@ -236,20 +236,34 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
     const float vfx = cf * Fx, vfy = cf * Fy;
     const float vgx = cg * dqx, vgy = cg * dqy;
     const float qxT = qx * invT, qyT = qy * invT;
+    float feq[9], geq[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const int cx = CXK(k), cy = CYK(k);
         const float W = w[cx + 1] * w[cy + 1];
-        const float feq = rho * px[cx + 1] * py[cy + 1];
+        feq[k] = rho * px[cx + 1] * py[cy + 1];
         const float contr = Axx * (float)(cx * cx) + Ayy * (float)(cy * cy) +
                             2.0f * Axy * (float)(cx * cy) - trA;
         float psi = 0.0f;
         if (k == 0) psi = dRx + dRy;
         else if (cy == 0) psi = -0.5f * dRx;
         else if (cx == 0) psi = -0.5f * dRy;
-        const float geq = W * (two_rho_E + qxT * (float)cx + qyT * (float)cy + contr * inv2T2) + psi;
-        f[k] = f[k] + omega * (feq - f[k]) + W * (vfx * (float)cx + vfy * (float)cy);
-        g[k] = g[k] + omega1 * (geq - g[k]) + W * (vgx * (float)cx + vgy * (float)cy);
+        geq[k] = W * (two_rho_E + qxT * (float)cx + qyT * (float)cy + contr * inv2T2) + psi;
+    }
+    // Close the conserved moments of the equilibria on the stored moments, so
+    // FP32 rounding of the product form cannot make mass, momentum or energy
+    // drift coherently over many steps (the same identities, evaluated so that
+    // sum f^eq = rho, sum f^eq c = rho u and sum g^eq = 2 rho E hold to one rounding).
+    feq[1] = jx + ((feq[3] + feq[6] + feq[7]) - (feq[5] + feq[8]));
+    feq[2] = jy + ((feq[4] + feq[7] + feq[8]) - (feq[5] + feq[6]));
+    feq[0] = rho - (((feq[1] + feq[2]) + (feq[3] + feq[4])) + ((feq[5] + feq[6]) + (feq[7] + feq[8])));
+    geq[0] = G - (((geq[1] + geq[2]) + (geq[3] + geq[4])) + ((geq[5] + geq[6]) + (geq[7] + geq[8])));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = CXK(k), cy = CYK(k);
+        const float W = w[cx + 1] * w[cy + 1];
+        f[k] = f[k] + omega * (feq[k] - f[k]) + W * (vfx * (float)cx + vfy * (float)cy);
+        g[k] = g[k] + omega1 * (geq[k] - g[k]) + W * (vgx * (float)cx + vgy * (float)cy);
     }
 }
 
@@ -341,6 +355,28 @@ __device__ __forceinline__ void metric(const K1Smem &sm, int c, const JStencil &
     }
 }
 
+// Phase-1 work item p -> R3 entry: the tile+1 region first (row-major), then
+// the ring of tile+3 outside it, so that a thread's phase-1 items below R1N
+// are exactly its phase-3 collision nodes (their populations stay in
+// registers between the two phases).
+constexpr int RING_ROWS = 2 * 2 * R3X;       // two rows above and below R1
+constexpr int R1_ROUNDS = (R1N + K1_THREADS - 1) / K1_THREADS;
+static_assert(R1_ROUNDS == 2, "phase-1/3 register hand-off assumes two rounds");
+
+__device__ __forceinline__ int phase1_entry(int p) {
+    if (p < R1N) return (p / R1X + 2) * R3X + (p % R1X + 2);
+    const int q = p - R1N;
+    if (q < RING_ROWS) {
+        const int r = q / R3X, c = q % R3X;
+        const int row = r < 2 ? r : R3Y - 4 + r;   // rows 0, 1, R3Y-2, R3Y-1
+        return row * R3X + c;
+    }
+    const int q2 = q - RING_ROWS;                 // columns 0, 1, R3X-2, R3X-1 of rows 2..R3Y-3
+    const int row = 2 + q2 / 4, k = q2 % 4;
+    const int col = k < 2 ? k : R3X - 4 + k;
+    return row * R3X + col;
+}
+
 template <int STORE>
 __global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
 k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
@@ -379,8 +415,15 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         Dry = (1.0 - r) * dy;
     }
 
+    // populations of this thread's collision nodes, kept from phase 1
+    float fk[R1_ROUNDS][9], gk[R1_ROUNDS][9];
+
     // ---- phase 1: tile+3 --------------------------------------------------
-    for (int e = t; e < R3N; e += K1_THREADS) {
+#pragma unroll
+    for (int rd = 0; rd < (R3N + K1_THREADS - 1) / K1_THREADS; ++rd) {
+        const int p = rd * K1_THREADS + t;
+        if (p >= R3N) break;
+        const int e = phase1_entry(p);
         const int u = e % R3X, v = e / R3X;
         int ig = i0 - 3 + u, jg = j0 - 3 + v;
         // wrap into the mesh; a node seen across a periodic seam has its
@@ -425,6 +468,13 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         for (int k = 0; k < 9; ++k) {
             f[k] = pop_ld<STORE>(P, src, k, idx);
             g[k] = pop_ld<STORE>(P, src, Q + k, idx);
+        }
+        if (rd < R1_ROUNDS && p < R1N) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                fk[rd][k] = f[k];
+                gk[rd][k] = g[k];
+            }
         }
         const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
         const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -474,7 +524,10 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
     __syncthreads();
 
     // ---- phase 3: tile+1: F_a = d_{x_a} D_a, collide -> LDS ------------------
-    for (int e = t; e < R1N; e += K1_THREADS) {
+#pragma unroll
+    for (int rd = 0; rd < R1_ROUNDS; ++rd) {
+        const int e = rd * K1_THREADS + t;           // R1 index (= phase-1 item)
+        if (e >= R1N) break;
         const int u1 = e % R1X, v1 = e / R1X;
         int ig = i0 - 1 + u1, jg = j0 - 1 + v1;
         while (ig < 0) ig += ni;
@@ -503,12 +556,11 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         }
         const float Fx = idet * (J[3] * dx_xi - J[2] * dx_eta);
         const float Fy = idet * (-J[1] * dy_xi + J[0] * dy_eta);
-        const long long idx = (long long)jg * ni + ig;
         float f[9], g[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_ld<STORE>(P, src, k, idx);
-            g[k] = pop_ld<STORE>(P, src, Q + k, idx);
+            f[k] = fk[rd][k];
+            g[k] = gk[rd][k];
         }
         collide(f, g, Fx, Fy, P, err);
 #pragma unroll
@@ -520,6 +572,7 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         const bool own = u1 >= 1 && u1 <= TILE_X && v1 >= 1 && v1 <= TILE_Y &&
                          i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
         if (own) {
+            const long long idx = (long long)jg * ni + ig;
             pop_st<STORE>(P, dst, 0, idx, f[0]);
             pop_st<STORE>(P, dst, Q, idx, g[0]);
         }
@@ -568,10 +621,14 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         // mesh velocity V_G = (x^{n+1} - x^n)/dt
         const float VGx = sm.dd[c3].x * inv_dt, VGy = sm.dd[c3].y * inv_dt;
         // linear departure offsets are affine in c_i:
-        //   dxi_i = -dt (dx^{n+1}/dxi)^{-1} (c_i - V_G) = A c_i + B0
+        //   dxi_i = -dt (dx^{n+1}/dxi)^{-1} (c_i - V_G) = A c_i + B0,
+        // and so is the target X_dp - X = (dX/dxi) dxi_i = (B A) c_i + B B0
         const float a11 = -dtf * idet * J[3], a12 = dtf * idet * J[1];
         const float a21 = dtf * idet * J[2], a22 = -dtf * idet * J[0];
         const float B0x = -(a11 * VGx + a12 * VGy), B0y = -(a21 * VGx + a22 * VGy);
+        const float p11 = BXxi * a11 + BXeta * a21, p12 = BXxi * a12 + BXeta * a22;
+        const float p21 = BYxi * a11 + BYeta * a21, p22 = BYxi * a12 + BYeta * a22;
+        const float P0x = BXxi * B0x + BXeta * B0y, P0y = BYxi * B0x + BYeta * B0y;
         const int vc = wall ? 1 : 0;                   // stencil centre row offset
         const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
         const long long idx = (long long)jg * ni + ig;
@@ -579,11 +636,9 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
             const float cx = (float)CXK(k), cy = (float)CYK(k);
-            const float dxi = a11 * cx + a12 * cy + B0x;
             const float deta = a21 * cx + a22 * cy + B0y;
-            // target X_dp - X = (dX/dxi) dxi, since c^ = (dx/dX)^{-1}(c - V_G)
-            const float Px = BXxi * dxi + BXeta * deta;
-            const float Py = BYxi * dxi + BYeta * deta;
+            const float Px = p11 * cx + p12 * cy + P0x;
+            const float Py = p21 * cx + p22 * cy + P0y;
             // quadrant (cell) holding X_dp, decided by which side of the straight
             // cell edges through the node the target lies on (the linear estimate
             // only seeds the choice); on the wall row only cells above exist
