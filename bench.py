@@ -99,6 +99,62 @@ def time_gpu(case, steps: int, warmup: int, kernel_reps: int = 20):
     return total_ms, kms, finite
 
 
+def time_batch(cases, steps: int, warmup: int, kernel_reps: int = 10):
+    """All instances in one Batch: one launch per kernel per step, schedule
+    picked by the library's autotuner."""
+    import torch
+
+    from paper_2107_01370_amd.fsilbm import Batch
+
+    b = Batch(cases, device="cuda:0")
+    for k, c in enumerate(cases):
+        b.init_equilibrium(k, c.rho, c.ux, c.uy, c.T)
+    b.step(warmup)
+    b.synchronize()
+    grid, order, _ = b.autotune(reps=5)
+    b.step(2)                                  # capture the tuned graph
+    b.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    b.step(steps)
+    stop.record(b.stream)
+    stop.synchronize()
+    b.synchronize()
+    total_ms = start.elapsed_time(stop)
+    kms = b.time_kernels(kernel_reps)
+    finite = all(bool(np.all(np.isfinite(b.macro(k)[0]))) for k in range(len(cases)))
+    b.close()
+    return total_ms, kms, (grid, order), finite
+
+
+def time_sequential(cases, steps: int, warmup: int):
+    """The same instances each in its own Simulation, run one after another
+    (per-instance launches, one HIP graph per step each)."""
+    import torch
+
+    from paper_2107_01370_amd.fsilbm import Simulation
+
+    sims = []
+    for c in cases:
+        s = Simulation(c.mesh, c.fluid, c.bodies, device="cuda:0")
+        s.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+        s.step(warmup)
+        sims.append(s)
+    for s in sims:
+        s.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    for s in sims:
+        s.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    for s in sims:
+        s.close()
+    return total_ms
+
+
 def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
     """Oracle (plain FP64 NumPy) timed on a strip of the same workload: the
     first `rows` radial rows of the O-grid (wall included) with the same
@@ -215,6 +271,25 @@ def main():
             "achieved_GBs": round(algorithmic_bytes_per_node(1) * N / (float(k16[0]) * 1e-3) / 1e9, 1),
             "finite_state": fin16,
         }]
+    if not args.no_variants and args.workload == "cylinder_heave_2048x4096" and storage == 0:
+        cases = synth.batched_sweep_cases(64)
+        nb = sum(c.mesh.n_nodes for c in cases)
+        bsteps = max(1, args.steps // 2)
+        tb, kb, sched, finb = time_batch(cases, bsteps, args.warmup)
+        ts = time_sequential(cases, bsteps, args.warmup)
+        out["variants"].append({
+            "workload": "batched_sweep_64: 64 independent 1DOF cylinder instances, "
+                        "n_r ~ U[128,384], n_theta = 2 n_r, seed 0, FP32 storage",
+            "nodes": nb,
+            "steps": bsteps,
+            "batched_MLUPS": round(nb * bsteps / (tb * 1e-3) / 1e6, 1),
+            "batched_ms_per_step": round(tb / bsteps, 5),
+            "schedule": {"grid": sched[0], "order": sched[1]},
+            "collide_stream_ms": round(float(kb[0]), 5),
+            "achieved_GBs": round(bpn * nb / (float(kb[0]) * 1e-3) / 1e9, 1),
+            "one_at_a_time_MLUPS": round(nb * bsteps / (ts * 1e-3) / 1e6, 1),
+            "finite_state": finb,
+        })
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -182,6 +182,51 @@ fsi_status fsi_load(fsi_ctx *ctx, const void *host_buf, size_t bytes);
  * topology does not use).  Synchronises. */
 fsi_status fsi_time_kernels(fsi_ctx *ctx, int reps, double out_ms[4]);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent instances (each one mesh + at most one body, of
+ * any sizes) advanced together.  Every step is ONE launch of each kernel over
+ * the concatenated work items of all instances, captured in one HIP graph.
+ * Instances keep their own parameters, state, history and error word.
+ * ------------------------------------------------------------------------- */
+typedef struct fsi_batch fsi_batch;
+
+/* Create a batch of n instances: fluids[n], meshes[n]; bodies[k] is used for
+ * instance k when nbodies[k] == 1 (nbodies may be NULL: no bodies).  All
+ * instances must use the same storage precision.  Validation as fsi_create;
+ * the failing instance is named in fsi_batch_last_error(). */
+fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mesh_desc *meshes,
+                            const fsi_body_desc *bodies, const int *nbodies, void *hip_stream,
+                            fsi_batch **out);
+fsi_status fsi_batch_workspace_bytes(const fsi_batch *b, size_t *bytes);
+fsi_status fsi_batch_bind_workspace(fsi_batch *b, void *dev_ptr, size_t bytes);
+/* Initial equilibria of instance k (NULL fields = its free stream). */
+fsi_status fsi_batch_init_equilibrium(fsi_batch *b, int k, const double *rho, const double *ux,
+                                      const double *uy, const double *T);
+/* Work distribution of the collision-streaming launch: `grid` workgroups (0 =
+ * one per work item; otherwise a persistent grid, rounded to a multiple of 8)
+ * and `order` of the work items (0: instance after instance, 1: instances by
+ * decreasing size).  Invalidates the captured graph. */
+fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order);
+/* Time candidate schedules on the current state and keep the fastest: for
+ * each (grid, order) candidate, `reps` launches of the collision-streaming
+ * kernel (each recomputes the same values, so the state is unchanged);
+ * best[3] = {grid, order, mean ms per launch}.  Synchronises. */
+fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[3]);
+fsi_status fsi_batch_step(fsi_batch *b, int nsteps);
+fsi_status fsi_batch_synchronize(fsi_batch *b);
+/* Per-instance queries, as the single-instance calls. */
+fsi_status fsi_batch_get_forces(fsi_batch *b, int k, int64_t first, int count, double *out);
+fsi_status fsi_batch_get_body_state(fsi_batch *b, int k, double out[4]);
+fsi_status fsi_batch_dump_macro(fsi_batch *b, int k, double *rho, double *ux, double *uy,
+                                double *T);
+fsi_status fsi_batch_get_populations(fsi_batch *b, int k, float *f, float *g);
+/* Mean ms per launch of the batched kernels, as fsi_time_kernels. */
+fsi_status fsi_batch_time_kernels(fsi_batch *b, int reps, double out_ms[4]);
+int64_t fsi_batch_nodes(const fsi_batch *b);
+const char *fsi_batch_last_error(const fsi_batch *b);
+/* Waits for queued work, then releases the batch (not the workspace). */
+void fsi_batch_destroy(fsi_batch *b);
+
 /* Message of the last error on this context (static storage of the context). */
 const char *fsi_last_error(const fsi_ctx *ctx);
 

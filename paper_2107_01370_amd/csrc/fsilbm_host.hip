@@ -739,3 +739,357 @@ void fsi_destroy(fsi_ctx *c) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent instances
+// ---------------------------------------------------------------------------
+struct fsi_batch {
+    std::vector<fsi_ctx *> ctx;
+    hipStream_t stream = nullptr;
+    int storage = 0;
+    bool any_wall = false;
+    size_t off_insts = 0, off_wk1 = 0, off_wbnd = 0, off_wwall = 0, total = 0;
+    std::vector<size_t> off_region;
+    char *ws = nullptr;
+    std::vector<int2> wk1, wbnd, wwall;
+    int grid = 0, order = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+fsi_status bfail(fsi_batch *b, fsi_status st, const std::string &msg) {
+    if (b) b->err = msg;
+    return st;
+}
+
+#define BHIP_TRY(b, expr)                                                            \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) return bfail(b, FSI_E_HIP, std::string(#expr) + ": " + \
+                                                         hipGetErrorString(e_));     \
+    } while (0)
+
+void batch_drop_graph(fsi_batch *b) {
+    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+}
+
+void batch_lists(fsi_batch *b) {
+    const int n = (int)b->ctx.size();
+    std::vector<int> ord(n);
+    for (int k = 0; k < n; ++k) ord[k] = k;
+    if (b->order == 1)
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+            return b->ctx[a]->inst.n_nodes > b->ctx[c]->inst.n_nodes;
+        });
+    b->wk1.clear();
+    b->wbnd.clear();
+    b->wwall.clear();
+    for (int k : ord) {
+        const Inst &P = b->ctx[k]->inst;
+        for (int t = 0; t < P.tiles_i * P.tiles_j; ++t) b->wk1.push_back(make_int2(k, t));
+    }
+    for (int k = 0; k < n; ++k) {
+        if (b->ctx[k]->topo != FSI_TOPO_OGRID) continue;
+        const int nb = (b->ctx[k]->ni + 63) / 64;
+        for (int q = 0; q < nb; ++q) {
+            b->wbnd.push_back(make_int2(k, 2 * q));
+            b->wbnd.push_back(make_int2(k, 2 * q + 1));
+            b->wwall.push_back(make_int2(k, q));
+        }
+    }
+}
+
+fsi_status batch_upload_lists(fsi_batch *b) {
+    BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_wk1, b->wk1.data(), b->wk1.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, b->stream));
+    if (!b->wbnd.empty()) {
+        BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_wbnd, b->wbnd.data(), b->wbnd.size() * sizeof(int2),
+                                   hipMemcpyHostToDevice, b->stream));
+        BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_wwall, b->wwall.data(), b->wwall.size() * sizeof(int2),
+                                   hipMemcpyHostToDevice, b->stream));
+    }
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    return FSI_OK;
+}
+
+const Inst *b_insts(fsi_batch *b) { return reinterpret_cast<const Inst *>(b->ws + b->off_insts); }
+
+fsi_status batch_enqueue_k1(fsi_batch *b) {
+    BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk1),
+                                           (int)b->wk1.size(), b->storage, b->stream, b->grid));
+    return FSI_OK;
+}
+
+fsi_status batch_enqueue_step(fsi_batch *b) {
+    fsi_status st = batch_enqueue_k1(b);
+    if (st != FSI_OK) return st;
+    if (b->any_wall) {
+        BHIP_TRY(b, fsi::launch_wall_targets(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wbnd),
+                                             (int)b->wbnd.size(), b->storage, b->stream));
+        BHIP_TRY(b, fsi::launch_wall_grad_force(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wwall),
+                                                (int)b->wwall.size(), b->storage, 1, b->stream));
+    }
+    BHIP_TRY(b, fsi::launch_body(b_insts(b), (int)b->ctx.size(), 1, b->stream));
+    return FSI_OK;
+}
+
+fsi_status batch_ready(fsi_batch *b, int k) {
+    if (!b) return FSI_E_ARG;
+    if (!b->ws) return bfail(b, FSI_E_UNBOUND, "workspace not bound");
+    if (k >= (int)b->ctx.size()) return bfail(b, FSI_E_ARG, "no such instance");
+    if (k < 0)
+        for (fsi_ctx *c : b->ctx)
+            if (!c->initialized) return bfail(b, FSI_E_UNBOUND, "an instance is not initialised");
+    return FSI_OK;
+}
+
+// forward a per-instance status and message
+fsi_status bfwd(fsi_batch *b, int k, fsi_status st) {
+    if (st != FSI_OK) b->err = "instance " + std::to_string(k) + ": " + b->ctx[k]->err;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mesh_desc *meshes,
+                            const fsi_body_desc *bodies, const int *nbodies, void *hip_stream,
+                            fsi_batch **out) {
+    if (!out) return FSI_E_ARG;
+    *out = nullptr;
+    fsi_batch *b = new (std::nothrow) fsi_batch();
+    if (!b) return FSI_E_NOMEM;
+    *out = b;
+    if (n < 1 || !fluids || !meshes) return bfail(b, FSI_E_ARG, "need n >= 1 fluids and meshes");
+    b->stream = (hipStream_t)hip_stream;
+    for (int k = 0; k < n; ++k) {
+        const int nb = nbodies ? nbodies[k] : 0;
+        if (nb && !bodies) return bfail(b, FSI_E_ARG, "bodies missing");
+        fsi_ctx *c = nullptr;
+        const fsi_status st = fsi_create(&fluids[k], &meshes[k], nb ? &bodies[k] : nullptr, nb,
+                                         hip_stream, &c);
+        if (st != FSI_OK) {
+            b->err = "instance " + std::to_string(k) + ": " + (c ? c->err : std::string("create failed"));
+            fsi_destroy(c);
+            return st;
+        }
+        b->ctx.push_back(c);
+        if (k == 0) b->storage = c->fluid.storage;
+        if (c->fluid.storage != b->storage) return bfail(b, FSI_E_ARG, "mixed storage precisions");
+        if (c->topo == FSI_TOPO_OGRID) b->any_wall = true;
+    }
+    batch_lists(b);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
+    b->off_insts = take(n * sizeof(Inst));
+    b->off_wk1 = take(b->wk1.size() * sizeof(int2));
+    b->off_wbnd = take(b->wbnd.size() * sizeof(int2));
+    b->off_wwall = take(b->wwall.size() * sizeof(int2));
+    for (fsi_ctx *c : b->ctx) b->off_region.push_back(take(c->total));
+    b->total = o;
+    return FSI_OK;
+}
+
+fsi_status fsi_batch_workspace_bytes(const fsi_batch *b, size_t *bytes) {
+    if (!b || !bytes) return FSI_E_ARG;
+    *bytes = b->total;
+    return FSI_OK;
+}
+
+fsi_status fsi_batch_bind_workspace(fsi_batch *b, void *dev_ptr, size_t bytes) {
+    if (!b || !dev_ptr) return FSI_E_ARG;
+    if (((uintptr_t)dev_ptr & 255) != 0) return bfail(b, FSI_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < b->total) return bfail(b, FSI_E_ARG, "workspace too small");
+    batch_drop_graph(b);
+    b->ws = static_cast<char *>(dev_ptr);
+    std::vector<Inst> insts(b->ctx.size());
+    for (size_t k = 0; k < b->ctx.size(); ++k) {
+        fsi_status st = fsi_bind_workspace(b->ctx[k], b->ws + b->off_region[k], b->ctx[k]->total);
+        if (st != FSI_OK) return bfwd(b, (int)k, st);
+        insts[k] = b->ctx[k]->inst;
+    }
+    BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_insts, insts.data(), insts.size() * sizeof(Inst),
+                               hipMemcpyHostToDevice, b->stream));
+    return batch_upload_lists(b);
+}
+
+fsi_status fsi_batch_init_equilibrium(fsi_batch *b, int k, const double *rho, const double *ux,
+                                      const double *uy, const double *T) {
+    fsi_status st = batch_ready(b, k);
+    if (st != FSI_OK) return st;
+    if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
+    return bfwd(b, k, fsi_init_equilibrium(b->ctx[k], rho, ux, uy, T));
+}
+
+fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order) {
+    if (!b) return FSI_E_ARG;
+    if (grid < 0 || (order != 0 && order != 1)) return bfail(b, FSI_E_ARG, "bad schedule");
+    batch_drop_graph(b);
+    b->grid = grid;
+    if (order != b->order) {
+        b->order = order;
+        batch_lists(b);
+        if (b->ws) return batch_upload_lists(b);
+    }
+    return FSI_OK;
+}
+
+fsi_status fsi_batch_step(fsi_batch *b, int nsteps) {
+    fsi_status st = batch_ready(b, -1);
+    if (st != FSI_OK) return st;
+    if (nsteps < 0) return bfail(b, FSI_E_ARG, "nsteps < 0");
+    if (nsteps == 0) return FSI_OK;
+    if (b->stream == nullptr) {
+        for (int k = 0; k < nsteps; ++k) {
+            st = batch_enqueue_step(b);
+            if (st != FSI_OK) return st;
+        }
+    } else {
+        if (!b->graph_exec) {
+            BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            st = batch_enqueue_step(b);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (st != FSI_OK) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return bfail(b, FSI_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            b->graph = g;
+            BHIP_TRY(b, hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0));
+        }
+        for (int k = 0; k < nsteps; ++k) BHIP_TRY(b, hipGraphLaunch(b->graph_exec, b->stream));
+    }
+    for (fsi_ctx *c : b->ctx) c->host_step += nsteps;
+    return FSI_OK;
+}
+
+fsi_status fsi_batch_synchronize(fsi_batch *b) {
+    fsi_status st = batch_ready(b, 0);
+    if (st != FSI_OK) return st;
+    for (size_t k = 0; k < b->ctx.size(); ++k) {
+        st = fsi_synchronize(b->ctx[k]);
+        if (st != FSI_OK) return bfwd(b, (int)k, st);
+    }
+    return FSI_OK;
+}
+
+fsi_status fsi_batch_get_forces(fsi_batch *b, int k, int64_t first, int count, double *out) {
+    fsi_status st = batch_ready(b, k);
+    if (st != FSI_OK) return st;
+    if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
+    return bfwd(b, k, fsi_get_forces(b->ctx[k], 0, first, count, out));
+}
+
+fsi_status fsi_batch_get_body_state(fsi_batch *b, int k, double out[4]) {
+    fsi_status st = batch_ready(b, k);
+    if (st != FSI_OK) return st;
+    if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
+    return bfwd(b, k, fsi_get_body_state(b->ctx[k], 0, out));
+}
+
+fsi_status fsi_batch_dump_macro(fsi_batch *b, int k, double *rho, double *ux, double *uy, double *T) {
+    fsi_status st = batch_ready(b, k);
+    if (st != FSI_OK) return st;
+    if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
+    return bfwd(b, k, fsi_dump_macro(b->ctx[k], rho, ux, uy, T));
+}
+
+fsi_status fsi_batch_get_populations(fsi_batch *b, int k, float *f, float *g) {
+    fsi_status st = batch_ready(b, k);
+    if (st != FSI_OK) return st;
+    if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
+    return bfwd(b, k, fsi_get_populations(b->ctx[k], f, g));
+}
+
+fsi_status fsi_batch_time_kernels(fsi_batch *b, int reps, double out_ms[4]) {
+    fsi_status st = batch_ready(b, -1);
+    if (st != FSI_OK) return st;
+    if (reps < 1 || !out_ms) return bfail(b, FSI_E_ARG, "reps must be >= 1");
+    st = fsi_batch_synchronize(b);
+    if (st != FSI_OK) return st;
+    hipEvent_t e0, e1;
+    BHIP_TRY(b, hipEventCreate(&e0));
+    BHIP_TRY(b, hipEventCreate(&e1));
+    const int2 *wbnd = reinterpret_cast<const int2 *>(b->ws + b->off_wbnd);
+    const int2 *wwall = reinterpret_cast<const int2 *>(b->ws + b->off_wwall);
+    for (int which = 0; which < 4; ++which) {
+        out_ms[which] = 0.0;
+        if (!b->any_wall && (which == 1 || which == 2)) continue;
+        for (int r = 0; r <= reps; ++r) {
+            if (r == 1) BHIP_TRY(b, hipEventRecord(e0, b->stream));
+            if (which == 0) {
+                st = batch_enqueue_k1(b);
+                if (st != FSI_OK) return st;
+            }
+            if (which == 1) BHIP_TRY(b, fsi::launch_wall_targets(b_insts(b), wbnd, (int)b->wbnd.size(), b->storage, b->stream));
+            if (which == 2) BHIP_TRY(b, fsi::launch_wall_grad_force(b_insts(b), wwall, (int)b->wwall.size(), b->storage, 0, b->stream));
+            if (which == 3) BHIP_TRY(b, fsi::launch_body(b_insts(b), (int)b->ctx.size(), 0, b->stream));
+        }
+        BHIP_TRY(b, hipEventRecord(e1, b->stream));
+        BHIP_TRY(b, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        BHIP_TRY(b, hipEventElapsedTime(&ms, e0, e1));
+        out_ms[which] = ms / reps;
+    }
+    BHIP_TRY(b, hipEventDestroy(e0));
+    BHIP_TRY(b, hipEventDestroy(e1));
+    return fsi_batch_synchronize(b);
+}
+
+fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[3]) {
+    fsi_status st = batch_ready(b, -1);
+    if (st != FSI_OK) return st;
+    if (reps < 1 || !best) return bfail(b, FSI_E_ARG, "reps must be >= 1");
+    // candidate grids: one workgroup per item, and persistent grids of a few
+    // multiples of the resident capacity (256 CUs x 2 tiles)
+    const int grids[] = {0, 4096, 2048, 1024, 512};
+    double best_ms = 1e30;
+    int best_grid = 0, best_order = 0;
+    for (int order = 0; order <= 1; ++order) {
+        for (int grid : grids) {
+            st = fsi_batch_set_schedule(b, grid, order);
+            if (st != FSI_OK) return st;
+            double ms[4];
+            st = fsi_batch_time_kernels(b, reps, ms);
+            if (st != FSI_OK) return st;
+            if (ms[0] < best_ms) {
+                best_ms = ms[0];
+                best_grid = grid;
+                best_order = order;
+            }
+        }
+    }
+    st = fsi_batch_set_schedule(b, best_grid, best_order);
+    if (st != FSI_OK) return st;
+    best[0] = best_grid;
+    best[1] = best_order;
+    best[2] = best_ms;
+    return FSI_OK;
+}
+
+int64_t fsi_batch_nodes(const fsi_batch *b) {
+    int64_t n = 0;
+    if (b)
+        for (const fsi_ctx *c : b->ctx) n += (int64_t)c->ni * c->nj;
+    return n;
+}
+
+const char *fsi_batch_last_error(const fsi_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void fsi_batch_destroy(fsi_batch *b) {
+    if (!b) return;
+    if (b->ws) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (fsi_ctx *c : b->ctx) fsi_destroy(c);
+    delete b;
+}
+
+}  // extern "C"

@@ -377,19 +377,10 @@ __device__ __forceinline__ int phase1_entry(int p) {
     return row * R3X + col;
 }
 
+// one work item (instance, tile) of the fused kernel
 template <int STORE>
-__global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
-k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
-    __shared__ K1Smem sm;
-    // XCD-aware work mapping: consecutive dispatch slots go round-robin over the
-    // 8 XCDs, so give each XCD a contiguous run of tiles (shared halos stay in
-    // that XCD's L2).
-    const int nb = gridDim.x;
-    const int per_xcd = (nb + 7) / 8;
-    const int b = blockIdx.x;
-    const int wk = (b % 8) * per_xcd + b / 8;
-    if (wk >= n_work) return;
-    const int2 item = work[wk];
+__device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__restrict__ insts,
+                                                    const int2 item) {
     const Inst &P = insts[item.x];
     const int tile = item.y;
     const int ti = tile % P.tiles_i, tj = tile / P.tiles_i;
@@ -697,6 +688,24 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         if (wall) P.wall_mask[ig] = miss;
     }
     if (err) atomicOr(P.err, err);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
+k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
+    __shared__ K1Smem sm;
+    // Work distribution: consecutive dispatch slots go round-robin over the 8
+    // XCDs, so each XCD owns a contiguous run of work items (neighbouring tiles
+    // share halos in that XCD's L2).  A grid smaller than the item count makes
+    // the kernel persistent: each workgroup strides over its XCD's run.
+    const int per_xcd = (n_work + 7) / 8;
+    const int xcd = blockIdx.x % 8, nloc = gridDim.x / 8;
+    for (int li = blockIdx.x / 8; li < per_xcd; li += nloc) {
+        const int wk = xcd * per_xcd + li;
+        if (wk >= n_work) break;
+        collide_stream_tile<STORE>(sm, insts, work[wk]);
+        __syncthreads();                      // LDS is reused by the next item
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1120,9 +1129,14 @@ __global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const
     } while (0)
 
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s) {
-    const int grid = ((n_work + 7) / 8) * 8;   // multiple of the XCD count
-    FSI_DISPATCH(storage, k_collide_stream, dim3(grid), dim3(K1_THREADS), s, insts, work, n_work);
+                                 hipStream_t s, int grid) {
+    // one workgroup per item unless a smaller (persistent) grid is requested;
+    // always a multiple of the XCD count
+    const int all = ((n_work + 7) / 8) * 8;
+    int g = grid > 0 ? ((grid + 7) / 8) * 8 : all;
+    if (g > all) g = all;
+    if (g < 8) g = 8;
+    FSI_DISPATCH(storage, k_collide_stream, dim3(g), dim3(K1_THREADS), s, insts, work, n_work);
     return hipGetLastError();
 }
 

@@ -24,7 +24,13 @@ EXPORTED = ("fsi_create", "fsi_workspace_bytes", "fsi_bind_workspace", "fsi_init
             "fsi_step", "fsi_synchronize", "fsi_get_step", "fsi_get_forces",
             "fsi_history_capacity", "fsi_get_body_state", "fsi_dump_macro",
             "fsi_get_populations", "fsi_set_populations", "fsi_state_bytes", "fsi_save",
-            "fsi_load", "fsi_time_kernels", "fsi_last_error", "fsi_destroy")
+            "fsi_load", "fsi_time_kernels", "fsi_last_error", "fsi_destroy",
+            "fsi_batch_create", "fsi_batch_workspace_bytes", "fsi_batch_bind_workspace",
+            "fsi_batch_init_equilibrium", "fsi_batch_set_schedule", "fsi_batch_autotune",
+            "fsi_batch_step", "fsi_batch_synchronize", "fsi_batch_get_forces",
+            "fsi_batch_get_body_state", "fsi_batch_dump_macro", "fsi_batch_get_populations",
+            "fsi_batch_time_kernels", "fsi_batch_nodes", "fsi_batch_last_error",
+            "fsi_batch_destroy")
 
 
 class FsiError(RuntimeError):
@@ -93,6 +99,25 @@ def load_library(path: str = LIB_PATH):
         "fsi_time_kernels": (ctypes.c_int, [P, ctypes.c_int, dp]),
         "fsi_last_error": (ctypes.c_char_p, [P]),
         "fsi_destroy": (None, [P]),
+        "fsi_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(FluidParams),
+                                            ctypes.POINTER(MeshDesc), ctypes.POINTER(BodyDesc),
+                                            ctypes.POINTER(ctypes.c_int), P, ctypes.POINTER(P)]),
+        "fsi_batch_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "fsi_batch_bind_workspace": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "fsi_batch_init_equilibrium": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
+        "fsi_batch_set_schedule": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int]),
+        "fsi_batch_autotune": (ctypes.c_int, [P, ctypes.c_int, dp]),
+        "fsi_batch_step": (ctypes.c_int, [P, ctypes.c_int]),
+        "fsi_batch_synchronize": (ctypes.c_int, [P]),
+        "fsi_batch_get_forces": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                                dp]),
+        "fsi_batch_get_body_state": (ctypes.c_int, [P, ctypes.c_int, dp]),
+        "fsi_batch_dump_macro": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
+        "fsi_batch_get_populations": (ctypes.c_int, [P, ctypes.c_int, fp, fp]),
+        "fsi_batch_time_kernels": (ctypes.c_int, [P, ctypes.c_int, dp]),
+        "fsi_batch_nodes": (ctypes.c_int64, [P]),
+        "fsi_batch_last_error": (ctypes.c_char_p, [P]),
+        "fsi_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -125,24 +150,39 @@ def _f64(a, shape):
 
 # ---- thin wrappers with the C names ------------------------------------------
 
-def fsi_create(fluid, mesh, bodies=(), stream_handle=None):
-    """fluid: synth.FluidParams-like; mesh: synth.MeshSpec-like; bodies: list of
-    BodyParams-like (0 or 1).  Returns (ctx, keepalive)."""
-    lib = load_library()
-    fp = FluidParams(fluid.gamma, fluid.Pr, fluid.mu, fluid.rho_inf, fluid.T_inf,
-                     (ctypes.c_double * 2)(*fluid.u_inf), fluid.dt, int(fluid.storage))
+def _fluid_struct(fluid):
+    return FluidParams(fluid.gamma, fluid.Pr, fluid.mu, fluid.rho_inf, fluid.T_inf,
+                       (ctypes.c_double * 2)(*fluid.u_inf), fluid.dt, int(fluid.storage))
+
+
+def _mesh_struct(mesh):
+    """Returns (MeshDesc, coordinate array that must outlive the call)."""
     X = np.ascontiguousarray(mesh.interleaved(), dtype=np.float64)
     md = MeshDesc(mesh.ni, mesh.nj, mesh.topo, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                   (ctypes.c_double * 2)(*mesh.shift_i), (ctypes.c_double * 2)(*mesh.shift_j))
+    return md, X
+
+
+def _body_struct(b):
+    return BodyDesc(int(b.dof), b.m, b.S_a, b.I_a, b.k_h, b.k_a,
+                    (ctypes.c_double * 2)(*b.center), (ctypes.c_double * 2)(*b.ea),
+                    b.r_rigid, b.r_blend, b.h0, b.a0, b.hd0, b.ad0, b.heave_amp,
+                    b.heave_freq, b.pitch_amp, b.pitch_freq)
+
+
+def fsi_create(fluid, mesh, bodies=(), stream_handle=None):
+    """fluid: synth.FluidParams-like; mesh: synth.MeshSpec-like; bodies: list of
+    BodyParams-like (0 or 1).  Returns the context handle."""
+    lib = load_library()
+    fp = _fluid_struct(fluid)
+    md, X = _mesh_struct(mesh)
     arr = (BodyDesc * max(1, len(bodies)))()
     for k, b in enumerate(bodies):
-        arr[k] = BodyDesc(int(b.dof), b.m, b.S_a, b.I_a, b.k_h, b.k_a,
-                          (ctypes.c_double * 2)(*b.center), (ctypes.c_double * 2)(*b.ea),
-                          b.r_rigid, b.r_blend, b.h0, b.a0, b.hd0, b.ad0, b.heave_amp,
-                          b.heave_freq, b.pitch_amp, b.pitch_freq)
+        arr[k] = _body_struct(b)
     ctx = ctypes.c_void_p()
     st = lib.fsi_create(ctypes.byref(fp), ctypes.byref(md), arr, len(bodies),
                         ctypes.c_void_p(stream_handle or 0), ctypes.byref(ctx))
+    del X
     if st != FSI_OK:
         msg = lib.fsi_last_error(ctx).decode() if ctx.value else ""
         if ctx.value:
@@ -248,6 +288,123 @@ def fsi_destroy(ctx):
         _lib.fsi_destroy(ctx)
 
 
+# ---- batches ---------------------------------------------------------------------
+
+def _bcheck(b, status):
+    if status != FSI_OK:
+        msg = _lib.fsi_batch_last_error(b).decode() if b else ""
+        raise FsiError(status, msg)
+
+
+def fsi_batch_create(cases, stream_handle=None):
+    """cases: sequence of (fluid, mesh, bodies) with 0 or 1 body each."""
+    lib = load_library()
+    n = len(cases)
+    fl = (FluidParams * n)()
+    ms = (MeshDesc * n)()
+    bd = (BodyDesc * n)()
+    nb = (ctypes.c_int * n)()
+    keep = []
+    for k, (fluid, mesh, bodies) in enumerate(cases):
+        if len(bodies) > 1:
+            raise FsiError(-1, "at most one body per batch instance")
+        fl[k] = _fluid_struct(fluid)
+        md, X = _mesh_struct(mesh)
+        keep.append(X)
+        ms[k] = md
+        if bodies:
+            bd[k] = _body_struct(bodies[0])
+            nb[k] = 1
+    b = ctypes.c_void_p()
+    st = lib.fsi_batch_create(n, fl, ms, bd, nb, ctypes.c_void_p(stream_handle or 0),
+                              ctypes.byref(b))
+    del keep
+    if st != FSI_OK:
+        msg = lib.fsi_batch_last_error(b).decode() if b.value else ""
+        if b.value:
+            lib.fsi_batch_destroy(b)
+        raise FsiError(st, msg)
+    return b
+
+
+def fsi_batch_workspace_bytes(b):
+    n = ctypes.c_size_t()
+    _bcheck(b, _lib.fsi_batch_workspace_bytes(b, ctypes.byref(n)))
+    return n.value
+
+
+def fsi_batch_bind_workspace(b, dev_ptr, nbytes):
+    _bcheck(b, _lib.fsi_batch_bind_workspace(b, ctypes.c_void_p(dev_ptr), nbytes))
+
+
+def fsi_batch_init_equilibrium(b, k, shape, rho=None, ux=None, uy=None, T=None):
+    arrs = [_f64(a, shape) for a in (rho, ux, uy, T)]
+    _bcheck(b, _lib.fsi_batch_init_equilibrium(b, int(k), *[_dptr(a) for a in arrs]))
+
+
+def fsi_batch_set_schedule(b, grid, order):
+    _bcheck(b, _lib.fsi_batch_set_schedule(b, int(grid), int(order)))
+
+
+def fsi_batch_autotune(b, reps):
+    """Returns (grid, order, ms per collision-streaming launch) of the fastest schedule."""
+    out = np.zeros(3, dtype=np.float64)
+    _bcheck(b, _lib.fsi_batch_autotune(b, int(reps), _dptr(out)))
+    return int(out[0]), int(out[1]), float(out[2])
+
+
+def fsi_batch_step(b, nsteps):
+    _bcheck(b, _lib.fsi_batch_step(b, int(nsteps)))
+
+
+def fsi_batch_synchronize(b):
+    _bcheck(b, _lib.fsi_batch_synchronize(b))
+
+
+def fsi_batch_get_forces(b, k, first, count):
+    out = np.zeros((count, 6), dtype=np.float64)
+    _bcheck(b, _lib.fsi_batch_get_forces(b, int(k), int(first), int(count), _dptr(out)))
+    return out
+
+
+def fsi_batch_get_body_state(b, k):
+    out = np.zeros(4, dtype=np.float64)
+    _bcheck(b, _lib.fsi_batch_get_body_state(b, int(k), _dptr(out)))
+    return out
+
+
+def fsi_batch_dump_macro(b, k, shape):
+    outs = [np.empty(shape, dtype=np.float64) for _ in range(4)]
+    _bcheck(b, _lib.fsi_batch_dump_macro(b, int(k), *[_dptr(o) for o in outs]))
+    return tuple(outs)
+
+
+def fsi_batch_get_populations(b, k, shape):
+    f = np.empty((9,) + tuple(shape), dtype=np.float32)
+    g = np.empty((9,) + tuple(shape), dtype=np.float32)
+    _bcheck(b, _lib.fsi_batch_get_populations(b, int(k), _fptr(f), _fptr(g)))
+    return f, g
+
+
+def fsi_batch_time_kernels(b, reps):
+    out = np.zeros(4, dtype=np.float64)
+    _bcheck(b, _lib.fsi_batch_time_kernels(b, int(reps), _dptr(out)))
+    return out
+
+
+def fsi_batch_nodes(b):
+    return int(_lib.fsi_batch_nodes(b))
+
+
+def fsi_batch_last_error(b):
+    return _lib.fsi_batch_last_error(b).decode()
+
+
+def fsi_batch_destroy(b):
+    if b:
+        _lib.fsi_batch_destroy(b)
+
+
 # ---- convenience wrapper -------------------------------------------------------
 
 class Simulation:
@@ -319,6 +476,81 @@ class Simulation:
         if self.ctx:
             fsi_destroy(self.ctx)
             self.ctx = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent instances on one GPU, advanced by one launch per kernel.
+
+    ``cases``: sequence of objects with ``mesh``, ``fluid`` and ``bodies``
+    (``synth.Case``), or of (fluid, mesh, bodies) tuples.
+    """
+
+    def __init__(self, cases, device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        triples = [c if isinstance(c, tuple) else (c.fluid, c.mesh, list(c.bodies)) for c in cases]
+        self.shapes = [(m.nj, m.ni) for _, m, _ in triples]
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.b = fsi_batch_create(triples, self.stream.cuda_stream)
+        try:
+            nbytes = fsi_batch_workspace_bytes(self.b)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+            fsi_batch_bind_workspace(self.b, self.ws_ptr, nbytes)
+        except Exception:
+            fsi_batch_destroy(self.b)
+            self.b = None
+            raise
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def nodes(self):
+        return fsi_batch_nodes(self.b)
+
+    def init_equilibrium(self, k, rho=None, ux=None, uy=None, T=None):
+        fsi_batch_init_equilibrium(self.b, k, self.shapes[k], rho, ux, uy, T)
+
+    def set_schedule(self, grid, order):
+        fsi_batch_set_schedule(self.b, grid, order)
+
+    def autotune(self, reps=5):
+        return fsi_batch_autotune(self.b, reps)
+
+    def step(self, nsteps=1):
+        fsi_batch_step(self.b, nsteps)
+
+    def synchronize(self):
+        fsi_batch_synchronize(self.b)
+
+    def forces(self, k, first, count):
+        return fsi_batch_get_forces(self.b, k, first, count)
+
+    def body_state(self, k):
+        return fsi_batch_get_body_state(self.b, k)
+
+    def macro(self, k):
+        return fsi_batch_dump_macro(self.b, k, self.shapes[k])
+
+    def populations(self, k):
+        return fsi_batch_get_populations(self.b, k, self.shapes[k])
+
+    def time_kernels(self, reps=20):
+        return fsi_batch_time_kernels(self.b, reps)
+
+    def close(self):
+        if self.b:
+            fsi_batch_destroy(self.b)
+            self.b = None
         self.workspace = None
 
     def __del__(self):

@@ -142,3 +142,59 @@ def test_tiny_mesh_is_rejected(F):
     with pytest.raises(F.FsiError) as e:
         F.fsi_create(c.fluid, synth.cartesian_mesh(4, 16), [], None)
     assert e.value.status == -1
+
+
+# ---- batches -----------------------------------------------------------------
+
+def _batch_cases():
+    a = synth.acoustic_pulse_case()
+    c1 = synth.cylinder_viv_case(n_r=32, n_theta=64, D=20.0, first_cell_frac=0.05,
+                                 r_far_D=8.0, blend_D=3.0)
+    c2 = synth.cylinder_viv_case(n_r=40, n_theta=72, D=20.0, first_cell_frac=0.05,
+                                 r_far_D=8.0, blend_D=3.0)
+    return [(a.fluid, a.mesh, []), (c1.fluid, c1.mesh, c1.bodies), (c2.fluid, c2.mesh, c2.bodies)]
+
+
+def test_batch_workspace_covers_every_instance(F):
+    cases = _batch_cases()
+    b = F.fsi_batch_create(cases)
+    try:
+        assert F.fsi_batch_nodes(b) == sum(m.n_nodes for _, m, _ in cases)
+        single = 0
+        for fl, m, bodies in cases:
+            ctx = F.fsi_create(fl, m, bodies, None)
+            single += F.fsi_workspace_bytes(ctx)
+            F.fsi_destroy(ctx)
+        ws = F.fsi_batch_workspace_bytes(b)
+        assert single <= ws < single + 2 ** 20
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_batch_step(b, 1)
+        assert e.value.status == -7
+    finally:
+        F.fsi_batch_destroy(b)
+
+
+def test_batch_rejects_bad_instance_and_mixed_storage(F):
+    cases = _batch_cases()
+    fl, m, bodies = cases[2]
+    bad = cases[:2] + [(synth.configs.replace(fl, gamma=1.0), m, bodies)]
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_batch_create(bad)
+    assert e.value.status == -1 and "instance 2" in str(e.value)
+    mixed = cases[:2] + [(synth.configs.replace(fl, storage=1), m, bodies)]
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_batch_create(mixed)
+    assert e.value.status == -1
+
+
+def test_batch_schedule_arguments_are_checked(F):
+    b = F.fsi_batch_create(_batch_cases())
+    try:
+        F.fsi_batch_set_schedule(b, 1024, 1)
+        F.fsi_batch_set_schedule(b, 0, 0)
+        for grid, order in ((-1, 0), (0, 2)):
+            with pytest.raises(F.FsiError) as e:
+                F.fsi_batch_set_schedule(b, grid, order)
+            assert e.value.status == -1
+    finally:
+        F.fsi_batch_destroy(b)
