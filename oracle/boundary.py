@@ -22,10 +22,15 @@ Readings taken where the text is silent or garbled:
 * gradients are FE derivatives on the mesh at t^{n+1}: centred along the wall,
   one-sided into the fluid, with the wall row holding the target values.
 
-Far field (row j = nj - 1): all populations are set to equilibrium
-(Sec. III.A.2).  Reading: a node is an inlet when u_inf . n_out < 0, with
-n_out the outward normal of the far-field row; inlets take the free-stream
-values, outlets copy rho, u, T from the adjacent interior node (zero gradient).
+Far field (row j = nj - 1, and the exit columns of a C-grid): all populations
+are set to equilibrium (Sec. III.A.2).  Reading: a node is an inlet when
+u_inf . n_out < 0, with n_out the outward normal of its boundary; inlets take
+the free-stream values, outlets copy rho, u, T from the adjacent interior node
+(zero gradient).
+
+C-grid: the wall is row 0 between the two trailing-edge copies (both are wall
+nodes); the cut nodes of row 0 are interior nodes and keep their streamed
+values, also where a wall node's tangential derivative reaches them.
 """
 
 from __future__ import annotations
@@ -38,34 +43,38 @@ from .stream import bilinear_inverse, lagrange_1d
 
 def wall_normals_undeformed(grid, X, Y):
     """Unit normal of the wall row pointing into the fluid, from the centred
-    tangent t = X_{i+1} - X_{i-1}: n = rot_{+90}(t)/|t| (meshes have
-    det(dX/dxi) > 0 with j pointing into the fluid)."""
+    tangent t = X_{i+1} - X_{i-1} of index neighbours: n = rot_{+90}(t)/|t|
+    (meshes have det(dX/dxi) > 0 with j pointing into the fluid).  Returned
+    for every column; only wall columns use it."""
     xp, yp = grid.neighbour_pos(X, Y, 1, 0)
     xm, ym = grid.neighbour_pos(X, Y, -1, 0)
     tx = (xp - xm)[0]
     ty = (yp - ym)[0]
     n = np.hypot(tx, ty)
-    return -ty / n, tx / n
+    with np.errstate(invalid="ignore"):
+        return -ty / n, tx / n
 
 
 def interpolate_B(grid, X, Y, field_row0, field_rows12, dt):
-    """Value at B = X_A + dt n (undeformed frame) for every wall node.
+    """Value at B = X_A + dt n (undeformed frame) for every wall node (NaN in
+    the other columns).
 
-    field_row0: wall-row values [ni]; field_rows12: full field [nj, ni] whose
+    field_row0: row-0 values [ni]; field_rows12: full field [nj, ni] whose
     rows 1 and 2 are used.
     """
     nx, ny = wall_normals_undeformed(grid, X, Y)
     ni = grid.ni
-    Bx = dt * nx
-    By = dt * ny                      # B - X_A
-    a = np.full(ni, np.nan)
-    b = np.full(ni, np.nan)
-    found = np.zeros(ni, dtype=bool)
+    cols = np.flatnonzero(grid.wall_col)
+    Bx = dt * nx[cols]
+    By = dt * ny[cols]                # B - X_A
+    a = np.full(cols.size, np.nan)
+    b = np.full(cols.size, np.nan)
+    found = np.zeros(cols.size, dtype=bool)
     for di0 in (-1, 0):
         corners = []
         for (ci, cj) in ((0, 0), (1, 0), (0, 1), (1, 1)):
             px, py = grid.neighbour_pos(X, Y, di0 + ci, cj)
-            corners.append((px[0] - X[0], py[0] - Y[0]))
+            corners.append((px[0, cols] - X[0, cols], py[0, cols] - Y[0, cols]))
         s, t, _ = bilinear_inverse(*corners, Bx, By)
         ok = (s >= -1e-12) & (s <= 1 + 1e-12) & (t >= -1e-12) & (t <= 1 + 1e-12)
         take = ok & ~found
@@ -77,13 +86,15 @@ def interpolate_B(grid, X, Y, field_row0, field_rows12, dt):
     # element centred on (i, 1): rows 0, 1, 2
     vals = np.stack([field_row0, field_rows12[1], field_rows12[2]])
     bc = b - 1.0
-    out = np.zeros(ni)
-    ii = np.arange(ni)
+    out = np.full(ni, np.nan)
+    acc = np.zeros(cols.size)
     for p in (-1, 0, 1):
         La = lagrange_1d(p, a)
+        si, _, _ = grid.node_index(cols + p, np.zeros_like(cols))
         for q in (-1, 0, 1):
             Lb = lagrange_1d(q, bc)
-            out = out + La * Lb * vals[q + 1, (ii + p) % ni]
+            acc = acc + La * Lb * vals[q + 1, si]
+    out[cols] = acc
     return out
 
 
@@ -106,10 +117,13 @@ def wall_grad_bc(grid, X, Y, x1, y1, VGx, VGy, f_new, g_new, missing,
     uy_t = VGy[0].copy()
     E_t = Cv * T_t + 0.5 * (ux_t ** 2 + uy_t ** 2)
 
-    # fields with the wall row set to the targets, for the FE gradients
+    # fields with the wall nodes set to the targets, for the FE gradients
+    # (cut nodes of a C-grid keep their streamed values)
+    wc = grid.wall_col
+
     def with_row0(F, row0):
         G = F.copy()
-        G[0] = row0
+        G[0] = np.where(wc, row0, F[0])
         return G
 
     Ux = with_row0(ux, ux_t)
@@ -150,32 +164,54 @@ def wall_grad_bc(grid, X, Y, x1, y1, VGx, VGy, f_new, g_new, missing,
         g1 = W[i] * ((q1x * cx + q1y * cy) / T_t
                      + (R1xx * (cx * cx - T_t) + 2.0 * R1xy * cx * cy
                         + R1yy * (cy * cy - T_t)) / (2.0 * T_t * T_t))
-        m = missing[i, 0]
+        m = missing[i, 0] & wc
         f_new[i, 0] = np.where(m, fe[i] + dt * f1, f_new[i, 0])
         g_new[i, 0] = np.where(m, ge[i] + dt * g1, g_new[i, 0])
     return rho_t, ux_t, uy_t, T_t
 
 
-def farfield_outward_normal(grid, X, Y):
-    """Outward normal (not normalised) of the far-field row: rot_{+90} of the
-    centred tangent, which points toward increasing j."""
-    xp, yp = grid.neighbour_pos(X, Y, 1, 0)
-    xm, ym = grid.neighbour_pos(X, Y, -1, 0)
-    tx = (xp - xm)[-1]
-    ty = (yp - ym)[-1]
-    return -ty, tx
+def farfield_nodes(grid, X, Y):
+    """Far-field nodes with their outward normals (not normalised) and the
+    interior node an outlet copies from (Sec. III.A.2).
+
+    Row nj - 1: n_out = rot_{+90}(dX/di), interior node (i, nj - 2) (its column
+    moved off a C-grid exit column).  C-grid exit columns i = 0 and ni - 1
+    (rows below nj - 1): n_out = rot_{+90}(dX/dj) at i = 0 and its opposite at
+    i = ni - 1, interior nodes (1, j) and (ni - 2, j).  Derivatives are the
+    index-space FE derivatives of the undeformed coordinates.
+    Returns (jj, ii, nx, ny, jref, iref) as flat arrays.
+    """
+    X_i, Y_i = grid.d_i(X), grid.d_i(Y)
+    X_j, Y_j = grid.d_j(X), grid.d_j(Y)
+    ni, nj = grid.ni, grid.nj
+    ii = list(range(ni))
+    jj = [nj - 1] * ni
+    nx = list(-Y_i[nj - 1])
+    ny = list(X_i[nj - 1])
+    iref = [min(max(i, 1), ni - 2) if grid.cgrid else i for i in range(ni)]
+    jref = [nj - 2] * ni
+    if grid.cgrid:
+        for j in range(nj - 1):
+            ii += [0, ni - 1]
+            jj += [j, j]
+            nx += [-Y_j[j, 0], Y_j[j, ni - 1]]
+            ny += [X_j[j, 0], -X_j[j, ni - 1]]
+            iref += [1, ni - 2]
+            jref += [j, j]
+    return (np.array(jj), np.array(ii), np.array(nx), np.array(ny), np.array(jref),
+            np.array(iref))
 
 
 def farfield_bc(grid, X, Y, f_new, g_new, gamma, rho_inf, u_inf, T_inf):
-    """Equilibrium populations on the far-field row (Sec. III.A.2)."""
-    nx, ny = farfield_outward_normal(grid, X, Y)
+    """Equilibrium populations on the far-field nodes (Sec. III.A.2)."""
+    jj, ii, nx, ny, jr, ir = farfield_nodes(grid, X, Y)
     inflow = (u_inf[0] * nx + u_inf[1] * ny) < 0.0
-    rho_in, ux_in, uy_in, _, T_in = L.macroscopic(f_new[:, -2, :], g_new[:, -2, :], gamma)
+    rho_in, ux_in, uy_in, _, T_in = L.macroscopic(f_new[:, jr, ir], g_new[:, jr, ir], gamma)
     rho = np.where(inflow, rho_inf, rho_in)
     ux = np.where(inflow, u_inf[0], ux_in)
     uy = np.where(inflow, u_inf[1], uy_in)
     T = np.where(inflow, T_inf, T_in)
     fe, ge = L.equilibrium_populations(rho, ux, uy, T, gamma)
-    f_new[:, -1, :] = fe
-    g_new[:, -1, :] = ge
+    f_new[:, jj, ii] = fe
+    g_new[:, jj, ii] = ge
     return inflow

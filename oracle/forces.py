@@ -10,6 +10,11 @@ into the fluid.  (Reading: the paper sums element forces; lumping each
 element's two end-node contributions onto the nodes gives this trapezoid
 form, and the lumped normals of a closed wall sum to zero exactly.)
 F = sum_k F_k and M_EA = sum_k (x_k - x_EA) x F_k, both summed in node order.
+
+The wall polygon is the closed sequence of distinct wall nodes: the whole
+row j = 0 of an O-grid; on a C-grid the columns from the lower trailing-edge
+copy up to, not including, the upper copy (the same point), so that the
+neighbours k +- 1 run cyclically along the section.
 """
 
 from __future__ import annotations
@@ -19,12 +24,19 @@ import numpy as np
 from . import lattice as L
 
 
+def wall_polygon(grid):
+    """Columns of the distinct wall nodes in polygon order."""
+    cols = np.flatnonzero(grid.wall_col)
+    return cols[:-1] if grid.cgrid else cols
+
+
 def wall_lumped_normals(grid, x, y):
-    xp, yp = grid.neighbour_pos(x, y, 1, 0)
-    xm, ym = grid.neighbour_pos(x, y, -1, 0)
-    tx = 0.5 * (xp - xm)[0]
-    ty = 0.5 * (yp - ym)[0]
-    return -ty, tx
+    """(n ds)_k for the wall polygon's nodes, from their cyclic neighbours."""
+    cols = wall_polygon(grid)
+    px, py = x[0, cols], y[0, cols]
+    tx = 0.5 * (np.roll(px, -1) - np.roll(px, 1))
+    ty = 0.5 * (np.roll(py, -1) - np.roll(py, 1))
+    return cols, -ty, tx
 
 
 def wall_stress(f0, g0, gamma, mu, Pr, dt):
@@ -46,19 +58,19 @@ def wall_stress(f0, g0, gamma, mu, Pr, dt):
 
 
 def wall_force(grid, f, g, x, y, gamma, mu, Pr, dt, ea_pos):
-    """Total (F_x, F_y, M_EA) on the wall row j = 0; ea_pos is the physical
-    position of the elastic axis at the same time level as (x, y)."""
-    sxx, sxy, syy = wall_stress(f[:, 0, :], g[:, 0, :], gamma, mu, Pr, dt)
-    nx, ny = wall_lumped_normals(grid, x, y)
+    """Total (F_x, F_y, M_EA) on the wall; ea_pos is the physical position of
+    the elastic axis at the same time level as (x, y)."""
+    cols, nx, ny = wall_lumped_normals(grid, x, y)
+    sxx, sxy, syy = wall_stress(f[:, 0, cols], g[:, 0, cols], gamma, mu, Pr, dt)
     Fx_k = sxx * nx + sxy * ny
     Fy_k = sxy * nx + syy * ny
-    rx = x[0] - ea_pos[0]
-    ry = y[0] - ea_pos[1]
+    rx = x[0, cols] - ea_pos[0]
+    ry = y[0, cols] - ea_pos[1]
     Mz_k = rx * Fy_k - ry * Fx_k
     Fx = 0.0
     Fy = 0.0
     Mz = 0.0
-    for k in range(grid.ni):
+    for k in range(cols.size):
         Fx += Fx_k[k]
         Fy += Fy_k[k]
         Mz += Mz_k[k]

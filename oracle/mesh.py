@@ -19,6 +19,7 @@ import numpy as np
 
 TOPO_PERIODIC2 = 0
 TOPO_OGRID = 1
+TOPO_CGRID = 2
 
 
 class Grid:
@@ -27,44 +28,75 @@ class Grid:
     periodic_i / periodic_j: wrap in that index.  shift_i / shift_j: vectors
     added to coordinates when a neighbour is taken across the periodic seam
     (zero for an O-grid's azimuthal seam, the period for a doubly periodic box).
+
+    C-grid: i is not periodic (columns 0 and ni-1 are the exit boundary) and
+    row j = 0 outside the wall columns is the wake cut, across which node
+    (i, -m) is node (ni - 1 - i, m).  Wall columns are [n_wake, ni - n_wake)
+    (both trailing-edge copies included); an O-grid's wall is the whole row.
     """
 
-    def __init__(self, ni, nj, topo, shift_i=(0.0, 0.0), shift_j=(0.0, 0.0)):
+    def __init__(self, ni, nj, topo, shift_i=(0.0, 0.0), shift_j=(0.0, 0.0), n_wake=0):
         self.ni, self.nj, self.topo = int(ni), int(nj), int(topo)
-        self.periodic_i = True
-        self.periodic_j = topo == TOPO_PERIODIC2
+        self.cgrid = self.topo == TOPO_CGRID
+        self.periodic_i = not self.cgrid
+        self.periodic_j = self.topo == TOPO_PERIODIC2
+        self.n_wake = int(n_wake) if self.cgrid else 0
         self.shift_i = np.asarray(shift_i, dtype=np.float64)
         self.shift_j = np.asarray(shift_j, dtype=np.float64)
         self.jj, self.ii = np.meshgrid(np.arange(self.nj), np.arange(self.ni),
                                        indexing="ij")
+        cols = np.arange(self.ni)
+        if self.cgrid:
+            self.wall_col = (cols >= self.n_wake) & (cols < self.ni - self.n_wake)
+        else:
+            self.wall_col = np.full(self.ni, not self.periodic_j)
+        self.cut_col = self.cgrid & ~self.wall_col
 
     @classmethod
     def from_mesh(cls, mesh):
-        return cls(mesh.ni, mesh.nj, mesh.topo, mesh.shift_i, mesh.shift_j)
+        return cls(mesh.ni, mesh.nj, mesh.topo, mesh.shift_i, mesh.shift_j,
+                   getattr(mesh, "n_wake", 0))
 
     # ---- neighbour access -------------------------------------------------
-    def neighbour(self, F, di, dj):
-        """F at (i + di, j + dj); NaN where the neighbour does not exist."""
-        ii = self.ii + di
-        jj = self.jj + dj
-        ii = ii % self.ni
-        valid = np.ones(F.shape, dtype=bool)
+    def node_index(self, ii, jj):
+        """Storage indices (i, j) of index-space positions (ii, jj), and whether
+        that node exists: wrap in periodic indices, mirror across the C-grid
+        cut for jj < 0."""
+        ii = np.asarray(ii)
+        jj = np.asarray(jj)
+        valid = np.ones(np.broadcast(ii, jj).shape, dtype=bool)
+        if self.cgrid:
+            below = jj < 0
+            ii = np.where(below, self.ni - 1 - ii, ii)
+            jj = np.where(below, -jj, jj)
+        if self.periodic_i:
+            ii = ii % self.ni
+        else:
+            valid &= (ii >= 0) & (ii < self.ni)
         if self.periodic_j:
             jj = jj % self.nj
         else:
-            valid = (jj >= 0) & (jj < self.nj)
-            jj = np.clip(jj, 0, self.nj - 1)
-        out = F[jj, ii].astype(np.float64)
-        return np.where(valid, out, np.nan)
+            valid &= (jj >= 0) & (jj < self.nj)
+        return np.clip(ii, 0, self.ni - 1), np.clip(jj, 0, self.nj - 1), valid
+
+    def gather(self, F, ii, jj):
+        """F at index-space positions (ii, jj); NaN where no node exists."""
+        si, sj, valid = self.node_index(ii, jj)
+        return np.where(valid, F[sj, si].astype(np.float64), np.nan)
+
+    def neighbour(self, F, di, dj):
+        """F at (i + di, j + dj); NaN where the neighbour does not exist."""
+        return self.gather(F, self.ii + di, self.jj + dj)
 
     def neighbour_pos(self, X, Y, di, dj):
         """Coordinates of node (i + di, j + dj) as seen from node (i, j), with
         the periodic shift applied across a seam."""
         xs = self.neighbour(X, di, dj)
         ys = self.neighbour(Y, di, dj)
-        wrap_i = np.floor_divide(self.ii + di, self.ni)
-        xs = xs + wrap_i * self.shift_i[0]
-        ys = ys + wrap_i * self.shift_i[1]
+        if self.periodic_i:
+            wrap_i = np.floor_divide(self.ii + di, self.ni)
+            xs = xs + wrap_i * self.shift_i[0]
+            ys = ys + wrap_i * self.shift_i[1]
         if self.periodic_j:
             wrap_j = np.floor_divide(self.jj + dj, self.nj)
             xs = xs + wrap_j * self.shift_j[0]
@@ -73,21 +105,34 @@ class Grid:
 
     # ---- index-space derivatives -------------------------------------------
     def d_i(self, F):
-        """dF/d(i): centred difference (i is periodic)."""
-        return 0.5 * (self.neighbour(F, 1, 0) - self.neighbour(F, -1, 0))
+        """dF/d(i): centred, one-sided 3-point on the C-grid exit columns."""
+        if self.periodic_i:
+            return 0.5 * (self.neighbour(F, 1, 0) - self.neighbour(F, -1, 0))
+        out = np.empty_like(F, dtype=np.float64)
+        out[:, 1:-1] = 0.5 * (F[:, 2:] - F[:, :-2])
+        out[:, 0] = 0.5 * (-3.0 * F[:, 0] + 4.0 * F[:, 1] - F[:, 2])
+        out[:, -1] = 0.5 * (3.0 * F[:, -1] - 4.0 * F[:, -2] + F[:, -3])
+        return out
 
     def d_j(self, F):
-        """dF/d(j): centred inside, one-sided 3-point on non-periodic end rows."""
+        """dF/d(j): centred inside (and across the C-grid cut), one-sided
+        3-point on the wall row and on the far-field row."""
         if self.periodic_j:
             return 0.5 * (self.neighbour(F, 0, 1) - self.neighbour(F, 0, -1))
         out = np.empty_like(F, dtype=np.float64)
         out[1:-1] = 0.5 * (F[2:] - F[:-2])
         out[0] = 0.5 * (-3.0 * F[0] + 4.0 * F[1] - F[2])
         out[-1] = 0.5 * (3.0 * F[-1] - 4.0 * F[-2] + F[-3])
+        if self.cgrid:
+            cut = self.cut_col
+            mirror = F[1, self.ni - 1 - np.arange(self.ni)]
+            out[0] = np.where(cut, 0.5 * (F[1] - mirror), out[0])
         return out
 
     def metrics(self, x, y):
         """(x_xi, x_eta, y_xi, y_eta) of a coordinate field, with seams shifted."""
+        if self.cgrid:
+            return self.d_i(x), self.d_j(x), self.d_i(y), self.d_j(y)
         xp, yp = self.neighbour_pos(x, y, 1, 0)
         xm, ym = self.neighbour_pos(x, y, -1, 0)
         x_xi = 0.5 * (xp - xm)

@@ -10,7 +10,7 @@ start of step n the load F^n of the populations f^n is known):
  2. s^{n+1}  body state (RK4 with F^n frozen, or prescribed motion)
  3. x^{n+1}  blended mesh; V_G = (x^{n+1} - x^n) / dt
  4. collide  f^n at the nodes of x^n, with the correction F_a computed from
-             nested FE gradients on x^n:
+             nested FE gradients on x^n (zero at a C-grid's trailing edge):
                  D_a = (1/omega - 1/2) dt d_a dQ_a,   F_a = d_a D_a
              (reading: the factor dt makes the correction cancel the
              (1/omega - 1/2) dt scaled defect of the viscous stress for any
@@ -18,6 +18,13 @@ start of step n the load F^n of the populations f^n is known):
              prints it for dt = 1)
  5. stream   ALE departure points with g and V_G at t^{n+1}; interpolation
  6. boundary far-field equilibria; Grad wall populations for the missing ones
+ 7. C-grid: the duplicated nodes of row 0 are made single-valued (reading:
+    the paper's unstructured meshes have no duplicated nodes).  The two
+    trailing-edge copies each see the cells of one side only, so population
+    by population the trailing edge takes the streamed value of the copy that
+    found its departure point, and the mean of the two copies where both or
+    neither did; the upper copy of every cut node takes the lower copy's
+    values (the two are mirror-image evaluations of the same update).
 """
 
 from __future__ import annotations
@@ -47,6 +54,20 @@ def correction_force(grid, f, g, x, y, gamma, mu, Pr, dt):
     return Fx, Fy
 
 
+def merge_cut_row(grid, f_new, g_new, missing):
+    """Single-valued trailing edge and cut nodes of a C-grid (step 7)."""
+    nw, ni = grid.n_wake, grid.ni
+    a, b = nw, ni - 1 - nw                    # lower and upper trailing-edge copies
+    ma, mb = missing[:, 0, a], missing[:, 0, b]
+    lower = np.arange(nw)
+    for F in (f_new, g_new):
+        va, vb = F[:, 0, a].copy(), F[:, 0, b].copy()
+        v = np.where(ma & ~mb, vb, np.where(mb & ~ma, va, 0.5 * (va + vb)))
+        F[:, 0, a] = v
+        F[:, 0, b] = v
+        F[:, 0, ni - 1 - lower] = F[:, 0, lower]
+
+
 class OracleSolver:
     """Plain FP64 reference of the whole coupled step on one structured mesh."""
 
@@ -69,7 +90,7 @@ class OracleSolver:
             uy = np.full(shape, fluid.u_inf[1])
             T = np.full(shape, fluid.T_inf)
         self.f, self.g = L.equilibrium_populations(rho, ux, uy, T, fluid.gamma)
-        self.has_wall = mesh.topo == 1
+        self.has_wall = mesh.topo in (1, 2)
 
     # ---- geometry ---------------------------------------------------------
     def positions(self, states):
@@ -110,17 +131,24 @@ class OracleSolver:
         else:
             Fx = np.zeros_like(self.X)
             Fy = np.zeros_like(self.X)
+        if self.grid.cgrid:
+            # the trailing edge collides once: its two copies' one-sided nested
+            # derivatives differ at the sharp edge, so the correction is dropped there
+            te = [self.grid.n_wake, self.grid.ni - 1 - self.grid.n_wake]
+            Fx[0, te] = 0.0
+            Fy[0, te] = 0.0
         fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt, Fx, Fy)
         # 5: streaming
-        skip = (self.grid.nj - 1,) if self.has_wall else ()
         f_new, g_new, missing = stream(self.grid, self.X, self.Y, x1, y1, VGx, VGy,
-                                       dt, fpost, gpost, skip_rows=skip)
+                                       dt, fpost, gpost)
         # 6: boundaries
         if self.has_wall:
             farfield_bc(self.grid, self.X, self.Y, f_new, g_new, fl.gamma,
                         fl.rho_inf, fl.u_inf, fl.T_inf)
             wall_grad_bc(self.grid, self.X, self.Y, x1, y1, VGx, VGy, f_new, g_new,
                          missing, self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt)
+        if self.grid.cgrid:
+            merge_cut_row(self.grid, f_new, g_new, missing)
         self.last_missing = missing
         self.f, self.g = f_new, g_new
         self.states = new_states

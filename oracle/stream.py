@@ -18,9 +18,11 @@ For every node and every moving velocity c_i:
    (Sec. II.B, Eq. for f_i(X, t)).
 
 Reading for the structured mesh: the 9-node element is the 3 x 3 block of
-nodes centred on the arriving node (shifted inward by one row on a
-non-periodic end row), with tensor-product quadratic Lagrange shape functions
-of the offsets of xi_dp from the block centre.
+nodes centred on the arriving node (shifted inward by one row on a wall or
+far-field row, by one column on a C-grid exit column), with tensor-product
+quadratic Lagrange shape functions of the offsets of xi_dp from the block
+centre.  On a C-grid the block of a cut node reaches across the cut (row -1
+is the mirrored row 1 of the other side).
 """
 
 from __future__ import annotations
@@ -97,8 +99,9 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
 
     Returns (a, b, missing): a, b are the index-space offsets of xi_dp from the
     node; ``missing`` marks departure points that leave the mesh through the
-    wall row j = 0 (only when ``wall_row``).  Raises CFLViolation if a
-    departure point lies in none of the four cells touching its node.
+    wall (only when ``wall_row``): wall nodes search only the cells above the
+    wall, and a point below them lies in the body.  Raises CFLViolation if a
+    departure point lies in none of the cells touching its node.
     """
     Pdx = -dt * chx                      # X_dp - X, relative to the node
     Pdy = -dt * chy
@@ -106,6 +109,7 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
     b = np.full(X.shape, np.nan)
     found = np.zeros(X.shape, dtype=bool)
     missing = np.zeros(X.shape, dtype=bool)
+    wall_node = (grid.jj == 0) & grid.wall_col[None, :] if wall_row else np.zeros(X.shape, bool)
     for (di0, dj0) in CANDIDATE_CELLS:
         corners = []
         for (ci, cj) in ((0, 0), (1, 0), (0, 1), (1, 1)):
@@ -115,14 +119,15 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
             s, t, _ = bilinear_inverse(*corners, Pdx, Pdy)
         inside = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL)
                   & (t >= -CELL_TOL) & (t <= 1 + CELL_TOL))
+        if dj0 < 0:
+            inside &= ~wall_node            # no cells below the wall
         take = inside & ~found
         a = np.where(take, di0 + s, a)
         b = np.where(take, dj0 + t, b)
         found |= take
         if wall_row and dj0 == 0:
-            # a wall-row departure point below the first cell row lies in the body
-            below = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL) & (t < -CELL_TOL)
-                     & (grid.jj == 0))
+            # a wall-node departure point below the first cell row lies in the body
+            below = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL) & (t < -CELL_TOL) & wall_node)
             missing |= below & ~found
     missing &= ~found
     bad = ~found & ~missing
@@ -142,69 +147,77 @@ def lagrange_1d(p, a):
     return out
 
 
-def stencil_centre_rows(grid):
-    """Row index of the 3x3 element centre for every node: the node's own row,
-    moved inward by one on a non-periodic end row."""
+def stencil_centres(grid):
+    """Index-space centre (ic, jc) of every node's 3 x 3 element: the node
+    itself, moved inward by one row on a wall or far-field row and by one
+    column on a C-grid exit column."""
+    ic = grid.ii.copy()
     jc = grid.jj.copy()
     if not grid.periodic_j:
-        jc[0] = 1
+        jc[0] = np.where(grid.wall_col, 1, 0)
         jc[-1] = grid.nj - 2
-    return jc
+    if grid.cgrid:
+        ic[:, 0] = 1
+        ic[:, -1] = grid.ni - 2
+    return ic, jc
 
 
 def interpolate(grid, fstar_i, a, b):
     """f_i(node) = sum_s N_s(xi_dp) f*_i(xi_s) over the 3 x 3 element
     (Sec. II.B, Eq. for f_i(X, t))."""
-    jc = stencil_centre_rows(grid)
+    ic, jc = stencil_centres(grid)
+    ac = a + (grid.ii - ic)
     bc = b + (grid.jj - jc)
     out = np.zeros(a.shape)
     for p in (-1, 0, 1):
-        La = lagrange_1d(p, a)
+        La = lagrange_1d(p, ac)
         for q in (-1, 0, 1):
             Lb = lagrange_1d(q, bc)
-            jj = jc + q
-            if grid.periodic_j:
-                jj = jj % grid.nj
-            ii = (grid.ii + p) % grid.ni
-            out = out + La * Lb * fstar_i[jj, ii]
+            out = out + La * Lb * grid.gather(fstar_i, ic + p, jc + q)
     return out
 
 
-def stream(grid, X, Y, x1, y1, VGx, VGy, dt, fpost, gpost, skip_rows=()):
+def boundary_nodes(grid):
+    """Nodes whose populations the far-field condition replaces: row nj - 1
+    of an O-grid or C-grid, and the two exit columns of a C-grid."""
+    far = np.zeros((grid.nj, grid.ni), dtype=bool)
+    if not grid.periodic_j:
+        far[-1] = True
+    if grid.cgrid:
+        far[:, 0] = True
+        far[:, -1] = True
+    return far
+
+
+def stream(grid, X, Y, x1, y1, VGx, VGy, dt, fpost, gpost):
     """Interpolating ALE streaming of both population sets.
 
-    Returns (f_new, g_new, missing[9]); rows in ``skip_rows`` (the far-field
-    row, whose populations the boundary condition replaces) are left NaN,
-    as are populations flagged missing at the wall.
+    Returns (f_new, g_new, missing[9]); far-field nodes (whose populations the
+    boundary condition replaces) are left NaN, as are populations flagged
+    missing at the wall.
     """
     chat = transformed_velocities(grid, X, Y, x1, y1, VGx, VGy)
     f_new = np.full(fpost.shape, np.nan)
     g_new = np.full(gpost.shape, np.nan)
     missing = np.zeros(fpost.shape, dtype=bool)
-    active = np.ones(X.shape, dtype=bool)
-    for r in skip_rows:
-        active[r] = False
-    wall = not grid.periodic_j
+    active = ~boundary_nodes(grid)
+    wall = bool(np.any(grid.wall_col))
     for i in range(Q):
         if i == 0:
             f_new[0] = fpost[0]
             g_new[0] = gpost[0]
             continue
         chx, chy = chat[i]
-        a, b, miss = _offsets_on_active(grid, X, Y, chx, chy, dt, active, wall)
-        fi = interpolate(grid, fpost[i], np.where(np.isnan(a), 0.0, a),
-                         np.where(np.isnan(b), 0.0, b))
-        gi = interpolate(grid, gpost[i], np.where(np.isnan(a), 0.0, a),
-                         np.where(np.isnan(b), 0.0, b))
+        # far-field nodes get a zero offset (never used) so they cannot raise
+        chx = np.where(active, chx, 0.0)
+        chy = np.where(active, chy, 0.0)
+        a, b, miss = departure_offsets(grid, X, Y, chx, chy, dt, wall_row=wall)
+        a = np.where(np.isnan(a), 0.0, a)
+        b = np.where(np.isnan(b), 0.0, b)
+        fi = interpolate(grid, fpost[i], a, b)
+        gi = interpolate(grid, gpost[i], a, b)
         keep = active & ~miss
         f_new[i] = np.where(keep, fi, np.nan)
         g_new[i] = np.where(keep, gi, np.nan)
         missing[i] = miss & active
     return f_new, g_new, missing
-
-
-def _offsets_on_active(grid, X, Y, chx, chy, dt, active, wall):
-    # inactive rows get a zero offset (never used) so they cannot raise
-    chx = np.where(active, chx, 0.0)
-    chy = np.where(active, chy, 0.0)
-    return departure_offsets(grid, X, Y, chx, chy, dt, wall_row=wall)

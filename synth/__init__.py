@@ -12,6 +12,7 @@ from .meshes import (  # noqa: F401
     periodic_sine_mesh,
     cartesian_mesh,
     ogrid_mesh,
+    cgrid_mesh,
     geometric_ratio,
 )
 from .configs import (  # noqa: F401
@@ -22,4 +23,6 @@ from .configs import (  # noqa: F401
     large_heave_case,
     batched_sweep_cases,
     gaussian_pulse_fields,
+    airfoil_flutter_case,
+    small_airfoil_case,
 )

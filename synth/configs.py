@@ -15,7 +15,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .meshes import MeshSpec, ogrid_mesh, periodic_sine_mesh
+from .meshes import MeshSpec, cgrid_mesh, ogrid_mesh, periodic_sine_mesh
 
 DOF_PRESCRIBED = 0
 DOF_HEAVE = 1
@@ -232,6 +232,105 @@ def batched_sweep_cases(n_instances: int = 64, seed: int = 0, D: float = 200.0,
                                        dt=1.0 / 3.0, steps=steps,
                                        name=f"sweep{k:02d}_{n_r}x{2 * n_r}"))
     return cases
+
+
+def distance_to_polygon(X: np.ndarray, Y: np.ndarray, px: np.ndarray, py: np.ndarray,
+                        chunk: int = 4096) -> np.ndarray:
+    """Distance from every point (X, Y) to the closed polygon (px, py)."""
+    ax, ay = px, py
+    bx, by = np.roll(px, -1), np.roll(py, -1)
+    ex, ey = bx - ax, by - ay
+    ee = np.maximum(ex * ex + ey * ey, 1e-300)
+    xf, yf = X.ravel(), Y.ravel()
+    out = np.empty(xf.size)
+    for k0 in range(0, xf.size, chunk):
+        x = xf[k0:k0 + chunk, None]
+        y = yf[k0:k0 + chunk, None]
+        t = np.clip(((x - ax) * ex + (y - ay) * ey) / ee, 0.0, 1.0)
+        dx = x - (ax + t * ex)
+        dy = y - (ay + t * ey)
+        out[k0:k0 + chunk] = np.sqrt(np.min(dx * dx + dy * dy, axis=1))
+    return out.reshape(X.shape)
+
+
+def airfoil_start_fields(mesh: MeshSpec, U: float, rho0: float, T0: float, delta: float):
+    """Uniform stream along +x multiplied by tanh(d / delta), d the distance to
+    the airfoil section (the wall row of the C-grid); uniform rho and T."""
+    nw = mesh.n_wake
+    px = mesh.X[0, nw:mesh.ni - nw - 1]
+    py = mesh.Y[0, nw:mesh.ni - nw - 1]
+    d = distance_to_polygon(mesh.X, mesh.Y, px, py)
+    ux = U * np.tanh(d / delta)
+    shape = mesh.X.shape
+    return np.full(shape, float(rho0)), ux, np.zeros(shape), np.full(shape, float(T0))
+
+
+def pitch_plunge_body_params(chord: float, rho: float, U: float, mstar: float,
+                             freq_ratio: float, x_alpha: float, r_alpha: float, VR: float,
+                             ea_frac: float, r_rigid: float, r_blend: float,
+                             alpha0: float = 0.0, origin=(0.0, 0.0)) -> BodyParams:
+    """2DOF pitch-plunge section (semi-chord b = chord / 2, leading edge at
+    ``origin``): m = m* pi rho b^2, I_a = m r_a^2 b^2, S_a = m x_a b,
+    omega_a = U / (b V_R sqrt(m*)), k_a = I_a omega_a^2, omega_h = ratio omega_a,
+    k_h = m omega_h^2; the elastic axis at ea_frac * chord, the blending centre
+    at mid-chord; alpha counter-clockwise, h along +y."""
+    b = 0.5 * chord
+    m = mstar * math.pi * rho * b * b
+    I_a = m * r_alpha * r_alpha * b * b
+    S_a = m * x_alpha * b
+    om_a = U / (b * VR * math.sqrt(mstar))
+    om_h = freq_ratio * om_a
+    return BodyParams(dof=DOF_PITCH_PLUNGE, m=m, S_a=S_a, I_a=I_a, k_h=m * om_h * om_h,
+                      k_a=I_a * om_a * om_a,
+                      center=(origin[0] + 0.5 * chord, origin[1]),
+                      ea=(origin[0] + ea_frac * chord, origin[1]),
+                      r_rigid=r_rigid, r_blend=r_blend, a0=alpha0)
+
+
+def airfoil_flutter_case(n_wake: int = 128, n_af: int = 512, nj: int = 256,
+                         chord: float = 200.0, first_cell: float = 0.25,
+                         far_chords: float = 20.0, Ma: float = 0.85, Re: float = 1.0e5,
+                         T_inf: float = 0.2, gamma: float = 1.4, Pr: float = 0.71,
+                         mstar: float = 60.0, freq_ratio: float = 0.34, x_alpha: float = 1.8,
+                         r_alpha: float = 1.87, VR: float = 0.5025, ea_frac: float = 0.25,
+                         alpha0_deg: float = 1.0, blend_chords: float = 10.0,
+                         steps: int = 50000, storage: int = 0,
+                         name: str | None = None) -> Case:
+    """Pitch-plunge NACA0012 section on a C-grid (768 x 256 with the defaults:
+    128 + 512 + 128 nodes along the wrap-around index, far field 20 chords).
+
+    dt is a third of the smallest wall spacing (first cell or wall-node
+    spacing); the start is a uniform stream with a tanh layer at the wall."""
+    mesh = cgrid_mesh(n_wake, n_af, nj, chord, first_cell, far_chords)
+    U = Ma * sound_speed(gamma, T_inf)
+    rho = 1.0
+    mu = rho * U * chord / Re
+    wall = np.hypot(np.diff(mesh.X[0, n_wake:n_wake + n_af]),
+                    np.diff(mesh.Y[0, n_wake:n_wake + n_af]))
+    h_min = min(first_cell, float(wall.min()))
+    dt = h_min / 3.0
+    fluid = FluidParams(gamma=gamma, Pr=Pr, mu=mu, rho_inf=rho, T_inf=T_inf,
+                        u_inf=(U, 0.0), dt=dt, storage=storage)
+    body = pitch_plunge_body_params(chord, rho, U, mstar, freq_ratio, x_alpha, r_alpha, VR,
+                                    ea_frac, r_rigid=0.55 * chord,
+                                    r_blend=blend_chords * chord,
+                                    alpha0=math.radians(alpha0_deg))
+    r, ux, uy, T = airfoil_start_fields(mesh, U, rho, T_inf, start_layer_width(chord, first_cell))
+    return Case(name or f"airfoil_flutter_{mesh.ni}x{nj}", mesh, fluid, [body], r, ux, uy, T,
+                steps, info={"chord": chord, "U": U, "Ma": Ma, "Re": Re, "mstar": mstar})
+
+
+def small_airfoil_case(n_wake: int = 16, n_af: int = 64, nj: int = 32, chord: float = 40.0,
+                       first_cell: float = 0.5, far_chords: float = 4.0, Ma: float = 0.3,
+                       Re: float = 200.0, T_inf: float = 1.0 / 3.0, mstar: float = 5.0,
+                       alpha0_deg: float = 1.0, blend_chords: float = 2.5,
+                       steps: int = 200) -> Case:
+    """A small C-grid pitch-plunge case the oracle can run for many steps."""
+    return airfoil_flutter_case(n_wake=n_wake, n_af=n_af, nj=nj, chord=chord,
+                                first_cell=first_cell, far_chords=far_chords, Ma=Ma, Re=Re,
+                                T_inf=T_inf, mstar=mstar, alpha0_deg=alpha0_deg,
+                                blend_chords=blend_chords, steps=steps,
+                                name=f"small_airfoil_{2 * n_wake + n_af}x{nj}")
 
 
 def with_fluid(case: Case, **kw) -> Case:

@@ -14,6 +14,15 @@ Topologies
     periodic in i without a coordinate shift; row j = 0 is a solid wall and row
     j = nj - 1 is the far-field boundary.  Nodes run clockwise in i so that
     det(d(x, y)/d(i, j)) > 0 with j pointing into the fluid.
+``TOPO_CGRID`` (2)
+    C-grid around an airfoil with a wake cut: i runs from the lower end of the
+    cut (downstream exit), along the lower side of the cut to the trailing
+    edge, round the airfoil (lower surface, leading edge, upper surface) back
+    to the trailing edge and along the upper side of the cut to the exit.
+    ``n_wake`` nodes lie on each side of the cut; the trailing edge appears
+    twice (i = n_wake and i = ni - 1 - n_wake) and every cut node (i, 0)
+    coincides with (ni - 1 - i, 0).  Row j = 0 between the trailing-edge
+    copies is the wall; row j = nj - 1 and columns i = 0, ni - 1 are far field.
 """
 
 from __future__ import annotations
@@ -37,6 +46,7 @@ class MeshSpec:
     shift_i: tuple = (0.0, 0.0)
     shift_j: tuple = (0.0, 0.0)
     info: dict = field(default_factory=dict)
+    n_wake: int = 0            # C-grid: nodes on each side of the wake cut
 
     @property
     def n_nodes(self) -> int:
@@ -121,3 +131,108 @@ def ogrid_mesh(n_r: int, n_theta: int, diameter: float, first_cell: float,
                     info={"kind": "ogrid", "diameter": diameter,
                           "first_cell": first_cell, "r_far": r_far, "ratio": q,
                           "center": tuple(center)})
+
+
+def naca_thickness(x: np.ndarray, chord: float, t: float) -> np.ndarray:
+    """Half-thickness of a symmetric NACA 4-digit section with a closed
+    trailing edge (last coefficient -0.1036 instead of -0.1015)."""
+    u = np.clip(x / chord, 0.0, 1.0)
+    return 5.0 * t * chord * (0.2969 * np.sqrt(u) - 0.1260 * u - 0.3516 * u ** 2
+                              + 0.2843 * u ** 3 - 0.1036 * u ** 4)
+
+
+def _airfoil_nodes(n_af: int, chord: float, t: float, cluster: float):
+    """Wall nodes from the lower trailing edge round the leading edge to the
+    upper trailing edge (both trailing-edge copies included), spaced in arc
+    length with density 1 - cluster cos(4 pi u): finest at the trailing and
+    leading edges, coarsest at mid-chord."""
+    # dense parametrisation: x = c (1 + cos(2 pi s)) / 2, lower surface for s < 1/2
+    s = np.linspace(0.0, 1.0, 200001)
+    x = 0.5 * chord * (1.0 + np.cos(2.0 * np.pi * s))
+    y = np.where(s < 0.5, -1.0, 1.0) * naca_thickness(x, chord, t)
+    seg = np.hypot(np.diff(x), np.diff(y))
+    S = np.concatenate([[0.0], np.cumsum(seg)])
+    u = np.arange(n_af, dtype=np.float64) / (n_af - 1)
+    phi = u - cluster * np.sin(4.0 * np.pi * u) / (4.0 * np.pi)
+    target = phi * S[-1]
+    sk = np.interp(target, S, s)
+    xk = 0.5 * chord * (1.0 + np.cos(2.0 * np.pi * sk))
+    yk = np.where(sk < 0.5, -1.0, 1.0) * naca_thickness(xk, chord, t)
+    xk[0] = xk[-1] = chord
+    yk[0] = yk[-1] = 0.0
+    # exact mirror symmetry about the chord line
+    half = n_af // 2
+    xk[n_af - half:] = xk[:half][::-1]
+    yk[n_af - half:] = -yk[:half][::-1]
+    return xk, yk
+
+
+def cgrid_mesh(n_wake: int, n_af: int, nj: int, chord: float, first_cell: float,
+               far_chords: float, t: float = 0.12, cluster: float = 0.6,
+               origin=(0.0, 0.0)) -> MeshSpec:
+    """C-grid around a NACA 00xx airfoil (leading edge at ``origin``, chord
+    along +x) from the parabolic map z = zeta^2 + x_o, with x_o half the
+    leading-edge radius so that the map's branch point lies inside the nose.
+
+    In the zeta = xi + i eta half plane the wake cut is eta = 0 and the
+    airfoil a graph eta_w(xi); column i is the line xi = xi_i, row j sits at
+    eta_w + (eta_max - eta_w) * (geometric fraction) with the first step
+    chosen so that the first physical cell is about ``first_cell`` long.  The
+    outer parabola eta = eta_max passes far_chords * chord upstream of the
+    leading edge and the exit columns far_chords * chord downstream of the
+    trailing edge; every far-field point is at least that far from the
+    leading edge.  The mesh is mirror-symmetric about the chord line.
+    """
+    if n_af % 2 or n_wake < 2:
+        raise ValueError("n_af must be even and n_wake >= 2")
+    ni = 2 * n_wake + n_af
+    x_o = 0.5 * 1.1019 * t * t * chord
+    xa, ya = _airfoil_nodes(n_af, chord, t, cluster)
+    # wake cut: from the trailing edge to the exit, geometric in x starting
+    # with the trailing-edge spacing of the airfoil nodes
+    te_step = float(np.hypot(xa[1] - xa[0], ya[1] - ya[0]))
+    q = geometric_ratio(n_wake, te_step, far_chords * chord)
+    k = np.arange(1, n_wake + 1, dtype=np.float64)
+    xw = chord + te_step * (q ** k - 1.0) / (q - 1.0)
+    xw[-1] = chord * (1.0 + far_chords)
+    # wall / cut points in the zeta plane (branch with Im zeta >= 0)
+    zw = (xa - x_o) + 1j * ya
+    ang = np.mod(np.angle(zw), 2.0 * np.pi)
+    zeta_af = np.sqrt(np.abs(zw)) * np.exp(0.5j * ang)
+    zeta_af[0] = -np.sqrt(chord - x_o)
+    zeta_af[-1] = np.sqrt(chord - x_o)
+    xi_w = np.sqrt(xw - x_o)
+    xi = np.concatenate([-xi_w[::-1], zeta_af.real, xi_w[::-1][::-1]])
+    eta_w = np.concatenate([np.zeros(n_wake), np.maximum(zeta_af.imag, 0.0), np.zeros(n_wake)])
+    eta_max = np.sqrt(far_chords * chord + x_o)
+    # per-column geometric distribution in eta; physical step ~ 2 |zeta| d eta
+    X = np.empty((nj, ni))
+    Y = np.empty((nj, ni))
+    jj = np.arange(nj, dtype=np.float64)
+    for i in range(ni):
+        zmag = max(abs(complex(xi[i], eta_w[i])), 1e-12)
+        d_eta = first_cell / (2.0 * zmag)
+        span = eta_max - eta_w[i]
+        qi = geometric_ratio(nj - 1, d_eta, span)
+        frac = jj if qi == 1.0 else (qi ** jj - 1.0) / (qi - 1.0)
+        eta = eta_w[i] + d_eta * frac
+        eta[-1] = eta_max
+        z = (xi[i] + 1j * eta) ** 2 + x_o
+        X[:, i] = z.real
+        Y[:, i] = z.imag
+    # wall row exactly on the section; the upper half is the exact mirror image
+    # of the lower half (so the cut rows are exactly duplicated)
+    X[0, n_wake:n_wake + n_af] = xa
+    Y[0, n_wake:n_wake + n_af] = ya
+    lo = np.arange(ni // 2)
+    X[:, ni - 1 - lo] = X[:, lo]
+    Y[:, ni - 1 - lo] = -Y[:, lo]
+    Y[0, :n_wake + 1] = 0.0
+    Y[0, ni - 1 - n_wake:] = 0.0
+    X += origin[0]
+    Y += origin[1]
+    return MeshSpec(ni, nj, TOPO_CGRID, X, Y, n_wake=n_wake,
+                    info={"kind": "cgrid", "n_wake": n_wake, "chord": chord,
+                          "thickness": t, "first_cell": first_cell,
+                          "far_chords": far_chords, "x_o": x_o, "wake_ratio": q,
+                          "origin": tuple(origin)})
