@@ -82,8 +82,21 @@ typedef struct {
  *              the coordinates.  No wall, no far field.
  *   OGRID:     periodic in i (no shift); row j = 0 is the body wall, row
  *              j = nj - 1 the far field.  dX/dxi must have a positive
- *              determinant (i runs clockwise when j points outward).        */
-typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1 } fsi_topo;
+ *              determinant (i runs clockwise when j points outward).
+ *   CGRID:     C-grid round a section with a wake cut.  i runs from the lower
+ *              exit along the lower side of the cut, round the section
+ *              (clockwise) and along the upper side of the cut to the upper
+ *              exit; n_wake nodes lie on each side of the cut.  Row 0 holds
+ *              every cut point and the trailing edge twice: (i, 0) and
+ *              (ni - 1 - i, 0) must coincide for i <= n_wake, and node (i, -m)
+ *              is node (ni - 1 - i, m).  The wall is row 0 between the two
+ *              trailing-edge copies (columns [n_wake, ni - n_wake)); row nj - 1
+ *              and the exit columns i = 0, ni - 1 are far field.  The
+ *              duplicated nodes are kept single-valued: the two trailing-edge
+ *              copies merge (per population, the streamed value of the copy
+ *              whose cells hold the departure point, else their mean) and the
+ *              upper copy of each cut node takes the lower copy's state.   */
+typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1, FSI_TOPO_CGRID = 2 } fsi_topo;
 
 typedef struct {
     int ni, nj;             /* nodes in i (fast) and j; ni >= 8, nj >= 8 */
@@ -91,6 +104,7 @@ typedef struct {
     const double *X;        /* host, [nj][ni][2] undeformed coordinates, FP64; copied */
     double shift_i[2];      /* PERIODIC2 only */
     double shift_j[2];      /* PERIODIC2 only */
+    int n_wake;             /* CGRID only: cut nodes on each side (>= 2) */
 } fsi_mesh_desc;
 
 /* Rigid-body degrees of freedom (Sec. IV). */

@@ -114,13 +114,13 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
         corners = []
         for (ci, cj) in ((0, 0), (1, 0), (0, 1), (1, 1)):
             px, py = grid.neighbour_pos(X, Y, di0 + ci, dj0 + cj)
+            if dj0 < 0:                     # no cells below the wall
+                px = np.where(wall_node, np.nan, px)
             corners.append((px - X, py - Y))
         with np.errstate(invalid="ignore", divide="ignore"):
             s, t, _ = bilinear_inverse(*corners, Pdx, Pdy)
         inside = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL)
                   & (t >= -CELL_TOL) & (t <= 1 + CELL_TOL))
-        if dj0 < 0:
-            inside &= ~wall_node            # no cells below the wall
         take = inside & ~found
         a = np.where(take, di0 + s, a)
         b = np.where(take, dj0 + t, b)

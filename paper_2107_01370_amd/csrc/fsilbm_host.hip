@@ -15,7 +15,8 @@ using fsi::Inst;
 
 struct fsi_ctx {
     fsi_fluid_params fluid{};
-    int ni = 0, nj = 0, topo = 0;
+    int ni = 0, nj = 0, topo = 0, n_wake = 0;
+    bool has_wall = false;      // O-grid or C-grid
     double shift_i[2] = {0, 0}, shift_j[2] = {0, 0};
     std::vector<double> X;          // [nj][ni][2]
     fsi_body_desc body{};
@@ -25,11 +26,13 @@ struct fsi_ctx {
     // workspace layout (byte offsets)
     size_t off_pop[2]{}, off_X = 0, off_mask = 0, off_tgt = 0, off_B = 0, off_inflow = 0,
            off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
-           off_wk1 = 0, off_wbnd = 0, off_wwall = 0, total = 0;
+           off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0,
+           total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
-    std::vector<uint8_t> inflow;
-    std::vector<int2> wk1, wbnd, wwall;
+    std::vector<uint8_t> inflow;        // per far-field list entry
+    std::vector<int2> ff;               // far-field (node, interior node)
+    std::vector<int2> wk0, wk1, wbnd, wwall;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int64_t host_step = 0;
@@ -62,6 +65,15 @@ int wrapi(int a, int n) { return ((a % n) + n) % n; }
 
 // coordinate of node (i, j) seen from an unwrapped index, with periodic shifts
 void coord(const fsi_ctx *c, int i, int j, double &x, double &y) {
+    if (c->topo == FSI_TOPO_CGRID) {
+        if (j < 0) {                       // across the wake cut
+            i = c->ni - 1 - i;
+            j = -j;
+        }
+        x = c->X[2 * ((size_t)j * c->ni + i)];
+        y = c->X[2 * ((size_t)j * c->ni + i) + 1];
+        return;
+    }
     const int wi = (int)floor((double)i / c->ni), wj = (int)floor((double)j / c->nj);
     const int ii = i - wi * c->ni;
     const int jj = c->topo == FSI_TOPO_PERIODIC2 ? j - wj * c->nj : j;
@@ -113,29 +125,69 @@ fsi::BodySlot slot_of(double h, double a, double hd, double ad) {
     return s;
 }
 
+bool is_wall_col(const fsi_ctx *c, int i) {
+    return c->topo == FSI_TOPO_OGRID || (i >= c->n_wake && i < c->ni - c->n_wake);
+}
+
+// index-space FE derivative of the undeformed coordinates at node (i, j):
+// centred, one-sided 3-point on wall columns of row 0, on row nj - 1 and on
+// the exit columns of a C-grid; across the cut (mirror) on C-grid cut columns
+void dX_di(const fsi_ctx *c, int i, int j, double &xd, double &yd) {
+    double x0, y0, x1, y1, x2, y2;
+    if (c->topo == FSI_TOPO_CGRID && (i == 0 || i == c->ni - 1)) {
+        const int s = i == 0 ? 1 : -1;
+        coord(c, i, j, x0, y0);
+        coord(c, i + s, j, x1, y1);
+        coord(c, i + 2 * s, j, x2, y2);
+        xd = s * (2.0 * (x1 - x0) - 0.5 * (x2 - x0));
+        yd = s * (2.0 * (y1 - y0) - 0.5 * (y2 - y0));
+        return;
+    }
+    coord(c, i + 1, j, x1, y1);
+    coord(c, i - 1, j, x0, y0);
+    xd = 0.5 * (x1 - x0);
+    yd = 0.5 * (y1 - y0);
+}
+
+void dX_dj(const fsi_ctx *c, int i, int j, double &xd, double &yd) {
+    double x0, y0, x1, y1, x2, y2;
+    const bool wall_row = c->has_wall && j == 0 && is_wall_col(c, i);
+    if (wall_row || (c->has_wall && j == c->nj - 1)) {
+        const int s = j == 0 ? 1 : -1;
+        coord(c, i, j, x0, y0);
+        coord(c, i, j + s, x1, y1);
+        coord(c, i, j + 2 * s, x2, y2);
+        xd = s * (2.0 * (x1 - x0) - 0.5 * (x2 - x0));
+        yd = s * (2.0 * (y1 - y0) - 0.5 * (y2 - y0));
+        return;
+    }
+    coord(c, i, j + 1, x1, y1);
+    coord(c, i, j - 1, x0, y0);
+    xd = 0.5 * (x1 - x0);
+    yd = 0.5 * (y1 - y0);
+}
+
 fsi_status validate_and_precompute(fsi_ctx *c) {
     const int ni = c->ni, nj = c->nj;
-    // det(dX/dxi) > 0 everywhere (FE metric: centred, one-sided on O-grid end rows)
+    if (c->topo == FSI_TOPO_CGRID) {
+        if (c->n_wake < 2 || ni - 2 * c->n_wake < 8)
+            return fail(c, FSI_E_MESH, "C-grid needs n_wake >= 2 and at least 8 wall nodes");
+        // row 0: cut nodes and the trailing edge appear twice
+        for (int i = 0; i <= c->n_wake; ++i) {
+            const double *a = &c->X[2 * (size_t)i], *b = &c->X[2 * (size_t)(ni - 1 - i)];
+            if (a[0] != b[0] || a[1] != b[1])
+                return fail(c, FSI_E_MESH, "C-grid cut nodes (i, 0) and (ni-1-i, 0) must coincide "
+                                           "for i <= n_wake (first mismatch at i = " +
+                                               std::to_string(i) + ")");
+        }
+    }
+    // det(dX/dxi) > 0 everywhere (FE metric of the topology)
     for (int j = 0; j < nj; ++j) {
         for (int i = 0; i < ni; ++i) {
-            double xp, yp, xm, ym, x0, y0, x1, y1, x2, y2;
-            coord(c, i + 1, j, xp, yp);
-            coord(c, i - 1, j, xm, ym);
-            double xe, ye;
-            if (c->topo == FSI_TOPO_OGRID && (j == 0 || j == nj - 1)) {
-                const int s = j == 0 ? 1 : -1;
-                coord(c, i, j, x0, y0);
-                coord(c, i, j + s, x1, y1);
-                coord(c, i, j + 2 * s, x2, y2);
-                xe = s * (2.0 * (x1 - x0) - 0.5 * (x2 - x0));
-                ye = s * (2.0 * (y1 - y0) - 0.5 * (y2 - y0));
-            } else {
-                coord(c, i, j + 1, x1, y1);
-                coord(c, i, j - 1, x0, y0);
-                xe = 0.5 * (x1 - x0);
-                ye = 0.5 * (y1 - y0);
-            }
-            const double det = 0.5 * (xp - xm) * ye - 0.5 * (yp - ym) * xe;
+            double xi, yi, xe, ye;
+            dX_di(c, i, j, xi, yi);
+            dX_dj(c, i, j, xe, ye);
+            const double det = xi * ye - yi * xe;
             if (!(det > 0))
                 return fail(c, FSI_E_MESH, "det(dX/dxi) <= 0 at node (" + std::to_string(i) + ", " +
                                                std::to_string(j) + "): mesh must be right-handed");
@@ -159,11 +211,13 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
                 }
         }
     }
-    if (c->topo == FSI_TOPO_OGRID) {
+    c->ff.clear();
+    c->inflow.clear();
+    c->wallB.assign(ni, make_float2(0, 0));
+    if (c->has_wall) {
         const double dt = c->fluid.dt;
-        c->wallB.assign(ni, make_float2(0, 0));
-        c->inflow.assign(ni, 0);
         for (int i = 0; i < ni; ++i) {
+            if (!is_wall_col(c, i)) continue;
             double xp, yp, xm, ym, x0, y0;
             coord(c, i + 1, 0, xp, yp);
             coord(c, i - 1, 0, xm, ym);
@@ -190,13 +244,28 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
             if (!found)
                 return fail(c, FSI_E_MESH, "wall point B (distance dt along the normal) leaves the "
                                            "first cell row at wall node " + std::to_string(i));
-            // far-field inlet flag: u_inf . n_out < 0, n_out = rot90(tangent)
-            double fxp, fyp, fxm, fym;
-            coord(c, i + 1, nj - 1, fxp, fyp);
-            coord(c, i - 1, nj - 1, fxm, fym);
-            const double ftx = fxp - fxm, fty = fyp - fym;
-            const double nx = -fty, ny = ftx;
-            c->inflow[i] = (c->fluid.u_inf[0] * nx + c->fluid.u_inf[1] * ny) < 0.0 ? 1 : 0;
+        }
+        // far-field nodes: row nj - 1 (n_out = rot90(dX/di)), then the C-grid
+        // exit columns (n_out = +-rot90(dX/dj)); inlet where u_inf . n_out < 0
+        const double ux = c->fluid.u_inf[0], uy = c->fluid.u_inf[1];
+        auto add = [&](int i, int j, double nx, double ny, int ir, int jr) {
+            c->ff.push_back(make_int2(j * ni + i, jr * ni + ir));
+            c->inflow.push_back((ux * nx + uy * ny) < 0.0 ? 1 : 0);
+        };
+        const bool cg = c->topo == FSI_TOPO_CGRID;
+        for (int i = 0; i < ni; ++i) {
+            double xd, yd;
+            dX_di(c, i, nj - 1, xd, yd);
+            add(i, nj - 1, -yd, xd, cg ? std::min(std::max(i, 1), ni - 2) : i, nj - 2);
+        }
+        if (cg) {
+            for (int j = 0; j < nj - 1; ++j) {
+                double xd, yd;
+                dX_dj(c, 0, j, xd, yd);
+                add(0, j, -yd, xd, 1, j);
+                dX_dj(c, ni - 1, j, xd, yd);
+                add(ni - 1, j, yd, -xd, ni - 2, j);
+            }
         }
     }
     return FSI_OK;
@@ -208,6 +277,13 @@ void fill_params(fsi_ctx *c) {
     P.ni = c->ni;
     P.nj = c->nj;
     P.periodic_j = c->topo == FSI_TOPO_PERIODIC2;
+    P.cgrid = c->topo == FSI_TOPO_CGRID;
+    P.n_wake = P.cgrid ? c->n_wake : 0;
+    P.wall_i0 = P.cgrid ? c->n_wake : 0;
+    P.wall_n = c->has_wall ? (P.cgrid ? c->ni - 2 * c->n_wake : c->ni) : 0;
+    P.force_n = P.cgrid ? P.wall_n - 1 : P.wall_n;
+    P.n_ff = (int)c->ff.size();
+    P.cut_n = P.cgrid ? 2 * (c->n_wake + 1) : 0;
     P.storage = fl.storage;
     P.tiles_i = (c->ni + fsi::TILE_X - 1) / fsi::TILE_X;
     P.tiles_j = (c->nj + fsi::TILE_Y - 1) / fsi::TILE_Y;
@@ -264,12 +340,21 @@ void fill_params(fsi_ctx *c) {
     for (int t = 0; t < ntiles; ++t) c->wk1[t] = make_int2(0, t);
     c->wbnd.clear();
     c->wwall.clear();
-    if (c->topo == FSI_TOPO_OGRID) {
-        const int nb = (c->ni + 63) / 64;
-        for (int b = 0; b < nb; ++b) {
+    c->wk0.clear();
+    if (c->has_wall) {
+        const int nw = (P.wall_n + 63) / 64, nf = (P.n_ff + 63) / 64;
+        for (int b = 0; b < nw; ++b) {
             c->wbnd.push_back(make_int2(0, 2 * b));
-            c->wbnd.push_back(make_int2(0, 2 * b + 1));
             c->wwall.push_back(make_int2(0, b));
+        }
+        for (int b = 0; b < nf; ++b) c->wbnd.push_back(make_int2(0, 2 * b + 1));
+    }
+    if (P.cgrid) {
+        // tiles of row block 0 that own a cut column or a trailing-edge copy
+        for (int ti = 0; ti < P.tiles_i; ++ti) {
+            const int a = ti * fsi::TILE_X, b = std::min(a + fsi::TILE_X, c->ni) - 1;
+            const bool lower = a <= c->n_wake, upper = b >= c->ni - 1 - c->n_wake;
+            if (lower || upper) c->wk0.push_back(make_int2(0, ti));
         }
     }
 }
@@ -285,7 +370,9 @@ void layout(fsi_ctx *c) {
     c->off_mask = take(c->ni * 2);
     c->off_tgt = take(c->ni * 16);
     c->off_B = take(c->ni * 8);
-    c->off_inflow = take(c->ni);
+    c->off_inflow = take(c->ff.size());
+    c->off_ff = take(c->ff.size() * sizeof(int2));
+    c->off_cut = take((size_t)16 * c->inst.cut_n * sizeof(float));
     c->off_force = take(c->ni * 32);
     c->off_slots = take(3 * sizeof(fsi::BodySlot));
     c->off_hist = take((size_t)fsi::HIST_CAP * 6 * 8);
@@ -295,6 +382,7 @@ void layout(fsi_ctx *c) {
     c->off_wk1 = take(c->wk1.size() * sizeof(int2));
     c->off_wbnd = take(c->wbnd.size() * sizeof(int2));
     c->off_wwall = take(c->wwall.size() * sizeof(int2));
+    c->off_wk0 = take(c->wk0.size() * sizeof(int2));
     c->total = o;
 }
 
@@ -309,9 +397,12 @@ const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c
 
 fsi_status enqueue_step(fsi_ctx *c) {
     const int st = c->fluid.storage;
+    if (!c->wk0.empty())
+        HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
+                                          (int)c->wk0.size(), st, c->stream));
     HIP_TRY(c, fsi::launch_collide_stream(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
                                           (int)c->wk1.size(), st, c->stream));
-    if (c->topo == FSI_TOPO_OGRID) {
+    if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
         HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
@@ -324,7 +415,7 @@ fsi_status enqueue_step(fsi_ctx *c) {
 
 // force of the current level and the next body state (no boundary update)
 fsi_status enqueue_load_update(fsi_ctx *c) {
-    if (c->topo == FSI_TOPO_OGRID)
+    if (c->has_wall)
         HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
                                                reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
                                                (int)c->wwall.size(), c->fluid.storage, 0, c->stream));
@@ -367,9 +458,11 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
     c->ni = mesh->ni;
     c->nj = mesh->nj;
     c->topo = mesh->topo;
+    c->n_wake = mesh->n_wake;
+    c->has_wall = c->topo == FSI_TOPO_OGRID || c->topo == FSI_TOPO_CGRID;
     c->stream = (hipStream_t)hip_stream;
     if (c->ni < 8 || c->nj < 8) return fail(c, FSI_E_ARG, "mesh needs ni >= 8 and nj >= 8");
-    if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_OGRID)
+    if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_OGRID && c->topo != FSI_TOPO_CGRID)
         return fail(c, FSI_E_ARG, "unsupported topology");
     if (nbodies < 0 || nbodies > 1 || (nbodies == 1 && !bodies))
         return fail(c, FSI_E_ARG, "nbodies must be 0 or 1");
@@ -384,7 +477,7 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
         c->shift_i[k] = mesh->shift_i[k];
         c->shift_j[k] = mesh->shift_j[k];
     }
-    if (c->topo == FSI_TOPO_OGRID) c->shift_i[0] = c->shift_i[1] = c->shift_j[0] = c->shift_j[1] = 0;
+    if (c->topo != FSI_TOPO_PERIODIC2) c->shift_i[0] = c->shift_i[1] = c->shift_j[0] = c->shift_j[1] = 0;
     c->X.assign(mesh->X, mesh->X + 2 * (size_t)c->ni * c->nj);
     for (double v : c->X)
         if (!isfinite(v)) return fail(c, FSI_E_MESH, "non-finite mesh coordinate");
@@ -421,6 +514,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     P.wall_tgt = reinterpret_cast<float4 *>(c->ws + c->off_tgt);
     P.wall_B = reinterpret_cast<const float2 *>(c->ws + c->off_B);
     P.inflow = reinterpret_cast<const uint8_t *>(c->ws + c->off_inflow);
+    P.ff = reinterpret_cast<const int2 *>(c->ws + c->off_ff);
+    P.cutbuf = reinterpret_cast<float *>(c->ws + c->off_cut);
     P.wall_force = reinterpret_cast<double4 *>(c->ws + c->off_force);
     P.slots = reinterpret_cast<fsi::BodySlot *>(c->ws + c->off_slots);
     P.history = reinterpret_cast<double *>(c->ws + c->off_hist);
@@ -434,9 +529,17 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_hist, 0, (size_t)fsi::HIST_CAP * 48, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_step, 0, 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
-    if (c->topo == FSI_TOPO_OGRID) {
+    if (!c->wk0.empty()) {
+        HIP_TRY(c, hipMemsetAsync(c->ws + c->off_cut, 0, (size_t)16 * c->inst.cut_n * 4, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk0, c->wk0.data(), c->wk0.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    if (c->has_wall) {
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_B, c->wallB.data(), c->ni * 8, hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inflow, c->inflow.data(), c->ni, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inflow, c->inflow.data(), c->inflow.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ff, c->ff.data(), c->ff.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wbnd, c->wbnd.data(), c->wbnd.size() * sizeof(int2),
                                   hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wwall, c->wwall.data(), c->wwall.size() * sizeof(int2),
@@ -704,11 +807,14 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
     const int2 *wwall = reinterpret_cast<const int2 *>(c->ws + c->off_wwall);
     for (int which = 0; which < 4; ++which) {
         out_ms[which] = 0.0;
-        if (c->topo != FSI_TOPO_OGRID && (which == 1 || which == 2)) continue;
+        if (!c->has_wall && (which == 1 || which == 2)) continue;
         // one untimed launch, then `reps` timed ones
         for (int r = 0; r <= reps; ++r) {
             if (r == 1) HIP_TRY(c, hipEventRecord(e0, c->stream));
             hipError_t e = hipSuccess;
+            if (which == 0 && !c->wk0.empty())
+                HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
+                                                  (int)c->wk0.size(), stg, c->stream));
             if (which == 0) e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
             // phase 0 of the wall kernel (traction only) and of the body kernel
@@ -748,10 +854,10 @@ struct fsi_batch {
     hipStream_t stream = nullptr;
     int storage = 0;
     bool any_wall = false;
-    size_t off_insts = 0, off_wk1 = 0, off_wbnd = 0, off_wwall = 0, total = 0;
+    size_t off_insts = 0, off_wk0 = 0, off_wk1 = 0, off_wbnd = 0, off_wwall = 0, total = 0;
     std::vector<size_t> off_region;
     char *ws = nullptr;
-    std::vector<int2> wk1, wbnd, wwall;
+    std::vector<int2> wk0, wk1, wbnd, wwall;
     int grid = 0, order = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -787,6 +893,7 @@ void batch_lists(fsi_batch *b) {
         std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
             return b->ctx[a]->inst.n_nodes > b->ctx[c]->inst.n_nodes;
         });
+    b->wk0.clear();
     b->wk1.clear();
     b->wbnd.clear();
     b->wwall.clear();
@@ -794,18 +901,18 @@ void batch_lists(fsi_batch *b) {
         const Inst &P = b->ctx[k]->inst;
         for (int t = 0; t < P.tiles_i * P.tiles_j; ++t) b->wk1.push_back(make_int2(k, t));
     }
+    // the per-instance lists, re-labelled with the instance index
     for (int k = 0; k < n; ++k) {
-        if (b->ctx[k]->topo != FSI_TOPO_OGRID) continue;
-        const int nb = (b->ctx[k]->ni + 63) / 64;
-        for (int q = 0; q < nb; ++q) {
-            b->wbnd.push_back(make_int2(k, 2 * q));
-            b->wbnd.push_back(make_int2(k, 2 * q + 1));
-            b->wwall.push_back(make_int2(k, q));
-        }
+        for (int2 w : b->ctx[k]->wk0) b->wk0.push_back(make_int2(k, w.y));
+        for (int2 w : b->ctx[k]->wbnd) b->wbnd.push_back(make_int2(k, w.y));
+        for (int2 w : b->ctx[k]->wwall) b->wwall.push_back(make_int2(k, w.y));
     }
 }
 
 fsi_status batch_upload_lists(fsi_batch *b) {
+    if (!b->wk0.empty())
+        BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_wk0, b->wk0.data(), b->wk0.size() * sizeof(int2),
+                                   hipMemcpyHostToDevice, b->stream));
     BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_wk1, b->wk1.data(), b->wk1.size() * sizeof(int2),
                                hipMemcpyHostToDevice, b->stream));
     if (!b->wbnd.empty()) {
@@ -821,6 +928,9 @@ fsi_status batch_upload_lists(fsi_batch *b) {
 const Inst *b_insts(fsi_batch *b) { return reinterpret_cast<const Inst *>(b->ws + b->off_insts); }
 
 fsi_status batch_enqueue_k1(fsi_batch *b) {
+    if (!b->wk0.empty())
+        BHIP_TRY(b, fsi::launch_cut_export(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk0),
+                                           (int)b->wk0.size(), b->storage, b->stream));
     BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk1),
                                            (int)b->wk1.size(), b->storage, b->stream, b->grid));
     return FSI_OK;
@@ -883,12 +993,13 @@ fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mes
         b->ctx.push_back(c);
         if (k == 0) b->storage = c->fluid.storage;
         if (c->fluid.storage != b->storage) return bfail(b, FSI_E_ARG, "mixed storage precisions");
-        if (c->topo == FSI_TOPO_OGRID) b->any_wall = true;
+        if (c->has_wall) b->any_wall = true;
     }
     batch_lists(b);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
     b->off_insts = take(n * sizeof(Inst));
+    b->off_wk0 = take(b->wk0.size() * sizeof(int2));
     b->off_wk1 = take(b->wk1.size() * sizeof(int2));
     b->off_wbnd = take(b->wbnd.size() * sizeof(int2));
     b->off_wwall = take(b->wwall.size() * sizeof(int2));

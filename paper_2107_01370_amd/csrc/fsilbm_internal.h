@@ -48,10 +48,16 @@ struct BodySlot {
 // device memory; kernels read it through the scalar cache.
 struct Inst {
     int ni, nj;
-    int periodic_j;           // 1: PERIODIC2 topology, 0: O-grid (wall + far field)
+    int periodic_j;           // 1: PERIODIC2 topology, 0: O-grid or C-grid (wall + far field)
     int storage;              // 0 FP32, 1 FP16 shifted
     int tiles_i, tiles_j;     // tile grid of the fused kernel
     int tile_base;            // first work item of this instance in a batch
+    int cgrid;                // C-grid: i not periodic, row 0 outside the wall is the wake cut
+    int n_wake;               // C-grid: cut nodes on each side of the cut
+    int wall_i0, wall_n;      // wall nodes: row 0, columns [wall_i0, wall_i0 + wall_n)
+    int force_n;              // distinct wall nodes of the force polygon, from wall_i0
+    int n_ff;                 // far-field nodes
+    int cut_n;                // C-grid: columns whose row-1 state crosses the cut (2 (n_wake + 1))
     int pad0;
     long long n_nodes;
     double shift_ix, shift_iy, shift_jx, shift_jy;
@@ -68,7 +74,9 @@ struct Inst {
     uint16_t *wall_mask;      // [ni] bit k: population k missing at the wall node
     float4 *wall_tgt;         // [ni] (rho, ux, uy, T) targets
     const float2 *wall_B;     // [ni] index offsets of point B from the wall node
-    const uint8_t *inflow;    // [ni] far-field node is an inlet
+    const int2 *ff;           // [n_ff] far-field node index, interior node an outlet copies
+    const uint8_t *inflow;    // [n_ff] far-field node is an inlet
+    float *cutbuf;            // C-grid: [16][cut_n] post-collision moving populations of row 1
     double4 *wall_force;      // [ni] per-node (Fx, Fy, Mz, 0)
     BodySlot *slots;          // [3] body states at levels n % 3
     double *history;          // [HIST_CAP][6]
@@ -83,6 +91,8 @@ namespace fsi {
 // host-callable launchers (fsilbm_kernels.hip)
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
                                  hipStream_t s, int grid = 0);
+hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
+                             hipStream_t s);
 hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,
                                hipStream_t s);
 hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_work, int storage,

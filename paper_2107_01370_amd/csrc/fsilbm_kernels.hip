@@ -2,7 +2,8 @@
 // (Bhadauria, Dorschner & Karlin, arXiv 2107.01370).
 //
 //   k_collide_stream   fused collision (Sec. II.C) + ALE semi-Lagrangian
-//                      streaming (Sec. II.A-B) over 64 x 8 node tiles
+//                      streaming (Sec. II.A-B) over 32 x 16 node tiles
+//   k_cut_export       C-grid pre-pass: row-1 post-collision state of the cut
 //   k_wall_targets     Grad targets at the wall (Sec. III.A.1) and
 //                      far-field equilibria (Sec. III.A.2)
 //   k_wall_grad_force  Grad populations at the wall and per-node traction
@@ -305,23 +306,69 @@ struct K1Smem {
     } u;
 };
 
-// index-space derivative along j: centred inside, one-sided 3-point on the
-// physical end rows of an O-grid
-struct JStencil {
-    int o1, o2;              // row offsets of the two other nodes
-    float w1, w2;            // d/dj = w1 (C_o1 - C_0) + w2 (C_o2 - C_0) ...
+// index-space first derivative: centred, or one-sided 3-point on a wall row,
+// the far-field row and the exit columns of a C-grid
+struct Sten {
+    int o1, o2;              // offsets (in nodes along the index) of the two other nodes
+    float w1, w2;            // d = w1 (C_o1 - C_0) + w2 (C_o2 - C_0) ...
     bool centred;            // ... or (C_{+1} - C_{-1}) / 2
 };
 
-__device__ __forceinline__ JStencil jstencil(const Inst &P, int jg) {
-    JStencil s;
+__device__ __forceinline__ Sten centred_sten() {
+    Sten s;
     s.centred = true; s.o1 = 1; s.o2 = -1; s.w1 = 0.5f; s.w2 = -0.5f;
-    if (!P.periodic_j && jg == 0) {
-        s.centred = false; s.o1 = 1; s.o2 = 2; s.w1 = 2.0f; s.w2 = -0.5f;
-    } else if (!P.periodic_j && jg == P.nj - 1) {
-        s.centred = false; s.o1 = -1; s.o2 = -2; s.w1 = -2.0f; s.w2 = 0.5f;
-    }
     return s;
+}
+
+__device__ __forceinline__ Sten forward_sten(int dir) {
+    Sten s;
+    s.centred = false; s.o1 = dir; s.o2 = 2 * dir; s.w1 = 2.0f * (float)dir; s.w2 = -0.5f * (float)dir;
+    return s;
+}
+
+// wall column: the whole row 0 of an O-grid, the section's columns of a C-grid
+__device__ __forceinline__ bool wall_col(const Inst &P, int ig) {
+    return !P.cgrid || (ig >= P.wall_i0 && ig < P.wall_i0 + P.wall_n);
+}
+
+// along j at (unwrapped) node (ig, jg); C-grid rows below 0 are across the cut
+__device__ __forceinline__ Sten jstencil(const Inst &P, int ig, int jg) {
+    if (!P.periodic_j) {
+        if (jg == P.nj - 1) return forward_sten(-1);
+        if (jg == 0 && wall_col(P, ig)) return forward_sten(1);
+    }
+    return centred_sten();
+}
+
+__device__ __forceinline__ Sten istencil(const Inst &P, int ig) {
+    if (P.cgrid) {
+        if (ig == 0) return forward_sten(1);
+        if (ig == P.ni - 1) return forward_sten(-1);
+    }
+    return centred_sten();
+}
+
+// derivative of an LDS field at entry c with `stride` entries per index step
+__device__ __forceinline__ float dsten(const float *F, int c, int stride, const Sten &s) {
+    if (s.centred) return 0.5f * (F[c + stride] - F[c - stride]);
+    const float f0 = F[c];
+    return s.w1 * (F[c + s.o1 * stride] - f0) + s.w2 * (F[c + s.o2 * stride] - f0);
+}
+
+// does local (unwrapped) node (ig, jg) exist: periodic indices always, C-grid
+// rows below 0 through the mirror across the cut
+__device__ __forceinline__ bool node_exists(const Inst &P, int ig, int jg) {
+    if (P.periodic_j) return true;
+    if (P.cgrid) return ig >= 0 && ig < P.ni && jg < P.nj;
+    return jg >= 0 && jg < P.nj;
+}
+
+// C-grid: slot of column i in the row-1 export buffer (-1: not exported)
+__device__ __forceinline__ int cut_slot(const Inst &P, int i) {
+    if (i >= 0 && i <= P.n_wake) return i;
+    const int up = P.ni - 1 - P.n_wake;
+    if (i >= up && i < P.ni) return P.n_wake + 1 + (i - up);
+    return -1;
 }
 
 // position difference x_a - x_b of two R3 entries: FP64 for X, FP32 for the
@@ -338,11 +385,18 @@ __device__ __forceinline__ float2 pos_diff(const K1Smem &sm, int a, int b, bool 
 }
 
 // metric (x_xi, x_eta, y_xi, y_eta) at R3 entry c
-__device__ __forceinline__ void metric(const K1Smem &sm, int c, const JStencil &js, bool level1,
-                                       float J[4]) {
-    const float2 di = pos_diff(sm, c + 1, c - 1, level1);
-    J[0] = 0.5f * di.x;
-    J[2] = 0.5f * di.y;
+__device__ __forceinline__ void metric(const K1Smem &sm, int c, const Sten &is, const Sten &js,
+                                       bool level1, float J[4]) {
+    if (is.centred) {
+        const float2 di = pos_diff(sm, c + 1, c - 1, level1);
+        J[0] = 0.5f * di.x;
+        J[2] = 0.5f * di.y;
+    } else {
+        const float2 d1 = pos_diff(sm, c + is.o1, c, level1);
+        const float2 d2 = pos_diff(sm, c + is.o2, c, level1);
+        J[0] = is.w1 * d1.x + is.w2 * d2.x;
+        J[2] = is.w1 * d1.y + is.w2 * d2.y;
+    }
     if (js.centred) {
         const float2 dj = pos_diff(sm, c + R3X, c - R3X, level1);
         J[1] = 0.5f * dj.x;
@@ -377,8 +431,13 @@ __device__ __forceinline__ int phase1_entry(int p) {
     return row * R3X + col;
 }
 
-// one work item (instance, tile) of the fused kernel
-template <int STORE>
+// one work item (instance, tile) of the fused kernel.  EXPORT: the C-grid
+// pre-pass, which stops after the collision and writes the row-1 post-collision
+// populations of the cut columns to P.cutbuf (the tiles across the cut read
+// them as their row -1 instead of colliding there: a node below the cut seen
+// from the other side has different neighbours on row 0 next to the trailing
+// edge, so its collision cannot be formed in the mirrored frame).
+template <int STORE, bool EXPORT>
 __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__restrict__ insts,
                                                     const int2 item) {
     const Inst &P = insts[item.x];
@@ -418,16 +477,22 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         const int u = e % R3X, v = e / R3X;
         int ig = i0 - 3 + u, jg = j0 - 3 + v;
         // wrap into the mesh; a node seen across a periodic seam has its
-        // coordinates shifted by the period
+        // coordinates shifted by the period; on a C-grid node (i, -m) is node
+        // (ni - 1 - i, m) across the wake cut
         int wi = 0, wj = 0;
-        while (ig < 0) { ig += ni; --wi; }
-        while (ig >= ni) { ig -= ni; ++wi; }
         bool valid = true;
-        if (P.periodic_j) {
-            while (jg < 0) { jg += nj; --wj; }
-            while (jg >= nj) { jg -= nj; ++wj; }
+        if (P.cgrid) {
+            if (jg < 0) { ig = ni - 1 - ig; jg = -jg; }
+            valid = ig >= 0 && ig < ni && jg < nj;
         } else {
-            valid = (jg >= 0 && jg < nj);
+            while (ig < 0) { ig += ni; --wi; }
+            while (ig >= ni) { ig -= ni; ++wi; }
+            if (P.periodic_j) {
+                while (jg < 0) { jg += nj; --wj; }
+                while (jg >= nj) { jg -= nj; ++wj; }
+            } else {
+                valid = (jg >= 0 && jg < nj);
+            }
         }
         if (!valid) {
             sm.X[e] = 0.0; sm.Y[e] = 0.0;
@@ -485,30 +550,20 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
     // ---- phase 2: tile+2: D_a = (mu/p) d_{x_a} dQ_a --------------------------
     for (int e = t; e < R2N; e += K1_THREADS) {
         const int u2 = e % R2X, v2 = e / R2X;
-        int jg = j0 - 2 + v2;
-        if (P.periodic_j) {
-            while (jg < 0) jg += nj;
-            while (jg >= nj) jg -= nj;
-        } else if (jg < 0 || jg >= nj) {
+        const int ig = i0 - 2 + u2, jg = j0 - 2 + v2;
+        if (!node_exists(P, ig, jg)) {
             sm.D[e] = make_float2(0.0f, 0.0f);
             continue;
         }
-        const JStencil js = jstencil(P, jg);
+        const Sten js = jstencil(P, ig, jg), is = istencil(P, ig);
         const int c = (v2 + 1) * R3X + (u2 + 1);    // R3 index
         float J[4];
-        metric(sm, c, js, false, J);
+        metric(sm, c, is, js, false, J);
         const float idet = rcpf(J[0] * J[3] - J[2] * J[1]);
-        const float qx_xi = 0.5f * (sm.u.q.Qx[c + 1] - sm.u.q.Qx[c - 1]);
-        const float qy_xi = 0.5f * (sm.u.q.Qy[c + 1] - sm.u.q.Qy[c - 1]);
-        float qx_eta, qy_eta;
-        if (js.centred) {
-            qx_eta = 0.5f * (sm.u.q.Qx[c + R3X] - sm.u.q.Qx[c - R3X]);
-            qy_eta = 0.5f * (sm.u.q.Qy[c + R3X] - sm.u.q.Qy[c - R3X]);
-        } else {
-            const int c1 = c + js.o1 * R3X, c2 = c + js.o2 * R3X;
-            qx_eta = js.w1 * (sm.u.q.Qx[c1] - sm.u.q.Qx[c]) + js.w2 * (sm.u.q.Qx[c2] - sm.u.q.Qx[c]);
-            qy_eta = js.w1 * (sm.u.q.Qy[c1] - sm.u.q.Qy[c]) + js.w2 * (sm.u.q.Qy[c2] - sm.u.q.Qy[c]);
-        }
+        const float qx_xi = dsten(sm.u.q.Qx, c, 1, is);
+        const float qy_xi = dsten(sm.u.q.Qy, c, 1, is);
+        const float qx_eta = dsten(sm.u.q.Qx, c, R3X, js);
+        const float qy_eta = dsten(sm.u.q.Qy, c, R3X, js);
         const float s = sm.u.q.S[c] * idet;
         sm.D[e] = make_float2(s * (J[3] * qx_xi - J[2] * qx_eta), s * (-J[1] * qy_xi + J[0] * qy_eta));
     }
@@ -520,33 +575,37 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         const int e = rd * K1_THREADS + t;           // R1 index (= phase-1 item)
         if (e >= R1N) break;
         const int u1 = e % R1X, v1 = e / R1X;
-        int ig = i0 - 1 + u1, jg = j0 - 1 + v1;
-        while (ig < 0) ig += ni;
-        while (ig >= ni) ig -= ni;
-        if (P.periodic_j) {
-            while (jg < 0) jg += nj;
-            while (jg >= nj) jg -= nj;
-        } else if (jg < 0 || jg >= nj) {
+        const int ig = i0 - 1 + u1, jg = j0 - 1 + v1;
+        if (!node_exists(P, ig, jg)) continue;
+        if (P.cgrid && jg < 0) {
+            // row -1 across the wake cut: the exported row-1 state of the
+            // mirrored column (only cut columns and the trailing edge are
+            // ever interpolated from)
+            if constexpr (!EXPORT) {
+                const int slot = cut_slot(P, ni - 1 - ig);
+                if (slot >= 0) {
+#pragma unroll
+                    for (int k = 0; k < NMOV; ++k) sm.u.FG[k][e] = P.cutbuf[k * P.cut_n + slot];
+                }
+            }
             continue;
         }
-        const JStencil js = jstencil(P, jg);
+        const Sten js = jstencil(P, ig, jg), is = istencil(P, ig);
         float J[4];
-        metric(sm, (v1 + 2) * R3X + (u1 + 2), js, false, J);
+        metric(sm, (v1 + 2) * R3X + (u1 + 2), is, js, false, J);
         const float idet = rcpf(J[0] * J[3] - J[2] * J[1]);
         const int c = (v1 + 1) * R2X + (u1 + 1);     // R2 index
-        const float dx_xi = 0.5f * (sm.D[c + 1].x - sm.D[c - 1].x);
-        const float dy_xi = 0.5f * (sm.D[c + 1].y - sm.D[c - 1].y);
-        float dx_eta, dy_eta;
-        if (js.centred) {
-            dx_eta = 0.5f * (sm.D[c + R2X].x - sm.D[c - R2X].x);
-            dy_eta = 0.5f * (sm.D[c + R2X].y - sm.D[c - R2X].y);
-        } else {
-            const int c1 = c + js.o1 * R2X, c2 = c + js.o2 * R2X;
-            dx_eta = js.w1 * (sm.D[c1].x - sm.D[c].x) + js.w2 * (sm.D[c2].x - sm.D[c].x);
-            dy_eta = js.w1 * (sm.D[c1].y - sm.D[c].y) + js.w2 * (sm.D[c2].y - sm.D[c].y);
+        const float *Dx = &sm.D[0].x;                // interleaved (x, y): stride 2 floats
+        const float dx_xi = dsten(Dx, 2 * c, 2, is), dy_xi = dsten(Dx + 1, 2 * c, 2, is);
+        const float dx_eta = dsten(Dx, 2 * c, 2 * R2X, js), dy_eta = dsten(Dx + 1, 2 * c, 2 * R2X, js);
+        float Fx = idet * (J[3] * dx_xi - J[2] * dx_eta);
+        float Fy = idet * (-J[1] * dy_xi + J[0] * dy_eta);
+        // C-grid trailing edge (both copies): no correction, so that the two
+        // copies of the one node collide identically
+        if (P.cgrid && jg == 0 && (ig == P.wall_i0 || ig == P.wall_i0 + P.wall_n - 1)) {
+            Fx = 0.0f;
+            Fy = 0.0f;
         }
-        const float Fx = idet * (J[3] * dx_xi - J[2] * dx_eta);
-        const float Fy = idet * (-J[1] * dy_xi + J[0] * dy_eta);
         float f[9], g[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -559,14 +618,28 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
             sm.u.FG[k - 1][e] = f[k];
             sm.u.FG[7 + k][e] = g[k];
         }
-        // rest populations do not move: store them for the tile's own nodes
         const bool own = u1 >= 1 && u1 <= TILE_X && v1 >= 1 && v1 <= TILE_Y &&
                          i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
-        if (own) {
-            const long long idx = (long long)jg * ni + ig;
+        if constexpr (EXPORT) {
+            // row-1 state of the cut columns for the tiles across the cut
+            const int slot = cut_slot(P, ig);
+            if (own && jg == 1 && slot >= 0) {
+#pragma unroll
+                for (int k = 1; k < 9; ++k) {
+                    P.cutbuf[(k - 1) * P.cut_n + slot] = f[k];
+                    P.cutbuf[(7 + k) * P.cut_n + slot] = g[k];
+                }
+            }
+        } else if (own) {
+            // rest populations do not move: store them for the tile's own nodes
+            const long long idx = (long long)jg * ni + wrap(ig, ni);
             pop_st<STORE>(P, dst, 0, idx, f[0]);
             pop_st<STORE>(P, dst, Q, idx, g[0]);
         }
+    }
+    if constexpr (EXPORT) {
+        if (err) atomicOr(P.err, err);
+        return;
     }
     __syncthreads();
 
@@ -577,13 +650,15 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         const int ut = e % TILE_X, vt = e / TILE_X;
         const int ig = i0 + ut, jg = j0 + vt;
         if (ig >= ni || jg >= nj) continue;
-        if (!P.periodic_j && jg == nj - 1) continue;   // far-field row: boundary kernel
+        // far-field row and C-grid exit columns: boundary kernel
+        if (!P.periodic_j && jg == nj - 1) continue;
+        if (P.cgrid && (ig == 0 || ig == ni - 1)) continue;
         const int c3 = (vt + 3) * R3X + (ut + 3);
-        const bool wall = (!P.periodic_j && jg == 0);
-        const JStencil js = jstencil(P, jg);
+        const bool wall = !P.periodic_j && jg == 0 && wall_col(P, ig);
+        const Sten js = jstencil(P, ig, jg);
         // metric of the mesh at t^{n+1} and its inverse
         float J[4];
-        metric(sm, c3, js, true, J);
+        metric(sm, c3, centred_sten(), js, true, J);
         const float det = J[0] * J[3] - J[2] * J[1];
         if (!(det > 0.0f)) err |= ERR_MESH;
         const float idet = rcpf(det);
@@ -703,9 +778,18 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
     for (int li = blockIdx.x / 8; li < per_xcd; li += nloc) {
         const int wk = xcd * per_xcd + li;
         if (wk >= n_work) break;
-        collide_stream_tile<STORE>(sm, insts, work[wk]);
+        collide_stream_tile<STORE, false>(sm, insts, work[wk]);
         __syncthreads();                      // LDS is reused by the next item
     }
+}
+
+// C-grid pre-pass: one workgroup per tile of row block 0 that holds cut columns
+template <int STORE>
+__global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
+k_cut_export(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
+    __shared__ K1Smem sm;
+    if ((int)blockIdx.x >= n_work) return;
+    collide_stream_tile<STORE, true>(sm, insts, work[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -746,7 +830,8 @@ __device__ __forceinline__ void node_pos(const Inst &P, long long idx, const Bod
 }
 
 // Wall targets (Grad BC, Sec. III.A.1) for item.y even, far-field
-// equilibria (Sec. III.A.2) for item.y odd.
+// equilibria (Sec. III.A.2) for item.y odd; item.y >> 1 is the block of 64
+// wall nodes (from column wall_i0) or of 64 far-field list entries.
 //   rho_t, T_t : values at B (distance dt along the wall normal), 9-node
 //                Lagrange element centred on row 1; the wall row of the
 //                element holds the previous step's values
@@ -758,12 +843,13 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
     if ((int)blockIdx.x >= n_work) return;
     const int2 item = work[blockIdx.x];
     const Inst &P = insts[item.x];
-    const int kind = item.y & 1, i0 = (item.y >> 1) * BND;
+    const int kind = item.y & 1, blk = item.y >> 1;
     const long long n = *P.step;
     const void *src = P.pop[n & 1];
     void *dst = P.pop[(n + 1) & 1];
-    const int ni = P.ni, nj = P.nj, t = threadIdx.x;
+    const int ni = P.ni, t = threadIdx.x;
     if (kind == 0) {
+        const int i0 = P.wall_i0 + blk * BND;
         for (int e = t; e < 3 * (BND + 2); e += BND) {
             const int r = e / (BND + 2), c = e % (BND + 2);
             const int ig = wrap(i0 - 1 + c, ni);
@@ -775,7 +861,7 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
         }
         __syncthreads();
         const int ig = i0 + t;
-        if (ig >= ni) return;
+        if (ig >= P.wall_i0 + P.wall_n) return;
         const float2 B = P.wall_B[ig];
         const float a = B.x, b = B.y - 1.0f;   // offsets from the element centre (i, 1)
         float rho_t = 0.0f, T_t = 0.0f;
@@ -799,33 +885,133 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
         }
         P.wall_tgt[ig] = make_float4(rho_t, VGx, VGy, T_t);
     } else {
-        const int ig = i0 + t;
-        if (ig >= ni) return;
+        const int k = blk * BND + t;
+        if (k >= P.n_ff) return;
+        const int2 node = P.ff[k];             // (far-field node, interior node)
         float rho, ux, uy, T;
-        if (P.inflow[ig]) {
+        if (P.inflow[k]) {
             rho = P.rho_inf; ux = P.ux_inf; uy = P.uy_inf; T = P.T_inf;
         } else {  // outlet: zero gradient, copy the adjacent interior node
             float f[9], g[9];
-            load_node<STORE>(P, dst, (long long)(nj - 2) * ni + ig, f, g);
+            load_node<STORE>(P, dst, node.y, f, g);
             const Moments m = moments(f, g, P.Cv);
             rho = m.rho; ux = m.ux; uy = m.uy; T = m.T;
         }
         const float E = P.Cv * T + 0.5f * (ux * ux + uy * uy);
         float feq[9], geq[9];
         equilibria<float>(rho, ux, uy, T, E, feq, geq);
-        const long long idx = (long long)(nj - 1) * ni + ig;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            pop_store<STORE>(P, dst, k, idx, feq[k]);
-            pop_store<STORE>(P, dst, Q + k, idx, geq[k]);
+        for (int q = 0; q < 9; ++q) {
+            pop_store<STORE>(P, dst, q, node.x, feq[q]);
+            pop_store<STORE>(P, dst, Q + q, node.x, geq[q]);
         }
     }
 }
 
+// Tangential neighbour values (ux, uy, T) for the wall-gradient stencil: the
+// neighbour's target if it is a wall node, else (a C-grid cut node next to the
+// trailing edge) its freshly streamed state.
+template <int STORE>
+__device__ __forceinline__ float4 wall_neighbour(const Inst &P, const void *buf, int i) {
+    if (wall_col(P, i)) return P.wall_tgt[i];
+    float f[9], g[9];
+    load_node<STORE>(P, buf, i, f, g);
+    const Moments m = moments(f, g, P.Cv);
+    return make_float4(m.rho, m.ux, m.uy, m.T);
+}
+
+// Grad populations (Sec. III.A.1) for the missing populations of wall node ig
+// of the level in `buf`: f, g enter as loaded and leave with the missing ones
+// replaced (unrounded).
+template <int STORE>
+__device__ void grad_fill(const Inst &P, const void *buf, const BodySlot &sL, int ig, float f[9],
+                          float g[9]) {
+    const uint16_t miss = P.wall_mask[ig];
+    if (!miss) return;
+    const int ni = P.ni;
+    const int im = P.cgrid ? ig - 1 : wrap(ig - 1, ni), ip = P.cgrid ? ig + 1 : wrap(ig + 1, ni);
+    double xm, ym, xp, yp, x0, y0;
+    node_pos(P, im, sL, xm, ym);
+    node_pos(P, ip, sL, xp, yp);
+    node_pos(P, ig, sL, x0, y0);
+    const float Cv = P.Cv, Cp = P.Cp, dt = P.dt;
+    const float4 tm = wall_neighbour<STORE>(P, buf, im), t0 = P.wall_tgt[ig];
+    const float4 tp = wall_neighbour<STORE>(P, buf, ip);
+    float f1[9], g1[9], f2[9], g2[9];
+    load_node<STORE>(P, buf, (long long)ni + ig, f1, g1);
+    load_node<STORE>(P, buf, 2LL * ni + ig, f2, g2);
+    const Moments m1 = moments(f1, g1, Cv), m2 = moments(f2, g2, Cv);
+    // metric of the mesh at t^{n+1} at the wall node: centred along the
+    // wall, one-sided into the fluid
+    double x1, y1, x2, y2;
+    node_pos(P, (long long)ni + ig, sL, x1, y1);
+    node_pos(P, 2LL * ni + ig, sL, x2, y2);
+    const float x_xi = (float)(0.5 * (xp - xm)), y_xi = (float)(0.5 * (yp - ym));
+    const float x_eta = (float)(2.0 * (x1 - x0) - 0.5 * (x2 - x0));
+    const float y_eta = (float)(2.0 * (y1 - y0) - 0.5 * (y2 - y0));
+    const float idet = 1.0f / (x_xi * y_eta - y_xi * x_eta);
+    const float rho_t = t0.x, ux_t = t0.y, uy_t = t0.z, T_t = t0.w;
+    const float E_t = Cv * T_t + 0.5f * (ux_t * ux_t + uy_t * uy_t);
+    const float Em = Cv * tm.w + 0.5f * (tm.y * tm.y + tm.z * tm.z);
+    const float Ep = Cv * tp.w + 0.5f * (tp.y * tp.y + tp.z * tp.z);
+    const float E1 = Cv * m1.T + 0.5f * (m1.ux * m1.ux + m1.uy * m1.uy);
+    const float E2 = Cv * m2.T + 0.5f * (m2.ux * m2.ux + m2.uy * m2.uy);
+    // (C_xi, C_eta) -> (dC/dx, dC/dy)
+    auto grad = [&](float cm, float c0, float cp, float c1, float c2, float &gx, float &gy) {
+        const float cxi = 0.5f * (cp - cm);
+        const float ceta = -1.5f * c0 + 2.0f * c1 - 0.5f * c2;
+        gx = idet * (y_eta * cxi - y_xi * ceta);
+        gy = idet * (-x_eta * cxi + x_xi * ceta);
+    };
+    float duxx, duxy, duyx, duyy, dTx, dTy, dEx, dEy;
+    grad(tm.y, ux_t, tp.y, m1.ux, m2.ux, duxx, duxy);
+    grad(tm.z, uy_t, tp.z, m1.uy, m2.uy, duyx, duyy);
+    grad(tm.w, T_t, tp.w, m1.T, m2.T, dTx, dTy);
+    grad(Em, E_t, Ep, E1, E2, dEx, dEy);
+    const float aa = P.mu / (rho_t * T_t * dt);
+    const float omega = 1.0f / (aa + 0.5f);
+    const float omega1 = 1.0f / (aa / P.Pr + 0.5f);
+    // S = grad u + grad u^T, (grad u)_ab = d_a u_b
+    const float Sxx = 2.0f * duxx, Syy = 2.0f * duyy, Sxy = duxy + duyx;
+    const float div = duxx + duyy;
+    const float pref = -rho_t * T_t / omega;
+    const float P1xx = pref * (Sxx - div / Cv);
+    const float P1yy = pref * (Syy - div / Cv);
+    const float P1xy = pref * Sxy;
+    const float q1x = -(2.0f / omega1) * rho_t * Cp * T_t * dTx + 2.0f * (ux_t * P1xx + uy_t * P1xy);
+    const float q1y = -(2.0f / omega1) * rho_t * Cp * T_t * dTy + 2.0f * (ux_t * P1xy + uy_t * P1yy);
+    const float rpref = -(2.0f / omega1) * rho_t * T_t;
+    const float e2 = E_t + 2.0f * T_t;
+    const float R1xx = rpref * (Sxx * e2 + 2.0f * ux_t * dEx);
+    const float R1yy = rpref * (Syy * e2 + 2.0f * uy_t * dEy);
+    const float R1xy = rpref * (Sxy * e2 + ux_t * dEy + uy_t * dEx);
+    float feq[9], geq[9];
+    equilibria<float>(rho_t, ux_t, uy_t, T_t, E_t, feq, geq);
+    const float w[3] = {0.5f * T_t, 1.0f - T_t, 0.5f * T_t};
+    const float invT = 1.0f / T_t, inv2T2 = 0.5f * invT * invT;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        if (!(miss & (1u << k))) continue;
+        const int cx = CXK(k), cy = CYK(k);
+        const float W = w[cx + 1] * w[cy + 1];
+        const float ccx = (float)(cx * cx) - T_t, ccy = (float)(cy * cy) - T_t;
+        const float cxy = 2.0f * (float)(cx * cy);
+        const float fneq = W * (P1xx * ccx + P1yy * ccy + P1xy * cxy) * inv2T2;
+        const float gneq = W * ((q1x * (float)cx + q1y * (float)cy) * invT +
+                                (R1xx * ccx + R1yy * ccy + R1xy * cxy) * inv2T2);
+        f[k] = feq[k] + dt * fneq;
+        g[k] = geq[k] + dt * gneq;
+    }
+}
+
 // Grad populations for the missing wall populations (phase 1 only) and the
-// traction F_k = sigma . (n ds)_k of every wall node at the current level
-// (Sec. III: sigma = -p I - (1 - omega/2) P^(1), P^(1) = sum (f - f^eq) c c;
-// (n ds)_k = 1/2 rot_{+90}(x_{k+1} - x_{k-1})).
+// traction F_k = sigma . (n ds)_k of every node of the wall polygon at the
+// current level (Sec. III: sigma = -p I - (1 - omega/2) P^(1),
+// P^(1) = sum (f - f^eq) c c; (n ds)_k = 1/2 rot_{+90}(x_{k+1} - x_{k-1}) with
+// k +- 1 the polygon neighbours).  C-grid: the thread of the lower
+// trailing-edge copy also fills the upper copy and stores one merged state in
+// both: population by population the streamed value of the copy that found its
+// departure point, else the mean of the two copies.
 template <int STORE>
 __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict__ insts,
                                                          const int2 *__restrict__ work, int n_work,
@@ -833,97 +1019,60 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
     if ((int)blockIdx.x >= n_work) return;
     const int2 item = work[blockIdx.x];
     const Inst &P = insts[item.x];
-    const int ni = P.ni;
-    const int ig = item.y * BND + threadIdx.x;
-    if (ig >= ni) return;
+    const int ig = P.wall_i0 + item.y * BND + threadIdx.x;
+    if (ig >= P.wall_i0 + P.wall_n) return;
+    const int te_up = P.wall_i0 + P.wall_n - 1;
+    if (P.cgrid && ig == te_up) return;       // handled with the lower copy
     const long long n = *P.step;
     const long long L = phase ? n + 1 : n;
     void *buf = P.pop[L & 1];
     const BodySlot sL = P.slots[L % 3];
-    const int im = wrap(ig - 1, ni), ip = wrap(ig + 1, ni);
-    double xm, ym, xp, yp, x0, y0;
-    node_pos(P, im, sL, xm, ym);
-    node_pos(P, ip, sL, xp, yp);
-    node_pos(P, ig, sL, x0, y0);
     float f[9], g[9];
     load_node<STORE>(P, buf, ig, f, g);
-    const float Cv = P.Cv, Cp = P.Cp, dt = P.dt;
     if (phase) {
-        const uint16_t miss = P.wall_mask[ig];
-        if (miss) {
-            const float4 tm = P.wall_tgt[im], t0 = P.wall_tgt[ig], tp = P.wall_tgt[ip];
-            float f1[9], g1[9], f2[9], g2[9];
-            load_node<STORE>(P, buf, (long long)ni + ig, f1, g1);
-            load_node<STORE>(P, buf, 2LL * ni + ig, f2, g2);
-            const Moments m1 = moments(f1, g1, Cv), m2 = moments(f2, g2, Cv);
-            // metric of the mesh at t^{n+1} at the wall node: centred along the
-            // wall, one-sided into the fluid
-            double x1, y1, x2, y2;
-            node_pos(P, (long long)ni + ig, sL, x1, y1);
-            node_pos(P, 2LL * ni + ig, sL, x2, y2);
-            const float x_xi = (float)(0.5 * (xp - xm)), y_xi = (float)(0.5 * (yp - ym));
-            const float x_eta = (float)(2.0 * (x1 - x0) - 0.5 * (x2 - x0));
-            const float y_eta = (float)(2.0 * (y1 - y0) - 0.5 * (y2 - y0));
-            const float idet = 1.0f / (x_xi * y_eta - y_xi * x_eta);
-            const float rho_t = t0.x, ux_t = t0.y, uy_t = t0.z, T_t = t0.w;
-            const float E_t = Cv * T_t + 0.5f * (ux_t * ux_t + uy_t * uy_t);
-            const float Em = Cv * tm.w + 0.5f * (tm.y * tm.y + tm.z * tm.z);
-            const float Ep = Cv * tp.w + 0.5f * (tp.y * tp.y + tp.z * tp.z);
-            const float E1 = Cv * m1.T + 0.5f * (m1.ux * m1.ux + m1.uy * m1.uy);
-            const float E2 = Cv * m2.T + 0.5f * (m2.ux * m2.ux + m2.uy * m2.uy);
-            // (C_xi, C_eta) -> (dC/dx, dC/dy)
-            auto grad = [&](float cm, float c0, float cp, float c1, float c2, float &gx, float &gy) {
-                const float cxi = 0.5f * (cp - cm);
-                const float ceta = -1.5f * c0 + 2.0f * c1 - 0.5f * c2;
-                gx = idet * (y_eta * cxi - y_xi * ceta);
-                gy = idet * (-x_eta * cxi + x_xi * ceta);
-            };
-            float duxx, duxy, duyx, duyy, dTx, dTy, dEx, dEy;
-            grad(tm.y, ux_t, tp.y, m1.ux, m2.ux, duxx, duxy);
-            grad(tm.z, uy_t, tp.z, m1.uy, m2.uy, duyx, duyy);
-            grad(tm.w, T_t, tp.w, m1.T, m2.T, dTx, dTy);
-            grad(Em, E_t, Ep, E1, E2, dEx, dEy);
-            const float aa = P.mu / (rho_t * T_t * dt);
-            const float omega = 1.0f / (aa + 0.5f);
-            const float omega1 = 1.0f / (aa / P.Pr + 0.5f);
-            // S = grad u + grad u^T, (grad u)_ab = d_a u_b
-            const float Sxx = 2.0f * duxx, Syy = 2.0f * duyy, Sxy = duxy + duyx;
-            const float div = duxx + duyy;
-            const float pref = -rho_t * T_t / omega;
-            const float P1xx = pref * (Sxx - div / Cv);
-            const float P1yy = pref * (Syy - div / Cv);
-            const float P1xy = pref * Sxy;
-            const float q1x = -(2.0f / omega1) * rho_t * Cp * T_t * dTx + 2.0f * (ux_t * P1xx + uy_t * P1xy);
-            const float q1y = -(2.0f / omega1) * rho_t * Cp * T_t * dTy + 2.0f * (ux_t * P1xy + uy_t * P1yy);
-            const float rpref = -(2.0f / omega1) * rho_t * T_t;
-            const float e2 = E_t + 2.0f * T_t;
-            const float R1xx = rpref * (Sxx * e2 + 2.0f * ux_t * dEx);
-            const float R1yy = rpref * (Syy * e2 + 2.0f * uy_t * dEy);
-            const float R1xy = rpref * (Sxy * e2 + ux_t * dEy + uy_t * dEx);
-            float feq[9], geq[9];
-            equilibria<float>(rho_t, ux_t, uy_t, T_t, E_t, feq, geq);
-            const float w[3] = {0.5f * T_t, 1.0f - T_t, 0.5f * T_t};
-            const float invT = 1.0f / T_t, inv2T2 = 0.5f * invT * invT;
+        grad_fill<STORE>(P, buf, sL, ig, f, g);
+        if (P.cgrid && ig == P.wall_i0) {
+            float fu[9], gu[9];
+            load_node<STORE>(P, buf, te_up, fu, gu);
+            grad_fill<STORE>(P, buf, sL, te_up, fu, gu);
+            const unsigned ml = P.wall_mask[ig], mu = P.wall_mask[te_up];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const bool lo_miss = ml & (1u << k), up_miss = mu & (1u << k);
+                f[k] = (lo_miss && !up_miss) ? fu[k] : ((up_miss && !lo_miss) ? f[k] : 0.5f * (f[k] + fu[k]));
+                g[k] = (lo_miss && !up_miss) ? gu[k] : ((up_miss && !lo_miss) ? g[k] : 0.5f * (g[k] + gu[k]));
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                pop_store<STORE>(P, buf, k, ig, f[k]);
+                pop_store<STORE>(P, buf, Q + k, ig, g[k]);
+                pop_store<STORE>(P, buf, k, te_up, f[k]);
+                pop_store<STORE>(P, buf, Q + k, te_up, g[k]);
+                f[k] = pop_round<STORE>(P, k, f[k]);
+                g[k] = pop_round<STORE>(P, Q + k, g[k]);
+            }
+        } else if (P.wall_mask[ig]) {
+            const unsigned miss = P.wall_mask[ig];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 if (!(miss & (1u << k))) continue;
-                const int cx = CXK(k), cy = CYK(k);
-                const float W = w[cx + 1] * w[cy + 1];
-                const float ccx = (float)(cx * cx) - T_t, ccy = (float)(cy * cy) - T_t;
-                const float cxy = 2.0f * (float)(cx * cy);
-                const float fneq = W * (P1xx * ccx + P1yy * ccy + P1xy * cxy) * inv2T2;
-                const float gneq = W * ((q1x * (float)cx + q1y * (float)cy) * invT +
-                                        (R1xx * ccx + R1yy * ccy + R1xy * cxy) * inv2T2);
-                pop_store<STORE>(P, buf, k, ig, feq[k] + dt * fneq);
-                pop_store<STORE>(P, buf, Q + k, ig, geq[k] + dt * gneq);
+                pop_store<STORE>(P, buf, k, ig, f[k]);
+                pop_store<STORE>(P, buf, Q + k, ig, g[k]);
                 // the traction below sees the populations as stored
-                f[k] = pop_round<STORE>(P, k, feq[k] + dt * fneq);
-                g[k] = pop_round<STORE>(P, Q + k, geq[k] + dt * gneq);
+                f[k] = pop_round<STORE>(P, k, f[k]);
+                g[k] = pop_round<STORE>(P, Q + k, g[k]);
             }
         }
     }
     // traction of the complete wall node, with the moments formed in FP64
-    // from the stored populations
+    // from the stored populations; normals from the polygon neighbours
+    const int fm = ig == P.wall_i0 ? P.wall_i0 + P.force_n - 1 : ig - 1;
+    const int fp = ig == P.wall_i0 + P.force_n - 1 ? P.wall_i0 : ig + 1;
+    double xm, ym, xp, yp, x0, y0;
+    node_pos(P, fm, sL, xm, ym);
+    node_pos(P, fp, sL, xp, yp);
+    node_pos(P, ig, sL, x0, y0);
+    const float Cv = P.Cv;
     double fd[9], gd[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -1022,11 +1171,25 @@ __global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ 
     const long long L = phase ? n + 1 : n;
     double fx = 0.0, fy = 0.0, mz = 0.0;
     if (!P.periodic_j) {
-        for (int i = t; i < P.ni; i += BODY_THREADS) {
-            const double4 v = P.wall_force[i];
+        for (int i = t; i < P.force_n; i += BODY_THREADS) {
+            const double4 v = P.wall_force[P.wall_i0 + i];
             fx += v.x;
             fy += v.y;
             mz += v.z;
+        }
+    }
+    if (phase && P.cgrid) {
+        // one state per cut point: the upper copy of each cut node takes the
+        // lower copy's populations (the trailing edge is merged at the wall)
+        void *buf = P.pop[(n + 1) & 1];
+        const size_t bpp = P.storage ? 2 : 4;
+        for (int e = t; e < NPOP * P.n_wake; e += BODY_THREADS) {
+            const int q = e / P.n_wake, i = e % P.n_wake;
+            char *base = static_cast<char *>(buf) + (size_t)q * P.n_nodes * bpp;
+            if (bpp == 4)
+                reinterpret_cast<float *>(base)[P.ni - 1 - i] = reinterpret_cast<const float *>(base)[i];
+            else
+                reinterpret_cast<uint16_t *>(base)[P.ni - 1 - i] = reinterpret_cast<const uint16_t *>(base)[i];
         }
     }
     sx[t] = fx; sy[t] = fy; sz[t] = mz;
@@ -1137,6 +1300,12 @@ hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work
     if (g > all) g = all;
     if (g < 8) g = 8;
     FSI_DISPATCH(storage, k_collide_stream, dim3(g), dim3(K1_THREADS), s, insts, work, n_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
+                             hipStream_t s) {
+    FSI_DISPATCH(storage, k_cut_export, dim3(n_work), dim3(K1_THREADS), s, insts, work, n_work);
     return hipGetLastError();
 }
 

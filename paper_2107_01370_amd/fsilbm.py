@@ -49,7 +49,7 @@ class FluidParams(ctypes.Structure):
 class MeshDesc(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("topo", ctypes.c_int),
                 ("X", ctypes.POINTER(ctypes.c_double)), ("shift_i", ctypes.c_double * 2),
-                ("shift_j", ctypes.c_double * 2)]
+                ("shift_j", ctypes.c_double * 2), ("n_wake", ctypes.c_int)]
 
 
 class BodyDesc(ctypes.Structure):
@@ -159,7 +159,8 @@ def _mesh_struct(mesh):
     """Returns (MeshDesc, coordinate array that must outlive the call)."""
     X = np.ascontiguousarray(mesh.interleaved(), dtype=np.float64)
     md = MeshDesc(mesh.ni, mesh.nj, mesh.topo, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                  (ctypes.c_double * 2)(*mesh.shift_i), (ctypes.c_double * 2)(*mesh.shift_j))
+                  (ctypes.c_double * 2)(*mesh.shift_i), (ctypes.c_double * 2)(*mesh.shift_j),
+                  int(getattr(mesh, "n_wake", 0)))
     return md, X
 
 

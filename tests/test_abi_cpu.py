@@ -198,3 +198,29 @@ def test_batch_schedule_arguments_are_checked(F):
             assert e.value.status == -1
     finally:
         F.fsi_batch_destroy(b)
+
+
+# ---- C-grid --------------------------------------------------------------------
+
+def test_cgrid_airfoil_is_accepted(F):
+    c = synth.small_airfoil_case()
+    ctx = F.fsi_create(c.fluid, c.mesh, c.bodies, None)
+    F.fsi_destroy(ctx)
+    big = synth.airfoil_flutter_case()
+    ctx = F.fsi_create(big.fluid, big.mesh, big.bodies, None)
+    F.fsi_destroy(ctx)
+
+
+def test_cgrid_with_unmatched_cut_is_rejected(F):
+    c = synth.small_airfoil_case()
+    m = c.mesh
+    X = m.X.copy()
+    X[0, m.ni - 3] += 1e-3                     # cut node no longer coincides with its twin
+    bad = synth.configs.replace(m, X=X)
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(c.fluid, bad, c.bodies, None)
+    assert e.value.status == -2 and "coincide" in str(e.value)
+    short = synth.configs.replace(m, n_wake=1)
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(c.fluid, short, c.bodies, None)
+    assert e.value.status == -2

@@ -56,7 +56,7 @@ def test_acoustic_pulse_100_steps_rho_p():
 
 
 def test_ragged_tiles_moving_blended_mesh():
-    """Mesh sizes that are not multiples of the 64 x 8 tile, strong sine
+    """Mesh sizes that are not multiples of the 32 x 16 tile, strong sine
     deformation, and a blended region moving with a prescribed heave + pitch."""
     mesh = synth.periodic_sine_mesh(amp=0.3, ni=72, nj=42)
     fluid = synth.FluidParams(gamma=1.4, Pr=0.71, mu=0.02, rho_inf=1.0, T_inf=0.25,
