@@ -401,7 +401,8 @@ fsi_status enqueue_step(fsi_ctx *c) {
         HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
     HIP_TRY(c, fsi::launch_collide_stream(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
-                                          (int)c->wk1.size(), st, c->stream));
+                                          (int)c->wk1.size(), st, c->stream, 0,
+                                          c->topo == FSI_TOPO_CGRID));
     if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
@@ -471,8 +472,9 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
         return fail(c, FSI_E_ARG, "fluid parameters out of range");
     if (fluid->storage != FSI_STORE_FP32 && fluid->storage != FSI_STORE_FP16_SHIFTED)
         return fail(c, FSI_E_ARG, "unknown storage mode");
-    if ((long long)c->ni * c->nj > (1LL << 31) / fsi::NPOP)
-        return fail(c, FSI_E_ARG, "mesh too large for 32-bit population offsets");
+    if ((long long)c->ni * c->nj * fsi::NPOP * 4 >= (1LL << 31))
+        return fail(c, FSI_E_ARG, "mesh too large: the kernels address each population array "
+                                  "with 32-bit offsets (18 * 4 * ni * nj < 2^31, ~29.8M nodes)");
     for (int k = 0; k < 2; ++k) {
         c->shift_i[k] = mesh->shift_i[k];
         c->shift_j[k] = mesh->shift_j[k];
@@ -815,7 +817,9 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
             if (which == 0 && !c->wk0.empty())
                 HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                                   (int)c->wk0.size(), stg, c->stream));
-            if (which == 0) e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream);
+            if (which == 0)
+                e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
+                                               c->topo == FSI_TOPO_CGRID);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
             // phase 0 of the wall kernel (traction only) and of the body kernel
             // recompute the current level without advancing it
@@ -932,7 +936,8 @@ fsi_status batch_enqueue_k1(fsi_batch *b) {
         BHIP_TRY(b, fsi::launch_cut_export(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk0),
                                            (int)b->wk0.size(), b->storage, b->stream));
     BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk1),
-                                           (int)b->wk1.size(), b->storage, b->stream, b->grid));
+                                           (int)b->wk1.size(), b->storage, b->stream, b->grid,
+                                           !b->wk0.empty()));
     return FSI_OK;
 }
 

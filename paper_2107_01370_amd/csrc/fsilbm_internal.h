@@ -90,7 +90,7 @@ struct Inst {
 namespace fsi {
 // host-callable launchers (fsilbm_kernels.hip)
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid = 0);
+                                 hipStream_t s, int grid, bool cgrid);
 hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
                              hipStream_t s);
 hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,

@@ -167,23 +167,74 @@ __device__ __forceinline__ double2 gld(const double2 *p) {
     return make_double2(q[0], q[1]);
 }
 
+// Values every lane of a wave shares, moved into scalar registers.  Loads from
+// device memory that kernels also write (the step counter, the body states,
+// the work list) come back per lane; declaring them uniform lets addresses
+// built from them stay scalar.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform(long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffLL));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double uniform(double v) {
+    return __longlong_as_double(uniform((long long)__double_as_longlong(v)));
+}
+__device__ __forceinline__ BodySlot uniform(const BodySlot &a) {
+    BodySlot b;
+    b.h = uniform(a.h); b.a = uniform(a.a); b.hd = uniform(a.hd); b.ad = uniform(a.ad);
+    b.cm1 = uniform(a.cm1); b.sa = uniform(a.sa); b.pad0 = 0.0; b.pad1 = 0.0;
+    return b;
+}
+
+// Hot-path accessors through a buffer resource: one descriptor per population
+// array (wave-uniform, scalar registers), the plane of population q as the
+// scalar offset q * nodes * bytes and the node as a 32-bit vector offset, so
+// every load / store is a single instruction with no per-lane address
+// arithmetic.  The descriptor bounds the access to the array (an offset
+// outside reads 0, a store outside is dropped).  Needs 18 * nodes * 4 < 2^31
+// (checked at creation).
+constexpr int kBufDword3 = 0x00020000;   // gfx9 descriptor word 3: 32-bit data format
+
+struct PopBuf {
+    __amdgpu_buffer_rsrc_t r;
+    int plane;                            // bytes per population plane
+};
+
 template <int STORE>
-__device__ __forceinline__ float pop_ld(const Inst &P, const void *base, int q, long long idx) {
+__device__ __forceinline__ PopBuf pop_buf(const Inst &P, const void *base) {
+    constexpr int B = STORE == 0 ? 4 : 2;
+    PopBuf b;
+    b.plane = (int)P.n_nodes * B;
+    b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, NPOP * b.plane,
+                                            kBufDword3);
+    return b;
+}
+
+// byte offset of node idx inside a plane
+template <int STORE>
+__device__ __forceinline__ int pop_off(int idx) {
+    return idx * (STORE == 0 ? 4 : 2);
+}
+
+template <int STORE>
+__device__ __forceinline__ float pop_ld(const Inst &P, const PopBuf &b, int q, int off) {
     if constexpr (STORE == 0) {
-        return gld(static_cast<const float *>(base) + q * P.n_nodes + idx);
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, off, q * b.plane, 0));
     } else {
-        const unsigned short h = *(gcushort *)(static_cast<const unsigned short *>(base) + q * P.n_nodes + idx);
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(b.r, off, q * b.plane, 0);
         return P.ref[q] + P.scale[q >= Q] * __half2float(__ushort_as_half(h));
     }
 }
 
 template <int STORE>
-__device__ __forceinline__ void pop_st(const Inst &P, void *base, int q, long long idx, float v) {
+__device__ __forceinline__ void pop_st(const Inst &P, const PopBuf &b, int q, int off, float v) {
     if constexpr (STORE == 0) {
-        *(gfloat *)(static_cast<float *>(base) + q * P.n_nodes + idx) = v;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), b.r, off, q * b.plane, 0);
     } else {
-        *(gushort *)(static_cast<unsigned short *>(base) + q * P.n_nodes + idx) =
+        const unsigned short h =
             __half_as_ushort(__float2half_rn((v - P.ref[q]) * P.inv_scale[q >= Q]));
+        __builtin_amdgcn_raw_buffer_store_b16(h, b.r, off, q * b.plane, 0);
     }
 }
 
@@ -326,22 +377,25 @@ __device__ __forceinline__ Sten forward_sten(int dir) {
     return s;
 }
 
-// wall column: the whole row 0 of an O-grid, the section's columns of a C-grid
-__device__ __forceinline__ bool wall_col(const Inst &P, int ig) {
-    return !P.cgrid || (ig >= P.wall_i0 && ig < P.wall_i0 + P.wall_n);
+// wall column: the whole row 0 of an O-grid, the section's columns of a C-grid.
+// `cg` (C-grid) is a compile-time false in the kernels built without C-grid
+// support, which folds every C-grid branch away.
+__device__ __forceinline__ bool wall_col(const Inst &P, int ig, bool cg) {
+    return !cg || (ig >= P.wall_i0 && ig < P.wall_i0 + P.wall_n);
 }
+__device__ __forceinline__ bool wall_col(const Inst &P, int ig) { return wall_col(P, ig, P.cgrid); }
 
 // along j at (unwrapped) node (ig, jg); C-grid rows below 0 are across the cut
-__device__ __forceinline__ Sten jstencil(const Inst &P, int ig, int jg) {
+__device__ __forceinline__ Sten jstencil(const Inst &P, int ig, int jg, bool cg) {
     if (!P.periodic_j) {
         if (jg == P.nj - 1) return forward_sten(-1);
-        if (jg == 0 && wall_col(P, ig)) return forward_sten(1);
+        if (jg == 0 && wall_col(P, ig, cg)) return forward_sten(1);
     }
     return centred_sten();
 }
 
-__device__ __forceinline__ Sten istencil(const Inst &P, int ig) {
-    if (P.cgrid) {
+__device__ __forceinline__ Sten istencil(const Inst &P, int ig, bool cg) {
+    if (cg) {
         if (ig == 0) return forward_sten(1);
         if (ig == P.ni - 1) return forward_sten(-1);
     }
@@ -357,9 +411,9 @@ __device__ __forceinline__ float dsten(const float *F, int c, int stride, const 
 
 // does local (unwrapped) node (ig, jg) exist: periodic indices always, C-grid
 // rows below 0 through the mirror across the cut
-__device__ __forceinline__ bool node_exists(const Inst &P, int ig, int jg) {
+__device__ __forceinline__ bool node_exists(const Inst &P, int ig, int jg, bool cg) {
     if (P.periodic_j) return true;
-    if (P.cgrid) return ig >= 0 && ig < P.ni && jg < P.nj;
+    if (cg) return ig >= 0 && ig < P.ni && jg < P.nj;
     return jg >= 0 && jg < P.nj;
 }
 
@@ -437,19 +491,20 @@ __device__ __forceinline__ int phase1_entry(int p) {
 // them as their row -1 instead of colliding there: a node below the cut seen
 // from the other side has different neighbours on row 0 next to the trailing
 // edge, so its collision cannot be formed in the mirrored frame).
-template <int STORE, bool EXPORT>
+template <int STORE, bool EXPORT, bool CG>
 __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__restrict__ insts,
                                                     const int2 item) {
     const Inst &P = insts[item.x];
+    const bool cg = CG && P.cgrid;
     const int tile = item.y;
     const int ti = tile % P.tiles_i, tj = tile / P.tiles_i;
     const int i0 = ti * TILE_X, j0 = tj * TILE_Y;
     const int ni = P.ni, nj = P.nj;
-    const long long n = *P.step;
-    const void *src = P.pop[n & 1];
-    void *dst = P.pop[(n + 1) & 1];
-    const BodySlot sn = P.slots[n % 3];
-    const BodySlot sn1 = P.slots[(n + 1) % 3];
+    const long long n = uniform(*P.step);
+    const PopBuf src = pop_buf<STORE>(P, P.pop[n & 1]);
+    const PopBuf dst = pop_buf<STORE>(P, P.pop[(n + 1) & 1]);
+    const BodySlot sn = uniform(P.slots[n % 3]);
+    const BodySlot sn1 = uniform(P.slots[(n + 1) % 3]);
     const Body &body = P.body;
     const int t = threadIdx.x;
     unsigned err = 0;
@@ -481,7 +536,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         // (ni - 1 - i, m) across the wake cut
         int wi = 0, wj = 0;
         bool valid = true;
-        if (P.cgrid) {
+        if (cg) {
             if (jg < 0) { ig = ni - 1 - ig; jg = -jg; }
             valid = ig >= 0 && ig < ni && jg < nj;
         } else {
@@ -500,7 +555,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
             sm.u.q.Qx[e] = 0.0f; sm.u.q.Qy[e] = 0.0f; sm.u.q.S[e] = 0.0f;
             continue;
         }
-        const long long idx = (long long)jg * ni + ig;
+        const int idx = jg * ni + ig;
         const double2 Xr = gld(P.X + idx);
         float2 dn = make_float2((float)(-Drx), (float)(-Dry)), dd = make_float2(0.0f, 0.0f);
         if (body.present) {
@@ -520,10 +575,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         sm.dn[e] = dn;
         sm.dd[e] = dd;
         float f[9], g[9];
+        const int off = pop_off<STORE>(idx);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_ld<STORE>(P, src, k, idx);
-            g[k] = pop_ld<STORE>(P, src, Q + k, idx);
+            f[k] = pop_ld<STORE>(P, src, k, off);
+            g[k] = pop_ld<STORE>(P, src, Q + k, off);
         }
         if (rd < R1_ROUNDS && p < R1N) {
 #pragma unroll
@@ -551,11 +607,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
     for (int e = t; e < R2N; e += K1_THREADS) {
         const int u2 = e % R2X, v2 = e / R2X;
         const int ig = i0 - 2 + u2, jg = j0 - 2 + v2;
-        if (!node_exists(P, ig, jg)) {
+        if (!node_exists(P, ig, jg, cg)) {
             sm.D[e] = make_float2(0.0f, 0.0f);
             continue;
         }
-        const Sten js = jstencil(P, ig, jg), is = istencil(P, ig);
+        const Sten js = jstencil(P, ig, jg, cg), is = istencil(P, ig, cg);
         const int c = (v2 + 1) * R3X + (u2 + 1);    // R3 index
         float J[4];
         metric(sm, c, is, js, false, J);
@@ -576,8 +632,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         if (e >= R1N) break;
         const int u1 = e % R1X, v1 = e / R1X;
         const int ig = i0 - 1 + u1, jg = j0 - 1 + v1;
-        if (!node_exists(P, ig, jg)) continue;
-        if (P.cgrid && jg < 0) {
+        if (!node_exists(P, ig, jg, cg)) continue;
+        if (cg && jg < 0) {
             // row -1 across the wake cut: the exported row-1 state of the
             // mirrored column (only cut columns and the trailing edge are
             // ever interpolated from)
@@ -590,7 +646,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
             }
             continue;
         }
-        const Sten js = jstencil(P, ig, jg), is = istencil(P, ig);
+        const Sten js = jstencil(P, ig, jg, cg), is = istencil(P, ig, cg);
         float J[4];
         metric(sm, (v1 + 2) * R3X + (u1 + 2), is, js, false, J);
         const float idet = rcpf(J[0] * J[3] - J[2] * J[1]);
@@ -602,7 +658,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         float Fy = idet * (-J[1] * dy_xi + J[0] * dy_eta);
         // C-grid trailing edge (both copies): no correction, so that the two
         // copies of the one node collide identically
-        if (P.cgrid && jg == 0 && (ig == P.wall_i0 || ig == P.wall_i0 + P.wall_n - 1)) {
+        if (cg && jg == 0 && (ig == P.wall_i0 || ig == P.wall_i0 + P.wall_n - 1)) {
             Fx = 0.0f;
             Fy = 0.0f;
         }
@@ -632,9 +688,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
             }
         } else if (own) {
             // rest populations do not move: store them for the tile's own nodes
-            const long long idx = (long long)jg * ni + wrap(ig, ni);
-            pop_st<STORE>(P, dst, 0, idx, f[0]);
-            pop_st<STORE>(P, dst, Q, idx, g[0]);
+            const int off = pop_off<STORE>(jg * ni + wrap(ig, ni));
+            pop_st<STORE>(P, dst, 0, off, f[0]);
+            pop_st<STORE>(P, dst, Q, off, g[0]);
         }
     }
     if constexpr (EXPORT) {
@@ -652,10 +708,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         if (ig >= ni || jg >= nj) continue;
         // far-field row and C-grid exit columns: boundary kernel
         if (!P.periodic_j && jg == nj - 1) continue;
-        if (P.cgrid && (ig == 0 || ig == ni - 1)) continue;
+        if (cg && (ig == 0 || ig == ni - 1)) continue;
         const int c3 = (vt + 3) * R3X + (ut + 3);
-        const bool wall = !P.periodic_j && jg == 0 && wall_col(P, ig);
-        const Sten js = jstencil(P, ig, jg);
+        const bool wall = !P.periodic_j && jg == 0 && wall_col(P, ig, cg);
+        const Sten js = jstencil(P, ig, jg, cg);
         // metric of the mesh at t^{n+1} and its inverse
         float J[4];
         metric(sm, c3, centred_sten(), js, true, J);
@@ -697,7 +753,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         const float P0x = BXxi * B0x + BXeta * B0y, P0y = BYxi * B0x + BYeta * B0y;
         const int vc = wall ? 1 : 0;                   // stencil centre row offset
         const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
-        const long long idx = (long long)jg * ni + ig;
+        const int off = pop_off<STORE>(jg * ni + ig);
         uint16_t miss = 0;
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
@@ -757,15 +813,15 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
                 }
                 outv[h] = row[1] + wbm * (row[0] - row[1]) + wbp * (row[2] - row[1]);
             }
-            pop_st<STORE>(P, dst, k, idx, outv[0]);
-            pop_st<STORE>(P, dst, Q + k, idx, outv[1]);
+            pop_st<STORE>(P, dst, k, off, outv[0]);
+            pop_st<STORE>(P, dst, Q + k, off, outv[1]);
         }
         if (wall) P.wall_mask[ig] = miss;
     }
     if (err) atomicOr(P.err, err);
 }
 
-template <int STORE>
+template <int STORE, bool CG>
 __global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
 k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
     __shared__ K1Smem sm;
@@ -778,7 +834,8 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
     for (int li = blockIdx.x / 8; li < per_xcd; li += nloc) {
         const int wk = xcd * per_xcd + li;
         if (wk >= n_work) break;
-        collide_stream_tile<STORE, false>(sm, insts, work[wk]);
+        const int2 w = work[wk];
+        collide_stream_tile<STORE, false, CG>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
         __syncthreads();                      // LDS is reused by the next item
     }
 }
@@ -789,7 +846,8 @@ __global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
 k_cut_export(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
     __shared__ K1Smem sm;
     if ((int)blockIdx.x >= n_work) return;
-    collide_stream_tile<STORE, true>(sm, insts, work[blockIdx.x]);
+    const int2 w = work[blockIdx.x];
+    collide_stream_tile<STORE, true, true>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
 }
 
 // ---------------------------------------------------------------------------
@@ -1292,14 +1350,22 @@ __global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const
     } while (0)
 
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid) {
+                                 hipStream_t s, int grid, bool cgrid) {
     // one workgroup per item unless a smaller (persistent) grid is requested;
     // always a multiple of the XCD count
     const int all = ((n_work + 7) / 8) * 8;
     int g = grid > 0 ? ((grid + 7) / 8) * 8 : all;
     if (g > all) g = all;
     if (g < 8) g = 8;
-    FSI_DISPATCH(storage, k_collide_stream, dim3(g), dim3(K1_THREADS), s, insts, work, n_work);
+    // the C-grid-capable build only when some instance of the launch needs it
+    const dim3 G(g), B(K1_THREADS);
+    if (storage == 0) {
+        if (cgrid) hipLaunchKernelGGL((k_collide_stream<0, true>), G, B, 0, s, insts, work, n_work);
+        else hipLaunchKernelGGL((k_collide_stream<0, false>), G, B, 0, s, insts, work, n_work);
+    } else {
+        if (cgrid) hipLaunchKernelGGL((k_collide_stream<1, true>), G, B, 0, s, insts, work, n_work);
+        else hipLaunchKernelGGL((k_collide_stream<1, false>), G, B, 0, s, insts, work, n_work);
+    }
     return hipGetLastError();
 }
 
