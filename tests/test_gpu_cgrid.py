@@ -8,7 +8,6 @@ disagree for a step.  The multi-step cases are therefore ones whose wall
 departure points stay at least MARGIN cells from the wall line, which the
 tests check on the oracle side."""
 
-import contextlib
 from dataclasses import replace
 
 import numpy as np
@@ -20,29 +19,6 @@ from oracle.solver import OracleSolver
 pytestmark = pytest.mark.gpu
 
 MARGIN = 5e-5          # >> the kernel's FP32 decision band (1e-5) and rounding (~1e-6)
-
-
-@contextlib.contextmanager
-def wall_margin():
-    """Record the smallest |b| (index-space distance from the wall line) of
-    the wall nodes' departure points found above the wall, over the steps the
-    oracle runs inside the block."""
-    import oracle.stream as S
-    orig = S.departure_offsets
-    seen = [np.inf]
-
-    def spy(grid, X, Y, chx, chy, dt, wall_row=False):
-        a, b, m = orig(grid, X, Y, chx, chy, dt, wall_row)
-        wall = (grid.jj == 0) & grid.wall_col[None, :] & ~np.isnan(b)
-        if np.any(wall):
-            seen[0] = min(seen[0], float(np.min(np.abs(b[wall]))))
-        return a, b, m
-
-    S.departure_offsets = spy
-    try:
-        yield seen
-    finally:
-        S.departure_offsets = orig
 
 
 def paired(c, fluid=None):
@@ -72,7 +48,7 @@ def test_cgrid_one_step_population_parity():
     assert np.array_equal(g[:, 0, lo], g[:, 0, ni - 1 - lo])
 
 
-def test_cgrid_pitch_plunge_60_steps():
+def test_cgrid_pitch_plunge_60_steps(wall_margin):
     c = synth.small_airfoil_case(alpha0_deg=0.5)
     sim, ora = paired(c)
     n = 60
@@ -107,7 +83,7 @@ def test_cgrid_fp16_storage_within_2e3():
     assert np.max(np.abs(rho * T - r_o * T_o) / (r_o * T_o)) <= 2e-3
 
 
-def test_airfoil_768x256_transonic_parity():
+def test_airfoil_768x256_transonic_parity(wall_margin):
     """The 768 x 256 C-grid at Ma 0.85, T 0.2, Re 1e5 with the 2DOF section:
     a few steps of the full-size case against the oracle.
 
