@@ -217,13 +217,22 @@ __device__ __forceinline__ int pop_off(int idx) {
     return idx * (STORE == 0 ? 4 : 2);
 }
 
+// raw stored bits of population q (FP32 bits, or the FP16 code zero-extended)
 template <int STORE>
-__device__ __forceinline__ float pop_ld(const Inst &P, const PopBuf &b, int q, int off) {
+__device__ __forceinline__ unsigned pop_ld_raw(const PopBuf &b, int q, int off) {
     if constexpr (STORE == 0) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, off, q * b.plane, 0));
+        return __builtin_amdgcn_raw_buffer_load_b32(b.r, off, q * b.plane, 0);
     } else {
-        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(b.r, off, q * b.plane, 0);
-        return P.ref[q] + P.scale[q >= Q] * __half2float(__ushort_as_half(h));
+        return __builtin_amdgcn_raw_buffer_load_b16(b.r, off, q * b.plane, 0);
+    }
+}
+
+template <int STORE>
+__device__ __forceinline__ float pop_decode(const Inst &P, int q, unsigned raw) {
+    if constexpr (STORE == 0) {
+        return __uint_as_float(raw);
+    } else {
+        return P.ref[q] + P.scale[q >= Q] * __half2float(__ushort_as_half((unsigned short)raw));
     }
 }
 
@@ -331,12 +340,14 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
 //   phase 4 (tile)  : departure points on x^{n+1}, 3x3 Lagrange
 //                     interpolation from LDS, store f^{n+1}, g^{n+1}
 //
-// Geometry in LDS: undeformed coordinates X (FP64, with periodic shifts) and,
-// in FP32, the blended displacement at t^n relative to an FP64 reference
-// displacement of the tile (dn) and its increment over the step (dd).  All
-// coordinate differences are formed in FP64 (X) and FP32 (small relative
-// displacements), so metrics keep FP32 relative accuracy on meshes with large
-// absolute coordinates and displacements.
+// Geometry in LDS, all FP32 and relative to FP64 references of the tile (its
+// first node's undeformed position and blended displacement at t^n): the
+// undeformed coordinates X - X_ref (with periodic shifts), the displacement at
+// t^n minus D_ref (dn) and the increment over the step (dd), each formed in
+// FP64 and rounded once.  Coordinate differences inside a tile are then single
+// FP32 subtractions whose rounding is ~1e-7 of the tile's extent (a few 1e-6
+// of a cell), on meshes with large absolute coordinates and displacements;
+// integer grids stay exact.
 // ---------------------------------------------------------------------------
 constexpr int R3X = TILE_X + 6, R3Y = TILE_Y + 6, R3N = R3X * R3Y;
 constexpr int R2X = TILE_X + 4, R2Y = TILE_Y + 4, R2N = R2X * R2Y;
@@ -344,8 +355,7 @@ constexpr int R1X = TILE_X + 2, R1Y = TILE_Y + 2, R1N = R1X * R1Y;
 constexpr int NMOV = 16;     // moving populations kept in LDS (f_1..8, g_1..8)
 
 struct K1Smem {
-    double X[R3N];
-    double Y[R3N];
+    float2 Xu[R3N];          // X - X_ref (undeformed, periodic shifts applied)
     float2 dn[R3N];          // (1 - r) d^n(X) - D_ref^n
     float2 dd[R3N];          // (1 - r)(d^{n+1}(X) - d^n(X))
     float2 D[R2N];           // nested correction, first level
@@ -429,8 +439,8 @@ __device__ __forceinline__ int cut_slot(const Inst &P, int i) {
 // relative displacement; `level1` adds the step increment (mesh at t^{n+1})
 __device__ __forceinline__ float2 pos_diff(const K1Smem &sm, int a, int b, bool level1) {
     float2 d;
-    d.x = (float)(sm.X[a] - sm.X[b]) + (sm.dn[a].x - sm.dn[b].x);
-    d.y = (float)(sm.Y[a] - sm.Y[b]) + (sm.dn[a].y - sm.dn[b].y);
+    d.x = (sm.Xu[a].x - sm.Xu[b].x) + (sm.dn[a].x - sm.dn[b].x);
+    d.y = (sm.Xu[a].y - sm.Xu[b].y) + (sm.dn[a].y - sm.dn[b].y);
     if (level1) {
         d.x += sm.dd[a].x - sm.dd[b].x;
         d.y += sm.dd[a].y - sm.dd[b].y;
@@ -509,13 +519,14 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
     const int t = threadIdx.x;
     unsigned err = 0;
 
-    // FP64 reference displacement of the tile: that of its first node
+    // FP64 references of the tile: position and displacement of its first node
+    const double2 Xref = P.X[(long long)min(j0, nj - 1) * ni + i0];
+    const double Xrx = uniform(Xref.x), Xry = uniform(Xref.y);
     double Drx = 0.0, Dry = 0.0;
     if (body.present) {
-        const double2 Xr = P.X[(long long)min(j0, nj - 1) * ni + i0];
-        const double r = blend_factor(body, Xr.x, Xr.y);
+        const double r = blend_factor(body, Xrx, Xry);
         double dx, dy;
-        rigid_disp(body, sn, Xr.x, Xr.y, dx, dy);
+        rigid_disp(body, sn, Xrx, Xry, dx, dy);
         Drx = (1.0 - r) * dx;
         Dry = (1.0 - r) * dy;
     }
@@ -550,7 +561,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
             }
         }
         if (!valid) {
-            sm.X[e] = 0.0; sm.Y[e] = 0.0;
+            sm.Xu[e] = make_float2(0.0f, 0.0f);
             sm.dn[e] = make_float2(0.0f, 0.0f); sm.dd[e] = make_float2(0.0f, 0.0f);
             sm.u.q.Qx[e] = 0.0f; sm.u.q.Qy[e] = 0.0f; sm.u.q.S[e] = 0.0f;
             continue;
@@ -570,16 +581,20 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
                 dd = make_float2((float)(om * (d1x - d0x)), (float)(om * (d1y - d0y)));
             }
         }
-        sm.X[e] = Xr.x + (double)wi * P.shift_ix + (double)wj * P.shift_jx;
-        sm.Y[e] = Xr.y + (double)wi * P.shift_iy + (double)wj * P.shift_jy;
+        sm.Xu[e] = make_float2((float)(Xr.x - Xrx + ((double)wi * P.shift_ix + (double)wj * P.shift_jx)),
+                               (float)(Xr.y - Xry + ((double)wi * P.shift_iy + (double)wj * P.shift_jy)));
         sm.dn[e] = dn;
         sm.dd[e] = dd;
         float f[9], g[9];
         const int off = pop_off<STORE>(idx);
+        // all 18 loads in flight before the first use
+        unsigned raw[NPOP];
+#pragma unroll
+        for (int q = 0; q < NPOP; ++q) raw[q] = pop_ld_raw<STORE>(src, q, off);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_ld<STORE>(P, src, k, off);
-            g[k] = pop_ld<STORE>(P, src, Q + k, off);
+            f[k] = pop_decode<STORE>(P, k, raw[k]);
+            g[k] = pop_decode<STORE>(P, Q + k, raw[Q + k]);
         }
         if (rd < R1_ROUNDS && p < R1N) {
 #pragma unroll
@@ -720,22 +735,22 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
         const float idet = rcpf(det);
         // undeformed neighbourhood relative to the node: R[dj+1][di+1]
         float RX[3][3], RY[3][3];
-        const double Xc = sm.X[c3], Yc = sm.Y[c3];
+        const float2 Xc = sm.Xu[c3];
 #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
             for (int di = -1; di <= 1; ++di) {
                 const int ee = c3 + dj * R3X + di;
-                RX[dj + 1][di + 1] = (float)(sm.X[ee] - Xc);
-                RY[dj + 1][di + 1] = (float)(sm.Y[ee] - Yc);
+                RX[dj + 1][di + 1] = sm.Xu[ee].x - Xc.x;
+                RY[dj + 1][di + 1] = sm.Xu[ee].y - Xc.y;
             }
         // centred metric of X (one-sided into the fluid on the wall row)
         const float BXxi = 0.5f * (RX[1][2] - RX[1][0]), BYxi = 0.5f * (RY[1][2] - RY[1][0]);
         float BXeta, BYeta;
         if (wall) {
             const int e2 = c3 + 2 * R3X;
-            BXeta = 2.0f * RX[2][1] - 0.5f * (float)(sm.X[e2] - Xc);
-            BYeta = 2.0f * RY[2][1] - 0.5f * (float)(sm.Y[e2] - Yc);
+            BXeta = 2.0f * RX[2][1] - 0.5f * (sm.Xu[e2].x - Xc.x);
+            BYeta = 2.0f * RY[2][1] - 0.5f * (sm.Xu[e2].y - Xc.y);
         } else {
             BXeta = 0.5f * (RX[2][1] - RX[0][1]);
             BYeta = 0.5f * (RY[2][1] - RY[0][1]);
