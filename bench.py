@@ -124,7 +124,7 @@ def time_batch(cases, steps: int, warmup: int, kernel_reps: int = 10):
         b.init_equilibrium(k, c.rho, c.ux, c.uy, c.T)
     b.step(warmup)
     b.synchronize()
-    grid, order, _ = b.autotune(reps=5)
+    grid, order, shape, _ = b.autotune(reps=5)
     b.step(2)                                  # capture the tuned graph
     b.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -138,7 +138,7 @@ def time_batch(cases, steps: int, warmup: int, kernel_reps: int = 10):
     kms = b.time_kernels(kernel_reps)
     finite = all(bool(np.all(np.isfinite(b.macro(k)[0]))) for k in range(len(cases)))
     b.close()
-    return total_ms, kms, (grid, order), finite
+    return total_ms, kms, (grid, order, shape), finite
 
 
 def time_sequential(cases, steps: int, warmup: int):
@@ -301,7 +301,7 @@ def main():
             "steps": bsteps,
             "batched_MLUPS": round(nb * bsteps / (tb * 1e-3) / 1e6, 1),
             "batched_ms_per_step": round(tb / bsteps, 5),
-            "schedule": {"grid": sched[0], "order": sched[1]},
+            "schedule": {"grid": sched[0], "order": sched[1], "tile_shape": sched[2]},
             "collide_stream_ms": round(float(kb[0]), 5),
             "achieved_GBs": round(bpn * nb / (float(kb[0]) * 1e-3) / 1e9, 1),
             "one_at_a_time_MLUPS": round(nb * bsteps / (ts * 1e-3) / 1e6, 1),
@@ -340,7 +340,7 @@ def main_batched(args, storage: int):
                         f"population storage",
             "nodes": N,
             "storage": args.storage,
-            "schedule": {"grid": sched[0], "order": sched[1]},
+            "schedule": {"grid": sched[0], "order": sched[1], "tile_shape": sched[2]},
             "kernel_ms": {"collide_stream": round(k1_ms, 5),
                           "wall_targets_farfield": round(float(kms[1]), 5),
                           "wall_grad_traction": round(float(kms[2]), 5),

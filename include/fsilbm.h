@@ -217,15 +217,18 @@ fsi_status fsi_batch_bind_workspace(fsi_batch *b, void *dev_ptr, size_t bytes);
 fsi_status fsi_batch_init_equilibrium(fsi_batch *b, int k, const double *rho, const double *ux,
                                       const double *uy, const double *T);
 /* Work distribution of the collision-streaming launch: `grid` workgroups (0 =
- * one per work item; otherwise a persistent grid, rounded to a multiple of 8)
- * and `order` of the work items (0: instance after instance, 1: instances by
- * decreasing size).  Invalidates the captured graph. */
-fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order);
-/* Time candidate schedules on the current state and keep the fastest: for
- * each (grid, order) candidate, `reps` launches of the collision-streaming
- * kernel (each recomputes the same values, so the state is unchanged);
- * best[3] = {grid, order, mean ms per launch}.  Synchronises. */
-fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[3]);
+ * one per work item; otherwise a persistent grid, rounded to a multiple of 8),
+ * `order` of the work items (0: instance after instance, 1: instances by
+ * decreasing size) and the tile `shape` of the arrival nodes one workgroup owns
+ * (0: 32 x 16, 1: 64 x 8, 2: 16 x 32; a batch holding a C-grid instance uses
+ * 0).  Invalidates the captured graph.  FSI_E_ARG on values out of range. */
+fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape);
+/* Time candidate schedules on the current state and keep the fastest: after
+ * warm-up launches, each (shape, order, grid) candidate is timed twice over
+ * `reps` launches of the collision-streaming kernel (each recomputes the same
+ * values, so the state is unchanged) and its faster pass counts;
+ * best[4] = {grid, order, shape, mean ms per launch}.  Synchronises. */
+fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]);
 fsi_status fsi_batch_step(fsi_batch *b, int nsteps);
 fsi_status fsi_batch_synchronize(fsi_batch *b);
 /* Per-instance queries, as the single-instance calls. */

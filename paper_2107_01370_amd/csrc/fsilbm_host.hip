@@ -402,7 +402,7 @@ fsi_status enqueue_step(fsi_ctx *c) {
                                           (int)c->wk0.size(), st, c->stream));
     HIP_TRY(c, fsi::launch_collide_stream(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
                                           (int)c->wk1.size(), st, c->stream, 0,
-                                          c->topo == FSI_TOPO_CGRID));
+                                          c->topo == FSI_TOPO_CGRID, 0));
     if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
@@ -819,7 +819,7 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                                                   (int)c->wk0.size(), stg, c->stream));
             if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
-                                               c->topo == FSI_TOPO_CGRID);
+                                               c->topo == FSI_TOPO_CGRID, 0);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
             // phase 0 of the wall kernel (traction only) and of the body kernel
             // recompute the current level without advancing it
@@ -862,7 +862,8 @@ struct fsi_batch {
     std::vector<size_t> off_region;
     char *ws = nullptr;
     std::vector<int2> wk0, wk1, wbnd, wwall;
-    int grid = 0, order = 0;
+    int grid = 0, order = 0, shape = 0;
+    bool any_cgrid = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::string err;
@@ -901,9 +902,11 @@ void batch_lists(fsi_batch *b) {
     b->wk1.clear();
     b->wbnd.clear();
     b->wwall.clear();
+    const int tx = fsi::TILE_SHAPES[b->shape][0], ty = fsi::TILE_SHAPES[b->shape][1];
     for (int k : ord) {
-        const Inst &P = b->ctx[k]->inst;
-        for (int t = 0; t < P.tiles_i * P.tiles_j; ++t) b->wk1.push_back(make_int2(k, t));
+        const fsi_ctx *c = b->ctx[k];
+        const int ntiles = ((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
+        for (int t = 0; t < ntiles; ++t) b->wk1.push_back(make_int2(k, t));
     }
     // the per-instance lists, re-labelled with the instance index
     for (int k = 0; k < n; ++k) {
@@ -937,7 +940,7 @@ fsi_status batch_enqueue_k1(fsi_batch *b) {
                                            (int)b->wk0.size(), b->storage, b->stream));
     BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk1),
                                            (int)b->wk1.size(), b->storage, b->stream, b->grid,
-                                           !b->wk0.empty()));
+                                           !b->wk0.empty(), b->shape));
     return FSI_OK;
 }
 
@@ -999,13 +1002,21 @@ fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mes
         if (k == 0) b->storage = c->fluid.storage;
         if (c->fluid.storage != b->storage) return bfail(b, FSI_E_ARG, "mixed storage precisions");
         if (c->has_wall) b->any_wall = true;
+        if (c->topo == FSI_TOPO_CGRID) b->any_cgrid = true;
     }
     batch_lists(b);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
     b->off_insts = take(n * sizeof(Inst));
     b->off_wk0 = take(b->wk0.size() * sizeof(int2));
-    b->off_wk1 = take(b->wk1.size() * sizeof(int2));
+    size_t max_items = 0;                 // the largest work list over the tile shapes
+    for (int sh = 0; sh < fsi::N_TILE_SHAPES; ++sh) {
+        size_t items = 0;
+        const int tx = fsi::TILE_SHAPES[sh][0], ty = fsi::TILE_SHAPES[sh][1];
+        for (fsi_ctx *c : b->ctx) items += (size_t)((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
+        max_items = std::max(max_items, items);
+    }
+    b->off_wk1 = take(max_items * sizeof(int2));
     b->off_wbnd = take(b->wbnd.size() * sizeof(int2));
     b->off_wwall = take(b->wwall.size() * sizeof(int2));
     for (fsi_ctx *c : b->ctx) b->off_region.push_back(take(c->total));
@@ -1044,13 +1055,17 @@ fsi_status fsi_batch_init_equilibrium(fsi_batch *b, int k, const double *rho, co
     return bfwd(b, k, fsi_init_equilibrium(b->ctx[k], rho, ux, uy, T));
 }
 
-fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order) {
+fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape) {
     if (!b) return FSI_E_ARG;
-    if (grid < 0 || (order != 0 && order != 1)) return bfail(b, FSI_E_ARG, "bad schedule");
+    if (grid < 0 || (order != 0 && order != 1) || shape < 0 || shape >= fsi::N_TILE_SHAPES)
+        return bfail(b, FSI_E_ARG, "bad schedule");
+    if (shape != 0 && b->any_cgrid)
+        return bfail(b, FSI_E_ARG, "a batch with C-grid instances uses tile shape 0");
     batch_drop_graph(b);
     b->grid = grid;
-    if (order != b->order) {
+    if (order != b->order || shape != b->shape) {
         b->order = order;
+        b->shape = shape;
         batch_lists(b);
         if (b->ws) return batch_upload_lists(b);
     }
@@ -1160,7 +1175,7 @@ fsi_status fsi_batch_time_kernels(fsi_batch *b, int reps, double out_ms[4]) {
     return fsi_batch_synchronize(b);
 }
 
-fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[3]) {
+fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]) {
     fsi_status st = batch_ready(b, -1);
     if (st != FSI_OK) return st;
     if (reps < 1 || !best) return bfail(b, FSI_E_ARG, "reps must be >= 1");
@@ -1168,26 +1183,40 @@ fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[3]) {
     // multiples of the resident capacity (256 CUs x 2 tiles)
     const int grids[] = {0, 4096, 2048, 1024, 512};
     double best_ms = 1e30;
-    int best_grid = 0, best_order = 0;
-    for (int order = 0; order <= 1; ++order) {
-        for (int grid : grids) {
-            st = fsi_batch_set_schedule(b, grid, order);
-            if (st != FSI_OK) return st;
-            double ms[4];
-            st = fsi_batch_time_kernels(b, reps, ms);
-            if (st != FSI_OK) return st;
-            if (ms[0] < best_ms) {
-                best_ms = ms[0];
-                best_grid = grid;
-                best_order = order;
+    int best_grid = 0, best_order = 0, best_shape = 0;
+    const int n_shapes = b->any_cgrid ? 1 : fsi::N_TILE_SHAPES;
+    // warm-up launches first (clocks ramp up over the first milliseconds),
+    // then each candidate timed twice and its faster pass kept
+    {
+        double ms[4];
+        st = fsi_batch_time_kernels(b, 4 * reps + 8, ms);
+        if (st != FSI_OK) return st;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int shape = 0; shape < n_shapes; ++shape) {
+            for (int order = 0; order <= 1; ++order) {
+                for (int grid : grids) {
+                    st = fsi_batch_set_schedule(b, grid, order, shape);
+                    if (st != FSI_OK) return st;
+                    double ms[4];
+                    st = fsi_batch_time_kernels(b, reps, ms);
+                    if (st != FSI_OK) return st;
+                    if (ms[0] < best_ms) {
+                        best_ms = ms[0];
+                        best_grid = grid;
+                        best_order = order;
+                        best_shape = shape;
+                    }
+                }
             }
         }
     }
-    st = fsi_batch_set_schedule(b, best_grid, best_order);
+    st = fsi_batch_set_schedule(b, best_grid, best_order, best_shape);
     if (st != FSI_OK) return st;
     best[0] = best_grid;
     best[1] = best_order;
-    best[2] = best_ms;
+    best[2] = best_shape;
+    best[3] = best_ms;
     return FSI_OK;
 }
 

@@ -10,8 +10,12 @@ namespace fsi {
 
 constexpr int Q = 9;
 constexpr int NPOP = 18;            // f_0..f_8 then g_0..g_8
-constexpr int TILE_X = 32;          // nodes along i per tile
-constexpr int TILE_Y = 16;          // nodes along j per tile
+constexpr int TILE_X = 32;          // nodes along i per tile (default shape)
+constexpr int TILE_Y = 16;          // nodes along j per tile (default shape)
+// tile shapes of the fused kernel (the batch autotuner chooses among them;
+// C-grid launches use shape 0)
+constexpr int N_TILE_SHAPES = 3;
+constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}};
 #ifndef FSI_K1_THREADS
 #define FSI_K1_THREADS 512
 #endif
@@ -90,7 +94,7 @@ struct Inst {
 namespace fsi {
 // host-callable launchers (fsilbm_kernels.hip)
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid, bool cgrid);
+                                 hipStream_t s, int grid, bool cgrid, int shape);
 hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
                              hipStream_t s);
 hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,

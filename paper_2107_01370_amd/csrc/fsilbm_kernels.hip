@@ -331,7 +331,8 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
 // ---------------------------------------------------------------------------
 // Fused collision + ALE interpolating streaming.
 //
-// One workgroup owns a TILE_X x TILE_Y block of arrival nodes.  The momentum
+// One workgroup owns a TX x TY block of arrival nodes (32 x 16 by default;
+// 64 x 8 and 16 x 32 are the other shapes the batch autotuner tries).  The momentum
 // correction needs nested gradients (reach 2) and the interpolation stencil
 // reaches one node, so the tile is processed with a halo of 3:
 //   phase 1 (tile+3): populations -> delta Q_a, mu/p;  mesh geometry -> LDS
@@ -349,21 +350,33 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
 // of a cell), on meshes with large absolute coordinates and displacements;
 // integer grids stay exact.
 // ---------------------------------------------------------------------------
-constexpr int R3X = TILE_X + 6, R3Y = TILE_Y + 6, R3N = R3X * R3Y;
-constexpr int R2X = TILE_X + 4, R2Y = TILE_Y + 4, R2N = R2X * R2Y;
-constexpr int R1X = TILE_X + 2, R1Y = TILE_Y + 2, R1N = R1X * R1Y;
 constexpr int NMOV = 16;     // moving populations kept in LDS (f_1..8, g_1..8)
 
+// extents of the tile and its halo rings for a TX x TY tile
+template <int TX, int TY>
+struct Geo {
+    static constexpr int TILE_X = TX, TILE_Y = TY;
+    static constexpr int R3X = TX + 6, R3Y = TY + 6, R3N = R3X * R3Y;
+    static constexpr int R2X = TX + 4, R2Y = TY + 4, R2N = R2X * R2Y;
+    static constexpr int R1X = TX + 2, R1Y = TY + 2, R1N = R1X * R1Y;
+    static constexpr int RING_ROWS = 2 * 2 * R3X;     // two rows above and below R1
+    static constexpr int R1_ROUNDS = (R1N + K1_THREADS - 1) / K1_THREADS;
+    static_assert(R1_ROUNDS == 2, "phase-1/3 register hand-off assumes two rounds");
+    static_assert(TX * TY == K1_THREADS, "one arrival node per thread");
+    static_assert(R3N <= 2 * K1_THREADS && R2N <= 2 * K1_THREADS, "two rounds per phase");
+};
+
+template <class G>
 struct K1Smem {
-    float2 Xu[R3N];          // X - X_ref (undeformed, periodic shifts applied)
-    float2 dn[R3N];          // (1 - r) d^n(X) - D_ref^n
-    float2 dd[R3N];          // (1 - r)(d^{n+1}(X) - d^n(X))
-    float2 D[R2N];           // nested correction, first level
+    float2 Xu[G::R3N];       // X - X_ref (undeformed, periodic shifts applied)
+    float2 dn[G::R3N];       // (1 - r) d^n(X) - D_ref^n
+    float2 dd[G::R3N];       // (1 - r)(d^{n+1}(X) - d^n(X))
+    float2 D[G::R2N];        // nested correction, first level
     union {
         struct {
-            float Qx[R3N], Qy[R3N], S[R3N];
+            float Qx[G::R3N], Qy[G::R3N], S[G::R3N];
         } q;
-        float FG[NMOV][R1N];
+        float FG[NMOV][G::R1N];
     } u;
 };
 
@@ -435,9 +448,10 @@ __device__ __forceinline__ int cut_slot(const Inst &P, int i) {
     return -1;
 }
 
-// position difference x_a - x_b of two R3 entries: FP64 for X, FP32 for the
-// relative displacement; `level1` adds the step increment (mesh at t^{n+1})
-__device__ __forceinline__ float2 pos_diff(const K1Smem &sm, int a, int b, bool level1) {
+// position difference x_a - x_b of two R3 entries; `level1` adds the step
+// increment (mesh at t^{n+1})
+template <class G>
+__device__ __forceinline__ float2 pos_diff(const K1Smem<G> &sm, int a, int b, bool level1) {
     float2 d;
     d.x = (sm.Xu[a].x - sm.Xu[b].x) + (sm.dn[a].x - sm.dn[b].x);
     d.y = (sm.Xu[a].y - sm.Xu[b].y) + (sm.dn[a].y - sm.dn[b].y);
@@ -449,8 +463,10 @@ __device__ __forceinline__ float2 pos_diff(const K1Smem &sm, int a, int b, bool 
 }
 
 // metric (x_xi, x_eta, y_xi, y_eta) at R3 entry c
-__device__ __forceinline__ void metric(const K1Smem &sm, int c, const Sten &is, const Sten &js,
+template <class G>
+__device__ __forceinline__ void metric(const K1Smem<G> &sm, int c, const Sten &is, const Sten &js,
                                        bool level1, float J[4]) {
+    constexpr int R3X = G::R3X;
     if (is.centred) {
         const float2 di = pos_diff(sm, c + 1, c - 1, level1);
         J[0] = 0.5f * di.x;
@@ -477,11 +493,9 @@ __device__ __forceinline__ void metric(const K1Smem &sm, int c, const Sten &is, 
 // the ring of tile+3 outside it, so that a thread's phase-1 items below R1N
 // are exactly its phase-3 collision nodes (their populations stay in
 // registers between the two phases).
-constexpr int RING_ROWS = 2 * 2 * R3X;       // two rows above and below R1
-constexpr int R1_ROUNDS = (R1N + K1_THREADS - 1) / K1_THREADS;
-static_assert(R1_ROUNDS == 2, "phase-1/3 register hand-off assumes two rounds");
-
+template <class G>
 __device__ __forceinline__ int phase1_entry(int p) {
+    constexpr int R1N = G::R1N, R1X = G::R1X, R3X = G::R3X, R3Y = G::R3Y, RING_ROWS = G::RING_ROWS;
     if (p < R1N) return (p / R1X + 2) * R3X + (p % R1X + 2);
     const int q = p - R1N;
     if (q < RING_ROWS) {
@@ -501,13 +515,18 @@ __device__ __forceinline__ int phase1_entry(int p) {
 // them as their row -1 instead of colliding there: a node below the cut seen
 // from the other side has different neighbours on row 0 next to the trailing
 // edge, so its collision cannot be formed in the mirrored frame).
-template <int STORE, bool EXPORT, bool CG>
-__device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__restrict__ insts,
-                                                    const int2 item) {
+template <int STORE, bool EXPORT, bool CG, int TX, int TY>
+__device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
+                                                    const Inst *__restrict__ insts, const int2 item) {
+    using G = Geo<TX, TY>;
+    constexpr int TILE_X = TX, TILE_Y = TY;
+    constexpr int R3X = G::R3X, R3N = G::R3N, R2X = G::R2X, R2N = G::R2N;
+    constexpr int R1X = G::R1X, R1N = G::R1N, R1_ROUNDS = G::R1_ROUNDS;
     const Inst &P = insts[item.x];
     const bool cg = CG && P.cgrid;
     const int tile = item.y;
-    const int ti = tile % P.tiles_i, tj = tile / P.tiles_i;
+    const int tiles_i = (P.ni + TX - 1) / TX;
+    const int ti = tile % tiles_i, tj = tile / tiles_i;
     const int i0 = ti * TILE_X, j0 = tj * TILE_Y;
     const int ni = P.ni, nj = P.nj;
     const long long n = uniform(*P.step);
@@ -539,7 +558,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
     for (int rd = 0; rd < (R3N + K1_THREADS - 1) / K1_THREADS; ++rd) {
         const int p = rd * K1_THREADS + t;
         if (p >= R3N) break;
-        const int e = phase1_entry(p);
+        const int e = phase1_entry<G>(p);
         const int u = e % R3X, v = e / R3X;
         int ig = i0 - 3 + u, jg = j0 - 3 + v;
         // wrap into the mesh; a node seen across a periodic seam has its
@@ -836,10 +855,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem &sm, const Inst *__re
     if (err) atomicOr(P.err, err);
 }
 
-template <int STORE, bool CG>
+template <int STORE, bool CG, int TX, int TY>
 __global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
 k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
-    __shared__ K1Smem sm;
+    __shared__ K1Smem<Geo<TX, TY>> sm;
     // Work distribution: consecutive dispatch slots go round-robin over the 8
     // XCDs, so each XCD owns a contiguous run of work items (neighbouring tiles
     // share halos in that XCD's L2).  A grid smaller than the item count makes
@@ -850,7 +869,7 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         const int wk = xcd * per_xcd + li;
         if (wk >= n_work) break;
         const int2 w = work[wk];
-        collide_stream_tile<STORE, false, CG>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
+        collide_stream_tile<STORE, false, CG, TX, TY>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
         __syncthreads();                      // LDS is reused by the next item
     }
 }
@@ -859,10 +878,10 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
 template <int STORE>
 __global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
 k_cut_export(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
-    __shared__ K1Smem sm;
+    __shared__ K1Smem<Geo<TILE_X, TILE_Y>> sm;
     if ((int)blockIdx.x >= n_work) return;
     const int2 w = work[blockIdx.x];
-    collide_stream_tile<STORE, true, true>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
+    collide_stream_tile<STORE, true, true, TILE_X, TILE_Y>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,22 +1384,31 @@ __global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const
     } while (0)
 
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid, bool cgrid) {
+                                 hipStream_t s, int grid, bool cgrid, int shape) {
     // one workgroup per item unless a smaller (persistent) grid is requested;
     // always a multiple of the XCD count
     const int all = ((n_work + 7) / 8) * 8;
     int g = grid > 0 ? ((grid + 7) / 8) * 8 : all;
     if (g > all) g = all;
     if (g < 8) g = 8;
-    // the C-grid-capable build only when some instance of the launch needs it
+    // the C-grid-capable build (default tile shape only) when some instance of
+    // the launch needs it
     const dim3 G(g), B(K1_THREADS);
+    if (cgrid && shape != 0) return hipErrorInvalidValue;
+#define FSI_K1(ST, CGV, TXV, TYV) \
+    hipLaunchKernelGGL((k_collide_stream<ST, CGV, TXV, TYV>), G, B, 0, s, insts, work, n_work)
     if (storage == 0) {
-        if (cgrid) hipLaunchKernelGGL((k_collide_stream<0, true>), G, B, 0, s, insts, work, n_work);
-        else hipLaunchKernelGGL((k_collide_stream<0, false>), G, B, 0, s, insts, work, n_work);
+        if (cgrid) FSI_K1(0, true, TILE_X, TILE_Y);
+        else if (shape == 1) FSI_K1(0, false, 64, 8);
+        else if (shape == 2) FSI_K1(0, false, 16, 32);
+        else FSI_K1(0, false, TILE_X, TILE_Y);
     } else {
-        if (cgrid) hipLaunchKernelGGL((k_collide_stream<1, true>), G, B, 0, s, insts, work, n_work);
-        else hipLaunchKernelGGL((k_collide_stream<1, false>), G, B, 0, s, insts, work, n_work);
+        if (cgrid) FSI_K1(1, true, TILE_X, TILE_Y);
+        else if (shape == 1) FSI_K1(1, false, 64, 8);
+        else if (shape == 2) FSI_K1(1, false, 16, 32);
+        else FSI_K1(1, false, TILE_X, TILE_Y);
     }
+#undef FSI_K1
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ def load_library(path: str = LIB_PATH):
         "fsi_batch_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "fsi_batch_bind_workspace": (ctypes.c_int, [P, P, ctypes.c_size_t]),
         "fsi_batch_init_equilibrium": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
-        "fsi_batch_set_schedule": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int]),
+        "fsi_batch_set_schedule": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "fsi_batch_autotune": (ctypes.c_int, [P, ctypes.c_int, dp]),
         "fsi_batch_step": (ctypes.c_int, [P, ctypes.c_int]),
         "fsi_batch_synchronize": (ctypes.c_int, [P]),
@@ -343,15 +343,16 @@ def fsi_batch_init_equilibrium(b, k, shape, rho=None, ux=None, uy=None, T=None):
     _bcheck(b, _lib.fsi_batch_init_equilibrium(b, int(k), *[_dptr(a) for a in arrs]))
 
 
-def fsi_batch_set_schedule(b, grid, order):
-    _bcheck(b, _lib.fsi_batch_set_schedule(b, int(grid), int(order)))
+def fsi_batch_set_schedule(b, grid, order, shape=0):
+    _bcheck(b, _lib.fsi_batch_set_schedule(b, int(grid), int(order), int(shape)))
 
 
 def fsi_batch_autotune(b, reps):
-    """Returns (grid, order, ms per collision-streaming launch) of the fastest schedule."""
-    out = np.zeros(3, dtype=np.float64)
+    """Returns (grid, order, shape, ms per collision-streaming launch) of the
+    fastest schedule."""
+    out = np.zeros(4, dtype=np.float64)
     _bcheck(b, _lib.fsi_batch_autotune(b, int(reps), _dptr(out)))
-    return int(out[0]), int(out[1]), float(out[2])
+    return int(out[0]), int(out[1]), int(out[2]), float(out[3])
 
 
 def fsi_batch_step(b, nsteps):
@@ -521,8 +522,8 @@ class Batch:
     def init_equilibrium(self, k, rho=None, ux=None, uy=None, T=None):
         fsi_batch_init_equilibrium(self.b, k, self.shapes[k], rho, ux, uy, T)
 
-    def set_schedule(self, grid, order):
-        fsi_batch_set_schedule(self.b, grid, order)
+    def set_schedule(self, grid, order, shape=0):
+        fsi_batch_set_schedule(self.b, grid, order, shape)
 
     def autotune(self, reps=5):
         return fsi_batch_autotune(self.b, reps)

@@ -190,11 +190,12 @@ def test_batch_rejects_bad_instance_and_mixed_storage(F):
 def test_batch_schedule_arguments_are_checked(F):
     b = F.fsi_batch_create(_batch_cases())
     try:
-        F.fsi_batch_set_schedule(b, 1024, 1)
-        F.fsi_batch_set_schedule(b, 0, 0)
-        for grid, order in ((-1, 0), (0, 2)):
+        F.fsi_batch_set_schedule(b, 1024, 1, 1)
+        F.fsi_batch_set_schedule(b, 0, 0, 2)
+        F.fsi_batch_set_schedule(b, 0, 0, 0)
+        for grid, order, shape in ((-1, 0, 0), (0, 2, 0), (0, 0, 3)):
             with pytest.raises(F.FsiError) as e:
-                F.fsi_batch_set_schedule(b, grid, order)
+                F.fsi_batch_set_schedule(b, grid, order, shape)
             assert e.value.status == -1
     finally:
         F.fsi_batch_destroy(b)
@@ -209,6 +210,17 @@ def test_cgrid_airfoil_is_accepted(F):
     big = synth.airfoil_flutter_case()
     ctx = F.fsi_create(big.fluid, big.mesh, big.bodies, None)
     F.fsi_destroy(ctx)
+
+
+def test_cgrid_batch_keeps_the_default_tile_shape(F):
+    c = synth.small_airfoil_case()
+    b = F.fsi_batch_create([(c.fluid, c.mesh, c.bodies)])
+    try:
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_batch_set_schedule(b, 0, 0, 1)
+        assert e.value.status == -1
+    finally:
+        F.fsi_batch_destroy(b)
 
 
 def test_cgrid_with_unmatched_cut_is_rejected(F):
