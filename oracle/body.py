@@ -11,6 +11,14 @@ integrated with the classical fourth-order Runge-Kutta method over one time
 step with the fluid load frozen (staggered weak coupling, Sec. III).
 Prescribed motion: h(t) = A_h sin(2 pi f_h t), alpha(t) = A_a sin(2 pi f_a t).
 A fixed body keeps its initial state.
+
+Forced start then release (Sec. V, the airfoil's protocol: a forced pitching
+perturbation for a number of periods, after which the section moves freely):
+a 1DOF or 2DOF body with release_time > 0 follows the prescribed motion while
+t^{n+1} <= release_time and integrates its ODE from the state reached
+afterwards.  Reading: the plunge is held by the forcing unless a heave
+amplitude is given; the first free step starts from the prescribed state of
+the last forced level.
 """
 
 from __future__ import annotations
@@ -61,15 +69,21 @@ def prescribed_state(body, t):
                      body.pitch_amp * wa * math.cos(wa * t)])
 
 
+def forced(body, t):
+    """True while a released body still follows its prescribed start."""
+    rt = getattr(body, "release_time", 0.0)
+    return body.dof in (DOF_HEAVE, DOF_PITCH_PLUNGE) and rt > 0.0 and t <= rt
+
+
 def initial_state(body):
-    if body.dof == DOF_PRESCRIBED:
+    if body.dof == DOF_PRESCRIBED or forced(body, 0.0):
         return prescribed_state(body, 0.0)
     return np.array([body.h0, body.a0, body.hd0, body.ad0], dtype=np.float64)
 
 
 def advance(body, state, Fy, M, t_next, dt):
     """State at t^{n+1} from the state at t^n and the frozen load at t^n."""
-    if body.dof == DOF_PRESCRIBED:
+    if body.dof == DOF_PRESCRIBED or forced(body, t_next):
         return prescribed_state(body, t_next)
     if body.dof == DOF_FIXED:
         return np.asarray(state, dtype=np.float64).copy()

@@ -169,11 +169,34 @@ def r5(s):
     return 10.0 * s ** 3 - 15.0 * s ** 4 + 6.0 * s ** 5
 
 
-def blend_factor(X, Y, body):
-    """r_blend: 0 inside the rigid radius, 1 beyond the blend radius, r_5 of
-    the normalised radial position in between (Sec. II.D).  Radial distance is
-    measured from the body's blending centre in the undeformed frame."""
-    d = np.hypot(X - body.center[0], Y - body.center[1])
+def distance_to_wall(X, Y, px, py):
+    """Euclidean distance from each point (X, Y) to the closed polygon with
+    vertices (px, py): the minimum over its edges of the point-segment
+    distance (brute force, row by row)."""
+    ax, ay = np.asarray(px, dtype=np.float64), np.asarray(py, dtype=np.float64)
+    ex, ey = np.roll(ax, -1) - ax, np.roll(ay, -1) - ay
+    ee = ex * ex + ey * ey
+    out = np.empty(X.shape)
+    for j in range(X.shape[0]):
+        x = X[j][:, None]
+        y = Y[j][:, None]
+        t = np.clip(((x - ax) * ex + (y - ay) * ey) / ee, 0.0, 1.0)
+        dx = x - (ax + t * ex)
+        dy = y - (ay + t * ey)
+        out[j] = np.sqrt(np.min(dx * dx + dy * dy, axis=1))
+    return out
+
+
+def blend_factor(X, Y, body, wall=None):
+    """r_blend: 0 inside the rigid region, 1 beyond the blend region, r_5 of
+    the normalised position in between (Sec. II.D).  The position is the
+    radial distance from the body's blending centre in the undeformed frame,
+    or, for blend_mode 1 (the distance-field variant the paper suggests for
+    slender bodies), the distance to the wall polygon `wall` = (px, py)."""
+    if getattr(body, "blend_mode", 0) == 1:
+        d = distance_to_wall(X, Y, wall[0], wall[1])
+    else:
+        d = np.hypot(X - body.center[0], Y - body.center[1])
     s = (d - body.r_rigid) / (body.r_blend - body.r_rigid)
     return np.where(s < 0.0, 0.0, np.where(s > 1.0, 1.0, r5(np.clip(s, 0.0, 1.0))))
 
@@ -198,18 +221,20 @@ def rigid_displacement(X, Y, body, h, alpha):
     return (c - 1.0) * dx - s * dy, h + s * dx + (c - 1.0) * dy
 
 
-def deformed_positions(X, Y, bodies, states):
+def deformed_positions(X, Y, bodies, states, wall=None, r=None):
     """x = r_blend X + (1 - r_blend) G'_x(X, t) (Sec. II.D), evaluated as
     x = X + (1 - r_blend)(G'_x(X) - X), which is the same expression.
 
     ``states`` holds (h, alpha, hdot, alphadot) per body.  A single body per
-    mesh is supported; with no body x = X.
+    mesh is supported; with no body x = X.  ``r``: the blending factor if
+    already known (it depends on the undeformed mesh only).
     """
     if not bodies:
         return X.copy(), Y.copy()
     assert len(bodies) == 1, "one moving body per mesh"
     body = bodies[0]
     h, alpha = states[0][0], states[0][1]
-    r = blend_factor(X, Y, body)
+    if r is None:
+        r = blend_factor(X, Y, body, wall)
     ux, uy = rigid_displacement(X, Y, body, h, alpha)
     return X + (1.0 - r) * ux, Y + (1.0 - r) * uy

@@ -91,10 +91,20 @@ class OracleSolver:
             T = np.full(shape, fluid.T_inf)
         self.f, self.g = L.equilibrium_populations(rho, ux, uy, T, fluid.gamma)
         self.has_wall = mesh.topo in (1, 2)
+        # undeformed wall polygon (distance-field blending)
+        self.wall = None
+        if self.has_wall:
+            from .forces import wall_polygon
+            cols = wall_polygon(self.grid)
+            self.wall = (self.X[0, cols], self.Y[0, cols])
+        self._r_cache = None
 
     # ---- geometry ---------------------------------------------------------
     def positions(self, states):
-        return deformed_positions(self.X, self.Y, self.bodies, states)
+        if self.bodies and self._r_cache is None:
+            from .mesh import blend_factor
+            self._r_cache = blend_factor(self.X, self.Y, self.bodies[0], self.wall)
+        return deformed_positions(self.X, self.Y, self.bodies, states, self.wall, self._r_cache)
 
     def ea_position(self, states):
         b = self.bodies[0]

@@ -55,6 +55,8 @@ class BodyParams:
     heave_freq: float = 0.0
     pitch_amp: float = 0.0
     pitch_freq: float = 0.0
+    release_time: float = 0.0    # > 0: prescribed motion until then, free afterwards
+    blend_mode: int = 0          # 0: radial from `center`; 1: distance to the wall
 
 
 @dataclass
