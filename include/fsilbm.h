@@ -113,11 +113,19 @@ enum { FSI_DOF_PRESCRIBED = 0, FSI_DOF_HEAVE = 1, FSI_DOF_PITCH_PLUNGE = 2,
 
 /* One body: spring-mass parameters (m h'' + S_a a'' + k_h h = F_y,
  * S_a h'' + I_a a'' + k_a a = M_EA), the blending region of influence
- * (rigid inside r_rigid, r_5 blend out to r_blend, Sec. II.D, radial from
- * `center`), the elastic axis `ea` (rotation centre), the initial state and,
- * for FSI_DOF_PRESCRIBED, h(t) = heave_amp sin(2 pi heave_freq t),
- * alpha(t) = pitch_amp sin(2 pi pitch_freq t).  h is along +y, alpha is
- * counter-clockwise. */
+ * (rigid inside r_rigid, r_5 blend out to r_blend, Sec. II.D), the elastic
+ * axis `ea` (rotation centre), the initial state and, for FSI_DOF_PRESCRIBED,
+ * h(t) = heave_amp sin(2 pi heave_freq t), alpha(t) = pitch_amp sin(2 pi
+ * pitch_freq t).  h is along +y, alpha is counter-clockwise.
+ *   blend_mode 0: r_rigid, r_blend are radii from `center` (the paper's
+ *     choice); 1: distances to the wall (the mesh's wall polygon in the
+ *     undeformed frame, computed once per node at creation; meshes with a
+ *     wall only, at most 4e9 node-edge pairs), the variant the paper suggests
+ *     for slender bodies.
+ *   release_time > 0 (FSI_DOF_HEAVE, FSI_DOF_PITCH_PLUNGE): the body follows
+ *     the prescribed motion above while t^{n+1} <= release_time and its ODE
+ *     afterwards, starting from the state reached (the forced-then-free
+ *     protocol of the paper's airfoil case, Sec. V). */
 typedef struct {
     int dof;
     double m, S_a, I_a, k_h, k_a;
@@ -125,6 +133,8 @@ typedef struct {
     double r_rigid, r_blend;
     double h0, a0, hd0, ad0;
     double heave_amp, heave_freq, pitch_amp, pitch_freq;
+    double release_time;     /* see above; 0: no forced start */
+    int blend_mode;          /* 0 radial, 1 distance to the wall */
 } fsi_body_desc;
 
 /* Create a context for one structured mesh with at most one moving body

@@ -26,10 +26,11 @@ struct fsi_ctx {
     // workspace layout (byte offsets)
     size_t off_pop[2]{}, off_X = 0, off_mask = 0, off_tgt = 0, off_B = 0, off_inflow = 0,
            off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
-           off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0,
+           off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0, off_dist = 0,
            total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
+    std::vector<double> wall_dist;      // blend_mode 1: distance of every node to the wall
     std::vector<uint8_t> inflow;        // per far-field list entry
     std::vector<int2> ff;               // far-field (node, interior node)
     std::vector<int2> wk0, wk1, wbnd, wwall;
@@ -200,6 +201,37 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
         if (b.dof == FSI_DOF_HEAVE && !(b.m > 0)) return fail(c, FSI_E_ARG, "heave body needs m > 0");
         if (b.dof == FSI_DOF_PITCH_PLUNGE && !(b.m * b.I_a - b.S_a * b.S_a > 0))
             return fail(c, FSI_E_ARG, "pitch-plunge body needs a positive-definite mass matrix");
+        if (!(b.release_time >= 0)) return fail(c, FSI_E_ARG, "release_time must be >= 0");
+        if (b.blend_mode != 0 && b.blend_mode != 1) return fail(c, FSI_E_ARG, "unknown blend_mode");
+        if (b.blend_mode == 1) {
+            if (!c->has_wall)
+                return fail(c, FSI_E_ARG, "distance blending needs a mesh with a wall");
+            // distance of every node to the closed wall polygon (undeformed frame)
+            std::vector<int> poly;
+            const int w0 = c->topo == FSI_TOPO_CGRID ? c->n_wake : 0;
+            const int w1 = c->topo == FSI_TOPO_CGRID ? ni - 1 - c->n_wake : ni;
+            for (int i = w0; i < w1; ++i) poly.push_back(i);
+            const size_t N = (size_t)ni * nj, E = poly.size();
+            if ((double)N * (double)E > 4e9)
+                return fail(c, FSI_E_ARG, "distance blending: mesh too large for the direct "
+                                          "distance computation (nodes x wall edges > 4e9)");
+            c->wall_dist.assign(N, 0.0);
+            for (size_t k = 0; k < N; ++k) {
+                const double px = c->X[2 * k], py = c->X[2 * k + 1];
+                double best = INFINITY;
+                for (size_t e = 0; e < E; ++e) {
+                    const double *a = &c->X[2 * (size_t)poly[e]];
+                    const double *q = &c->X[2 * (size_t)poly[(e + 1) % E]];
+                    const double ex = q[0] - a[0], ey = q[1] - a[1];
+                    const double ee = ex * ex + ey * ey;
+                    double t = ee > 0 ? ((px - a[0]) * ex + (py - a[1]) * ey) / ee : 0.0;
+                    t = t < 0 ? 0 : (t > 1 ? 1 : t);
+                    const double dx = px - (a[0] + t * ex), dy = py - (a[1] + t * ey);
+                    best = std::min(best, dx * dx + dy * dy);
+                }
+                c->wall_dist[k] = sqrt(best);
+            }
+        }
         if (c->topo == FSI_TOPO_PERIODIC2) {
             // the blended region must not reach the periodic seams
             for (int j = 0; j < nj; ++j)
@@ -333,6 +365,8 @@ void fill_params(fsi_ctx *c) {
         B.inv_width = 1.0 / (b.r_blend - b.r_rigid);
         B.heave_amp = b.heave_amp; B.heave_omega = 2.0 * M_PI * b.heave_freq;
         B.pitch_amp = b.pitch_amp; B.pitch_omega = 2.0 * M_PI * b.pitch_freq;
+        B.release_time = b.release_time;
+        B.blend_mode = b.blend_mode;
     }
     // work lists
     const int ntiles = P.tiles_i * P.tiles_j;
@@ -383,6 +417,7 @@ void layout(fsi_ctx *c) {
     c->off_wbnd = take(c->wbnd.size() * sizeof(int2));
     c->off_wwall = take(c->wwall.size() * sizeof(int2));
     c->off_wk0 = take(c->wk0.size() * sizeof(int2));
+    c->off_dist = take(c->wall_dist.size() * sizeof(double));
     c->total = o;
 }
 
@@ -518,6 +553,10 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     P.inflow = reinterpret_cast<const uint8_t *>(c->ws + c->off_inflow);
     P.ff = reinterpret_cast<const int2 *>(c->ws + c->off_ff);
     P.cutbuf = reinterpret_cast<float *>(c->ws + c->off_cut);
+    P.wall_dist = c->wall_dist.empty() ? nullptr : reinterpret_cast<const double *>(c->ws + c->off_dist);
+    if (!c->wall_dist.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_dist, c->wall_dist.data(), c->wall_dist.size() * 8,
+                                  hipMemcpyHostToDevice, c->stream));
     P.wall_force = reinterpret_cast<double4 *>(c->ws + c->off_force);
     P.slots = reinterpret_cast<fsi::BodySlot *>(c->ws + c->off_slots);
     P.history = reinterpret_cast<double *>(c->ws + c->off_hist);
@@ -575,7 +614,8 @@ fsi_status fsi_init_equilibrium(fsi_ctx *c, const double *rho, const double *ux,
     fsi::BodySlot slots[3];
     if (c->has_body) {
         const fsi_body_desc &b = c->body;
-        if (b.dof == FSI_DOF_PRESCRIBED)
+        const bool forced = (b.dof == FSI_DOF_HEAVE || b.dof == FSI_DOF_PITCH_PLUNGE) && b.release_time > 0;
+        if (b.dof == FSI_DOF_PRESCRIBED || forced)
             slots[0] = slot_of(0.0, 0.0, b.heave_amp * 2 * M_PI * b.heave_freq,
                                b.pitch_amp * 2 * M_PI * b.pitch_freq);
         else

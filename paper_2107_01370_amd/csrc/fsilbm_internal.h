@@ -39,6 +39,9 @@ struct Body {
     double ex, ey;            // elastic axis / rotation centre (undeformed frame)
     double r_rigid, inv_width;// 1 / (r_blend - r_rigid)
     double heave_amp, heave_omega, pitch_amp, pitch_omega;
+    double release_time;      // > 0: prescribed motion until then (1DOF / 2DOF)
+    int blend_mode;           // 0: radial from (cx, cy); 1: per-node wall distance
+    int pad;
 };
 
 // Body state at one time level, plus the rotation terms the kernels need.
@@ -82,6 +85,7 @@ struct Inst {
     const uint8_t *inflow;    // [n_ff] far-field node is an inlet
     float *cutbuf;            // C-grid: [16][cut_n] post-collision moving populations of row 1
     double4 *wall_force;      // [ni] per-node (Fx, Fy, Mz, 0)
+    const double *wall_dist;  // [nj][ni] distance to the wall (blend_mode 1), else null
     BodySlot *slots;          // [3] body states at levels n % 3
     double *history;          // [HIST_CAP][6]
     long long *step;          // completed steps

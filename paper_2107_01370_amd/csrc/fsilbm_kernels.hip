@@ -68,10 +68,20 @@ __device__ __forceinline__ void pop_store(const Inst &P, void *base, int q, long
 // ---------------------------------------------------------------------------
 // geometry (FP64): blending factor and rigid displacement (Sec. II.D)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double blend_factor(const Body &b, double X, double Y) {
+// r of node idx at undeformed position (X, Y): the position in the region of
+// influence is the radial distance from the blending centre, or (blend_mode 1)
+// the node's precomputed distance to the wall
+__device__ __forceinline__ double blend_factor(const Inst &P, long long idx, double X, double Y) {
+    const Body &b = P.body;
     if (!b.present) return 1.0;
-    const double dx = X - b.cx, dy = Y - b.cy;
-    const double s = (sqrt(dx * dx + dy * dy) - b.r_rigid) * b.inv_width;
+    double d;
+    if (b.blend_mode == 1) {
+        d = P.wall_dist[idx];
+    } else {
+        const double dx = X - b.cx, dy = Y - b.cy;
+        d = sqrt(dx * dx + dy * dy);
+    }
+    const double s = (d - b.r_rigid) * b.inv_width;
     if (s <= 0.0) return 0.0;
     if (s >= 1.0) return 1.0;
     return s * s * s * (10.0 + s * (-15.0 + 6.0 * s));
@@ -539,11 +549,12 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     unsigned err = 0;
 
     // FP64 references of the tile: position and displacement of its first node
-    const double2 Xref = P.X[(long long)min(j0, nj - 1) * ni + i0];
+    const long long iref = (long long)min(j0, nj - 1) * ni + i0;
+    const double2 Xref = P.X[iref];
     const double Xrx = uniform(Xref.x), Xry = uniform(Xref.y);
     double Drx = 0.0, Dry = 0.0;
     if (body.present) {
-        const double r = blend_factor(body, Xrx, Xry);
+        const double r = uniform(blend_factor(P, iref, Xrx, Xry));
         double dx, dy;
         rigid_disp(body, sn, Xrx, Xry, dx, dy);
         Drx = (1.0 - r) * dx;
@@ -590,7 +601,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         float2 dn = make_float2((float)(-Drx), (float)(-Dry)), dd = make_float2(0.0f, 0.0f);
         if (body.present) {
             // blending factor and displacements from the unshifted node
-            const double r = blend_factor(body, Xr.x, Xr.y);
+            const double r = blend_factor(P, idx, Xr.x, Xr.y);
             if (r < 1.0) {
                 double d0x, d0y, d1x, d1y;
                 rigid_disp(body, sn, Xr.x, Xr.y, d0x, d0y);
@@ -910,7 +921,7 @@ __device__ __forceinline__ void load_node(const Inst &P, const void *base, long 
 __device__ __forceinline__ void node_pos(const Inst &P, long long idx, const BodySlot &s, double &x,
                                          double &y) {
     const double2 X = P.X[idx];
-    const double r = blend_factor(P.body, X.x, X.y);
+    const double r = blend_factor(P, idx, X.x, X.y);
     x = X.x;
     y = X.y;
     if (r < 1.0) {
@@ -967,7 +978,7 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
             }
         float VGx = 0.0f, VGy = 0.0f;
         const double2 X = P.X[ig];
-        const double r = blend_factor(P.body, X.x, X.y);
+        const double r = blend_factor(P, ig, X.x, X.y);
         if (r < 1.0) {
             double d1x, d1y, d0x, d0y;
             rigid_disp(P.body, P.slots[(n + 1) % 3], X.x, X.y, d1x, d1y);
@@ -1224,7 +1235,9 @@ __device__ void body_accel(const Body &b, double h, double a, double Fy, double 
 __device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, double M, double t_next,
                                  double dt) {
     BodySlot o = s;
-    if (b.present && b.dof == DOF_PRESCRIBED) {
+    const bool forced = (b.dof == DOF_HEAVE || b.dof == DOF_PITCH_PLUNGE) && b.release_time > 0.0 &&
+                        t_next <= b.release_time;
+    if (b.present && (b.dof == DOF_PRESCRIBED || forced)) {
         o.h = b.heave_amp * sin(b.heave_omega * t_next);
         o.hd = b.heave_amp * b.heave_omega * cos(b.heave_omega * t_next);
         o.a = b.pitch_amp * sin(b.pitch_omega * t_next);

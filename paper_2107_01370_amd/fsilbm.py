@@ -60,7 +60,8 @@ class BodyDesc(ctypes.Structure):
                 ("h0", ctypes.c_double), ("a0", ctypes.c_double), ("hd0", ctypes.c_double),
                 ("ad0", ctypes.c_double), ("heave_amp", ctypes.c_double),
                 ("heave_freq", ctypes.c_double), ("pitch_amp", ctypes.c_double),
-                ("pitch_freq", ctypes.c_double)]
+                ("pitch_freq", ctypes.c_double), ("release_time", ctypes.c_double),
+                ("blend_mode", ctypes.c_int)]
 
 
 _lib = None
@@ -168,7 +169,8 @@ def _body_struct(b):
     return BodyDesc(int(b.dof), b.m, b.S_a, b.I_a, b.k_h, b.k_a,
                     (ctypes.c_double * 2)(*b.center), (ctypes.c_double * 2)(*b.ea),
                     b.r_rigid, b.r_blend, b.h0, b.a0, b.hd0, b.ad0, b.heave_amp,
-                    b.heave_freq, b.pitch_amp, b.pitch_freq)
+                    b.heave_freq, b.pitch_amp, b.pitch_freq,
+                    float(getattr(b, "release_time", 0.0)), int(getattr(b, "blend_mode", 0)))
 
 
 def fsi_create(fluid, mesh, bodies=(), stream_handle=None):

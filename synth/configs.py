@@ -296,13 +296,16 @@ def airfoil_flutter_case(n_wake: int = 128, n_af: int = 512, nj: int = 256,
                          mstar: float = 60.0, freq_ratio: float = 0.34, x_alpha: float = 1.8,
                          r_alpha: float = 1.87, VR: float = 0.5025, ea_frac: float = 0.25,
                          alpha0_deg: float = 1.0, blend_chords: float = 10.0,
-                         steps: int = 50000, storage: int = 0,
+                         steps: int = 50000, storage: int = 0, forced_periods: int = 0,
                          name: str | None = None) -> Case:
     """Pitch-plunge NACA0012 section on a C-grid (768 x 256 with the defaults:
     128 + 512 + 128 nodes along the wrap-around index, far field 20 chords).
 
     dt is a third of the smallest wall spacing (first cell or wall-node
-    spacing); the start is a uniform stream with a tanh layer at the wall."""
+    spacing); the start is a uniform stream with a tanh layer at the wall.
+    forced_periods > 0: the paper's protocol instead of an initial pitch: a
+    sinusoidal pitching of amplitude alpha0 at the pitch natural frequency for
+    that many periods, then release."""
     mesh = cgrid_mesh(n_wake, n_af, nj, chord, first_cell, far_chords)
     U = Ma * sound_speed(gamma, T_inf)
     rho = 1.0
@@ -317,6 +320,11 @@ def airfoil_flutter_case(n_wake: int = 128, n_af: int = 512, nj: int = 256,
                                     ea_frac, r_rigid=0.55 * chord,
                                     r_blend=blend_chords * chord,
                                     alpha0=math.radians(alpha0_deg))
+    if forced_periods > 0:
+        om_a = math.sqrt(body.k_a / body.I_a)
+        body = replace(body, a0=0.0, pitch_amp=math.radians(alpha0_deg),
+                       pitch_freq=om_a / (2.0 * math.pi),
+                       release_time=forced_periods * 2.0 * math.pi / om_a)
     r, ux, uy, T = airfoil_start_fields(mesh, U, rho, T_inf, start_layer_width(chord, first_cell))
     return Case(name or f"airfoil_flutter_{mesh.ni}x{nj}", mesh, fluid, [body], r, ux, uy, T,
                 steps, info={"chord": chord, "U": U, "Ma": Ma, "Re": Re, "mstar": mstar})

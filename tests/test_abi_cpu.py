@@ -236,3 +236,23 @@ def test_cgrid_with_unmatched_cut_is_rejected(F):
     with pytest.raises(F.FsiError) as e:
         F.fsi_create(c.fluid, short, c.bodies, None)
     assert e.value.status == -2
+
+
+# ---- forced start and distance blending --------------------------------------
+
+def test_release_and_distance_blending_are_validated(F):
+    c = synth.small_airfoil_case()
+    b = synth.configs.replace(c.bodies[0], blend_mode=1, r_rigid=1.0, r_blend=60.0,
+                              release_time=5.0, pitch_amp=0.01, pitch_freq=0.1)
+    ctx = F.fsi_create(c.fluid, c.mesh, [b], None)
+    F.fsi_destroy(ctx)
+    for bad in (dict(blend_mode=2), dict(release_time=-1.0)):
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_create(c.fluid, c.mesh, [synth.configs.replace(b, **bad)], None)
+        assert e.value.status == -1
+    a = synth.acoustic_pulse_case()
+    body = synth.BodyParams(dof=0, center=(32.0, 32.0), r_rigid=2.0, r_blend=10.0,
+                            heave_amp=0.5, heave_freq=0.01, blend_mode=1)
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(a.fluid, a.mesh, [body], None)
+    assert e.value.status == -1 and "wall" in str(e.value)

@@ -133,3 +133,34 @@ def test_batch_mixing_cgrid_and_ogrid_equals_alone():
         assert np.array_equal(f, ref[k][0][0]) and np.array_equal(g, ref[k][0][1]), k
         assert np.array_equal(b.forces(k, 0, 10), ref[k][1]), k
     b.close()
+
+
+def test_forced_start_release_and_distance_blending(wall_margin):
+    """The airfoil protocol: pitching forced for one period (50 steps), then
+    free 2DOF motion; blending by the distance to the section."""
+    c = synth.small_airfoil_case(alpha0_deg=0.0, n_af=72, n_wake=20)
+    dt = c.fluid.dt
+    body = replace(c.bodies[0], blend_mode=1, r_rigid=1.0, r_blend=70.0,
+                   pitch_amp=np.radians(1.0), pitch_freq=1.0 / (50 * dt), release_time=50 * dt)
+    c = replace(c, bodies=[body])
+    sim, ora = paired(c)
+    n = 80
+    sim.step(n)
+    with wall_margin() as margin:
+        ora.run(n)
+    assert margin[0] >= MARGIN
+    hist = sim.forces(0, n)
+    ho = np.array(ora.history)
+    # forced phase: the pitch history is the prescribed one, on both sides
+    t = ho[:51, 0] * dt
+    assert np.allclose(ho[:51, 5], body.pitch_amp * np.sin(2 * np.pi * body.pitch_freq * t), atol=1e-15)
+    assert np.max(np.abs(hist[:51, 5] - ho[:51, 5])) <= 1e-15
+    rho, ux, uy, T = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(rho - r_o) / r_o) <= 1e-5
+    assert np.max(np.abs(rho * T - r_o * T_o) / (r_o * T_o)) <= 1e-5
+    fscale = np.max(np.hypot(ho[:, 1], ho[:, 2]))
+    assert np.max(np.abs(hist[:, 1:4] - ho[:, 1:4])[:, :2]) <= 1e-4 * fscale
+    for col in (4, 5):                          # free plunge and pitch after release
+        assert np.max(np.abs(hist[:, col] - ho[:, col])) <= 1e-4 * np.max(np.abs(ho[:, col]))
+    assert np.max(np.abs(ho[51:, 4])) > 0       # the section moves freely after release
