@@ -14,13 +14,9 @@ constexpr int TILE_X = 32;          // nodes along i per tile (default shape)
 constexpr int TILE_Y = 16;          // nodes along j per tile (default shape)
 // tile shapes of the fused kernel (the batch autotuner chooses among them;
 // C-grid launches use shape 0)
-constexpr int N_TILE_SHAPES = 3;
-constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}};
-#ifndef FSI_K1_THREADS
-#define FSI_K1_THREADS 512
-#endif
-constexpr int K1_THREADS = FSI_K1_THREADS;      // threads per fused-kernel tile
-constexpr int K1_WAVES_PER_SIMD = (K1_THREADS / 64) * 2 / 4;   // two tiles per CU
+// (one thread per arrival node: 512-thread workgroups, 256 for 16 x 16)
+constexpr int N_TILE_SHAPES = 4;
+constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}, {16, 16}};
 constexpr int HIST_CAP = 1 << 16;   // force / displacement history records kept
 
 // error bits of the device error word

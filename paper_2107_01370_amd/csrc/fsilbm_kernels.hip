@@ -341,8 +341,9 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
 // ---------------------------------------------------------------------------
 // Fused collision + ALE interpolating streaming.
 //
-// One workgroup owns a TX x TY block of arrival nodes (32 x 16 by default;
-// 64 x 8 and 16 x 32 are the other shapes the batch autotuner tries).  The momentum
+// One workgroup of TX * TY threads owns a TX x TY block of arrival nodes
+// (32 x 16 by default; 64 x 8, 16 x 32 and 16 x 16 are the other shapes the
+// batch autotuner tries).  The momentum
 // correction needs nested gradients (reach 2) and the interpolation stencil
 // reaches one node, so the tile is processed with a halo of 3:
 //   phase 1 (tile+3): populations -> delta Q_a, mu/p;  mesh geometry -> LDS
@@ -361,19 +362,22 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
 // integer grids stay exact.
 // ---------------------------------------------------------------------------
 constexpr int NMOV = 16;     // moving populations kept in LDS (f_1..8, g_1..8)
+// waves per SIMD the launch bounds ask for (16 waves per CU: two 512-thread or
+// four 256-thread workgroups), which caps the VGPRs at 128
+constexpr int kWavesPerSimd = 4;
 
 // extents of the tile and its halo rings for a TX x TY tile
 template <int TX, int TY>
 struct Geo {
     static constexpr int TILE_X = TX, TILE_Y = TY;
+    static constexpr int NT = TX * TY;                 // threads: one arrival node each
     static constexpr int R3X = TX + 6, R3Y = TY + 6, R3N = R3X * R3Y;
     static constexpr int R2X = TX + 4, R2Y = TY + 4, R2N = R2X * R2Y;
     static constexpr int R1X = TX + 2, R1Y = TY + 2, R1N = R1X * R1Y;
     static constexpr int RING_ROWS = 2 * 2 * R3X;     // two rows above and below R1
-    static constexpr int R1_ROUNDS = (R1N + K1_THREADS - 1) / K1_THREADS;
+    static constexpr int R1_ROUNDS = (R1N + NT - 1) / NT;
     static_assert(R1_ROUNDS == 2, "phase-1/3 register hand-off assumes two rounds");
-    static_assert(TX * TY == K1_THREADS, "one arrival node per thread");
-    static_assert(R3N <= 2 * K1_THREADS && R2N <= 2 * K1_THREADS, "two rounds per phase");
+    static_assert(R3N <= 2 * NT && R2N <= 2 * NT, "two rounds per phase");
 };
 
 template <class G>
@@ -532,6 +536,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     constexpr int TILE_X = TX, TILE_Y = TY;
     constexpr int R3X = G::R3X, R3N = G::R3N, R2X = G::R2X, R2N = G::R2N;
     constexpr int R1X = G::R1X, R1N = G::R1N, R1_ROUNDS = G::R1_ROUNDS;
+    constexpr int K1_THREADS = G::NT;
     const Inst &P = insts[item.x];
     const bool cg = CG && P.cgrid;
     const int tile = item.y;
@@ -867,7 +872,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
 }
 
 template <int STORE, bool CG, int TX, int TY>
-__global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
+__global__ void __launch_bounds__(TX * TY, kWavesPerSimd)
 k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
     __shared__ K1Smem<Geo<TX, TY>> sm;
     // Work distribution: consecutive dispatch slots go round-robin over the 8
@@ -887,7 +892,7 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
 
 // C-grid pre-pass: one workgroup per tile of row block 0 that holds cut columns
 template <int STORE>
-__global__ void __launch_bounds__(K1_THREADS, K1_WAVES_PER_SIMD)
+__global__ void __launch_bounds__(TILE_X * TILE_Y, kWavesPerSimd)
 k_cut_export(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
     __shared__ K1Smem<Geo<TILE_X, TILE_Y>> sm;
     if ((int)blockIdx.x >= n_work) return;
@@ -1406,19 +1411,22 @@ hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work
     if (g < 8) g = 8;
     // the C-grid-capable build (default tile shape only) when some instance of
     // the launch needs it
-    const dim3 G(g), B(K1_THREADS);
     if (cgrid && shape != 0) return hipErrorInvalidValue;
+    if (shape < 0 || shape >= N_TILE_SHAPES) return hipErrorInvalidValue;
+    const dim3 G(g), B(TILE_SHAPES[shape][0] * TILE_SHAPES[shape][1]);
 #define FSI_K1(ST, CGV, TXV, TYV) \
     hipLaunchKernelGGL((k_collide_stream<ST, CGV, TXV, TYV>), G, B, 0, s, insts, work, n_work)
     if (storage == 0) {
         if (cgrid) FSI_K1(0, true, TILE_X, TILE_Y);
         else if (shape == 1) FSI_K1(0, false, 64, 8);
         else if (shape == 2) FSI_K1(0, false, 16, 32);
+        else if (shape == 3) FSI_K1(0, false, 16, 16);
         else FSI_K1(0, false, TILE_X, TILE_Y);
     } else {
         if (cgrid) FSI_K1(1, true, TILE_X, TILE_Y);
         else if (shape == 1) FSI_K1(1, false, 64, 8);
         else if (shape == 2) FSI_K1(1, false, 16, 32);
+        else if (shape == 3) FSI_K1(1, false, 16, 16);
         else FSI_K1(1, false, TILE_X, TILE_Y);
     }
 #undef FSI_K1
@@ -1427,7 +1435,7 @@ hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work
 
 hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
                              hipStream_t s) {
-    FSI_DISPATCH(storage, k_cut_export, dim3(n_work), dim3(K1_THREADS), s, insts, work, n_work);
+    FSI_DISPATCH(storage, k_cut_export, dim3(n_work), dim3(TILE_X * TILE_Y), s, insts, work, n_work);
     return hipGetLastError();
 }
 

@@ -193,7 +193,8 @@ def test_batch_schedule_arguments_are_checked(F):
         F.fsi_batch_set_schedule(b, 1024, 1, 1)
         F.fsi_batch_set_schedule(b, 0, 0, 2)
         F.fsi_batch_set_schedule(b, 0, 0, 0)
-        for grid, order, shape in ((-1, 0, 0), (0, 2, 0), (0, 0, 3)):
+        F.fsi_batch_set_schedule(b, 0, 0, 3)
+        for grid, order, shape in ((-1, 0, 0), (0, 2, 0), (0, 0, 4)):
             with pytest.raises(F.FsiError) as e:
                 F.fsi_batch_set_schedule(b, grid, order, shape)
             assert e.value.status == -1

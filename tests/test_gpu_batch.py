@@ -60,7 +60,7 @@ def _compare(b, cases, ref, nsteps, exact=True):
 
 
 @pytest.mark.parametrize("grid,order,shape", [(0, 0, 0), (0, 1, 0), (16, 0, 0), (64, 1, 0),
-                                              (0, 0, 1), (24, 1, 2)])
+                                              (0, 0, 1), (24, 1, 2), (0, 0, 3), (40, 1, 3)])
 def test_batch_equals_instances_run_alone(reference, grid, order, shape):
     """Bitwise equal to the instances run alone for the default tile shape; the
     other tile shapes change only which tile computes a halo node's collision
@@ -79,7 +79,7 @@ def test_autotune_keeps_the_state(reference):
     b = _batch(cases)
     b.step(5)
     grid, order, shape, ms = b.autotune(reps=2)
-    assert grid >= 0 and order in (0, 1) and shape in (0, 1, 2) and ms > 0
+    assert grid >= 0 and order in (0, 1) and shape in (0, 1, 2, 3) and ms > 0
     b.set_schedule(0, 0, 0)              # the reference runs used the default shape
     kms = b.time_kernels(2)
     assert kms[0] > 0
