@@ -11,10 +11,12 @@ element's two end-node contributions onto the nodes gives this trapezoid
 form, and the lumped normals of a closed wall sum to zero exactly.)
 F = sum_k F_k and M_EA = sum_k (x_k - x_EA) x F_k, both summed in node order.
 
-The wall polygon is the closed sequence of distinct wall nodes: the whole
-row j = 0 of an O-grid; on a C-grid the columns from the lower trailing-edge
-copy up to, not including, the upper copy (the same point), so that the
-neighbours k +- 1 run cyclically along the section.
+The wall polygon of a body is the closed sequence of its distinct wall
+nodes: the whole row j = 0 of an O-grid; on a C-grid the columns from the
+lower trailing-edge copy up to, not including, the upper copy (the same
+point), and on a twin O-grid the columns of the body's wall segment without
+its second junction copy, so that the neighbours k +- 1 run cyclically round
+the body.
 """
 
 from __future__ import annotations
@@ -24,15 +26,16 @@ import numpy as np
 from . import lattice as L
 
 
-def wall_polygon(grid):
-    """Columns of the distinct wall nodes in polygon order."""
-    cols = np.flatnonzero(grid.wall_col)
-    return cols[:-1] if grid.cgrid else cols
+def wall_polygon(grid, seg=0):
+    """Columns of the distinct wall nodes of wall segment `seg` (body `seg`)
+    in polygon order."""
+    i0, n, dup = grid.segments[seg]
+    return np.arange(i0, i0 + n - (1 if dup else 0))
 
 
-def wall_lumped_normals(grid, x, y):
+def wall_lumped_normals(grid, x, y, seg=0):
     """(n ds)_k for the wall polygon's nodes, from their cyclic neighbours."""
-    cols = wall_polygon(grid)
+    cols = wall_polygon(grid, seg)
     px, py = x[0, cols], y[0, cols]
     tx = 0.5 * (np.roll(px, -1) - np.roll(px, 1))
     ty = 0.5 * (np.roll(py, -1) - np.roll(py, 1))
@@ -57,10 +60,11 @@ def wall_stress(f0, g0, gamma, mu, Pr, dt):
     return -p - k * P1xx, -k * P1xy, -p - k * P1yy
 
 
-def wall_force(grid, f, g, x, y, gamma, mu, Pr, dt, ea_pos):
-    """Total (F_x, F_y, M_EA) on the wall; ea_pos is the physical position of
-    the elastic axis at the same time level as (x, y)."""
-    cols, nx, ny = wall_lumped_normals(grid, x, y)
+def wall_force(grid, f, g, x, y, gamma, mu, Pr, dt, ea_pos, seg=0):
+    """Total (F_x, F_y, M_EA) on the wall of body `seg`; ea_pos is the
+    physical position of the elastic axis (about which the moment is taken)
+    at the same time level as (x, y)."""
+    cols, nx, ny = wall_lumped_normals(grid, x, y, seg)
     sxx, sxy, syy = wall_stress(f[:, 0, cols], g[:, 0, cols], gamma, mu, Pr, dt)
     Fx_k = sxx * nx + sxy * ny
     Fy_k = sxy * nx + syy * ny

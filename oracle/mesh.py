@@ -20,6 +20,7 @@ import numpy as np
 TOPO_PERIODIC2 = 0
 TOPO_OGRID = 1
 TOPO_CGRID = 2
+TOPO_TWIN = 3
 
 
 class Grid:
@@ -29,33 +30,68 @@ class Grid:
     added to coordinates when a neighbour is taken across the periodic seam
     (zero for an O-grid's azimuthal seam, the period for a doubly periodic box).
 
-    C-grid: i is not periodic (columns 0 and ni-1 are the exit boundary) and
-    row j = 0 outside the wall columns is the wake cut, across which node
-    (i, -m) is node (ni - 1 - i, m).  Wall columns are [n_wake, ni - n_wake)
-    (both trailing-edge copies included); an O-grid's wall is the whole row.
+    Cut topologies (a C-grid, a twin O-grid): part of row j = 0 is a cut
+    across which node (i, -m) is node (mirror(i), m), mirror(i) = M - i
+    (mod ni on a twin O-grid).  The cut columns are the "primary" columns
+    cut_a < i < cut_b and their mirror images; every other column of row 0 is
+    a wall column.  C-grid: i is not periodic (columns 0 and ni - 1 are the
+    exit boundary), M = ni - 1, primary columns 0 .. n_wake - 1, and the wall
+    columns [n_wake, ni - n_wake) include both trailing-edge copies.  Twin
+    O-grid: i periodic, nA = ni - 2 n_wake - n_wall2, M = nA, primary columns
+    nA < i < nA + n_wake (one side of the slit); the walls are the columns
+    [0, nA] of the first body and [nA + n_wake, nA + n_wake + n_wall2] of the
+    second, each with its junction point twice.  An O-grid's wall is the
+    whole row.
+
+    ``segments``: the walls as (first column, columns, duplicated end), the
+    last column of a segment with a duplicated end being the same point as
+    its first; segment k is the wall of body k.
     """
 
-    def __init__(self, ni, nj, topo, shift_i=(0.0, 0.0), shift_j=(0.0, 0.0), n_wake=0):
+    def __init__(self, ni, nj, topo, shift_i=(0.0, 0.0), shift_j=(0.0, 0.0), n_wake=0,
+                 n_wall2=0):
         self.ni, self.nj, self.topo = int(ni), int(nj), int(topo)
         self.cgrid = self.topo == TOPO_CGRID
+        self.twin = self.topo == TOPO_TWIN
+        self.cut = self.cgrid or self.twin
         self.periodic_i = not self.cgrid
         self.periodic_j = self.topo == TOPO_PERIODIC2
-        self.n_wake = int(n_wake) if self.cgrid else 0
+        self.n_wake = int(n_wake) if self.cut else 0
         self.shift_i = np.asarray(shift_i, dtype=np.float64)
         self.shift_j = np.asarray(shift_j, dtype=np.float64)
         self.jj, self.ii = np.meshgrid(np.arange(self.nj), np.arange(self.ni),
                                        indexing="ij")
         cols = np.arange(self.ni)
         if self.cgrid:
-            self.wall_col = (cols >= self.n_wake) & (cols < self.ni - self.n_wake)
+            self.cut_a, self.cut_b, self.M = -1, self.n_wake, self.ni - 1
+            self.segments = [(self.n_wake, self.ni - 2 * self.n_wake, True)]
+        elif self.twin:
+            nB = int(n_wall2)
+            nA = self.ni - 2 * self.n_wake - nB
+            self.cut_a, self.cut_b, self.M = nA, nA + self.n_wake, nA
+            self.segments = [(0, nA + 1, True), (nA + self.n_wake, nB + 1, True)]
         else:
+            self.cut_a = self.cut_b = self.M = 0
+            self.segments = [] if self.periodic_j else [(0, self.ni, False)]
+        if self.cut:
+            prim = (cols > self.cut_a) & (cols < self.cut_b)
+            self.cut_col = prim | prim[self.mirror(cols)]
+            self.primary_cols = cols[prim]
+            self.wall_col = ~self.cut_col
+        else:
+            self.cut_col = np.zeros(self.ni, dtype=bool)
+            self.primary_cols = cols[:0]
             self.wall_col = np.full(self.ni, not self.periodic_j)
-        self.cut_col = self.cgrid & ~self.wall_col
+
+    def mirror(self, i):
+        """Column of the node across the cut from column i."""
+        m = self.M - np.asarray(i)
+        return m % self.ni if self.periodic_i else m
 
     @classmethod
     def from_mesh(cls, mesh):
         return cls(mesh.ni, mesh.nj, mesh.topo, mesh.shift_i, mesh.shift_j,
-                   getattr(mesh, "n_wake", 0))
+                   getattr(mesh, "n_wake", 0), getattr(mesh, "n_wall2", 0))
 
     # ---- neighbour access -------------------------------------------------
     def node_index(self, ii, jj):
@@ -65,9 +101,9 @@ class Grid:
         ii = np.asarray(ii)
         jj = np.asarray(jj)
         valid = np.ones(np.broadcast(ii, jj).shape, dtype=bool)
-        if self.cgrid:
+        if self.cut:
             below = jj < 0
-            ii = np.where(below, self.ni - 1 - ii, ii)
+            ii = np.where(below, self.M - ii, ii)
             jj = np.where(below, -jj, jj)
         if self.periodic_i:
             ii = ii % self.ni
@@ -123,15 +159,14 @@ class Grid:
         out[1:-1] = 0.5 * (F[2:] - F[:-2])
         out[0] = 0.5 * (-3.0 * F[0] + 4.0 * F[1] - F[2])
         out[-1] = 0.5 * (3.0 * F[-1] - 4.0 * F[-2] + F[-3])
-        if self.cgrid:
-            cut = self.cut_col
-            mirror = F[1, self.ni - 1 - np.arange(self.ni)]
-            out[0] = np.where(cut, 0.5 * (F[1] - mirror), out[0])
+        if self.cut:
+            mirror = F[1, self.mirror(np.arange(self.ni))]
+            out[0] = np.where(self.cut_col, 0.5 * (F[1] - mirror), out[0])
         return out
 
     def metrics(self, x, y):
         """(x_xi, x_eta, y_xi, y_eta) of a coordinate field, with seams shifted."""
-        if self.cgrid:
+        if self.cut:
             return self.d_i(x), self.d_j(x), self.d_i(y), self.d_j(y)
         xp, yp = self.neighbour_pos(x, y, 1, 0)
         xm, ym = self.neighbour_pos(x, y, -1, 0)
@@ -221,20 +256,52 @@ def rigid_displacement(X, Y, body, h, alpha):
     return (c - 1.0) * dx - s * dy, h + s * dx + (c - 1.0) * dy
 
 
+def master_of(bodies, k):
+    """Index of the body whose rigid motion body k follows: itself, or the
+    body it is linked to (a rigid assembly with one set of degrees of
+    freedom)."""
+    link = getattr(bodies[k], "link", -1)
+    return k if link < 0 else link
+
+
+def blend_factors(X, Y, bodies, walls=None):
+    """r_blend of every body (list of arrays).  Each body has its own region
+    of influence; the regions may not overlap (Sec. II.D, several bodies):
+    asserted here, node by node, as at most one body with r < 1."""
+    walls = walls if walls is not None else [None] * len(bodies)
+    r = [blend_factor(X, Y, b, w) for b, w in zip(bodies, walls)]
+    if len(r) > 1:
+        inside = np.sum([rk < 1.0 for rk in r], axis=0)
+        assert np.all(inside <= 1), "regions of influence overlap"
+    return r
+
+
 def deformed_positions(X, Y, bodies, states, wall=None, r=None):
     """x = r_blend X + (1 - r_blend) G'_x(X, t) (Sec. II.D), evaluated as
-    x = X + (1 - r_blend)(G'_x(X) - X), which is the same expression.
+    x = X + (1 - r_blend)(G'_x(X) - X), which is the same expression.  With
+    several bodies every body moves the nodes of its own region of influence:
+    x = X + sum_k (1 - r_k)(G'_k(X) - X), at most one term being non-zero at a
+    node; G'_k of a linked body is the rigid map (elastic axis and state) of
+    the body it is linked to.
 
-    ``states`` holds (h, alpha, hdot, alphadot) per body.  A single body per
-    mesh is supported; with no body x = X.  ``r``: the blending factor if
-    already known (it depends on the undeformed mesh only).
+    ``states`` holds (h, alpha, hdot, alphadot) per body.  With no body x = X.
+    ``wall``: the wall polygon (px, py) of the body (one body) or the list of
+    polygons (one per body), used by distance blending.  ``r``: the blending
+    factor(s) if already known (they depend on the undeformed mesh only).
     """
     if not bodies:
         return X.copy(), Y.copy()
-    assert len(bodies) == 1, "one moving body per mesh"
-    body = bodies[0]
-    h, alpha = states[0][0], states[0][1]
+    if wall is not None and len(bodies) == 1 and not isinstance(wall, list):
+        wall = [wall]
     if r is None:
-        r = blend_factor(X, Y, body, wall)
-    ux, uy = rigid_displacement(X, Y, body, h, alpha)
-    return X + (1.0 - r) * ux, Y + (1.0 - r) * uy
+        r = blend_factors(X, Y, bodies, wall)
+    elif not isinstance(r, list):
+        r = [r]
+    dx = np.zeros_like(X, dtype=np.float64)
+    dy = np.zeros_like(Y, dtype=np.float64)
+    for k in range(len(bodies)):
+        m = master_of(bodies, k)
+        ux, uy = rigid_displacement(X, Y, bodies[m], states[m][0], states[m][1])
+        dx = dx + (1.0 - r[k]) * ux
+        dy = dy + (1.0 - r[k]) * uy
+    return X + dx, Y + dy

@@ -18,13 +18,21 @@ start of step n the load F^n of the populations f^n is known):
              prints it for dt = 1)
  5. stream   ALE departure points with g and V_G at t^{n+1}; interpolation
  6. boundary far-field equilibria; Grad wall populations for the missing ones
- 7. C-grid: the duplicated nodes of row 0 are made single-valued (reading:
-    the paper's unstructured meshes have no duplicated nodes).  The two
-    trailing-edge copies each see the cells of one side only, so population
-    by population the trailing edge takes the streamed value of the copy that
-    found its departure point, and the mean of the two copies where both or
-    neither did; the upper copy of every cut node takes the lower copy's
-    values (the two are mirror-image evaluations of the same update).
+ 7. cut topologies (C-grid, twin O-grid): the duplicated nodes of row 0 are
+    made single-valued (reading: the paper's unstructured meshes have no
+    duplicated nodes).  The two copies of a trailing edge or of a junction of
+    the slit with a body each see the cells of one side only, so population
+    by population the point takes the streamed value of the copy that found
+    its departure point, and the mean of the two copies where both or neither
+    did; the mirror copy of every cut node takes the primary copy's values
+    (the two are mirror-image evaluations of the same update).
+
+Several bodies (Sec. II.D and the tandem-cylinder cases of Sec. V): each has
+its own wall segment (body k <-> segment k of the mesh), its own region of
+influence and its own load.  A body linked to another (a rigid assembly on
+one spring, as the linked tandem cylinders) has no equation of its own: it
+moves with that body, and its load joins that body's equation (forces
+summed, moments about that body's elastic axis).
 """
 
 from __future__ import annotations
@@ -35,7 +43,7 @@ from . import lattice as L
 from . import body as B
 from .boundary import farfield_bc, wall_grad_bc
 from .forces import wall_force
-from .mesh import Grid, deformed_positions
+from .mesh import Grid, deformed_positions, master_of
 from .stream import stream
 
 
@@ -55,17 +63,29 @@ def correction_force(grid, f, g, x, y, gamma, mu, Pr, dt):
 
 
 def merge_cut_row(grid, f_new, g_new, missing):
-    """Single-valued trailing edge and cut nodes of a C-grid (step 7)."""
-    nw, ni = grid.n_wake, grid.ni
-    a, b = nw, ni - 1 - nw                    # lower and upper trailing-edge copies
-    ma, mb = missing[:, 0, a], missing[:, 0, b]
-    lower = np.arange(nw)
+    """Single-valued duplicated points of row 0 (step 7)."""
+    for (i0, n, dup) in grid.segments:
+        if not dup:
+            continue
+        a, b = i0, i0 + n - 1                 # the two copies of one point
+        ma, mb = missing[:, 0, a], missing[:, 0, b]
+        for F in (f_new, g_new):
+            va, vb = F[:, 0, a].copy(), F[:, 0, b].copy()
+            v = np.where(ma & ~mb, vb, np.where(mb & ~ma, va, 0.5 * (va + vb)))
+            F[:, 0, a] = v
+            F[:, 0, b] = v
+    prim = grid.primary_cols
     for F in (f_new, g_new):
-        va, vb = F[:, 0, a].copy(), F[:, 0, b].copy()
-        v = np.where(ma & ~mb, vb, np.where(mb & ~ma, va, 0.5 * (va + vb)))
-        F[:, 0, a] = v
-        F[:, 0, b] = v
-        F[:, 0, ni - 1 - lower] = F[:, 0, lower]
+        F[:, 0, grid.mirror(prim)] = F[:, 0, prim]
+
+
+def junction_columns(grid):
+    """Columns of row 0 that are one copy of a duplicated wall point."""
+    out = []
+    for (i0, n, dup) in grid.segments:
+        if dup:
+            out += [i0, i0 + n - 1]
+    return out
 
 
 class OracleSolver:
@@ -81,8 +101,14 @@ class OracleSolver:
         self.bodies = list(bodies)
         self.correction = correction
         self.n = 0
+        for k, b in enumerate(self.bodies):
+            link = getattr(b, "link", -1)
+            assert link < k and (link < 0 or master_of(self.bodies, link) == link), \
+                "a body links to an earlier body that is not linked itself"
         self.states = [B.initial_state(b) for b in self.bodies]
-        self.history = []
+        self.states = [self.states[master_of(self.bodies, k)] for k in range(len(self.bodies))]
+        self.history = []                     # body 0
+        self.histories = [[] for _ in self.bodies]
         shape = self.X.shape
         if rho is None:
             rho = np.full(shape, fluid.rho_inf)
@@ -90,45 +116,76 @@ class OracleSolver:
             uy = np.full(shape, fluid.u_inf[1])
             T = np.full(shape, fluid.T_inf)
         self.f, self.g = L.equilibrium_populations(rho, ux, uy, T, fluid.gamma)
-        self.has_wall = mesh.topo in (1, 2)
-        # undeformed wall polygon (distance-field blending)
-        self.wall = None
+        self.has_wall = mesh.topo in (1, 2, 3)
+        if self.bodies:
+            assert len(self.bodies) <= max(1, len(self.grid.segments)), \
+                "one wall segment per body"
+        # undeformed wall polygons (distance-field blending), one per body
+        self.walls = None
         if self.has_wall:
             from .forces import wall_polygon
-            cols = wall_polygon(self.grid)
-            self.wall = (self.X[0, cols], self.Y[0, cols])
+            self.walls = []
+            for k in range(len(self.grid.segments)):
+                cols = wall_polygon(self.grid, k)
+                self.walls.append((self.X[0, cols], self.Y[0, cols]))
+        self.wall = self.walls[0] if self.walls else None
         self._r_cache = None
 
     # ---- geometry ---------------------------------------------------------
     def positions(self, states):
         if self.bodies and self._r_cache is None:
-            from .mesh import blend_factor
-            self._r_cache = blend_factor(self.X, self.Y, self.bodies[0], self.wall)
-        return deformed_positions(self.X, self.Y, self.bodies, states, self.wall, self._r_cache)
+            from .mesh import blend_factors
+            walls = self.walls[:len(self.bodies)] if self.walls else None
+            self._r_cache = blend_factors(self.X, self.Y, self.bodies, walls)
+        return deformed_positions(self.X, self.Y, self.bodies, states, None, self._r_cache)
 
-    def ea_position(self, states):
-        b = self.bodies[0]
-        return (b.ea[0], b.ea[1] + states[0][0])
+    def ea_position(self, states, k=0):
+        """Physical elastic axis about which body k's moment is taken: the
+        axis of the body it moves with."""
+        m = master_of(self.bodies, k)
+        b = self.bodies[m]
+        return (b.ea[0], b.ea[1] + states[m][0])
 
     # ---- step pieces --------------------------------------------------------
-    def forces(self):
+    def body_forces(self):
+        """(F_x, F_y, M) on the wall of every body at the current level."""
         if not (self.has_wall and self.bodies):
-            return (0.0, 0.0, 0.0)
+            return [(0.0, 0.0, 0.0) for _ in self.bodies]
         fl = self.fluid
         x, y = self.positions(self.states)
-        return wall_force(self.grid, self.f, self.g, x, y, fl.gamma, fl.mu, fl.Pr,
-                          fl.dt, self.ea_position(self.states))
+        return [wall_force(self.grid, self.f, self.g, x, y, fl.gamma, fl.mu, fl.Pr,
+                           fl.dt, self.ea_position(self.states, k), seg=k)
+                for k in range(len(self.bodies))]
+
+    def forces(self):
+        if not self.bodies:
+            return (0.0, 0.0, 0.0)
+        return self.body_forces()[0]
 
     def step(self):
         fl = self.fluid
         dt = fl.dt
         # 1-2: load at t^n, structure to t^{n+1}
-        F = self.forces()
-        new_states = [B.advance(b, s, F[1], F[2], (self.n + 1) * dt, dt)
-                      for b, s in zip(self.bodies, self.states)]
-        if self.bodies:
-            s = self.states[0]
-            self.history.append((self.n, F[0], F[1], F[2], s[0], s[1]))
+        Fb = self.body_forces()
+        nb = len(self.bodies)
+        new_states = [None] * nb
+        for m in range(nb):
+            if master_of(self.bodies, m) != m:
+                continue
+            Fy = 0.0
+            Mz = 0.0
+            for k in range(nb):                      # own load, then linked bodies'
+                if master_of(self.bodies, k) == m:
+                    Fy += Fb[k][1]
+                    Mz += Fb[k][2]
+            new_states[m] = B.advance(self.bodies[m], self.states[m], Fy, Mz,
+                                      (self.n + 1) * dt, dt)
+        for k in range(nb):
+            new_states[k] = new_states[master_of(self.bodies, k)]
+            s = self.states[k]
+            self.histories[k].append((self.n, Fb[k][0], Fb[k][1], Fb[k][2], s[0], s[1]))
+        if nb:
+            self.history = self.histories[0]
         # 3: mesh
         x0, y0 = self.positions(self.states)
         x1, y1 = self.positions(new_states)
@@ -141,10 +198,10 @@ class OracleSolver:
         else:
             Fx = np.zeros_like(self.X)
             Fy = np.zeros_like(self.X)
-        if self.grid.cgrid:
-            # the trailing edge collides once: its two copies' one-sided nested
+        if self.grid.cut:
+            # a duplicated point collides once: its two copies' one-sided nested
             # derivatives differ at the sharp edge, so the correction is dropped there
-            te = [self.grid.n_wake, self.grid.ni - 1 - self.grid.n_wake]
+            te = junction_columns(self.grid)
             Fx[0, te] = 0.0
             Fy[0, te] = 0.0
         fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt, Fx, Fy)
@@ -157,7 +214,7 @@ class OracleSolver:
                         fl.rho_inf, fl.u_inf, fl.T_inf)
             wall_grad_bc(self.grid, self.X, self.Y, x1, y1, VGx, VGy, f_new, g_new,
                          missing, self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt)
-        if self.grid.cgrid:
+        if self.grid.cut:
             merge_cut_row(self.grid, f_new, g_new, missing)
         self.last_missing = missing
         self.f, self.g = f_new, g_new

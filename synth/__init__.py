@@ -13,6 +13,7 @@ from .meshes import (  # noqa: F401
     cartesian_mesh,
     ogrid_mesh,
     cgrid_mesh,
+    twin_mesh,
     geometric_ratio,
 )
 from .configs import (  # noqa: F401
@@ -25,4 +26,6 @@ from .configs import (  # noqa: F401
     gaussian_pulse_fields,
     airfoil_flutter_case,
     small_airfoil_case,
+    tandem_cylinders_case,
+    small_tandem_case,
 )

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .meshes import MeshSpec, cgrid_mesh, ogrid_mesh, periodic_sine_mesh
+from .meshes import MeshSpec, cgrid_mesh, ogrid_mesh, periodic_sine_mesh, twin_mesh
 
 DOF_PRESCRIBED = 0
 DOF_HEAVE = 1
@@ -57,6 +57,7 @@ class BodyParams:
     pitch_freq: float = 0.0
     release_time: float = 0.0    # > 0: prescribed motion until then, free afterwards
     blend_mode: int = 0          # 0: radial from `center`; 1: distance to the wall
+    link: int = -1               # >= 0: moves rigidly with that (earlier) body, no ODE of its own
 
 
 @dataclass
@@ -341,6 +342,102 @@ def small_airfoil_case(n_wake: int = 16, n_af: int = 64, nj: int = 32, chord: fl
                                 T_inf=T_inf, mstar=mstar, alpha0_deg=alpha0_deg,
                                 blend_chords=blend_chords, steps=steps,
                                 name=f"small_airfoil_{2 * n_wake + n_af}x{nj}")
+
+
+def smallest_metric_scale(mesh: MeshSpec, rows: int = 4) -> float:
+    """Smallest singular value of the index-space Jacobian d(x, y)/d(i, j)
+    (centred in i, one-sided into the mesh from the wall row) over the first
+    rows of a wall-bounded periodic mesh: the shortest physical step that one
+    index step can take there.  A time step of a third of it keeps every
+    departure point of a node within half a cell of it in index space."""
+    X, Y = mesh.X[:rows + 2], mesh.Y[:rows + 2]
+    xi = 0.5 * (np.roll(X, -1, 1) - np.roll(X, 1, 1))[:rows]
+    yi = 0.5 * (np.roll(Y, -1, 1) - np.roll(Y, 1, 1))[:rows]
+    xe = np.empty_like(xi)
+    ye = np.empty_like(yi)
+    xe[0] = -1.5 * X[0] + 2.0 * X[1] - 0.5 * X[2]
+    ye[0] = -1.5 * Y[0] + 2.0 * Y[1] - 0.5 * Y[2]
+    xe[1:] = 0.5 * (X[2:rows + 1] - X[:rows - 1])
+    ye[1:] = 0.5 * (Y[2:rows + 1] - Y[:rows - 1])
+    a = xi * xi + yi * yi
+    c = xe * xe + ye * ye
+    b = xi * xe + yi * ye
+    lam_min = 0.5 * (a + c) - np.sqrt(0.25 * (a - c) ** 2 + b * b)
+    return float(np.sqrt(np.min(lam_min)))
+
+
+def tandem_start_fields(mesh: MeshSpec, D: float, centers, U: float, rho0: float, T0: float,
+                        delta: float):
+    """Uniform stream along +x multiplied by tanh(d / delta), d the distance to
+    the nearer cylinder surface; uniform rho and T."""
+    d = np.min([np.hypot(mesh.X - cx, mesh.Y - cy) for (cx, cy) in centers], axis=0) - 0.5 * D
+    ux = U * np.tanh(np.maximum(d, 0.0) / delta)
+    shape = mesh.X.shape
+    return np.full(shape, float(rho0)), ux, np.zeros(shape), np.full(shape, float(T0))
+
+
+def tandem_cylinders_case(linked: bool = False, n_wall: int = 512, n_slit: int = 640,
+                          nj: int = 320, D: float = 200.0, L_D: float = 5.0,
+                          first_cell: float = 1.0, far_D: float = 30.0, Ma: float = 0.1,
+                          Re: float = 1000.0, T_inf: float = 1.0 / 3.0, gamma: float = 1.4,
+                          Pr: float = 0.71, mstar: float = 4.0, ustar: float = 6.0,
+                          rigid_gap_D: float = 0.25, blend_gap_D: float = 2.0,
+                          h0_frac: float = 0.0, steps: int = 20000, storage: int = 0,
+                          name: str | None = None) -> Case:
+    """Two cylinders of diameter D in tandem (centres L_D * D apart on the x
+    axis, the stream along +x) on a twin O-grid.
+
+    Independent (linked=False, the 1+1DOF case): each cylinder is a 1DOF
+    cross-flow oscillator with m = m* rho pi D^2 / 4 and f_N = U / (U* D).
+    Linked (the 1DOF case of two rigidly connected cylinders on one spring):
+    the downstream cylinder is linked to the upstream one, whose equation
+    carries the assembly, m = m* rho 2 pi D^2 / 4 (reading: the mass ratio of
+    the assembly to the fluid both cylinders displace), and the sum of the
+    two loads.  Regions of influence: rigid to rigid_gap_D * D and blended to
+    blend_gap_D * D from each surface (the paper's 50 and 400 lattice units at
+    D = 200), capped at half the centre distance so they do not overlap.
+    dt is a third of the smallest index-step length near the walls."""
+    L = L_D * D
+    mesh = twin_mesh(n_wall, n_slit, nj, D, L, first_cell, far_D)
+    U = Ma * sound_speed(gamma, T_inf)
+    rho = 1.0
+    mu = rho * U * D / Re
+    dt = smallest_metric_scale(mesh) / 3.0
+    fluid = FluidParams(gamma=gamma, Pr=Pr, mu=mu, rho_inf=rho, T_inf=T_inf,
+                        u_inf=(U, 0.0), dt=dt, storage=storage)
+    R = 0.5 * D
+    r_rigid = R + rigid_gap_D * D
+    r_blend = min(R + blend_gap_D * D, 0.5 * L)
+    centers = ((-0.5 * L, 0.0), (0.5 * L, 0.0))
+    fN = U / (ustar * D)
+    m1 = mstar * rho * math.pi * D * D / 4.0
+    bodies = []
+    for k, c in enumerate(centers):
+        m = m1 * (2.0 if linked else 1.0)
+        b = BodyParams(dof=DOF_HEAVE, m=m, k_h=m * (2.0 * math.pi * fN) ** 2, center=c, ea=c,
+                       r_rigid=r_rigid, r_blend=r_blend, h0=h0_frac * D)
+        if linked and k == 1:
+            b = replace(b, link=0, m=1.0, k_h=0.0, h0=0.0)
+        bodies.append(b)
+    r, ux, uy, T = tandem_start_fields(mesh, D, centers, U, rho, T_inf,
+                                       start_layer_width(D, first_cell))
+    kind = "linked" if linked else "independent"
+    return Case(name or f"tandem_{kind}_{mesh.ni}x{nj}", mesh, fluid, bodies, r, ux, uy, T,
+                steps, info={"D": D, "L": L, "U": U, "Ma": Ma, "Re": Re, "mstar": mstar,
+                             "ustar": ustar, "centers": centers})
+
+
+def small_tandem_case(linked: bool = False, n_wall: int = 48, n_slit: int = 30, nj: int = 40,
+                      D: float = 30.0, L_D: float = 3.0, first_cell: float = 0.5,
+                      far_D: float = 8.0, Ma: float = 0.2, Re: float = 100.0,
+                      mstar: float = 2.0, ustar: float = 4.0, h0_frac: float = 0.01,
+                      steps: int = 100) -> Case:
+    """A small tandem-cylinder twin O-grid case the oracle can run for many steps."""
+    return tandem_cylinders_case(linked=linked, n_wall=n_wall, n_slit=n_slit, nj=nj, D=D,
+                                 L_D=L_D, first_cell=first_cell, far_D=far_D, Ma=Ma, Re=Re,
+                                 mstar=mstar, ustar=ustar, rigid_gap_D=0.1, blend_gap_D=0.5,
+                                 h0_frac=h0_frac, steps=steps,
+                                 name=f"small_tandem_{2 * n_wall + 2 * n_slit}x{nj}")
 
 
 def with_fluid(case: Case, **kw) -> Case:

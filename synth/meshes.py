@@ -23,6 +23,14 @@ Topologies
     twice (i = n_wake and i = ni - 1 - n_wake) and every cut node (i, 0)
     coincides with (ni - 1 - i, 0).  Row j = 0 between the trailing-edge
     copies is the wall; row j = nj - 1 and columns i = 0, ni - 1 are far field.
+``TOPO_TWIN`` (3)
+    O-grid around two bodies joined by a slit (a cut of zero thickness):
+    periodic in i, row j = nj - 1 far field.  Row 0 runs round the first
+    body (columns 0 .. nA, both ends the same junction point), along one side
+    of the slit (``n_wake`` cells), round the second body (``n_wall2`` cells,
+    both ends the other junction point) and back along the other side of the
+    slit, with ni = nA + 2 n_wake + n_wall2.  Across the slit node (i, -m) is
+    node ((nA - i) mod ni, m).
 """
 
 from __future__ import annotations
@@ -34,6 +42,7 @@ import numpy as np
 TOPO_PERIODIC2 = 0
 TOPO_OGRID = 1
 TOPO_CGRID = 2
+TOPO_TWIN = 3
 
 
 @dataclass
@@ -46,7 +55,8 @@ class MeshSpec:
     shift_i: tuple = (0.0, 0.0)
     shift_j: tuple = (0.0, 0.0)
     info: dict = field(default_factory=dict)
-    n_wake: int = 0            # C-grid: nodes on each side of the wake cut
+    n_wake: int = 0            # C-grid: nodes on each side of the wake cut; twin O-grid: slit cells
+    n_wall2: int = 0           # twin O-grid: wall cells round the second body
 
     @property
     def n_nodes(self) -> int:
@@ -236,3 +246,117 @@ def cgrid_mesh(n_wake: int, n_af: int, nj: int, chord: float, first_cell: float,
                           "thickness": t, "first_cell": first_cell,
                           "far_chords": far_chords, "x_o": x_o, "wake_ratio": q,
                           "origin": tuple(origin)})
+
+
+def _bipolar(w, a):
+    """Bipolar coordinates w = sigma + i tau -> z = a (1 + e^{iw}) / (1 - e^{iw})
+    (x = a sinh tau / (cosh tau - cos sigma), y = a sin sigma / (cosh tau -
+    cos sigma)): tau = +-tau_0 are circles round the foci (+-a, 0), sigma = +-pi
+    the segment between them, and w = 0 is the point at infinity."""
+    e = np.exp(1j * w)
+    return a * (1.0 + e) / (1.0 - e)
+
+
+def twin_mesh(n_wall: int, n_slit: int, nj: int, diameter: float, spacing: float,
+              first_cell: float, far_diameters: float, samples: int = 6000) -> MeshSpec:
+    """Twin O-grid round two circles of the given diameter whose centres lie
+    ``spacing`` apart on the x axis (at -+ spacing / 2), joined by a slit
+    along the x axis between them.
+
+    Bipolar coordinates with the circles as tau = -+tau_0 map the rectangle
+    |sigma| <= pi, |tau| <= tau_0 conformally onto the plane outside the two
+    circles and the slit (the edges sigma = +-pi are the slit's two sides and
+    the rectangle's corners the two junctions of each side with the circles);
+    its centre is the point at infinity.  Row j = 0 holds ``n_wall`` equal
+    arcs on each circle and ``n_slit`` equal steps along the slit; column i
+    follows the straight line from its wall point w_b to the centre,
+    w = w_b (eps / |w_b|)^lambda with |w| = eps the far boundary (a near-circle
+    of radius far_diameters * diameter), and its nodes are placed by arc
+    length, geometric from ``first_cell``.  Straight lines to the centre of a
+    rectangle do not cross, so no cell folds; cells next to the junctions are
+    skewed (the fluid angle there is 90 degrees).  The mesh is exactly
+    symmetric about both axes (columns i and (nA - i) mod ni mirror in y,
+    i and (nA + n_slit + n_wall - i) mod ni in x).
+    """
+    if n_wall % 2 or n_wall < 8 or n_slit < 2:
+        raise ValueError("n_wall must be even and >= 8, n_slit >= 2")
+    R = 0.5 * diameter
+    d = 0.5 * spacing
+    if not d > R:
+        raise ValueError("the circles overlap")
+    a = float(np.sqrt(d * d - R * R))
+    tau0 = float(np.arccosh(d / R))
+    nA = nB = n_wall
+    s = n_slit
+    ni = nA + 2 * s + nB
+    zb = np.empty(ni, dtype=complex)
+    wb = np.empty(ni, dtype=complex)
+
+    def w_of(z, tau):
+        return np.angle((z - a) / (z + a)) + 1j * tau
+
+    th = -2.0 * np.pi * np.arange(nA + 1) / nA           # clockwise from the junction
+    zA = -d + R * np.cos(th) + 1j * R * np.sin(th)
+    zb[:nA + 1] = zA
+    wb[:nA + 1] = w_of(zA, -tau0)
+    xs = -(d - R) + (spacing - diameter) * np.arange(s + 1) / s
+    zb[nA:nA + s + 1] = xs
+    wb[nA:nA + s + 1] = np.pi + 2j * np.arctanh(xs / a)
+    th = np.pi - 2.0 * np.pi * np.arange(nB + 1) / nB
+    zB = d + R * np.cos(th) + 1j * R * np.sin(th)
+    zb[nA + s:nA + s + nB + 1] = zB
+    wb[nA + s:nA + s + nB + 1] = w_of(zB, tau0)
+    low = np.arange(nA + s + nB, ni)
+    xl = xs[::-1][:-1]
+    zb[low] = xl
+    wb[low] = -np.pi + 2j * np.arctanh(xl / a)
+    for i, wc in ((0, -np.pi - 1j * tau0), (nA, np.pi - 1j * tau0),
+                  (nA + s, np.pi + 1j * tau0), (nA + s + nB, -np.pi + 1j * tau0)):
+        wb[i] = wc
+    # points on the axes: the far sides of the circles and the slit's middle
+    for i, x in ((nA // 2, -d - R), (nA + s + nB // 2, d + R)):
+        zb[i] = x
+        wb[i] = 1j * wb[i].imag
+    if s % 2 == 0:
+        for i in (nA + s // 2, nA + s + nB + s // 2):
+            zb[i] = 0.0
+            wb[i] = wb[i].real
+    eps = 2.0 * a / (far_diameters * diameter)
+    lam = (np.arange(samples + 1) / samples) ** 2.5
+    shrink = eps / np.abs(wb)
+    W = wb[:, None] * shrink[:, None] ** lam[None, :]
+    Z = _bipolar(W, a)
+    Z[:, 0] = zb
+    S = np.concatenate([np.zeros((ni, 1)), np.cumsum(np.abs(np.diff(Z, axis=1)), axis=1)], axis=1)
+    X = np.empty((nj, ni))
+    Y = np.empty((nj, ni))
+    jj = np.arange(nj, dtype=np.float64)
+    for i in range(ni):
+        q = geometric_ratio(nj - 1, first_cell, S[i, -1])
+        r = first_cell * jj if q == 1.0 else first_cell * (q ** jj - 1.0) / (q - 1.0)
+        r[-1] = S[i, -1]
+        li = np.interp(r, S[i], lam)
+        z = _bipolar(wb[i] * shrink[i] ** li, a)
+        z[0] = zb[i]
+        X[:, i] = z.real
+        Y[:, i] = z.imag
+    # exact symmetries: mirror in y (source sigma > 0), then in x (source tau < 0)
+    cols = np.arange(ni)
+    my = (nA - cols) % ni
+    up = wb.real > 0
+    X[:, my[up]] = X[:, up]
+    Y[:, my[up]] = -Y[:, up]
+    Y[:, wb.real == 0] = 0.0
+    mx = (nA + s + nB - cols) % ni
+    left = wb.imag < 0
+    X[:, mx[left]] = -X[:, left]
+    Y[:, mx[left]] = Y[:, left]
+    X[:, wb.imag == 0] = 0.0
+    Y[0, nA:nA + s + 1] = 0.0
+    Y[0, low] = 0.0
+    Y[0, 0] = 0.0
+    return MeshSpec(ni, nj, TOPO_TWIN, X, Y, n_wake=s, n_wall2=nB,
+                    info={"kind": "twin", "diameter": diameter, "spacing": spacing,
+                          "first_cell": first_cell, "far_diameters": far_diameters,
+                          "n_wall": n_wall, "n_slit": s, "centers": ((-d, 0.0), (d, 0.0)),
+                          "focus": a, "tau0": tau0})
