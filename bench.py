@@ -70,6 +70,10 @@ WORKLOADS = {
                                "m* 60, alpha0 1 deg",
     "batched_sweep_64": "64 independent 1DOF cylinder instances, n_r ~ U[128,384], "
                         "n_theta = 2 n_r, seed 0, one launch per kernel per step",
+    "tandem_independent_2304x320": "twin O-grid, two cylinders in tandem (L/D 5, D 200) each "
+                                   "on its own spring (1+1DOF), Ma 0.1, Re 1000, m* 4, U* 6",
+    "tandem_linked_2304x320": "twin O-grid, two rigidly linked cylinders in tandem (L/D 5, "
+                              "D 200) on one spring (1DOF), Ma 0.1, Re 1000, m* 4, U* 6",
 }
 
 
@@ -82,6 +86,10 @@ def workload_case(name: str, storage: int):
         return c
     if name == "airfoil_flutter_768x256":
         return synth.airfoil_flutter_case(storage=storage)
+    if name == "tandem_independent_2304x320":
+        return synth.tandem_cylinders_case(linked=False, h0_frac=0.01, storage=storage)
+    if name == "tandem_linked_2304x320":
+        return synth.tandem_cylinders_case(linked=True, h0_frac=0.01, storage=storage)
     raise SystemExit(f"unknown workload {name}")
 
 

@@ -95,8 +95,26 @@ typedef struct {
  *              duplicated nodes are kept single-valued: the two trailing-edge
  *              copies merge (per population, the streamed value of the copy
  *              whose cells hold the departure point, else their mean) and the
- *              upper copy of each cut node takes the lower copy's state.   */
-typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1, FSI_TOPO_CGRID = 2 } fsi_topo;
+ *              upper copy of each cut node takes the lower copy's state.
+ *   TWIN:      O-grid round two bodies joined by a slit (a cut of zero
+ *              thickness; for several bodies in one flow, Sec. II.D and the
+ *              tandem cases of Sec. V).  i is periodic (no shift); row
+ *              nj - 1 is far field.  Row 0 runs round the first body (columns
+ *              0 .. nA, both ends being the same junction point), along one
+ *              side of the slit (n_wake cells), round the second body
+ *              (n_wall2 cells: columns nA + n_wake .. nA + n_wake + n_wall2,
+ *              both ends the other junction point) and back along the other
+ *              side of the slit; nA = ni - 2 n_wake - n_wall2.  Node (i, -m)
+ *              is node ((nA - i) mod ni, m), and (i, 0) must coincide with
+ *              ((nA - i) mod ni, 0) for nA <= i <= nA + n_wake.  Wall column
+ *              segment 0 belongs to body 0, segment 1 to body 1 (nbodies must
+ *              be 2).  Junction copies merge and slit copies are kept
+ *              single-valued as on a C-grid.                               */
+typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1, FSI_TOPO_CGRID = 2,
+               FSI_TOPO_TWIN = 3 } fsi_topo;
+
+/* Most bodies one mesh carries (TWIN: exactly this many). */
+#define FSI_MAX_BODIES 2
 
 typedef struct {
     int ni, nj;             /* nodes in i (fast) and j; ni >= 8, nj >= 8 */
@@ -104,7 +122,8 @@ typedef struct {
     const double *X;        /* host, [nj][ni][2] undeformed coordinates, FP64; copied */
     double shift_i[2];      /* PERIODIC2 only */
     double shift_j[2];      /* PERIODIC2 only */
-    int n_wake;             /* CGRID only: cut nodes on each side (>= 2) */
+    int n_wake;             /* CGRID: cut nodes on each side (>= 2); TWIN: slit cells (>= 2) */
+    int n_wall2;            /* TWIN only: wall cells round the second body (>= 8) */
 } fsi_mesh_desc;
 
 /* Rigid-body degrees of freedom (Sec. IV). */
@@ -125,7 +144,17 @@ enum { FSI_DOF_PRESCRIBED = 0, FSI_DOF_HEAVE = 1, FSI_DOF_PITCH_PLUNGE = 2,
  *   release_time > 0 (FSI_DOF_HEAVE, FSI_DOF_PITCH_PLUNGE): the body follows
  *     the prescribed motion above while t^{n+1} <= release_time and its ODE
  *     afterwards, starting from the state reached (the forced-then-free
- *     protocol of the paper's airfoil case, Sec. V). */
+ *     protocol of the paper's airfoil case, Sec. V).
+ *   Several bodies (Sec. II.D): each moves the nodes of its own region of
+ *     influence; the regions may not overlap (FSI_E_ARG names a node that
+ *     lies in two).  Distance blending measures from the body's own wall.
+ *   link >= 0 (an earlier body that is not linked itself): the body is part
+ *     of a rigid assembly with that body (the paper's linked tandem
+ *     cylinders): it has no equation of its own, moves with that body's
+ *     rigid map (its elastic axis and state; this body's dof, masses,
+ *     stiffnesses, ea, initial state and motion are ignored), and its load
+ *     joins that body's equation (forces summed, moment about that body's
+ *     elastic axis).  Its history reports its own load.  -1: own equation. */
 typedef struct {
     int dof;
     double m, S_a, I_a, k_h, k_a;
@@ -135,12 +164,14 @@ typedef struct {
     double heave_amp, heave_freq, pitch_amp, pitch_freq;
     double release_time;     /* see above; 0: no forced start */
     int blend_mode;          /* 0 radial, 1 distance to the wall */
+    int link;                /* -1, or the body this one moves with */
 } fsi_body_desc;
 
-/* Create a context for one structured mesh with at most one moving body
- * (nbodies = 0 or 1).  `hip_stream` is a hipStream_t (NULL = default stream).
- * Validates the mesh (FSI_E_MESH) and precomputes the static boundary
- * geometry on the host.  No device memory is allocated. */
+/* Create a context for one structured mesh with its moving bodies: 0 or 1 on
+ * a PERIODIC2, OGRID or CGRID mesh, FSI_MAX_BODIES on a TWIN mesh (body k
+ * owns wall segment k).  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  Validates the mesh (FSI_E_MESH) and precomputes the static
+ * boundary geometry on the host.  No device memory is allocated. */
 fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
                       const fsi_body_desc *bodies, int nbodies, void *hip_stream,
                       fsi_ctx **out);
@@ -207,17 +238,18 @@ fsi_status fsi_load(fsi_ctx *ctx, const void *host_buf, size_t bytes);
 fsi_status fsi_time_kernels(fsi_ctx *ctx, int reps, double out_ms[4]);
 
 /* ---------------------------------------------------------------------------
- * Batches: many independent instances (each one mesh + at most one body, of
- * any sizes) advanced together.  Every step is ONE launch of each kernel over
+ * Batches: many independent instances (each one mesh with its bodies, of any
+ * sizes) advanced together.  Every step is ONE launch of each kernel over
  * the concatenated work items of all instances, captured in one HIP graph.
  * Instances keep their own parameters, state, history and error word.
  * ------------------------------------------------------------------------- */
 typedef struct fsi_batch fsi_batch;
 
-/* Create a batch of n instances: fluids[n], meshes[n]; bodies[k] is used for
- * instance k when nbodies[k] == 1 (nbodies may be NULL: no bodies).  All
- * instances must use the same storage precision.  Validation as fsi_create;
- * the failing instance is named in fsi_batch_last_error(). */
+/* Create a batch of n instances: fluids[n], meshes[n]; instance k has
+ * nbodies[k] bodies (nbodies may be NULL: no bodies), stored back to back in
+ * `bodies` in instance order.  All instances must use the same storage
+ * precision.  Validation as fsi_create; the failing instance is named in
+ * fsi_batch_last_error(). */
 fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mesh_desc *meshes,
                             const fsi_body_desc *bodies, const int *nbodies, void *hip_stream,
                             fsi_batch **out);
@@ -231,7 +263,7 @@ fsi_status fsi_batch_init_equilibrium(fsi_batch *b, int k, const double *rho, co
  * `order` of the work items (0: instance after instance, 1: instances by
  * decreasing size) and the tile `shape` of the arrival nodes one workgroup owns
  * (0: 32 x 16, 1: 64 x 8, 2: 16 x 32, 3: 16 x 16 with 256-thread workgroups; a
- * batch holding a C-grid instance uses 0).  Invalidates the captured graph.
+ * batch holding a C-grid or TWIN instance uses 0).  Invalidates the captured graph.
  * FSI_E_ARG on values out of range. */
 fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape);
 /* Time candidate schedules on the current state and keep the fastest: after
@@ -243,8 +275,9 @@ fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]);
 fsi_status fsi_batch_step(fsi_batch *b, int nsteps);
 fsi_status fsi_batch_synchronize(fsi_batch *b);
 /* Per-instance queries, as the single-instance calls. */
-fsi_status fsi_batch_get_forces(fsi_batch *b, int k, int64_t first, int count, double *out);
-fsi_status fsi_batch_get_body_state(fsi_batch *b, int k, double out[4]);
+fsi_status fsi_batch_get_forces(fsi_batch *b, int k, int body, int64_t first, int count,
+                                double *out);
+fsi_status fsi_batch_get_body_state(fsi_batch *b, int k, int body, double out[4]);
 fsi_status fsi_batch_dump_macro(fsi_batch *b, int k, double *rho, double *ux, double *uy,
                                 double *T);
 fsi_status fsi_batch_get_populations(fsi_batch *b, int k, float *f, float *g);

@@ -39,6 +39,13 @@ class CFLViolation(ValueError):
 # candidate cells touching a node, by the index offset of their lower-left corner
 CANDIDATE_CELLS = ((-1, -1), (0, -1), (-1, 0), (0, 0))
 CELL_TOL = 1e-12
+# Reading (the paper does not say how a departure point on the wall line is
+# classified): a wall node's departure point less than WALL_TOL (index units)
+# below the wall line counts as on it, so it is interpolated, not missing.
+# The tolerance makes the decision independent of rounding for points that
+# lie on the wall line in exact arithmetic, such as those of populations
+# moving along a straight slit at a junction with a body.
+WALL_TOL = 1e-4
 
 
 def bilinear_inverse(P00, P10, P01, P11, Px, Py, iters=60):
@@ -100,8 +107,10 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
     Returns (a, b, missing): a, b are the index-space offsets of xi_dp from the
     node; ``missing`` marks departure points that leave the mesh through the
     wall (only when ``wall_row``): wall nodes search only the cells above the
-    wall, and a point below them lies in the body.  Raises CFLViolation if a
-    departure point lies in none of the cells touching its node.
+    wall, and a point more than WALL_TOL below them lies in the body (for
+    those a is NaN and b the offset below the wall line).  Raises
+    CFLViolation if a departure point lies in none of the cells touching its
+    node.
     """
     Pdx = -dt * chx                      # X_dp - X, relative to the node
     Pdy = -dt * chy
@@ -119,16 +128,19 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
             corners.append((px - X, py - Y))
         with np.errstate(invalid="ignore", divide="ignore"):
             s, t, _ = bilinear_inverse(*corners, Pdx, Pdy)
+        t_lo = np.where(wall_node, -WALL_TOL, -CELL_TOL) if dj0 == 0 else -CELL_TOL
         inside = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL)
-                  & (t >= -CELL_TOL) & (t <= 1 + CELL_TOL))
+                  & (t >= t_lo) & (t <= 1 + CELL_TOL))
         take = inside & ~found
         a = np.where(take, di0 + s, a)
         b = np.where(take, dj0 + t, b)
         found |= take
         if wall_row and dj0 == 0:
             # a wall-node departure point below the first cell row lies in the body
-            below = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL) & (t < -CELL_TOL) & wall_node)
-            missing |= below & ~found
+            below = ((s >= -CELL_TOL) & (s <= 1 + CELL_TOL) & (t < -WALL_TOL) & wall_node)
+            new = below & ~found & ~missing
+            b = np.where(new, t, b)
+            missing |= new
     missing &= ~found
     bad = ~found & ~missing
     if np.any(bad):

@@ -15,12 +15,15 @@ using fsi::Inst;
 
 struct fsi_ctx {
     fsi_fluid_params fluid{};
-    int ni = 0, nj = 0, topo = 0, n_wake = 0;
-    bool has_wall = false;      // O-grid or C-grid
+    int ni = 0, nj = 0, topo = 0, n_wake = 0, n_wall2 = 0;
+    bool has_wall = false;      // O-grid, C-grid or twin O-grid
+    bool cut = false;           // C-grid or twin O-grid
+    int cut_a = 0, cut_b = 0, mirror = 0;
+    int seg_i0[fsi::MAX_BODIES] = {}, seg_n[fsi::MAX_BODIES] = {}, seg_dup[fsi::MAX_BODIES] = {};
+    int n_seg = 0;
     double shift_i[2] = {0, 0}, shift_j[2] = {0, 0};
     std::vector<double> X;          // [nj][ni][2]
-    fsi_body_desc body{};
-    bool has_body = false;
+    std::vector<fsi_body_desc> bodies;
     hipStream_t stream = nullptr;
     Inst inst{};
     // workspace layout (byte offsets)
@@ -30,7 +33,7 @@ struct fsi_ctx {
            total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
-    std::vector<double> wall_dist;      // blend_mode 1: distance of every node to the wall
+    std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
     std::vector<uint8_t> inflow;        // per far-field list entry
     std::vector<int2> ff;               // far-field (node, interior node)
     std::vector<int2> wk0, wk1, wbnd, wwall;
@@ -43,7 +46,7 @@ struct fsi_ctx {
 
 namespace {
 
-constexpr int64_t kMagic = 0x46534c424d303031LL;   // checkpoint tag
+constexpr int64_t kMagic = 0x46534c424d303032LL;   // checkpoint tag
 
 fsi_status fail(fsi_ctx *c, fsi_status st, const std::string &msg) {
     if (c) c->err = msg;
@@ -66,11 +69,12 @@ int wrapi(int a, int n) { return ((a % n) + n) % n; }
 
 // coordinate of node (i, j) seen from an unwrapped index, with periodic shifts
 void coord(const fsi_ctx *c, int i, int j, double &x, double &y) {
-    if (c->topo == FSI_TOPO_CGRID) {
-        if (j < 0) {                       // across the wake cut
-            i = c->ni - 1 - i;
+    if (c->cut) {
+        if (j < 0) {                       // across the cut
+            i = c->mirror - i;
             j = -j;
         }
+        if (c->topo == FSI_TOPO_TWIN) i = wrapi(i, c->ni);
         x = c->X[2 * ((size_t)j * c->ni + i)];
         y = c->X[2 * ((size_t)j * c->ni + i) + 1];
         return;
@@ -109,8 +113,10 @@ bool bilinear_inverse(const double c[4][2], double px, double py, double &s, dou
     return isfinite(s) && isfinite(t);
 }
 
-double blend_r(const fsi_body_desc &b, double X, double Y) {
-    const double d = hypot(X - b.center[0], Y - b.center[1]);
+// blending factor of body b at (X, Y), d_wall its distance to the body's wall
+// (distance blending)
+double blend_r(const fsi_body_desc &b, double X, double Y, double d_wall = 0.0) {
+    const double d = b.blend_mode == 1 ? d_wall : hypot(X - b.center[0], Y - b.center[1]);
     const double s = (d - b.r_rigid) / (b.r_blend - b.r_rigid);
     if (s <= 0) return 0;
     if (s >= 1) return 1;
@@ -126,9 +132,18 @@ fsi::BodySlot slot_of(double h, double a, double hd, double ad) {
     return s;
 }
 
-bool is_wall_col(const fsi_ctx *c, int i) {
-    return c->topo == FSI_TOPO_OGRID || (i >= c->n_wake && i < c->ni - c->n_wake);
+int mirror_of(const fsi_ctx *c, int i) {
+    const int m = c->mirror - i;
+    return c->topo == FSI_TOPO_TWIN ? wrapi(m, c->ni) : m;
 }
+
+bool is_cut_col(const fsi_ctx *c, int i) {
+    if (!c->cut) return false;
+    const int m = mirror_of(c, i);
+    return (i > c->cut_a && i < c->cut_b) || (m > c->cut_a && m < c->cut_b);
+}
+
+bool is_wall_col(const fsi_ctx *c, int i) { return c->has_wall && !is_cut_col(c, i); }
 
 // index-space FE derivative of the undeformed coordinates at node (i, j):
 // centred, one-sided 3-point on wall columns of row 0, on row nj - 1 and on
@@ -168,18 +183,45 @@ void dX_dj(const fsi_ctx *c, int i, int j, double &xd, double &yd) {
     yd = 0.5 * (y1 - y0);
 }
 
-fsi_status validate_and_precompute(fsi_ctx *c) {
-    const int ni = c->ni, nj = c->nj;
-    if (c->topo == FSI_TOPO_CGRID) {
+// cut constants and wall segments of the topology (sizes validated first)
+fsi_status topology(fsi_ctx *c) {
+    const int ni = c->ni;
+    c->cut = c->topo == FSI_TOPO_CGRID || c->topo == FSI_TOPO_TWIN;
+    c->n_seg = 0;
+    if (c->topo == FSI_TOPO_OGRID) {
+        c->n_seg = 1;
+        c->seg_i0[0] = 0; c->seg_n[0] = ni; c->seg_dup[0] = 0;
+    } else if (c->topo == FSI_TOPO_CGRID) {
         if (c->n_wake < 2 || ni - 2 * c->n_wake < 8)
             return fail(c, FSI_E_MESH, "C-grid needs n_wake >= 2 and at least 8 wall nodes");
-        // row 0: cut nodes and the trailing edge appear twice
-        for (int i = 0; i <= c->n_wake; ++i) {
-            const double *a = &c->X[2 * (size_t)i], *b = &c->X[2 * (size_t)(ni - 1 - i)];
+        c->cut_a = -1; c->cut_b = c->n_wake; c->mirror = ni - 1;
+        c->n_seg = 1;
+        c->seg_i0[0] = c->n_wake; c->seg_n[0] = ni - 2 * c->n_wake; c->seg_dup[0] = 1;
+    } else if (c->topo == FSI_TOPO_TWIN) {
+        const int nA = ni - 2 * c->n_wake - c->n_wall2;
+        if (c->n_wake < 2 || c->n_wall2 < 8 || nA < 8)
+            return fail(c, FSI_E_MESH, "twin O-grid needs n_wake >= 2 slit cells and at least 8 "
+                                       "wall cells round each body");
+        c->cut_a = nA; c->cut_b = nA + c->n_wake; c->mirror = nA;
+        c->n_seg = 2;
+        c->seg_i0[0] = 0; c->seg_n[0] = nA + 1; c->seg_dup[0] = 1;
+        c->seg_i0[1] = nA + c->n_wake; c->seg_n[1] = c->n_wall2 + 1; c->seg_dup[1] = 1;
+    }
+    return FSI_OK;
+}
+
+fsi_status validate_and_precompute(fsi_ctx *c) {
+    const int ni = c->ni, nj = c->nj;
+    fsi_status tst = topology(c);
+    if (tst != FSI_OK) return tst;
+    if (c->cut) {
+        // row 0: every cut point and every duplicated wall point appears twice
+        for (int i = std::max(c->cut_a, 0); i <= c->cut_b; ++i) {
+            const int m = mirror_of(c, i);
+            const double *a = &c->X[2 * (size_t)i], *b = &c->X[2 * (size_t)m];
             if (a[0] != b[0] || a[1] != b[1])
-                return fail(c, FSI_E_MESH, "C-grid cut nodes (i, 0) and (ni-1-i, 0) must coincide "
-                                           "for i <= n_wake (first mismatch at i = " +
-                                               std::to_string(i) + ")");
+                return fail(c, FSI_E_MESH, "cut nodes (i, 0) and (mirror(i), 0) must coincide "
+                                           "(first mismatch at i = " + std::to_string(i) + ")");
         }
     }
     // det(dX/dxi) > 0 everywhere (FE metric of the topology)
@@ -194,54 +236,82 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
                                                std::to_string(j) + "): mesh must be right-handed");
         }
     }
-    if (c->has_body) {
-        const fsi_body_desc &b = c->body;
+    const int nb = (int)c->bodies.size();
+    const size_t N = (size_t)ni * nj;
+    bool any_dist = false;
+    for (int k = 0; k < nb; ++k) {
+        const fsi_body_desc &b = c->bodies[k];
+        const std::string who = "body " + std::to_string(k) + ": ";
+        if (b.link < -1 || b.link >= k || (b.link >= 0 && c->bodies[b.link].link != -1))
+            return fail(c, FSI_E_ARG, who + "link must be -1 or an earlier body that is not linked");
         if (!(b.r_blend > b.r_rigid) || !(b.r_rigid >= 0))
-            return fail(c, FSI_E_ARG, "body needs 0 <= r_rigid < r_blend");
-        if (b.dof == FSI_DOF_HEAVE && !(b.m > 0)) return fail(c, FSI_E_ARG, "heave body needs m > 0");
+            return fail(c, FSI_E_ARG, who + "needs 0 <= r_rigid < r_blend");
+        if (b.blend_mode != 0 && b.blend_mode != 1) return fail(c, FSI_E_ARG, who + "unknown blend_mode");
+        if (b.blend_mode == 1 && !c->has_wall)
+            return fail(c, FSI_E_ARG, who + "distance blending needs a mesh with a wall");
+        any_dist |= b.blend_mode == 1;
+        if (b.link >= 0) continue;           // no equation of its own
+        if (b.dof == FSI_DOF_HEAVE && !(b.m > 0)) return fail(c, FSI_E_ARG, who + "heave body needs m > 0");
         if (b.dof == FSI_DOF_PITCH_PLUNGE && !(b.m * b.I_a - b.S_a * b.S_a > 0))
-            return fail(c, FSI_E_ARG, "pitch-plunge body needs a positive-definite mass matrix");
-        if (!(b.release_time >= 0)) return fail(c, FSI_E_ARG, "release_time must be >= 0");
-        if (b.blend_mode != 0 && b.blend_mode != 1) return fail(c, FSI_E_ARG, "unknown blend_mode");
-        if (b.blend_mode == 1) {
-            if (!c->has_wall)
-                return fail(c, FSI_E_ARG, "distance blending needs a mesh with a wall");
-            // distance of every node to the closed wall polygon (undeformed frame)
+            return fail(c, FSI_E_ARG, who + "pitch-plunge body needs a positive-definite mass matrix");
+        if (!(b.release_time >= 0)) return fail(c, FSI_E_ARG, who + "release_time must be >= 0");
+    }
+    c->wall_dist.clear();
+    if (any_dist) {
+        // distance of every node to each distance-blended body's closed wall
+        // polygon (undeformed frame); the polygons of the other bodies stay 0
+        size_t E = 0;
+        for (int k = 0; k < nb; ++k)
+            if (c->bodies[k].blend_mode == 1) E += (size_t)(c->seg_n[k] - c->seg_dup[k]);
+        if ((double)N * (double)E > 4e9)
+            return fail(c, FSI_E_ARG, "distance blending: mesh too large for the direct "
+                                      "distance computation (nodes x wall edges > 4e9)");
+        c->wall_dist.assign((size_t)nb * N, 0.0);
+        for (int k = 0; k < nb; ++k) {
+            if (c->bodies[k].blend_mode != 1) continue;
             std::vector<int> poly;
-            const int w0 = c->topo == FSI_TOPO_CGRID ? c->n_wake : 0;
-            const int w1 = c->topo == FSI_TOPO_CGRID ? ni - 1 - c->n_wake : ni;
-            for (int i = w0; i < w1; ++i) poly.push_back(i);
-            const size_t N = (size_t)ni * nj, E = poly.size();
-            if ((double)N * (double)E > 4e9)
-                return fail(c, FSI_E_ARG, "distance blending: mesh too large for the direct "
-                                          "distance computation (nodes x wall edges > 4e9)");
-            c->wall_dist.assign(N, 0.0);
-            for (size_t k = 0; k < N; ++k) {
-                const double px = c->X[2 * k], py = c->X[2 * k + 1];
+            for (int i = 0; i < c->seg_n[k] - c->seg_dup[k]; ++i) poly.push_back(c->seg_i0[k] + i);
+            const size_t Ek = poly.size();
+            for (size_t q = 0; q < N; ++q) {
+                const double px = c->X[2 * q], py = c->X[2 * q + 1];
                 double best = INFINITY;
-                for (size_t e = 0; e < E; ++e) {
+                for (size_t e = 0; e < Ek; ++e) {
                     const double *a = &c->X[2 * (size_t)poly[e]];
-                    const double *q = &c->X[2 * (size_t)poly[(e + 1) % E]];
-                    const double ex = q[0] - a[0], ey = q[1] - a[1];
+                    const double *bq = &c->X[2 * (size_t)poly[(e + 1) % Ek]];
+                    const double ex = bq[0] - a[0], ey = bq[1] - a[1];
                     const double ee = ex * ex + ey * ey;
                     double t = ee > 0 ? ((px - a[0]) * ex + (py - a[1]) * ey) / ee : 0.0;
                     t = t < 0 ? 0 : (t > 1 ? 1 : t);
                     const double dx = px - (a[0] + t * ex), dy = py - (a[1] + t * ey);
                     best = std::min(best, dx * dx + dy * dy);
                 }
-                c->wall_dist[k] = sqrt(best);
+                c->wall_dist[(size_t)k * N + q] = sqrt(best);
             }
         }
-        if (c->topo == FSI_TOPO_PERIODIC2) {
-            // the blended region must not reach the periodic seams
+    }
+    // regions of influence: at most one body moves a node
+    if (nb > 1) {
+        for (size_t q = 0; q < N; ++q) {
+            int inside = 0;
+            for (int k = 0; k < nb; ++k) {
+                const double dw = c->wall_dist.empty() ? 0.0 : c->wall_dist[(size_t)k * N + q];
+                if (blend_r(c->bodies[k], c->X[2 * q], c->X[2 * q + 1], dw) < 1.0) ++inside;
+            }
+            if (inside > 1)
+                return fail(c, FSI_E_ARG, "regions of influence overlap at node (" +
+                                              std::to_string(q % ni) + ", " + std::to_string(q / ni) + ")");
+        }
+    }
+    if (c->topo == FSI_TOPO_PERIODIC2) {
+        // a blended region must not reach the periodic seams
+        for (int k = 0; k < nb; ++k)
             for (int j = 0; j < nj; ++j)
                 for (int i = 0; i < ni; ++i) {
                     if (i > 3 && i < ni - 4 && j > 3 && j < nj - 4) continue;
                     const double *p = &c->X[2 * ((size_t)j * ni + i)];
-                    if (blend_r(b, p[0], p[1]) < 1.0)
+                    if (blend_r(c->bodies[k], p[0], p[1]) < 1.0)
                         return fail(c, FSI_E_MESH, "blending region reaches a periodic seam");
                 }
-        }
     }
     c->ff.clear();
     c->inflow.clear();
@@ -284,7 +354,7 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
             c->ff.push_back(make_int2(j * ni + i, jr * ni + ir));
             c->inflow.push_back((ux * nx + uy * ny) < 0.0 ? 1 : 0);
         };
-        const bool cg = c->topo == FSI_TOPO_CGRID;
+        const bool cg = c->topo == FSI_TOPO_CGRID;     // exit columns
         for (int i = 0; i < ni; ++i) {
             double xd, yd;
             dX_di(c, i, nj - 1, xd, yd);
@@ -309,13 +379,21 @@ void fill_params(fsi_ctx *c) {
     P.ni = c->ni;
     P.nj = c->nj;
     P.periodic_j = c->topo == FSI_TOPO_PERIODIC2;
-    P.cgrid = c->topo == FSI_TOPO_CGRID;
-    P.n_wake = P.cgrid ? c->n_wake : 0;
-    P.wall_i0 = P.cgrid ? c->n_wake : 0;
-    P.wall_n = c->has_wall ? (P.cgrid ? c->ni - 2 * c->n_wake : c->ni) : 0;
-    P.force_n = P.cgrid ? P.wall_n - 1 : P.wall_n;
+    P.cut = c->cut ? 1 : 0;
+    P.exits = c->topo == FSI_TOPO_CGRID ? 1 : 0;
+    P.cut_a = c->cut_a;
+    P.cut_b = c->cut_b;
+    P.mirror = c->mirror;
+    P.exp_lo = std::max(c->cut_a, 0);
+    P.cut_n = c->cut ? 2 * (c->cut_b - P.exp_lo + 1) : 0;
+    P.n_seg = c->n_seg;
+    for (int k = 0; k < fsi::MAX_BODIES; ++k) {
+        P.seg_i0[k] = c->seg_i0[k];
+        P.seg_n[k] = c->seg_n[k];
+        P.seg_dup[k] = c->seg_dup[k];
+    }
     P.n_ff = (int)c->ff.size();
-    P.cut_n = P.cgrid ? 2 * (c->n_wake + 1) : 0;
+    P.nbody = (int)c->bodies.size();
     P.storage = fl.storage;
     P.tiles_i = (c->ni + fsi::TILE_X - 1) / fsi::TILE_X;
     P.tiles_j = (c->nj + fsi::TILE_Y - 1) / fsi::TILE_Y;
@@ -353,19 +431,26 @@ void fill_params(fsi_ctx *c) {
         P.inv_scale[0] = 64.0f;
         P.inv_scale[1] = 16.0f;
     }
-    fsi::Body &B = P.body;
-    B = fsi::Body{};
-    B.present = c->has_body ? 1 : 0;
-    B.dof = c->has_body ? c->body.dof : fsi::DOF_FIXED;
-    if (c->has_body) {
-        const fsi_body_desc &b = c->body;
-        B.m = b.m; B.S_a = b.S_a; B.I_a = b.I_a; B.k_h = b.k_h; B.k_a = b.k_a;
-        B.cx = b.center[0]; B.cy = b.center[1]; B.ex = b.ea[0]; B.ey = b.ea[1];
+    for (int k = 0; k < fsi::MAX_BODIES; ++k) {
+        fsi::Body &B = P.body[k];
+        B = fsi::Body{};
+        B.master = k;
+        B.dof = fsi::DOF_FIXED;
+        if (k >= (int)c->bodies.size()) continue;
+        const fsi_body_desc &b = c->bodies[k];
+        // a linked body moves with its master's rigid map and state
+        const int m = b.link >= 0 ? b.link : k;
+        const fsi_body_desc &bm = c->bodies[m];
+        B.present = 1;
+        B.master = m;
+        B.dof = bm.dof;
+        B.m = bm.m; B.S_a = bm.S_a; B.I_a = bm.I_a; B.k_h = bm.k_h; B.k_a = bm.k_a;
+        B.cx = b.center[0]; B.cy = b.center[1]; B.ex = bm.ea[0]; B.ey = bm.ea[1];
         B.r_rigid = b.r_rigid;
         B.inv_width = 1.0 / (b.r_blend - b.r_rigid);
-        B.heave_amp = b.heave_amp; B.heave_omega = 2.0 * M_PI * b.heave_freq;
-        B.pitch_amp = b.pitch_amp; B.pitch_omega = 2.0 * M_PI * b.pitch_freq;
-        B.release_time = b.release_time;
+        B.heave_amp = bm.heave_amp; B.heave_omega = 2.0 * M_PI * bm.heave_freq;
+        B.pitch_amp = bm.pitch_amp; B.pitch_omega = 2.0 * M_PI * bm.pitch_freq;
+        B.release_time = bm.release_time;
         B.blend_mode = b.blend_mode;
     }
     // work lists
@@ -376,19 +461,26 @@ void fill_params(fsi_ctx *c) {
     c->wwall.clear();
     c->wk0.clear();
     if (c->has_wall) {
-        const int nw = (P.wall_n + 63) / 64, nf = (P.n_ff + 63) / 64;
+        int nw = 0;
+        for (int k = 0; k < c->n_seg; ++k) nw += (c->seg_n[k] + 63) / 64;
+        const int nf = (P.n_ff + 63) / 64;
         for (int b = 0; b < nw; ++b) {
             c->wbnd.push_back(make_int2(0, 2 * b));
             c->wwall.push_back(make_int2(0, b));
         }
         for (int b = 0; b < nf; ++b) c->wbnd.push_back(make_int2(0, 2 * b + 1));
     }
-    if (P.cgrid) {
-        // tiles of row block 0 that own a cut column or a trailing-edge copy
+    if (c->cut) {
+        // tiles of row block 0 that own a column whose row-1 state crosses
+        // the cut (exported primary columns and their mirror images)
         for (int ti = 0; ti < P.tiles_i; ++ti) {
             const int a = ti * fsi::TILE_X, b = std::min(a + fsi::TILE_X, c->ni) - 1;
-            const bool lower = a <= c->n_wake, upper = b >= c->ni - 1 - c->n_wake;
-            if (lower || upper) c->wk0.push_back(make_int2(0, ti));
+            bool own = false;
+            for (int i = a; i <= b && !own; ++i) {
+                const int m = mirror_of(c, i);
+                own = (i >= P.exp_lo && i <= c->cut_b) || (m >= P.exp_lo && m <= c->cut_b);
+            }
+            if (own) c->wk0.push_back(make_int2(0, ti));
         }
     }
 }
@@ -408,8 +500,8 @@ void layout(fsi_ctx *c) {
     c->off_ff = take(c->ff.size() * sizeof(int2));
     c->off_cut = take((size_t)16 * c->inst.cut_n * sizeof(float));
     c->off_force = take(c->ni * 32);
-    c->off_slots = take(3 * sizeof(fsi::BodySlot));
-    c->off_hist = take((size_t)fsi::HIST_CAP * 6 * 8);
+    c->off_slots = take(3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot));
+    c->off_hist = take((size_t)fsi::MAX_BODIES * fsi::HIST_CAP * 6 * 8);
     c->off_step = take(8);
     c->off_err = take(4);
     c->off_inst = take(sizeof(Inst));
@@ -436,8 +528,7 @@ fsi_status enqueue_step(fsi_ctx *c) {
         HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
     HIP_TRY(c, fsi::launch_collide_stream(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
-                                          (int)c->wk1.size(), st, c->stream, 0,
-                                          c->topo == FSI_TOPO_CGRID, 0));
+                                          (int)c->wk1.size(), st, c->stream, 0, c->cut, 0));
     if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
@@ -495,13 +586,17 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
     c->nj = mesh->nj;
     c->topo = mesh->topo;
     c->n_wake = mesh->n_wake;
-    c->has_wall = c->topo == FSI_TOPO_OGRID || c->topo == FSI_TOPO_CGRID;
+    c->n_wall2 = mesh->n_wall2;
+    c->has_wall = c->topo == FSI_TOPO_OGRID || c->topo == FSI_TOPO_CGRID || c->topo == FSI_TOPO_TWIN;
     c->stream = (hipStream_t)hip_stream;
     if (c->ni < 8 || c->nj < 8) return fail(c, FSI_E_ARG, "mesh needs ni >= 8 and nj >= 8");
-    if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_OGRID && c->topo != FSI_TOPO_CGRID)
+    if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_OGRID && c->topo != FSI_TOPO_CGRID &&
+        c->topo != FSI_TOPO_TWIN)
         return fail(c, FSI_E_ARG, "unsupported topology");
-    if (nbodies < 0 || nbodies > 1 || (nbodies == 1 && !bodies))
-        return fail(c, FSI_E_ARG, "nbodies must be 0 or 1");
+    if (c->topo == FSI_TOPO_TWIN ? nbodies != fsi::MAX_BODIES : (nbodies < 0 || nbodies > 1))
+        return fail(c, FSI_E_ARG, c->topo == FSI_TOPO_TWIN ? "a twin O-grid carries 2 bodies"
+                                                           : "nbodies must be 0 or 1");
+    if (nbodies > 0 && !bodies) return fail(c, FSI_E_ARG, "bodies missing");
     if (!(fluid->gamma > 1) || !(fluid->mu > 0) || !(fluid->dt > 0) || !(fluid->Pr > 0) ||
         !(fluid->rho_inf > 0) || !(fluid->T_inf > 0 && fluid->T_inf < 1))
         return fail(c, FSI_E_ARG, "fluid parameters out of range");
@@ -518,10 +613,10 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
     c->X.assign(mesh->X, mesh->X + 2 * (size_t)c->ni * c->nj);
     for (double v : c->X)
         if (!isfinite(v)) return fail(c, FSI_E_MESH, "non-finite mesh coordinate");
-    if (nbodies == 1) {
-        c->body = bodies[0];
-        c->has_body = true;
-        if (c->body.dof < 0 || c->body.dof > 3) return fail(c, FSI_E_ARG, "unknown body dof");
+    for (int k = 0; k < nbodies; ++k) {
+        c->bodies.push_back(bodies[k]);
+        if ((bodies[k].link < 0 && (bodies[k].dof < 0 || bodies[k].dof > 3)))
+            return fail(c, FSI_E_ARG, "unknown body dof");
     }
     fsi_status st = validate_and_precompute(c);
     if (st != FSI_OK) return st;
@@ -567,7 +662,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_X, c->X.data(), N * 16, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_mask, 0, c->ni * 2, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_force, 0, c->ni * 32, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_hist, 0, (size_t)fsi::HIST_CAP * 48, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_hist, 0, (size_t)fsi::MAX_BODIES * fsi::HIST_CAP * 48,
+                              c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_step, 0, 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
     if (!c->wk0.empty()) {
@@ -611,19 +707,21 @@ fsi_status fsi_init_equilibrium(fsi_ctx *c, const double *rho, const double *ux,
     }
     double *scratch = reinterpret_cast<double *>(c->ws + c->off_pop[1]);
     HIP_TRY(c, hipMemcpyAsync(scratch, macro.data(), 4 * N * 8, hipMemcpyHostToDevice, c->stream));
-    fsi::BodySlot slots[3];
-    if (c->has_body) {
-        const fsi_body_desc &b = c->body;
+    fsi::BodySlot slots[3][fsi::MAX_BODIES];
+    for (int k = 0; k < fsi::MAX_BODIES; ++k) {
+        slots[0][k] = slot_of(0, 0, 0, 0);
+        if (k >= (int)c->bodies.size()) continue;
+        // a linked body starts in the state of the body it moves with
+        const int m = c->bodies[k].link >= 0 ? c->bodies[k].link : k;
+        const fsi_body_desc &b = c->bodies[m];
         const bool forced = (b.dof == FSI_DOF_HEAVE || b.dof == FSI_DOF_PITCH_PLUNGE) && b.release_time > 0;
         if (b.dof == FSI_DOF_PRESCRIBED || forced)
-            slots[0] = slot_of(0.0, 0.0, b.heave_amp * 2 * M_PI * b.heave_freq,
-                               b.pitch_amp * 2 * M_PI * b.pitch_freq);
+            slots[0][k] = slot_of(0.0, 0.0, b.heave_amp * 2 * M_PI * b.heave_freq,
+                                  b.pitch_amp * 2 * M_PI * b.pitch_freq);
         else
-            slots[0] = slot_of(b.h0, b.a0, b.hd0, b.ad0);
-    } else {
-        slots[0] = slot_of(0, 0, 0, 0);
+            slots[0][k] = slot_of(b.h0, b.a0, b.hd0, b.ad0);
     }
-    slots[1] = slots[2] = slots[0];
+    for (int k = 0; k < fsi::MAX_BODIES; ++k) slots[1][k] = slots[2][k] = slots[0][k];
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_slots, slots, sizeof(slots), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_step, 0, 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
@@ -686,7 +784,8 @@ fsi_status fsi_get_step(fsi_ctx *c, int64_t *step) {
 fsi_status fsi_get_forces(fsi_ctx *c, int body, int64_t first, int count, double *out) {
     fsi_status st = check_ready(c, true);
     if (st != FSI_OK) return st;
-    if (body != 0 || count < 0 || (count > 0 && !out)) return fail(c, FSI_E_ARG, "bad history request");
+    if (body < 0 || body >= std::max(1, (int)c->bodies.size()) || count < 0 || (count > 0 && !out))
+        return fail(c, FSI_E_ARG, "bad history request");
     const int64_t last = c->host_step;   // record `last` exists once the queue drained
     const int64_t oldest = std::max<int64_t>(0, last - fsi::HIST_CAP + 1);
     if (first < oldest || first + count - 1 > last)
@@ -696,8 +795,9 @@ fsi_status fsi_get_forces(fsi_ctx *c, int body, int64_t first, int count, double
     if (st != FSI_OK) return st;
     for (int k = 0; k < count; ++k) {
         const int64_t L = first + k;
-        HIP_TRY(c, hipMemcpy(out + 6 * (size_t)k, c->ws + c->off_hist + (size_t)(L % fsi::HIST_CAP) * 48, 48,
-                             hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(out + 6 * (size_t)k,
+                             c->ws + c->off_hist + ((size_t)body * fsi::HIST_CAP + (size_t)(L % fsi::HIST_CAP)) * 48,
+                             48, hipMemcpyDeviceToHost));
     }
     return FSI_OK;
 }
@@ -705,11 +805,13 @@ fsi_status fsi_get_forces(fsi_ctx *c, int body, int64_t first, int count, double
 fsi_status fsi_get_body_state(fsi_ctx *c, int body, double out[4]) {
     fsi_status st = check_ready(c, true);
     if (st != FSI_OK) return st;
-    if (body != 0 || !out) return fail(c, FSI_E_ARG, "bad body index");
+    if (body < 0 || body >= std::max(1, (int)c->bodies.size()) || !out)
+        return fail(c, FSI_E_ARG, "bad body index");
     st = sync_check(c);
     if (st != FSI_OK) return st;
     fsi::BodySlot s;
-    HIP_TRY(c, hipMemcpy(&s, c->ws + c->off_slots + (size_t)(c->host_step % 3) * sizeof(fsi::BodySlot),
+    HIP_TRY(c, hipMemcpy(&s, c->ws + c->off_slots +
+                                 ((size_t)(c->host_step % 3) * fsi::MAX_BODIES + body) * sizeof(fsi::BodySlot),
                          sizeof(s), hipMemcpyDeviceToHost));
     out[0] = s.h; out[1] = s.a; out[2] = s.hd; out[3] = s.ad;
     return FSI_OK;
@@ -782,7 +884,7 @@ fsi_status fsi_state_bytes(const fsi_ctx *c, size_t *bytes) {
     if (!c || !bytes) return FSI_E_ARG;
     const size_t N = (size_t)c->ni * c->nj;
     const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
-    *bytes = 8 * 6 + 3 * sizeof(fsi::BodySlot) + fsi::NPOP * N * bpp;
+    *bytes = 8 * 6 + 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot) + fsi::NPOP * N * bpp;
     return FSI_OK;
 }
 
@@ -800,8 +902,9 @@ fsi_status fsi_save(fsi_ctx *c, void *host_buf, size_t bytes) {
     hdr[0] = kMagic; hdr[1] = c->ni; hdr[2] = c->nj; hdr[3] = c->fluid.storage; hdr[4] = c->host_step;
     hdr[5] = c->topo;
     char *p = static_cast<char *>(host_buf) + 48;
-    HIP_TRY(c, hipMemcpy(p, c->ws + c->off_slots, 3 * sizeof(fsi::BodySlot), hipMemcpyDeviceToHost));
-    p += 3 * sizeof(fsi::BodySlot);
+    HIP_TRY(c, hipMemcpy(p, c->ws + c->off_slots, 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot),
+                         hipMemcpyDeviceToHost));
+    p += 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot);
     HIP_TRY(c, hipMemcpy(p, c->ws + c->off_pop[c->host_step & 1], fsi::NPOP * N * bpp, hipMemcpyDeviceToHost));
     return FSI_OK;
 }
@@ -820,8 +923,9 @@ fsi_status fsi_load(fsi_ctx *c, const void *host_buf, size_t bytes) {
     const int64_t step = hdr[4];
     const char *p = static_cast<const char *>(host_buf) + 48;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipMemcpy(c->ws + c->off_slots, p, 3 * sizeof(fsi::BodySlot), hipMemcpyHostToDevice));
-    p += 3 * sizeof(fsi::BodySlot);
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_slots, p, 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot),
+                         hipMemcpyHostToDevice));
+    p += 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot);
     HIP_TRY(c, hipMemcpy(c->ws + c->off_pop[step & 1], p, fsi::NPOP * N * bpp, hipMemcpyHostToDevice));
     long long s = step;
     HIP_TRY(c, hipMemcpy(c->ws + c->off_step, &s, 8, hipMemcpyHostToDevice));
@@ -859,7 +963,7 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                                                   (int)c->wk0.size(), stg, c->stream));
             if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
-                                               c->topo == FSI_TOPO_CGRID, 0);
+                                               c->cut, 0);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
             // phase 0 of the wall kernel (traction only) and of the body kernel
             // recompute the current level without advancing it
@@ -903,7 +1007,7 @@ struct fsi_batch {
     char *ws = nullptr;
     std::vector<int2> wk0, wk1, wbnd, wwall;
     int grid = 0, order = 0, shape = 0;
-    bool any_cgrid = false;
+    bool any_cut = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::string err;
@@ -980,7 +1084,7 @@ fsi_status batch_enqueue_k1(fsi_batch *b) {
                                            (int)b->wk0.size(), b->storage, b->stream));
     BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk1),
                                            (int)b->wk1.size(), b->storage, b->stream, b->grid,
-                                           !b->wk0.empty(), b->shape));
+                                           b->any_cut, b->shape));
     return FSI_OK;
 }
 
@@ -1027,12 +1131,15 @@ fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mes
     *out = b;
     if (n < 1 || !fluids || !meshes) return bfail(b, FSI_E_ARG, "need n >= 1 fluids and meshes");
     b->stream = (hipStream_t)hip_stream;
+    size_t first_body = 0;
     for (int k = 0; k < n; ++k) {
         const int nb = nbodies ? nbodies[k] : 0;
         if (nb && !bodies) return bfail(b, FSI_E_ARG, "bodies missing");
+        if (nb < 0) return bfail(b, FSI_E_ARG, "instance " + std::to_string(k) + ": nbodies < 0");
         fsi_ctx *c = nullptr;
-        const fsi_status st = fsi_create(&fluids[k], &meshes[k], nb ? &bodies[k] : nullptr, nb,
+        const fsi_status st = fsi_create(&fluids[k], &meshes[k], nb ? &bodies[first_body] : nullptr, nb,
                                          hip_stream, &c);
+        first_body += (size_t)nb;
         if (st != FSI_OK) {
             b->err = "instance " + std::to_string(k) + ": " + (c ? c->err : std::string("create failed"));
             fsi_destroy(c);
@@ -1042,7 +1149,7 @@ fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mes
         if (k == 0) b->storage = c->fluid.storage;
         if (c->fluid.storage != b->storage) return bfail(b, FSI_E_ARG, "mixed storage precisions");
         if (c->has_wall) b->any_wall = true;
-        if (c->topo == FSI_TOPO_CGRID) b->any_cgrid = true;
+        if (c->cut) b->any_cut = true;
     }
     batch_lists(b);
     size_t o = 0;
@@ -1099,8 +1206,8 @@ fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape) 
     if (!b) return FSI_E_ARG;
     if (grid < 0 || (order != 0 && order != 1) || shape < 0 || shape >= fsi::N_TILE_SHAPES)
         return bfail(b, FSI_E_ARG, "bad schedule");
-    if (shape != 0 && b->any_cgrid)
-        return bfail(b, FSI_E_ARG, "a batch with C-grid instances uses tile shape 0");
+    if (shape != 0 && b->any_cut)
+        return bfail(b, FSI_E_ARG, "a batch with C-grid or twin O-grid instances uses tile shape 0");
     batch_drop_graph(b);
     b->grid = grid;
     if (order != b->order || shape != b->shape) {
@@ -1152,18 +1259,19 @@ fsi_status fsi_batch_synchronize(fsi_batch *b) {
     return FSI_OK;
 }
 
-fsi_status fsi_batch_get_forces(fsi_batch *b, int k, int64_t first, int count, double *out) {
+fsi_status fsi_batch_get_forces(fsi_batch *b, int k, int body, int64_t first, int count,
+                                double *out) {
     fsi_status st = batch_ready(b, k);
     if (st != FSI_OK) return st;
     if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
-    return bfwd(b, k, fsi_get_forces(b->ctx[k], 0, first, count, out));
+    return bfwd(b, k, fsi_get_forces(b->ctx[k], body, first, count, out));
 }
 
-fsi_status fsi_batch_get_body_state(fsi_batch *b, int k, double out[4]) {
+fsi_status fsi_batch_get_body_state(fsi_batch *b, int k, int body, double out[4]) {
     fsi_status st = batch_ready(b, k);
     if (st != FSI_OK) return st;
     if (k < 0) return bfail(b, FSI_E_ARG, "no such instance");
-    return bfwd(b, k, fsi_get_body_state(b->ctx[k], 0, out));
+    return bfwd(b, k, fsi_get_body_state(b->ctx[k], body, out));
 }
 
 fsi_status fsi_batch_dump_macro(fsi_batch *b, int k, double *rho, double *ux, double *uy, double *T) {
@@ -1224,7 +1332,7 @@ fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]) {
     const int grids[] = {0, 4096, 2048, 1024, 512};
     double best_ms = 1e30;
     int best_grid = 0, best_order = 0, best_shape = 0;
-    const int n_shapes = b->any_cgrid ? 1 : fsi::N_TILE_SHAPES;
+    const int n_shapes = b->any_cut ? 1 : fsi::N_TILE_SHAPES;
     // warm-up launches first (clocks ramp up over the first milliseconds),
     // then each candidate timed twice and its faster pass kept
     {

@@ -13,7 +13,7 @@ constexpr int NPOP = 18;            // f_0..f_8 then g_0..g_8
 constexpr int TILE_X = 32;          // nodes along i per tile (default shape)
 constexpr int TILE_Y = 16;          // nodes along j per tile (default shape)
 // tile shapes of the fused kernel (the batch autotuner chooses among them;
-// C-grid launches use shape 0)
+// launches over cut topologies use shape 0)
 // (one thread per arrival node: 512-thread workgroups, 256 for 16 x 16)
 constexpr int N_TILE_SHAPES = 4;
 constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}, {16, 16}};
@@ -26,18 +26,21 @@ constexpr unsigned ERR_MESH = 4u;   // det(dx/dxi) <= 0 after blending
 
 enum Dof { DOF_PRESCRIBED = 0, DOF_HEAVE = 1, DOF_PITCH_PLUNGE = 2, DOF_FIXED = 3 };
 
-// Constant description of the (single) body of an instance.
+constexpr int MAX_BODIES = 2;      // bodies per instance
+
+// Constant description of one body of an instance.
 struct Body {
     int dof;
     int present;
     double m, S_a, I_a, k_h, k_a;
     double cx, cy;            // blending centre (undeformed frame)
-    double ex, ey;            // elastic axis / rotation centre (undeformed frame)
+    double ex, ey;            // rotation centre of its rigid map: its elastic axis, or
+                              // the axis of the body it is linked to
     double r_rigid, inv_width;// 1 / (r_blend - r_rigid)
     double heave_amp, heave_omega, pitch_amp, pitch_omega;
     double release_time;      // > 0: prescribed motion until then (1DOF / 2DOF)
     int blend_mode;           // 0: radial from (cx, cy); 1: per-node wall distance
-    int pad;
+    int master;               // body whose equation moves it (itself unless linked)
 };
 
 // Body state at one time level, plus the rotation terms the kernels need.
@@ -47,21 +50,31 @@ struct BodySlot {
     double pad0, pad1;
 };
 
-// Everything one instance (one mesh + body) needs on the device.  Lives in
-// device memory; kernels read it through the scalar cache.
+// Everything one instance (one mesh + its bodies) needs on the device.  Lives
+// in device memory; kernels read it through the scalar cache.
+//
+// Cut topologies (C-grid, twin O-grid): node (i, -m) is node (mirror - i, m)
+// (mod ni when i is periodic).  The cut columns of row 0 are the primary
+// columns cut_a < i < cut_b and their mirror images; the row-1 state of the
+// columns exp_lo .. cut_b and of their mirror images crosses the cut through
+// cutbuf.  Walls: n_seg column segments [seg_i0, seg_i0 + seg_n) of row 0
+// (segment k belongs to body k); a segment with seg_dup = 1 ends on a second
+// copy of its first point.
 struct Inst {
     int ni, nj;
-    int periodic_j;           // 1: PERIODIC2 topology, 0: O-grid or C-grid (wall + far field)
+    int periodic_j;           // 1: PERIODIC2 topology, 0: wall + far field
     int storage;              // 0 FP32, 1 FP16 shifted
     int tiles_i, tiles_j;     // tile grid of the fused kernel
     int tile_base;            // first work item of this instance in a batch
-    int cgrid;                // C-grid: i not periodic, row 0 outside the wall is the wake cut
-    int n_wake;               // C-grid: cut nodes on each side of the cut
-    int wall_i0, wall_n;      // wall nodes: row 0, columns [wall_i0, wall_i0 + wall_n)
-    int force_n;              // distinct wall nodes of the force polygon, from wall_i0
+    int cut;                  // C-grid or twin O-grid: row 0 has a cut
+    int exits;                // C-grid: i not periodic, columns 0 and ni - 1 are far field
+    int cut_a, cut_b, mirror; // see above
+    int exp_lo;               // first exported primary column (max(cut_a, 0))
+    int cut_n;                // columns whose row-1 state crosses the cut (2 (cut_b - exp_lo + 1))
+    int n_seg;
+    int seg_i0[MAX_BODIES], seg_n[MAX_BODIES], seg_dup[MAX_BODIES];
     int n_ff;                 // far-field nodes
-    int cut_n;                // C-grid: columns whose row-1 state crosses the cut (2 (n_wake + 1))
-    int pad0;
+    int nbody;                // bodies (0 .. MAX_BODIES)
     long long n_nodes;
     double shift_ix, shift_iy, shift_jx, shift_jy;
     double dt_d;
@@ -70,7 +83,7 @@ struct Inst {
     float ref[NPOP];          // FP16 shifted storage: reference populations
     float scale[2];           // FP16 shifted storage: f, g scales
     float inv_scale[2];
-    Body body;
+    Body body[MAX_BODIES];
     // device buffers (all inside the caller's workspace)
     void *pop[2];             // ping-pong [18][nj][ni], float or half
     const double2 *X;         // [nj][ni] undeformed coordinates
@@ -79,11 +92,11 @@ struct Inst {
     const float2 *wall_B;     // [ni] index offsets of point B from the wall node
     const int2 *ff;           // [n_ff] far-field node index, interior node an outlet copies
     const uint8_t *inflow;    // [n_ff] far-field node is an inlet
-    float *cutbuf;            // C-grid: [16][cut_n] post-collision moving populations of row 1
+    float *cutbuf;            // cut topologies: [16][cut_n] post-collision moving populations of row 1
     double4 *wall_force;      // [ni] per-node (Fx, Fy, Mz, 0)
-    const double *wall_dist;  // [nj][ni] distance to the wall (blend_mode 1), else null
-    BodySlot *slots;          // [3] body states at levels n % 3
-    double *history;          // [HIST_CAP][6]
+    const double *wall_dist;  // [nbody][nj][ni] distance to each body's wall (blend_mode 1), else null
+    BodySlot *slots;          // [3][MAX_BODIES] body states at levels n % 3
+    double *history;          // [MAX_BODIES][HIST_CAP][6]
     long long *step;          // completed steps
     unsigned *err;            // sticky error word
     double *scratch;          // init / dump staging (aliases the idle ping-pong side)
@@ -94,7 +107,7 @@ struct Inst {
 namespace fsi {
 // host-callable launchers (fsilbm_kernels.hip)
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid, bool cgrid, int shape);
+                                 hipStream_t s, int grid, bool cut, int shape);
 hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
                              hipStream_t s);
 hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,

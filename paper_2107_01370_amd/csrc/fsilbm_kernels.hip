@@ -68,15 +68,16 @@ __device__ __forceinline__ void pop_store(const Inst &P, void *base, int q, long
 // ---------------------------------------------------------------------------
 // geometry (FP64): blending factor and rigid displacement (Sec. II.D)
 // ---------------------------------------------------------------------------
-// r of node idx at undeformed position (X, Y): the position in the region of
-// influence is the radial distance from the blending centre, or (blend_mode 1)
-// the node's precomputed distance to the wall
-__device__ __forceinline__ double blend_factor(const Inst &P, long long idx, double X, double Y) {
-    const Body &b = P.body;
+// r of body k at node idx, undeformed position (X, Y): the position in the
+// body's region of influence is the radial distance from its blending centre,
+// or (blend_mode 1) the node's precomputed distance to the body's wall
+__device__ __forceinline__ double blend_factor(const Inst &P, int k, long long idx, double X,
+                                               double Y) {
+    const Body &b = P.body[k];
     if (!b.present) return 1.0;
     double d;
     if (b.blend_mode == 1) {
-        d = P.wall_dist[idx];
+        d = P.wall_dist[k * P.n_nodes + idx];
     } else {
         const double dx = X - b.cx, dy = Y - b.cy;
         d = sqrt(dx * dx + dy * dy);
@@ -414,15 +415,35 @@ __device__ __forceinline__ Sten forward_sten(int dir) {
     return s;
 }
 
-// wall column: the whole row 0 of an O-grid, the section's columns of a C-grid.
-// `cg` (C-grid) is a compile-time false in the kernels built without C-grid
-// support, which folds every C-grid branch away.
-__device__ __forceinline__ bool wall_col(const Inst &P, int ig, bool cg) {
-    return !cg || (ig >= P.wall_i0 && ig < P.wall_i0 + P.wall_n);
+// column across the cut from column i (cut topologies)
+__device__ __forceinline__ int mirror_col(const Inst &P, int i) {
+    const int m = P.mirror - i;
+    return P.exits ? m : wrap(m, P.ni);
 }
-__device__ __forceinline__ bool wall_col(const Inst &P, int ig) { return wall_col(P, ig, P.cgrid); }
 
-// along j at (unwrapped) node (ig, jg); C-grid rows below 0 are across the cut
+// cut column of row 0: a primary cut column or the mirror image of one
+__device__ __forceinline__ bool cut_col(const Inst &P, int i) {
+    const int m = mirror_col(P, i);
+    return (i > P.cut_a && i < P.cut_b) || (m > P.cut_a && m < P.cut_b);
+}
+
+// wall column: the whole row 0 of an O-grid, every column of row 0 but the
+// cut ones on a cut topology.  `cg` (cut topology) is a compile-time false in
+// the kernels built without cut support, which folds every cut branch away.
+__device__ __forceinline__ bool wall_col(const Inst &P, int ig, bool cg) {
+    return !cg || !cut_col(P, wrap(ig, P.ni));
+}
+__device__ __forceinline__ bool wall_col(const Inst &P, int ig) { return wall_col(P, ig, P.cut); }
+
+// a copy of a duplicated wall point (C-grid trailing edge, twin junction)
+__device__ __forceinline__ bool dup_point(const Inst &P, int i) {
+    for (int k = 0; k < P.n_seg; ++k)
+        if (P.seg_dup[k] && (i == P.seg_i0[k] || i == P.seg_i0[k] + P.seg_n[k] - 1)) return true;
+    return false;
+}
+
+// along j at (unwrapped) node (ig, jg); rows below 0 of a cut topology are
+// across the cut
 __device__ __forceinline__ Sten jstencil(const Inst &P, int ig, int jg, bool cg) {
     if (!P.periodic_j) {
         if (jg == P.nj - 1) return forward_sten(-1);
@@ -432,7 +453,7 @@ __device__ __forceinline__ Sten jstencil(const Inst &P, int ig, int jg, bool cg)
 }
 
 __device__ __forceinline__ Sten istencil(const Inst &P, int ig, bool cg) {
-    if (cg) {
+    if (cg && P.exits) {
         if (ig == 0) return forward_sten(1);
         if (ig == P.ni - 1) return forward_sten(-1);
     }
@@ -446,19 +467,21 @@ __device__ __forceinline__ float dsten(const float *F, int c, int stride, const 
     return s.w1 * (F[c + s.o1 * stride] - f0) + s.w2 * (F[c + s.o2 * stride] - f0);
 }
 
-// does local (unwrapped) node (ig, jg) exist: periodic indices always, C-grid
-// rows below 0 through the mirror across the cut
+// does local (unwrapped) node (ig, jg) exist: periodic indices always, rows
+// below 0 of a cut topology through the mirror across the cut
 __device__ __forceinline__ bool node_exists(const Inst &P, int ig, int jg, bool cg) {
     if (P.periodic_j) return true;
-    if (cg) return ig >= 0 && ig < P.ni && jg < P.nj;
+    if (cg) return (!P.exits || (ig >= 0 && ig < P.ni)) && jg < P.nj;
     return jg >= 0 && jg < P.nj;
 }
 
-// C-grid: slot of column i in the row-1 export buffer (-1: not exported)
+// cut topologies: slot of column i (in [0, ni)) in the row-1 export buffer
+// (-1: not exported): the primary columns exp_lo .. cut_b, then their mirrors
 __device__ __forceinline__ int cut_slot(const Inst &P, int i) {
-    if (i >= 0 && i <= P.n_wake) return i;
-    const int up = P.ni - 1 - P.n_wake;
-    if (i >= up && i < P.ni) return P.n_wake + 1 + (i - up);
+    const int half = P.cut_b - P.exp_lo + 1;
+    if (i >= P.exp_lo && i <= P.cut_b) return i - P.exp_lo;
+    const int m = mirror_col(P, i);
+    if (m >= P.exp_lo && m <= P.cut_b) return half + (m - P.exp_lo);
     return -1;
 }
 
@@ -538,7 +561,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     constexpr int R1X = G::R1X, R1N = G::R1N, R1_ROUNDS = G::R1_ROUNDS;
     constexpr int K1_THREADS = G::NT;
     const Inst &P = insts[item.x];
-    const bool cg = CG && P.cgrid;
+    const bool cg = CG && P.cut;
+    // bodies whose regions the tile may see (one in the kernels built
+    // without cut support, which serve meshes with at most one body)
+    constexpr int NB = CG ? MAX_BODIES : 1;
     const int tile = item.y;
     const int tiles_i = (P.ni + TX - 1) / TX;
     const int ti = tile % tiles_i, tj = tile / tiles_i;
@@ -547,9 +573,13 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     const long long n = uniform(*P.step);
     const PopBuf src = pop_buf<STORE>(P, P.pop[n & 1]);
     const PopBuf dst = pop_buf<STORE>(P, P.pop[(n + 1) & 1]);
-    const BodySlot sn = uniform(P.slots[n % 3]);
-    const BodySlot sn1 = uniform(P.slots[(n + 1) % 3]);
-    const Body &body = P.body;
+    BodySlot sn[NB], sn1[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        sn[k] = uniform(P.slots[(n % 3) * MAX_BODIES + k]);
+        sn1[k] = uniform(P.slots[((n + 1) % 3) * MAX_BODIES + k]);
+    }
+    const int nbody = min(P.nbody, NB);
     const int t = threadIdx.x;
     unsigned err = 0;
 
@@ -558,12 +588,14 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     const double2 Xref = P.X[iref];
     const double Xrx = uniform(Xref.x), Xry = uniform(Xref.y);
     double Drx = 0.0, Dry = 0.0;
-    if (body.present) {
-        const double r = uniform(blend_factor(P, iref, Xrx, Xry));
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        if (k >= nbody || !P.body[k].present) continue;
+        const double r = uniform(blend_factor(P, k, iref, Xrx, Xry));
         double dx, dy;
-        rigid_disp(body, sn, Xrx, Xry, dx, dy);
-        Drx = (1.0 - r) * dx;
-        Dry = (1.0 - r) * dy;
+        rigid_disp(P.body[k], sn[k], Xrx, Xry, dx, dy);
+        Drx += (1.0 - r) * dx;
+        Dry += (1.0 - r) * dy;
     }
 
     // populations of this thread's collision nodes, kept from phase 1
@@ -578,13 +610,18 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const int u = e % R3X, v = e / R3X;
         int ig = i0 - 3 + u, jg = j0 - 3 + v;
         // wrap into the mesh; a node seen across a periodic seam has its
-        // coordinates shifted by the period; on a C-grid node (i, -m) is node
-        // (ni - 1 - i, m) across the wake cut
+        // coordinates shifted by the period; on a cut topology node (i, -m) is
+        // node (mirror - i, m) across the cut (no shifts on these meshes)
         int wi = 0, wj = 0;
         bool valid = true;
         if (cg) {
-            if (jg < 0) { ig = ni - 1 - ig; jg = -jg; }
-            valid = ig >= 0 && ig < ni && jg < nj;
+            if (jg < 0) { ig = P.mirror - ig; jg = -jg; }
+            if (P.exits) {
+                valid = ig >= 0 && ig < ni && jg < nj;
+            } else {
+                ig = wrap(ig, ni);
+                valid = jg < nj;
+            }
         } else {
             while (ig < 0) { ig += ni; --wi; }
             while (ig >= ni) { ig -= ni; ++wi; }
@@ -603,18 +640,30 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         }
         const int idx = jg * ni + ig;
         const double2 Xr = gld(P.X + idx);
-        float2 dn = make_float2((float)(-Drx), (float)(-Dry)), dd = make_float2(0.0f, 0.0f);
-        if (body.present) {
-            // blending factor and displacements from the unshifted node
-            const double r = blend_factor(P, idx, Xr.x, Xr.y);
+        // blending factors and displacements from the unshifted node: every
+        // body moves the nodes of its own region of influence
+        double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
+        bool moved = false;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (k >= nbody || !P.body[k].present) continue;
+            const double r = blend_factor(P, k, idx, Xr.x, Xr.y);
             if (r < 1.0) {
                 double d0x, d0y, d1x, d1y;
-                rigid_disp(body, sn, Xr.x, Xr.y, d0x, d0y);
-                rigid_disp(body, sn1, Xr.x, Xr.y, d1x, d1y);
+                rigid_disp(P.body[k], sn[k], Xr.x, Xr.y, d0x, d0y);
+                rigid_disp(P.body[k], sn1[k], Xr.x, Xr.y, d1x, d1y);
                 const double om = 1.0 - r;
-                dn = make_float2((float)(om * d0x - Drx), (float)(om * d0y - Dry));
-                dd = make_float2((float)(om * (d1x - d0x)), (float)(om * (d1y - d0y)));
+                a0x += om * d0x;
+                a0y += om * d0y;
+                a1x += om * (d1x - d0x);
+                a1y += om * (d1y - d0y);
+                moved = true;
             }
+        }
+        float2 dn = make_float2((float)(-Drx), (float)(-Dry)), dd = make_float2(0.0f, 0.0f);
+        if (moved) {
+            dn = make_float2((float)(a0x - Drx), (float)(a0y - Dry));
+            dd = make_float2((float)a1x, (float)a1y);
         }
         sm.Xu[e] = make_float2((float)(Xr.x - Xrx + ((double)wi * P.shift_ix + (double)wj * P.shift_jx)),
                                (float)(Xr.y - Xry + ((double)wi * P.shift_iy + (double)wj * P.shift_jy)));
@@ -684,11 +733,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const int ig = i0 - 1 + u1, jg = j0 - 1 + v1;
         if (!node_exists(P, ig, jg, cg)) continue;
         if (cg && jg < 0) {
-            // row -1 across the wake cut: the exported row-1 state of the
-            // mirrored column (only cut columns and the trailing edge are
-            // ever interpolated from)
+            // row -1 across the cut: the exported row-1 state of the mirrored
+            // column (only cut columns and duplicated wall points are ever
+            // interpolated from)
             if constexpr (!EXPORT) {
-                const int slot = cut_slot(P, ni - 1 - ig);
+                const int slot = cut_slot(P, mirror_col(P, P.exits ? ig : wrap(ig, ni)));
                 if (slot >= 0) {
 #pragma unroll
                     for (int k = 0; k < NMOV; ++k) sm.u.FG[k][e] = P.cutbuf[k * P.cut_n + slot];
@@ -706,9 +755,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const float dx_eta = dsten(Dx, 2 * c, 2 * R2X, js), dy_eta = dsten(Dx + 1, 2 * c, 2 * R2X, js);
         float Fx = idet * (J[3] * dx_xi - J[2] * dx_eta);
         float Fy = idet * (-J[1] * dy_xi + J[0] * dy_eta);
-        // C-grid trailing edge (both copies): no correction, so that the two
-        // copies of the one node collide identically
-        if (cg && jg == 0 && (ig == P.wall_i0 || ig == P.wall_i0 + P.wall_n - 1)) {
+        // duplicated wall points (both copies): no correction, so that the
+        // two copies of the one node collide identically
+        if (cg && jg == 0 && dup_point(P, P.exits ? ig : wrap(ig, ni))) {
             Fx = 0.0f;
             Fy = 0.0f;
         }
@@ -728,7 +777,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                          i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
         if constexpr (EXPORT) {
             // row-1 state of the cut columns for the tiles across the cut
-            const int slot = cut_slot(P, ig);
+            const int slot = cut_slot(P, P.exits ? ig : wrap(ig, ni));
             if (own && jg == 1 && slot >= 0) {
 #pragma unroll
                 for (int k = 1; k < 9; ++k) {
@@ -758,7 +807,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         if (ig >= ni || jg >= nj) continue;
         // far-field row and C-grid exit columns: boundary kernel
         if (!P.periodic_j && jg == nj - 1) continue;
-        if (cg && (ig == 0 || ig == ni - 1)) continue;
+        if (cg && P.exits && (ig == 0 || ig == ni - 1)) continue;
         const int c3 = (vt + 3) * R3X + (ut + 3);
         const bool wall = !P.periodic_j && jg == 0 && wall_col(P, ig, cg);
         const Sten js = jstencil(P, ig, jg, cg);
@@ -843,7 +892,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             }
             const float a = li ? -uu : uu;
             float bb = lj ? -vv : vv;
-            if (wall && vv < -1e-5f) { miss |= (uint16_t)(1u << k); continue; }
+            // a point more than 1e-4 of the cell below the wall line lies in
+            // the body (nearer, it counts as on the line)
+            if (wall && vv < -1e-4f) { miss |= (uint16_t)(1u << k); continue; }
             if (!(fabsf(a) <= 1.0f + 1e-4f) || !(fabsf(bb) <= 1.0f + 1e-4f)) err |= ERR_CFL;
             bb -= (float)vc;
             const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
@@ -922,24 +973,42 @@ __device__ __forceinline__ void load_node(const Inst &P, const void *base, long 
     }
 }
 
-// physical position of node idx at the level of slot s (FP64)
-__device__ __forceinline__ void node_pos(const Inst &P, long long idx, const BodySlot &s, double &x,
+// physical position of node idx at the level whose body states are s[] (FP64):
+// every body moves the nodes of its own region of influence
+__device__ __forceinline__ void node_pos(const Inst &P, long long idx, const BodySlot *s, double &x,
                                          double &y) {
     const double2 X = P.X[idx];
-    const double r = blend_factor(P, idx, X.x, X.y);
     x = X.x;
     y = X.y;
-    if (r < 1.0) {
-        double dx, dy;
-        rigid_disp(P.body, s, X.x, X.y, dx, dy);
-        x += (1.0 - r) * dx;
-        y += (1.0 - r) * dy;
+    for (int k = 0; k < P.nbody; ++k) {
+        const double r = blend_factor(P, k, idx, X.x, X.y);
+        if (r < 1.0) {
+            double dx, dy;
+            rigid_disp(P.body[k], s[k], X.x, X.y, dx, dy);
+            x += (1.0 - r) * dx;
+            y += (1.0 - r) * dy;
+        }
     }
+}
+
+// wall block blk (BND columns of one wall segment): its segment and first
+// column; false past the last block
+__device__ __forceinline__ bool wall_block(const Inst &P, int blk, int &seg, int &c0) {
+    for (int k = 0; k < P.n_seg; ++k) {
+        const int nb = (P.seg_n[k] + BND - 1) / BND;
+        if (blk < nb) {
+            seg = k;
+            c0 = P.seg_i0[k] + blk * BND;
+            return true;
+        }
+        blk -= nb;
+    }
+    return false;
 }
 
 // Wall targets (Grad BC, Sec. III.A.1) for item.y even, far-field
 // equilibria (Sec. III.A.2) for item.y odd; item.y >> 1 is the block of 64
-// wall nodes (from column wall_i0) or of 64 far-field list entries.
+// wall nodes (of one wall segment) or of 64 far-field list entries.
 //   rho_t, T_t : values at B (distance dt along the wall normal), 9-node
 //                Lagrange element centred on row 1; the wall row of the
 //                element holds the previous step's values
@@ -957,7 +1026,9 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
     void *dst = P.pop[(n + 1) & 1];
     const int ni = P.ni, t = threadIdx.x;
     if (kind == 0) {
-        const int i0 = P.wall_i0 + blk * BND;
+        int seg, i0;
+        if (!wall_block(P, blk, seg, i0)) return;
+        const int iend = P.seg_i0[seg] + P.seg_n[seg];
         for (int e = t; e < 3 * (BND + 2); e += BND) {
             const int r = e / (BND + 2), c = e % (BND + 2);
             const int ig = wrap(i0 - 1 + c, ni);
@@ -969,7 +1040,7 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
         }
         __syncthreads();
         const int ig = i0 + t;
-        if (ig >= P.wall_i0 + P.wall_n) return;
+        if (ig >= iend) return;
         const float2 B = P.wall_B[ig];
         const float a = B.x, b = B.y - 1.0f;   // offsets from the element centre (i, 1)
         float rho_t = 0.0f, T_t = 0.0f;
@@ -981,17 +1052,20 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
                 rho_t += w * s_rho[q + 1][t + 1 + p];
                 T_t += w * s_T[q + 1][t + 1 + p];
             }
-        float VGx = 0.0f, VGy = 0.0f;
+        double vx = 0.0, vy = 0.0;
         const double2 X = P.X[ig];
-        const double r = blend_factor(P, ig, X.x, X.y);
-        if (r < 1.0) {
-            double d1x, d1y, d0x, d0y;
-            rigid_disp(P.body, P.slots[(n + 1) % 3], X.x, X.y, d1x, d1y);
-            rigid_disp(P.body, P.slots[n % 3], X.x, X.y, d0x, d0y);
-            VGx = (float)((1.0 - r) * (d1x - d0x) / P.dt_d);
-            VGy = (float)((1.0 - r) * (d1y - d0y) / P.dt_d);
+        const BodySlot *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES, *s0 = P.slots + (n % 3) * MAX_BODIES;
+        for (int k = 0; k < P.nbody; ++k) {
+            const double r = blend_factor(P, k, ig, X.x, X.y);
+            if (r < 1.0) {
+                double d1x, d1y, d0x, d0y;
+                rigid_disp(P.body[k], s1[k], X.x, X.y, d1x, d1y);
+                rigid_disp(P.body[k], s0[k], X.x, X.y, d0x, d0y);
+                vx += (1.0 - r) * (d1x - d0x) / P.dt_d;
+                vy += (1.0 - r) * (d1y - d0y) / P.dt_d;
+            }
         }
-        P.wall_tgt[ig] = make_float4(rho_t, VGx, VGy, T_t);
+        P.wall_tgt[ig] = make_float4(rho_t, (float)vx, (float)vy, T_t);
     } else {
         const int k = blk * BND + t;
         if (k >= P.n_ff) return;
@@ -1032,12 +1106,12 @@ __device__ __forceinline__ float4 wall_neighbour(const Inst &P, const void *buf,
 // of the level in `buf`: f, g enter as loaded and leave with the missing ones
 // replaced (unrounded).
 template <int STORE>
-__device__ void grad_fill(const Inst &P, const void *buf, const BodySlot &sL, int ig, float f[9],
+__device__ void grad_fill(const Inst &P, const void *buf, const BodySlot *sL, int ig, float f[9],
                           float g[9]) {
     const uint16_t miss = P.wall_mask[ig];
     if (!miss) return;
     const int ni = P.ni;
-    const int im = P.cgrid ? ig - 1 : wrap(ig - 1, ni), ip = P.cgrid ? ig + 1 : wrap(ig + 1, ni);
+    const int im = P.exits ? ig - 1 : wrap(ig - 1, ni), ip = P.exits ? ig + 1 : wrap(ig + 1, ni);
     double xm, ym, xp, yp, x0, y0;
     node_pos(P, im, sL, xm, ym);
     node_pos(P, ip, sL, xp, yp);
@@ -1113,13 +1187,14 @@ __device__ void grad_fill(const Inst &P, const void *buf, const BodySlot &sL, in
 }
 
 // Grad populations for the missing wall populations (phase 1 only) and the
-// traction F_k = sigma . (n ds)_k of every node of the wall polygon at the
-// current level (Sec. III: sigma = -p I - (1 - omega/2) P^(1),
+// traction F_k = sigma . (n ds)_k of every node of each body's wall polygon at
+// the current level (Sec. III: sigma = -p I - (1 - omega/2) P^(1),
 // P^(1) = sum (f - f^eq) c c; (n ds)_k = 1/2 rot_{+90}(x_{k+1} - x_{k-1}) with
-// k +- 1 the polygon neighbours).  C-grid: the thread of the lower
-// trailing-edge copy also fills the upper copy and stores one merged state in
-// both: population by population the streamed value of the copy that found its
-// departure point, else the mean of the two copies.
+// k +- 1 the polygon neighbours).  A wall segment that ends on a second copy
+// of its first point (a C-grid's trailing edge, a twin O-grid's junctions):
+// the thread of the first copy also fills the second and stores one merged
+// state in both: population by population the streamed value of the copy that
+// found its departure point, else the mean of the two copies.
 template <int STORE>
 __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict__ insts,
                                                          const int2 *__restrict__ work, int n_work,
@@ -1127,19 +1202,22 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
     if ((int)blockIdx.x >= n_work) return;
     const int2 item = work[blockIdx.x];
     const Inst &P = insts[item.x];
-    const int ig = P.wall_i0 + item.y * BND + threadIdx.x;
-    if (ig >= P.wall_i0 + P.wall_n) return;
-    const int te_up = P.wall_i0 + P.wall_n - 1;
-    if (P.cgrid && ig == te_up) return;       // handled with the lower copy
+    int seg, c0;
+    if (!wall_block(P, item.y, seg, c0)) return;
+    const int ig = c0 + threadIdx.x;
+    const int w0 = P.seg_i0[seg], dup = P.seg_dup[seg];
+    if (ig >= w0 + P.seg_n[seg]) return;
+    const int te_up = w0 + P.seg_n[seg] - 1;
+    if (dup && ig == te_up) return;           // handled with the first copy
     const long long n = *P.step;
     const long long L = phase ? n + 1 : n;
     void *buf = P.pop[L & 1];
-    const BodySlot sL = P.slots[L % 3];
+    const BodySlot *sL = P.slots + (L % 3) * MAX_BODIES;
     float f[9], g[9];
     load_node<STORE>(P, buf, ig, f, g);
     if (phase) {
         grad_fill<STORE>(P, buf, sL, ig, f, g);
-        if (P.cgrid && ig == P.wall_i0) {
+        if (dup && ig == w0) {
             float fu[9], gu[9];
             load_node<STORE>(P, buf, te_up, fu, gu);
             grad_fill<STORE>(P, buf, sL, te_up, fu, gu);
@@ -1174,8 +1252,9 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
     }
     // traction of the complete wall node, with the moments formed in FP64
     // from the stored populations; normals from the polygon neighbours
-    const int fm = ig == P.wall_i0 ? P.wall_i0 + P.force_n - 1 : ig - 1;
-    const int fp = ig == P.wall_i0 + P.force_n - 1 ? P.wall_i0 : ig + 1;
+    const int fn = P.seg_n[seg] - dup;       // distinct nodes of the polygon
+    const int fm = ig == w0 ? w0 + fn - 1 : ig - 1;
+    const int fp = ig == w0 + fn - 1 ? w0 : ig + 1;
     double xm, ym, xp, yp, x0, y0;
     node_pos(P, fm, sL, xm, ym);
     node_pos(P, fp, sL, xp, yp);
@@ -1215,7 +1294,7 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
     const double nx = -0.5 * (yp - ym), ny = 0.5 * (xp - xm);
     const double Fx = sxx * nx + sxy * ny;
     const double Fy = sxy * nx + syy * ny;
-    const double rx = x0 - P.body.ex, ry = y0 - (P.body.ey + sL.h);
+    const double rx = x0 - P.body[seg].ex, ry = y0 - (P.body[seg].ey + sL[seg].h);
     P.wall_force[ig] = make_double4(Fx, Fy, rx * Fy - ry * Fx, 0.0);
     if (!state_ok((float)rho, (float)ux, (float)uy, (float)T)) atomicOr(P.err, ERR_STATE);
 }
@@ -1279,45 +1358,71 @@ __global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ 
     const int t = threadIdx.x;
     const long long n = *P.step;
     const long long L = phase ? n + 1 : n;
-    double fx = 0.0, fy = 0.0, mz = 0.0;
-    if (!P.periodic_j) {
-        for (int i = t; i < P.force_n; i += BODY_THREADS) {
-            const double4 v = P.wall_force[P.wall_i0 + i];
+    // the load of every body: the traction sum over its wall polygon
+    double F[MAX_BODIES][3] = {};
+    for (int k = 0; k < P.n_seg; ++k) {
+        double fx = 0.0, fy = 0.0, mz = 0.0;
+        const int fn = P.seg_n[k] - P.seg_dup[k];
+        for (int i = t; i < fn; i += BODY_THREADS) {
+            const double4 v = P.wall_force[P.seg_i0[k] + i];
             fx += v.x;
             fy += v.y;
             mz += v.z;
         }
-    }
-    if (phase && P.cgrid) {
-        // one state per cut point: the upper copy of each cut node takes the
-        // lower copy's populations (the trailing edge is merged at the wall)
-        void *buf = P.pop[(n + 1) & 1];
-        const size_t bpp = P.storage ? 2 : 4;
-        for (int e = t; e < NPOP * P.n_wake; e += BODY_THREADS) {
-            const int q = e / P.n_wake, i = e % P.n_wake;
-            char *base = static_cast<char *>(buf) + (size_t)q * P.n_nodes * bpp;
-            if (bpp == 4)
-                reinterpret_cast<float *>(base)[P.ni - 1 - i] = reinterpret_cast<const float *>(base)[i];
-            else
-                reinterpret_cast<uint16_t *>(base)[P.ni - 1 - i] = reinterpret_cast<const uint16_t *>(base)[i];
+        sx[t] = fx; sy[t] = fy; sz[t] = mz;
+        __syncthreads();
+        for (int s = BODY_THREADS / 2; s > 0; s >>= 1) {
+            if (t < s) {
+                sx[t] += sx[t + s];
+                sy[t] += sy[t + s];
+                sz[t] += sz[t + s];
+            }
+            __syncthreads();
         }
-    }
-    sx[t] = fx; sy[t] = fy; sz[t] = mz;
-    __syncthreads();
-    for (int s = BODY_THREADS / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            sx[t] += sx[t + s];
-            sy[t] += sy[t + s];
-            sz[t] += sz[t + s];
-        }
+        F[k][0] = sx[0];
+        F[k][1] = sy[0];
+        F[k][2] = sz[0];
         __syncthreads();
     }
+    if (phase && P.cut) {
+        // one state per cut point: the mirror copy of each primary cut node
+        // takes its populations (duplicated wall points are merged at the wall)
+        void *buf = P.pop[(n + 1) & 1];
+        const size_t bpp = P.storage ? 2 : 4;
+        const int np = P.cut_b - P.cut_a - 1;
+        for (int e = t; e < NPOP * np; e += BODY_THREADS) {
+            const int q = e / np, c = P.cut_a + 1 + e % np;
+            const int m = P.exits ? P.mirror - c : wrap(P.mirror - c, P.ni);
+            char *base = static_cast<char *>(buf) + (size_t)q * P.n_nodes * bpp;
+            if (bpp == 4)
+                reinterpret_cast<float *>(base)[m] = reinterpret_cast<const float *>(base)[c];
+            else
+                reinterpret_cast<uint16_t *>(base)[m] = reinterpret_cast<const uint16_t *>(base)[c];
+        }
+    }
     if (t == 0) {
-        const BodySlot cur = P.slots[L % 3];
-        double *rec = P.history + (L % HIST_CAP) * 6;
-        rec[0] = (double)L; rec[1] = sx[0]; rec[2] = sy[0]; rec[3] = sz[0];
-        rec[4] = cur.h; rec[5] = cur.a;
-        P.slots[(L + 1) % 3] = body_advance(P.body, cur, sy[0], sz[0], (double)(L + 1) * P.dt_d, P.dt_d);
+        const BodySlot *cur = P.slots + (L % 3) * MAX_BODIES;
+        BodySlot *nxt = P.slots + ((L + 1) % 3) * MAX_BODIES;
+        const int nrec = P.nbody > 0 ? P.nbody : 1;
+        for (int k = 0; k < nrec; ++k) {
+            double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(L % HIST_CAP)) * 6;
+            rec[0] = (double)L; rec[1] = F[k][0]; rec[2] = F[k][1]; rec[3] = F[k][2];
+            rec[4] = cur[k].h; rec[5] = cur[k].a;
+        }
+        // each body with an equation of its own takes its load plus those of
+        // the bodies linked to it; linked bodies then take its new state
+        for (int m = 0; m < nrec; ++m) {
+            if (P.body[m].master != m) continue;
+            double fy = 0.0, mz = 0.0;
+            for (int k = 0; k < nrec; ++k) {
+                if (P.body[k].master != m) continue;
+                fy += F[k][1];
+                mz += F[k][2];
+            }
+            nxt[m] = body_advance(P.body[m], cur[m], fy, mz, (double)(L + 1) * P.dt_d, P.dt_d);
+        }
+        for (int k = 0; k < nrec; ++k)
+            if (P.body[k].master != k) nxt[k] = nxt[P.body[k].master];
         if (phase) *P.step = n + 1;
     }
 }
@@ -1402,7 +1507,7 @@ __global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const
     } while (0)
 
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid, bool cgrid, int shape) {
+                                 hipStream_t s, int grid, bool cut, int shape) {
     // one workgroup per item unless a smaller (persistent) grid is requested;
     // always a multiple of the XCD count
     const int all = ((n_work + 7) / 8) * 8;
@@ -1411,19 +1516,19 @@ hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work
     if (g < 8) g = 8;
     // the C-grid-capable build (default tile shape only) when some instance of
     // the launch needs it
-    if (cgrid && shape != 0) return hipErrorInvalidValue;
+    if (cut && shape != 0) return hipErrorInvalidValue;
     if (shape < 0 || shape >= N_TILE_SHAPES) return hipErrorInvalidValue;
     const dim3 G(g), B(TILE_SHAPES[shape][0] * TILE_SHAPES[shape][1]);
 #define FSI_K1(ST, CGV, TXV, TYV) \
     hipLaunchKernelGGL((k_collide_stream<ST, CGV, TXV, TYV>), G, B, 0, s, insts, work, n_work)
     if (storage == 0) {
-        if (cgrid) FSI_K1(0, true, TILE_X, TILE_Y);
+        if (cut) FSI_K1(0, true, TILE_X, TILE_Y);
         else if (shape == 1) FSI_K1(0, false, 64, 8);
         else if (shape == 2) FSI_K1(0, false, 16, 32);
         else if (shape == 3) FSI_K1(0, false, 16, 16);
         else FSI_K1(0, false, TILE_X, TILE_Y);
     } else {
-        if (cgrid) FSI_K1(1, true, TILE_X, TILE_Y);
+        if (cut) FSI_K1(1, true, TILE_X, TILE_Y);
         else if (shape == 1) FSI_K1(1, false, 64, 8);
         else if (shape == 2) FSI_K1(1, false, 16, 32);
         else if (shape == 3) FSI_K1(1, false, 16, 16);

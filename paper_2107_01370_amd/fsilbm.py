@@ -49,7 +49,8 @@ class FluidParams(ctypes.Structure):
 class MeshDesc(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("topo", ctypes.c_int),
                 ("X", ctypes.POINTER(ctypes.c_double)), ("shift_i", ctypes.c_double * 2),
-                ("shift_j", ctypes.c_double * 2), ("n_wake", ctypes.c_int)]
+                ("shift_j", ctypes.c_double * 2), ("n_wake", ctypes.c_int),
+                ("n_wall2", ctypes.c_int)]
 
 
 class BodyDesc(ctypes.Structure):
@@ -61,7 +62,7 @@ class BodyDesc(ctypes.Structure):
                 ("ad0", ctypes.c_double), ("heave_amp", ctypes.c_double),
                 ("heave_freq", ctypes.c_double), ("pitch_amp", ctypes.c_double),
                 ("pitch_freq", ctypes.c_double), ("release_time", ctypes.c_double),
-                ("blend_mode", ctypes.c_int)]
+                ("blend_mode", ctypes.c_int), ("link", ctypes.c_int)]
 
 
 _lib = None
@@ -110,9 +111,9 @@ def load_library(path: str = LIB_PATH):
         "fsi_batch_autotune": (ctypes.c_int, [P, ctypes.c_int, dp]),
         "fsi_batch_step": (ctypes.c_int, [P, ctypes.c_int]),
         "fsi_batch_synchronize": (ctypes.c_int, [P]),
-        "fsi_batch_get_forces": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
-                                                dp]),
-        "fsi_batch_get_body_state": (ctypes.c_int, [P, ctypes.c_int, dp]),
+        "fsi_batch_get_forces": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                                ctypes.c_int, dp]),
+        "fsi_batch_get_body_state": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, dp]),
         "fsi_batch_dump_macro": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
         "fsi_batch_get_populations": (ctypes.c_int, [P, ctypes.c_int, fp, fp]),
         "fsi_batch_time_kernels": (ctypes.c_int, [P, ctypes.c_int, dp]),
@@ -161,7 +162,7 @@ def _mesh_struct(mesh):
     X = np.ascontiguousarray(mesh.interleaved(), dtype=np.float64)
     md = MeshDesc(mesh.ni, mesh.nj, mesh.topo, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                   (ctypes.c_double * 2)(*mesh.shift_i), (ctypes.c_double * 2)(*mesh.shift_j),
-                  int(getattr(mesh, "n_wake", 0)))
+                  int(getattr(mesh, "n_wake", 0)), int(getattr(mesh, "n_wall2", 0)))
     return md, X
 
 
@@ -170,12 +171,13 @@ def _body_struct(b):
                     (ctypes.c_double * 2)(*b.center), (ctypes.c_double * 2)(*b.ea),
                     b.r_rigid, b.r_blend, b.h0, b.a0, b.hd0, b.ad0, b.heave_amp,
                     b.heave_freq, b.pitch_amp, b.pitch_freq,
-                    float(getattr(b, "release_time", 0.0)), int(getattr(b, "blend_mode", 0)))
+                    float(getattr(b, "release_time", 0.0)), int(getattr(b, "blend_mode", 0)),
+                    int(getattr(b, "link", -1)))
 
 
 def fsi_create(fluid, mesh, bodies=(), stream_handle=None):
     """fluid: synth.FluidParams-like; mesh: synth.MeshSpec-like; bodies: list of
-    BodyParams-like (0 or 1).  Returns the context handle."""
+    BodyParams-like (0 or 1; 2 on a twin O-grid).  Returns the context handle."""
     lib = load_library()
     fp = _fluid_struct(fluid)
     md, X = _mesh_struct(mesh)
@@ -300,24 +302,24 @@ def _bcheck(b, status):
 
 
 def fsi_batch_create(cases, stream_handle=None):
-    """cases: sequence of (fluid, mesh, bodies) with 0 or 1 body each."""
+    """cases: sequence of (fluid, mesh, bodies); the bodies of all instances
+    go to the library back to back."""
     lib = load_library()
     n = len(cases)
     fl = (FluidParams * n)()
     ms = (MeshDesc * n)()
-    bd = (BodyDesc * n)()
     nb = (ctypes.c_int * n)()
+    all_bodies = [b for (_, _, bodies) in cases for b in bodies]
+    bd = (BodyDesc * max(1, len(all_bodies)))()
+    for q, b in enumerate(all_bodies):
+        bd[q] = _body_struct(b)
     keep = []
     for k, (fluid, mesh, bodies) in enumerate(cases):
-        if len(bodies) > 1:
-            raise FsiError(-1, "at most one body per batch instance")
         fl[k] = _fluid_struct(fluid)
         md, X = _mesh_struct(mesh)
         keep.append(X)
         ms[k] = md
-        if bodies:
-            bd[k] = _body_struct(bodies[0])
-            nb[k] = 1
+        nb[k] = len(bodies)
     b = ctypes.c_void_p()
     st = lib.fsi_batch_create(n, fl, ms, bd, nb, ctypes.c_void_p(stream_handle or 0),
                               ctypes.byref(b))
@@ -365,15 +367,16 @@ def fsi_batch_synchronize(b):
     _bcheck(b, _lib.fsi_batch_synchronize(b))
 
 
-def fsi_batch_get_forces(b, k, first, count):
+def fsi_batch_get_forces(b, k, first, count, body=0):
     out = np.zeros((count, 6), dtype=np.float64)
-    _bcheck(b, _lib.fsi_batch_get_forces(b, int(k), int(first), int(count), _dptr(out)))
+    _bcheck(b, _lib.fsi_batch_get_forces(b, int(k), int(body), int(first), int(count),
+                                         _dptr(out)))
     return out
 
 
-def fsi_batch_get_body_state(b, k):
+def fsi_batch_get_body_state(b, k, body=0):
     out = np.zeros(4, dtype=np.float64)
-    _bcheck(b, _lib.fsi_batch_get_body_state(b, int(k), _dptr(out)))
+    _bcheck(b, _lib.fsi_batch_get_body_state(b, int(k), int(body), _dptr(out)))
     return out
 
 
@@ -451,11 +454,11 @@ class Simulation:
     def step_count(self):
         return fsi_get_step(self.ctx)
 
-    def forces(self, first, count):
-        return fsi_get_forces(self.ctx, first, count)
+    def forces(self, first, count, body=0):
+        return fsi_get_forces(self.ctx, first, count, body)
 
-    def body_state(self):
-        return fsi_get_body_state(self.ctx)
+    def body_state(self, body=0):
+        return fsi_get_body_state(self.ctx, body)
 
     def macro(self):
         return fsi_dump_macro(self.ctx, self.shape)
@@ -536,11 +539,11 @@ class Batch:
     def synchronize(self):
         fsi_batch_synchronize(self.b)
 
-    def forces(self, k, first, count):
-        return fsi_batch_get_forces(self.b, k, first, count)
+    def forces(self, k, first, count, body=0):
+        return fsi_batch_get_forces(self.b, k, first, count, body)
 
-    def body_state(self, k):
-        return fsi_batch_get_body_state(self.b, k)
+    def body_state(self, k, body=0):
+        return fsi_batch_get_body_state(self.b, k, body)
 
     def macro(self, k):
         return fsi_batch_dump_macro(self.b, k, self.shapes[k])

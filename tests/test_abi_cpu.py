@@ -257,3 +257,70 @@ def test_release_and_distance_blending_are_validated(F):
     with pytest.raises(F.FsiError) as e:
         F.fsi_create(a.fluid, a.mesh, [body], None)
     assert e.value.status == -1 and "wall" in str(e.value)
+
+
+# ---- twin O-grid: two bodies ---------------------------------------------------
+
+def test_twin_tandem_cases_are_accepted(F):
+    for linked in (False, True):
+        c = synth.small_tandem_case(linked=linked)
+        ctx = F.fsi_create(c.fluid, c.mesh, c.bodies, None)
+        F.fsi_destroy(ctx)
+    big = synth.tandem_cylinders_case()
+    ctx = F.fsi_create(big.fluid, big.mesh, big.bodies, None)
+    F.fsi_destroy(ctx)
+
+
+def test_twin_body_count_links_and_regions_are_validated(F):
+    c = synth.small_tandem_case()
+    b0, b1 = c.bodies
+    R = synth.configs.replace
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(c.fluid, c.mesh, [b0], None)
+    assert e.value.status == -1 and "2 bodies" in str(e.value)
+    for bad in ([R(b0, link=0), b1], [R(b0, link=1), b1], [b0, R(b1, link=1)],
+                [b0, R(b1, link=5)]):
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_create(c.fluid, c.mesh, bad, None)
+        assert e.value.status == -1 and "link" in str(e.value)
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(c.fluid, c.mesh, [b0, R(b1, r_blend=75.0)], None)
+    assert e.value.status == -1 and "overlap" in str(e.value)
+    # a linked body's own equation parameters are ignored (m = 0 is fine)
+    ctx = F.fsi_create(c.fluid, c.mesh, [b0, R(b1, link=0, m=0.0, dof=7)], None)
+    F.fsi_destroy(ctx)
+    # distance blending from each body's own wall
+    dist = [R(b0, blend_mode=1, r_rigid=1.0, r_blend=12.0),
+            R(b1, blend_mode=1, r_rigid=1.0, r_blend=12.0)]
+    ctx = F.fsi_create(c.fluid, c.mesh, dist, None)
+    F.fsi_destroy(ctx)
+
+
+def test_twin_mesh_with_unmatched_slit_or_sizes_is_rejected(F):
+    c = synth.small_tandem_case()
+    m = c.mesh
+    X = m.X.copy()
+    X[0, m.ni - 2] += 1e-3                     # a slit node no longer meets its twin
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(c.fluid, synth.configs.replace(m, X=X), c.bodies, None)
+    assert e.value.status == -2 and "coincide" in str(e.value)
+    for bad in (dict(n_wake=1), dict(n_wall2=4), dict(n_wall2=m.ni)):
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_create(c.fluid, synth.configs.replace(m, **bad), c.bodies, None)
+        assert e.value.status == -2
+
+
+def test_batch_takes_bodies_back_to_back(F):
+    t = synth.small_tandem_case()
+    o = synth.cylinder_viv_case(n_r=40, n_theta=80, D=40.0, first_cell_frac=0.025,
+                                r_far_D=10.0, blend_D=4.0)
+    p = synth.acoustic_pulse_case()
+    b = F.fsi_batch_create([(o.fluid, o.mesh, o.bodies), (p.fluid, p.mesh, []),
+                            (t.fluid, t.mesh, t.bodies)])
+    try:
+        assert F.fsi_batch_nodes(b) == o.mesh.n_nodes + p.mesh.n_nodes + t.mesh.n_nodes
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_batch_set_schedule(b, 0, 0, 2)
+        assert e.value.status == -1
+    finally:
+        F.fsi_batch_destroy(b)

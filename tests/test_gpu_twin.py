@@ -1,0 +1,142 @@
+"""GPU parity with two bodies on the twin O-grid (tandem cylinders joined by a
+slit): independent cylinders (one equation each) and a linked pair (one
+equation, both loads), against the FP64 oracle through the C ABI.
+
+As on the other walls, whether a wall population is missing is decided in
+FP32 by the kernel and in FP64 by the oracle; the multi-step cases check on
+the oracle side that no wall departure point comes within MARGIN of the
+decision line."""
+
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.solver import OracleSolver
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-5          # several times the kernel's FP32 rounding of the offset (~2e-6)
+
+
+def paired(c, fluid=None):
+    from paper_2107_01370_amd.fsilbm import Simulation
+    fl = fluid or c.fluid
+    sim = Simulation(c.mesh, fl, c.bodies)
+    sim.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+    f0, g0 = sim.populations()
+    ora = OracleSolver(c.mesh, c.fluid, c.bodies, c.rho, c.ux, c.uy, c.T)
+    ora.f = f0.astype(np.float64)
+    ora.g = g0.astype(np.float64)
+    return sim, ora
+
+
+def duplicated_columns(mesh):
+    """(column, its twin) for every point of row 0 that is stored twice."""
+    ni, s, nB = mesh.ni, mesh.n_wake, mesh.n_wall2
+    nA = ni - 2 * s - nB
+    return [(i, (nA - i) % ni) for i in range(nA, nA + s + 1)]
+
+
+def test_twin_one_step_population_parity():
+    c = synth.small_tandem_case()
+    sim, ora = paired(c)
+    sim.step(1)
+    ora.step()
+    f, g = sim.populations()
+    assert np.max(np.abs(f - ora.f)) <= 1e-6 * np.max(np.abs(ora.f))
+    assert np.max(np.abs(g - ora.g)) <= 1e-6 * np.max(np.abs(ora.g))
+    for i, m in duplicated_columns(c.mesh):
+        assert np.array_equal(f[:, 0, i], f[:, 0, m]) and np.array_equal(g[:, 0, i], g[:, 0, m]), i
+
+
+@pytest.mark.parametrize("linked", [False, True])
+def test_tandem_cylinders_60_steps(wall_margin, linked):
+    c = synth.small_tandem_case(linked=linked)
+    sim, ora = paired(c)
+    n = 60
+    sim.step(n)
+    with wall_margin() as margin:
+        ora.run(n)
+    assert margin[0] >= MARGIN
+    rho, ux, uy, T = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(rho - r_o) / r_o) <= 1e-5
+    assert np.max(np.abs(rho * T - r_o * T_o) / (r_o * T_o)) <= 1e-5
+    for k in range(2):
+        hist = sim.forces(0, n, body=k)
+        ho = np.array(ora.histories[k])
+        assert np.array_equal(hist[:, 0], ho[:, 0])
+        fscale = np.max(np.hypot(ho[:, 1], ho[:, 2]))
+        assert np.max(np.abs(hist[:, 1:3] - ho[:, 1:3])) <= 1e-4 * fscale, k
+        h_amp = np.max(np.abs(ho[:, 4] - ho[0, 4]))
+        assert h_amp > 0
+        assert np.max(np.abs(hist[:, 4] - ho[:, 4])) <= 1e-4 * h_amp, k
+        st = sim.body_state(k)
+        assert abs(st[0] - ora.states[k][0]) <= 1e-4 * h_amp
+    if linked:
+        # the linked cylinder moves with the upstream one, bit for bit
+        assert np.array_equal(sim.forces(0, n, body=1)[:, 4], sim.forces(0, n, body=0)[:, 4])
+        assert np.array_equal(sim.body_state(1), sim.body_state(0))
+
+
+def test_twin_fp16_storage_within_2e3():
+    c = synth.small_tandem_case()
+    from paper_2107_01370_amd.fsilbm import Simulation
+    sim = Simulation(c.mesh, replace(c.fluid, storage=1), c.bodies)
+    sim.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+    ora = OracleSolver(c.mesh, c.fluid, c.bodies, c.rho, c.ux, c.uy, c.T)
+    sim.step(40)
+    ora.run(40)
+    rho, ux, uy, T = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(rho - r_o) / r_o) <= 2e-3
+    assert np.max(np.abs(rho * T - r_o * T_o) / (r_o * T_o)) <= 2e-3
+
+
+def test_batch_mixing_twin_and_ogrid_equals_alone():
+    from paper_2107_01370_amd.fsilbm import Batch, Simulation
+    cases = [synth.small_tandem_case(linked=True),
+             synth.cylinder_viv_case(n_r=40, n_theta=80, D=40.0, first_cell_frac=0.025,
+                                     r_far_D=10.0, blend_D=4.0, h0_frac=0.01, mstar=2.0),
+             synth.small_tandem_case(n_wall=40, n_slit=24, nj=36, L_D=2.5)]
+    ref = []
+    for c in cases:
+        s = Simulation(c.mesh, c.fluid, c.bodies)
+        s.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+        s.step(10)
+        ref.append((s.populations(), [s.forces(0, 10, body=k) for k in range(len(c.bodies))]))
+        s.close()
+    b = Batch(cases)
+    for k, c in enumerate(cases):
+        b.init_equilibrium(k, c.rho, c.ux, c.uy, c.T)
+    b.set_schedule(64, 1)
+    b.step(10)
+    b.synchronize()
+    for k, c in enumerate(cases):
+        f, g = b.populations(k)
+        assert np.array_equal(f, ref[k][0][0]) and np.array_equal(g, ref[k][0][1]), k
+        for q in range(len(c.bodies)):
+            assert np.array_equal(b.forces(k, 0, 10, body=q), ref[k][1][q]), (k, q)
+    b.close()
+
+
+def test_tandem_2304x320_full_size_step(wall_margin):
+    """The 2304 x 320 twin O-grid of the tandem-cylinder workload (D = 200,
+    L/D = 5, Re 1000, independent cylinders, launched as the benchmark
+    launches it): one step against the oracle (about 35 s of oracle time)."""
+    c = synth.tandem_cylinders_case(h0_frac=0.01)
+    sim, ora = paired(c)
+    with wall_margin() as margin:
+        sim.step(1)
+        ora.step()
+    assert margin[0] >= MARGIN
+    f, g = sim.populations()
+    assert np.max(np.abs(f - ora.f)) <= 1e-6 * np.max(np.abs(ora.f))
+    assert np.max(np.abs(g - ora.g)) <= 1e-6 * np.max(np.abs(ora.g))
+    for k in range(2):
+        h = sim.forces(0, 1, body=k)
+        ho = np.array(ora.histories[k])
+        scale = np.max(np.abs(ho[:, 1:3]))
+        assert np.max(np.abs(h[:, 1:3] - ho[:, 1:3])) <= 1e-4 * scale
