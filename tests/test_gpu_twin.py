@@ -133,10 +133,22 @@ def test_tandem_2304x320_full_size_step(wall_margin):
         ora.step()
     assert margin[0] >= MARGIN
     f, g = sim.populations()
-    assert np.max(np.abs(f - ora.f)) <= 1e-6 * np.max(np.abs(ora.f))
-    assert np.max(np.abs(g - ora.g)) <= 1e-6 * np.max(np.abs(ora.g))
+    # moving populations within 1e-6 of the population scale; the rest
+    # populations within 2e-6: their equilibria are formed as conserved moment
+    # minus the other eight, which costs a few FP32 ulp of 2 rho E (~1.67 here,
+    # ulp 1.2e-7), and the collision (omega ~ 1.3) carries that over
+    for name, a, b in (("f", f, ora.f), ("g", g, ora.g)):
+        scale = np.max(np.abs(b))
+        err = np.abs(a - b)
+        where = np.unravel_index(np.argmax(err[1:]), err[1:].shape)
+        assert np.max(err[1:]) <= 1e-6 * scale, (name, "moving", where, np.max(err[1:]))
+        where0 = np.unravel_index(np.argmax(err[0]), err[0].shape)
+        assert np.max(err[0]) <= 2e-6 * scale, (name, "rest", where0, np.max(err[0]))
+    # loads on the new populations (the record of step 1): 1e-4 of the load,
+    # plus the FP32 rounding of a pressure sum round the wall (1e-7 p pi D)
+    Fo = ora.body_forces()
+    floor = 1e-7 * c.fluid.T_inf * np.pi * c.info["D"]
     for k in range(2):
-        h = sim.forces(0, 1, body=k)
-        ho = np.array(ora.histories[k])
-        scale = np.max(np.abs(ho[:, 1:3]))
-        assert np.max(np.abs(h[:, 1:3] - ho[:, 1:3])) <= 1e-4 * scale
+        h = sim.forces(1, 1, body=k)[0]
+        for q in (1, 2):
+            assert abs(h[q] - Fo[k][q - 1]) <= 1e-4 * abs(Fo[k][q - 1]) + floor, (k, q, h, Fo[k])
