@@ -8,7 +8,8 @@ counter-clockwise about the elastic axis.
 2DOF (Sec. IV.B):  m h'' + S_a a'' + k_h h = F_y
                    S_a h'' + I_a a'' + k_a a = M_EA
 integrated with the classical fourth-order Runge-Kutta method over one time
-step with the fluid load frozen (staggered weak coupling, Sec. III).
+step with the fluid load frozen (staggered weak coupling, Sec. III), or, in
+the sub-iterations of strong coupling, varying linearly over the step.
 Prescribed motion: h(t) = A_h sin(2 pi f_h t), alpha(t) = A_a sin(2 pi f_a t).
 A fixed body keeps its initial state.
 
@@ -46,17 +47,24 @@ def accelerations(body, h, a, Fy, M):
     raise ValueError("no dynamics for this dof")
 
 
-def rk4_step(body, state, Fy, M, dt):
-    """One RK4 step of the first-order system y' = (hdot, adot, h'', a'')."""
-    def rhs(y):
-        hdd, add = accelerations(body, y[0], y[1], Fy, M)
+def rk4_step(body, state, Fy, M, dt, Fy1=None, M1=None):
+    """One RK4 step of the first-order system y' = (hdot, adot, h'', a'').
+
+    The load is (Fy, M) throughout, or, with (Fy1, M1), varies linearly in
+    time from (Fy, M) at the start of the step to (Fy1, M1) at its end (each
+    stage takes the load at its own time)."""
+    if Fy1 is None:
+        Fy1, M1 = Fy, M
+
+    def rhs(y, c):
+        hdd, add = accelerations(body, y[0], y[1], Fy + c * (Fy1 - Fy), M + c * (M1 - M))
         return np.array([y[2], y[3], hdd, add])
 
     y = np.asarray(state, dtype=np.float64)
-    k1 = rhs(y)
-    k2 = rhs(y + 0.5 * dt * k1)
-    k3 = rhs(y + 0.5 * dt * k2)
-    k4 = rhs(y + dt * k3)
+    k1 = rhs(y, 0.0)
+    k2 = rhs(y + 0.5 * dt * k1, 0.5)
+    k3 = rhs(y + 0.5 * dt * k2, 0.5)
+    k4 = rhs(y + dt * k3, 1.0)
     return y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
@@ -81,10 +89,11 @@ def initial_state(body):
     return np.array([body.h0, body.a0, body.hd0, body.ad0], dtype=np.float64)
 
 
-def advance(body, state, Fy, M, t_next, dt):
-    """State at t^{n+1} from the state at t^n and the frozen load at t^n."""
+def advance(body, state, Fy, M, t_next, dt, Fy1=None, M1=None):
+    """State at t^{n+1} from the state at t^n and the frozen load at t^n, or
+    (with Fy1, M1) the load varying linearly to (Fy1, M1) at t^{n+1}."""
     if body.dof == DOF_PRESCRIBED or forced(body, t_next):
         return prescribed_state(body, t_next)
     if body.dof == DOF_FIXED:
         return np.asarray(state, dtype=np.float64).copy()
-    return rk4_step(body, state, Fy, M, dt)
+    return rk4_step(body, state, Fy, M, dt, Fy1, M1)

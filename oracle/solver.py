@@ -130,6 +130,27 @@ class OracleSolver:
                 self.walls.append((self.X[0, cols], self.Y[0, cols]))
         self.wall = self.walls[0] if self.walls else None
         self._r_cache = None
+        self.subiterations = 1
+        self.relaxation = 1.0
+        self.residuals = []
+
+    def coupling(self, subiterations=1, relaxation=1.0):
+        """Strong coupling by sub-iterations (the alternative to the staggered
+        scheme that Sec. III names for low mass ratios; the paper gives no
+        algorithm).  Reading: each step starts from the staggered predictor
+        (the structure advanced with the load at t^n frozen); a sub-iteration
+        streams the post-collision populations of t^n onto the mesh of the
+        current structure estimate, applies the boundary conditions, takes the
+        load F^{n+1} of the result, re-solves the structure over the step with
+        the load varying linearly from F^n to F^{n+1}, and relaxes the estimate
+        towards that solution with the factor `relaxation`.  The last
+        sub-iteration's fluid state and the structure state it was computed
+        with are accepted (so populations and mesh stay consistent); the
+        remaining change |solution - estimate| of each sub-iteration is kept in
+        `residuals`.  One sub-iteration is the staggered scheme itself."""
+        assert subiterations >= 1 and 0.0 < relaxation <= 1.0
+        self.subiterations = int(subiterations)
+        self.relaxation = float(relaxation)
 
     # ---- geometry ---------------------------------------------------------
     def positions(self, states):
@@ -162,36 +183,73 @@ class OracleSolver:
             return (0.0, 0.0, 0.0)
         return self.body_forces()[0]
 
+    def _advance_bodies(self, Fb, Fb1=None):
+        """New states of all bodies over one step from the loads Fb at t^n
+        (frozen), or varying linearly to Fb1 at t^{n+1}; linked bodies take
+        the state of the body they move with, whose equation carries their
+        loads."""
+        dt = self.fluid.dt
+        nb = len(self.bodies)
+        new_states = [None] * nb
+        for m in range(nb):
+            if master_of(self.bodies, m) != m:
+                continue
+            Fy = Mz = 0.0
+            Fy1 = Mz1 = None if Fb1 is None else 0.0
+            for k in range(nb):                      # own load, then linked bodies'
+                if master_of(self.bodies, k) == m:
+                    Fy += Fb[k][1]
+                    Mz += Fb[k][2]
+                    if Fb1 is not None:
+                        Fy1 += Fb1[k][1]
+                        Mz1 += Fb1[k][2]
+            new_states[m] = B.advance(self.bodies[m], self.states[m], Fy, Mz,
+                                      (self.n + 1) * dt, dt, Fy1, Mz1)
+        return [new_states[master_of(self.bodies, k)] for k in range(nb)]
+
+    def _loads(self, f, g, states):
+        """Loads of every body from populations (f, g) on the mesh of `states`."""
+        if not (self.has_wall and self.bodies):
+            return [(0.0, 0.0, 0.0) for _ in self.bodies]
+        fl = self.fluid
+        x, y = self.positions(states)
+        return [wall_force(self.grid, f, g, x, y, fl.gamma, fl.mu, fl.Pr, fl.dt,
+                           self.ea_position(states, k), seg=k)
+                for k in range(len(self.bodies))]
+
+    def _fluid(self, fpost, gpost, x0, y0, new_states):
+        """Streaming onto the mesh of `new_states` and the boundary conditions
+        (steps 3, 5-7) from the post-collision populations."""
+        fl = self.fluid
+        dt = fl.dt
+        x1, y1 = self.positions(new_states)
+        VGx = (x1 - x0) / dt
+        VGy = (y1 - y0) / dt
+        f_new, g_new, missing = stream(self.grid, self.X, self.Y, x1, y1, VGx, VGy,
+                                       dt, fpost, gpost)
+        if self.has_wall:
+            farfield_bc(self.grid, self.X, self.Y, f_new, g_new, fl.gamma,
+                        fl.rho_inf, fl.u_inf, fl.T_inf)
+            wall_grad_bc(self.grid, self.X, self.Y, x1, y1, VGx, VGy, f_new, g_new,
+                         missing, self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt)
+        if self.grid.cut:
+            merge_cut_row(self.grid, f_new, g_new, missing)
+        return f_new, g_new, missing
+
     def step(self):
         fl = self.fluid
         dt = fl.dt
         # 1-2: load at t^n, structure to t^{n+1}
         Fb = self.body_forces()
         nb = len(self.bodies)
-        new_states = [None] * nb
-        for m in range(nb):
-            if master_of(self.bodies, m) != m:
-                continue
-            Fy = 0.0
-            Mz = 0.0
-            for k in range(nb):                      # own load, then linked bodies'
-                if master_of(self.bodies, k) == m:
-                    Fy += Fb[k][1]
-                    Mz += Fb[k][2]
-            new_states[m] = B.advance(self.bodies[m], self.states[m], Fy, Mz,
-                                      (self.n + 1) * dt, dt)
+        new_states = self._advance_bodies(Fb)
         for k in range(nb):
-            new_states[k] = new_states[master_of(self.bodies, k)]
             s = self.states[k]
             self.histories[k].append((self.n, Fb[k][0], Fb[k][1], Fb[k][2], s[0], s[1]))
         if nb:
             self.history = self.histories[0]
-        # 3: mesh
+        # 4: collision on x^n (it does not depend on the new mesh)
         x0, y0 = self.positions(self.states)
-        x1, y1 = self.positions(new_states)
-        VGx = (x1 - x0) / dt
-        VGy = (y1 - y0) / dt
-        # 4: collision on x^n
         if self.correction:
             Fx, Fy = correction_force(self.grid, self.f, self.g, x0, y0, fl.gamma,
                                       fl.mu, fl.Pr, dt)
@@ -205,17 +263,21 @@ class OracleSolver:
             Fx[0, te] = 0.0
             Fy[0, te] = 0.0
         fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt, Fx, Fy)
-        # 5: streaming
-        f_new, g_new, missing = stream(self.grid, self.X, self.Y, x1, y1, VGx, VGy,
-                                       dt, fpost, gpost)
-        # 6: boundaries
-        if self.has_wall:
-            farfield_bc(self.grid, self.X, self.Y, f_new, g_new, fl.gamma,
-                        fl.rho_inf, fl.u_inf, fl.T_inf)
-            wall_grad_bc(self.grid, self.X, self.Y, x1, y1, VGx, VGy, f_new, g_new,
-                         missing, self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt)
-        if self.grid.cut:
-            merge_cut_row(self.grid, f_new, g_new, missing)
+        # 3, 5-7: mesh, streaming, boundaries; with strong coupling, repeated
+        # with the structure re-solved against the new load (see `coupling`)
+        self.residuals = []
+        for it in range(self.subiterations):
+            f_new, g_new, missing = self._fluid(fpost, gpost, x0, y0, new_states)
+            if self.subiterations == 1:
+                break
+            Fb1 = self._loads(f_new, g_new, new_states)
+            target = self._advance_bodies(Fb, Fb1)
+            self.residuals.append(max((float(np.max(np.abs(np.asarray(t) - np.asarray(s))))
+                                       for t, s in zip(target, new_states)), default=0.0))
+            if it + 1 < self.subiterations:
+                w = self.relaxation
+                new_states = [np.asarray(s) + w * (np.asarray(t) - np.asarray(s))
+                              for s, t in zip(new_states, target)]
         self.last_missing = missing
         self.f, self.g = f_new, g_new
         self.states = new_states
