@@ -229,6 +229,26 @@ fsi_status fsi_state_bytes(const fsi_ctx *ctx, size_t *bytes);
 fsi_status fsi_save(fsi_ctx *ctx, void *host_buf, size_t bytes);
 fsi_status fsi_load(fsi_ctx *ctx, const void *host_buf, size_t bytes);
 
+/* Strong coupling by sub-iterations (Sec. III names it as the alternative to
+ * the staggered scheme for small solid-to-fluid mass ratios; the paper gives
+ * no algorithm).  Each step starts from the staggered predictor (the body
+ * advanced with the load of t^n frozen); each of the first subiterations - 1
+ * passes streams the post-collision populations of t^n onto the mesh of the
+ * current body estimate, applies the boundary conditions, takes the new load,
+ * re-solves the body equation over the step with the load varying linearly
+ * from F^n to it, and moves the estimate that fraction `relaxation` of the way
+ * to the solution; the last pass is accepted (populations and the body state
+ * they were computed with).  1 sub-iteration = the staggered scheme (the
+ * default).  Each pass costs one collision-streaming launch.  FSI_E_ARG unless
+ * 1 <= subiterations <= 64 and 0 < relaxation <= 1.  Invalidates the captured
+ * graph; the state is kept. */
+fsi_status fsi_set_coupling(fsi_ctx *ctx, int subiterations, double relaxation);
+
+/* Largest change |solution - estimate| of body `body`'s state components in
+ * the last pass of the latest step (how far the sub-iterations are from
+ * converged; 0 with one sub-iteration).  Synchronises. */
+fsi_status fsi_get_coupling_residual(fsi_ctx *ctx, int body, double *residual);
+
 /* Time each kernel of one coupled step with HIP events on the context's
  * stream: `reps` back-to-back launches of the collision-streaming kernel, of
  * the two wall kernels and of the body kernel, at the current step (every
@@ -272,6 +292,8 @@ fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape);
  * values, so the state is unchanged) and its faster pass counts;
  * best[4] = {grid, order, shape, mean ms per launch}.  Synchronises. */
 fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]);
+/* The same coupling for every instance, as fsi_set_coupling. */
+fsi_status fsi_batch_set_coupling(fsi_batch *b, int subiterations, double relaxation);
 fsi_status fsi_batch_step(fsi_batch *b, int nsteps);
 fsi_status fsi_batch_synchronize(fsi_batch *b);
 /* Per-instance queries, as the single-instance calls. */

@@ -25,12 +25,14 @@ struct fsi_ctx {
     std::vector<double> X;          // [nj][ni][2]
     std::vector<fsi_body_desc> bodies;
     hipStream_t stream = nullptr;
+    int n_sub = 1;                  // coupling sub-iterations per step
+    double relax = 1.0;
     Inst inst{};
     // workspace layout (byte offsets)
     size_t off_pop[2]{}, off_X = 0, off_mask = 0, off_tgt = 0, off_B = 0, off_inflow = 0,
            off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
            off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0, off_dist = 0,
-           total = 0;
+           off_resid = 0, total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
     std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
@@ -394,6 +396,8 @@ void fill_params(fsi_ctx *c) {
     }
     P.n_ff = (int)c->ff.size();
     P.nbody = (int)c->bodies.size();
+    P.n_sub = c->n_sub;
+    P.relax = c->relax;
     P.storage = fl.storage;
     P.tiles_i = (c->ni + fsi::TILE_X - 1) / fsi::TILE_X;
     P.tiles_j = (c->nj + fsi::TILE_Y - 1) / fsi::TILE_Y;
@@ -510,6 +514,7 @@ void layout(fsi_ctx *c) {
     c->off_wwall = take(c->wwall.size() * sizeof(int2));
     c->off_wk0 = take(c->wk0.size() * sizeof(int2));
     c->off_dist = take(c->wall_dist.size() * sizeof(double));
+    c->off_resid = take(fsi::MAX_BODIES * sizeof(double));
     c->total = o;
 }
 
@@ -522,7 +527,10 @@ fsi_status check_ready(fsi_ctx *c, bool need_init) {
 
 const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c->off_inst); }
 
-fsi_status enqueue_step(fsi_ctx *c) {
+// one pass of the fluid part of a step on the populations of level n: the cut
+// pre-pass, collision-streaming, wall targets and far field, Grad populations
+// and traction of the new level
+fsi_status enqueue_fluid(fsi_ctx *c) {
     const int st = c->fluid.storage;
     if (!c->wk0.empty())
         HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
@@ -536,7 +544,18 @@ fsi_status enqueue_step(fsi_ctx *c) {
                                                reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
                                                (int)c->wwall.size(), st, 1, c->stream));
     }
-    HIP_TRY(c, fsi::launch_body(d_inst(c), 1, 1, c->stream));
+    return FSI_OK;
+}
+
+// one coupled step: with strong coupling, n_sub - 1 sub-iterations (fluid pass,
+// structure re-solved and relaxed) before the final pass, which the body
+// kernel accepts and records
+fsi_status enqueue_step(fsi_ctx *c) {
+    for (int k = 0; k < c->n_sub; ++k) {
+        fsi_status st = enqueue_fluid(c);
+        if (st != FSI_OK) return st;
+        HIP_TRY(c, fsi::launch_body(d_inst(c), 1, k + 1 < c->n_sub ? 2 : 1, c->stream));
+    }
     return FSI_OK;
 }
 
@@ -655,6 +674,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     P.wall_force = reinterpret_cast<double4 *>(c->ws + c->off_force);
     P.slots = reinterpret_cast<fsi::BodySlot *>(c->ws + c->off_slots);
     P.history = reinterpret_cast<double *>(c->ws + c->off_hist);
+    P.resid = reinterpret_cast<double *>(c->ws + c->off_resid);
     P.step = reinterpret_cast<long long *>(c->ws + c->off_step);
     P.err = reinterpret_cast<unsigned *>(c->ws + c->off_err);
     P.scratch = nullptr;
@@ -666,6 +686,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                               c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_step, 0, 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_resid, 0, fsi::MAX_BODIES * sizeof(double), c->stream));
     if (!c->wk0.empty()) {
         HIP_TRY(c, hipMemsetAsync(c->ws + c->off_cut, 0, (size_t)16 * c->inst.cut_n * 4, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk0, c->wk0.data(), c->wk0.size() * sizeof(int2),
@@ -982,6 +1003,35 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
     return sync_check(c);
 }
 
+fsi_status fsi_set_coupling(fsi_ctx *c, int subiterations, double relaxation) {
+    if (!c) return FSI_E_ARG;
+    if (subiterations < 1 || subiterations > 64 || !(relaxation > 0.0 && relaxation <= 1.0))
+        return fail(c, FSI_E_ARG, "coupling needs 1 <= subiterations <= 64 and 0 < relaxation <= 1");
+    drop_graph(c);
+    c->n_sub = subiterations;
+    c->relax = relaxation;
+    c->inst.n_sub = subiterations;
+    c->inst.relax = relaxation;
+    if (c->ws) {
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return FSI_OK;
+}
+
+fsi_status fsi_get_coupling_residual(fsi_ctx *c, int body, double *residual) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (body < 0 || body >= std::max(1, (int)c->bodies.size()) || !residual)
+        return fail(c, FSI_E_ARG, "bad body index");
+    st = sync_check(c);
+    if (st != FSI_OK) return st;
+    HIP_TRY(c, hipMemcpy(residual, c->ws + c->off_resid + (size_t)body * sizeof(double), sizeof(double),
+                         hipMemcpyDeviceToHost));
+    return FSI_OK;
+}
+
 const char *fsi_last_error(const fsi_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void fsi_destroy(fsi_ctx *c) {
@@ -1007,6 +1057,7 @@ struct fsi_batch {
     char *ws = nullptr;
     std::vector<int2> wk0, wk1, wbnd, wwall;
     int grid = 0, order = 0, shape = 0;
+    int n_sub = 1;                  // coupling sub-iterations per step (all instances)
     bool any_cut = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -1089,15 +1140,18 @@ fsi_status batch_enqueue_k1(fsi_batch *b) {
 }
 
 fsi_status batch_enqueue_step(fsi_batch *b) {
-    fsi_status st = batch_enqueue_k1(b);
-    if (st != FSI_OK) return st;
-    if (b->any_wall) {
-        BHIP_TRY(b, fsi::launch_wall_targets(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wbnd),
-                                             (int)b->wbnd.size(), b->storage, b->stream));
-        BHIP_TRY(b, fsi::launch_wall_grad_force(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wwall),
-                                                (int)b->wwall.size(), b->storage, 1, b->stream));
+    for (int k = 0; k < b->n_sub; ++k) {
+        fsi_status st = batch_enqueue_k1(b);
+        if (st != FSI_OK) return st;
+        if (b->any_wall) {
+            BHIP_TRY(b, fsi::launch_wall_targets(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wbnd),
+                                                 (int)b->wbnd.size(), b->storage, b->stream));
+            BHIP_TRY(b, fsi::launch_wall_grad_force(b_insts(b),
+                                                    reinterpret_cast<const int2 *>(b->ws + b->off_wwall),
+                                                    (int)b->wwall.size(), b->storage, 1, b->stream));
+        }
+        BHIP_TRY(b, fsi::launch_body(b_insts(b), (int)b->ctx.size(), k + 1 < b->n_sub ? 2 : 1, b->stream));
     }
-    BHIP_TRY(b, fsi::launch_body(b_insts(b), (int)b->ctx.size(), 1, b->stream));
     return FSI_OK;
 }
 
@@ -1365,6 +1419,33 @@ fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]) {
     best[1] = best_order;
     best[2] = best_shape;
     best[3] = best_ms;
+    return FSI_OK;
+}
+
+fsi_status fsi_batch_set_coupling(fsi_batch *b, int subiterations, double relaxation) {
+    if (!b) return FSI_E_ARG;
+    for (size_t k = 0; k < b->ctx.size(); ++k) {
+        fsi_ctx *c = b->ctx[k];
+        if (subiterations < 1 || subiterations > 64 || !(relaxation > 0.0 && relaxation <= 1.0))
+            return bfail(b, FSI_E_ARG, "coupling needs 1 <= subiterations <= 64 and 0 < relaxation <= 1");
+        c->n_sub = subiterations;
+        c->relax = relaxation;
+        c->inst.n_sub = subiterations;
+        c->inst.relax = relaxation;
+    }
+    batch_drop_graph(b);
+    b->n_sub = subiterations;
+    if (b->ws) {
+        std::vector<Inst> insts(b->ctx.size());
+        for (size_t k = 0; k < b->ctx.size(); ++k) {
+            insts[k] = b->ctx[k]->inst;
+            BHIP_TRY(b, hipMemcpyAsync(b->ctx[k]->ws + b->ctx[k]->off_inst, &b->ctx[k]->inst, sizeof(Inst),
+                                       hipMemcpyHostToDevice, b->stream));
+        }
+        BHIP_TRY(b, hipMemcpyAsync(b->ws + b->off_insts, insts.data(), insts.size() * sizeof(Inst),
+                                   hipMemcpyHostToDevice, b->stream));
+        BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    }
     return FSI_OK;
 }
 

@@ -75,6 +75,9 @@ struct Inst {
     int seg_i0[MAX_BODIES], seg_n[MAX_BODIES], seg_dup[MAX_BODIES];
     int n_ff;                 // far-field nodes
     int nbody;                // bodies (0 .. MAX_BODIES)
+    int n_sub;                // coupling sub-iterations per step (1: staggered)
+    int pad1;
+    double relax;             // sub-iteration relaxation factor
     long long n_nodes;
     double shift_ix, shift_iy, shift_jx, shift_jy;
     double dt_d;
@@ -97,6 +100,7 @@ struct Inst {
     const double *wall_dist;  // [nbody][nj][ni] distance to each body's wall (blend_mode 1), else null
     BodySlot *slots;          // [3][MAX_BODIES] body states at levels n % 3
     double *history;          // [MAX_BODIES][HIST_CAP][6]
+    double *resid;            // [MAX_BODIES] remaining change of the last coupling sub-iteration
     long long *step;          // completed steps
     unsigned *err;            // sticky error word
     double *scratch;          // init / dump staging (aliases the idle ping-pong side)

@@ -1316,8 +1316,11 @@ __device__ void body_accel(const Body &b, double h, double a, double Fy, double 
     }
 }
 
-__device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, double M, double t_next,
-                                 double dt) {
+// state at t^{n+1} from s at t^n: the prescribed motion, or RK4 of the body
+// equation with the load varying linearly from (Fy, M) at t^n to (Fy1, M1) at
+// t^{n+1} (equal for the staggered step, whose load is frozen)
+__device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, double M, double Fy1,
+                                 double M1, double t_next, double dt) {
     BodySlot o = s;
     const bool forced = (b.dof == DOF_HEAVE || b.dof == DOF_PITCH_PLUNGE) && b.release_time > 0.0 &&
                         t_next <= b.release_time;
@@ -1333,7 +1336,7 @@ __device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, do
             double z[4];
             for (int q = 0; q < 4; ++q) z[q] = st == 0 ? y[q] : y[q] + c * k[st - 1][q];
             double hdd, add;
-            body_accel(b, z[0], z[1], Fy, M, hdd, add);
+            body_accel(b, z[0], z[1], Fy + c / dt * (Fy1 - Fy), M + c / dt * (M1 - M), hdd, add);
             k[st][0] = z[2];
             k[st][1] = z[3];
             k[st][2] = hdd;
@@ -1384,7 +1387,7 @@ __global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ 
         F[k][2] = sz[0];
         __syncthreads();
     }
-    if (phase && P.cut) {
+    if (phase == 1 && P.cut) {
         // one state per cut point: the mirror copy of each primary cut node
         // takes its populations (duplicated wall points are merged at the wall)
         void *buf = P.pop[(n + 1) & 1];
@@ -1400,31 +1403,79 @@ __global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ 
                 reinterpret_cast<uint16_t *>(base)[m] = reinterpret_cast<const uint16_t *>(base)[c];
         }
     }
-    if (t == 0) {
-        const BodySlot *cur = P.slots + (L % 3) * MAX_BODIES;
-        BodySlot *nxt = P.slots + ((L + 1) % 3) * MAX_BODIES;
-        const int nrec = P.nbody > 0 ? P.nbody : 1;
-        for (int k = 0; k < nrec; ++k) {
-            double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(L % HIST_CAP)) * 6;
-            rec[0] = (double)L; rec[1] = F[k][0]; rec[2] = F[k][1]; rec[3] = F[k][2];
-            rec[4] = cur[k].h; rec[5] = cur[k].a;
-        }
-        // each body with an equation of its own takes its load plus those of
-        // the bodies linked to it; linked bodies then take its new state
+    if (t != 0) return;
+    const int nrec = P.nbody > 0 ? P.nbody : 1;
+    if (phase == 2 || (phase == 1 && P.n_sub > 1)) {
+        // strong coupling: the structure re-solved over step n -> n+1 with the
+        // load varying linearly from F^n (the record of level n) to the load of
+        // the new populations; a sub-iteration relaxes the estimate of level
+        // n+1 towards it, the last one only measures the remaining change
+        const BodySlot *sn = P.slots + (n % 3) * MAX_BODIES;
+        BodySlot *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES;
+        BodySlot target[MAX_BODIES];
         for (int m = 0; m < nrec; ++m) {
             if (P.body[m].master != m) continue;
-            double fy = 0.0, mz = 0.0;
+            double fy0 = 0.0, mz0 = 0.0, fy1 = 0.0, mz1 = 0.0;
             for (int k = 0; k < nrec; ++k) {
                 if (P.body[k].master != m) continue;
-                fy += F[k][1];
-                mz += F[k][2];
+                const double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(n % HIST_CAP)) * 6;
+                fy0 += rec[2];
+                mz0 += rec[3];
+                fy1 += F[k][1];
+                mz1 += F[k][2];
             }
-            nxt[m] = body_advance(P.body[m], cur[m], fy, mz, (double)(L + 1) * P.dt_d, P.dt_d);
+            target[m] = body_advance(P.body[m], sn[m], fy0, mz0, fy1, mz1, (double)(n + 1) * P.dt_d,
+                                     P.dt_d);
         }
-        for (int k = 0; k < nrec; ++k)
-            if (P.body[k].master != k) nxt[k] = nxt[P.body[k].master];
-        if (phase) *P.step = n + 1;
+        for (int k = 0; k < nrec; ++k) {
+            const BodySlot &tg = target[P.body[k].master];
+            const BodySlot &cur = s1[k];
+            P.resid[k] = fmax(fmax(fabs(tg.h - cur.h), fabs(tg.a - cur.a)),
+                              fmax(fabs(tg.hd - cur.hd), fabs(tg.ad - cur.ad)));
+        }
+        if (phase == 2) {
+            for (int m = 0; m < nrec; ++m) {
+                if (P.body[m].master != m) continue;
+                BodySlot o = s1[m];
+                const BodySlot &tg = target[m];
+                const double w = P.relax;
+                o.h += w * (tg.h - o.h);
+                o.a += w * (tg.a - o.a);
+                o.hd += w * (tg.hd - o.hd);
+                o.ad += w * (tg.ad - o.ad);
+                const double sh = sin(0.5 * o.a);
+                o.cm1 = -2.0 * sh * sh;
+                o.sa = sin(o.a);
+                s1[m] = o;
+            }
+            for (int k = 0; k < nrec; ++k)
+                if (P.body[k].master != k) s1[k] = s1[P.body[k].master];
+            return;
+        }
     }
+    const BodySlot *cur = P.slots + (L % 3) * MAX_BODIES;
+    BodySlot *nxt = P.slots + ((L + 1) % 3) * MAX_BODIES;
+    for (int k = 0; k < nrec; ++k) {
+        double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(L % HIST_CAP)) * 6;
+        rec[0] = (double)L; rec[1] = F[k][0]; rec[2] = F[k][1]; rec[3] = F[k][2];
+        rec[4] = cur[k].h; rec[5] = cur[k].a;
+    }
+    // each body with an equation of its own takes its load plus those of the
+    // bodies linked to it (frozen over the next step: the staggered scheme,
+    // and the predictor of strong coupling); linked bodies then take its state
+    for (int m = 0; m < nrec; ++m) {
+        if (P.body[m].master != m) continue;
+        double fy = 0.0, mz = 0.0;
+        for (int k = 0; k < nrec; ++k) {
+            if (P.body[k].master != m) continue;
+            fy += F[k][1];
+            mz += F[k][2];
+        }
+        nxt[m] = body_advance(P.body[m], cur[m], fy, mz, fy, mz, (double)(L + 1) * P.dt_d, P.dt_d);
+    }
+    for (int k = 0; k < nrec; ++k)
+        if (P.body[k].master != k) nxt[k] = nxt[P.body[k].master];
+    if (phase) *P.step = n + 1;
 }
 
 // ---------------------------------------------------------------------------

@@ -24,10 +24,10 @@ EXPORTED = ("fsi_create", "fsi_workspace_bytes", "fsi_bind_workspace", "fsi_init
             "fsi_step", "fsi_synchronize", "fsi_get_step", "fsi_get_forces",
             "fsi_history_capacity", "fsi_get_body_state", "fsi_dump_macro",
             "fsi_get_populations", "fsi_set_populations", "fsi_state_bytes", "fsi_save",
-            "fsi_load", "fsi_time_kernels", "fsi_last_error", "fsi_destroy",
-            "fsi_batch_create", "fsi_batch_workspace_bytes", "fsi_batch_bind_workspace",
+            "fsi_load", "fsi_time_kernels", "fsi_set_coupling", "fsi_get_coupling_residual",
+            "fsi_last_error", "fsi_destroy", "fsi_batch_create", "fsi_batch_workspace_bytes", "fsi_batch_bind_workspace",
             "fsi_batch_init_equilibrium", "fsi_batch_set_schedule", "fsi_batch_autotune",
-            "fsi_batch_step", "fsi_batch_synchronize", "fsi_batch_get_forces",
+            "fsi_batch_set_coupling", "fsi_batch_step", "fsi_batch_synchronize", "fsi_batch_get_forces",
             "fsi_batch_get_body_state", "fsi_batch_dump_macro", "fsi_batch_get_populations",
             "fsi_batch_time_kernels", "fsi_batch_nodes", "fsi_batch_last_error",
             "fsi_batch_destroy")
@@ -99,6 +99,9 @@ def load_library(path: str = LIB_PATH):
         "fsi_save": (ctypes.c_int, [P, P, ctypes.c_size_t]),
         "fsi_load": (ctypes.c_int, [P, P, ctypes.c_size_t]),
         "fsi_time_kernels": (ctypes.c_int, [P, ctypes.c_int, dp]),
+        "fsi_set_coupling": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_double]),
+        "fsi_get_coupling_residual": (ctypes.c_int, [P, ctypes.c_int, dp]),
+        "fsi_batch_set_coupling": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_double]),
         "fsi_last_error": (ctypes.c_char_p, [P]),
         "fsi_destroy": (None, [P]),
         "fsi_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(FluidParams),
@@ -284,6 +287,16 @@ def fsi_time_kernels(ctx, reps):
     return out
 
 
+def fsi_set_coupling(ctx, subiterations, relaxation=1.0):
+    _check(ctx, _lib.fsi_set_coupling(ctx, int(subiterations), float(relaxation)))
+
+
+def fsi_get_coupling_residual(ctx, body=0):
+    out = np.zeros(1, dtype=np.float64)
+    _check(ctx, _lib.fsi_get_coupling_residual(ctx, int(body), _dptr(out)))
+    return float(out[0])
+
+
 def fsi_last_error(ctx):
     return _lib.fsi_last_error(ctx).decode()
 
@@ -357,6 +370,10 @@ def fsi_batch_autotune(b, reps):
     out = np.zeros(4, dtype=np.float64)
     _bcheck(b, _lib.fsi_batch_autotune(b, int(reps), _dptr(out)))
     return int(out[0]), int(out[1]), int(out[2]), float(out[3])
+
+
+def fsi_batch_set_coupling(b, subiterations, relaxation=1.0):
+    _bcheck(b, _lib.fsi_batch_set_coupling(b, int(subiterations), float(relaxation)))
 
 
 def fsi_batch_step(b, nsteps):
@@ -460,6 +477,12 @@ class Simulation:
     def body_state(self, body=0):
         return fsi_get_body_state(self.ctx, body)
 
+    def set_coupling(self, subiterations, relaxation=1.0):
+        fsi_set_coupling(self.ctx, subiterations, relaxation)
+
+    def coupling_residual(self, body=0):
+        return fsi_get_coupling_residual(self.ctx, body)
+
     def macro(self):
         return fsi_dump_macro(self.ctx, self.shape)
 
@@ -532,6 +555,9 @@ class Batch:
 
     def autotune(self, reps=5):
         return fsi_batch_autotune(self.b, reps)
+
+    def set_coupling(self, subiterations, relaxation=1.0):
+        fsi_batch_set_coupling(self.b, subiterations, relaxation)
 
     def step(self, nsteps=1):
         fsi_batch_step(self.b, nsteps)

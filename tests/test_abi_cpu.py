@@ -324,3 +324,18 @@ def test_batch_takes_bodies_back_to_back(F):
         assert e.value.status == -1
     finally:
         F.fsi_batch_destroy(b)
+
+
+def test_coupling_arguments_are_checked(F):
+    c = synth.cylinder_viv_case(n_r=40, n_theta=80, D=40.0, first_cell_frac=0.025,
+                                r_far_D=10.0, blend_D=4.0)
+    ctx = F.fsi_create(c.fluid, c.mesh, c.bodies, None)
+    try:
+        F.fsi_set_coupling(ctx, 3, 0.7)
+        F.fsi_set_coupling(ctx, 1, 1.0)
+        for bad in ((0, 1.0), (65, 1.0), (2, 0.0), (2, 1.5)):
+            with pytest.raises(F.FsiError) as e:
+                F.fsi_set_coupling(ctx, *bad)
+            assert e.value.status == -1
+    finally:
+        F.fsi_destroy(ctx)

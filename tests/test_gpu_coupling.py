@@ -1,0 +1,89 @@
+"""GPU parity of strong coupling by sub-iterations against the FP64 oracle:
+a light cylinder (m* = 0.5) and the linked tandem pair, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.solver import OracleSolver
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-5
+
+
+def paired(c, K, w):
+    from paper_2107_01370_amd.fsilbm import Simulation
+    sim = Simulation(c.mesh, c.fluid, c.bodies)
+    sim.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+    sim.set_coupling(K, w)
+    f0, g0 = sim.populations()
+    ora = OracleSolver(c.mesh, c.fluid, c.bodies, c.rho, c.ux, c.uy, c.T)
+    ora.coupling(K, w)
+    ora.f = f0.astype(np.float64)
+    ora.g = g0.astype(np.float64)
+    return sim, ora
+
+
+def light_cylinder():
+    return synth.cylinder_viv_case(n_r=32, n_theta=64, D=20.0, first_cell_frac=0.05,
+                                   r_far_D=8.0, blend_D=3.0, h0_frac=0.05, mstar=0.5,
+                                   ustar=4.0, Ma=0.2, Re=50.0)
+
+
+def test_one_subiteration_equals_the_default_step():
+    from paper_2107_01370_amd.fsilbm import Simulation
+    c = light_cylinder()
+    runs = []
+    for K in (None, 1):
+        s = Simulation(c.mesh, c.fluid, c.bodies)
+        s.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+        if K:
+            s.set_coupling(K)
+        s.step(20)
+        runs.append((s.populations(), s.forces(0, 20)))
+        s.close()
+    assert np.array_equal(runs[0][0][0], runs[1][0][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("K,w", [(3, 1.0), (4, 0.7)])
+def test_light_cylinder_subiterations(wall_margin, K, w):
+    c = light_cylinder()
+    sim, ora = paired(c, K, w)
+    n = 40
+    sim.step(n)
+    with wall_margin() as margin:
+        ora.run(n)
+    assert margin[0] >= MARGIN
+    rho, ux, uy, T = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(rho - r_o) / r_o) <= 1e-5
+    hist = sim.forces(0, n)
+    ho = np.array(ora.history)
+    fscale = np.max(np.hypot(ho[:, 1], ho[:, 2]))
+    assert np.max(np.abs(hist[:, 1:3] - ho[:, 1:3])) <= 1e-4 * fscale
+    amp = np.max(np.abs(ho[:, 4] - ho[0, 4]))
+    assert amp > 0 and np.max(np.abs(hist[:, 4] - ho[:, 4])) <= 1e-4 * amp
+    # the remaining change of the last pass, as the oracle measures it
+    res = sim.coupling_residual()
+    assert res <= 10 * ora.residuals[-1] + 1e-6 * amp
+    assert ora.residuals[-1] < ora.residuals[0]
+
+
+def test_linked_tandem_subiterations(wall_margin):
+    c = synth.small_tandem_case(linked=True)
+    sim, ora = paired(c, 2, 1.0)
+    n = 30
+    sim.step(n)
+    with wall_margin() as margin:
+        ora.run(n)
+    assert margin[0] >= MARGIN
+    for k in range(2):
+        hist = sim.forces(0, n, body=k)
+        ho = np.array(ora.histories[k])
+        fscale = np.max(np.hypot(ho[:, 1], ho[:, 2]))
+        assert np.max(np.abs(hist[:, 1:3] - ho[:, 1:3])) <= 1e-4 * fscale
+        amp = np.max(np.abs(ho[:, 4] - ho[0, 4]))
+        assert np.max(np.abs(hist[:, 4] - ho[:, 4])) <= 1e-4 * amp
+    assert np.array_equal(sim.body_state(0), sim.body_state(1))
