@@ -497,7 +497,7 @@ void layout(fsi_ctx *c) {
     c->off_pop[0] = take(fsi::NPOP * N * bpp);
     c->off_pop[1] = take(fsi::NPOP * N * bpp);
     c->off_X = take(N * 16);
-    c->off_mask = take(c->ni * 2);
+    c->off_mask = take(c->ni * 4);                 // missing mask, then the ambiguity mask
     c->off_tgt = take(c->ni * 16);
     c->off_B = take(c->ni * 8);
     c->off_inflow = take(c->ff.size());
@@ -662,6 +662,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     P.pop[1] = c->ws + c->off_pop[1];
     P.X = reinterpret_cast<const double2 *>(c->ws + c->off_X);
     P.wall_mask = reinterpret_cast<uint16_t *>(c->ws + c->off_mask);
+    P.wall_amb = P.wall_mask + c->ni;
     P.wall_tgt = reinterpret_cast<float4 *>(c->ws + c->off_tgt);
     P.wall_B = reinterpret_cast<const float2 *>(c->ws + c->off_B);
     P.inflow = reinterpret_cast<const uint8_t *>(c->ws + c->off_inflow);
@@ -680,7 +681,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     P.scratch = nullptr;
     const size_t N = (size_t)c->ni * c->nj;
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_X, c->X.data(), N * 16, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_mask, 0, c->ni * 2, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_mask, 0, c->ni * 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_force, 0, c->ni * 32, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_hist, 0, (size_t)fsi::MAX_BODIES * fsi::HIST_CAP * 48,
                               c->stream));

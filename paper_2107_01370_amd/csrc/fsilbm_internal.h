@@ -91,6 +91,7 @@ struct Inst {
     void *pop[2];             // ping-pong [18][nj][ni], float or half
     const double2 *X;         // [nj][ni] undeformed coordinates
     uint16_t *wall_mask;      // [ni] bit k: population k missing at the wall node
+    uint16_t *wall_amb;       // [ni] bit k: departure point within FP32 reach of the wall decision line
     float4 *wall_tgt;         // [ni] (rho, ux, uy, T) targets
     const float2 *wall_B;     // [ni] index offsets of point B from the wall node
     const int2 *ff;           // [n_ff] far-field node index, interior node an outlet copies

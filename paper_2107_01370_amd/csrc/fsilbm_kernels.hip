@@ -853,7 +853,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const int vc = wall ? 1 : 0;                   // stencil centre row offset
         const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
         const int off = pop_off<STORE>(jg * ni + ig);
-        uint16_t miss = 0;
+        uint16_t miss = 0, amb = 0;
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
             const float cx = (float)CXK(k), cy = (float)CYK(k);
@@ -893,8 +893,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             const float a = li ? -uu : uu;
             float bb = lj ? -vv : vv;
             // a point more than 1e-4 of the cell below the wall line lies in
-            // the body (nearer, it counts as on the line)
-            if (wall && vv < -1e-4f) { miss |= (uint16_t)(1u << k); continue; }
+            // the body (nearer, it counts as on the line).  Within 1e-5 of that
+            // line (several times the FP32 error of vv) the population is
+            // interpolated here and the wall kernel decides in FP64.
+            if (wall && vv < -1.1e-4f) { miss |= (uint16_t)(1u << k); continue; }
+            if (wall && vv < -0.9e-4f) amb |= (uint16_t)(1u << k);
             if (!(fabsf(a) <= 1.0f + 1e-4f) || !(fabsf(bb) <= 1.0f + 1e-4f)) err |= ERR_CFL;
             bb -= (float)vc;
             const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
@@ -917,7 +920,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             pop_st<STORE>(P, dst, k, off, outv[0]);
             pop_st<STORE>(P, dst, Q + k, off, outv[1]);
         }
-        if (wall) P.wall_mask[ig] = miss;
+        if (wall) {
+            P.wall_mask[ig] = miss;
+            P.wall_amb[ig] = amb;
+        }
     }
     if (err) atomicOr(P.err, err);
 }
@@ -1006,6 +1012,69 @@ __device__ __forceinline__ bool wall_block(const Inst &P, int blk, int &seg, int
     return false;
 }
 
+// FP64 bilinear coordinate v (in units of the first cell row, 0 on the wall
+// line) of the departure point of population k at wall node ig, from the
+// undeformed coordinates and the body states of levels n and n+1: the same
+// steps as the collision-streaming kernel's FP32 evaluation (metric of
+// x^{n+1} centred along the wall and one-sided into the fluid, V_G, the
+// linear departure offset mapped to the undeformed frame, bilinear inverse
+// of the first-row cell whose i-range holds the point), in absolute FP64
+// coordinates.  Used for the populations whose FP32 v lies within reach of
+// the line at which a population counts as missing.
+__device__ double wall_departure_v(const Inst &P, int ig, int k, long long n) {
+    const int ni = P.ni;
+    const int im = P.exits ? ig - 1 : wrap(ig - 1, ni), ip = P.exits ? ig + 1 : wrap(ig + 1, ni);
+    const BodySlot *s0 = P.slots + (n % 3) * MAX_BODIES, *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES;
+    const long long i1 = (long long)ni + ig, i2 = 2LL * ni + ig;
+    double xm, ym, xp, yp, x0, y0, x1, y1, x2, y2, x0n, y0n;
+    node_pos(P, im, s1, xm, ym);
+    node_pos(P, ip, s1, xp, yp);
+    node_pos(P, ig, s1, x0, y0);
+    node_pos(P, i1, s1, x1, y1);
+    node_pos(P, i2, s1, x2, y2);
+    node_pos(P, ig, s0, x0n, y0n);
+    const double2 X0 = P.X[ig], Xm = P.X[im], Xp = P.X[ip], X1 = P.X[i1], X2 = P.X[i2];
+    const double2 Xm1 = P.X[(long long)ni + im], Xp1 = P.X[(long long)ni + ip];
+    // metric of x^{n+1} and of X
+    const double j11 = 0.5 * (xp - xm), j21 = 0.5 * (yp - ym);
+    const double j12 = 2.0 * (x1 - x0) - 0.5 * (x2 - x0), j22 = 2.0 * (y1 - y0) - 0.5 * (y2 - y0);
+    const double b11 = 0.5 * (Xp.x - Xm.x), b21 = 0.5 * (Xp.y - Xm.y);
+    const double b12 = 2.0 * (X1.x - X0.x) - 0.5 * (X2.x - X0.x);
+    const double b22 = 2.0 * (X1.y - X0.y) - 0.5 * (X2.y - X0.y);
+    const double vgx = (x0 - x0n) / P.dt_d, vgy = (y0 - y0n) / P.dt_d;
+    const double wx = (double)CXK(k) - vgx, wy = (double)CYK(k) - vgy;
+    const double idet = 1.0 / (j11 * j22 - j12 * j21);
+    const double ax = -P.dt_d * idet * (j22 * wx - j12 * wy);
+    const double ay = -P.dt_d * idet * (-j21 * wx + j11 * wy);
+    const double px = b11 * ax + b12 * ay, py = b21 * ax + b22 * ay;
+    // the two first-row cells: toward i - 1 and toward i + 1
+    double v_best = 0.0, u_err = 1e300;
+    for (int side = 0; side < 2; ++side) {
+        const double2 Xs = side ? Xp : Xm, Xs1 = side ? Xp1 : Xm1;
+        const double eix = Xs.x - X0.x, eiy = Xs.y - X0.y;
+        const double ejx = X1.x - X0.x, ejy = X1.y - X0.y;
+        const double twx = (Xs1.x - X0.x) - eix - ejx, twy = (Xs1.y - X0.y) - eiy - ejy;
+        double u = 0.0, v = 0.0;
+        for (int it = 0; it < 30; ++it) {   // Newton on u e_i + v e_j + u v tw = p
+            const double rx = u * eix + v * ejx + u * v * twx - px;
+            const double ry = u * eiy + v * ejy + u * v * twy - py;
+            const double jux = eix + v * twx, juy = eiy + v * twy;
+            const double jvx = ejx + u * twx, jvy = ejy + u * twy;
+            const double d = jux * jvy - juy * jvx;
+            const double du = (jvy * rx - jvx * ry) / d, dv = (-juy * rx + jux * ry) / d;
+            u -= du;
+            v -= dv;
+            if (fabs(du) + fabs(dv) < 1e-15) break;
+        }
+        const double e = u < 0.0 ? -u : (u > 1.0 ? u - 1.0 : 0.0);   // distance outside [0, 1]
+        if (e < u_err) {
+            u_err = e;
+            v_best = v;
+        }
+    }
+    return v_best;
+}
+
 // Wall targets (Grad BC, Sec. III.A.1) for item.y even, far-field
 // equilibria (Sec. III.A.2) for item.y odd; item.y >> 1 is the block of 64
 // wall nodes (of one wall segment) or of 64 far-field list entries.
@@ -1041,6 +1110,14 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
         __syncthreads();
         const int ig = i0 + t;
         if (ig >= iend) return;
+        // missing or not, decided in FP64 where the FP32 evaluation was too close to call
+        const uint16_t amb = P.wall_amb[ig];
+        if (amb) {
+            uint16_t miss = P.wall_mask[ig];
+            for (int k = 1; k < 9; ++k)
+                if ((amb & (1u << k)) && wall_departure_v(P, ig, k, n) < -1e-4) miss |= (uint16_t)(1u << k);
+            P.wall_mask[ig] = miss;
+        }
         const float2 B = P.wall_B[ig];
         const float a = B.x, b = B.y - 1.0f;   // offsets from the element centre (i, 1)
         float rho_t = 0.0f, T_t = 0.0f;

@@ -19,9 +19,9 @@ def wall_margin():
     inside it, the smallest index-space distance of the wall nodes' departure
     points (found or missing) from the line at which a population counts as
     missing (WALL_TOL below the wall line).  Both sides decide at that line,
-    the kernel in FP32 and the oracle in FP64; parity over many steps is
-    meaningful when no point comes closer to it than a few times the kernel's
-    rounding of the offset (~2e-6 cells)."""
+    the oracle in FP64, the kernel in FP32 and, within 1e-5 of the line, in
+    FP64; parity over many steps is meaningful when no point comes closer to
+    it than the differences of two FP64 evaluations (~1e-13 cells)."""
     import contextlib
 
     import numpy as np

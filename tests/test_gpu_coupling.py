@@ -9,7 +9,7 @@ from oracle.solver import OracleSolver
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = 1e-5
+MARGIN = 1e-9          # the kernel decides near the line in FP64 (evaluation-order differences ~1e-13)
 
 
 def paired(c, K, w):

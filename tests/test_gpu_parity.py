@@ -93,7 +93,7 @@ def test_cylinder_force_and_displacement_parity(wall_margin):
     sim.step(n)
     with wall_margin() as margin:
         ora.run(n)
-    assert margin[0] >= 1e-5
+    assert margin[0] >= 1e-9
     hist = sim.forces(0, n)
     ho = np.array(ora.history)
     assert np.array_equal(hist[:, 0], ho[:, 0])
