@@ -896,8 +896,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             // the body (nearer, it counts as on the line).  Within 1e-5 of that
             // line (several times the FP32 error of vv) the population is
             // interpolated here and the wall kernel decides in FP64.
+            const bool near = wall && vv < -0.9e-4f;
+            amb |= near ? (uint16_t)(1u << k) : (uint16_t)0;
             if (wall && vv < -1.1e-4f) { miss |= (uint16_t)(1u << k); continue; }
-            if (wall && vv < -0.9e-4f) amb |= (uint16_t)(1u << k);
             if (!(fabsf(a) <= 1.0f + 1e-4f) || !(fabsf(bb) <= 1.0f + 1e-4f)) err |= ERR_CFL;
             bb -= (float)vc;
             const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
@@ -922,7 +923,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         }
         if (wall) {
             P.wall_mask[ig] = miss;
-            P.wall_amb[ig] = amb;
+            P.wall_amb[ig] = amb & (uint16_t)~miss;
         }
     }
     if (err) atomicOr(P.err, err);
