@@ -1,0 +1,232 @@
+"""The step on an unstructured mesh of second-order (9-node) quadrilateral
+elements, in float64 (paper Sec. II.B: the semi-Lagrangian method on
+unstructured finite-element meshes).  Test infrastructure only.
+
+Populations live at the mesh nodes.  One step on a static periodic mesh:
+
+1. moments, delta Q_a and mu/p at every node (Sec. II.C);
+2. nodal gradients by the finite-element derivative dC/dX = J^{-T} sum_s C_s
+   grad_xi N_s of each element containing the node, evaluated at the node's
+   own position in that element, and averaged over those elements (reading:
+   the element derivatives are discontinuous across element edges; the paper
+   does not say how a nodal value is formed from them); D_a = (mu/p) d_a
+   delta Q_a, F_a = d_a D_a from the same recovery (Sec. II.C correction);
+3. collision (Sec. II.C);
+4. departure point X_dp = X - dt c_i, located among the elements that contain
+   the node with the element's first-order (bilinear, corner-node) map,
+   solved by Newton (Sec. II.B: the first-order element saves time);
+5. f_i(X) = sum_s N_s(xi_dp) f*_i(X_s) with the element's nine quadratic
+   Lagrange shape functions N_s (Sec. II.B).
+
+Element node order and local positions: corners (-1,-1), (1,-1), (1,1),
+(-1,1), edge midpoints (0,-1), (1,0), (0,1), (-1,0), centre (0,0).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import lattice as L
+
+LOCAL = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1],
+                  [0, -1], [1, 0], [0, 1], [-1, 0], [0, 0]], dtype=np.float64)
+INSIDE_TOL = 1e-12
+
+
+def lagrange(p, a):
+    """Quadratic Lagrange basis on {-1, 0, 1}: the polynomial of degree 2
+    that is 1 at p and 0 at the other two nodes."""
+    out = np.ones_like(a, dtype=np.float64)
+    for m in (-1.0, 0.0, 1.0):
+        if m != p:
+            out = out * (a - m) / (p - m)
+    return out
+
+
+def dlagrange(p, a):
+    """Derivative of `lagrange(p, .)` at a."""
+    out = np.zeros_like(a, dtype=np.float64)
+    others = [m for m in (-1.0, 0.0, 1.0) if m != p]
+    den = (p - others[0]) * (p - others[1])
+    return out + ((a - others[1]) + (a - others[0])) / den
+
+
+def shape(xi, eta):
+    """N_s(xi, eta), s = 0..8, stacked on the first axis."""
+    return np.stack([lagrange(LOCAL[s, 0], xi) * lagrange(LOCAL[s, 1], eta) for s in range(9)])
+
+
+def shape_grad(xi, eta):
+    """(dN_s/dxi, dN_s/deta), each stacked on the first axis."""
+    dxi = np.stack([dlagrange(LOCAL[s, 0], xi) * lagrange(LOCAL[s, 1], eta) for s in range(9)])
+    deta = np.stack([lagrange(LOCAL[s, 0], xi) * dlagrange(LOCAL[s, 1], eta) for s in range(9)])
+    return dxi, deta
+
+
+class UGrid:
+    """Connectivity and geometry of an unstructured periodic Q9 mesh."""
+
+    def __init__(self, mesh):
+        self.N = mesh.n_nodes
+        self.E = mesh.n_elems
+        self.elems = np.asarray(mesh.elems, dtype=np.int64)
+        Lx, Ly = mesh.period
+        sh = np.asarray(mesh.shifts, dtype=np.float64)
+        # unwrapped node coordinates of every element
+        self.ex = mesh.X[self.elems] + sh[..., 0] * Lx
+        self.ey = mesh.Y[self.elems] + sh[..., 1] * Ly
+        # patches: the (element, local node) pairs of every node, by element index
+        pairs = sorted((int(n), e, a) for e in range(self.E) for a, n in enumerate(self.elems[e]))
+        self.patch = [[] for _ in range(self.N)]
+        for n, e, a in pairs:
+            self.patch[n].append((e, a))
+        self.P = max(len(p) for p in self.patch)
+        self.pe = np.zeros((self.N, self.P), dtype=np.int64)
+        self.pa = np.zeros((self.N, self.P), dtype=np.int64)
+        self.pm = np.zeros((self.N, self.P), dtype=bool)
+        for n, p in enumerate(self.patch):
+            for k, (e, a) in enumerate(p):
+                self.pe[n, k], self.pa[n, k], self.pm[n, k] = e, a, True
+        self.count = self.pm.sum(axis=1)
+        # element derivative operator at each element's own nodes:
+        # dC/dx at local node a of element e = sum_s Wx[e, a, s] C_s
+        self.Wx = np.zeros((self.E, 9, 9))
+        self.Wy = np.zeros((self.E, 9, 9))
+        for a in range(9):
+            dxi, deta = shape_grad(np.array(LOCAL[a, 0]), np.array(LOCAL[a, 1]))
+            x_xi = self.ex @ dxi
+            x_eta = self.ex @ deta
+            y_xi = self.ey @ dxi
+            y_eta = self.ey @ deta
+            det = x_xi * y_eta - y_xi * x_eta
+            # [dC/dx, dC/dy] = J^{-T} [dC/dxi, dC/deta]
+            self.Wx[:, a, :] = (y_eta[:, None] * dxi[None, :] - y_xi[:, None] * deta[None, :]) / det[:, None]
+            self.Wy[:, a, :] = (-x_eta[:, None] * dxi[None, :] + x_xi[:, None] * deta[None, :]) / det[:, None]
+        self.det_min = None
+
+    def grad(self, C):
+        """Nodal gradient (dC/dx, dC/dy): the mean over the node's elements of
+        the element derivative at the node."""
+        Ce = C[self.elems]                                    # [E, 9]
+        gx_e = np.einsum("eas,es->ea", self.Wx, Ce)           # [E, 9] at each element node
+        gy_e = np.einsum("eas,es->ea", self.Wy, Ce)
+        gx = np.where(self.pm, gx_e[self.pe, self.pa], 0.0).sum(axis=1) / self.count
+        gy = np.where(self.pm, gy_e[self.pe, self.pa], 0.0).sum(axis=1) / self.count
+        return gx, gy
+
+    def locate(self, dx, dy):
+        """For every node n, the element of its patch whose bilinear (corner)
+        map holds the point at displacement (dx[n], dy[n]) from the node, and
+        the local coordinates there.  Returns (element, xi, eta).  Raises
+        ValueError if a point lies in none of the node's elements."""
+        found = np.zeros(self.N, dtype=bool)
+        elem = np.zeros(self.N, dtype=np.int64)
+        XI = np.zeros(self.N)
+        ETA = np.zeros(self.N)
+        for k in range(self.P):
+            e = self.pe[:, k]
+            a = self.pa[:, k]
+            px = self.ex[e, a] + dx
+            py = self.ey[e, a] + dy
+            cx = self.ex[e, :4]
+            cy = self.ey[e, :4]
+            xi, eta = bilinear_local(cx, cy, px, py)
+            inside = (self.pm[:, k] & (np.abs(xi) <= 1 + INSIDE_TOL)
+                      & (np.abs(eta) <= 1 + INSIDE_TOL))
+            take = inside & ~found
+            elem = np.where(take, e, elem)
+            XI = np.where(take, xi, XI)
+            ETA = np.where(take, eta, ETA)
+            found |= take
+        if not np.all(found):
+            raise ValueError(f"departure point outside the patch of node {int(np.argmin(found))}")
+        return elem, XI, ETA
+
+
+def bilinear_local(cx, cy, px, py, iters=60):
+    """Local (xi, eta) in [-1, 1]^2 of points P under the bilinear map of
+    quadrilaterals with corners (cx, cy)[:, 0..3] at (-1,-1), (1,-1), (1,1),
+    (-1,1); Newton from the centre."""
+    xi = np.zeros(px.shape)
+    eta = np.zeros(px.shape)
+    for _ in range(iters):
+        n = [(1 - xi) * (1 - eta) / 4, (1 + xi) * (1 - eta) / 4,
+             (1 + xi) * (1 + eta) / 4, (1 - xi) * (1 + eta) / 4]
+        nxi = [-(1 - eta) / 4, (1 - eta) / 4, (1 + eta) / 4, -(1 + eta) / 4]
+        neta = [-(1 - xi) / 4, -(1 + xi) / 4, (1 + xi) / 4, (1 - xi) / 4]
+        rx = sum(n[c] * cx[:, c] for c in range(4)) - px
+        ry = sum(n[c] * cy[:, c] for c in range(4)) - py
+        a = sum(nxi[c] * cx[:, c] for c in range(4))
+        b = sum(neta[c] * cx[:, c] for c in range(4))
+        c_ = sum(nxi[c] * cy[:, c] for c in range(4))
+        d = sum(neta[c] * cy[:, c] for c in range(4))
+        det = a * d - b * c_
+        dxi = (d * rx - b * ry) / det
+        deta = (-c_ * rx + a * ry) / det
+        xi = xi - dxi
+        eta = eta - deta
+        if np.all(np.abs(dxi) + np.abs(deta) < 1e-15):
+            break
+    return xi, eta
+
+
+class UnstructuredSolver:
+    """Plain FP64 reference of the step on a static periodic Q9 mesh."""
+
+    def __init__(self, mesh, fluid, rho=None, ux=None, uy=None, T=None, correction=True):
+        self.grid = UGrid(mesh)
+        self.fluid = fluid
+        self.correction = correction
+        N = self.grid.N
+        if rho is None:
+            rho = np.full(N, fluid.rho_inf)
+            ux = np.full(N, fluid.u_inf[0])
+            uy = np.full(N, fluid.u_inf[1])
+            T = np.full(N, fluid.T_inf)
+        self.f, self.g = L.equilibrium_populations(rho, ux, uy, T, fluid.gamma)
+        self.n = 0
+        # departure points: element and local coordinates per direction (static mesh)
+        self.dep = [None] * L.Q
+        for i in range(1, L.Q):
+            self.dep[i] = self.grid.locate(-fluid.dt * L.CX[i], -fluid.dt * L.CY[i])
+
+    def correction_force(self):
+        fl = self.fluid
+        rho, ux, uy, E, T = L.macroscopic(self.f, self.g, fl.gamma)
+        omega, _ = L.relaxation_rates(rho, T, fl.mu, fl.Pr, fl.dt)
+        dQx, dQy = L.momentum_defect(rho, ux, uy, T)
+        gx, _ = self.grid.grad(dQx)
+        _, gy = self.grid.grad(dQy)
+        Dx = (1.0 / omega - 0.5) * fl.dt * gx
+        Dy = (1.0 / omega - 0.5) * fl.dt * gy
+        Fx, _ = self.grid.grad(Dx)
+        _, Fy = self.grid.grad(Dy)
+        return Fx, Fy
+
+    def step(self):
+        fl = self.fluid
+        if self.correction:
+            Fx, Fy = self.correction_force()
+        else:
+            Fx = Fy = np.zeros(self.grid.N)
+        fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, fl.dt, Fx, Fy)
+        f_new = np.empty_like(fpost)
+        g_new = np.empty_like(gpost)
+        f_new[0] = fpost[0]
+        g_new[0] = gpost[0]
+        els = self.grid.elems
+        for i in range(1, L.Q):
+            e, xi, eta = self.dep[i]
+            Nw = shape(xi, eta)                                 # [9, N]
+            nodes = els[e]                                       # [N, 9]
+            f_new[i] = np.sum(Nw.T * fpost[i][nodes], axis=1)
+            g_new[i] = np.sum(Nw.T * gpost[i][nodes], axis=1)
+        self.f, self.g = f_new, g_new
+        self.n += 1
+
+    def run(self, nsteps):
+        for _ in range(nsteps):
+            self.step()
+
+    def macroscopic(self):
+        return L.macroscopic(self.f, self.g, self.fluid.gamma)

@@ -1,0 +1,196 @@
+"""Unstructured second-order quadrilateral meshes (9-node elements) on a
+periodic box, as input data: node coordinates and element connectivity only.
+
+The paper's own discretisation uses unstructured second-order finite-element
+meshes.  This generator makes genuinely unstructured ones without an external
+mesher: a periodic m x m square grid is split into triangles (one diagonal per
+square, alternating with a seeded coin), every triangle is split into three
+quadrilaterals through its edge midpoints and centroid, and every
+quadrilateral becomes a 9-node element by adding its edge midpoints (shared
+with the neighbour) and its centre.  Vertices of the grid meet 4 to 8
+quadrilaterals, triangle centroids 3, edge midpoints 4.  The element corners
+are then displaced by a smooth periodic field, the edge and centre nodes put
+where the corners' bilinear map places them (straight-sided elements), and
+the nodes renumbered along a space-filling (Morton) order.
+
+Element node order: corners at local (-1,-1), (1,-1), (1,1), (-1,1), then the
+edge midpoints (0,-1), (1,0), (0,1), (-1,0), then the centre (0,0), counter-
+clockwise (positive Jacobian).  Elements crossing the periodic seams carry,
+for each of their nodes, the number of periods (sx, sy) to add to that node's
+stored coordinates to place it next to the element's other nodes.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# local (xi, eta) of the 9 element nodes, in element node order
+Q9_LOCAL = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1],
+                     [0, -1], [1, 0], [0, 1], [-1, 0], [0, 0]], dtype=np.int64)
+
+
+@dataclass
+class UnstructuredMesh:
+    X: np.ndarray            # [N] float64
+    Y: np.ndarray            # [N] float64
+    elems: np.ndarray        # [E, 9] int32 node indices
+    shifts: np.ndarray       # [E, 9, 2] int8 periods added to each element node
+    period: tuple            # (Lx, Ly)
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.X.size)
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.elems.shape[0])
+
+
+def _morton(ix, iy, bits=16):
+    out = np.zeros_like(ix, dtype=np.int64)
+    for b in range(bits):
+        out |= ((ix >> b) & 1) << (2 * b)
+        out |= ((iy >> b) & 1) << (2 * b + 1)
+    return out
+
+
+def unstructured_q9_mesh(m: int = 32, L: float | None = None, amp: float = 0.06,
+                         seed: int = 0) -> UnstructuredMesh:
+    """Periodic box [0, L)^2 (L = 6 m by default, so that the smallest node
+    spacing is about one lattice unit), 6 m^2 elements, 24 m^2 nodes.
+
+    amp: amplitude of the smooth displacement, in units of the grid spacing
+    L / m (x += amp h sin(2 pi y / L) sin(2 pi x / L + 1), y += amp h
+    sin(2 pi x / L) cos(2 pi y / L + 2))."""
+    L = float(6 * m if L is None else L)
+    h = L / m
+    rng = np.random.default_rng(seed)
+    # exact positions in units of h/24 (integers): grid points are multiples
+    # of 24, triangle edge midpoints of 12, centroids of 8, and the element
+    # edge midpoints and centres built from them stay integral
+    S = 24 * m                                  # period in lattice units
+    key_to_id = {}
+    pts = []
+
+    def node(px, py):
+        k = (px % S, py % S)
+        i = key_to_id.get(k)
+        if i is None:
+            i = len(pts)
+            key_to_id[k] = i
+            pts.append(k)
+        return i
+
+    elems = []
+    shifts = []
+
+    def add_quad(c):
+        # c: 4 corners (unwrapped lattice coordinates), counter-clockwise
+        mids = [((c[a][0] + c[b][0]) // 2, (c[a][1] + c[b][1]) // 2)
+                for a, b in ((0, 1), (1, 2), (2, 3), (3, 0))]
+        cen = (sum(p[0] for p in c) // 4, sum(p[1] for p in c) // 4)
+        allp = list(c) + mids + [cen]
+        ids = [node(*p) for p in allp]
+        sh = [((p[0] - (p[0] % S)) // S, (p[1] - (p[1] % S)) // S) for p in allp]
+        elems.append(ids)
+        shifts.append(sh)
+
+    for j in range(m):
+        for i in range(m):
+            x0, y0 = 24 * i, 24 * j
+            A, B, C, D = (x0, y0), (x0 + 24, y0), (x0 + 24, y0 + 24), (x0, y0 + 24)
+            tris = [(A, B, C), (A, C, D)] if rng.random() < 0.5 else [(A, B, D), (B, C, D)]
+            for (p, q, r) in tris:
+                g = ((p[0] + q[0] + r[0]) // 3, (p[1] + q[1] + r[1]) // 3)
+                mpq = ((p[0] + q[0]) // 2, (p[1] + q[1]) // 2)
+                mqr = ((q[0] + r[0]) // 2, (q[1] + r[1]) // 2)
+                mrp = ((r[0] + p[0]) // 2, (r[1] + p[1]) // 2)
+                add_quad([p, mpq, g, mrp])
+                add_quad([q, mqr, g, mpq])
+                add_quad([r, mrp, g, mqr])
+    P = np.array(pts, dtype=np.int64)
+    E = np.array(elems, dtype=np.int64)
+    SH = np.array(shifts, dtype=np.int64)
+    # lattice units -> length; the smooth periodic displacement moves the
+    # element corners, and the edge and centre nodes are then placed where
+    # the corners' bilinear map puts them (straight-sided elements, as a
+    # second-order mesher makes away from curved boundaries)
+    x = P[:, 0] * (L / S)
+    y = P[:, 1] * (L / S)
+    tx, ty = 2 * np.pi * x / L, 2 * np.pi * y / L
+    X = x + amp * h * np.sin(ty) * np.sin(tx + 1.0)
+    Y = y + amp * h * np.sin(tx) * np.cos(ty + 2.0)
+    ex = X[E] + SH[..., 0] * L
+    ey = Y[E] + SH[..., 1] * L
+    for k, (a, b) in enumerate(((0, 1), (1, 2), (2, 3), (3, 0))):
+        X[E[:, 4 + k]] = 0.5 * (ex[:, a] + ex[:, b]) - SH[:, 4 + k, 0] * L
+        Y[E[:, 4 + k]] = 0.5 * (ey[:, a] + ey[:, b]) - SH[:, 4 + k, 1] * L
+    X[E[:, 8]] = 0.25 * (ex[:, 0] + ex[:, 1] + ex[:, 2] + ex[:, 3]) - SH[:, 8, 0] * L
+    Y[E[:, 8]] = 0.25 * (ey[:, 0] + ey[:, 1] + ey[:, 2] + ey[:, 3]) - SH[:, 8, 1] * L
+    # Morton renumbering of the nodes
+    order = np.argsort(_morton(P[:, 0], P[:, 1]), kind="stable")
+    new_id = np.empty_like(order)
+    new_id[order] = np.arange(order.size)
+    X, Y = X[order], Y[order]
+    E = new_id[E]
+    # elements in Morton order of their centre node
+    eorder = np.argsort(E[:, 8], kind="stable")
+    E, SH = E[eorder], SH[eorder]
+    return UnstructuredMesh(X.astype(np.float64), Y.astype(np.float64), E.astype(np.int32),
+                            SH.astype(np.int8), (L, L),
+                            info={"kind": "tri_split_q9", "m": m, "amp": amp, "seed": seed})
+
+
+def element_coords(mesh: UnstructuredMesh):
+    """Unwrapped coordinates [E, 9] of every element's nodes."""
+    ex = mesh.X[mesh.elems] + mesh.shifts[..., 0] * mesh.period[0]
+    ey = mesh.Y[mesh.elems] + mesh.shifts[..., 1] * mesh.period[1]
+    return ex, ey
+
+
+def smallest_patch_reach(mesh: UnstructuredMesh) -> float:
+    """A lower bound on how far a departure point may move from its node and
+    stay inside the node's elements: over all elements, the smallest distance
+    from one of its nodes to an edge of the element that does not hold that
+    node, halved (a node's elements surround it at least that far)."""
+    ex, ey = element_coords(mesh)
+    corners = [(0, 1), (1, 2), (2, 3), (3, 0)]
+    best = np.inf
+    for a in range(9):
+        for (p, q) in corners:
+            # skip edges that contain node a (corners p, q or the midpoint between them)
+            mid = 4 + corners.index((p, q))
+            if a in (p, q, mid):
+                continue
+            x1, y1, x2, y2 = ex[:, p], ey[:, p], ex[:, q], ey[:, q]
+            tx, ty = x2 - x1, y2 - y1
+            d = np.abs((ex[:, a] - x1) * ty - (ey[:, a] - y1) * tx) / np.hypot(tx, ty)
+            best = min(best, float(d.min()))
+    return 0.5 * best
+
+
+def unstructured_pulse_case(m: int = 16, amp: float = 0.06, seed: int = 0, Ma: float = 0.1,
+                            nu: float = 0.02, pulse: float = 1e-3, T0: float = 1.0 / 3.0,
+                            gamma: float = 1.4, Pr: float = 0.71, storage: int = 0):
+    """Gas streaming diagonally through the periodic unstructured box with a
+    Gaussian density pulse (width 4 lattice units) at the centre.  dt is a
+    third of the smallest patch reach divided by sqrt(2), so every departure
+    point stays inside its node's elements."""
+    from .configs import FluidParams, sound_speed
+    mesh = unstructured_q9_mesh(m, amp=amp, seed=seed)
+    dt = smallest_patch_reach(mesh) / (3.0 * np.sqrt(2.0))
+    U = Ma * sound_speed(gamma, T0)
+    u0 = (U / np.sqrt(2.0), U / np.sqrt(2.0))
+    fluid = FluidParams(gamma=gamma, Pr=Pr, mu=nu, rho_inf=1.0, T_inf=T0, u_inf=u0, dt=dt,
+                        storage=storage)
+    Lx, Ly = mesh.period
+    dx = mesh.X - 0.5 * Lx
+    dy = mesh.Y - 0.5 * Ly
+    dx -= Lx * np.round(dx / Lx)
+    dy -= Ly * np.round(dy / Ly)
+    rho = 1.0 + pulse * np.exp(-(dx * dx + dy * dy) / (2.0 * 16.0))
+    N = mesh.n_nodes
+    return mesh, fluid, (rho, np.full(N, u0[0]), np.full(N, u0[1]), np.full(N, T0))
