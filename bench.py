@@ -36,10 +36,15 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2107_01370_amd", "csrc", "fsilbm_kernels.hip")
 
 
-def algorithmic_bytes_per_node(storage: int) -> int:
+def algorithmic_bytes_per_node(storage: int, unstructured: bool = False) -> int:
     """Populations read once and written once (18 values each way) plus the
-    FP64 node coordinates (16 B) needed to recompute the departure points."""
+    FP64 node coordinates (16 B) needed to recompute the departure points.
+    Unstructured 9-node meshes (static): the populations plus the static
+    connectivity and geometry, 0.25 elements per node of 9 node indices and 9
+    FP32 offsets (108 B) and the node-to-element table (3.25 ints): 40 B."""
     per_pop = 2 if storage == 1 else 4
+    if unstructured:
+        return 2 * 18 * per_pop + 40
     return 2 * 18 * per_pop + 16
 
 
@@ -74,6 +79,9 @@ WORKLOADS = {
                                    "on its own spring (1+1DOF), Ma 0.1, Re 1000, m* 4, U* 6",
     "tandem_linked_2304x320": "twin O-grid, two rigidly linked cylinders in tandem (L/D 5, "
                               "D 200) on one spring (1DOF), Ma 0.1, Re 1000, m* 4, U* 6",
+    "unstructured_q9_1572864": "unstructured periodic mesh of 393,216 nine-node quadrilateral "
+                               "elements (1,572,864 nodes, triangles split into quadrilaterals), "
+                               "diagonal stream Ma 0.1 with a density pulse",
 }
 
 
@@ -90,7 +98,17 @@ def workload_case(name: str, storage: int):
         return synth.tandem_cylinders_case(linked=False, h0_frac=0.01, storage=storage)
     if name == "tandem_linked_2304x320":
         return synth.tandem_cylinders_case(linked=True, h0_frac=0.01, storage=storage)
+    if name == "unstructured_q9_1572864":
+        return unstructured_case(256, storage)
     raise SystemExit(f"unknown workload {name}")
+
+
+def unstructured_case(m: int, storage: int):
+    from synth.configs import Case
+    from synth.unstructured import unstructured_pulse_case
+    mesh, fluid, (rho, ux, uy, T) = unstructured_pulse_case(m, storage=storage)
+    return Case(f"unstructured_q9_{mesh.n_nodes}", mesh, fluid, [], rho[None], ux[None], uy[None],
+                T[None])
 
 
 def time_gpu(case, steps: int, warmup: int, kernel_reps: int = 20, subiterations: int = 1,
@@ -179,6 +197,35 @@ def time_sequential(cases, steps: int, warmup: int):
     return total_ms
 
 
+def cpu_baseline_unstructured(target_s: float = 20.0, m: int = 48):
+    """Oracle (plain FP64 NumPy) timed on a smaller mesh of the same
+    construction and physics (m = 48: 55,296 nodes)."""
+    from oracle.unstructured import UnstructuredSolver
+    from synth.unstructured import unstructured_pulse_case
+
+    mesh, fluid, (rho, ux, uy, T) = unstructured_pulse_case(m)
+    ora = UnstructuredSolver(mesh, fluid, rho, ux, uy, T)
+    ora.step()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        ora.step()
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or n >= 200:
+            break
+    threads = os.environ.get("OMP_NUM_THREADS", "1")
+    return {
+        "value": mesh.n_nodes * n / el / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n} steps of the same construction at m = {m} ({mesh.n_nodes} nodes, "
+                  f"{mesh.n_elems} elements) with the same physics, {el:.1f} s, single-threaded "
+                  f"NumPy (OMP_NUM_THREADS={threads}), os.cpu_count()={os.cpu_count()}",
+    }
+
+
 def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
     """Oracle (plain FP64 NumPy) timed on a strip of the same workload: the
     first `rows` radial rows of the O-grid (wall included) with the same
@@ -254,7 +301,7 @@ def main():
                                      relaxation=args.relaxation)
     ms_per_step = total_ms / args.steps
     mlups = N * args.steps / (total_ms * 1e-3) / 1e6
-    bpn = algorithmic_bytes_per_node(storage)
+    bpn = algorithmic_bytes_per_node(storage, args.workload.startswith("unstructured"))
     k1_ms = float(kms[0])
     achieved = bpn * N / (k1_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, storage, N)
@@ -285,7 +332,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_collide_stream",
+            "kernel": ("k_u_moments + k_u_grad + k_u_collide + k_u_stream"
+                       if args.workload.startswith("unstructured") else "k_collide_stream"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -326,7 +374,8 @@ def main():
             "finite_state": finb,
         })
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"] = (cpu_baseline_unstructured() if args.workload.startswith("unstructured")
+                               else cpu_baseline(case))
     print(json.dumps(out), flush=True)
 
 

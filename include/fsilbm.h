@@ -109,9 +109,23 @@ typedef struct {
  *              ((nA - i) mod ni, 0) for nA <= i <= nA + n_wake.  Wall column
  *              segment 0 belongs to body 0, segment 1 to body 1 (nbodies must
  *              be 2).  Junction copies merge and slit copies are kept
- *              single-valued as on a C-grid.                               */
+ *              single-valued as on a C-grid.
+ *   Q9:        unstructured mesh of 9-node quadrilateral elements (the
+ *              paper's own discretisation, Sec. II.B), static and periodic
+ *              (period shift_i[0] along x, shift_j[1] along y); no wall, no
+ *              far field, no body.  ni = number of nodes, nj = 1; X holds the
+ *              node coordinates; `elems` [n_elems][9] the nodes of each
+ *              element in the order corners (-1,-1), (1,-1), (1,1), (-1,1),
+ *              edge midpoints (0,-1), (1,0), (0,1), (-1,0), centre (0,0),
+ *              counter-clockwise; `elem_shifts` [n_elems][9][2] the periods
+ *              to add to each node's coordinates to place it next to the
+ *              element's other nodes.  Edge and centre nodes must sit where
+ *              the corners' bilinear map puts them (straight-sided elements):
+ *              departure points are located with that map and interpolated
+ *              with the nine shape functions.  Nodal derivatives are the mean
+ *              over a node's elements of the element derivatives there.    */
 typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1, FSI_TOPO_CGRID = 2,
-               FSI_TOPO_TWIN = 3 } fsi_topo;
+               FSI_TOPO_TWIN = 3, FSI_TOPO_Q9 = 4 } fsi_topo;
 
 /* Most bodies one mesh carries (TWIN: exactly this many). */
 #define FSI_MAX_BODIES 2
@@ -124,6 +138,9 @@ typedef struct {
     double shift_j[2];      /* PERIODIC2 only */
     int n_wake;             /* CGRID: cut nodes on each side (>= 2); TWIN: slit cells (>= 2) */
     int n_wall2;            /* TWIN only: wall cells round the second body (>= 8) */
+    int n_elems;            /* Q9 only: elements */
+    const int32_t *elems;   /* Q9 only: host, [n_elems][9] node indices; copied */
+    const int8_t *elem_shifts;  /* Q9 only: host, [n_elems][9][2] periods (-1, 0, 1); copied */
 } fsi_mesh_desc;
 
 /* Rigid-body degrees of freedom (Sec. IV). */

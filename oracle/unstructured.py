@@ -75,19 +75,23 @@ class UGrid:
         # unwrapped node coordinates of every element
         self.ex = mesh.X[self.elems] + sh[..., 0] * Lx
         self.ey = mesh.Y[self.elems] + sh[..., 1] * Ly
-        # patches: the (element, local node) pairs of every node, by element index
-        pairs = sorted((int(n), e, a) for e in range(self.E) for a, n in enumerate(self.elems[e]))
-        self.patch = [[] for _ in range(self.N)]
-        for n, e, a in pairs:
-            self.patch[n].append((e, a))
-        self.P = max(len(p) for p in self.patch)
+        # patches: the (element, local node) pairs of every node, by element
+        # index (a stable sort of all pairs by node)
+        node = self.elems.ravel()
+        elem = np.repeat(np.arange(self.E), 9)
+        loc = np.tile(np.arange(9), self.E)
+        order = np.lexsort((elem, node))
+        node, elem, loc = node[order], elem[order], loc[order]
+        self.count = np.bincount(node, minlength=self.N)
+        start = np.concatenate([[0], np.cumsum(self.count)[:-1]])
+        rank = np.arange(node.size) - start[node]
+        self.P = int(self.count.max())
         self.pe = np.zeros((self.N, self.P), dtype=np.int64)
         self.pa = np.zeros((self.N, self.P), dtype=np.int64)
         self.pm = np.zeros((self.N, self.P), dtype=bool)
-        for n, p in enumerate(self.patch):
-            for k, (e, a) in enumerate(p):
-                self.pe[n, k], self.pa[n, k], self.pm[n, k] = e, a, True
-        self.count = self.pm.sum(axis=1)
+        self.pe[node, rank] = elem
+        self.pa[node, rank] = loc
+        self.pm[node, rank] = True
         # element derivative operator at each element's own nodes:
         # dC/dx at local node a of element e = sum_s Wx[e, a, s] C_s
         self.Wx = np.zeros((self.E, 9, 9))
@@ -123,51 +127,73 @@ class UGrid:
         elem = np.zeros(self.N, dtype=np.int64)
         XI = np.zeros(self.N)
         ETA = np.zeros(self.N)
+        dx = np.broadcast_to(dx, (self.N,))
+        dy = np.broadcast_to(dy, (self.N,))
         for k in range(self.P):
-            e = self.pe[:, k]
-            a = self.pa[:, k]
-            px = self.ex[e, a] + dx
-            py = self.ey[e, a] + dy
-            cx = self.ex[e, :4]
-            cy = self.ey[e, :4]
-            xi, eta = bilinear_local(cx, cy, px, py)
-            inside = (self.pm[:, k] & (np.abs(xi) <= 1 + INSIDE_TOL)
-                      & (np.abs(eta) <= 1 + INSIDE_TOL))
-            take = inside & ~found
-            elem = np.where(take, e, elem)
-            XI = np.where(take, xi, XI)
-            ETA = np.where(take, eta, ETA)
-            found |= take
+            # the k-th element of the patches of the nodes not yet placed
+            todo = np.flatnonzero(self.pm[:, k] & ~found)
+            if todo.size == 0:
+                continue
+            e = self.pe[todo, k]
+            a = self.pa[todo, k]
+            # coordinates relative to the node (well conditioned)
+            cx = self.ex[e, :4] - self.ex[e, a][:, None]
+            cy = self.ey[e, :4] - self.ey[e, a][:, None]
+            xi, eta = bilinear_local(cx, cy, dx[todo], dy[todo])
+            inside = (np.abs(xi) <= 1 + INSIDE_TOL) & (np.abs(eta) <= 1 + INSIDE_TOL)
+            hit = todo[inside]
+            elem[hit] = e[inside]
+            XI[hit] = xi[inside]
+            ETA[hit] = eta[inside]
+            found[hit] = True
         if not np.all(found):
             raise ValueError(f"departure point outside the patch of node {int(np.argmin(found))}")
         return elem, XI, ETA
 
 
-def bilinear_local(cx, cy, px, py, iters=60):
-    """Local (xi, eta) in [-1, 1]^2 of points P under the bilinear map of
-    quadrilaterals with corners (cx, cy)[:, 0..3] at (-1,-1), (1,-1), (1,1),
-    (-1,1); Newton from the centre."""
+def bilinear_local(cx, cy, px, py, iters=25):
+    """Local (xi, eta) of points P under the bilinear map of quadrilaterals
+    with corners (cx, cy)[:, 0..3] at (-1,-1), (1,-1), (1,1), (-1,1); Newton
+    from the centre.  Inside a convex element it converges quadratically in a
+    few steps; points where it has not settled after `iters` steps (far
+    outside, where the extended map can fold) get NaN."""
     xi = np.zeros(px.shape)
     eta = np.zeros(px.shape)
+    # the points still moving, with their data kept compact
+    live = np.arange(px.size)
+    cx, cy, px, py = cx, cy, px, py
+    x_, e_ = xi.copy(), eta.copy()
     for _ in range(iters):
-        n = [(1 - xi) * (1 - eta) / 4, (1 + xi) * (1 - eta) / 4,
-             (1 + xi) * (1 + eta) / 4, (1 - xi) * (1 + eta) / 4]
-        nxi = [-(1 - eta) / 4, (1 - eta) / 4, (1 + eta) / 4, -(1 + eta) / 4]
-        neta = [-(1 - xi) / 4, -(1 + xi) / 4, (1 + xi) / 4, (1 - xi) / 4]
-        rx = sum(n[c] * cx[:, c] for c in range(4)) - px
-        ry = sum(n[c] * cy[:, c] for c in range(4)) - py
-        a = sum(nxi[c] * cx[:, c] for c in range(4))
-        b = sum(neta[c] * cx[:, c] for c in range(4))
-        c_ = sum(nxi[c] * cy[:, c] for c in range(4))
-        d = sum(neta[c] * cy[:, c] for c in range(4))
-        det = a * d - b * c_
-        dxi = (d * rx - b * ry) / det
-        deta = (-c_ * rx + a * ry) / det
-        xi = xi - dxi
-        eta = eta - deta
-        if np.all(np.abs(dxi) + np.abs(deta) < 1e-15):
+        if live.size == 0:
             break
+        dxi, deta = _newton_update(cx, cy, px, py, x_, e_)
+        x_ = x_ - dxi
+        e_ = e_ - deta
+        xi[live] = x_
+        eta[live] = e_
+        moving = ~(np.abs(dxi) + np.abs(deta) < 1e-13)   # quadratic convergence: error ~1e-26 after
+        if not np.all(moving):
+            live, cx, cy, px, py = live[moving], cx[moving], cy[moving], px[moving], py[moving]
+            x_, e_ = x_[moving], e_[moving]
+    xi[live] = np.nan
+    eta[live] = np.nan
     return xi, eta
+
+
+def _newton_update(cx, cy, px, py, xi, eta):
+    """One Newton correction (dxi, deta) of the bilinear corner map."""
+    n = [(1 - xi) * (1 - eta) / 4, (1 + xi) * (1 - eta) / 4,
+         (1 + xi) * (1 + eta) / 4, (1 - xi) * (1 + eta) / 4]
+    nxi = [-(1 - eta) / 4, (1 - eta) / 4, (1 + eta) / 4, -(1 + eta) / 4]
+    neta = [-(1 - xi) / 4, -(1 + xi) / 4, (1 + xi) / 4, (1 - xi) / 4]
+    rx = sum(n[c] * cx[:, c] for c in range(4)) - px
+    ry = sum(n[c] * cy[:, c] for c in range(4)) - py
+    a = sum(nxi[c] * cx[:, c] for c in range(4))
+    b = sum(neta[c] * cx[:, c] for c in range(4))
+    c_ = sum(nxi[c] * cy[:, c] for c in range(4))
+    d = sum(neta[c] * cy[:, c] for c in range(4))
+    det = a * d - b * c_
+    return (d * rx - b * ry) / det, (-c_ * rx + a * ry) / det
 
 
 class UnstructuredSolver:

@@ -24,6 +24,11 @@ struct fsi_ctx {
     double shift_i[2] = {0, 0}, shift_j[2] = {0, 0};
     std::vector<double> X;          // [nj][ni][2]
     std::vector<fsi_body_desc> bodies;
+    // unstructured 9-node meshes
+    int n_elems = 0;
+    std::vector<int> elems;         // [E][9]
+    std::vector<float2> erel;       // [E][9] offsets from the element's centre node
+    std::vector<int> patch_off, patch_ent;
     hipStream_t stream = nullptr;
     int n_sub = 1;                  // coupling sub-iterations per step
     double relax = 1.0;
@@ -32,7 +37,8 @@ struct fsi_ctx {
     size_t off_pop[2]{}, off_X = 0, off_mask = 0, off_tgt = 0, off_B = 0, off_inflow = 0,
            off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
            off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0, off_dist = 0,
-           off_resid = 0, total = 0;
+           off_resid = 0, off_elems = 0, off_erel = 0, off_poff = 0, off_pent = 0, off_uq = 0,
+           off_ud = 0, off_upost = 0, total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
     std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
@@ -212,8 +218,80 @@ fsi_status topology(fsi_ctx *c) {
     return FSI_OK;
 }
 
+// unstructured 9-node mesh: connectivity, periodic offsets, node patches and
+// element geometry; every element positively oriented at all nine nodes
+fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
+    const int N = c->ni, E = mesh->n_elems;
+    if (E < 1 || !mesh->elems || !mesh->elem_shifts)
+        return fail(c, FSI_E_MESH, "Q9 mesh needs n_elems >= 1, elems and elem_shifts");
+    const double Lx = c->shift_i[0], Ly = c->shift_j[1];
+    if (!(Lx > 0) || !(Ly > 0)) return fail(c, FSI_E_MESH, "Q9 mesh needs periods shift_i[0], shift_j[1] > 0");
+    c->n_elems = E;
+    c->elems.assign(mesh->elems, mesh->elems + 9 * (size_t)E);
+    std::vector<int> count(N, 0);
+    for (int e = 0; e < E; ++e)
+        for (int a = 0; a < 9; ++a) {
+            const int v = c->elems[9 * (size_t)e + a];
+            const int sx = mesh->elem_shifts[18 * (size_t)e + 2 * a], sy = mesh->elem_shifts[18 * (size_t)e + 2 * a + 1];
+            if (v < 0 || v >= N || sx < -1 || sx > 1 || sy < -1 || sy > 1)
+                return fail(c, FSI_E_MESH, "Q9 element " + std::to_string(e) + ": node index or shift out of range");
+            ++count[v];
+        }
+    for (int v = 0; v < N; ++v)
+        if (!count[v]) return fail(c, FSI_E_MESH, "Q9 node " + std::to_string(v) + " belongs to no element");
+    // patches in element order
+    c->patch_off.assign(N + 1, 0);
+    for (int v = 0; v < N; ++v) c->patch_off[v + 1] = c->patch_off[v] + count[v];
+    c->patch_ent.assign(9 * (size_t)E, 0);
+    std::vector<int> fill(c->patch_off.begin(), c->patch_off.end() - 1);
+    for (int e = 0; e < E; ++e)
+        for (int a = 0; a < 9; ++a) c->patch_ent[fill[c->elems[9 * (size_t)e + a]]++] = e * 16 + a;
+    // geometry: FP64 unwrapped coordinates, offsets from the centre node in FP32
+    const int lp[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0}, lq[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
+    auto dl = [](int p, int x) { return p < 0 ? x - 0.5 : (p == 0 ? -2.0 * x : x + 0.5); };
+    c->erel.assign(9 * (size_t)E, make_float2(0, 0));
+    for (int e = 0; e < E; ++e) {
+        double x[9], y[9];
+        for (int a = 0; a < 9; ++a) {
+            const int v = c->elems[9 * (size_t)e + a];
+            x[a] = c->X[2 * (size_t)v] + mesh->elem_shifts[18 * (size_t)e + 2 * a] * Lx;
+            y[a] = c->X[2 * (size_t)v + 1] + mesh->elem_shifts[18 * (size_t)e + 2 * a + 1] * Ly;
+        }
+        for (int a = 0; a < 9; ++a) c->erel[9 * (size_t)e + a] = make_float2((float)(x[a] - x[8]), (float)(y[a] - y[8]));
+        // edge and centre nodes on the corners' bilinear map
+        const int ca[4] = {0, 1, 2, 3}, cb[4] = {1, 2, 3, 0};
+        const double h = fabs(x[1] - x[0]) + fabs(y[1] - y[0]) + fabs(x[3] - x[0]) + fabs(y[3] - y[0]);
+        for (int k = 0; k < 4; ++k) {
+            const double mx = 0.5 * (x[ca[k]] + x[cb[k]]), my = 0.5 * (y[ca[k]] + y[cb[k]]);
+            if (fabs(x[4 + k] - mx) + fabs(y[4 + k] - my) > 1e-9 * h)
+                return fail(c, FSI_E_MESH, "Q9 element " + std::to_string(e) + ": edge node off its edge's midpoint");
+        }
+        if (fabs(x[8] - 0.25 * (x[0] + x[1] + x[2] + x[3])) + fabs(y[8] - 0.25 * (y[0] + y[1] + y[2] + y[3])) > 1e-9 * h)
+            return fail(c, FSI_E_MESH, "Q9 element " + std::to_string(e) + ": centre node off the corners' centre");
+        // positive Jacobian at the nine nodes
+        for (int a = 0; a < 9; ++a) {
+            double xxi = 0, yxi = 0, xeta = 0, yeta = 0;
+            for (int m = -1; m <= 1; ++m) {
+                int si = -1, sj = -1;
+                for (int b = 0; b < 9; ++b) {
+                    if (lp[b] == m && lq[b] == lq[a]) si = b;
+                    if (lp[b] == lp[a] && lq[b] == m) sj = b;
+                }
+                xxi += dl(m, lp[a]) * x[si];
+                yxi += dl(m, lp[a]) * y[si];
+                xeta += dl(m, lq[a]) * x[sj];
+                yeta += dl(m, lq[a]) * y[sj];
+            }
+            if (!(xxi * yeta - yxi * xeta > 0))
+                return fail(c, FSI_E_MESH, "Q9 element " + std::to_string(e) + ": det J <= 0 at a node");
+        }
+    }
+    return FSI_OK;
+}
+
 fsi_status validate_and_precompute(fsi_ctx *c) {
     const int ni = c->ni, nj = c->nj;
+    if (c->topo == FSI_TOPO_Q9) return FSI_OK;    // validated by validate_q9
     fsi_status tst = topology(c);
     if (tst != FSI_OK) return tst;
     if (c->cut) {
@@ -399,6 +477,7 @@ void fill_params(fsi_ctx *c) {
     P.n_sub = c->n_sub;
     P.relax = c->relax;
     P.storage = fl.storage;
+    P.n_elems = c->n_elems;
     P.tiles_i = (c->ni + fsi::TILE_X - 1) / fsi::TILE_X;
     P.tiles_j = (c->nj + fsi::TILE_Y - 1) / fsi::TILE_Y;
     P.tile_base = 0;
@@ -458,7 +537,7 @@ void fill_params(fsi_ctx *c) {
         B.blend_mode = b.blend_mode;
     }
     // work lists
-    const int ntiles = P.tiles_i * P.tiles_j;
+    const int ntiles = c->topo == FSI_TOPO_Q9 ? 0 : P.tiles_i * P.tiles_j;
     c->wk1.resize(ntiles);
     for (int t = 0; t < ntiles; ++t) c->wk1[t] = make_int2(0, t);
     c->wbnd.clear();
@@ -515,6 +594,15 @@ void layout(fsi_ctx *c) {
     c->off_wk0 = take(c->wk0.size() * sizeof(int2));
     c->off_dist = take(c->wall_dist.size() * sizeof(double));
     c->off_resid = take(fsi::MAX_BODIES * sizeof(double));
+    if (c->topo == FSI_TOPO_Q9) {
+        c->off_elems = take(c->elems.size() * 4);
+        c->off_erel = take(c->erel.size() * sizeof(float2));
+        c->off_poff = take(c->patch_off.size() * 4);
+        c->off_pent = take(c->patch_ent.size() * 4);
+        c->off_uq = take(N * sizeof(float4));
+        c->off_ud = take(N * sizeof(float2));
+        c->off_upost = take(fsi::NPOP * N * bpp);
+    }
     c->total = o;
 }
 
@@ -532,6 +620,10 @@ const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c
 // and traction of the new level
 fsi_status enqueue_fluid(fsi_ctx *c) {
     const int st = c->fluid.storage;
+    if (c->topo == FSI_TOPO_Q9) {
+        HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, st, c->stream));
+        return FSI_OK;
+    }
     if (!c->wk0.empty())
         HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
@@ -608,10 +700,13 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
     c->n_wall2 = mesh->n_wall2;
     c->has_wall = c->topo == FSI_TOPO_OGRID || c->topo == FSI_TOPO_CGRID || c->topo == FSI_TOPO_TWIN;
     c->stream = (hipStream_t)hip_stream;
-    if (c->ni < 8 || c->nj < 8) return fail(c, FSI_E_ARG, "mesh needs ni >= 8 and nj >= 8");
     if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_OGRID && c->topo != FSI_TOPO_CGRID &&
-        c->topo != FSI_TOPO_TWIN)
+        c->topo != FSI_TOPO_TWIN && c->topo != FSI_TOPO_Q9)
         return fail(c, FSI_E_ARG, "unsupported topology");
+    if (c->topo == FSI_TOPO_Q9 ? (c->ni < 9 || c->nj != 1) : (c->ni < 8 || c->nj < 8))
+        return fail(c, FSI_E_ARG, c->topo == FSI_TOPO_Q9 ? "a Q9 mesh has ni = nodes >= 9 and nj = 1"
+                                                         : "mesh needs ni >= 8 and nj >= 8");
+    if (c->topo == FSI_TOPO_Q9 && nbodies != 0) return fail(c, FSI_E_ARG, "a Q9 mesh carries no body");
     if (c->topo == FSI_TOPO_TWIN ? nbodies != fsi::MAX_BODIES : (nbodies < 0 || nbodies > 1))
         return fail(c, FSI_E_ARG, c->topo == FSI_TOPO_TWIN ? "a twin O-grid carries 2 bodies"
                                                            : "nbodies must be 0 or 1");
@@ -628,7 +723,8 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
         c->shift_i[k] = mesh->shift_i[k];
         c->shift_j[k] = mesh->shift_j[k];
     }
-    if (c->topo != FSI_TOPO_PERIODIC2) c->shift_i[0] = c->shift_i[1] = c->shift_j[0] = c->shift_j[1] = 0;
+    if (c->topo != FSI_TOPO_PERIODIC2 && c->topo != FSI_TOPO_Q9)
+        c->shift_i[0] = c->shift_i[1] = c->shift_j[0] = c->shift_j[1] = 0;
     c->X.assign(mesh->X, mesh->X + 2 * (size_t)c->ni * c->nj);
     for (double v : c->X)
         if (!isfinite(v)) return fail(c, FSI_E_MESH, "non-finite mesh coordinate");
@@ -636,6 +732,10 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
         c->bodies.push_back(bodies[k]);
         if ((bodies[k].link < 0 && (bodies[k].dof < 0 || bodies[k].dof > 3)))
             return fail(c, FSI_E_ARG, "unknown body dof");
+    }
+    if (c->topo == FSI_TOPO_Q9) {
+        fsi_status sq = validate_q9(c, mesh);
+        if (sq != FSI_OK) return sq;
     }
     fsi_status st = validate_and_precompute(c);
     if (st != FSI_OK) return st;
@@ -676,6 +776,23 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     P.slots = reinterpret_cast<fsi::BodySlot *>(c->ws + c->off_slots);
     P.history = reinterpret_cast<double *>(c->ws + c->off_hist);
     P.resid = reinterpret_cast<double *>(c->ws + c->off_resid);
+    if (c->topo == FSI_TOPO_Q9) {
+        P.elems = reinterpret_cast<const int *>(c->ws + c->off_elems);
+        P.erel = reinterpret_cast<const float2 *>(c->ws + c->off_erel);
+        P.patch_off = reinterpret_cast<const int *>(c->ws + c->off_poff);
+        P.patch_ent = reinterpret_cast<const int *>(c->ws + c->off_pent);
+        P.uq = reinterpret_cast<float4 *>(c->ws + c->off_uq);
+        P.ud = reinterpret_cast<float2 *>(c->ws + c->off_ud);
+        P.upost = c->ws + c->off_upost;
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_elems, c->elems.data(), c->elems.size() * 4,
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_erel, c->erel.data(), c->erel.size() * sizeof(float2),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_poff, c->patch_off.data(), c->patch_off.size() * 4,
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_pent, c->patch_ent.data(), c->patch_ent.size() * 4,
+                                  hipMemcpyHostToDevice, c->stream));
+    }
     P.step = reinterpret_cast<long long *>(c->ws + c->off_step);
     P.err = reinterpret_cast<unsigned *>(c->ws + c->off_err);
     P.scratch = nullptr;
@@ -983,7 +1100,9 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
             if (which == 0 && !c->wk0.empty())
                 HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                                   (int)c->wk0.size(), stg, c->stream));
-            if (which == 0)
+            if (which == 0 && c->topo == FSI_TOPO_Q9)
+                e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, stg, c->stream);
+            else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
                                                c->cut, 0);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
@@ -1201,6 +1320,8 @@ fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mes
             return st;
         }
         b->ctx.push_back(c);
+        if (c->topo == FSI_TOPO_Q9)
+            return bfail(b, FSI_E_ARG, "instance " + std::to_string(k) + ": Q9 meshes run as single contexts");
         if (k == 0) b->storage = c->fluid.storage;
         if (c->fluid.storage != b->storage) return bfail(b, FSI_E_ARG, "mixed storage precisions");
         if (c->has_wall) b->any_wall = true;

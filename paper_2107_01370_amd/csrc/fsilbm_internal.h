@@ -105,6 +105,16 @@ struct Inst {
     long long *step;          // completed steps
     unsigned *err;            // sticky error word
     double *scratch;          // init / dump staging (aliases the idle ping-pong side)
+    // unstructured 9-node meshes (topology FSI_TOPO_Q9); ni = nodes, nj = 1
+    int n_elems;
+    int pad2;
+    const int *elems;         // [n_elems][9] node indices
+    const float2 *erel;       // [n_elems][9] node positions relative to the element's centre node
+    const int *patch_off;     // [n_nodes + 1] CSR offsets of each node's elements
+    const int *patch_ent;     // [9 n_elems] element * 16 + the node's local index in it
+    float4 *uq;               // [n_nodes] (delta Q_x, delta Q_y, mu / p, 0)
+    float2 *ud;               // [n_nodes] D_a = (mu / p) d_a delta Q_a
+    void *upost;              // [18][n_nodes] post-collision populations (storage format)
 };
 
 }  // namespace fsi
@@ -120,6 +130,7 @@ hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, 
 hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_work, int storage,
                                   int phase, hipStream_t s);
 hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
+hipError_t launch_unstructured(const Inst *inst, long long n_nodes, int storage, hipStream_t s);
 hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,
                                    int storage, hipStream_t s);
 hipError_t launch_dump_macro(const Inst *inst, int side, double *out, long long n_nodes, int storage,

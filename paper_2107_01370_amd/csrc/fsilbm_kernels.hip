@@ -1627,6 +1627,210 @@ __global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const
 }
 
 // ---------------------------------------------------------------------------
+// Unstructured meshes of 9-node quadrilateral elements (Sec. II.B on the
+// paper's own finite-element meshes), static and periodic.  Node-wise
+// kernels, data reached through the element connectivity:
+//   k_u_moments  delta Q_a and mu/p at every node
+//   k_u_grad     D_a = (mu/p) d_a delta Q_a at every node
+//   k_u_collide  F_a = d_a D_a, collision, post-collision populations
+//   k_u_stream   departure point located among the node's elements with the
+//                corner (first-order) map, 9-node interpolation
+// A nodal derivative is the mean over the node's elements of the element
+// derivative J^{-T} sum_s C_s grad_xi N_s at the node's own local position,
+// where only the three nodes on each of the node's element lines contribute
+// (the shape functions are Kronecker at the nodes).  Element coordinates are
+// FP32 offsets from each element's centre node (formed in FP64 on the host).
+// ---------------------------------------------------------------------------
+constexpr int U_THREADS = 256;
+
+// element node at local position (p, q), p, q in {-1, 0, 1}
+__device__ __forceinline__ int q9_node(int p, int q) {
+    // rows q = -1, 0, 1; columns p = -1, 0, 1
+    const int t[3][3] = {{0, 4, 1}, {7, 8, 5}, {3, 6, 2}};
+    return t[q + 1][p + 1];
+}
+__device__ __forceinline__ int q9_p(int a) { return a == 0 || a == 3 || a == 7 ? -1 : (a == 1 || a == 2 || a == 5 ? 1 : 0); }
+__device__ __forceinline__ int q9_q(int a) { return a == 0 || a == 1 || a == 4 ? -1 : (a == 2 || a == 3 || a == 6 ? 1 : 0); }
+
+// derivative at x in {-1, 0, 1} of the quadratic Lagrange basis of node p
+__device__ __forceinline__ float dlag_at(int p, int x) {
+    if (p < 0) return (float)x - 0.5f;
+    if (p == 0) return -2.0f * (float)x;
+    return (float)x + 0.5f;
+}
+
+// element derivative (dC/dx, dC/dy) of the nodal field picked by `val` at
+// local node a of element e
+template <class V>
+__device__ __forceinline__ float2 elem_grad(const Inst &P, int e, int a, V val) {
+    const int pa = q9_p(a), qa = q9_q(a);
+    const int *nodes = P.elems + 9 * (long long)e;
+    const float2 *rel = P.erel + 9 * (long long)e;
+    float cxi = 0.0f, ceta = 0.0f, xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
+#pragma unroll
+    for (int m = -1; m <= 1; ++m) {
+        const int si = q9_node(m, qa), sj = q9_node(pa, m);
+        const float wi = dlag_at(m, pa), wj = dlag_at(m, qa);
+        const float2 ri = rel[si], rj = rel[sj];
+        cxi += wi * val(nodes[si]);
+        xxi += wi * ri.x;
+        yxi += wi * ri.y;
+        ceta += wj * val(nodes[sj]);
+        xeta += wj * rj.x;
+        yeta += wj * rj.y;
+    }
+    const float idet = 1.0f / (xxi * yeta - yxi * xeta);
+    return make_float2(idet * (yeta * cxi - yxi * ceta), idet * (-xeta * cxi + xxi * ceta));
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_THREADS) k_u_moments(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    const void *src = P.pop[n & 1];
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, idx);
+            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+        }
+        const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+        const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+        const float ir = 1.0f / rho;
+        const float ux = jx * ir, uy = jy * ir;
+        const float T = (0.5f * G * ir - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
+        const float one3T = 1.0f - 3.0f * T;
+        P.uq[idx] = make_float4(jx * (one3T - ux * ux), jy * (one3T - uy * uy), P.mu / (rho * T), 0.0f);
+    }
+}
+
+__global__ void __launch_bounds__(U_THREADS) k_u_grad(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const float4 *uq = P.uq;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+        float gx = 0.0f, gy = 0.0f;
+        for (int k = b; k < e_end; ++k) {
+            const int ent = P.patch_ent[k];
+            gx += elem_grad(P, ent >> 4, ent & 15, [&](int v) { return uq[v].x; }).x;
+            gy += elem_grad(P, ent >> 4, ent & 15, [&](int v) { return uq[v].y; }).y;
+        }
+        const float inv = 1.0f / (float)(e_end - b), S = uq[idx].z;
+        P.ud[idx] = make_float2(S * gx * inv, S * gy * inv);
+    }
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_THREADS) k_u_collide(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    const void *src = P.pop[n & 1];
+    void *dst = P.pop[(n + 1) & 1];
+    const float2 *ud = P.ud;
+    unsigned err = 0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+        float Fx = 0.0f, Fy = 0.0f;
+        for (int k = b; k < e_end; ++k) {
+            const int ent = P.patch_ent[k];
+            Fx += elem_grad(P, ent >> 4, ent & 15, [&](int v) { return ud[v].x; }).x;
+            Fy += elem_grad(P, ent >> 4, ent & 15, [&](int v) { return ud[v].y; }).y;
+        }
+        const float inv = 1.0f / (float)(e_end - b);
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, idx);
+            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+        }
+        collide(f, g, Fx * inv, Fy * inv, P, err);
+        // rest populations do not move
+        pop_store<STORE>(P, dst, 0, idx, f[0]);
+        pop_store<STORE>(P, dst, Q, idx, g[0]);
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {
+            pop_store<STORE>(P, P.upost, k, idx, f[k]);
+            pop_store<STORE>(P, P.upost, Q + k, idx, g[k]);
+        }
+    }
+    if (err) atomicOr(P.err, err);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    void *dst = P.pop[(n + 1) & 1];
+    const float dt = P.dt;
+    unsigned err = 0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+#pragma unroll 1
+        for (int k = 1; k < 9; ++k) {
+            const float dx = -dt * (float)CXK(k), dy = -dt * (float)CYK(k);
+            int e_found = -1;
+            float xi = 0.0f, eta = 0.0f;
+            for (int q = b; q < e_end && e_found < 0; ++q) {
+                const int ent = P.patch_ent[q], e = ent >> 4, a = ent & 15;
+                const float2 *rel = P.erel + 9 * (long long)e;
+                const float2 c0 = rel[0], c1 = rel[1], c2 = rel[2], c3 = rel[3], ra = rel[a];
+                const float px = ra.x + dx, py = ra.y + dy;
+                // Newton on the bilinear corner map from the node's own position
+                float u = (float)q9_p(a), v = (float)q9_q(a);
+#pragma unroll
+                for (int it = 0; it < 6; ++it) {
+                    const float n0 = (1 - u) * (1 - v), n1 = (1 + u) * (1 - v);
+                    const float n2 = (1 + u) * (1 + v), n3 = (1 - u) * (1 + v);
+                    const float rx = 0.25f * (n0 * c0.x + n1 * c1.x + n2 * c2.x + n3 * c3.x) - px;
+                    const float ry = 0.25f * (n0 * c0.y + n1 * c1.y + n2 * c2.y + n3 * c3.y) - py;
+                    const float ja = 0.25f * (-(1 - v) * c0.x + (1 - v) * c1.x + (1 + v) * c2.x - (1 + v) * c3.x);
+                    const float jb = 0.25f * (-(1 - u) * c0.x - (1 + u) * c1.x + (1 + u) * c2.x + (1 - u) * c3.x);
+                    const float jc = 0.25f * (-(1 - v) * c0.y + (1 - v) * c1.y + (1 + v) * c2.y - (1 + v) * c3.y);
+                    const float jd = 0.25f * (-(1 - u) * c0.y - (1 + u) * c1.y + (1 + u) * c2.y + (1 - u) * c3.y);
+                    const float id = 1.0f / (ja * jd - jb * jc);
+                    u -= id * (jd * rx - jb * ry);
+                    v -= id * (-jc * rx + ja * ry);
+                }
+                if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
+                    e_found = e;
+                    xi = u;
+                    eta = v;
+                }
+            }
+            if (e_found < 0) {
+                err |= ERR_CFL;
+                continue;
+            }
+            // 9-node interpolation of the post-collision populations
+            const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
+            const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
+            const int *nodes = P.elems + 9 * (long long)e_found;
+            float vf = 0.0f, vg = 0.0f;
+#pragma unroll
+            for (int qq = -1; qq <= 1; ++qq)
+#pragma unroll
+                for (int pp = -1; pp <= 1; ++pp) {
+                    const int s = q9_node(pp, qq);
+                    const float w = lx[pp + 1] * ly[qq + 1];
+                    const int node = nodes[s];
+                    vf += w * pop_load<STORE>(P, P.upost, k, node);
+                    vg += w * pop_load<STORE>(P, P.upost, Q + k, node);
+                }
+            pop_store<STORE>(P, dst, k, idx, vf);
+            pop_store<STORE>(P, dst, Q + k, idx, vg);
+        }
+    }
+    if (err) atomicOr(P.err, err);
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 #define FSI_DISPATCH(storage, KERNEL, GRID, BLOCK, STREAM, ...)                              \
@@ -1693,6 +1897,16 @@ hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s) 
 static int io_grid(long long n) {
     long long g = (n + 255) / 256;
     return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+hipError_t launch_unstructured(const Inst *inst, long long n_nodes, int storage, hipStream_t s) {
+    const long long g64 = (n_nodes + U_THREADS - 1) / U_THREADS;
+    const dim3 grid((unsigned)(g64 > 0 ? g64 : 1)), block(U_THREADS);
+    FSI_DISPATCH(storage, k_u_moments, grid, block, s, inst);
+    hipLaunchKernelGGL(k_u_grad, grid, block, 0, s, inst);
+    FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
+    FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,

@@ -50,7 +50,9 @@ class MeshDesc(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("topo", ctypes.c_int),
                 ("X", ctypes.POINTER(ctypes.c_double)), ("shift_i", ctypes.c_double * 2),
                 ("shift_j", ctypes.c_double * 2), ("n_wake", ctypes.c_int),
-                ("n_wall2", ctypes.c_int)]
+                ("n_wall2", ctypes.c_int), ("n_elems", ctypes.c_int),
+                ("elems", ctypes.POINTER(ctypes.c_int32)),
+                ("elem_shifts", ctypes.POINTER(ctypes.c_int8))]
 
 
 class BodyDesc(ctypes.Structure):
@@ -161,12 +163,20 @@ def _fluid_struct(fluid):
 
 
 def _mesh_struct(mesh):
-    """Returns (MeshDesc, coordinate array that must outlive the call)."""
+    """Returns (MeshDesc, arrays that must outlive the call)."""
     X = np.ascontiguousarray(mesh.interleaved(), dtype=np.float64)
     md = MeshDesc(mesh.ni, mesh.nj, mesh.topo, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                   (ctypes.c_double * 2)(*mesh.shift_i), (ctypes.c_double * 2)(*mesh.shift_j),
                   int(getattr(mesh, "n_wake", 0)), int(getattr(mesh, "n_wall2", 0)))
-    return md, X
+    keep = (X,)
+    if getattr(mesh, "elems", None) is not None:
+        el = np.ascontiguousarray(mesh.elems, dtype=np.int32)
+        sh = np.ascontiguousarray(mesh.shifts, dtype=np.int8)
+        md.n_elems = el.shape[0]
+        md.elems = el.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        md.elem_shifts = sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        keep = (X, el, sh)
+    return md, keep
 
 
 def _body_struct(b):

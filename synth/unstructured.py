@@ -48,6 +48,26 @@ class UnstructuredMesh:
     def n_elems(self) -> int:
         return int(self.elems.shape[0])
 
+    # the library's mesh description: topology 4, ni = nodes, nj = 1, the
+    # periods as the seam shifts
+    topo = 4
+    nj = 1
+
+    @property
+    def ni(self) -> int:
+        return self.n_nodes
+
+    @property
+    def shift_i(self):
+        return (float(self.period[0]), 0.0)
+
+    @property
+    def shift_j(self):
+        return (0.0, float(self.period[1]))
+
+    def interleaved(self) -> np.ndarray:
+        return np.stack([self.X, self.Y], axis=-1)[None]
+
 
 def _morton(ix, iy, bits=16):
     out = np.zeros_like(ix, dtype=np.int64)

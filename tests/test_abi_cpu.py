@@ -339,3 +339,32 @@ def test_coupling_arguments_are_checked(F):
             assert e.value.status == -1
     finally:
         F.fsi_destroy(ctx)
+
+
+# ---- unstructured 9-node meshes ----------------------------------------------
+
+def test_q9_mesh_is_accepted_and_validated(F):
+    from dataclasses import replace as R
+
+    from synth.unstructured import unstructured_pulse_case
+    mesh, fl, _ = unstructured_pulse_case(6)
+    ctx = F.fsi_create(fl, mesh, [], None)
+    F.fsi_destroy(ctx)
+    bad_node = mesh.elems.copy()
+    bad_node[3, 2] = mesh.n_nodes
+    X = mesh.X.copy()
+    X[mesh.elems[5, 4]] += 0.3                     # an edge node off its edge
+    flipped = mesh.elems.copy()
+    flipped[7, [1, 3]] = flipped[7, [3, 1]]        # clockwise corners
+    for bad, what in ((R(mesh, elems=bad_node), "range"), (R(mesh, X=X), "edge node"),
+                      (R(mesh, elems=flipped), "")):
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_create(fl, bad, [], None)
+        assert e.value.status == -2 and what in str(e.value)
+    body = synth.BodyParams(dof=0, center=(10.0, 10.0), r_rigid=1.0, r_blend=3.0)
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(fl, mesh, [body], None)
+    assert e.value.status == -1
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_batch_create([(fl, mesh, [])])
+    assert e.value.status == -1

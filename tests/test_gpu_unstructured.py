@@ -1,0 +1,91 @@
+"""GPU parity on unstructured periodic meshes of 9-node quadrilateral elements
+(element connectivity, nodal finite-element gradients, point location among
+a node's elements, 9-node interpolation) against the FP64 oracle, through the
+C ABI."""
+
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle.unstructured import UnstructuredSolver
+from synth.unstructured import unstructured_pulse_case
+
+pytestmark = pytest.mark.gpu
+
+
+def paired(mesh, fl, fields):
+    from paper_2107_01370_amd.fsilbm import Simulation
+    sim = Simulation(mesh, fl, [])
+    rho, ux, uy, T = fields
+    sim.init_equilibrium(rho[None], ux[None], uy[None], T[None])
+    f0, g0 = sim.populations()
+    ora = UnstructuredSolver(mesh, fl, rho, ux, uy, T)
+    ora.f = f0[:, 0, :].astype(np.float64)
+    ora.g = g0[:, 0, :].astype(np.float64)
+    return sim, ora
+
+
+def check_step(f, g, ora, bound=1e-6):
+    for a, b in ((f[:, 0, :], ora.f), (g[:, 0, :], ora.g)):
+        err = np.abs(a - b)
+        assert np.max(err) <= bound * np.max(np.abs(b)), (np.unravel_index(np.argmax(err), err.shape), np.max(err))
+
+
+def test_unstructured_one_step_parity():
+    mesh, fl, fields = unstructured_pulse_case(8)
+    sim, ora = paired(mesh, fl, fields)
+    sim.step(1)
+    ora.step()
+    f, g = sim.populations()
+    check_step(f, g, ora)
+
+
+def test_unstructured_100_steps_rho_p():
+    mesh, fl, fields = unstructured_pulse_case(12, seed=5)
+    sim, ora = paired(mesh, fl, fields)
+    sim.step(100)
+    ora.run(100)
+    rho, ux, uy, T = sim.macro()
+    r_o, ux_o, uy_o, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(rho[0] - r_o) / r_o) <= 1e-5
+    assert np.max(np.abs(rho[0] * T[0] - r_o * T_o) / (r_o * T_o)) <= 1e-5
+    # the pulse moved and spread: a non-trivial state
+    assert np.max(r_o) - np.min(r_o) > 1e-5
+
+
+def test_unstructured_uniform_stream_preserved():
+    mesh, fl, _ = unstructured_pulse_case(8)
+    from paper_2107_01370_amd.fsilbm import Simulation
+    sim = Simulation(mesh, fl, [])
+    sim.init_equilibrium()
+    f0, g0 = sim.populations()
+    sim.step(100)
+    f, g = sim.populations()
+    assert np.max(np.abs(f - f0)) <= 1e-6 and np.max(np.abs(g - g0)) <= 1e-6
+
+
+def test_unstructured_fp16_storage_within_2e3():
+    mesh, fl, fields = unstructured_pulse_case(8)
+    from paper_2107_01370_amd.fsilbm import Simulation
+    sim = Simulation(mesh, replace(fl, storage=1), [])
+    rho, ux, uy, T = fields
+    sim.init_equilibrium(rho[None], ux[None], uy[None], T[None])
+    ora = UnstructuredSolver(mesh, fl, rho, ux, uy, T)
+    sim.step(40)
+    ora.run(40)
+    r, _, _, Tg = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(r[0] - r_o) / r_o) <= 2e-3
+    assert np.max(np.abs(r[0] * Tg[0] - r_o * T_o) / (r_o * T_o)) <= 2e-3
+
+
+def test_unstructured_full_size_step():
+    """The 1,572,864-node mesh of the unstructured workload (m = 256,
+    393,216 elements), launched as the benchmark launches it: one step."""
+    mesh, fl, fields = unstructured_pulse_case(256)
+    sim, ora = paired(mesh, fl, fields)
+    sim.step(1)
+    ora.step()
+    f, g = sim.populations()
+    check_step(f, g, ora)

@@ -96,7 +96,7 @@ def test_point_location_in_the_patch(mesh, grid):
         assert np.all(np.abs(xi) <= 1 + 1e-12) and np.all(np.abs(eta) <= 1 + 1e-12)
         # the bilinear map of the element takes (xi, eta) to the point
         n = np.arange(grid.N)
-        a = np.array([grid.patch[i][[p[0] for p in grid.patch[i]].index(e[i])][1] for i in n])
+        a = grid.pa[n, np.argmax((grid.pe == e[:, None]) & grid.pm, axis=1)]
         px = grid.ex[e, a] + dx
         py = grid.ey[e, a] + dy
         cx, cy = grid.ex[e, :4], grid.ey[e, :4]
