@@ -1666,18 +1666,22 @@ __device__ __forceinline__ float2 elem_grad(const Inst &P, int e, int a, V val) 
     const int pa = q9_p(a), qa = q9_q(a);
     const int *nodes = P.elems + 9 * (long long)e;
     const float2 *rel = P.erel + 9 * (long long)e;
+    // differences from the node's own value (the weights of each line sum to
+    // zero), so that a constant field has a zero derivative exactly
+    const float ca = val(nodes[a]);
+    const float2 ra = rel[a];
     float cxi = 0.0f, ceta = 0.0f, xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
 #pragma unroll
     for (int m = -1; m <= 1; ++m) {
         const int si = q9_node(m, qa), sj = q9_node(pa, m);
         const float wi = dlag_at(m, pa), wj = dlag_at(m, qa);
         const float2 ri = rel[si], rj = rel[sj];
-        cxi += wi * val(nodes[si]);
-        xxi += wi * ri.x;
-        yxi += wi * ri.y;
-        ceta += wj * val(nodes[sj]);
-        xeta += wj * rj.x;
-        yeta += wj * rj.y;
+        cxi += wi * (val(nodes[si]) - ca);
+        xxi += wi * (ri.x - ra.x);
+        yxi += wi * (ri.y - ra.y);
+        ceta += wj * (val(nodes[sj]) - ca);
+        xeta += wj * (rj.x - ra.x);
+        yeta += wj * (rj.y - ra.y);
     }
     const float idet = 1.0f / (xxi * yeta - yxi * xeta);
     return make_float2(idet * (yeta * cxi - yxi * ceta), idet * (-xeta * cxi + xxi * ceta));
@@ -1808,11 +1812,14 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
                 err |= ERR_CFL;
                 continue;
             }
-            // 9-node interpolation of the post-collision populations
+            // 9-node interpolation of the post-collision populations, as the
+            // node's own value plus weighted differences (the weights sum to
+            // one), so that constants are reproduced exactly
             const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
             const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
             const int *nodes = P.elems + 9 * (long long)e_found;
-            float vf = 0.0f, vg = 0.0f;
+            const float f0 = pop_load<STORE>(P, P.upost, k, idx), g0 = pop_load<STORE>(P, P.upost, Q + k, idx);
+            float vf = f0, vg = g0;
 #pragma unroll
             for (int qq = -1; qq <= 1; ++qq)
 #pragma unroll
@@ -1820,8 +1827,8 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
                     const int s = q9_node(pp, qq);
                     const float w = lx[pp + 1] * ly[qq + 1];
                     const int node = nodes[s];
-                    vf += w * pop_load<STORE>(P, P.upost, k, node);
-                    vg += w * pop_load<STORE>(P, P.upost, Q + k, node);
+                    vf += w * (pop_load<STORE>(P, P.upost, k, node) - f0);
+                    vg += w * (pop_load<STORE>(P, P.upost, Q + k, node) - g0);
                 }
             pop_store<STORE>(P, dst, k, idx, vf);
             pop_store<STORE>(P, dst, Q + k, idx, vg);
