@@ -38,7 +38,7 @@ struct fsi_ctx {
            off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
            off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0, off_dist = 0,
            off_resid = 0, off_elems = 0, off_erel = 0, off_poff = 0, off_pent = 0, off_uq = 0,
-           off_ud = 0, off_upost = 0, total = 0;
+           off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0, total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
     std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
@@ -599,9 +599,13 @@ void layout(fsi_ctx *c) {
         c->off_erel = take(c->erel.size() * sizeof(float2));
         c->off_poff = take(c->patch_off.size() * 4);
         c->off_pent = take(c->patch_ent.size() * 4);
-        c->off_uq = take(N * sizeof(float4));
+        c->off_uq = take(N * sizeof(float2));
+        c->off_us = take(N * sizeof(float));
         c->off_ud = take(N * sizeof(float2));
-        c->off_upost = take(fsi::NPOP * N * bpp);
+        c->off_ueg = take(9 * (size_t)c->n_elems * sizeof(float2));
+        c->off_upost = take(16 * N * sizeof(float));
+        c->off_dep_e = take(8 * N * 4);
+        c->off_dep_xy = take(8 * N * sizeof(float2));
     }
     c->total = o;
 }
@@ -621,7 +625,8 @@ const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c
 fsi_status enqueue_fluid(fsi_ctx *c) {
     const int st = c->fluid.storage;
     if (c->topo == FSI_TOPO_Q9) {
-        HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, st, c->stream));
+        HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, st,
+                                            c->inst.uq, c->inst.ud, c->inst.ueg, c->stream));
         return FSI_OK;
     }
     if (!c->wk0.empty())
@@ -781,9 +786,13 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.erel = reinterpret_cast<const float2 *>(c->ws + c->off_erel);
         P.patch_off = reinterpret_cast<const int *>(c->ws + c->off_poff);
         P.patch_ent = reinterpret_cast<const int *>(c->ws + c->off_pent);
-        P.uq = reinterpret_cast<float4 *>(c->ws + c->off_uq);
+        P.uq = reinterpret_cast<float2 *>(c->ws + c->off_uq);
+        P.us = reinterpret_cast<float *>(c->ws + c->off_us);
         P.ud = reinterpret_cast<float2 *>(c->ws + c->off_ud);
+        P.ueg = reinterpret_cast<float2 *>(c->ws + c->off_ueg);
         P.upost = c->ws + c->off_upost;
+        P.dep_e = reinterpret_cast<int *>(c->ws + c->off_dep_e);
+        P.dep_xy = reinterpret_cast<float2 *>(c->ws + c->off_dep_xy);
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_elems, c->elems.data(), c->elems.size() * 4,
                                   hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_erel, c->erel.data(), c->erel.size() * sizeof(float2),
@@ -824,7 +833,17 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk1, c->wk1.data(), c->wk1.size() * sizeof(int2),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+    // static unstructured mesh: the departure points once
+    if (c->topo == FSI_TOPO_Q9)
+        HIP_TRY(c, fsi::launch_unstructured_locate(d_inst(c), (long long)c->ni, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->topo == FSI_TOPO_Q9) {
+        unsigned e = 0;
+        HIP_TRY(c, hipMemcpy(&e, c->ws + c->off_err, 4, hipMemcpyDeviceToHost));
+        if (e & fsi::ERR_CFL)
+            return fail(c, FSI_E_CFL, "a departure point lies outside the elements of its node "
+                                      "(dt too large for this mesh)");
+    }
     return FSI_OK;
 }
 
@@ -1101,7 +1120,8 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                 HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                                   (int)c->wk0.size(), stg, c->stream));
             if (which == 0 && c->topo == FSI_TOPO_Q9)
-                e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, stg, c->stream);
+                e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, stg,
+                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
                                                c->cut, 0);

@@ -112,9 +112,13 @@ struct Inst {
     const float2 *erel;       // [n_elems][9] node positions relative to the element's centre node
     const int *patch_off;     // [n_nodes + 1] CSR offsets of each node's elements
     const int *patch_ent;     // [9 n_elems] element * 16 + the node's local index in it
-    float4 *uq;               // [n_nodes] (delta Q_x, delta Q_y, mu / p, 0)
+    float2 *uq;               // [n_nodes] (delta Q_x, delta Q_y)
+    float *us;                // [n_nodes] mu / p
     float2 *ud;               // [n_nodes] D_a = (mu / p) d_a delta Q_a
-    void *upost;              // [18][n_nodes] post-collision populations (storage format)
+    float2 *ueg;              // [n_elems][9] element derivatives at the element's nodes
+    void *upost;              // [n_nodes][8][2] post-collision moving populations (f_k, g_k), FP32
+    int *dep_e;               // [8][n_nodes] element holding each departure point
+    float2 *dep_xy;           // [8][n_nodes] its local coordinates there
 };
 
 }  // namespace fsi
@@ -130,7 +134,9 @@ hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, 
 hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_work, int storage,
                                   int phase, hipStream_t s);
 hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
-hipError_t launch_unstructured(const Inst *inst, long long n_nodes, int storage, hipStream_t s);
+hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
+                               float2 *uq, float2 *ud, float2 *ueg, hipStream_t s);
+hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s);
 hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,
                                    int storage, hipStream_t s);
 hipError_t launch_dump_macro(const Inst *inst, int side, double *out, long long n_nodes, int storage,
