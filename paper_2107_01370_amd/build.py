@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfsilbm.so")
-SOURCES = ["fsilbm_kernels.hip", "fsilbm_host.hip"]
+SOURCES = ["fsilbm_kernels.hip", "fsilbm_unstructured.hip", "fsilbm_host.hip"]
 ARCH = os.environ.get("FSILBM_ARCH", "gfx950")
 
 

@@ -1,0 +1,288 @@
+// gfx950 kernels of the step on unstructured meshes of 9-node quadrilateral
+// elements (Bhadauria, Dorschner & Karlin, arXiv 2107.01370, Sec. II.B on the
+// paper's own second-order finite-element meshes).
+#include "fsilbm_device.h"
+
+namespace fsi {
+
+// ---------------------------------------------------------------------------
+// Unstructured meshes of 9-node quadrilateral elements (Sec. II.B on the
+// paper's own finite-element meshes), static and periodic.  Node-wise
+// kernels, data reached through the element connectivity:
+//   k_u_moments  delta Q_a and mu/p at every node
+//   k_u_egrad    element derivatives at the element's nine nodes
+//   k_u_nodeD    D_a = (mu/p) d_a delta Q_a at every node (nodal means)
+//   k_u_egrad    again, of D
+//   k_u_collide  F_a = d_a D_a (nodal means), collision, post-collision
+//                populations (the moving ones in FP32 node by node for the
+//                gathers)
+//   k_u_stream   9-node interpolation at the departure points, which
+//                k_u_locate finds once (static mesh) among the node's
+//                elements with the corner (first-order) map
+// A nodal derivative is the mean over the node's elements of the element
+// derivative J^{-T} sum_s C_s grad_xi N_s at the node's own local position,
+// where only the three nodes on each of the node's element lines contribute
+// (the shape functions are Kronecker at the nodes); the element derivatives
+// are formed element by element and summed node by node in a fixed order.  Element coordinates are
+// FP32 offsets from each element's centre node (formed in FP64 on the host).
+// ---------------------------------------------------------------------------
+constexpr int U_THREADS = 256;
+
+// element node at local position (p, q), p, q in {-1, 0, 1}
+__device__ __forceinline__ int q9_node(int p, int q) {
+    // rows q = -1, 0, 1; columns p = -1, 0, 1
+    const int t[3][3] = {{0, 4, 1}, {7, 8, 5}, {3, 6, 2}};
+    return t[q + 1][p + 1];
+}
+__device__ __forceinline__ int q9_p(int a) { return a == 0 || a == 3 || a == 7 ? -1 : (a == 1 || a == 2 || a == 5 ? 1 : 0); }
+__device__ __forceinline__ int q9_q(int a) { return a == 0 || a == 1 || a == 4 ? -1 : (a == 2 || a == 3 || a == 6 ? 1 : 0); }
+
+// derivative at x in {-1, 0, 1} of the quadratic Lagrange basis of node p
+__device__ __forceinline__ float dlag_at(int p, int x) {
+    if (p < 0) return (float)x - 0.5f;
+    if (p == 0) return -2.0f * (float)x;
+    return (float)x + 0.5f;
+}
+
+// Element pass of a nodal derivative: one thread per element evaluates, at
+// each of its nine nodes, d/dx of the first and d/dy of the second component
+// of the float2 nodal field `v` (the correction needs only these) and writes
+// them to eg[9 e + a].  Differences from the node's own value (the weights of
+// each line sum to zero) make the derivative of a constant field exactly zero.
+__global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ pinst,
+                                                       const float2 *__restrict__ v,
+                                                       float2 *__restrict__ eg) {
+    const Inst &P = *pinst;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < P.n_elems;
+         e += (long long)gridDim.x * blockDim.x) {
+        float2 val[9], rel[9];
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            val[s] = v[P.elems[9 * e + s]];
+            rel[s] = P.erel[9 * e + s];
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int pa = q9_p(a), qa = q9_q(a);
+            float axi = 0.0f, aeta = 0.0f, bxi = 0.0f, beta = 0.0f;
+            float xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
+#pragma unroll
+            for (int m = -1; m <= 1; ++m) {
+                if (m != pa) {
+                    const int si = q9_node(m, qa);
+                    const float w = dlag_at(m, pa);
+                    axi += w * (val[si].x - val[a].x);
+                    bxi += w * (val[si].y - val[a].y);
+                    xxi += w * (rel[si].x - rel[a].x);
+                    yxi += w * (rel[si].y - rel[a].y);
+                }
+                if (m != qa) {
+                    const int sj = q9_node(pa, m);
+                    const float w = dlag_at(m, qa);
+                    aeta += w * (val[sj].x - val[a].x);
+                    beta += w * (val[sj].y - val[a].y);
+                    xeta += w * (rel[sj].x - rel[a].x);
+                    yeta += w * (rel[sj].y - rel[a].y);
+                }
+            }
+            const float idet = 1.0f / (xxi * yeta - yxi * xeta);
+            eg[9 * e + a] = make_float2(idet * (yeta * axi - yxi * aeta), idet * (-xeta * bxi + xxi * beta));
+        }
+    }
+}
+
+// nodal mean of the element derivatives of node idx
+__device__ __forceinline__ float2 node_mean(const Inst &P, const float2 *__restrict__ eg, long long idx) {
+    const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+    float gx = 0.0f, gy = 0.0f;
+    for (int k = b; k < e_end; ++k) {
+        const int ent = P.patch_ent[k];
+        const float2 d = eg[9 * (long long)(ent >> 4) + (ent & 15)];
+        gx += d.x;
+        gy += d.y;
+    }
+    const float inv = 1.0f / (float)(e_end - b);
+    return make_float2(gx * inv, gy * inv);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_THREADS) k_u_moments(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    const void *src = P.pop[n & 1];
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, idx);
+            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+        }
+        const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+        const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+        const float ir = 1.0f / rho;
+        const float ux = jx * ir, uy = jy * ir;
+        const float T = (0.5f * G * ir - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
+        const float one3T = 1.0f - 3.0f * T;
+        P.uq[idx] = make_float2(jx * (one3T - ux * ux), jy * (one3T - uy * uy));
+        P.us[idx] = P.mu / (rho * T);
+    }
+}
+
+// D_a = (mu / p) d_a delta Q_a at every node
+__global__ void __launch_bounds__(U_THREADS) k_u_nodeD(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const float2 g = node_mean(P, P.ueg, idx);
+        const float S = P.us[idx];
+        P.ud[idx] = make_float2(S * g.x, S * g.y);
+    }
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_THREADS) k_u_collide(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    const void *src = P.pop[n & 1];
+    void *dst = P.pop[(n + 1) & 1];
+    unsigned err = 0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const float2 F = node_mean(P, P.ueg, idx);
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, idx);
+            g[k] = pop_load<STORE>(P, src, Q + k, idx);
+        }
+        collide(f, g, F.x, F.y, P, err);
+        // rest populations do not move
+        pop_store<STORE>(P, dst, 0, idx, f[0]);
+        pop_store<STORE>(P, dst, Q, idx, g[0]);
+        // the 16 moving ones node by node (f_k and g_k of a node side by side,
+        // one 64-byte line per node), FP32: the interpolation gathers them
+        float4 *up = reinterpret_cast<float4 *>(P.upost) + 4 * idx;
+        up[0] = make_float4(f[1], g[1], f[2], g[2]);
+        up[1] = make_float4(f[3], g[3], f[4], g[4]);
+        up[2] = make_float4(f[5], g[5], f[6], g[6]);
+        up[3] = make_float4(f[7], g[7], f[8], g[8]);
+    }
+    if (err) atomicOr(P.err, err);
+}
+
+// Departure points of a static mesh: for every node and moving direction the
+// element of the node's patch whose corner (first-order) map holds
+// X - dt c_k, and the local coordinates there (Newton from the node's own
+// position, FP32 offsets from the element's centre node).  Run once when the
+// workspace is bound; ERR_CFL if a point lies outside every element of the
+// patch.
+__global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const float dt = P.dt;
+    unsigned err = 0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+        for (int k = 1; k < 9; ++k) {
+            const float dx = -dt * (float)CXK(k), dy = -dt * (float)CYK(k);
+            int e_found = -1;
+            float xi = 0.0f, eta = 0.0f;
+            for (int q = b; q < e_end && e_found < 0; ++q) {
+                const int ent = P.patch_ent[q], e = ent >> 4, a = ent & 15;
+                const float2 *rel = P.erel + 9 * (long long)e;
+                const float2 c0 = rel[0], c1 = rel[1], c2 = rel[2], c3 = rel[3], ra = rel[a];
+                const float px = ra.x + dx, py = ra.y + dy;
+                float u = (float)q9_p(a), v = (float)q9_q(a);
+                for (int it = 0; it < 8; ++it) {
+                    const float n0 = (1 - u) * (1 - v), n1 = (1 + u) * (1 - v);
+                    const float n2 = (1 + u) * (1 + v), n3 = (1 - u) * (1 + v);
+                    const float rx = 0.25f * (n0 * c0.x + n1 * c1.x + n2 * c2.x + n3 * c3.x) - px;
+                    const float ry = 0.25f * (n0 * c0.y + n1 * c1.y + n2 * c2.y + n3 * c3.y) - py;
+                    const float ja = 0.25f * (-(1 - v) * c0.x + (1 - v) * c1.x + (1 + v) * c2.x - (1 + v) * c3.x);
+                    const float jb = 0.25f * (-(1 - u) * c0.x - (1 + u) * c1.x + (1 + u) * c2.x + (1 - u) * c3.x);
+                    const float jc = 0.25f * (-(1 - v) * c0.y + (1 - v) * c1.y + (1 + v) * c2.y - (1 + v) * c3.y);
+                    const float jd = 0.25f * (-(1 - u) * c0.y - (1 + u) * c1.y + (1 + u) * c2.y + (1 - u) * c3.y);
+                    const float id = 1.0f / (ja * jd - jb * jc);
+                    u -= id * (jd * rx - jb * ry);
+                    v -= id * (-jc * rx + ja * ry);
+                }
+                if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
+                    e_found = e;
+                    xi = u;
+                    eta = v;
+                }
+            }
+            if (e_found < 0) {
+                err |= ERR_CFL;
+                e_found = P.patch_ent[b] >> 4;
+            }
+            P.dep_e[(k - 1) * P.n_nodes + idx] = e_found;
+            P.dep_xy[(k - 1) * P.n_nodes + idx] = make_float2(xi, eta);
+        }
+    }
+    if (err) atomicOr(P.err, err);
+}
+
+// 9-node interpolation of the post-collision populations at the tabulated
+// departure points, as the node's own value plus weighted differences (the
+// weights sum to one), so that constants are reproduced exactly
+template <int STORE>
+__global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    void *dst = P.pop[(n + 1) & 1];
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+#pragma unroll 2
+        for (int k = 1; k < 9; ++k) {
+            const int e = P.dep_e[(k - 1) * P.n_nodes + idx];
+            const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
+            const float xi = d.x, eta = d.y;
+            const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
+            const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
+            const int *nodes = P.elems + 9 * (long long)e;
+            const float2 *up = reinterpret_cast<const float2 *>(P.upost);
+            const float2 fg0 = up[8 * idx + (k - 1)];
+            float vf = fg0.x, vg = fg0.y;
+#pragma unroll
+            for (int qq = -1; qq <= 1; ++qq)
+#pragma unroll
+                for (int pp = -1; pp <= 1; ++pp) {
+                    const float w = lx[pp + 1] * ly[qq + 1];
+                    const float2 fg = up[8 * (long long)nodes[q9_node(pp, qq)] + (k - 1)];
+                    vf += w * (fg.x - fg0.x);
+                    vg += w * (fg.y - fg0.y);
+                }
+            pop_store<STORE>(P, dst, k, idx, vf);
+            pop_store<STORE>(P, dst, Q + k, idx, vg);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s) {
+    const long long g64 = (n_nodes + U_THREADS - 1) / U_THREADS;
+    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 1)), dim3(U_THREADS), 0, s, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
+                               float2 *uq, float2 *ud, float2 *ueg, hipStream_t s) {
+    const long long g64 = (n_nodes + U_THREADS - 1) / U_THREADS;
+    const long long e64 = (n_elems + U_THREADS - 1) / U_THREADS;
+    const dim3 grid((unsigned)(g64 > 0 ? g64 : 1)), egrid((unsigned)(e64 > 0 ? e64 : 1)), block(U_THREADS);
+    FSI_DISPATCH(storage, k_u_moments, grid, block, s, inst);
+    hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, uq, ueg);
+    hipLaunchKernelGGL(k_u_nodeD, grid, block, 0, s, inst);
+    hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, ud, ueg);
+    FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
+    FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
+    return hipGetLastError();
+}
+
+}  // namespace fsi
