@@ -2,10 +2,12 @@
 // boundary geometry, workspace layout, graph capture of one coupled step, and
 // host <-> device transfers.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/fsilbm.h"
@@ -29,6 +31,10 @@ struct fsi_ctx {
     std::vector<int> elems;         // [E][9]
     std::vector<float2> erel;       // [E][9] offsets from the element's centre node
     std::vector<int> patch_off, patch_ent;
+    // node blocks of the LDS-staged interpolation (empty: device-memory gathers)
+    std::vector<int> bh_off, bh_nodes, be_off, be_elem;
+    std::vector<uint16_t> be_nodes, uself;
+    int u_hmax = 0, u_lemax = 0;
     hipStream_t stream = nullptr;
     int n_sub = 1;                  // coupling sub-iterations per step
     double relax = 1.0;
@@ -38,7 +44,9 @@ struct fsi_ctx {
            off_force = 0, off_slots = 0, off_hist = 0, off_step = 0, off_err = 0, off_inst = 0,
            off_wk1 = 0, off_wbnd = 0, off_wwall = 0, off_ff = 0, off_cut = 0, off_wk0 = 0, off_dist = 0,
            off_resid = 0, off_elems = 0, off_erel = 0, off_poff = 0, off_pent = 0, off_uq = 0,
-           off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0, total = 0;
+           off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0,
+           off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
+           off_uself = 0, off_dep_le = 0, total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
     std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
@@ -220,6 +228,59 @@ fsi_status topology(fsi_ctx *c) {
 
 // unstructured 9-node mesh: connectivity, periodic offsets, node patches and
 // element geometry; every element positively oriented at all nine nodes
+// Blocks of U_BLOCK consecutive nodes for the LDS-staged interpolation: the
+// elements holding a node of the block (every departure element of the
+// block's nodes is one of them), the nodes of those elements (the block's
+// halo), each element's nodes as halo positions and each node's own position.
+// The block path is left off (empty tables) if the largest block's halo and
+// element list do not fit 64 KiB of LDS, or if FSILBM_UNSTRUCTURED_GATHER is
+// set to "device" (every block then gathers from device memory; both paths
+// give identical results).
+void build_q9_blocks(fsi_ctx *c) {
+    c->bh_off.clear(); c->bh_nodes.clear(); c->be_off.clear(); c->be_elem.clear();
+    c->be_nodes.clear(); c->uself.clear();
+    c->u_hmax = c->u_lemax = 0;
+    const char *env = getenv("FSILBM_UNSTRUCTURED_GATHER");
+    if (env && std::string(env) == "device") return;
+    const int N = c->ni, nb = (N + fsi::U_BLOCK - 1) / fsi::U_BLOCK;
+    std::vector<int> bh_off(nb + 1, 0), be_off(nb + 1, 0), bh_nodes, be_elem;
+    std::vector<uint16_t> be_nodes, uself(N, 0);
+    std::vector<int> els, nodes;
+    int hmax = 0, lemax = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int n0 = b * fsi::U_BLOCK, n1 = std::min(N, n0 + fsi::U_BLOCK);
+        els.clear();
+        for (int v = n0; v < n1; ++v)
+            for (int q = c->patch_off[v]; q < c->patch_off[v + 1]; ++q) els.push_back(c->patch_ent[q] >> 4);
+        std::sort(els.begin(), els.end());
+        els.erase(std::unique(els.begin(), els.end()), els.end());
+        nodes.clear();
+        for (int e : els)
+            for (int a = 0; a < 9; ++a) nodes.push_back(c->elems[9 * (size_t)e + a]);
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        if (nodes.size() > 65535) return;
+        auto pos = [&](int v) {
+            return (uint16_t)(std::lower_bound(nodes.begin(), nodes.end(), v) - nodes.begin());
+        };
+        for (int e : els) {
+            be_elem.push_back(e);
+            for (int a = 0; a < 16; ++a) be_nodes.push_back(a < 9 ? pos(c->elems[9 * (size_t)e + a]) : 0);
+        }
+        for (int v = n0; v < n1; ++v) uself[v] = pos(v);
+        bh_nodes.insert(bh_nodes.end(), nodes.begin(), nodes.end());
+        bh_off[b + 1] = (int)bh_nodes.size();
+        be_off[b + 1] = (int)be_elem.size();
+        hmax = std::max(hmax, (int)nodes.size());
+        lemax = std::max(lemax, (int)els.size());
+    }
+    if ((size_t)hmax * 64 + (size_t)lemax * 32 > 65536) return;
+    c->bh_off.swap(bh_off); c->bh_nodes.swap(bh_nodes); c->be_off.swap(be_off);
+    c->be_elem.swap(be_elem); c->be_nodes.swap(be_nodes); c->uself.swap(uself);
+    c->u_hmax = hmax;
+    c->u_lemax = lemax;
+}
+
 fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
     const int N = c->ni, E = mesh->n_elems;
     if (E < 1 || !mesh->elems || !mesh->elem_shifts)
@@ -286,6 +347,7 @@ fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
                 return fail(c, FSI_E_MESH, "Q9 element " + std::to_string(e) + ": det J <= 0 at a node");
         }
     }
+    build_q9_blocks(c);
     return FSI_OK;
 }
 
@@ -606,6 +668,15 @@ void layout(fsi_ctx *c) {
         c->off_upost = take(16 * N * sizeof(float));
         c->off_dep_e = take(8 * N * 4);
         c->off_dep_xy = take(8 * N * sizeof(float2));
+        if (!c->bh_off.empty()) {
+            c->off_bh_off = take(c->bh_off.size() * 4);
+            c->off_bh_nodes = take(c->bh_nodes.size() * 4);
+            c->off_be_off = take(c->be_off.size() * 4);
+            c->off_be_elem = take(c->be_elem.size() * 4);
+            c->off_be_nodes = take(c->be_nodes.size() * 2);
+            c->off_uself = take(c->uself.size() * 2);
+            c->off_dep_le = take(8 * N * 2);
+        }
     }
     c->total = o;
 }
@@ -626,7 +697,8 @@ fsi_status enqueue_fluid(fsi_ctx *c) {
     const int st = c->fluid.storage;
     if (c->topo == FSI_TOPO_Q9) {
         HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, st,
-                                            c->inst.uq, c->inst.ud, c->inst.ueg, c->stream));
+                                            c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
+                                            c->inst.u_hmax, c->inst.u_lemax, c->stream));
         return FSI_OK;
     }
     if (!c->wk0.empty())
@@ -648,16 +720,22 @@ fsi_status enqueue_fluid(fsi_ctx *c) {
 // structure re-solved and relaxed) before the final pass, which the body
 // kernel accepts and records
 fsi_status enqueue_step(fsi_ctx *c) {
-    for (int k = 0; k < c->n_sub; ++k) {
+    // without a body there is nothing to iterate on: one pass
+    const int passes = c->bodies.empty() ? 1 : c->n_sub;
+    for (int k = 0; k < passes; ++k) {
         fsi_status st = enqueue_fluid(c);
         if (st != FSI_OK) return st;
-        HIP_TRY(c, fsi::launch_body(d_inst(c), 1, k + 1 < c->n_sub ? 2 : 1, c->stream));
+        HIP_TRY(c, fsi::launch_body(d_inst(c), 1, k + 1 < passes ? 2 : 1, c->stream));
     }
     return FSI_OK;
 }
 
 // force of the current level and the next body state (no boundary update)
 fsi_status enqueue_load_update(fsi_ctx *c) {
+    // unstructured meshes: the moments the next step's correction starts from
+    // (each step's interpolation forms them for the populations it writes)
+    if (c->topo == FSI_TOPO_Q9)
+        HIP_TRY(c, fsi::launch_unstructured_moments(d_inst(c), (long long)c->ni, c->fluid.storage, c->stream));
     if (c->has_wall)
         HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
                                                reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
@@ -801,6 +879,34 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                                   hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_pent, c->patch_ent.data(), c->patch_ent.size() * 4,
                                   hipMemcpyHostToDevice, c->stream));
+        P.u_nblk = c->bh_off.empty() ? 0 : (int)c->bh_off.size() - 1;
+        P.u_hmax = c->u_hmax;
+        P.u_lemax = c->u_lemax;
+        if (!c->bh_off.empty()) {
+            P.bh_off = reinterpret_cast<const int *>(c->ws + c->off_bh_off);
+            P.bh_nodes = reinterpret_cast<const int *>(c->ws + c->off_bh_nodes);
+            P.be_off = reinterpret_cast<const int *>(c->ws + c->off_be_off);
+            P.be_elem = reinterpret_cast<const int *>(c->ws + c->off_be_elem);
+            P.be_nodes = reinterpret_cast<const uint16_t *>(c->ws + c->off_be_nodes);
+            P.uself = reinterpret_cast<const uint16_t *>(c->ws + c->off_uself);
+            P.dep_le = reinterpret_cast<uint16_t *>(c->ws + c->off_dep_le);
+            const std::pair<size_t, const void *> up[] = {
+                {c->off_bh_off, c->bh_off.data()}, {c->off_bh_nodes, c->bh_nodes.data()},
+                {c->off_be_off, c->be_off.data()}, {c->off_be_elem, c->be_elem.data()}};
+            const size_t nbytes[] = {c->bh_off.size() * 4, c->bh_nodes.size() * 4, c->be_off.size() * 4,
+                                     c->be_elem.size() * 4};
+            for (int q = 0; q < 4; ++q)
+                HIP_TRY(c, hipMemcpyAsync(c->ws + up[q].first, up[q].second, nbytes[q], hipMemcpyHostToDevice,
+                                          c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_be_nodes, c->be_nodes.data(), c->be_nodes.size() * 2,
+                                      hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_uself, c->uself.data(), c->uself.size() * 2,
+                                      hipMemcpyHostToDevice, c->stream));
+        } else {
+            P.bh_off = P.bh_nodes = P.be_off = P.be_elem = nullptr;
+            P.be_nodes = P.uself = nullptr;
+            P.dep_le = nullptr;
+        }
     }
     P.step = reinterpret_cast<long long *>(c->ws + c->off_step);
     P.err = reinterpret_cast<unsigned *>(c->ws + c->off_err);
@@ -1121,7 +1227,8 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                                                   (int)c->wk0.size(), stg, c->stream));
             if (which == 0 && c->topo == FSI_TOPO_Q9)
                 e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, stg,
-                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->stream);
+                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
+                                             c->inst.u_hmax, c->inst.u_lemax, c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
                                                c->cut, 0);
@@ -1140,6 +1247,9 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
     }
     HIP_TRY(c, hipEventDestroy(e0));
     HIP_TRY(c, hipEventDestroy(e1));
+    // the repeated unstructured launches left the moments of the scratch side
+    if (c->topo == FSI_TOPO_Q9)
+        HIP_TRY(c, fsi::launch_unstructured_moments(d_inst(c), (long long)c->ni, c->fluid.storage, c->stream));
     return sync_check(c);
 }
 

@@ -119,7 +119,20 @@ struct Inst {
     void *upost;              // [n_nodes][8][2] post-collision moving populations (f_k, g_k), FP32
     int *dep_e;               // [8][n_nodes] element holding each departure point
     float2 *dep_xy;           // [8][n_nodes] its local coordinates there
+    // node blocks of U_BLOCK consecutive nodes for the LDS-staged interpolation
+    // (null bh_off: every block gathers from device memory instead)
+    int u_nblk, u_hmax, u_lemax, pad3;
+    const int *bh_off;        // [u_nblk + 1] offsets into bh_nodes
+    const int *bh_nodes;      // nodes of the elements of the block's nodes (its halo), ascending
+    const int *be_off;        // [u_nblk + 1] offsets into be_elem / be_nodes
+    const int *be_elem;       // elements holding a node of the block, ascending
+    const uint16_t *be_nodes; // [.][16] their nine nodes as halo positions (7 unused)
+    const uint16_t *uself;    // [n_nodes] each node's own position in its block's halo
+    uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
 };
+
+// nodes per block of the LDS-staged interpolation
+constexpr int U_BLOCK = 256;
 
 }  // namespace fsi
 
@@ -135,8 +148,10 @@ hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_wor
                                   int phase, hipStream_t s);
 hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
-                               float2 *uq, float2 *ud, float2 *ueg, hipStream_t s);
+                               float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
+                               hipStream_t s);
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s);
+hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int storage, hipStream_t s);
 hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,
                                    int storage, hipStream_t s);
 hipError_t launch_dump_macro(const Inst *inst, int side, double *out, long long n_nodes, int storage,

@@ -9,8 +9,8 @@ namespace fsi {
 // Unstructured meshes of 9-node quadrilateral elements (Sec. II.B on the
 // paper's own finite-element meshes), static and periodic.  Node-wise
 // kernels, data reached through the element connectivity:
-//   k_u_moments  delta Q_a and mu/p at every node
-//   k_u_egrad    element derivatives at the element's nine nodes
+//   k_u_egrad    element derivatives at the element's nine nodes (of delta Q_a,
+//                which the previous step's interpolation formed with mu/p)
 //   k_u_nodeD    D_a = (mu/p) d_a delta Q_a at every node (nodal means)
 //   k_u_egrad    again, of D
 //   k_u_collide  F_a = d_a D_a (nodal means), collision, post-collision
@@ -18,7 +18,9 @@ namespace fsi {
 //                gathers)
 //   k_u_stream   9-node interpolation at the departure points, which
 //                k_u_locate finds once (static mesh) among the node's
-//                elements with the corner (first-order) map
+//                elements with the corner (first-order) map; then delta Q_a
+//                and mu/p of the new populations for the next step
+//                (k_u_moments forms them when the host sets populations)
 // A nodal derivative is the mean over the node's elements of the element
 // derivative J^{-T} sum_s C_s grad_xi N_s at the node's own local position,
 // where only the three nodes on each of the node's element lines contribute
@@ -27,6 +29,15 @@ namespace fsi {
 // FP32 offsets from each element's centre node (formed in FP64 on the host).
 // ---------------------------------------------------------------------------
 constexpr int U_THREADS = 256;
+
+// Workgroup slot -> block of consecutive nodes (or elements), so that each of
+// the 8 XCDs takes a contiguous run of blocks (dispatch slot b goes to XCD
+// b mod 8) and the neighbours a block gathers from sit in the same L2.  The
+// grid is a multiple of 8; the map is a bijection of [0, gridDim.x).
+__device__ __forceinline__ long long xcd_block() {
+    const unsigned per = gridDim.x / 8;
+    return (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
 
 // element node at local position (p, q), p, q in {-1, 0, 1}
 __device__ __forceinline__ int q9_node(int p, int q) {
@@ -53,7 +64,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ 
                                                        const float2 *__restrict__ v,
                                                        float2 *__restrict__ eg) {
     const Inst &P = *pinst;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < P.n_elems;
+    for (long long e = xcd_block() * blockDim.x + threadIdx.x; e < P.n_elems;
          e += (long long)gridDim.x * blockDim.x) {
         float2 val[9], rel[9];
 #pragma unroll
@@ -105,12 +116,31 @@ __device__ __forceinline__ float2 node_mean(const Inst &P, const float2 *__restr
     return make_float2(gx * inv, gy * inv);
 }
 
+// delta Q_a and mu/p of a node from its 18 populations, for the correction of
+// the step that collides them
+__device__ __forceinline__ void u_node_moments(const Inst &P, long long idx, const float f[9],
+                                               const float g[9]) {
+    const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float ir = 1.0f / rho;
+    const float ux = jx * ir, uy = jy * ir;
+    const float T = (0.5f * G * ir - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
+    const float one3T = 1.0f - 3.0f * T;
+    P.uq[idx] = make_float2(jx * (one3T - ux * ux), jy * (one3T - uy * uy));
+    P.us[idx] = P.mu / (rho * T);
+}
+
+// the moments of the current populations; the interpolation kernels form
+// them for the populations they write, so this runs only when the host sets
+// the populations (initial state, set, checkpoint load, after a timing pass)
 template <int STORE>
 __global__ void __launch_bounds__(U_THREADS) k_u_moments(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
     const long long n = *P.step;
     const void *src = P.pop[n & 1];
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
         float f[9], g[9];
 #pragma unroll
@@ -118,23 +148,14 @@ __global__ void __launch_bounds__(U_THREADS) k_u_moments(const Inst *__restrict_
             f[k] = pop_load<STORE>(P, src, k, idx);
             g[k] = pop_load<STORE>(P, src, Q + k, idx);
         }
-        const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-        const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-        const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-        const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-        const float ir = 1.0f / rho;
-        const float ux = jx * ir, uy = jy * ir;
-        const float T = (0.5f * G * ir - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
-        const float one3T = 1.0f - 3.0f * T;
-        P.uq[idx] = make_float2(jx * (one3T - ux * ux), jy * (one3T - uy * uy));
-        P.us[idx] = P.mu / (rho * T);
+        u_node_moments(P, idx, f, g);
     }
 }
 
 // D_a = (mu / p) d_a delta Q_a at every node
 __global__ void __launch_bounds__(U_THREADS) k_u_nodeD(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
         const float2 g = node_mean(P, P.ueg, idx);
         const float S = P.us[idx];
@@ -149,7 +170,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_collide(const Inst *__restrict_
     const void *src = P.pop[n & 1];
     void *dst = P.pop[(n + 1) & 1];
     unsigned err = 0;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
         const float2 F = node_mean(P, P.ueg, idx);
         float f[9], g[9];
@@ -183,7 +204,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
     const Inst &P = *pinst;
     const float dt = P.dt;
     unsigned err = 0;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
         const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
         for (int k = 1; k < 9; ++k) {
@@ -221,6 +242,19 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
             }
             P.dep_e[(k - 1) * P.n_nodes + idx] = e_found;
             P.dep_xy[(k - 1) * P.n_nodes + idx] = make_float2(xi, eta);
+            if (P.be_off) {
+                // its position in the block's ascending element list (it holds
+                // every element of the node's patch)
+                const long long blk = idx / U_BLOCK;
+                int lo = P.be_off[blk], hi = P.be_off[blk + 1];
+                const int first = lo;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (P.be_elem[mid] <= e_found) lo = mid;
+                    else hi = mid;
+                }
+                P.dep_le[(k - 1) * P.n_nodes + idx] = (uint16_t)(lo - first);
+            }
         }
     }
     if (err) atomicOr(P.err, err);
@@ -234,9 +268,13 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
     const Inst &P = *pinst;
     const long long n = *P.step;
     void *dst = P.pop[(n + 1) & 1];
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < P.n_nodes;
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
-#pragma unroll 2
+        // the rest populations k_u_collide wrote, then the moving ones
+        float f[9], g[9];
+        f[0] = pop_load<STORE>(P, dst, 0, idx);
+        g[0] = pop_load<STORE>(P, dst, Q, idx);
+#pragma unroll
         for (int k = 1; k < 9; ++k) {
             const int e = P.dep_e[(k - 1) * P.n_nodes + idx];
             const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
@@ -258,30 +296,119 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
                 }
             pop_store<STORE>(P, dst, k, idx, vf);
             pop_store<STORE>(P, dst, Q + k, idx, vg);
+            f[k] = pop_round<STORE>(P, k, vf);
+            g[k] = pop_round<STORE>(P, Q + k, vg);
         }
+        // moments of the new populations as the next step reads them back
+        u_node_moments(P, idx, f, g);
     }
+}
+
+// The same interpolation with the gathers staged through LDS: one workgroup
+// per block of U_BLOCK consecutive nodes (Morton-ordered meshes keep a block
+// compact) first copies the post-collision lines of the block's halo nodes
+// into LDS, one plane per direction, and the element lists of the block as
+// halo positions; every gather then reads LDS.  Same arithmetic in the same
+// order as k_u_stream, so both give identical results.  Blocks go to XCDs in
+// contiguous runs, so neighbouring blocks share halo lines in one L2.
+template <int STORE>
+__global__ void __launch_bounds__(U_BLOCK) k_u_stream_blk(const Inst *__restrict__ pinst) {
+    extern __shared__ __align__(16) unsigned char u_lds[];
+    const Inst &P = *pinst;
+    const int nb = P.u_nblk, per_xcd = (nb + 7) / 8;
+    const int b = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (b >= nb) return;                              // the whole workgroup
+    const long long n = *P.step;
+    void *dst = P.pop[(n + 1) & 1];
+    const int H = P.u_hmax;
+    float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [8][H]
+    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][16]
+    const int h0 = P.bh_off[b], nh = P.bh_off[b + 1] - h0;
+    const int e0 = P.be_off[b], ne = P.be_off[b + 1] - e0;
+    // halo lines: four lanes per 64-byte node line (a quarter each, two directions)
+    const float4 *up4 = reinterpret_cast<const float4 *>(P.upost);
+    for (int x = threadIdx.x; x < 4 * nh; x += U_BLOCK) {
+        const int h = x >> 2, q = x & 3;
+        const float4 v = up4[4 * (long long)P.bh_nodes[h0 + h] + q];
+        pl[(2 * q) * H + h] = make_float2(v.x, v.y);
+        pl[(2 * q + 1) * H + h] = make_float2(v.z, v.w);
+    }
+    const uint4 *en4 = reinterpret_cast<const uint4 *>(P.be_nodes) + 2 * (long long)e0;
+    uint4 *el4 = reinterpret_cast<uint4 *>(el);
+    for (int x = threadIdx.x; x < 2 * ne; x += U_BLOCK) el4[x] = en4[x];
+    __syncthreads();
+    const long long idx = (long long)b * U_BLOCK + threadIdx.x;
+    if (idx >= P.n_nodes) return;
+    const int self = P.uself[idx];
+    float f[9], g[9];
+    f[0] = pop_load<STORE>(P, dst, 0, idx);
+    g[0] = pop_load<STORE>(P, dst, Q, idx);
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+        const int le = P.dep_le[(k - 1) * P.n_nodes + idx];
+        const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
+        const float xi = d.x, eta = d.y;
+        const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
+        const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
+        const uint4 w8 = el4[2 * le];
+        const int nodes[9] = {(int)(w8.x & 0xffffu), (int)(w8.x >> 16), (int)(w8.y & 0xffffu),
+                              (int)(w8.y >> 16),     (int)(w8.z & 0xffffu), (int)(w8.z >> 16),
+                              (int)(w8.w & 0xffffu), (int)(w8.w >> 16),     (int)el[16 * le + 8]};
+        const float2 *plk = pl + (k - 1) * H;
+        const float2 fg0 = plk[self];
+        float vf = fg0.x, vg = fg0.y;
+#pragma unroll
+        for (int qq = -1; qq <= 1; ++qq)
+#pragma unroll
+            for (int pp = -1; pp <= 1; ++pp) {
+                const float w = lx[pp + 1] * ly[qq + 1];
+                const float2 fg = plk[nodes[q9_node(pp, qq)]];
+                vf += w * (fg.x - fg0.x);
+                vg += w * (fg.y - fg0.y);
+            }
+        pop_store<STORE>(P, dst, k, idx, vf);
+        pop_store<STORE>(P, dst, Q + k, idx, vg);
+        f[k] = pop_round<STORE>(P, k, vf);
+        g[k] = pop_round<STORE>(P, Q + k, vg);
+    }
+    u_node_moments(P, idx, f, g);
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s) {
-    const long long g64 = (n_nodes + U_THREADS - 1) / U_THREADS;
-    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 1)), dim3(U_THREADS), 0, s, inst);
+    const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int storage, hipStream_t s) {
+    const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    FSI_DISPATCH(storage, k_u_moments, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), s, inst);
     return hipGetLastError();
 }
 
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
-                               float2 *uq, float2 *ud, float2 *ueg, hipStream_t s) {
-    const long long g64 = (n_nodes + U_THREADS - 1) / U_THREADS;
-    const long long e64 = (n_elems + U_THREADS - 1) / U_THREADS;
-    const dim3 grid((unsigned)(g64 > 0 ? g64 : 1)), egrid((unsigned)(e64 > 0 ? e64 : 1)), block(U_THREADS);
-    FSI_DISPATCH(storage, k_u_moments, grid, block, s, inst);
+                               float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
+                               hipStream_t s) {
+    // multiples of the XCD count (see xcd_block)
+    const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    const long long e64 = ((n_elems + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    const dim3 grid((unsigned)(g64 > 0 ? g64 : 8)), egrid((unsigned)(e64 > 0 ? e64 : 8)), block(U_THREADS);
     hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, uq, ueg);
     hipLaunchKernelGGL(k_u_nodeD, grid, block, 0, s, inst);
     hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, ud, ueg);
     FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
-    FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
+    if (n_blocks > 0) {
+        // a multiple of the XCD count; the kernel maps slots to blocks
+        const unsigned g = (unsigned)(((n_blocks + 7) / 8) * 8);
+        const size_t lds = (size_t)hmax * 8 * sizeof(float2) + (size_t)lemax * 16 * sizeof(uint16_t);
+        if (storage == 0) hipLaunchKernelGGL(k_u_stream_blk<0>, dim3(g), dim3(U_BLOCK), lds, s, inst);
+        else hipLaunchKernelGGL(k_u_stream_blk<1>, dim3(g), dim3(U_BLOCK), lds, s, inst);
+    } else {
+        FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
+    }
     return hipGetLastError();
 }
 
