@@ -53,8 +53,9 @@ struct fsi_ctx {
     std::vector<uint8_t> inflow;        // per far-field list entry
     std::vector<int2> ff;               // far-field (node, interior node)
     std::vector<int2> wk0, wk1, wbnd, wwall;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    // captured steps: [0] one step, [1] kGraphSteps steps (fewer graph launches)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     int64_t host_step = 0;
     bool initialized = false;
     std::string err;
@@ -755,10 +756,33 @@ fsi_status sync_check(fsi_ctx *c) {
 }
 
 void drop_graph(fsi_ctx *c) {
-    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
+    for (int q = 0; q < 2; ++q) {
+        if (c->graph_exec[q]) hipGraphExecDestroy(c->graph_exec[q]);
+        if (c->graph[q]) hipGraphDestroy(c->graph[q]);
+        c->graph_exec[q] = nullptr;
+        c->graph[q] = nullptr;
+    }
+}
+
+// Steps per replay of the long graph: a graph launch costs a few microseconds
+// between steps, kernels inside one graph follow each other without a gap.
+constexpr int kGraphSteps = 16;
+
+// capture `count` steps into graph slot q
+fsi_status capture_steps(fsi_ctx *c, int q, int count) {
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    fsi_status st = FSI_OK;
+    for (int k = 0; k < count && st == FSI_OK; ++k) st = enqueue_step(c);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != FSI_OK) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    c->graph[q] = g;
+    HIP_TRY(c, hipGraphInstantiate(&c->graph_exec[q], g, nullptr, nullptr, 0));
+    return FSI_OK;
 }
 
 }  // namespace
@@ -1009,20 +1033,17 @@ fsi_status fsi_step(fsi_ctx *c, int nsteps) {
             if (st != FSI_OK) return st;
         }
     } else {
-        if (!c->graph_exec) {
-            HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_step(c);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(c->stream, &g);
-            if (st != FSI_OK) {
-                if (g) hipGraphDestroy(g);
-                return st;
-            }
-            if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-            c->graph = g;
-            HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        const int nlong = nsteps / kGraphSteps, nshort = nsteps % kGraphSteps;
+        if (nlong && !c->graph_exec[1]) {
+            st = capture_steps(c, 1, kGraphSteps);
+            if (st != FSI_OK) return st;
         }
-        for (int k = 0; k < nsteps; ++k) HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+        if (nshort && !c->graph_exec[0]) {
+            st = capture_steps(c, 0, 1);
+            if (st != FSI_OK) return st;
+        }
+        for (int k = 0; k < nlong; ++k) HIP_TRY(c, hipGraphLaunch(c->graph_exec[1], c->stream));
+        for (int k = 0; k < nshort; ++k) HIP_TRY(c, hipGraphLaunch(c->graph_exec[0], c->stream));
     }
     c->host_step += nsteps;
     return FSI_OK;
@@ -1309,8 +1330,8 @@ struct fsi_batch {
     int grid = 0, order = 0, shape = 0;
     int n_sub = 1;                  // coupling sub-iterations per step (all instances)
     bool any_cut = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     std::string err;
 };
 
@@ -1329,10 +1350,12 @@ fsi_status bfail(fsi_batch *b, fsi_status st, const std::string &msg) {
     } while (0)
 
 void batch_drop_graph(fsi_batch *b) {
-    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    b->graph_exec = nullptr;
-    b->graph = nullptr;
+    for (int q = 0; q < 2; ++q) {
+        if (b->graph_exec[q]) hipGraphExecDestroy(b->graph_exec[q]);
+        if (b->graph[q]) hipGraphDestroy(b->graph[q]);
+        b->graph_exec[q] = nullptr;
+        b->graph[q] = nullptr;
+    }
 }
 
 void batch_lists(fsi_batch *b) {
@@ -1536,9 +1559,12 @@ fsi_status fsi_batch_step(fsi_batch *b, int nsteps) {
             if (st != FSI_OK) return st;
         }
     } else {
-        if (!b->graph_exec) {
+        const int nlong = nsteps / kGraphSteps, nshort = nsteps % kGraphSteps;
+        for (int q = 0; q < 2; ++q) {
+            if ((q ? nlong : nshort) == 0 || b->graph_exec[q]) continue;
             BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            st = batch_enqueue_step(b);
+            st = FSI_OK;
+            for (int k = 0; k < (q ? kGraphSteps : 1) && st == FSI_OK; ++k) st = batch_enqueue_step(b);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(b->stream, &g);
             if (st != FSI_OK) {
@@ -1546,10 +1572,11 @@ fsi_status fsi_batch_step(fsi_batch *b, int nsteps) {
                 return st;
             }
             if (e != hipSuccess) return bfail(b, FSI_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-            b->graph = g;
-            BHIP_TRY(b, hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0));
+            b->graph[q] = g;
+            BHIP_TRY(b, hipGraphInstantiate(&b->graph_exec[q], g, nullptr, nullptr, 0));
         }
-        for (int k = 0; k < nsteps; ++k) BHIP_TRY(b, hipGraphLaunch(b->graph_exec, b->stream));
+        for (int k = 0; k < nlong; ++k) BHIP_TRY(b, hipGraphLaunch(b->graph_exec[1], b->stream));
+        for (int k = 0; k < nshort; ++k) BHIP_TRY(b, hipGraphLaunch(b->graph_exec[0], b->stream));
     }
     for (fsi_ctx *c : b->ctx) c->host_step += nsteps;
     return FSI_OK;

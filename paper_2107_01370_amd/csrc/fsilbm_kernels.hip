@@ -1113,38 +1113,58 @@ __device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, do
     return o;
 }
 
-constexpr int BODY_THREADS = 256;
+constexpr int BODY_THREADS = 1024;
 
 __global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ insts, int phase) {
-    __shared__ double sx[BODY_THREADS], sy[BODY_THREADS], sz[BODY_THREADS];
+    constexpr int NW = BODY_THREADS / 64;
+    __shared__ double sx[NW], sy[NW], sz[NW];
     const Inst &P = insts[blockIdx.x];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const long long n = *P.step;
     const long long L = phase ? n + 1 : n;
-    // the load of every body: the traction sum over its wall polygon
+    // the load of every body: the traction sum over its wall polygon, in a
+    // fixed order (per thread a stride of the polygon, loads issued four at a
+    // time; then the lanes of each wave pairwise; then the waves in order)
     double F[MAX_BODIES][3] = {};
     for (int k = 0; k < P.n_seg; ++k) {
         double fx = 0.0, fy = 0.0, mz = 0.0;
         const int fn = P.seg_n[k] - P.seg_dup[k];
-        for (int i = t; i < fn; i += BODY_THREADS) {
-            const double4 v = P.wall_force[P.seg_i0[k] + i];
-            fx += v.x;
-            fy += v.y;
-            mz += v.z;
-        }
-        sx[t] = fx; sy[t] = fy; sz[t] = mz;
-        __syncthreads();
-        for (int s = BODY_THREADS / 2; s > 0; s >>= 1) {
-            if (t < s) {
-                sx[t] += sx[t + s];
-                sy[t] += sy[t + s];
-                sz[t] += sz[t + s];
+        const double4 *wf = P.wall_force + P.seg_i0[k];
+        for (int i0 = t; i0 < fn; i0 += 4 * BODY_THREADS) {
+            double4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * BODY_THREADS;
+                v[u] = i < fn ? wf[i] : make_double4(0.0, 0.0, 0.0, 0.0);
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                fx += v[u].x;
+                fy += v[u].y;
+                mz += v[u].z;
+            }
         }
-        F[k][0] = sx[0];
-        F[k][1] = sy[0];
-        F[k][2] = sz[0];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            fx += __shfl_down(fx, o, 64);
+            fy += __shfl_down(fy, o, 64);
+            mz += __shfl_down(mz, o, 64);
+        }
+        if (lane == 0) {
+            sx[wv] = fx;
+            sy[wv] = fy;
+            sz[wv] = mz;
+        }
+        __syncthreads();
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            ax += sx[w];
+            ay += sy[w];
+            az += sz[w];
+        }
+        F[k][0] = ax;
+        F[k][1] = ay;
+        F[k][2] = az;
         __syncthreads();
     }
     if (phase == 1 && P.cut) {

@@ -113,6 +113,23 @@ def test_runs_are_deterministic():
     assert np.array_equal(out[0][1], out[1][1])
 
 
+def test_long_and_single_step_graphs_agree():
+    """fsi_step replays a captured graph of 16 steps and a one-step graph for
+    the remainder: 37 steps in one call equal 37 calls of one step."""
+    c = small_cylinder()
+    out = []
+    for calls in ([37], [1] * 37, [5, 16, 16]):
+        s = Sim(c.mesh, c.fluid, c.bodies)
+        s.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+        for k in calls:
+            s.step(k)
+        assert s.step_count() == 37
+        out.append((s.populations(), s.forces(0, 38), s.body_state()))
+    for o in out[1:]:
+        assert np.array_equal(o[0][0], out[0][0][0]) and np.array_equal(o[0][1], out[0][0][1])
+        assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[2], out[0][2])
+
+
 # ---- device error reporting ------------------------------------------------------
 
 def test_departure_outside_cells_reports_cfl():
