@@ -33,9 +33,12 @@ import synth  # noqa: E402
 
 METRIC = "MLUPS (f+g, D2Q9) and % HBM roofline; batched/FP16 vs plain FP32"
 HBM_PEAK_GBS = 8000.0
-# the sources of the structured-mesh kernels (the counter record is tied to them)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_01370_amd", "csrc", name)
-                  for name in ("fsilbm_device.h", "fsilbm_kernels.hip")]
+# VALU issue: 256 CUs x 2.4 GHz x one 64-lane wave instruction per cycle per CU
+VALU_PEAK_G = 256 * 2.4
+# the source of the collision-streaming kernel (the counter records are tied to
+# it): the shared device header and its section of the kernel file
+CSRC = os.path.join(ROOT, "paper_2107_01370_amd", "csrc")
+K1_SECTION = ("// Fused collision + ALE interpolating streaming.", "// Boundary kernels")
 
 
 def algorithmic_bytes_per_node(storage: int, unstructured: bool = False) -> int:
@@ -52,9 +55,12 @@ def algorithmic_bytes_per_node(storage: int, unstructured: bool = False) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(CSRC, "fsilbm_device.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(CSRC, "fsilbm_kernels.hip"), encoding="utf-8") as fh:
+        text = fh.read()
+    a = text.index(K1_SECTION[0])
+    h.update(text[a:text.index(K1_SECTION[1], a)].encode())
     return h.hexdigest()[:16]
 
 
@@ -70,6 +76,27 @@ def measured_traffic(workload: str, storage: int, n_nodes: int):
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def measured_valu(workload: str, storage: int, n_nodes: int, k1_ms: float):
+    """VALU issue of the collision-streaming kernel from the committed counter
+    summary (SQ_INSTS_VALU, wave instructions per dispatch), if it was taken on
+    the current kernel source: against one wave instruction per cycle per CU
+    (four 16-lane SIMDs, 4 cycles per 64-lane instruction; packed FP32 off)."""
+    path = os.path.join(ROOT, "profiles", f"valu_collide_stream_{workload}_"
+                                          f"{'fp16' if storage else 'fp32'}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    wi = float(rec["valu_wave_instructions_per_dispatch"])
+    achieved = wi / (k1_ms * 1e-3) / 1e9
+    return {"wave_instructions_per_launch": round(wi),
+            "per_node": round(wi * 64 / n_nodes, 1),
+            "achieved": round(achieved, 1), "peak": VALU_PEAK_G, "unit": "G wave-instr/s",
+            "frac": round(achieved / VALU_PEAK_G, 4)}
 
 
 WORKLOADS = {
@@ -345,6 +372,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_node": bpn,
+            "valu_issue": (None if args.workload.startswith("unstructured")
+                           else measured_valu(args.workload, storage, N, k1_ms)),
         },
     }
     if not args.no_variants and args.workload == "cylinder_heave_2048x4096" and storage == 0:
