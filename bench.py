@@ -364,7 +364,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_u_moments + 2 k_u_egrad + k_u_nodeD + k_u_collide + k_u_stream"
+            "kernel": ("2 k_u_egrad + k_u_nodeD + k_u_collide + k_u_stream_blk"
                        if args.workload.startswith("unstructured") else "k_collide_stream"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
