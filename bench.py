@@ -231,12 +231,20 @@ def time_sequential(cases, steps: int, warmup: int):
 
 def cpu_baseline_unstructured(target_s: float = 20.0, m: int = 48):
     """Oracle (plain FP64 NumPy) timed on a smaller mesh of the same
-    construction and physics (m = 48: 55,296 nodes)."""
+    construction and physics (m = 48: 55,296 nodes), started from the
+    populations the GPU path initialises; returns the timing and the accuracy
+    of the GPU path against it on the same steps."""
     from oracle.unstructured import UnstructuredSolver
+    from paper_2107_01370_amd.fsilbm import Simulation
     from synth.unstructured import unstructured_pulse_case
 
     mesh, fluid, (rho, ux, uy, T) = unstructured_pulse_case(m)
+    sim = Simulation(mesh, fluid, [], device="cuda:0")
+    sim.init_equilibrium(rho[None], ux[None], uy[None], T[None])
+    f0, g0 = sim.populations()
     ora = UnstructuredSolver(mesh, fluid, rho, ux, uy, T)
+    ora.f = f0[:, 0, :].astype(np.float64)
+    ora.g = g0[:, 0, :].astype(np.float64)
     ora.step()
     t0 = time.perf_counter()
     n = 0
@@ -246,30 +254,45 @@ def cpu_baseline_unstructured(target_s: float = 20.0, m: int = 48):
         el = time.perf_counter() - t0
         if el >= target_s or n >= 200:
             break
+    sim.step(n + 1)
+    r, _, _, Tg = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    sim.close()
     threads = os.environ.get("OMP_NUM_THREADS", "1")
-    return {
-        "value": mesh.n_nodes * n / el / 1e6,
-        "unit": "MLUPS",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"{n} steps of the same construction at m = {m} ({mesh.n_nodes} nodes, "
-                  f"{mesh.n_elems} elements) with the same physics, {el:.1f} s, single-threaded "
-                  f"NumPy (OMP_NUM_THREADS={threads}), os.cpu_count()={os.cpu_count()}",
+    sample = (f"{n} steps of the same construction at m = {m} ({mesh.n_nodes} nodes, "
+              f"{mesh.n_elems} elements) with the same physics, {el:.1f} s, single-threaded "
+              f"NumPy (OMP_NUM_THREADS={threads}), os.cpu_count()={os.cpu_count()}")
+    accuracy = {
+        "against": "FP64 oracle, same sample as cpu_baseline, from the same initial populations",
+        "steps": n + 1,
+        "rho_max_rel": float(np.max(np.abs(r[0] - r_o) / r_o)),
+        "p_max_rel": float(np.max(np.abs(r[0] * Tg[0] - r_o * T_o) / (r_o * T_o))),
     }
+    return {"value": mesh.n_nodes * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": sample}, accuracy
 
 
 def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
     """Oracle (plain FP64 NumPy) timed on a strip of the same workload: the
     first `rows` radial rows of the O-grid (wall included) with the same
-    physics, stepped until about `target_s` seconds of CPU work."""
+    physics, stepped until about `target_s` seconds of CPU work, from the
+    populations the GPU path initialises on that strip; returns the timing and
+    the accuracy of the GPU path against it on the same steps (density,
+    pressure, wall forces, heave)."""
     from dataclasses import replace
 
     from oracle.solver import OracleSolver
+    from paper_2107_01370_amd.fsilbm import Simulation
 
     m = case.mesh
     strip = replace(m, nj=rows, X=m.X[:rows].copy(), Y=m.Y[:rows].copy())
-    ora = OracleSolver(strip, case.fluid, case.bodies, case.rho[:rows], case.ux[:rows],
-                       case.uy[:rows], case.T[:rows])
+    macro = (case.rho[:rows], case.ux[:rows], case.uy[:rows], case.T[:rows])
+    sim = Simulation(strip, case.fluid, case.bodies, device="cuda:0")
+    sim.init_equilibrium(*macro)
+    f0, g0 = sim.populations()
+    ora = OracleSolver(strip, case.fluid, case.bodies, *macro)
+    ora.f = f0.astype(np.float64)
+    ora.g = g0.astype(np.float64)
     ora.step()                         # warm-up (first-call overheads)
     t0 = time.perf_counter()
     n = 0
@@ -279,6 +302,31 @@ def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
         el = time.perf_counter() - t0
         if el >= target_s or n >= 50:
             break
+    nsteps = n + 1
+    sim.step(nsteps)
+    r, _, _, Tg = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    accuracy = {
+        "against": "FP64 oracle, same sample as cpu_baseline, from the same initial populations",
+        "steps": nsteps,
+        "rho_max_rel": float(np.max(np.abs(r - r_o) / r_o)),
+        "p_max_rel": float(np.max(np.abs(r * Tg - r_o * T_o) / (r_o * T_o))),
+    }
+    for k in range(len(case.bodies)):
+        # the records of levels 0 .. nsteps-1 (the oracle records a level when
+        # it steps from it)
+        hist = sim.forces(0, nsteps, body=k)
+        ho = np.array(ora.histories[k])[:nsteps]
+        fscale = float(np.max(np.hypot(ho[:, 1], ho[:, 2])))
+        # drag and lift against the peak force magnitude (they share the
+        # dynamic-pressure scale), heave against the body diameter scale of
+        # its own motion
+        accuracy[f"body{k}"] = {
+            "drag_max_rel": float(np.max(np.abs(hist[:, 1] - ho[:, 1])) / fscale),
+            "lift_max_rel": float(np.max(np.abs(hist[:, 2] - ho[:, 2])) / fscale),
+            "heave_max_abs": float(np.max(np.abs(hist[:, 4] - ho[:, 4]))),
+        }
+    sim.close()
     nodes = strip.ni * strip.nj
     threads = os.environ.get("OMP_NUM_THREADS", "1")
     return {
@@ -290,7 +338,7 @@ def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
                   f"of the same mesh and physics, {el:.1f} s, single-threaded NumPy "
                   f"(OMP_NUM_THREADS={threads}), host {platform.processor() or platform.machine()}, "
                   f"os.cpu_count()={os.cpu_count()}",
-    }
+    }, accuracy
 
 
 def main():
@@ -408,8 +456,9 @@ def main():
             "finite_state": finb,
         })
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = (cpu_baseline_unstructured() if args.workload.startswith("unstructured")
-                               else cpu_baseline(case))
+        out["cpu_baseline"], out["accuracy"] = (
+            cpu_baseline_unstructured() if args.workload.startswith("unstructured")
+            else cpu_baseline(case))
     print(json.dumps(out), flush=True)
 
 
