@@ -233,10 +233,10 @@ fsi_status topology(fsi_ctx *c) {
 // elements holding a node of the block (every departure element of the
 // block's nodes is one of them), the nodes of those elements (the block's
 // halo), each element's nodes as halo positions and each node's own position.
-// The block path is left off (empty tables) if the largest block's halo and
-// element list do not fit 64 KiB of LDS, or if FSILBM_UNSTRUCTURED_GATHER is
-// set to "device" (every block then gathers from device memory; both paths
-// give identical results).
+// The block path is left off (empty tables) if the largest block's halo, element
+// list and rest populations do not fit 64 KiB of LDS, or if FSILBM_UNSTRUCTURED_GATHER is
+// set to "device" (k_u_collide and k_u_stream then go through device memory;
+// both paths agree to FP32 rounding).
 void build_q9_blocks(fsi_ctx *c) {
     c->bh_off.clear(); c->bh_nodes.clear(); c->be_off.clear(); c->be_elem.clear();
     c->be_nodes.clear(); c->uself.clear();
@@ -275,7 +275,7 @@ void build_q9_blocks(fsi_ctx *c) {
         hmax = std::max(hmax, (int)nodes.size());
         lemax = std::max(lemax, (int)els.size());
     }
-    if ((size_t)hmax * 64 + (size_t)lemax * 32 > 65536) return;
+    if (fsi::u_block_lds_bytes(hmax, lemax) > 65536) return;
     c->bh_off.swap(bh_off); c->bh_nodes.swap(bh_nodes); c->be_off.swap(be_off);
     c->be_elem.swap(be_elem); c->be_nodes.swap(be_nodes); c->uself.swap(uself);
     c->u_hmax = hmax;

@@ -134,6 +134,12 @@ struct Inst {
 // nodes per block of the LDS-staged interpolation
 constexpr int U_BLOCK = 256;
 
+// LDS of one node block: 8 planes of (f_k, g_k) over the halo, the element
+// lists as halo positions (16 u16 per element), the block's rest populations
+inline size_t u_block_lds_bytes(int hmax, int lemax) {
+    return (size_t)hmax * 8 * 8 + (size_t)lemax * 16 * 2 + (size_t)U_BLOCK * 8;
+}
+
 }  // namespace fsi
 
 namespace fsi {

@@ -13,9 +13,10 @@ namespace fsi {
 //                which the previous step's interpolation formed with mu/p)
 //   k_u_nodeD    D_a = (mu/p) d_a delta Q_a at every node (nodal means)
 //   k_u_egrad    again, of D
-//   k_u_collide  F_a = d_a D_a (nodal means), collision, post-collision
-//                populations (the moving ones in FP32 node by node for the
-//                gathers)
+//   k_u_collide_stream_blk  per block of nodes: F_a = d_a D_a (nodal means)
+//                and collision of the block's halo into LDS, then the
+//                interpolation below from LDS (k_u_collide + k_u_stream do the
+//                same through device memory when a block's halo would not fit)
 //   k_u_stream   9-node interpolation at the departure points, which
 //                k_u_locate finds once (static mesh) among the node's
 //                elements with the corner (first-order) map; then delta Q_a
@@ -102,17 +103,35 @@ __global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ 
     }
 }
 
-// nodal mean of the element derivatives of node idx
+// nodal mean of the element derivatives of node idx, summed in the order of
+// the node's element list; the first U_PATCH entries are fetched together
+// (their loads in flight at once), a longer list continues one by one
+constexpr int U_PATCH = 8;
 __device__ __forceinline__ float2 node_mean(const Inst &P, const float2 *__restrict__ eg, long long idx) {
     const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+    const int cnt = e_end - b;
+    int ent[U_PATCH];
+#pragma unroll
+    for (int j = 0; j < U_PATCH; ++j) ent[j] = j < cnt ? P.patch_ent[b + j] : -1;
+    float2 d[U_PATCH];
+#pragma unroll
+    for (int j = 0; j < U_PATCH; ++j)
+        d[j] = ent[j] >= 0 ? eg[9 * (long long)(ent[j] >> 4) + (ent[j] & 15)] : make_float2(0.0f, 0.0f);
     float gx = 0.0f, gy = 0.0f;
-    for (int k = b; k < e_end; ++k) {
-        const int ent = P.patch_ent[k];
-        const float2 d = eg[9 * (long long)(ent >> 4) + (ent & 15)];
-        gx += d.x;
-        gy += d.y;
+#pragma unroll
+    for (int j = 0; j < U_PATCH; ++j) {
+        if (j < cnt) {
+            gx += d[j].x;
+            gy += d[j].y;
+        }
     }
-    const float inv = 1.0f / (float)(e_end - b);
+    for (int k = b + U_PATCH; k < e_end; ++k) {
+        const int e2 = P.patch_ent[k];
+        const float2 d2 = eg[9 * (long long)(e2 >> 4) + (e2 & 15)];
+        gx += d2.x;
+        gy += d2.y;
+    }
+    const float inv = 1.0f / (float)cnt;
     return make_float2(gx * inv, gy * inv);
 }
 
@@ -304,45 +323,65 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
     }
 }
 
-// The same interpolation with the gathers staged through LDS: one workgroup
-// per block of U_BLOCK consecutive nodes (Morton-ordered meshes keep a block
-// compact) first copies the post-collision lines of the block's halo nodes
-// into LDS, one plane per direction, and the element lists of the block as
-// halo positions; every gather then reads LDS.  Same arithmetic in the same
-// order as k_u_stream, so both give identical results.  Blocks go to XCDs in
-// contiguous runs, so neighbouring blocks share halo lines in one L2.
+// Collision and interpolation of one block of U_BLOCK consecutive nodes, the
+// gathers staged through LDS (Morton-ordered meshes keep a block compact): the
+// block first collides every node of its halo (the nodes of the elements of
+// its nodes; halo nodes are collided by every block that sees them) straight
+// into LDS, one plane of (f_k, g_k) per moving direction, and copies the
+// block's element lists as halo positions; each node then interpolates from
+// LDS.  The same arithmetic as k_u_collide followed by k_u_stream (the
+// compiler may fuse multiply-adds differently in the two kernels, so the paths
+// agree to FP32 rounding).  Blocks go to XCDs in
+// contiguous runs, so neighbouring blocks share their halo's lines in one L2.
 template <int STORE>
-__global__ void __launch_bounds__(U_BLOCK) k_u_stream_blk(const Inst *__restrict__ pinst) {
+__global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__restrict__ pinst) {
     extern __shared__ __align__(16) unsigned char u_lds[];
     const Inst &P = *pinst;
     const int nb = P.u_nblk, per_xcd = (nb + 7) / 8;
     const int b = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
     if (b >= nb) return;                              // the whole workgroup
     const long long n = *P.step;
+    const void *src = P.pop[n & 1];
     void *dst = P.pop[(n + 1) & 1];
     const int H = P.u_hmax;
     float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [8][H]
     uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][16]
+    float2 *rest = reinterpret_cast<float2 *>(el + 16 * (size_t)P.u_lemax);            // [U_BLOCK]
     const int h0 = P.bh_off[b], nh = P.bh_off[b + 1] - h0;
     const int e0 = P.be_off[b], ne = P.be_off[b + 1] - e0;
-    // halo lines: four lanes per 64-byte node line (a quarter each, two directions)
-    const float4 *up4 = reinterpret_cast<const float4 *>(P.upost);
-    for (int x = threadIdx.x; x < 4 * nh; x += U_BLOCK) {
-        const int h = x >> 2, q = x & 3;
-        const float4 v = up4[4 * (long long)P.bh_nodes[h0 + h] + q];
-        pl[(2 * q) * H + h] = make_float2(v.x, v.y);
-        pl[(2 * q + 1) * H + h] = make_float2(v.z, v.w);
+    const long long n0 = (long long)b * U_BLOCK;
+    unsigned err = 0;
+    for (int h = threadIdx.x; h < nh; h += U_BLOCK) {
+        const long long v = P.bh_nodes[h0 + h];
+        const float2 F = node_mean(P, P.ueg, v);
+        float f[9], g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = pop_load<STORE>(P, src, k, v);
+            g[k] = pop_load<STORE>(P, src, Q + k, v);
+        }
+        collide(f, g, F.x, F.y, P, err);
+#pragma unroll
+        for (int k = 1; k < 9; ++k) pl[(k - 1) * H + h] = make_float2(f[k], g[k]);
+        // the block's own nodes: rest populations (they do not move)
+        const long long own = v - n0;
+        if (own >= 0 && own < U_BLOCK) {
+            pop_store<STORE>(P, dst, 0, v, f[0]);
+            pop_store<STORE>(P, dst, Q, v, g[0]);
+            rest[own] = make_float2(pop_round<STORE>(P, 0, f[0]), pop_round<STORE>(P, Q, g[0]));
+        }
     }
+    if (err) atomicOr(P.err, err);
     const uint4 *en4 = reinterpret_cast<const uint4 *>(P.be_nodes) + 2 * (long long)e0;
     uint4 *el4 = reinterpret_cast<uint4 *>(el);
     for (int x = threadIdx.x; x < 2 * ne; x += U_BLOCK) el4[x] = en4[x];
     __syncthreads();
-    const long long idx = (long long)b * U_BLOCK + threadIdx.x;
+    const long long idx = n0 + threadIdx.x;
     if (idx >= P.n_nodes) return;
     const int self = P.uself[idx];
     float f[9], g[9];
-    f[0] = pop_load<STORE>(P, dst, 0, idx);
-    g[0] = pop_load<STORE>(P, dst, Q, idx);
+    f[0] = rest[threadIdx.x].x;
+    g[0] = rest[threadIdx.x].y;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
         const int le = P.dep_le[(k - 1) * P.n_nodes + idx];
@@ -399,14 +438,14 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
     hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, uq, ueg);
     hipLaunchKernelGGL(k_u_nodeD, grid, block, 0, s, inst);
     hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, ud, ueg);
-    FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
     if (n_blocks > 0) {
         // a multiple of the XCD count; the kernel maps slots to blocks
         const unsigned g = (unsigned)(((n_blocks + 7) / 8) * 8);
-        const size_t lds = (size_t)hmax * 8 * sizeof(float2) + (size_t)lemax * 16 * sizeof(uint16_t);
-        if (storage == 0) hipLaunchKernelGGL(k_u_stream_blk<0>, dim3(g), dim3(U_BLOCK), lds, s, inst);
-        else hipLaunchKernelGGL(k_u_stream_blk<1>, dim3(g), dim3(U_BLOCK), lds, s, inst);
+        const size_t lds = u_block_lds_bytes(hmax, lemax);
+        if (storage == 0) hipLaunchKernelGGL(k_u_collide_stream_blk<0>, dim3(g), dim3(U_BLOCK), lds, s, inst);
+        else hipLaunchKernelGGL(k_u_collide_stream_blk<1>, dim3(g), dim3(U_BLOCK), lds, s, inst);
     } else {
+        FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
         FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
     }
     return hipGetLastError();

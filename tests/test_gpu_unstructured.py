@@ -91,10 +91,14 @@ def test_unstructured_full_size_step():
     check_step(f, g, ora)
 
 
-def test_unstructured_lds_staged_equals_device_gathers(monkeypatch):
-    """The interpolation staged through LDS per node block and the one that
-    gathers from device memory (FSILBM_UNSTRUCTURED_GATHER=device at creation)
-    perform the same arithmetic: identical populations after 30 steps."""
+def test_unstructured_lds_staged_and_device_gathers_agree(monkeypatch):
+    """The block path (halo collided into LDS, interpolation from LDS) and the
+    path through device memory (k_u_collide then k_u_stream, selected with
+    FSILBM_UNSTRUCTURED_GATHER=device at creation) perform the same
+    arithmetic; the compiler may fuse multiply-adds differently in the two
+    kernels, so they agree to FP32 rounding: one step of each against the
+    oracle, and 30 steps against each other at the multi-step bar (1e-5 of the
+    population scale; FP32 rounding differences grow by ~1e-7 per step)."""
     from paper_2107_01370_amd.fsilbm import Simulation
     mesh, fl, (rho, ux, uy, T) = unstructured_pulse_case(12, seed=2)
     out = []
@@ -103,12 +107,16 @@ def test_unstructured_lds_staged_equals_device_gathers(monkeypatch):
             monkeypatch.setenv("FSILBM_UNSTRUCTURED_GATHER", mode)
         else:
             monkeypatch.delenv("FSILBM_UNSTRUCTURED_GATHER", raising=False)
-        sim = Simulation(mesh, fl, [])
-        sim.init_equilibrium(rho[None], ux[None], uy[None], T[None])
-        sim.step(30)
+        sim, ora = paired(mesh, fl, (rho, ux, uy, T))
+        sim.step(1)
+        ora.step()
+        f, g = sim.populations()
+        check_step(f, g, ora)
+        sim.step(29)
         out.append(sim.populations())
         sim.close()
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for a, b in zip(out[0], out[1]):
+        assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
 
 
 def test_unstructured_restart_set_and_timing_keep_the_run():
