@@ -123,7 +123,14 @@ typedef struct {
  *              the corners' bilinear map puts them (straight-sided elements):
  *              departure points are located with that map and interpolated
  *              with the nine shape functions.  Nodal derivatives are the mean
- *              over a node's elements of the element derivatives there.    */
+ *              over a node's elements of the element derivatives there.
+ *              Number nodes along a space-filling curve: each step collides
+ *              and interpolates blocks of 256 consecutive nodes through LDS,
+ *              so a compact block keeps its halo small (a mesh whose largest
+ *              block halo does not fit 64 KiB of LDS, or a context created
+ *              with the environment variable FSILBM_UNSTRUCTURED_GATHER set to
+ *              "device", gathers through device memory instead; the two agree
+ *              to FP32 rounding).                                          */
 typedef enum { FSI_TOPO_PERIODIC2 = 0, FSI_TOPO_OGRID = 1, FSI_TOPO_CGRID = 2,
                FSI_TOPO_TWIN = 3, FSI_TOPO_Q9 = 4 } fsi_topo;
 
@@ -198,7 +205,9 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
 fsi_status fsi_workspace_bytes(const fsi_ctx *ctx, size_t *bytes);
 
 /* Lend `bytes` of device memory at `dev_ptr` (256-byte aligned) to the
- * context and upload the static data.  Synchronises the stream. */
+ * context and upload the static data.  Synchronises the stream.  Q9 meshes:
+ * also locates every departure point of the static mesh once; FSI_E_CFL if
+ * one lies outside the elements of its node (dt too large for the mesh). */
 fsi_status fsi_bind_workspace(fsi_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Initial populations = equilibria (f^eq, g^eq with Psi) of the given host

@@ -156,3 +156,14 @@ def test_unstructured_restart_set_and_timing_keep_the_run():
     assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1])
     for s in (a, b, c, d):
         s.close()
+
+
+def test_unstructured_departure_outside_patch_reports_cfl():
+    """A time step that carries departure points beyond a node's elements is
+    refused when the workspace is bound (the departure points of a static
+    mesh are located once, then)."""
+    from paper_2107_01370_amd.fsilbm import FsiError, Simulation
+    mesh, fl, _ = unstructured_pulse_case(6)
+    with pytest.raises(FsiError) as e:
+        Simulation(mesh, replace(fl, dt=8.0 * fl.dt), [])
+    assert e.value.status == -3
