@@ -98,6 +98,51 @@ def interpolate_B(grid, X, Y, field_row0, field_rows12, dt):
     return out
 
 
+def grad_populations(rho_t, ux_t, uy_t, T_t, E_t, du_x, du_y, dT, dE, gamma, mu, Pr, dt):
+    """Grad's approximation f_i = f_i^eq + dt f_i^(1), g_i = g_i^eq + dt g_i^(1)
+    (Sec. III.A.1) of all nine populations from the target values and the
+    gradients (d/dx, d/dy) of u_x, u_y, T and E at the wall nodes."""
+    Cv, Cp = L.specific_heats(gamma)
+    dux_dx, dux_dy = du_x
+    duy_dx, duy_dy = du_y
+    dT_dx, dT_dy = dT
+    dE_dx, dE_dy = dE
+    omega, omega1 = L.relaxation_rates(rho_t, T_t, mu, Pr, dt)
+    # strain rate S = grad u + grad u^T, (grad u)_ab = d_a u_b
+    Sxx = 2.0 * dux_dx
+    Syy = 2.0 * duy_dy
+    Sxy = dux_dy + duy_dx
+    div = dux_dx + duy_dy
+    pref = -(1.0 / omega) * rho_t * T_t
+    P1xx = pref * (Sxx - div / Cv)
+    P1yy = pref * (Syy - div / Cv)
+    P1xy = pref * Sxy
+    # q^(1) = -(2/omega1) rho C_p T grad T + 2 u . P^(1)
+    q1x = -(2.0 / omega1) * rho_t * Cp * T_t * dT_dx + 2.0 * (ux_t * P1xx + uy_t * P1xy)
+    q1y = -(2.0 / omega1) * rho_t * Cp * T_t * dT_dy + 2.0 * (ux_t * P1xy + uy_t * P1yy)
+    # R^(1) = -(2/omega1) rho T [S (E + 2T) + u (grad E)^T + grad E u^T]
+    rpref = -(2.0 / omega1) * rho_t * T_t
+    R1xx = rpref * (Sxx * (E_t + 2.0 * T_t) + 2.0 * ux_t * dE_dx)
+    R1yy = rpref * (Syy * (E_t + 2.0 * T_t) + 2.0 * uy_t * dE_dy)
+    R1xy = rpref * (Sxy * (E_t + 2.0 * T_t) + ux_t * dE_dy + uy_t * dE_dx)
+
+    fe = L.feq(rho_t, ux_t, uy_t, T_t)
+    ge = L.geq(rho_t, ux_t, uy_t, E_t, T_t)
+    W = L.weights(T_t)
+    fw = np.empty((L.Q,) + np.shape(rho_t))
+    gw = np.empty_like(fw)
+    for i in range(L.Q):
+        cx, cy = L.CX[i], L.CY[i]
+        f1 = W[i] * (P1xx * (cx * cx - T_t) + 2.0 * P1xy * cx * cy
+                     + P1yy * (cy * cy - T_t)) / (2.0 * T_t * T_t)
+        g1 = W[i] * ((q1x * cx + q1y * cy) / T_t
+                     + (R1xx * (cx * cx - T_t) + 2.0 * R1xy * cx * cy
+                        + R1yy * (cy * cy - T_t)) / (2.0 * T_t * T_t))
+        fw[i] = fe[i] + dt * f1
+        gw[i] = ge[i] + dt * g1
+    return fw, gw
+
+
 def wall_grad_bc(grid, X, Y, x1, y1, VGx, VGy, f_new, g_new, missing,
                  f_old, g_old, gamma, mu, Pr, dt):
     """Fill the missing wall populations of (f_new, g_new) in place with
@@ -135,38 +180,12 @@ def wall_grad_bc(grid, X, Y, x1, y1, VGx, VGy, f_new, g_new, missing,
     dT_dx, dT_dy = (v[0] for v in grid.grad(TT, x1, y1))
     dE_dx, dE_dy = (v[0] for v in grid.grad(EE, x1, y1))
 
-    omega, omega1 = L.relaxation_rates(rho_t, T_t, mu, Pr, dt)
-    # strain rate S = grad u + grad u^T, (grad u)_ab = d_a u_b
-    Sxx = 2.0 * dux_dx
-    Syy = 2.0 * duy_dy
-    Sxy = dux_dy + duy_dx
-    div = dux_dx + duy_dy
-    pref = -(1.0 / omega) * rho_t * T_t
-    P1xx = pref * (Sxx - div / Cv)
-    P1yy = pref * (Syy - div / Cv)
-    P1xy = pref * Sxy
-    # q^(1) = -(2/omega1) rho C_p T grad T + 2 u . P^(1)
-    q1x = -(2.0 / omega1) * rho_t * Cp * T_t * dT_dx + 2.0 * (ux_t * P1xx + uy_t * P1xy)
-    q1y = -(2.0 / omega1) * rho_t * Cp * T_t * dT_dy + 2.0 * (ux_t * P1xy + uy_t * P1yy)
-    # R^(1) = -(2/omega1) rho T [S (E + 2T) + u (grad E)^T + grad E u^T]
-    rpref = -(2.0 / omega1) * rho_t * T_t
-    R1xx = rpref * (Sxx * (E_t + 2.0 * T_t) + 2.0 * ux_t * dE_dx)
-    R1yy = rpref * (Syy * (E_t + 2.0 * T_t) + 2.0 * uy_t * dE_dy)
-    R1xy = rpref * (Sxy * (E_t + 2.0 * T_t) + ux_t * dE_dy + uy_t * dE_dx)
-
-    fe = L.feq(rho_t, ux_t, uy_t, T_t)
-    ge = L.geq(rho_t, ux_t, uy_t, E_t, T_t)
-    W = L.weights(T_t)
+    fw, gw = grad_populations(rho_t, ux_t, uy_t, T_t, E_t, (dux_dx, dux_dy), (duy_dx, duy_dy),
+                              (dT_dx, dT_dy), (dE_dx, dE_dy), gamma, mu, Pr, dt)
     for i in range(L.Q):
-        cx, cy = L.CX[i], L.CY[i]
-        f1 = W[i] * (P1xx * (cx * cx - T_t) + 2.0 * P1xy * cx * cy
-                     + P1yy * (cy * cy - T_t)) / (2.0 * T_t * T_t)
-        g1 = W[i] * ((q1x * cx + q1y * cy) / T_t
-                     + (R1xx * (cx * cx - T_t) + 2.0 * R1xy * cx * cy
-                        + R1yy * (cy * cy - T_t)) / (2.0 * T_t * T_t))
         m = missing[i, 0] & wc
-        f_new[i, 0] = np.where(m, fe[i] + dt * f1, f_new[i, 0])
-        g_new[i, 0] = np.where(m, ge[i] + dt * g1, g_new[i, 0])
+        f_new[i, 0] = np.where(m, fw[i], f_new[i, 0])
+        g_new[i, 0] = np.where(m, gw[i], g_new[i, 0])
     return rho_t, ux_t, uy_t, T_t
 
 

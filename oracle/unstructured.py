@@ -118,24 +118,29 @@ class UGrid:
         gy = np.where(self.pm, gy_e[self.pe, self.pa], 0.0).sum(axis=1) / self.count
         return gx, gy
 
-    def locate(self, dx, dy):
-        """For every node n, the element of its patch whose bilinear (corner)
-        map holds the point at displacement (dx[n], dy[n]) from the node, and
-        the local coordinates there.  Returns (element, xi, eta).  Raises
-        ValueError if a point lies in none of the node's elements."""
-        found = np.zeros(self.N, dtype=bool)
-        elem = np.zeros(self.N, dtype=np.int64)
-        XI = np.zeros(self.N)
-        ETA = np.zeros(self.N)
-        dx = np.broadcast_to(dx, (self.N,))
-        dy = np.broadcast_to(dy, (self.N,))
+    def locate(self, dx, dy, nodes=None, allow_missing=None):
+        """For every node n (or those listed in `nodes`), the element of its
+        patch whose bilinear (corner) map holds the point at displacement
+        (dx[n], dy[n]) from the node, and the local coordinates there.
+        Returns (element, xi, eta).  A point in none of the node's elements
+        raises ValueError, unless allow_missing[n] is set (a boundary node,
+        whose point then lies outside the mesh): element -1 there."""
+        nodes = np.arange(self.N) if nodes is None else np.asarray(nodes, dtype=np.int64)
+        M = nodes.size
+        found = np.zeros(M, dtype=bool)
+        elem = np.full(M, -1, dtype=np.int64)
+        XI = np.zeros(M)
+        ETA = np.zeros(M)
+        dx = np.broadcast_to(dx, (M,))
+        dy = np.broadcast_to(dy, (M,))
+        pm, pe, pa = self.pm[nodes], self.pe[nodes], self.pa[nodes]
         for k in range(self.P):
             # the k-th element of the patches of the nodes not yet placed
-            todo = np.flatnonzero(self.pm[:, k] & ~found)
+            todo = np.flatnonzero(pm[:, k] & ~found)
             if todo.size == 0:
                 continue
-            e = self.pe[todo, k]
-            a = self.pa[todo, k]
+            e = pe[todo, k]
+            a = pa[todo, k]
             # coordinates relative to the node (well conditioned)
             cx = self.ex[e, :4] - self.ex[e, a][:, None]
             cy = self.ey[e, :4] - self.ey[e, a][:, None]
@@ -146,8 +151,9 @@ class UGrid:
             XI[hit] = xi[inside]
             ETA[hit] = eta[inside]
             found[hit] = True
-        if not np.all(found):
-            raise ValueError(f"departure point outside the patch of node {int(np.argmin(found))}")
+        ok = found if allow_missing is None else (found | np.asarray(allow_missing)[nodes])
+        if not np.all(ok):
+            raise ValueError(f"departure point outside the patch of node {int(nodes[np.argmin(ok)])}")
         return elem, XI, ETA
 
 
@@ -256,3 +262,148 @@ class UnstructuredSolver:
 
     def macroscopic(self):
         return L.macroscopic(self.f, self.g, self.fluid.gamma)
+
+
+class UnstructuredWallSolver(UnstructuredSolver):
+    """The step on a static unstructured Q9 mesh round a fixed body, in
+    float64 (paper Sec. II.B on its own kind of mesh, with the boundary
+    conditions of Sec. III.A and the wall force of Sec. III).  Test
+    infrastructure only.
+
+    The mesh carries `wall_nodes` (the body polygon, clockwise, so that a
+    +90 degree rotation of its tangent points into the fluid) and
+    `far_nodes` (the outer boundary).  Readings:
+
+    * a population of a boundary node is missing when its departure point
+      lies in none of the node's elements (outside the mesh);
+    * far field: all populations of the far-field nodes are set to the
+      free-stream equilibrium (the outer circle lies far from the body);
+    * wall: missing populations take Grad's approximation (Sec. III.A.1) with
+      u_t = 0 (fixed body), rho_t, T_t the 9-node interpolation at
+      B = x + dt n (n the unit normal of the lumped wall polygon normal) in
+      the wall node's element that holds B, the wall nodes of that element
+      carrying the values of the previous level (their new populations are
+      being built), and gradients of u, T, E at the wall node by the nodal
+      finite-element derivative with the wall nodes holding the targets;
+    * force: sigma . (n ds) summed over the wall nodes in list order, with
+      (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2 from the polygon neighbours,
+      the moment about the body's elastic axis (Sec. III).
+    """
+
+    def __init__(self, mesh, fluid, body, rho=None, ux=None, uy=None, T=None, correction=True):
+        self.grid = UGrid(mesh)
+        self.fluid = fluid
+        self.correction = correction
+        self.body = body
+        g = self.grid
+        N = g.N
+        if rho is None:
+            rho = np.full(N, fluid.rho_inf)
+            ux = np.full(N, fluid.u_inf[0])
+            uy = np.full(N, fluid.u_inf[1])
+            T = np.full(N, fluid.T_inf)
+        self.f, self.g = L.equilibrium_populations(rho, ux, uy, T, fluid.gamma)
+        self.n = 0
+        self.wall = np.asarray(mesh.wall_nodes, dtype=np.int64)
+        self.far = np.asarray(mesh.far_nodes, dtype=np.int64)
+        bnd = np.zeros(N, dtype=bool)
+        bnd[self.wall] = True
+        bnd[self.far] = True
+        self.dep = [None] * L.Q
+        for i in range(1, L.Q):
+            self.dep[i] = g.locate(-fluid.dt * L.CX[i], -fluid.dt * L.CY[i], allow_missing=bnd)
+        # lumped wall normals (into the fluid) and the points B
+        xw, yw = mesh.X[self.wall], mesh.Y[self.wall]
+        self.nds_x = -0.5 * (np.roll(yw, -1) - np.roll(yw, 1))
+        self.nds_y = 0.5 * (np.roll(xw, -1) - np.roll(xw, 1))
+        nn = np.hypot(self.nds_x, self.nds_y)
+        self.B = g.locate(fluid.dt * self.nds_x / nn, fluid.dt * self.nds_y / nn, nodes=self.wall)
+        self.xw, self.yw = xw, yw
+        self.history = []
+
+    def missing(self, i):
+        """Mask of the nodes whose population i is missing."""
+        return self.dep[i][0] < 0
+
+    def wall_force(self):
+        """(F_x, F_y, M_EA) on the body from the current populations."""
+        from .forces import wall_stress
+        fl = self.fluid
+        sxx, sxy, syy = wall_stress(self.f[:, self.wall], self.g[:, self.wall], fl.gamma, fl.mu,
+                                    fl.Pr, fl.dt)
+        Fx_k = sxx * self.nds_x + sxy * self.nds_y
+        Fy_k = sxy * self.nds_x + syy * self.nds_y
+        rx = self.xw - self.body.ea[0]
+        ry = self.yw - self.body.ea[1]
+        Mz_k = rx * Fy_k - ry * Fx_k
+        Fx = Fy = Mz = 0.0
+        for k in range(self.wall.size):
+            Fx += Fx_k[k]
+            Fy += Fy_k[k]
+            Mz += Mz_k[k]
+        return Fx, Fy, Mz
+
+    def step(self):
+        from .boundary import grad_populations
+        fl = self.fluid
+        g = self.grid
+        Fx_b, Fy_b, Mz_b = self.wall_force()
+        self.history.append([float(self.n), Fx_b, Fy_b, Mz_b, 0.0, 0.0])
+        rho0, _, _, _, T0 = L.macroscopic(self.f[:, self.wall], self.g[:, self.wall], fl.gamma)
+        if self.correction:
+            Fx, Fy = self.correction_force()
+        else:
+            Fx = Fy = np.zeros(g.N)
+        fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, fl.dt, Fx, Fy)
+        f_new = np.full_like(fpost, np.nan)
+        g_new = np.full_like(gpost, np.nan)
+        f_new[0] = fpost[0]
+        g_new[0] = gpost[0]
+        for i in range(1, L.Q):
+            e, xi, eta = self.dep[i]
+            ok = e >= 0
+            Nw = shape(xi[ok], eta[ok])
+            nodes = g.elems[e[ok]]
+            f_new[i, ok] = np.sum(Nw.T * fpost[i][nodes], axis=1)
+            g_new[i, ok] = np.sum(Nw.T * gpost[i][nodes], axis=1)
+        # far field: free-stream equilibrium
+        nf = self.far.size
+        fe, ge = L.equilibrium_populations(np.full(nf, fl.rho_inf), np.full(nf, fl.u_inf[0]),
+                                           np.full(nf, fl.u_inf[1]), np.full(nf, fl.T_inf), fl.gamma)
+        f_new[:, self.far] = fe
+        g_new[:, self.far] = ge
+        # wall: targets at B and gradients at the wall nodes
+        Cv, _ = L.specific_heats(fl.gamma)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            rho_s, ux_s, uy_s, E_s, T_s = L.macroscopic(np.nan_to_num(f_new), np.nan_to_num(g_new),
+                                                        fl.gamma)
+        R = rho_s.copy()
+        R[self.wall] = rho0
+        TT = T_s.copy()
+        TT[self.wall] = T0
+        eB, xiB, etaB = self.B
+        NB = shape(xiB, etaB)                                 # [9, nw]
+        nodesB = g.elems[eB]
+        rho_t = np.sum(NB.T * R[nodesB], axis=1)
+        T_t = np.sum(NB.T * TT[nodesB], axis=1)
+        nw = self.wall.size
+        ux_t = np.zeros(nw)
+        uy_t = np.zeros(nw)
+        E_t = Cv * T_t
+        Ux, Uy, Tg, Eg = ux_s.copy(), uy_s.copy(), T_s.copy(), E_s.copy()
+        Ux[self.wall] = ux_t
+        Uy[self.wall] = uy_t
+        Tg[self.wall] = T_t
+        Eg[self.wall] = E_t
+        grads = []
+        for F in (Ux, Uy, Tg, Eg):
+            gx, gy = g.grad(F)
+            grads.append((gx[self.wall], gy[self.wall]))
+        fw, gw = grad_populations(rho_t, ux_t, uy_t, T_t, E_t, *grads, fl.gamma, fl.mu, fl.Pr, fl.dt)
+        for i in range(1, L.Q):
+            m = self.missing(i)[self.wall]
+            f_new[i, self.wall[m]] = fw[i, m]
+            g_new[i, self.wall[m]] = gw[i, m]
+        assert not np.any(np.isnan(f_new)) and not np.any(np.isnan(g_new))
+        self.f, self.g = f_new, g_new
+        self.n += 1

@@ -214,3 +214,158 @@ def unstructured_pulse_case(m: int = 16, amp: float = 0.06, seed: int = 0, Ma: f
     rho = 1.0 + pulse * np.exp(-(dx * dx + dy * dy) / (2.0 * 16.0))
     N = mesh.n_nodes
     return mesh, fluid, (rho, np.full(N, u0[0]), np.full(N, u0[1]), np.full(N, T0))
+
+
+def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, seed: int = 0,
+                     center=(0.0, 0.0), mirror: bool = False) -> UnstructuredMesh:
+    """Unstructured 9-node quadrilateral mesh of the annulus between a
+    cylinder of diameter D and a circle of far_D * D, as input data: the
+    annulus is cut into n_theta x n_r cells of a polar grid (square cells:
+    radii growing by 1 + 2 pi / n_theta), every cell into two triangles by a
+    seeded diagonal, every triangle into three quadrilaterals through its edge
+    midpoints and centroid, all in physical coordinates (straight-sided
+    elements; the wall is the polygon through the grid's wall points, with
+    the element edge nodes on its chords).  Nodes renumbered in Morton order
+    of their coordinates, elements by their centre node.
+
+    mirror (n_theta even): the lower half is the mirror image of the upper
+    half about the x axis through the centre (diagonals mirrored, corner
+    coordinates mirrored exactly).
+
+    Also returns, on the mesh: `wall_nodes`, the nodes on the body polygon
+    in clockwise order (a rotation by +90 degrees of the polygon's tangent
+    points into the fluid), and `far_nodes`, the nodes on the outer circle."""
+    rng = np.random.default_rng(seed)
+    R = 0.5 * D
+    q = 1.0 + 2.0 * np.pi / n_theta
+    n_r = int(np.ceil(np.log(far_D * D / D) / np.log(q)))
+    S = 24 * n_theta                                   # index-space period along theta
+
+    def corner(i, j):
+        i = i % n_theta
+        r = R * q ** j
+        if mirror and 2 * i > n_theta:
+            x, y = corner(n_theta - i, j)
+            return (x, 2.0 * center[1] - y)
+        t = 2.0 * np.pi * i / n_theta
+        return (center[0] + r * np.cos(t), center[1] + r * np.sin(t))
+
+    if mirror and n_theta % 2:
+        raise ValueError("a mirrored mesh needs an even n_theta")
+
+    key_to_id = {}
+    pos = []
+
+    def node(key, p):
+        k = (key[0] % S, key[1])
+        i = key_to_id.get(k)
+        if i is None:
+            i = len(pos)
+            key_to_id[k] = i
+            pos.append(p)
+        return i
+
+    elems = []
+
+    def mid(a, b):
+        return ((a[0] + b[0]) // 2, (a[1] + b[1]) // 2)
+
+    def pmid(a, b):
+        return (0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]))
+
+    def add_quad(keys, pts):
+        # keys / pts: 4 corners; orient counter-clockwise in physical space
+        area = 0.5 * sum(pts[c][0] * pts[(c + 1) % 4][1] - pts[(c + 1) % 4][0] * pts[c][1]
+                         for c in range(4))
+        if area < 0:
+            keys = [keys[0], keys[3], keys[2], keys[1]]
+            pts = [pts[0], pts[3], pts[2], pts[1]]
+        ids = [node(keys[c], pts[c]) for c in range(4)]
+        for a, b in ((0, 1), (1, 2), (2, 3), (3, 0)):
+            ids.append(node(mid(keys[a], keys[b]), pmid(pts[a], pts[b])))
+        ck = (sum(k[0] for k in keys) // 4, sum(k[1] for k in keys) // 4)
+        ids.append(node(ck, (0.25 * sum(p[0] for p in pts), 0.25 * sum(p[1] for p in pts))))
+        elems.append(ids)
+
+    coin = {}
+    for j in range(n_r):
+        for i in range(n_theta):
+            if mirror and 2 * i >= n_theta:
+                ac = not coin[(n_theta - 1 - i, j)]      # the mirror of A-C is B-D
+            else:
+                ac = bool(rng.random() < 0.5)
+            coin[(i, j)] = ac
+            ks = {(a, b): (24 * (i + a), 24 * (j + b)) for a in (0, 1) for b in (0, 1)}
+            ps = {ab: corner(i + ab[0], j + ab[1]) for ab in ks}
+            A, B, C, Dd = (0, 0), (1, 0), (1, 1), (0, 1)
+            tris = [(A, B, C), (A, C, Dd)] if ac else [(A, B, Dd), (B, C, Dd)]
+            for (p, qq, r) in tris:
+                kp, kq, kr = ks[p], ks[qq], ks[r]
+                pp, pq, pr = ps[p], ps[qq], ps[r]
+                kg = ((kp[0] + kq[0] + kr[0]) // 3, (kp[1] + kq[1] + kr[1]) // 3)
+                pg = ((pp[0] + pq[0] + pr[0]) / 3.0, (pp[1] + pq[1] + pr[1]) / 3.0)
+                kpq, kqr, krp = mid(kp, kq), mid(kq, kr), mid(kr, kp)
+                ppq, pqr, prp = pmid(pp, pq), pmid(pq, pr), pmid(pr, pp)
+                add_quad([kp, kpq, kg, krp], [pp, ppq, pg, prp])
+                add_quad([kq, kqr, kg, kpq], [pq, pqr, pg, ppq])
+                add_quad([kr, krp, kg, kqr], [pr, prp, pg, pqr])
+    P = np.array(pos, dtype=np.float64)
+    E = np.array(elems, dtype=np.int64)
+    keys = np.empty((len(pos), 2), dtype=np.int64)
+    for k, v in key_to_id.items():
+        keys[v] = k
+    # Morton renumbering over a uniform quantisation of the coordinates
+    lo = P.min(axis=0)
+    span = float((P.max(axis=0) - lo).max())
+    qx = np.floor((P[:, 0] - lo[0]) / span * 65535.0).astype(np.int64)
+    qy = np.floor((P[:, 1] - lo[1]) / span * 65535.0).astype(np.int64)
+    order = np.argsort(_morton(qx, qy), kind="stable")
+    new_id = np.empty_like(order)
+    new_id[order] = np.arange(order.size)
+    P, keys = P[order], keys[order]
+    E = new_id[E]
+    E = E[np.argsort(E[:, 8], kind="stable")]
+    # wall nodes clockwise (theta key descending), far-field nodes
+    on_wall = np.flatnonzero(keys[:, 1] == 0)
+    wall = on_wall[np.argsort(-keys[on_wall, 0], kind="stable")]
+    far = np.flatnonzero(keys[:, 1] == 24 * n_r)
+    mesh = UnstructuredMesh(P[:, 0].copy(), P[:, 1].copy(), E.astype(np.int32),
+                            np.zeros((E.shape[0], 9, 2), dtype=np.int8), (0.0, 0.0),
+                            info={"kind": "cylinder_q9", "n_theta": n_theta, "n_r": n_r, "D": D,
+                                  "far_D": far_D, "seed": seed, "center": tuple(center),
+                                  "mirror": mirror})
+    mesh.wall_nodes = wall.astype(np.int32)
+    mesh.far_nodes = far.astype(np.int32)
+    return mesh
+
+
+def q9_cylinder_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: int = 1,
+                     Ma: float = 0.2, Re: float = 100.0, T0: float = 1.0 / 3.0,
+                     gamma: float = 1.4, Pr: float = 0.71, storage: int = 0,
+                     mirror: bool = False):
+    """Flow past a fixed cylinder on the unstructured mesh of
+    `cylinder_q9_mesh`: free stream along +x at Mach Ma, Re = rho U D / mu,
+    started from potential flow times tanh((r - R) / delta) (delta = D / 8),
+    uniform density and temperature; dt = (smallest patch reach) / (3 sqrt 2).
+    Returns (mesh, fluid, body, (rho, ux, uy, T)); the body is fixed
+    (elastic axis at the centre)."""
+    from .configs import DOF_FIXED, BodyParams, FluidParams, sound_speed
+    mesh = cylinder_q9_mesh(n_theta, D, far_D, seed=seed, mirror=mirror)
+    U = Ma * sound_speed(gamma, T0)
+    mu = 1.0 * U * D / Re
+    dt = smallest_patch_reach(mesh) / (3.0 * np.sqrt(2.0))
+    fluid = FluidParams(gamma=gamma, Pr=Pr, mu=mu, rho_inf=1.0, T_inf=T0, u_inf=(U, 0.0), dt=dt,
+                        storage=storage)
+    body = BodyParams(dof=DOF_FIXED, center=(0.0, 0.0), ea=(0.0, 0.0), r_rigid=0.5 * D,
+                      r_blend=D)
+    R = 0.5 * D
+    r = np.hypot(mesh.X, mesh.Y)
+    c, s = mesh.X / r, mesh.Y / r
+    a = (R / r) ** 2
+    layer = np.tanh(np.maximum(r - R, 0.0) / (D / 8.0))
+    ur = U * (1.0 - a) * c
+    ut = -U * (1.0 + a) * s
+    ux = (ur * c - ut * s) * layer
+    uy = (ur * s + ut * c) * layer
+    N = mesh.n_nodes
+    return mesh, fluid, body, (np.ones(N), ux, uy, np.full(N, T0))

@@ -1,0 +1,121 @@
+"""Oracle pins for the step on an unstructured 9-node mesh round a fixed
+cylinder: the mesh (annulus tiled, wall and far-field nodes on their
+polygons, clockwise wall), missing populations at the wall exactly those
+arriving from inside the body, the points B, gas at rest kept at rest with
+zero force, and exact mirror symmetry (zero lift) of the flow past the body
+on a mesh that is its own mirror image."""
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from oracle import lattice as L
+from oracle.unstructured import UGrid, UnstructuredWallSolver, shape
+from synth.configs import BodyParams, FluidParams
+from synth.unstructured import (cylinder_q9_mesh, element_coords, q9_cylinder_case,
+                                smallest_patch_reach)
+
+
+@pytest.fixture(scope="module")
+def mesh():
+    return cylinder_q9_mesh(32, 40.0, 6.0, seed=1)
+
+
+def polygon_area(x, y):
+    return 0.5 * np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y)
+
+
+def test_annulus_mesh(mesh):
+    ex, ey = element_coords(mesh)
+    x, y = ex[:, :4], ey[:, :4]
+    area = 0.5 * np.sum(x * np.roll(y, -1, axis=1) - np.roll(x, -1, axis=1) * y, axis=1)
+    assert np.all(area > 0)
+    w, f = mesh.wall_nodes, mesh.far_nodes
+    # the wall polygon is clockwise, the elements tile the region between it
+    # and the outer polygon
+    aw = polygon_area(mesh.X[w], mesh.Y[w])
+    order = np.argsort(np.arctan2(mesh.Y[f], mesh.X[f]))
+    af = polygon_area(mesh.X[f][order], mesh.Y[f][order])
+    assert aw < 0
+    assert abs(area.sum() - (af + aw)) < 1e-9 * af
+    # wall nodes on the chords between the grid's wall points (radius R)
+    R = 20.0
+    r = np.hypot(mesh.X[w], mesh.Y[w])
+    assert np.max(r) <= R + 1e-12 and np.min(r) > R * np.cos(np.pi / 32) - 1e-12
+    # every boundary edge of the mesh joins two wall or two far-field nodes
+    edges = {}
+    for e in mesh.elems:
+        for a, b, m in ((0, 1, 4), (1, 2, 5), (2, 3, 6), (3, 0, 7)):
+            k = (min(e[a], e[b]), max(e[a], e[b]))
+            edges[k] = edges.get(k, 0) + 1
+    bnd = set(w.tolist()) | set(f.tolist())
+    for (a, b), c in edges.items():
+        if c == 1:
+            assert a in bnd and b in bnd
+    assert len(set(w.tolist()) & set(f.tolist())) == 0
+
+
+def test_missing_populations_come_from_inside_the_body(mesh):
+    dt = smallest_patch_reach(mesh) / (3 * np.sqrt(2))
+    fl = FluidParams(gamma=1.4, Pr=0.71, mu=0.05, rho_inf=1.0, T_inf=1 / 3, u_inf=(0, 0), dt=dt)
+    o = UnstructuredWallSolver(mesh, fl, BodyParams(dof=3))
+    w = o.wall
+    wall_set = np.zeros(o.grid.N, dtype=bool)
+    wall_set[w] = True
+    bnd = wall_set.copy()
+    bnd[o.far] = True
+    # chord-interior wall nodes (not on the circle): missing exactly when the
+    # direction points out of the body, c . n > 0
+    on_chord = np.hypot(mesh.X[w], mesh.Y[w]) < 20.0 - 1e-9
+    nx, ny = o.nds_x / np.hypot(o.nds_x, o.nds_y), o.nds_y / np.hypot(o.nds_x, o.nds_y)
+    checked = 0
+    for i in range(1, L.Q):
+        miss = o.missing(i)
+        assert not np.any(miss & ~bnd)
+        cn = L.CX[i] * nx + L.CY[i] * ny
+        sel = on_chord & (np.abs(cn) > 1e-6)
+        assert np.array_equal(miss[w][sel], cn[sel] > 0)
+        checked += sel.sum()
+    assert checked > 100
+
+
+def test_points_B_are_located(mesh):
+    dt = smallest_patch_reach(mesh) / (3 * np.sqrt(2))
+    fl = FluidParams(gamma=1.4, Pr=0.71, mu=0.05, rho_inf=1.0, T_inf=1 / 3, u_inf=(0, 0), dt=dt)
+    o = UnstructuredWallSolver(mesh, fl, BodyParams(dof=3))
+    e, xi, eta = o.B
+    assert np.all(e >= 0) and np.all(np.abs(xi) <= 1 + 1e-12) and np.all(np.abs(eta) <= 1 + 1e-12)
+    nn = np.hypot(o.nds_x, o.nds_y)
+    Bx = o.xw + dt * o.nds_x / nn
+    By = o.yw + dt * o.nds_y / nn
+    # the 9-node map (exact for the straight-sided elements) returns B
+    N = shape(xi, eta)
+    ex, ey = element_coords(mesh)
+    assert np.max(np.abs(np.sum(N.T * ex[e], axis=1) - Bx)) < 1e-10
+    assert np.max(np.abs(np.sum(N.T * ey[e], axis=1) - By)) < 1e-10
+
+
+def test_gas_at_rest_stays_at_rest_with_zero_force(mesh):
+    dt = smallest_patch_reach(mesh) / (3 * np.sqrt(2))
+    fl = FluidParams(gamma=1.4, Pr=0.71, mu=0.05, rho_inf=1.0, T_inf=1 / 3, u_inf=(0, 0), dt=dt)
+    o = UnstructuredWallSolver(mesh, fl, BodyParams(dof=3))
+    f0, g0 = o.f.copy(), o.g.copy()
+    o.run(20)
+    assert np.max(np.abs(o.f - f0)) < 1e-13 and np.max(np.abs(o.g - g0)) < 1e-13
+    h = np.array(o.history)
+    scale = (1 / 3) * np.pi * 40.0
+    assert np.max(np.abs(h[:, 1:4])) < 1e-12 * scale * 20.0
+
+
+def test_flow_past_the_body_is_mirror_symmetric_with_zero_lift():
+    m, fl, b, (rho, ux, uy, T) = q9_cylinder_case(mirror=True)
+    _, mm = cKDTree(np.c_[m.X, m.Y]).query(np.c_[m.X, -m.Y])
+    o = UnstructuredWallSolver(m, fl, b, rho, ux, uy, T)
+    o.run(100)
+    r, u, v, E, Tt = o.macroscopic()
+    assert np.max(np.abs(r - r[mm])) < 1e-12 and np.max(np.abs(v + v[mm])) < 1e-12
+    h = np.array(o.history)
+    assert h[-1, 1] > 0.1                              # drag in the stream
+    assert np.max(np.abs(h[:, 2])) < 1e-11 * h[-1, 1]  # no lift
+    # a developed, non-uniform flow
+    assert np.max(np.abs(r - 1.0)) > 1e-4
