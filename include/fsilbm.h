@@ -111,9 +111,21 @@ typedef struct {
  *              be 2).  Junction copies merge and slit copies are kept
  *              single-valued as on a C-grid.
  *   Q9:        unstructured mesh of 9-node quadrilateral elements (the
- *              paper's own discretisation, Sec. II.B), static and periodic
- *              (period shift_i[0] along x, shift_j[1] along y); no wall, no
- *              far field, no body.  ni = number of nodes, nj = 1; X holds the
+ *              paper's own discretisation, Sec. II.B), static: periodic
+ *              (period shift_i[0] along x, shift_j[1] along y, shifts used by
+ *              `elem_shifts`), or bounded, round one fixed body
+ *              (FSI_DOF_FIXED): `wall_nodes` the body polygon, clockwise (a
+ *              +90 degree rotation of its tangent points into the fluid),
+ *              `far_nodes` the outer boundary.  A boundary node's population
+ *              whose departure point lies in none of the node's elements is
+ *              missing: far-field nodes take the free-stream equilibrium, wall
+ *              nodes Grad's populations (u = 0; rho, T interpolated at
+ *              B = x + dt n in the element of the node that holds it, the
+ *              wall nodes there at their previous values; gradients by the
+ *              nodal finite-element derivative with the wall nodes at their
+ *              targets).  The force is sigma . (n ds) summed over the wall
+ *              polygon, (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2, the moment
+ *              about the body's `ea`.  ni = number of nodes, nj = 1; X holds the
  *              node coordinates; `elems` [n_elems][9] the nodes of each
  *              element in the order corners (-1,-1), (1,-1), (1,1), (-1,1),
  *              edge midpoints (0,-1), (1,0), (0,1), (-1,0), centre (0,0),
@@ -148,6 +160,10 @@ typedef struct {
     int n_elems;            /* Q9 only: elements */
     const int32_t *elems;   /* Q9 only: host, [n_elems][9] node indices; copied */
     const int8_t *elem_shifts;  /* Q9 only: host, [n_elems][9][2] periods (-1, 0, 1); copied */
+    int n_wall_nodes;       /* Q9 only: nodes of the body's wall polygon (0: no body) */
+    const int32_t *wall_nodes;  /* Q9 only: host, [n_wall_nodes], clockwise round the body; copied */
+    int n_far_nodes;        /* Q9 only: nodes of the outer boundary (0: periodic mesh) */
+    const int32_t *far_nodes;   /* Q9 only: host, [n_far_nodes]; copied */
 } fsi_mesh_desc;
 
 /* Rigid-body degrees of freedom (Sec. IV). */

@@ -35,6 +35,12 @@ struct fsi_ctx {
     std::vector<int> bh_off, bh_nodes, be_off, be_elem;
     std::vector<uint16_t> be_nodes, uself;
     int u_hmax = 0, u_lemax = 0;
+    // unstructured meshes round a fixed body
+    std::vector<uint8_t> qflag;
+    std::vector<int> qw_nodes, qw_idx, qf_nodes, qw_eB;
+    std::vector<double4> qw_geo;
+    std::vector<float2> qw_xyB;
+    std::vector<double> ecoord;     // [E][9][2] unwrapped FP64 element node coordinates
     hipStream_t stream = nullptr;
     int n_sub = 1;                  // coupling sub-iterations per step
     double relax = 1.0;
@@ -46,7 +52,8 @@ struct fsi_ctx {
            off_resid = 0, off_elems = 0, off_erel = 0, off_poff = 0, off_pent = 0, off_uq = 0,
            off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0,
            off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
-           off_uself = 0, off_dep_le = 0, total = 0;
+           off_uself = 0, off_dep_le = 0, off_qflag = 0, off_qw = 0, off_qwidx = 0, off_qf = 0,
+           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
     std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
@@ -282,12 +289,90 @@ void build_q9_blocks(fsi_ctx *c) {
     c->u_lemax = lemax;
 }
 
+// Local coordinates (xi, eta) of the point at offset (px, py) from local node
+// a of element e under the element's corner (first-order) map, by Newton in
+// FP64 from the node's own position; false if the point is not in the element.
+bool q9_locate_fp64(const fsi_ctx *c, int e, int a, double px, double py, double &xi, double &eta) {
+    const int lp[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0}, lq[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
+    const double *xy = c->ecoord.data() + 18 * (size_t)e;
+    double cx[4], cy[4];
+    for (int k = 0; k < 4; ++k) {
+        cx[k] = xy[2 * k] - xy[2 * a];
+        cy[k] = xy[2 * k + 1] - xy[2 * a + 1];
+    }
+    double u = lp[a], v = lq[a];
+    for (int it = 0; it < 40; ++it) {
+        const double n0 = (1 - u) * (1 - v), n1 = (1 + u) * (1 - v), n2 = (1 + u) * (1 + v), n3 = (1 - u) * (1 + v);
+        const double rx = 0.25 * (n0 * cx[0] + n1 * cx[1] + n2 * cx[2] + n3 * cx[3]) - px;
+        const double ry = 0.25 * (n0 * cy[0] + n1 * cy[1] + n2 * cy[2] + n3 * cy[3]) - py;
+        const double ja = 0.25 * (-(1 - v) * cx[0] + (1 - v) * cx[1] + (1 + v) * cx[2] - (1 + v) * cx[3]);
+        const double jb = 0.25 * (-(1 - u) * cx[0] - (1 + u) * cx[1] + (1 + u) * cx[2] + (1 - u) * cx[3]);
+        const double jc = 0.25 * (-(1 - v) * cy[0] + (1 - v) * cy[1] + (1 + v) * cy[2] - (1 + v) * cy[3]);
+        const double jd = 0.25 * (-(1 - u) * cy[0] - (1 + u) * cy[1] + (1 + u) * cy[2] + (1 - u) * cy[3]);
+        const double det = ja * jd - jb * jc;
+        const double du = (jd * rx - jb * ry) / det, dv = (-jc * rx + ja * ry) / det;
+        u -= du;
+        v -= dv;
+        if (fabs(du) + fabs(dv) < 1e-14) break;
+    }
+    xi = u;
+    eta = v;
+    return fabs(u) <= 1.0 + 1e-12 && fabs(v) <= 1.0 + 1e-12;
+}
+
+// The body on a Q9 mesh: one fixed body with the mesh's wall polygon; the
+// lumped normals (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2, the moment arms and
+// the points B = x + dt n located in the wall node's elements (FP64).
+fsi_status q9_wall_geometry(fsi_ctx *c) {
+    const int nw = (int)c->qw_nodes.size();
+    if ((int)c->bodies.size() != (nw > 0 ? 1 : 0))
+        return fail(c, FSI_E_ARG, nw > 0 ? "a Q9 mesh with a wall polygon carries one body"
+                                         : "a Q9 mesh without a wall polygon carries no body");
+    c->qw_geo.clear();
+    c->qw_eB.clear();
+    c->qw_xyB.clear();
+    c->n_seg = 0;
+    if (nw == 0) return FSI_OK;
+    const fsi_body_desc &b = c->bodies[0];
+    if (b.dof != FSI_DOF_FIXED || b.link >= 0)
+        return fail(c, FSI_E_ARG, "a body on a Q9 mesh is fixed (FSI_DOF_FIXED, no link)");
+    const double dt = c->fluid.dt;
+    for (int k = 0; k < nw; ++k) {
+        const int v = c->qw_nodes[k], vm = c->qw_nodes[(k + nw - 1) % nw], vp = c->qw_nodes[(k + 1) % nw];
+        const double x = c->X[2 * (size_t)v], y = c->X[2 * (size_t)v + 1];
+        const double nx = -0.5 * (c->X[2 * (size_t)vp + 1] - c->X[2 * (size_t)vm + 1]);
+        const double ny = 0.5 * (c->X[2 * (size_t)vp] - c->X[2 * (size_t)vm]);
+        c->qw_geo.push_back(make_double4(nx, ny, x - b.ea[0], y - b.ea[1]));
+        const double nn = sqrt(nx * nx + ny * ny);
+        if (!(nn > 0)) return fail(c, FSI_E_MESH, "degenerate Q9 wall polygon at wall node " + std::to_string(k));
+        int eB = -1;
+        double xi = 0, eta = 0;
+        for (int q = c->patch_off[v]; q < c->patch_off[v + 1] && eB < 0; ++q) {
+            const int ent = c->patch_ent[q];
+            if (q9_locate_fp64(c, ent >> 4, ent & 15, dt * nx / nn, dt * ny / nn, xi, eta)) eB = ent >> 4;
+        }
+        if (eB < 0)
+            return fail(c, FSI_E_MESH, "point B of Q9 wall node " + std::to_string(k) +
+                                       " lies outside its elements (is the wall clockwise?)");
+        c->qw_eB.push_back(eB);
+        c->qw_xyB.push_back(make_float2((float)xi, (float)eta));
+    }
+    c->n_seg = 1;
+    c->seg_i0[0] = 0;
+    c->seg_n[0] = nw;
+    c->seg_dup[0] = 0;
+    return FSI_OK;
+}
+
 fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
     const int N = c->ni, E = mesh->n_elems;
     if (E < 1 || !mesh->elems || !mesh->elem_shifts)
         return fail(c, FSI_E_MESH, "Q9 mesh needs n_elems >= 1, elems and elem_shifts");
     const double Lx = c->shift_i[0], Ly = c->shift_j[1];
-    if (!(Lx > 0) || !(Ly > 0)) return fail(c, FSI_E_MESH, "Q9 mesh needs periods shift_i[0], shift_j[1] > 0");
+    bool shifted = false;
+    for (size_t q = 0; q < 18 * (size_t)E; ++q) shifted = shifted || mesh->elem_shifts[q] != 0;
+    if (shifted && (!(Lx > 0) || !(Ly > 0)))
+        return fail(c, FSI_E_MESH, "a Q9 mesh with element shifts needs periods shift_i[0], shift_j[1] > 0");
     c->n_elems = E;
     c->elems.assign(mesh->elems, mesh->elems + 9 * (size_t)E);
     std::vector<int> count(N, 0);
@@ -301,6 +386,29 @@ fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
         }
     for (int v = 0; v < N; ++v)
         if (!count[v]) return fail(c, FSI_E_MESH, "Q9 node " + std::to_string(v) + " belongs to no element");
+    // boundary nodes
+    c->qflag.assign(N, 0);
+    c->qw_idx.assign(N, -1);
+    c->qw_nodes.clear();
+    c->qf_nodes.clear();
+    if (mesh->n_wall_nodes < 0 || mesh->n_far_nodes < 0 || (mesh->n_wall_nodes > 0 && !mesh->wall_nodes) ||
+        (mesh->n_far_nodes > 0 && !mesh->far_nodes))
+        return fail(c, FSI_E_MESH, "Q9 boundary node lists missing");
+    if (mesh->n_wall_nodes > 0 && mesh->n_wall_nodes < 3)
+        return fail(c, FSI_E_MESH, "a Q9 wall polygon needs at least 3 nodes");
+    for (int q = 0; q < mesh->n_wall_nodes + mesh->n_far_nodes; ++q) {
+        const bool wall = q < mesh->n_wall_nodes;
+        const int v = wall ? mesh->wall_nodes[q] : mesh->far_nodes[q - mesh->n_wall_nodes];
+        if (v < 0 || v >= N || c->qflag[v])
+            return fail(c, FSI_E_MESH, "Q9 boundary node out of range or listed twice");
+        c->qflag[v] = wall ? 1 : 2;
+        if (wall) {
+            c->qw_idx[v] = q;
+            c->qw_nodes.push_back(v);
+        } else {
+            c->qf_nodes.push_back(v);
+        }
+    }
     // patches in element order
     c->patch_off.assign(N + 1, 0);
     for (int v = 0; v < N; ++v) c->patch_off[v + 1] = c->patch_off[v] + count[v];
@@ -312,12 +420,15 @@ fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
     const int lp[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0}, lq[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
     auto dl = [](int p, int x) { return p < 0 ? x - 0.5 : (p == 0 ? -2.0 * x : x + 0.5); };
     c->erel.assign(9 * (size_t)E, make_float2(0, 0));
+    c->ecoord.assign(18 * (size_t)E, 0.0);
     for (int e = 0; e < E; ++e) {
         double x[9], y[9];
         for (int a = 0; a < 9; ++a) {
             const int v = c->elems[9 * (size_t)e + a];
             x[a] = c->X[2 * (size_t)v] + mesh->elem_shifts[18 * (size_t)e + 2 * a] * Lx;
             y[a] = c->X[2 * (size_t)v + 1] + mesh->elem_shifts[18 * (size_t)e + 2 * a + 1] * Ly;
+            c->ecoord[18 * (size_t)e + 2 * a] = x[a];
+            c->ecoord[18 * (size_t)e + 2 * a + 1] = y[a];
         }
         for (int a = 0; a < 9; ++a) c->erel[9 * (size_t)e + a] = make_float2((float)(x[a] - x[8]), (float)(y[a] - y[8]));
         // edge and centre nodes on the corners' bilinear map
@@ -669,6 +780,14 @@ void layout(fsi_ctx *c) {
         c->off_upost = take(16 * N * sizeof(float));
         c->off_dep_e = take(8 * N * 4);
         c->off_dep_xy = take(8 * N * sizeof(float2));
+        c->off_qflag = take(N);
+        c->off_qwidx = take(N * 4);
+        c->off_qw = take(c->qw_nodes.size() * 4);
+        c->off_qf = take(c->qf_nodes.size() * 4);
+        c->off_qwgeo = take(c->qw_geo.size() * sizeof(double4));
+        c->off_qweB = take(c->qw_eB.size() * 4);
+        c->off_qwxyB = take(c->qw_xyB.size() * sizeof(float2));
+        c->off_qwprev = take(c->qw_nodes.size() * sizeof(float2));
         if (!c->bh_off.empty()) {
             c->off_bh_off = take(c->bh_off.size() * 4);
             c->off_bh_nodes = take(c->bh_nodes.size() * 4);
@@ -700,6 +819,9 @@ fsi_status enqueue_fluid(fsi_ctx *c) {
         HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, st,
                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
                                             c->inst.u_hmax, c->inst.u_lemax, c->stream));
+        if (!c->qw_nodes.empty() || !c->qf_nodes.empty())
+            HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(),
+                                                         (int)c->qf_nodes.size(), st, 1, c->stream));
         return FSI_OK;
     }
     if (!c->wk0.empty())
@@ -735,8 +857,12 @@ fsi_status enqueue_step(fsi_ctx *c) {
 fsi_status enqueue_load_update(fsi_ctx *c) {
     // unstructured meshes: the moments the next step's correction starts from
     // (each step's interpolation forms them for the populations it writes)
-    if (c->topo == FSI_TOPO_Q9)
+    if (c->topo == FSI_TOPO_Q9) {
         HIP_TRY(c, fsi::launch_unstructured_moments(d_inst(c), (long long)c->ni, c->fluid.storage, c->stream));
+        if (!c->qw_nodes.empty())
+            HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(), 0,
+                                                         c->fluid.storage, 0, c->stream));
+    }
     if (c->has_wall)
         HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
                                                reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
@@ -813,7 +939,7 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
     if (c->topo == FSI_TOPO_Q9 ? (c->ni < 9 || c->nj != 1) : (c->ni < 8 || c->nj < 8))
         return fail(c, FSI_E_ARG, c->topo == FSI_TOPO_Q9 ? "a Q9 mesh has ni = nodes >= 9 and nj = 1"
                                                          : "mesh needs ni >= 8 and nj >= 8");
-    if (c->topo == FSI_TOPO_Q9 && nbodies != 0) return fail(c, FSI_E_ARG, "a Q9 mesh carries no body");
+    if (c->topo == FSI_TOPO_Q9 && nbodies > 1) return fail(c, FSI_E_ARG, "a Q9 mesh carries at most one body");
     if (c->topo == FSI_TOPO_TWIN ? nbodies != fsi::MAX_BODIES : (nbodies < 0 || nbodies > 1))
         return fail(c, FSI_E_ARG, c->topo == FSI_TOPO_TWIN ? "a twin O-grid carries 2 bodies"
                                                            : "nbodies must be 0 or 1");
@@ -842,6 +968,8 @@ fsi_status fsi_create(const fsi_fluid_params *fluid, const fsi_mesh_desc *mesh,
     }
     if (c->topo == FSI_TOPO_Q9) {
         fsi_status sq = validate_q9(c, mesh);
+        if (sq != FSI_OK) return sq;
+        sq = q9_wall_geometry(c);
         if (sq != FSI_OK) return sq;
     }
     fsi_status st = validate_and_precompute(c);
@@ -903,6 +1031,30 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                                   hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_pent, c->patch_ent.data(), c->patch_ent.size() * 4,
                                   hipMemcpyHostToDevice, c->stream));
+        P.n_qw = (int)c->qw_nodes.size();
+        P.n_qf = (int)c->qf_nodes.size();
+        P.qflag = reinterpret_cast<const uint8_t *>(c->ws + c->off_qflag);
+        P.qw_idx = reinterpret_cast<const int *>(c->ws + c->off_qwidx);
+        P.qw_nodes = reinterpret_cast<const int *>(c->ws + c->off_qw);
+        P.qf_nodes = reinterpret_cast<const int *>(c->ws + c->off_qf);
+        P.qw_geo = reinterpret_cast<const double4 *>(c->ws + c->off_qwgeo);
+        P.qw_eB = reinterpret_cast<const int *>(c->ws + c->off_qweB);
+        P.qw_xyB = reinterpret_cast<const float2 *>(c->ws + c->off_qwxyB);
+        P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
+        {
+            const std::pair<size_t, std::pair<const void *, size_t>> up[] = {
+                {c->off_qflag, {c->qflag.data(), c->qflag.size()}},
+                {c->off_qwidx, {c->qw_idx.data(), c->qw_idx.size() * 4}},
+                {c->off_qw, {c->qw_nodes.data(), c->qw_nodes.size() * 4}},
+                {c->off_qf, {c->qf_nodes.data(), c->qf_nodes.size() * 4}},
+                {c->off_qwgeo, {c->qw_geo.data(), c->qw_geo.size() * sizeof(double4)}},
+                {c->off_qweB, {c->qw_eB.data(), c->qw_eB.size() * 4}},
+                {c->off_qwxyB, {c->qw_xyB.data(), c->qw_xyB.size() * sizeof(float2)}}};
+            for (const auto &u : up)
+                if (u.second.second)
+                    HIP_TRY(c, hipMemcpyAsync(c->ws + u.first, u.second.first, u.second.second,
+                                              hipMemcpyHostToDevice, c->stream));
+        }
         P.u_nblk = c->bh_off.empty() ? 0 : (int)c->bh_off.size() - 1;
         P.u_hmax = c->u_hmax;
         P.u_lemax = c->u_lemax;

@@ -129,6 +129,16 @@ struct Inst {
     const uint16_t *be_nodes; // [.][16] their nine nodes as halo positions (7 unused)
     const uint16_t *uself;    // [n_nodes] each node's own position in its block's halo
     uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
+    // unstructured meshes round a fixed body: wall and far-field nodes
+    int n_qw, n_qf;
+    const uint8_t *qflag;     // [n_nodes] 1 wall node, 2 far-field node, 0 interior
+    const int *qw_nodes;      // [n_qw] wall polygon, clockwise
+    const int *qw_idx;        // [n_nodes] position in qw_nodes, -1 elsewhere
+    const int *qf_nodes;      // [n_qf]
+    const double4 *qw_geo;    // [n_qw] (n ds)_x, (n ds)_y, x - x_ea, y - y_ea
+    const int *qw_eB;         // [n_qw] element holding the point B
+    const float2 *qw_xyB;     // [n_qw] local coordinates of B there
+    float2 *qw_prev;          // [n_qw] (rho, T) of the completed wall node, previous level
 };
 
 // nodes per block of the LDS-staged interpolation
@@ -158,6 +168,10 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
                                hipStream_t s);
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s);
 hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int storage, hipStream_t s);
+// far field, wall targets, Grad populations and traction (phase 1), or
+// traction and wall values of the current level only (phase 0)
+hipError_t launch_unstructured_boundary(const Inst *inst, int n_wall, int n_far, int storage, int phase,
+                                        hipStream_t s);
 hipError_t launch_init_equilibrium(const Inst *inst, const double *macro, long long n_nodes,
                                    int storage, hipStream_t s);
 hipError_t launch_dump_macro(const Inst *inst, int side, double *out, long long n_nodes, int storage,

@@ -18,6 +18,7 @@
 // mesh displacements, the traction sum and the body ODE are FP64; coordinate
 // differences are formed in FP64 and only then rounded to FP32.
 #include "fsilbm_device.h"
+#include "fsilbm_wall.h"
 
 namespace fsi {
 
@@ -910,40 +911,8 @@ __device__ void grad_fill(const Inst &P, const void *buf, const BodySlot *sL, in
     grad(tm.z, uy_t, tp.z, m1.uy, m2.uy, duyx, duyy);
     grad(tm.w, T_t, tp.w, m1.T, m2.T, dTx, dTy);
     grad(Em, E_t, Ep, E1, E2, dEx, dEy);
-    const float aa = P.mu / (rho_t * T_t * dt);
-    const float omega = 1.0f / (aa + 0.5f);
-    const float omega1 = 1.0f / (aa / P.Pr + 0.5f);
-    // S = grad u + grad u^T, (grad u)_ab = d_a u_b
-    const float Sxx = 2.0f * duxx, Syy = 2.0f * duyy, Sxy = duxy + duyx;
-    const float div = duxx + duyy;
-    const float pref = -rho_t * T_t / omega;
-    const float P1xx = pref * (Sxx - div / Cv);
-    const float P1yy = pref * (Syy - div / Cv);
-    const float P1xy = pref * Sxy;
-    const float q1x = -(2.0f / omega1) * rho_t * Cp * T_t * dTx + 2.0f * (ux_t * P1xx + uy_t * P1xy);
-    const float q1y = -(2.0f / omega1) * rho_t * Cp * T_t * dTy + 2.0f * (ux_t * P1xy + uy_t * P1yy);
-    const float rpref = -(2.0f / omega1) * rho_t * T_t;
-    const float e2 = E_t + 2.0f * T_t;
-    const float R1xx = rpref * (Sxx * e2 + 2.0f * ux_t * dEx);
-    const float R1yy = rpref * (Syy * e2 + 2.0f * uy_t * dEy);
-    const float R1xy = rpref * (Sxy * e2 + ux_t * dEy + uy_t * dEx);
-    float feq[9], geq[9];
-    equilibria<float>(rho_t, ux_t, uy_t, T_t, E_t, feq, geq);
-    const float w[3] = {0.5f * T_t, 1.0f - T_t, 0.5f * T_t};
-    const float invT = 1.0f / T_t, inv2T2 = 0.5f * invT * invT;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        if (!(miss & (1u << k))) continue;
-        const int cx = CXK(k), cy = CYK(k);
-        const float W = w[cx + 1] * w[cy + 1];
-        const float ccx = (float)(cx * cx) - T_t, ccy = (float)(cy * cy) - T_t;
-        const float cxy = 2.0f * (float)(cx * cy);
-        const float fneq = W * (P1xx * ccx + P1yy * ccy + P1xy * cxy) * inv2T2;
-        const float gneq = W * ((q1x * (float)cx + q1y * (float)cy) * invT +
-                                (R1xx * ccx + R1yy * ccy + R1xy * cxy) * inv2T2);
-        f[k] = feq[k] + dt * fneq;
-        g[k] = geq[k] + dt * gneq;
-    }
+    grad_populations(P, miss, rho_t, ux_t, uy_t, T_t, E_t, duxx, duxy, duyx, duyy, dTx, dTy, dEx, dEy,
+                     f, g);
 }
 
 // Grad populations for the missing wall populations (phase 1 only) and the
@@ -1019,44 +988,14 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
     node_pos(P, fm, sL, xm, ym);
     node_pos(P, fp, sL, xp, yp);
     node_pos(P, ig, sL, x0, y0);
-    const float Cv = P.Cv;
-    double fd[9], gd[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        fd[k] = f[k];
-        gd[k] = g[k];
-    }
-    double rho = 0, jx = 0, jy = 0, G = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        rho += fd[k];
-        jx += CXK(k) * fd[k];
-        jy += CYK(k) * fd[k];
-        G += gd[k];
-    }
-    const double ux = jx / rho, uy = jy / rho, E = 0.5 * G / rho;
-    const double T = (E - 0.5 * (ux * ux + uy * uy)) / (double)Cv;
-    double feq[9], geq[9];
-    equilibria<double>(rho, ux, uy, T, E, feq, geq);
-    double Pxx = 0.0, Pyy = 0.0, Pxy = 0.0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const double d = fd[k] - feq[k];
-        const int cx = CXK(k), cy = CYK(k);
-        Pxx += d * (double)(cx * cx);
-        Pyy += d * (double)(cy * cy);
-        Pxy += d * (double)(cx * cy);
-    }
-    const double p = rho * T;
-    const double omega = 1.0 / ((double)P.mu / (p * P.dt_d) + 0.5);
-    const double kk = 1.0 - 0.5 * omega;
-    const double sxx = -p - kk * Pxx, syy = -p - kk * Pyy, sxy = -kk * Pxy;
+    double sxx, sxy, syy;
+    const bool ok = wall_stress(P, f, g, sxx, sxy, syy);
     const double nx = -0.5 * (yp - ym), ny = 0.5 * (xp - xm);
     const double Fx = sxx * nx + sxy * ny;
     const double Fy = sxy * nx + syy * ny;
     const double rx = x0 - P.body[seg].ex, ry = y0 - (P.body[seg].ey + sL[seg].h);
     P.wall_force[ig] = make_double4(Fx, Fy, rx * Fy - ry * Fx, 0.0);
-    if (!state_ok((float)rho, (float)ux, (float)uy, (float)T)) atomicOr(P.err, ERR_STATE);
+    if (!ok) atomicOr(P.err, ERR_STATE);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,6 +2,7 @@
 // elements (Bhadauria, Dorschner & Karlin, arXiv 2107.01370, Sec. II.B on the
 // paper's own second-order finite-element meshes).
 #include "fsilbm_device.h"
+#include "fsilbm_wall.h"
 
 namespace fsi {
 
@@ -30,6 +31,8 @@ namespace fsi {
 // FP32 offsets from each element's centre node (formed in FP64 on the host).
 // ---------------------------------------------------------------------------
 constexpr int U_THREADS = 256;
+// departure element of a missing population (block positions)
+constexpr uint16_t U_MISSING = 0xffff;
 
 // Workgroup slot -> block of consecutive nodes (or elements), so that each of
 // the 8 XCDs takes a contiguous run of blocks (dispatch slot b goes to XCD
@@ -226,6 +229,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
     for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
         const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+        const bool bnd = P.n_qw + P.n_qf > 0 && P.qflag[idx] != 0;
         for (int k = 1; k < 9; ++k) {
             const float dx = -dt * (float)CXK(k), dy = -dt * (float)CYK(k);
             int e_found = -1;
@@ -255,13 +259,17 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
                     eta = v;
                 }
             }
-            if (e_found < 0) {
+            // a boundary node's point outside its elements lies outside the
+            // mesh: the population is missing (set by the boundary kernels)
+            if (e_found < 0 && !bnd) {
                 err |= ERR_CFL;
                 e_found = P.patch_ent[b] >> 4;
             }
             P.dep_e[(k - 1) * P.n_nodes + idx] = e_found;
             P.dep_xy[(k - 1) * P.n_nodes + idx] = make_float2(xi, eta);
-            if (P.be_off) {
+            if (P.be_off && e_found < 0) {
+                P.dep_le[(k - 1) * P.n_nodes + idx] = U_MISSING;
+            } else if (P.be_off) {
                 // its position in the block's ascending element list (it holds
                 // every element of the node's patch)
                 const long long blk = idx / U_BLOCK;
@@ -296,6 +304,10 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
             const int e = P.dep_e[(k - 1) * P.n_nodes + idx];
+            if (e < 0) {                      // missing: the boundary kernels set it
+                f[k] = g[k] = 0.0f;
+                continue;
+            }
             const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
             const float xi = d.x, eta = d.y;
             const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
@@ -385,6 +397,10 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
         const int le = P.dep_le[(k - 1) * P.n_nodes + idx];
+        if (le == U_MISSING) {                // missing: the boundary kernels set it
+            f[k] = g[k] = 0.0f;
+            continue;
+        }
         const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
         const float xi = d.x, eta = d.y;
         const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
@@ -411,6 +427,187 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         g[k] = pop_round<STORE>(P, Q + k, vg);
     }
     u_node_moments(P, idx, f, g);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary of a bounded Q9 mesh round a fixed body (Sec. III.A, III):
+//   k_u_far           far-field nodes: free-stream equilibrium
+//   k_u_wall_targets  rho, T at B (9-node interpolation in the element that
+//                     holds B; wall nodes there at their previous values)
+//   k_u_wall          Grad populations for the missing ones (gradients by the
+//                     nodal finite-element derivative, wall nodes at their
+//                     targets), moments for the next step, traction, and the
+//                     wall node's (rho, T) for the next step's targets
+// One thread per boundary node; run after the interpolation.
+// ---------------------------------------------------------------------------
+constexpr int U_BND = 64;
+
+template <int STORE>
+__global__ void __launch_bounds__(U_BND) k_u_far(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const int k = blockIdx.x * U_BND + threadIdx.x;
+    if (k >= P.n_qf) return;
+    const long long n = *P.step;
+    void *dst = P.pop[(n + 1) & 1];
+    const long long v = P.qf_nodes[k];
+    const float T = P.T_inf, ux = P.ux_inf, uy = P.uy_inf;
+    const float E = P.Cv * T + 0.5f * (ux * ux + uy * uy);
+    float f[9], g[9];
+    equilibria<float>(P.rho_inf, ux, uy, T, E, f, g);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        pop_store<STORE>(P, dst, q, v, f[q]);
+        pop_store<STORE>(P, dst, Q + q, v, g[q]);
+        f[q] = pop_round<STORE>(P, q, f[q]);
+        g[q] = pop_round<STORE>(P, Q + q, g[q]);
+    }
+    u_node_moments(P, v, f, g);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_BND) k_u_wall_targets(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const int k = blockIdx.x * U_BND + threadIdx.x;
+    if (k >= P.n_qw) return;
+    const long long n = *P.step;
+    const void *dst = P.pop[(n + 1) & 1];
+    const int e = P.qw_eB[k];
+    const float2 B = P.qw_xyB[k];
+    const float lx[3] = {0.5f * B.x * (B.x - 1.0f), 1.0f - B.x * B.x, 0.5f * B.x * (B.x + 1.0f)};
+    const float ly[3] = {0.5f * B.y * (B.y - 1.0f), 1.0f - B.y * B.y, 0.5f * B.y * (B.y + 1.0f)};
+    float rho_t = 0.0f, T_t = 0.0f;
+    for (int s = 0; s < 9; ++s) {
+        const long long v = P.elems[9 * (long long)e + s];
+        const int wi = P.qw_idx[v];
+        float r, T;
+        if (wi >= 0) {
+            const float2 pv = P.qw_prev[wi];
+            r = pv.x;
+            T = pv.y;
+        } else {
+            float f[9], g[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                f[q] = pop_load<STORE>(P, dst, q, v);
+                g[q] = pop_load<STORE>(P, dst, Q + q, v);
+            }
+            const Moments m = moments(f, g, P.Cv);
+            r = m.rho;
+            T = m.T;
+        }
+        const float w = lx[q9_p(s) + 1] * ly[q9_q(s) + 1];
+        rho_t += w * r;
+        T_t += w * T;
+    }
+    P.wall_tgt[k] = make_float4(rho_t, 0.0f, 0.0f, T_t);
+}
+
+// (u_x, u_y, T, E) of node v for a wall node's gradient: the target at wall
+// nodes (fixed body: u = 0), the moments of the new populations elsewhere
+template <int STORE>
+__device__ float4 q9_wall_field(const Inst &P, const void *buf, long long v) {
+    const int wi = P.qw_idx[v];
+    if (wi >= 0) {
+        const float T = P.wall_tgt[wi].w;
+        return make_float4(0.0f, 0.0f, T, P.Cv * T);
+    }
+    float f[9], g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        f[q] = pop_load<STORE>(P, buf, q, v);
+        g[q] = pop_load<STORE>(P, buf, Q + q, v);
+    }
+    const Moments m = moments(f, g, P.Cv);
+    return make_float4(m.ux, m.uy, m.T, m.E);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(U_BND) k_u_wall(const Inst *__restrict__ pinst, int phase) {
+    const Inst &P = *pinst;
+    const int k = blockIdx.x * U_BND + threadIdx.x;
+    if (k >= P.n_qw) return;
+    const long long n = *P.step;
+    void *buf = P.pop[(phase ? n + 1 : n) & 1];
+    const long long w = P.qw_nodes[k];
+    float f[9], g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        f[q] = pop_load<STORE>(P, buf, q, w);
+        g[q] = pop_load<STORE>(P, buf, Q + q, w);
+    }
+    unsigned miss = 0;
+    for (int q = 1; q < 9; ++q)
+        if (P.dep_e[(q - 1) * P.n_nodes + w] < 0) miss |= 1u << q;
+    if (phase && miss) {
+        const float4 t0 = P.wall_tgt[k];
+        const float rho_t = t0.x, T_t = t0.w, E_t = P.Cv * T_t;
+        // nodal derivative: mean over the node's elements of the element
+        // derivative at the node (the nodes on its two element lines)
+        float d[4][2] = {};
+        const int b = P.patch_off[w], e_end = P.patch_off[w + 1];
+        for (int q = b; q < e_end; ++q) {
+            const int ent = P.patch_ent[q], e = ent >> 4, a = ent & 15;
+            const int pa = q9_p(a), qa = q9_q(a);
+            const float2 *rel = P.erel + 9 * (long long)e;
+            const int *nodes = P.elems + 9 * (long long)e;
+            const float4 Ca = make_float4(0.0f, 0.0f, T_t, E_t);
+            float ax[4] = {}, ae[4] = {};
+            float xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
+            for (int m = -1; m <= 1; ++m) {
+                if (m != pa) {
+                    const int si = q9_node(m, qa);
+                    const float wt = dlag_at(m, pa);
+                    const float4 C = q9_wall_field<STORE>(P, buf, nodes[si]);
+                    ax[0] += wt * (C.x - Ca.x);
+                    ax[1] += wt * (C.y - Ca.y);
+                    ax[2] += wt * (C.z - Ca.z);
+                    ax[3] += wt * (C.w - Ca.w);
+                    xxi += wt * (rel[si].x - rel[a].x);
+                    yxi += wt * (rel[si].y - rel[a].y);
+                }
+                if (m != qa) {
+                    const int sj = q9_node(pa, m);
+                    const float wt = dlag_at(m, qa);
+                    const float4 C = q9_wall_field<STORE>(P, buf, nodes[sj]);
+                    ae[0] += wt * (C.x - Ca.x);
+                    ae[1] += wt * (C.y - Ca.y);
+                    ae[2] += wt * (C.z - Ca.z);
+                    ae[3] += wt * (C.w - Ca.w);
+                    xeta += wt * (rel[sj].x - rel[a].x);
+                    yeta += wt * (rel[sj].y - rel[a].y);
+                }
+            }
+            const float idet = 1.0f / (xxi * yeta - yxi * xeta);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                d[c][0] += idet * (yeta * ax[c] - yxi * ae[c]);
+                d[c][1] += idet * (-xeta * ax[c] + xxi * ae[c]);
+            }
+        }
+        const float inv = 1.0f / (float)(e_end - b);
+        grad_populations(P, miss, rho_t, 0.0f, 0.0f, T_t, E_t, d[0][0] * inv, d[0][1] * inv,
+                         d[1][0] * inv, d[1][1] * inv, d[2][0] * inv, d[2][1] * inv, d[3][0] * inv,
+                         d[3][1] * inv, f, g);
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+            if (!(miss & (1u << q))) continue;
+            pop_store<STORE>(P, buf, q, w, f[q]);
+            pop_store<STORE>(P, buf, Q + q, w, g[q]);
+            f[q] = pop_round<STORE>(P, q, f[q]);
+            g[q] = pop_round<STORE>(P, Q + q, g[q]);
+        }
+    }
+    if (phase) u_node_moments(P, w, f, g);
+    // traction of the complete wall node; its (rho, T) for the next targets
+    double sxx, sxy, syy;
+    const bool ok = wall_stress(P, f, g, sxx, sxy, syy);
+    const double4 geo = P.qw_geo[k];
+    const double Fx = sxx * geo.x + sxy * geo.y;
+    const double Fy = sxy * geo.x + syy * geo.y;
+    P.wall_force[k] = make_double4(Fx, Fy, geo.z * Fy - geo.w * Fx, 0.0);
+    const Moments m = moments(f, g, P.Cv);
+    P.qw_prev[k] = make_float2(m.rho, m.T);
+    if (!ok) atomicOr(P.err, ERR_STATE);
 }
 
 // ---------------------------------------------------------------------------
@@ -447,6 +644,19 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
     } else {
         FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
         FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unstructured_boundary(const Inst *inst, int n_wall, int n_far, int storage, int phase,
+                                        hipStream_t s) {
+    const dim3 block(U_BND);
+    if (phase && n_far > 0)
+        FSI_DISPATCH(storage, k_u_far, dim3((n_far + U_BND - 1) / U_BND), block, s, inst);
+    if (n_wall > 0) {
+        const dim3 grid((n_wall + U_BND - 1) / U_BND);
+        if (phase) FSI_DISPATCH(storage, k_u_wall_targets, grid, block, s, inst);
+        FSI_DISPATCH(storage, k_u_wall, grid, block, s, inst, phase);
     }
     return hipGetLastError();
 }

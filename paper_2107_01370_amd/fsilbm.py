@@ -52,7 +52,9 @@ class MeshDesc(ctypes.Structure):
                 ("shift_j", ctypes.c_double * 2), ("n_wake", ctypes.c_int),
                 ("n_wall2", ctypes.c_int), ("n_elems", ctypes.c_int),
                 ("elems", ctypes.POINTER(ctypes.c_int32)),
-                ("elem_shifts", ctypes.POINTER(ctypes.c_int8))]
+                ("elem_shifts", ctypes.POINTER(ctypes.c_int8)),
+                ("n_wall_nodes", ctypes.c_int), ("wall_nodes", ctypes.POINTER(ctypes.c_int32)),
+                ("n_far_nodes", ctypes.c_int), ("far_nodes", ctypes.POINTER(ctypes.c_int32))]
 
 
 class BodyDesc(ctypes.Structure):
@@ -176,6 +178,13 @@ def _mesh_struct(mesh):
         md.elems = el.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         md.elem_shifts = sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
         keep = (X, el, sh)
+        for name in ("wall_nodes", "far_nodes"):
+            v = getattr(mesh, name, None)
+            if v is not None and len(v):
+                a = np.ascontiguousarray(v, dtype=np.int32)
+                setattr(md, "n_" + name, a.size)
+                setattr(md, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+                keep = keep + (a,)
     return md, keep
 
 

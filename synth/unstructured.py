@@ -37,8 +37,10 @@ class UnstructuredMesh:
     Y: np.ndarray            # [N] float64
     elems: np.ndarray        # [E, 9] int32 node indices
     shifts: np.ndarray       # [E, 9, 2] int8 periods added to each element node
-    period: tuple            # (Lx, Ly)
+    period: tuple            # (Lx, Ly); (0, 0) for a bounded mesh
     info: dict = field(default_factory=dict)
+    wall_nodes: np.ndarray | None = None   # [n] body polygon, clockwise (bounded meshes)
+    far_nodes: np.ndarray | None = None    # [m] outer boundary (bounded meshes)
 
     @property
     def n_nodes(self) -> int:
@@ -329,14 +331,12 @@ def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, see
     on_wall = np.flatnonzero(keys[:, 1] == 0)
     wall = on_wall[np.argsort(-keys[on_wall, 0], kind="stable")]
     far = np.flatnonzero(keys[:, 1] == 24 * n_r)
-    mesh = UnstructuredMesh(P[:, 0].copy(), P[:, 1].copy(), E.astype(np.int32),
+    return UnstructuredMesh(P[:, 0].copy(), P[:, 1].copy(), E.astype(np.int32),
                             np.zeros((E.shape[0], 9, 2), dtype=np.int8), (0.0, 0.0),
                             info={"kind": "cylinder_q9", "n_theta": n_theta, "n_r": n_r, "D": D,
                                   "far_D": far_D, "seed": seed, "center": tuple(center),
-                                  "mirror": mirror})
-    mesh.wall_nodes = wall.astype(np.int32)
-    mesh.far_nodes = far.astype(np.int32)
-    return mesh
+                                  "mirror": mirror},
+                            wall_nodes=wall.astype(np.int32), far_nodes=far.astype(np.int32))
 
 
 def q9_cylinder_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: int = 1,

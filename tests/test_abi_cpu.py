@@ -368,3 +368,26 @@ def test_q9_mesh_is_accepted_and_validated(F):
     with pytest.raises(F.FsiError) as e:
         F.fsi_batch_create([(fl, mesh, [])])
     assert e.value.status == -1
+
+
+def test_q9_mesh_round_a_body_is_accepted_and_validated(F):
+    from dataclasses import replace as R
+
+    from synth.unstructured import q9_cylinder_case
+    mesh, fl, body, _ = q9_cylinder_case(16, 20.0, 4.0)
+    ctx = F.fsi_create(fl, mesh, [body], None)
+    F.fsi_destroy(ctx)
+    # the wall polygon must run clockwise (its rotated tangent points into the fluid)
+    ccw = R(mesh, wall_nodes=mesh.wall_nodes[::-1].copy())
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(fl, ccw, [body], None)
+    assert e.value.status == -2 and "clockwise" in str(e.value)
+    # one fixed body, and only with a wall polygon
+    for bodies in ([], [R(body, dof=1)], [body, body]):
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_create(fl, mesh, bodies, None)
+        assert e.value.status == -1
+    dup = R(mesh, far_nodes=np.concatenate([mesh.far_nodes, mesh.wall_nodes[:1]]))
+    with pytest.raises(F.FsiError) as e:
+        F.fsi_create(fl, dup, [body], None)
+    assert e.value.status == -2
