@@ -114,6 +114,10 @@ WORKLOADS = {
     "unstructured_q9_1572864": "unstructured periodic mesh of 393,216 nine-node quadrilateral "
                                "elements (1,572,864 nodes, triangles split into quadrilaterals), "
                                "diagonal stream Ma 0.1 with a density pulse",
+    "unstructured_cylinder_q9_2103296": "unstructured mesh of 525,312 nine-node quadrilateral "
+                                        "elements (2,103,296 nodes) round a fixed cylinder (D 640, "
+                                        "far field 8 D), Ma 0.2, Re 1000, Grad wall, free-stream "
+                                        "far field",
 }
 
 
@@ -132,6 +136,8 @@ def workload_case(name: str, storage: int):
         return synth.tandem_cylinders_case(linked=True, h0_frac=0.01, storage=storage)
     if name == "unstructured_q9_1572864":
         return unstructured_case(256, storage)
+    if name == "unstructured_cylinder_q9_2103296":
+        return unstructured_cylinder_case(512, 640.0, storage)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -141,6 +147,15 @@ def unstructured_case(m: int, storage: int):
     mesh, fluid, (rho, ux, uy, T) = unstructured_pulse_case(m, storage=storage)
     return Case(f"unstructured_q9_{mesh.n_nodes}", mesh, fluid, [], rho[None], ux[None], uy[None],
                 T[None])
+
+
+def unstructured_cylinder_case(n_theta: int, D: float, storage: int):
+    from synth.configs import Case
+    from synth.unstructured import q9_cylinder_case
+    mesh, fluid, body, (rho, ux, uy, T) = q9_cylinder_case(n_theta, D, 8.0, seed=1, Ma=0.2,
+                                                          Re=1000.0, storage=storage)
+    return Case(f"unstructured_cylinder_q9_{mesh.n_nodes}", mesh, fluid, [body], rho[None],
+                ux[None], uy[None], T[None])
 
 
 def time_gpu(case, steps: int, warmup: int, kernel_reps: int = 20, subiterations: int = 1,
@@ -270,6 +285,56 @@ def cpu_baseline_unstructured(target_s: float = 20.0, m: int = 48):
     }
     return {"value": mesh.n_nodes * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": sample}, accuracy
+
+
+def cpu_baseline_unstructured_cylinder(target_s: float = 20.0, n_theta: int = 64):
+    """Oracle (plain FP64 NumPy) timed on a smaller mesh of the same
+    construction round the same body shape and physics (n_theta = 64,
+    D = 80), started from the populations the GPU path initialises; returns
+    the timing and the accuracy of the GPU path against it on the same steps."""
+    from oracle.unstructured import UnstructuredWallSolver
+    from paper_2107_01370_amd.fsilbm import Simulation
+
+    case = unstructured_cylinder_case(n_theta, 80.0, 0)
+    mesh, fluid, body = case.mesh, case.fluid, case.bodies[0]
+    rho, ux, uy, T = case.rho[0], case.ux[0], case.uy[0], case.T[0]
+    sim = Simulation(mesh, fluid, [body], device="cuda:0")
+    sim.init_equilibrium(case.rho, case.ux, case.uy, case.T)
+    f0, g0 = sim.populations()
+    ora = UnstructuredWallSolver(mesh, fluid, body, rho, ux, uy, T)
+    ora.f = f0[:, 0, :].astype(np.float64)
+    ora.g = g0[:, 0, :].astype(np.float64)
+    ora.step()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        ora.step()
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or n >= 200:
+            break
+    nsteps = n + 1
+    sim.step(nsteps)
+    r, _, _, Tg = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    hist = sim.forces(0, nsteps)
+    ho = np.array(ora.history)[:nsteps]
+    fscale = float(np.max(np.hypot(ho[:, 1], ho[:, 2])))
+    sim.close()
+    threads = os.environ.get("OMP_NUM_THREADS", "1")
+    accuracy = {
+        "against": "FP64 oracle, same sample as cpu_baseline, from the same initial populations",
+        "steps": nsteps,
+        "rho_max_rel": float(np.max(np.abs(r[0] - r_o) / r_o)),
+        "p_max_rel": float(np.max(np.abs(r[0] * Tg[0] - r_o * T_o) / (r_o * T_o))),
+        "body0": {"drag_max_rel": float(np.max(np.abs(hist[:, 1] - ho[:, 1])) / fscale),
+                  "lift_max_rel": float(np.max(np.abs(hist[:, 2] - ho[:, 2])) / fscale)},
+    }
+    return {"value": mesh.n_nodes * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n} steps of the same construction at n_theta = {n_theta}, D = 80 "
+                      f"({mesh.n_nodes} nodes, {mesh.n_elems} elements) with the same physics, "
+                      f"{el:.1f} s, single-threaded NumPy (OMP_NUM_THREADS={threads}), "
+                      f"os.cpu_count()={os.cpu_count()}"}, accuracy
 
 
 def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
@@ -412,7 +477,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("2 k_u_egrad + k_u_nodeD + k_u_collide + k_u_stream_blk"
+            "kernel": ("2 k_u_egrad + k_u_nodeD + k_u_collide_stream_blk"
                        if args.workload.startswith("unstructured") else "k_collide_stream"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -457,7 +522,8 @@ def main():
         })
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = (
-            cpu_baseline_unstructured() if args.workload.startswith("unstructured")
+            cpu_baseline_unstructured_cylinder() if args.workload.startswith("unstructured_cyl")
+            else cpu_baseline_unstructured() if args.workload.startswith("unstructured")
             else cpu_baseline(case))
     print(json.dumps(out), flush=True)
 
