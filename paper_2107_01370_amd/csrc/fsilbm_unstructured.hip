@@ -438,7 +438,8 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
 //                     nodal finite-element derivative, wall nodes at their
 //                     targets), moments for the next step, traction, and the
 //                     wall node's (rho, T) for the next step's targets
-// One thread per boundary node; run after the interpolation.
+// One thread per far-field node, one wave per wall node; run after the
+// interpolation.
 // ---------------------------------------------------------------------------
 constexpr int U_BND = 64;
 
@@ -464,20 +465,18 @@ __global__ void __launch_bounds__(U_BND) k_u_far(const Inst *__restrict__ pinst)
     u_node_moments(P, v, f, g);
 }
 
+// one wave per wall node: nine lanes fetch the element's node values at once
 template <int STORE>
-__global__ void __launch_bounds__(U_BND) k_u_wall_targets(const Inst *__restrict__ pinst) {
+__global__ void __launch_bounds__(64) k_u_wall_targets(const Inst *__restrict__ pinst) {
+    __shared__ float sv[9][2];
     const Inst &P = *pinst;
-    const int k = blockIdx.x * U_BND + threadIdx.x;
+    const int k = blockIdx.x, t = threadIdx.x;
     if (k >= P.n_qw) return;
     const long long n = *P.step;
     const void *dst = P.pop[(n + 1) & 1];
     const int e = P.qw_eB[k];
-    const float2 B = P.qw_xyB[k];
-    const float lx[3] = {0.5f * B.x * (B.x - 1.0f), 1.0f - B.x * B.x, 0.5f * B.x * (B.x + 1.0f)};
-    const float ly[3] = {0.5f * B.y * (B.y - 1.0f), 1.0f - B.y * B.y, 0.5f * B.y * (B.y + 1.0f)};
-    float rho_t = 0.0f, T_t = 0.0f;
-    for (int s = 0; s < 9; ++s) {
-        const long long v = P.elems[9 * (long long)e + s];
+    if (t < 9) {
+        const long long v = P.elems[9 * (long long)e + t];
         const int wi = P.qw_idx[v];
         float r, T;
         if (wi >= 0) {
@@ -495,9 +494,19 @@ __global__ void __launch_bounds__(U_BND) k_u_wall_targets(const Inst *__restrict
             r = m.rho;
             T = m.T;
         }
-        const float w = lx[q9_p(s) + 1] * ly[q9_q(s) + 1];
-        rho_t += w * r;
-        T_t += w * T;
+        sv[t][0] = r;
+        sv[t][1] = T;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    const float2 B = P.qw_xyB[k];
+    const float lx[3] = {0.5f * B.x * (B.x - 1.0f), 1.0f - B.x * B.x, 0.5f * B.x * (B.x + 1.0f)};
+    const float ly[3] = {0.5f * B.y * (B.y - 1.0f), 1.0f - B.y * B.y, 0.5f * B.y * (B.y + 1.0f)};
+    float rho_t = 0.0f, T_t = 0.0f;
+    for (int s2 = 0; s2 < 9; ++s2) {
+        const float w = lx[q9_p(s2) + 1] * ly[q9_q(s2) + 1];
+        rho_t += w * sv[s2][0];
+        T_t += w * sv[s2][1];
     }
     P.wall_tgt[k] = make_float4(rho_t, 0.0f, 0.0f, T_t);
 }
@@ -521,73 +530,113 @@ __device__ float4 q9_wall_field(const Inst &P, const void *buf, long long v) {
     return make_float4(m.ux, m.uy, m.T, m.E);
 }
 
+// element lines through local node a: the two other nodes along xi (r = 0, 1)
+// and along eta (r = 2, 3), with their derivative weights at a
+__device__ __forceinline__ void wall_line_node(int a, int r, int &s, float &w) {
+    const int pa = q9_p(a), qa = q9_q(a);
+    int cnt = 0;
+    s = a;
+    w = 0.0f;
+    for (int m = -1; m <= 1; ++m) {
+        if (r < 2 && m != pa && cnt++ == r) { s = q9_node(m, qa); w = dlag_at(m, pa); }
+        if (r >= 2 && m != qa && cnt++ == r - 2) { s = q9_node(pa, m); w = dlag_at(m, qa); }
+    }
+}
+
+// one wave per wall node: lanes fetch the line nodes of the node's elements
+// at once (four per element), the element derivatives follow per element, and
+// one lane completes the node
+constexpr int U_WALL_ENT = 16;   // elements of a wall node handled per pass
 template <int STORE>
-__global__ void __launch_bounds__(U_BND) k_u_wall(const Inst *__restrict__ pinst, int phase) {
+__global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, int phase) {
+    __shared__ float4 sval[U_WALL_ENT][4];
+    __shared__ float sder[U_WALL_ENT][4][2];
+    __shared__ float sgrad[4][2];
     const Inst &P = *pinst;
-    const int k = blockIdx.x * U_BND + threadIdx.x;
+    const int k = blockIdx.x, t = threadIdx.x;
     if (k >= P.n_qw) return;
     const long long n = *P.step;
     void *buf = P.pop[(phase ? n + 1 : n) & 1];
     const long long w = P.qw_nodes[k];
+    unsigned miss = 0;
+    for (int q = 1; q < 9; ++q)
+        if (P.dep_e[(q - 1) * P.n_nodes + w] < 0) miss |= 1u << q;
+    const float4 t0 = P.wall_tgt[k];
+    const float T_t = t0.w, E_t = P.Cv * T_t;
+    const bool fill = phase && miss;
+    if (fill) {
+        // nodal derivative: mean over the node's elements of the element
+        // derivative at the node (the nodes on its two element lines), the
+        // wall nodes at their targets
+        const int b = P.patch_off[w], e_end = P.patch_off[w + 1];
+        const float4 Ca = make_float4(0.0f, 0.0f, T_t, E_t);
+        float acc[4][2] = {};
+        for (int base = b; base < e_end; base += U_WALL_ENT) {
+            const int cnt = min(U_WALL_ENT, e_end - base);
+            if (t < 4 * cnt) {
+                const int j = t >> 2, r = t & 3;
+                const int ent = P.patch_ent[base + j], e = ent >> 4, a = ent & 15;
+                int sn;
+                float wt;
+                wall_line_node(a, r, sn, wt);
+                sval[j][r] = q9_wall_field<STORE>(P, buf, P.elems[9 * (long long)e + sn]);
+            }
+            __syncthreads();
+            if (t < cnt) {
+                const int ent = P.patch_ent[base + t], e = ent >> 4, a = ent & 15;
+                const float2 *rel = P.erel + 9 * (long long)e;
+                float ax[4] = {}, ae[4] = {};
+                float xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
+                for (int r = 0; r < 4; ++r) {
+                    int sn;
+                    float wt;
+                    wall_line_node(a, r, sn, wt);
+                    const float4 C = sval[t][r];
+                    const float dC[4] = {C.x - Ca.x, C.y - Ca.y, C.z - Ca.z, C.w - Ca.w};
+                    const float dx = rel[sn].x - rel[a].x, dy = rel[sn].y - rel[a].y;
+                    if (r < 2) {
+                        for (int c = 0; c < 4; ++c) ax[c] += wt * dC[c];
+                        xxi += wt * dx;
+                        yxi += wt * dy;
+                    } else {
+                        for (int c = 0; c < 4; ++c) ae[c] += wt * dC[c];
+                        xeta += wt * dx;
+                        yeta += wt * dy;
+                    }
+                }
+                const float idet = 1.0f / (xxi * yeta - yxi * xeta);
+                for (int c = 0; c < 4; ++c) {
+                    sder[t][c][0] = idet * (yeta * ax[c] - yxi * ae[c]);
+                    sder[t][c][1] = idet * (-xeta * ax[c] + xxi * ae[c]);
+                }
+            }
+            __syncthreads();
+            if (t == 0)
+                for (int j = 0; j < cnt; ++j)
+                    for (int c = 0; c < 4; ++c) {
+                        acc[c][0] += sder[j][c][0];
+                        acc[c][1] += sder[j][c][1];
+                    }
+            __syncthreads();
+        }
+        if (t == 0) {
+            const float inv = 1.0f / (float)(e_end - b);
+            for (int c = 0; c < 4; ++c) {
+                sgrad[c][0] = acc[c][0] * inv;
+                sgrad[c][1] = acc[c][1] * inv;
+            }
+        }
+    }
+    if (t != 0) return;
     float f[9], g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         f[q] = pop_load<STORE>(P, buf, q, w);
         g[q] = pop_load<STORE>(P, buf, Q + q, w);
     }
-    unsigned miss = 0;
-    for (int q = 1; q < 9; ++q)
-        if (P.dep_e[(q - 1) * P.n_nodes + w] < 0) miss |= 1u << q;
-    if (phase && miss) {
-        const float4 t0 = P.wall_tgt[k];
-        const float rho_t = t0.x, T_t = t0.w, E_t = P.Cv * T_t;
-        // nodal derivative: mean over the node's elements of the element
-        // derivative at the node (the nodes on its two element lines)
-        float d[4][2] = {};
-        const int b = P.patch_off[w], e_end = P.patch_off[w + 1];
-        for (int q = b; q < e_end; ++q) {
-            const int ent = P.patch_ent[q], e = ent >> 4, a = ent & 15;
-            const int pa = q9_p(a), qa = q9_q(a);
-            const float2 *rel = P.erel + 9 * (long long)e;
-            const int *nodes = P.elems + 9 * (long long)e;
-            const float4 Ca = make_float4(0.0f, 0.0f, T_t, E_t);
-            float ax[4] = {}, ae[4] = {};
-            float xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
-            for (int m = -1; m <= 1; ++m) {
-                if (m != pa) {
-                    const int si = q9_node(m, qa);
-                    const float wt = dlag_at(m, pa);
-                    const float4 C = q9_wall_field<STORE>(P, buf, nodes[si]);
-                    ax[0] += wt * (C.x - Ca.x);
-                    ax[1] += wt * (C.y - Ca.y);
-                    ax[2] += wt * (C.z - Ca.z);
-                    ax[3] += wt * (C.w - Ca.w);
-                    xxi += wt * (rel[si].x - rel[a].x);
-                    yxi += wt * (rel[si].y - rel[a].y);
-                }
-                if (m != qa) {
-                    const int sj = q9_node(pa, m);
-                    const float wt = dlag_at(m, qa);
-                    const float4 C = q9_wall_field<STORE>(P, buf, nodes[sj]);
-                    ae[0] += wt * (C.x - Ca.x);
-                    ae[1] += wt * (C.y - Ca.y);
-                    ae[2] += wt * (C.z - Ca.z);
-                    ae[3] += wt * (C.w - Ca.w);
-                    xeta += wt * (rel[sj].x - rel[a].x);
-                    yeta += wt * (rel[sj].y - rel[a].y);
-                }
-            }
-            const float idet = 1.0f / (xxi * yeta - yxi * xeta);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                d[c][0] += idet * (yeta * ax[c] - yxi * ae[c]);
-                d[c][1] += idet * (-xeta * ax[c] + xxi * ae[c]);
-            }
-        }
-        const float inv = 1.0f / (float)(e_end - b);
-        grad_populations(P, miss, rho_t, 0.0f, 0.0f, T_t, E_t, d[0][0] * inv, d[0][1] * inv,
-                         d[1][0] * inv, d[1][1] * inv, d[2][0] * inv, d[2][1] * inv, d[3][0] * inv,
-                         d[3][1] * inv, f, g);
+    if (fill) {
+        grad_populations(P, miss, t0.x, 0.0f, 0.0f, T_t, E_t, sgrad[0][0], sgrad[0][1], sgrad[1][0],
+                         sgrad[1][1], sgrad[2][0], sgrad[2][1], sgrad[3][0], sgrad[3][1], f, g);
 #pragma unroll
         for (int q = 1; q < 9; ++q) {
             if (!(miss & (1u << q))) continue;
@@ -654,9 +703,9 @@ hipError_t launch_unstructured_boundary(const Inst *inst, int n_wall, int n_far,
     if (phase && n_far > 0)
         FSI_DISPATCH(storage, k_u_far, dim3((n_far + U_BND - 1) / U_BND), block, s, inst);
     if (n_wall > 0) {
-        const dim3 grid((n_wall + U_BND - 1) / U_BND);
-        if (phase) FSI_DISPATCH(storage, k_u_wall_targets, grid, block, s, inst);
-        FSI_DISPATCH(storage, k_u_wall, grid, block, s, inst, phase);
+        // one wave per wall node
+        if (phase) FSI_DISPATCH(storage, k_u_wall_targets, dim3(n_wall), dim3(64), s, inst);
+        FSI_DISPATCH(storage, k_u_wall, dim3(n_wall), dim3(64), s, inst, phase);
     }
     return hipGetLastError();
 }
