@@ -273,7 +273,7 @@ void build_q9_blocks(fsi_ctx *c) {
         };
         for (int e : els) {
             be_elem.push_back(e);
-            for (int a = 0; a < 16; ++a) be_nodes.push_back(a < 9 ? pos(c->elems[9 * (size_t)e + a]) : 0);
+            for (int a = 0; a < fsi::U_ELEM_U16; ++a) be_nodes.push_back(a < 9 ? pos(c->elems[9 * (size_t)e + a]) : 0);
         }
         for (int v = n0; v < n1; ++v) uself[v] = pos(v);
         bh_nodes.insert(bh_nodes.end(), nodes.begin(), nodes.end());

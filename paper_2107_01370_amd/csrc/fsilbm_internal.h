@@ -126,7 +126,7 @@ struct Inst {
     const int *bh_nodes;      // nodes of the elements of the block's nodes (its halo), ascending
     const int *be_off;        // [u_nblk + 1] offsets into be_elem / be_nodes
     const int *be_elem;       // elements holding a node of the block, ascending
-    const uint16_t *be_nodes; // [.][16] their nine nodes as halo positions (7 unused)
+    const uint16_t *be_nodes; // [.][U_ELEM_U16] their nine nodes as halo positions (one unused)
     const uint16_t *uself;    // [n_nodes] each node's own position in its block's halo
     uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
     // unstructured meshes round a fixed body: wall and far-field nodes
@@ -144,10 +144,17 @@ struct Inst {
 // nodes per block of the LDS-staged interpolation
 constexpr int U_BLOCK = 256;
 
+// u16 per element in a block's element list: nine halo positions and one
+// pad, five 32-bit words
+constexpr int U_ELEM_U16 = 10;
+
 // LDS of one node block: 8 planes of (f_k, g_k) over the halo, the element
-// lists as halo positions (16 u16 per element), the block's rest populations
-inline size_t u_block_lds_bytes(int hmax, int lemax) {
-    return (size_t)hmax * 8 * 8 + (size_t)lemax * 16 * 2 + (size_t)U_BLOCK * 8;
+// lists as halo positions, the block's rest populations (8-byte aligned)
+__host__ __device__ inline size_t u_block_elem_bytes(int lemax) {
+    return (((size_t)lemax * U_ELEM_U16 * 2 + 7) / 8) * 8;
+}
+__host__ __device__ inline size_t u_block_lds_bytes(int hmax, int lemax) {
+    return (size_t)hmax * 8 * 8 + u_block_elem_bytes(lemax) + (size_t)U_BLOCK * 8;
 }
 
 }  // namespace fsi

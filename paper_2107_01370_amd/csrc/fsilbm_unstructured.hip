@@ -357,8 +357,9 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     void *dst = P.pop[(n + 1) & 1];
     const int H = P.u_hmax;
     float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [8][H]
-    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][16]
-    float2 *rest = reinterpret_cast<float2 *>(el + 16 * (size_t)P.u_lemax);            // [U_BLOCK]
+    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][10]
+    float2 *rest = reinterpret_cast<float2 *>(reinterpret_cast<unsigned char *>(el) +
+                                              u_block_elem_bytes(P.u_lemax));      // [U_BLOCK]
     const int h0 = P.bh_off[b], nh = P.bh_off[b + 1] - h0;
     const int e0 = P.be_off[b], ne = P.be_off[b + 1] - e0;
     const long long n0 = (long long)b * U_BLOCK;
@@ -384,9 +385,10 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         }
     }
     if (err) atomicOr(P.err, err);
-    const uint4 *en4 = reinterpret_cast<const uint4 *>(P.be_nodes) + 2 * (long long)e0;
-    uint4 *el4 = reinterpret_cast<uint4 *>(el);
-    for (int x = threadIdx.x; x < 2 * ne; x += U_BLOCK) el4[x] = en4[x];
+    constexpr int EW = U_ELEM_U16 / 2;      // 32-bit words per element
+    const uint32_t *en = reinterpret_cast<const uint32_t *>(P.be_nodes) + EW * (long long)e0;
+    uint32_t *elw = reinterpret_cast<uint32_t *>(el);
+    for (int x = threadIdx.x; x < EW * ne; x += U_BLOCK) elw[x] = en[x];
     __syncthreads();
     const long long idx = n0 + threadIdx.x;
     if (idx >= P.n_nodes) return;
@@ -405,10 +407,11 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         const float xi = d.x, eta = d.y;
         const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
         const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
-        const uint4 w8 = el4[2 * le];
-        const int nodes[9] = {(int)(w8.x & 0xffffu), (int)(w8.x >> 16), (int)(w8.y & 0xffffu),
-                              (int)(w8.y >> 16),     (int)(w8.z & 0xffffu), (int)(w8.z >> 16),
-                              (int)(w8.w & 0xffffu), (int)(w8.w >> 16),     (int)el[16 * le + 8]};
+        const uint32_t *ew = elw + EW * le;
+        const uint32_t w0 = ew[0], w1 = ew[1], w2 = ew[2], w3 = ew[3], w4 = ew[4];
+        const int nodes[9] = {(int)(w0 & 0xffffu), (int)(w0 >> 16), (int)(w1 & 0xffffu),
+                              (int)(w1 >> 16),     (int)(w2 & 0xffffu), (int)(w2 >> 16),
+                              (int)(w3 & 0xffffu), (int)(w3 >> 16),     (int)(w4 & 0xffffu)};
         const float2 *plk = pl + (k - 1) * H;
         const float2 fg0 = plk[self];
         float vf = fg0.x, vg = fg0.y;
