@@ -34,7 +34,7 @@ struct fsi_ctx {
     // node blocks of the LDS-staged interpolation (empty: device-memory gathers)
     std::vector<int> bh_off, bh_nodes, be_off, be_elem;
     std::vector<uint16_t> be_nodes, uself;
-    int u_hmax = 0, u_lemax = 0;
+    int u_hmax = 0, u_lemax = 0, u_eu16 = 16;
     // unstructured meshes round a fixed body
     std::vector<uint8_t> qflag;
     std::vector<int> qw_nodes, qw_idx, qf_nodes, qw_eB;
@@ -273,7 +273,7 @@ void build_q9_blocks(fsi_ctx *c) {
         };
         for (int e : els) {
             be_elem.push_back(e);
-            for (int a = 0; a < fsi::U_ELEM_U16; ++a) be_nodes.push_back(a < 9 ? pos(c->elems[9 * (size_t)e + a]) : 0);
+            for (int a = 0; a < 16; ++a) be_nodes.push_back(a < 9 ? pos(c->elems[9 * (size_t)e + a]) : 0);
         }
         for (int v = n0; v < n1; ++v) uself[v] = pos(v);
         bh_nodes.insert(bh_nodes.end(), nodes.begin(), nodes.end());
@@ -282,7 +282,18 @@ void build_q9_blocks(fsi_ctx *c) {
         hmax = std::max(hmax, (int)nodes.size());
         lemax = std::max(lemax, (int)els.size());
     }
-    if (fsi::u_block_lds_bytes(hmax, lemax) > 65536) return;
+    // the widest element stride that keeps four blocks per CU, else the narrowest
+    int eu16 = 10;
+    for (int w : {16, 12, 10})
+        if (fsi::u_block_lds_bytes(hmax, lemax, w) <= fsi::U_LDS_PER_BLOCK) { eu16 = w; break; }
+    if (fsi::u_block_lds_bytes(hmax, lemax, eu16) > 65536) return;
+    if (eu16 != 16) {
+        std::vector<uint16_t> packed(be_nodes.size() / 16 * eu16, 0);
+        for (size_t e = 0; e < be_nodes.size() / 16; ++e)
+            for (int a = 0; a < 9; ++a) packed[e * eu16 + a] = be_nodes[e * 16 + a];
+        be_nodes.swap(packed);
+    }
+    c->u_eu16 = eu16;
     c->bh_off.swap(bh_off); c->bh_nodes.swap(bh_nodes); c->be_off.swap(be_off);
     c->be_elem.swap(be_elem); c->be_nodes.swap(be_nodes); c->uself.swap(uself);
     c->u_hmax = hmax;
@@ -818,7 +829,7 @@ fsi_status enqueue_fluid(fsi_ctx *c) {
     if (c->topo == FSI_TOPO_Q9) {
         HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, st,
                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
-                                            c->inst.u_hmax, c->inst.u_lemax, c->stream));
+                                            c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->stream));
         if (!c->qw_nodes.empty() || !c->qf_nodes.empty())
             HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(),
                                                          (int)c->qf_nodes.size(), st, 1, c->stream));
@@ -1058,6 +1069,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.u_nblk = c->bh_off.empty() ? 0 : (int)c->bh_off.size() - 1;
         P.u_hmax = c->u_hmax;
         P.u_lemax = c->u_lemax;
+        P.u_eu16 = c->u_eu16;
         if (!c->bh_off.empty()) {
             P.bh_off = reinterpret_cast<const int *>(c->ws + c->off_bh_off);
             P.bh_nodes = reinterpret_cast<const int *>(c->ws + c->off_bh_nodes);
@@ -1401,7 +1413,7 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
             if (which == 0 && c->topo == FSI_TOPO_Q9)
                 e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, stg,
                                              c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
-                                             c->inst.u_hmax, c->inst.u_lemax, c->stream);
+                                             c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
                                                c->cut, 0);

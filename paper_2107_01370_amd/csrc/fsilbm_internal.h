@@ -121,12 +121,12 @@ struct Inst {
     float2 *dep_xy;           // [8][n_nodes] its local coordinates there
     // node blocks of U_BLOCK consecutive nodes for the LDS-staged interpolation
     // (null bh_off: every block gathers from device memory instead)
-    int u_nblk, u_hmax, u_lemax, pad3;
+    int u_nblk, u_hmax, u_lemax, u_eu16;
     const int *bh_off;        // [u_nblk + 1] offsets into bh_nodes
     const int *bh_nodes;      // nodes of the elements of the block's nodes (its halo), ascending
     const int *be_off;        // [u_nblk + 1] offsets into be_elem / be_nodes
     const int *be_elem;       // elements holding a node of the block, ascending
-    const uint16_t *be_nodes; // [.][U_ELEM_U16] their nine nodes as halo positions (one unused)
+    const uint16_t *be_nodes; // [.][u_eu16] their nine nodes as halo positions (padded)
     const uint16_t *uself;    // [n_nodes] each node's own position in its block's halo
     uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
     // unstructured meshes round a fixed body: wall and far-field nodes
@@ -144,17 +144,18 @@ struct Inst {
 // nodes per block of the LDS-staged interpolation
 constexpr int U_BLOCK = 256;
 
-// u16 per element in a block's element list: nine halo positions and one
-// pad, five 32-bit words
-constexpr int U_ELEM_U16 = 10;
+// u16 per element in a block's element list (nine halo positions, padded):
+// 16 (read as 16 + 2 bytes), 12 (8 + 8 + 2) or 10 (five 4-byte words); the
+// widest whose block still lets four blocks share a CU's 160 KiB of LDS
+constexpr size_t U_LDS_PER_BLOCK = 40960;
 
 // LDS of one node block: 8 planes of (f_k, g_k) over the halo, the element
 // lists as halo positions, the block's rest populations (8-byte aligned)
-__host__ __device__ inline size_t u_block_elem_bytes(int lemax) {
-    return (((size_t)lemax * U_ELEM_U16 * 2 + 7) / 8) * 8;
+__host__ __device__ inline size_t u_block_elem_bytes(int lemax, int eu16) {
+    return (((size_t)lemax * eu16 * 2 + 7) / 8) * 8;
 }
-__host__ __device__ inline size_t u_block_lds_bytes(int hmax, int lemax) {
-    return (size_t)hmax * 8 * 8 + u_block_elem_bytes(lemax) + (size_t)U_BLOCK * 8;
+__host__ __device__ inline size_t u_block_lds_bytes(int hmax, int lemax, int eu16) {
+    return (size_t)hmax * 8 * 8 + u_block_elem_bytes(lemax, eu16) + (size_t)U_BLOCK * 8;
 }
 
 }  // namespace fsi
@@ -172,7 +173,7 @@ hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_wor
 hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
                                float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
-                               hipStream_t s);
+                               int eu16, hipStream_t s);
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s);
 hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int storage, hipStream_t s);
 // far field, wall targets, Grad populations and traction (phase 1), or

@@ -303,11 +303,10 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
         g[0] = pop_load<STORE>(P, dst, Q, idx);
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
-            const int e = P.dep_e[(k - 1) * P.n_nodes + idx];
-            if (e < 0) {                      // missing: the boundary kernels set it
-                f[k] = g[k] = 0.0f;
-                continue;
-            }
+            // a missing population (boundary node) is interpolated in element 0
+            // at (0, 0), a value the boundary kernels replace
+            const int e0 = P.dep_e[(k - 1) * P.n_nodes + idx];
+            const int e = e0 < 0 ? 0 : e0;
             const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
             const float xi = d.x, eta = d.y;
             const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
@@ -345,7 +344,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
 // compiler may fuse multiply-adds differently in the two kernels, so the paths
 // agree to FP32 rounding).  Blocks go to XCDs in
 // contiguous runs, so neighbouring blocks share their halo's lines in one L2.
-template <int STORE>
+template <int STORE, int EU16>
 __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__restrict__ pinst) {
     extern __shared__ __align__(16) unsigned char u_lds[];
     const Inst &P = *pinst;
@@ -357,9 +356,9 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     void *dst = P.pop[(n + 1) & 1];
     const int H = P.u_hmax;
     float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [8][H]
-    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][10]
+    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][EU16]
     float2 *rest = reinterpret_cast<float2 *>(reinterpret_cast<unsigned char *>(el) +
-                                              u_block_elem_bytes(P.u_lemax));      // [U_BLOCK]
+                                              u_block_elem_bytes(P.u_lemax, EU16));  // [U_BLOCK]
     const int h0 = P.bh_off[b], nh = P.bh_off[b + 1] - h0;
     const int e0 = P.be_off[b], ne = P.be_off[b + 1] - e0;
     const long long n0 = (long long)b * U_BLOCK;
@@ -385,7 +384,7 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         }
     }
     if (err) atomicOr(P.err, err);
-    constexpr int EW = U_ELEM_U16 / 2;      // 32-bit words per element
+    constexpr int EW = EU16 / 2;            // 32-bit words per element
     const uint32_t *en = reinterpret_cast<const uint32_t *>(P.be_nodes) + EW * (long long)e0;
     uint32_t *elw = reinterpret_cast<uint32_t *>(el);
     for (int x = threadIdx.x; x < EW * ne; x += U_BLOCK) elw[x] = en[x];
@@ -398,20 +397,30 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     g[0] = rest[threadIdx.x].y;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
-        const int le = P.dep_le[(k - 1) * P.n_nodes + idx];
-        if (le == U_MISSING) {                // missing: the boundary kernels set it
-            f[k] = g[k] = 0.0f;
-            continue;
-        }
+        // a missing population (boundary node) is interpolated in the block's
+        // first element at (0, 0), a value the boundary kernels replace
+        const int le0 = P.dep_le[(k - 1) * P.n_nodes + idx];
+        const int le = le0 == U_MISSING ? 0 : le0;
         const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
         const float xi = d.x, eta = d.y;
         const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
         const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
         const uint32_t *ew = elw + EW * le;
-        const uint32_t w0 = ew[0], w1 = ew[1], w2 = ew[2], w3 = ew[3], w4 = ew[4];
+        uint32_t w0, w1, w2, w3;
+        if constexpr (EU16 == 16) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(ew);
+            w0 = v.x; w1 = v.y; w2 = v.z; w3 = v.w;
+        } else if constexpr (EU16 == 12) {
+            const uint2 v0 = *reinterpret_cast<const uint2 *>(ew);
+            const uint2 v1 = *reinterpret_cast<const uint2 *>(ew + 2);
+            w0 = v0.x; w1 = v0.y; w2 = v1.x; w3 = v1.y;
+        } else {
+            w0 = ew[0]; w1 = ew[1]; w2 = ew[2]; w3 = ew[3];
+        }
+        const int n8 = (int)(ew[4] & 0xffffu);
         const int nodes[9] = {(int)(w0 & 0xffffu), (int)(w0 >> 16), (int)(w1 & 0xffffu),
                               (int)(w1 >> 16),     (int)(w2 & 0xffffu), (int)(w2 >> 16),
-                              (int)(w3 & 0xffffu), (int)(w3 >> 16),     (int)(w4 & 0xffffu)};
+                              (int)(w3 & 0xffffu), (int)(w3 >> 16),     n8};
         const float2 *plk = pl + (k - 1) * H;
         const float2 fg0 = plk[self];
         float vf = fg0.x, vg = fg0.y;
@@ -679,7 +688,7 @@ hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int 
 
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
                                float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
-                               hipStream_t s) {
+                               int eu16, hipStream_t s) {
     // multiples of the XCD count (see xcd_block)
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
     const long long e64 = ((n_elems + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
@@ -690,9 +699,19 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
     if (n_blocks > 0) {
         // a multiple of the XCD count; the kernel maps slots to blocks
         const unsigned g = (unsigned)(((n_blocks + 7) / 8) * 8);
-        const size_t lds = u_block_lds_bytes(hmax, lemax);
-        if (storage == 0) hipLaunchKernelGGL(k_u_collide_stream_blk<0>, dim3(g), dim3(U_BLOCK), lds, s, inst);
-        else hipLaunchKernelGGL(k_u_collide_stream_blk<1>, dim3(g), dim3(U_BLOCK), lds, s, inst);
+        const size_t lds = u_block_lds_bytes(hmax, lemax, eu16);
+#define FSI_U_BLK(ST, EU)                                                                     \
+    hipLaunchKernelGGL((k_u_collide_stream_blk<ST, EU>), dim3(g), dim3(U_BLOCK), lds, s, inst)
+        if (storage == 0) {
+            if (eu16 == 16) FSI_U_BLK(0, 16);
+            else if (eu16 == 12) FSI_U_BLK(0, 12);
+            else FSI_U_BLK(0, 10);
+        } else {
+            if (eu16 == 16) FSI_U_BLK(1, 16);
+            else if (eu16 == 12) FSI_U_BLK(1, 12);
+            else FSI_U_BLK(1, 10);
+        }
+#undef FSI_U_BLK
     } else {
         FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
         FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
