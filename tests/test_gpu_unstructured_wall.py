@@ -102,3 +102,25 @@ def test_wall_checkpoint_and_single_steps_keep_the_run():
     assert np.array_equal(a.forces(7, 21), b.forces(7, 21))
     a.close()
     b.close()
+
+
+def test_wall_2103296_full_size_step():
+    """The 2,103,296-node mesh round the cylinder of the bounded unstructured
+    workload (D 640, far field 8 D, Ma 0.2, Re 1000), launched as the
+    benchmark launches it: one step against the oracle (populations and the
+    force record)."""
+    case = q9_cylinder_case(512, 640.0, 8.0, seed=1, Ma=0.2, Re=1000.0)
+    sim, ora = paired(case)
+    sim.step(1)
+    ora.step()
+    f, g = sim.populations()
+    for a, b in ((f[:, 0, :], ora.f), (g[:, 0, :], ora.g)):
+        err = np.abs(a - b)
+        assert np.max(err) <= 1e-6 * np.max(np.abs(b)), (np.unravel_index(np.argmax(err), err.shape),
+                                                         np.max(err))
+    # the load on the new populations (record of level 1): 1e-4 of the load
+    # plus the FP32 rounding of a pressure sum round the wall (1e-7 p pi D)
+    h = sim.forces(1, 1)[0]
+    Fx, Fy, _ = ora.wall_force()
+    floor = 1e-7 * (1.0 / 3.0) * np.pi * 640.0
+    assert abs(h[1] - Fx) <= 1e-4 * abs(Fx) + floor and abs(h[2] - Fy) <= 1e-4 * abs(Fy) + floor
