@@ -273,10 +273,9 @@ def cpu_baseline_unstructured(target_s: float = 20.0, m: int = 48):
     r, _, _, Tg = sim.macro()
     r_o, _, _, _, T_o = ora.macroscopic()
     sim.close()
-    threads = os.environ.get("OMP_NUM_THREADS", "1")
     sample = (f"{n} steps of the same construction at m = {m} ({mesh.n_nodes} nodes, "
               f"{mesh.n_elems} elements) with the same physics, {el:.1f} s, single-threaded "
-              f"NumPy (OMP_NUM_THREADS={threads}), os.cpu_count()={os.cpu_count()}")
+              f"NumPy (BLAS/OpenMP pools limited to one thread), os.cpu_count()={os.cpu_count()}")
     accuracy = {
         "against": "FP64 oracle, same sample as cpu_baseline, from the same initial populations",
         "steps": n + 1,
@@ -321,7 +320,6 @@ def cpu_baseline_unstructured_cylinder(target_s: float = 20.0, n_theta: int = 64
     ho = np.array(ora.history)[:nsteps]
     fscale = float(np.max(np.hypot(ho[:, 1], ho[:, 2])))
     sim.close()
-    threads = os.environ.get("OMP_NUM_THREADS", "1")
     accuracy = {
         "against": "FP64 oracle, same sample as cpu_baseline, from the same initial populations",
         "steps": nsteps,
@@ -333,7 +331,7 @@ def cpu_baseline_unstructured_cylinder(target_s: float = 20.0, n_theta: int = 64
     return {"value": mesh.n_nodes * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{n} steps of the same construction at n_theta = {n_theta}, D = 80 "
                       f"({mesh.n_nodes} nodes, {mesh.n_elems} elements) with the same physics, "
-                      f"{el:.1f} s, single-threaded NumPy (OMP_NUM_THREADS={threads}), "
+                      f"{el:.1f} s, single-threaded NumPy (BLAS/OpenMP pools limited to one thread), "
                       f"os.cpu_count()={os.cpu_count()}"}, accuracy
 
 
@@ -393,7 +391,6 @@ def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
         }
     sim.close()
     nodes = strip.ni * strip.nj
-    threads = os.environ.get("OMP_NUM_THREADS", "1")
     return {
         "value": nodes * n / el / 1e6,
         "unit": "MLUPS",
@@ -401,7 +398,8 @@ def cpu_baseline(case, target_s: float = 20.0, rows: int = 64):
         "kind": "oracle",
         "sample": f"{n} steps of a {strip.ni}x{rows} strip (rows 0..{rows - 1}, wall included) "
                   f"of the same mesh and physics, {el:.1f} s, single-threaded NumPy "
-                  f"(OMP_NUM_THREADS={threads}), host {platform.processor() or platform.machine()}, "
+                  f"(BLAS/OpenMP pools limited to one thread), host "
+                  f"{platform.processor() or platform.machine()}, "
                   f"os.cpu_count()={os.cpu_count()}",
     }, accuracy
 
@@ -521,10 +519,12 @@ def main():
             "finite_state": finb,
         })
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["accuracy"] = (
-            cpu_baseline_unstructured_cylinder() if args.workload.startswith("unstructured_cyl")
-            else cpu_baseline_unstructured() if args.workload.startswith("unstructured")
-            else cpu_baseline(case))
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            out["cpu_baseline"], out["accuracy"] = (
+                cpu_baseline_unstructured_cylinder() if args.workload.startswith("unstructured_cyl")
+                else cpu_baseline_unstructured() if args.workload.startswith("unstructured")
+                else cpu_baseline(case))
     print(json.dumps(out), flush=True)
 
 
