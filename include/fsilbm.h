@@ -233,8 +233,9 @@ fsi_status fsi_bind_workspace(fsi_ctx *ctx, void *dev_ptr, size_t bytes);
 fsi_status fsi_init_equilibrium(fsi_ctx *ctx, const double *rho, const double *ux,
                                 const double *uy, const double *T);
 
-/* Enqueue `nsteps` coupled steps (replays of a captured HIP graph of one
- * step).  Asynchronous. */
+/* Enqueue `nsteps` coupled steps: replays of a captured HIP graph of 16
+ * steps, then of one step for the remainder (both captured on first use).
+ * Asynchronous. */
 fsi_status fsi_step(fsi_ctx *ctx, int nsteps);
 
 /* Wait for the stream and report the sticky device error word
