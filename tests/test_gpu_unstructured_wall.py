@@ -124,3 +124,27 @@ def test_wall_2103296_full_size_step():
     Fx, Fy, _ = ora.wall_force()
     floor = 1e-7 * (1.0 / 3.0) * np.pi * 640.0
     assert abs(h[1] - Fx) <= 1e-4 * abs(Fx) + floor and abs(h[2] - Fy) <= 1e-4 * abs(Fy) + floor
+
+
+def test_wall_device_gathers_agree_with_the_block_path(monkeypatch):
+    """Round a body too, the interpolation through device memory
+    (FSILBM_UNSTRUCTURED_GATHER=device) and the LDS-staged block path agree
+    to FP32 rounding (missing populations take a placeholder in both, which
+    the wall and far-field kernels replace)."""
+    from paper_2107_01370_amd.fsilbm import Simulation
+    mesh, fl, body, (rho, ux, uy, T) = q9_cylinder_case(seed=6)
+    out = []
+    for mode in (None, "device"):
+        if mode:
+            monkeypatch.setenv("FSILBM_UNSTRUCTURED_GATHER", mode)
+        else:
+            monkeypatch.delenv("FSILBM_UNSTRUCTURED_GATHER", raising=False)
+        sim = Simulation(mesh, fl, [body])
+        sim.init_equilibrium(rho[None], ux[None], uy[None], T[None])
+        sim.step(30)
+        out.append((sim.populations(), sim.forces(0, 31)))
+        sim.close()
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
+    fs = np.max(np.hypot(out[1][1][:, 1], out[1][1][:, 2]))
+    assert np.max(np.abs(out[0][1][:, 1:3] - out[1][1][:, 1:3])) <= 1e-4 * fs
