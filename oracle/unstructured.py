@@ -92,28 +92,37 @@ class UGrid:
         self.pe[node, rank] = elem
         self.pa[node, rank] = loc
         self.pm[node, rank] = True
-        # element derivative operator at each element's own nodes:
-        # dC/dx at local node a of element e = sum_s Wx[e, a, s] C_s
-        self.Wx = np.zeros((self.E, 9, 9))
-        self.Wy = np.zeros((self.E, 9, 9))
-        for a in range(9):
-            dxi, deta = shape_grad(np.array(LOCAL[a, 0]), np.array(LOCAL[a, 1]))
-            x_xi = self.ex @ dxi
-            x_eta = self.ex @ deta
-            y_xi = self.ey @ dxi
-            y_eta = self.ey @ deta
-            det = x_xi * y_eta - y_xi * x_eta
-            # [dC/dx, dC/dy] = J^{-T} [dC/dxi, dC/deta]
-            self.Wx[:, a, :] = (y_eta[:, None] * dxi[None, :] - y_xi[:, None] * deta[None, :]) / det[:, None]
-            self.Wy[:, a, :] = (-x_eta[:, None] * dxi[None, :] + x_xi[:, None] * deta[None, :]) / det[:, None]
+        self.Wx, self.Wy = self.operator(self.ex, self.ey)
         self.det_min = None
 
-    def grad(self, C):
+    @staticmethod
+    def operator(ex, ey):
+        """Element derivative operator at each element's own nodes for element
+        node coordinates (ex, ey) [E, 9]: dC/dx at local node a of element e
+        = sum_s Wx[e, a, s] C_s (and Wy for d/dy)."""
+        E = ex.shape[0]
+        Wx = np.zeros((E, 9, 9))
+        Wy = np.zeros((E, 9, 9))
+        for a in range(9):
+            dxi, deta = shape_grad(np.array(LOCAL[a, 0]), np.array(LOCAL[a, 1]))
+            x_xi = ex @ dxi
+            x_eta = ex @ deta
+            y_xi = ey @ dxi
+            y_eta = ey @ deta
+            det = x_xi * y_eta - y_xi * x_eta
+            # [dC/dx, dC/dy] = J^{-T} [dC/dxi, dC/deta]
+            Wx[:, a, :] = (y_eta[:, None] * dxi[None, :] - y_xi[:, None] * deta[None, :]) / det[:, None]
+            Wy[:, a, :] = (-x_eta[:, None] * dxi[None, :] + x_xi[:, None] * deta[None, :]) / det[:, None]
+        return Wx, Wy
+
+    def grad(self, C, W=None):
         """Nodal gradient (dC/dx, dC/dy): the mean over the node's elements of
-        the element derivative at the node."""
+        the element derivative at the node; W = (Wx, Wy) an operator of other
+        (deformed) element coordinates, else the mesh's own."""
+        Wx, Wy = W if W is not None else (self.Wx, self.Wy)
         Ce = C[self.elems]                                    # [E, 9]
-        gx_e = np.einsum("eas,es->ea", self.Wx, Ce)           # [E, 9] at each element node
-        gy_e = np.einsum("eas,es->ea", self.Wy, Ce)
+        gx_e = np.einsum("eas,es->ea", Wx, Ce)                # [E, 9] at each element node
+        gy_e = np.einsum("eas,es->ea", Wy, Ce)
         gx = np.where(self.pm, gx_e[self.pe, self.pa], 0.0).sum(axis=1) / self.count
         gy = np.where(self.pm, gy_e[self.pe, self.pa], 0.0).sum(axis=1) / self.count
         return gx, gy
@@ -265,10 +274,10 @@ class UnstructuredSolver:
 
 
 class UnstructuredWallSolver(UnstructuredSolver):
-    """The step on a static unstructured Q9 mesh round a fixed body, in
-    float64 (paper Sec. II.B on its own kind of mesh, with the boundary
-    conditions of Sec. III.A and the wall force of Sec. III).  Test
-    infrastructure only.
+    """The step on an unstructured Q9 mesh round a body, in float64 (paper
+    Sec. II.B on its own kind of mesh, with the boundary conditions of
+    Sec. III.A, the wall force of Sec. III, the blended mesh of Sec. II.D and
+    the rigid body of Sec. IV, staggered).  Test infrastructure only.
 
     The mesh carries `wall_nodes` (the body polygon, clockwise, so that a
     +90 degree rotation of its tangent points into the fluid) and
@@ -279,18 +288,31 @@ class UnstructuredWallSolver(UnstructuredSolver):
     * far field: all populations of the far-field nodes are set to the
       free-stream equilibrium (the outer circle lies far from the body);
     * wall: missing populations take Grad's approximation (Sec. III.A.1) with
-      u_t = 0 (fixed body), rho_t, T_t the 9-node interpolation at
-      B = x + dt n (n the unit normal of the lumped wall polygon normal) in
-      the wall node's element that holds B, the wall nodes of that element
+      u_t the wall node's mesh velocity, rho_t, T_t the 9-node interpolation
+      at B = X + dt n in the undeformed frame (n the unit normal of the
+      lumped wall polygon; the wall's elements lie in the rigid zone, where
+      the deformed element is a rigid image of the undeformed one) in the
+      wall node's element that holds B, the wall nodes of that element
       carrying the values of the previous level (their new populations are
       being built), and gradients of u, T, E at the wall node by the nodal
-      finite-element derivative with the wall nodes holding the targets;
+      finite-element derivative on the mesh of the new level, the wall nodes
+      holding the targets;
     * force: sigma . (n ds) summed over the wall nodes in list order, with
-      (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2 from the polygon neighbours,
-      the moment about the body's elastic axis (Sec. III).
+      (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2 from the polygon neighbours on
+      the mesh of the level, the moment about the body's displaced elastic
+      axis (Sec. III);
+    * a moving body (any dof but fixed): nodes move by the blending of
+      Sec. II.D, x = X + (1 - r)(G'(X) - X); the departure point of node X is
+      X - dt g^{-1}(c_i - V_G) in the undeformed frame (g = dx/dX at the new
+      level by the nodal finite-element derivative on the undeformed mesh,
+      V_G = (x^{n+1} - x^n)/dt), located among the node's undeformed
+      elements every step; the correction's derivatives are taken on the
+      mesh of level n.
     """
 
     def __init__(self, mesh, fluid, body, rho=None, ux=None, uy=None, T=None, correction=True):
+        from . import body as B
+        from .mesh import blend_factors
         self.grid = UGrid(mesh)
         self.fluid = fluid
         self.correction = correction
@@ -304,37 +326,67 @@ class UnstructuredWallSolver(UnstructuredSolver):
             T = np.full(N, fluid.T_inf)
         self.f, self.g = L.equilibrium_populations(rho, ux, uy, T, fluid.gamma)
         self.n = 0
+        self.X = np.asarray(mesh.X, dtype=np.float64)
+        self.Y = np.asarray(mesh.Y, dtype=np.float64)
+        self.moving = body.dof != B.DOF_FIXED
+        self.state = B.initial_state(body)
+        self.r = blend_factors(self.X, self.Y, [body])[0]
         self.wall = np.asarray(mesh.wall_nodes, dtype=np.int64)
         self.far = np.asarray(mesh.far_nodes, dtype=np.int64)
-        bnd = np.zeros(N, dtype=bool)
-        bnd[self.wall] = True
-        bnd[self.far] = True
+        self.bnd = np.zeros(N, dtype=bool)
+        self.bnd[self.wall] = True
+        self.bnd[self.far] = True
         self.dep = [None] * L.Q
-        for i in range(1, L.Q):
-            self.dep[i] = g.locate(-fluid.dt * L.CX[i], -fluid.dt * L.CY[i], allow_missing=bnd)
-        # lumped wall normals (into the fluid) and the points B
-        xw, yw = mesh.X[self.wall], mesh.Y[self.wall]
-        self.nds_x = -0.5 * (np.roll(yw, -1) - np.roll(yw, 1))
-        self.nds_y = 0.5 * (np.roll(xw, -1) - np.roll(xw, 1))
+        if not self.moving:
+            for i in range(1, L.Q):
+                self.dep[i] = g.locate(-fluid.dt * L.CX[i], -fluid.dt * L.CY[i], allow_missing=self.bnd)
+        # lumped wall normals of the undeformed polygon and the points B
+        self.xw, self.yw = self.X[self.wall], self.Y[self.wall]
+        self.nds_x, self.nds_y = self._nds(self.xw, self.yw)
         nn = np.hypot(self.nds_x, self.nds_y)
         self.B = g.locate(fluid.dt * self.nds_x / nn, fluid.dt * self.nds_y / nn, nodes=self.wall)
-        self.xw, self.yw = xw, yw
         self.history = []
 
+    @staticmethod
+    def _nds(xw, yw):
+        return -0.5 * (np.roll(yw, -1) - np.roll(yw, 1)), 0.5 * (np.roll(xw, -1) - np.roll(xw, 1))
+
+    def positions(self, state):
+        """Node positions on the blended mesh of body state `state`."""
+        from .mesh import rigid_displacement
+        if not self.moving:
+            return self.X.copy(), self.Y.copy()
+        dx, dy = rigid_displacement(self.X, self.Y, self.body, state[0], state[1])
+        return self.X + (1.0 - self.r) * dx, self.Y + (1.0 - self.r) * dy
+
+    def _operator(self, x, y):
+        if not self.moving:
+            return None
+        g = self.grid
+        return g.operator(x[g.elems], y[g.elems])
+
     def missing(self, i):
-        """Mask of the nodes whose population i is missing."""
+        """Mask of the nodes whose population i is missing (last step's
+        departure points on a moving mesh)."""
         return self.dep[i][0] < 0
 
-    def wall_force(self):
-        """(F_x, F_y, M_EA) on the body from the current populations."""
+    def wall_force(self, x=None, y=None, state=None):
+        """(F_x, F_y, M_EA) on the body from the current populations on the
+        mesh (x, y) of the body state `state` (default: the current level)."""
         from .forces import wall_stress
+        if state is None:
+            state = self.state
+        if x is None:
+            x, y = self.positions(state)
         fl = self.fluid
         sxx, sxy, syy = wall_stress(self.f[:, self.wall], self.g[:, self.wall], fl.gamma, fl.mu,
                                     fl.Pr, fl.dt)
-        Fx_k = sxx * self.nds_x + sxy * self.nds_y
-        Fy_k = sxy * self.nds_x + syy * self.nds_y
-        rx = self.xw - self.body.ea[0]
-        ry = self.yw - self.body.ea[1]
+        xw, yw = x[self.wall], y[self.wall]
+        nx, ny = self._nds(xw, yw)
+        Fx_k = sxx * nx + sxy * ny
+        Fy_k = sxy * nx + syy * ny
+        rx = xw - self.body.ea[0]
+        ry = yw - (self.body.ea[1] + state[0])
         Mz_k = rx * Fy_k - ry * Fx_k
         Fx = Fy = Mz = 0.0
         for k in range(self.wall.size):
@@ -344,17 +396,42 @@ class UnstructuredWallSolver(UnstructuredSolver):
         return Fx, Fy, Mz
 
     def step(self):
+        from . import body as B
         from .boundary import grad_populations
         fl = self.fluid
         g = self.grid
-        Fx_b, Fy_b, Mz_b = self.wall_force()
-        self.history.append([float(self.n), Fx_b, Fy_b, Mz_b, 0.0, 0.0])
+        dt = fl.dt
+        x0, y0 = self.positions(self.state)
+        Fx_b, Fy_b, Mz_b = self.wall_force(x0, y0, self.state)
+        self.history.append([float(self.n), Fx_b, Fy_b, Mz_b, self.state[0], self.state[1]])
+        new_state = B.advance(self.body, self.state, Fy_b, Mz_b, (self.n + 1) * dt, dt)
+        x1, y1 = self.positions(new_state)
+        VGx, VGy = (x1 - x0) / dt, (y1 - y0) / dt
+        if self.moving:
+            # departure points in the undeformed frame: X - dt g^{-1}(c - V_G)
+            gxx, gxy = g.grad(x1)
+            gyx, gyy = g.grad(y1)
+            det = gxx * gyy - gxy * gyx
+            for i in range(1, L.Q):
+                ax, ay = L.CX[i] - VGx, L.CY[i] - VGy
+                chx = (gyy * ax - gxy * ay) / det
+                chy = (-gyx * ax + gxx * ay) / det
+                self.dep[i] = g.locate(-dt * chx, -dt * chy, allow_missing=self.bnd)
         rho0, _, _, _, T0 = L.macroscopic(self.f[:, self.wall], self.g[:, self.wall], fl.gamma)
         if self.correction:
-            Fx, Fy = self.correction_force()
+            W0 = self._operator(x0, y0)
+            rho, ux, uy, E, T = L.macroscopic(self.f, self.g, fl.gamma)
+            omega, _ = L.relaxation_rates(rho, T, fl.mu, fl.Pr, dt)
+            dQx, dQy = L.momentum_defect(rho, ux, uy, T)
+            gx, _ = g.grad(dQx, W0)
+            _, gy = g.grad(dQy, W0)
+            Dx = (1.0 / omega - 0.5) * dt * gx
+            Dy = (1.0 / omega - 0.5) * dt * gy
+            Fx, _ = g.grad(Dx, W0)
+            _, Fy = g.grad(Dy, W0)
         else:
             Fx = Fy = np.zeros(g.N)
-        fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, fl.dt, Fx, Fy)
+        fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt, Fx, Fy)
         f_new = np.full_like(fpost, np.nan)
         g_new = np.full_like(gpost, np.nan)
         f_new[0] = fpost[0]
@@ -372,7 +449,7 @@ class UnstructuredWallSolver(UnstructuredSolver):
                                            np.full(nf, fl.u_inf[1]), np.full(nf, fl.T_inf), fl.gamma)
         f_new[:, self.far] = fe
         g_new[:, self.far] = ge
-        # wall: targets at B and gradients at the wall nodes
+        # wall: targets at B and gradients at the wall nodes on the new mesh
         Cv, _ = L.specific_heats(fl.gamma)
         with np.errstate(invalid="ignore", divide="ignore"):
             rho_s, ux_s, uy_s, E_s, T_s = L.macroscopic(np.nan_to_num(f_new), np.nan_to_num(g_new),
@@ -386,24 +463,25 @@ class UnstructuredWallSolver(UnstructuredSolver):
         nodesB = g.elems[eB]
         rho_t = np.sum(NB.T * R[nodesB], axis=1)
         T_t = np.sum(NB.T * TT[nodesB], axis=1)
-        nw = self.wall.size
-        ux_t = np.zeros(nw)
-        uy_t = np.zeros(nw)
-        E_t = Cv * T_t
+        ux_t = VGx[self.wall]
+        uy_t = VGy[self.wall]
+        E_t = Cv * T_t + 0.5 * (ux_t ** 2 + uy_t ** 2)
         Ux, Uy, Tg, Eg = ux_s.copy(), uy_s.copy(), T_s.copy(), E_s.copy()
         Ux[self.wall] = ux_t
         Uy[self.wall] = uy_t
         Tg[self.wall] = T_t
         Eg[self.wall] = E_t
+        W1 = self._operator(x1, y1)
         grads = []
         for F in (Ux, Uy, Tg, Eg):
-            gx, gy = g.grad(F)
+            gx, gy = g.grad(F, W1)
             grads.append((gx[self.wall], gy[self.wall]))
-        fw, gw = grad_populations(rho_t, ux_t, uy_t, T_t, E_t, *grads, fl.gamma, fl.mu, fl.Pr, fl.dt)
+        fw, gw = grad_populations(rho_t, ux_t, uy_t, T_t, E_t, *grads, fl.gamma, fl.mu, fl.Pr, dt)
         for i in range(1, L.Q):
             m = self.missing(i)[self.wall]
             f_new[i, self.wall[m]] = fw[i, m]
             g_new[i, self.wall[m]] = gw[i, m]
         assert not np.any(np.isnan(f_new)) and not np.any(np.isnan(g_new))
         self.f, self.g = f_new, g_new
+        self.state = new_state
         self.n += 1

@@ -219,7 +219,7 @@ def unstructured_pulse_case(m: int = 16, amp: float = 0.06, seed: int = 0, Ma: f
 
 
 def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, seed: int = 0,
-                     center=(0.0, 0.0), mirror: bool = False) -> UnstructuredMesh:
+                     center=(0.0, 0.0), mirror: bool = False, quarter_turn: bool = False) -> UnstructuredMesh:
     """Unstructured 9-node quadrilateral mesh of the annulus between a
     cylinder of diameter D and a circle of far_D * D, as input data: the
     annulus is cut into n_theta x n_r cells of a polar grid (square cells:
@@ -232,7 +232,9 @@ def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, see
 
     mirror (n_theta even): the lower half is the mirror image of the upper
     half about the x axis through the centre (diagonals mirrored, corner
-    coordinates mirrored exactly).
+    coordinates mirrored exactly).  quarter_turn: the mesh turned by +90
+    degrees about the centre (a mirrored mesh is then symmetric about the y
+    axis through the centre).
 
     Also returns, on the mesh: `wall_nodes`, the nodes on the body polygon
     in clockwise order (a rotation by +90 degrees of the polygon's tangent
@@ -312,6 +314,9 @@ def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, see
                 add_quad([kq, kqr, kg, kpq], [pq, pqr, pg, ppq])
                 add_quad([kr, krp, kg, kqr], [pr, prp, pg, pqr])
     P = np.array(pos, dtype=np.float64)
+    if quarter_turn:
+        P = np.stack([2.0 * center[0] - (P[:, 1] - center[1]) - center[0],
+                      center[1] + (P[:, 0] - center[0])], axis=1)
     E = np.array(elems, dtype=np.int64)
     keys = np.empty((len(pos), 2), dtype=np.int64)
     for k, v in key_to_id.items():
@@ -335,7 +340,7 @@ def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, see
                             np.zeros((E.shape[0], 9, 2), dtype=np.int8), (0.0, 0.0),
                             info={"kind": "cylinder_q9", "n_theta": n_theta, "n_r": n_r, "D": D,
                                   "far_D": far_D, "seed": seed, "center": tuple(center),
-                                  "mirror": mirror},
+                                  "mirror": mirror, "quarter_turn": quarter_turn},
                             wall_nodes=wall.astype(np.int32), far_nodes=far.astype(np.int32))
 
 
@@ -369,3 +374,37 @@ def q9_cylinder_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, see
     uy = (ur * s + ut * c) * layer
     N = mesh.n_nodes
     return mesh, fluid, body, (np.ones(N), ux, uy, np.full(N, T0))
+
+
+def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: int = 1,
+                  amp_D: float = 0.02, Ma_body: float = 0.05, T0: float = 1.0 / 3.0,
+                  nu: float = 0.02, gamma: float = 1.4, Pr: float = 0.71, storage: int = 0,
+                  dof: int = 0, mstar: float = 2.0, ustar: float = 5.0,
+                  symmetric: bool = False):
+    """A cylinder on the unstructured mesh of `cylinder_q9_mesh` in gas at
+    rest, moving along y: prescribed heave h = A sin(w t) (dof 0; A = amp_D D,
+    peak speed Ma_body times the speed of sound), or released from h0 = A on a
+    spring (dof 1, mass ratio mstar, reduced velocity ustar against the same
+    speed).  Blending: rigid out to R + D/4, blended out to R + 2D.
+    symmetric: the mesh is its own mirror image about the y axis (the line of
+    the motion).
+    dt = (smallest patch reach) / (3 sqrt 2).  Returns (mesh, fluid, body,
+    (rho, ux, uy, T))."""
+    from .configs import BodyParams, FluidParams, sound_speed
+    mesh = cylinder_q9_mesh(n_theta, D, far_D, seed=seed, mirror=symmetric, quarter_turn=symmetric)
+    R = 0.5 * D
+    c = sound_speed(gamma, T0)
+    A = amp_D * D
+    w = Ma_body * c / A
+    dt = smallest_patch_reach(mesh) / (3.0 * np.sqrt(2.0))
+    fluid = FluidParams(gamma=gamma, Pr=Pr, mu=nu, rho_inf=1.0, T_inf=T0, u_inf=(0.0, 0.0), dt=dt,
+                        storage=storage)
+    m = mstar * np.pi * R * R
+    U = Ma_body * c
+    k_h = m * (2.0 * np.pi * U / (ustar * D)) ** 2
+    body = BodyParams(dof=dof, m=m, k_h=k_h, center=(0.0, 0.0), ea=(0.0, 0.0),
+                      r_rigid=R + 0.25 * D, r_blend=R + 2.0 * D,
+                      heave_amp=A if dof == 0 else 0.0, heave_freq=w / (2.0 * np.pi) if dof == 0 else 0.0,
+                      h0=A if dof == 1 else 0.0)
+    N = mesh.n_nodes
+    return mesh, fluid, body, (np.ones(N), np.zeros(N), np.zeros(N), np.full(N, T0))

@@ -119,3 +119,53 @@ def test_flow_past_the_body_is_mirror_symmetric_with_zero_lift():
     assert np.max(np.abs(h[:, 2])) < 1e-11 * h[-1, 1]  # no lift
     # a developed, non-uniform flow
     assert np.max(np.abs(r - 1.0)) > 1e-4
+
+
+def test_moving_body_departures_in_the_rigid_zone():
+    """A heaving body on the blended unstructured mesh: in the rigid zone
+    (r = 0) the mesh translates with the body, g = dx/dX = I and the
+    departure point in the undeformed frame is X - dt (c_i - V_G) with
+    V_G = (h^{n+1} - h^n) / dt along y; the located element and local
+    coordinates map back to that point."""
+    from synth.unstructured import q9_heave_case
+    m, fl, b, (r, u, v, T) = q9_heave_case(16, 20.0, 4.0)
+    o = UnstructuredWallSolver(m, fl, b, r, u, v, T)
+    h0 = o.state[0]
+    o.step()
+    h1 = o.state[0]
+    vg = (h1 - h0) / fl.dt
+    assert abs(vg) > 1e-3
+    # nodes whose elements lie wholly in the rigid zone (their nodal
+    # derivative sees no blending)
+    rel = np.all(o.r[m.elems] == 0.0, axis=1)
+    g = o.grid
+    rigid = np.all(np.where(g.pm, rel[g.pe], True), axis=1)
+    ex, ey = element_coords(m)
+    checked = 0
+    for i in range(1, L.Q):
+        e, xi, eta = o.dep[i]
+        ok = rigid & (e >= 0)
+        Nw = shape(xi[ok], eta[ok])
+        px = np.sum(Nw.T * ex[e[ok]], axis=1)
+        py = np.sum(Nw.T * ey[e[ok]], axis=1)
+        assert np.max(np.abs(px - (m.X[ok] - fl.dt * L.CX[i]))) < 1e-10
+        assert np.max(np.abs(py - (m.Y[ok] - fl.dt * (L.CY[i] - vg)))) < 1e-10
+        checked += ok.sum()
+    assert checked > 500
+
+
+def test_heaving_body_flow_is_mirror_symmetric():
+    """A cylinder heaving along y in gas at rest, on a mesh that is its own
+    mirror image about the y axis: the flow stays mirror-symmetric and the
+    force along x vanishes, while the body feels a force along y."""
+    from synth.unstructured import q9_heave_case
+    m, fl, b, (r, u, v, T) = q9_heave_case(16, 20.0, 4.0, symmetric=True)
+    _, mm = cKDTree(np.c_[m.X, m.Y]).query(np.c_[-m.X, m.Y])
+    o = UnstructuredWallSolver(m, fl, b, r, u, v, T)
+    o.run(40)
+    rr, ux, uy, E, Tt = o.macroscopic()
+    assert np.max(np.abs(rr - rr[mm])) < 1e-12 and np.max(np.abs(ux + ux[mm])) < 1e-12
+    assert np.max(np.abs(uy - uy[mm])) < 1e-12
+    h = np.array(o.history)
+    assert abs(h[-1, 2]) > 0.1 and h[-1, 4] != 0.0
+    assert np.max(np.abs(h[:, 1])) < 1e-11 * abs(h[-1, 2])
