@@ -41,6 +41,7 @@ struct fsi_ctx {
     std::vector<double4> qw_geo;
     std::vector<float2> qw_xyB;
     std::vector<double> ecoord;     // [E][9][2] unwrapped FP64 element node coordinates
+    bool q9_moving = false;         // a moving body on a Q9 mesh
     hipStream_t stream = nullptr;
     int n_sub = 1;                  // coupling sub-iterations per step
     double relax = 1.0;
@@ -53,7 +54,8 @@ struct fsi_ctx {
            off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0,
            off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
            off_uself = 0, off_dep_le = 0, off_qflag = 0, off_qw = 0, off_qwidx = 0, off_qf = 0,
-           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, total = 0;
+           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_uegd = 0,
+           total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
     std::vector<double> wall_dist;      // blend_mode 1: [body][node] distance to the body's wall
@@ -345,8 +347,26 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
     c->n_seg = 0;
     if (nw == 0) return FSI_OK;
     const fsi_body_desc &b = c->bodies[0];
-    if (b.dof != FSI_DOF_FIXED || b.link >= 0)
-        return fail(c, FSI_E_ARG, "a body on a Q9 mesh is fixed (FSI_DOF_FIXED, no link)");
+    if (b.link >= 0) return fail(c, FSI_E_ARG, "a body on a Q9 mesh has no link");
+    c->q9_moving = b.dof != FSI_DOF_FIXED;
+    if (c->q9_moving) {
+        if (b.blend_mode != 0 || !(b.r_blend > b.r_rigid))
+            return fail(c, FSI_E_ARG, "a moving body on a Q9 mesh blends radially (blend_mode 0, r_blend > r_rigid)");
+        // the wall nodes' elements move rigidly with the body (B is placed
+        // in the undeformed frame)
+        for (int k = 0; k < nw; ++k) {
+            const int v = c->qw_nodes[k];
+            for (int q = c->patch_off[v]; q < c->patch_off[v + 1]; ++q) {
+                const int e = c->patch_ent[q] >> 4;
+                for (int a = 0; a < 9; ++a) {
+                    const int u = c->elems[9 * (size_t)e + a];
+                    if (blend_r(b, c->X[2 * (size_t)u], c->X[2 * (size_t)u + 1]) != 0.0)
+                        return fail(c, FSI_E_ARG, "the elements at the wall must lie in the moving body's rigid zone "
+                                                  "(r_rigid too small)");
+                }
+            }
+        }
+    }
     const double dt = c->fluid.dt;
     for (int k = 0; k < nw; ++k) {
         const int v = c->qw_nodes[k], vm = c->qw_nodes[(k + nw - 1) % nw], vp = c->qw_nodes[(k + 1) % nw];
@@ -799,6 +819,10 @@ void layout(fsi_ctx *c) {
         c->off_qweB = take(c->qw_eB.size() * 4);
         c->off_qwxyB = take(c->qw_xyB.size() * sizeof(float2));
         c->off_qwprev = take(c->qw_nodes.size() * sizeof(float2));
+        if (c->q9_moving) {
+            c->off_qdisp = take(2 * N * sizeof(double2));
+            c->off_uegd = take(9 * (size_t)c->n_elems * sizeof(float4));
+        }
         if (!c->bh_off.empty()) {
             c->off_bh_off = take(c->bh_off.size() * 4);
             c->off_bh_nodes = take(c->bh_nodes.size() * 4);
@@ -827,9 +851,14 @@ const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c
 fsi_status enqueue_fluid(fsi_ctx *c) {
     const int st = c->fluid.storage;
     if (c->topo == FSI_TOPO_Q9) {
+        // a moving body: the mesh of both levels and the departure points on it
+        if (c->q9_moving)
+            HIP_TRY(c, fsi::launch_unstructured_motion(d_inst(c), (long long)c->ni, (long long)c->n_elems, 1,
+                                                       c->stream));
         HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, st,
                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
-                                            c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->stream));
+                                            c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->inst.qdisp,
+                                            c->stream));
         if (!c->qw_nodes.empty() || !c->qf_nodes.empty())
             HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(),
                                                          (int)c->qf_nodes.size(), st, 1, c->stream));
@@ -870,6 +899,9 @@ fsi_status enqueue_load_update(fsi_ctx *c) {
     // (each step's interpolation forms them for the populations it writes)
     if (c->topo == FSI_TOPO_Q9) {
         HIP_TRY(c, fsi::launch_unstructured_moments(d_inst(c), (long long)c->ni, c->fluid.storage, c->stream));
+        if (c->q9_moving)
+            HIP_TRY(c, fsi::launch_unstructured_motion(d_inst(c), (long long)c->ni, (long long)c->n_elems, 0,
+                                                       c->stream));
         if (!c->qw_nodes.empty())
             HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(), 0,
                                                          c->fluid.storage, 0, c->stream));
@@ -1052,6 +1084,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.qw_eB = reinterpret_cast<const int *>(c->ws + c->off_qweB);
         P.qw_xyB = reinterpret_cast<const float2 *>(c->ws + c->off_qwxyB);
         P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
+        P.qdisp = c->q9_moving ? reinterpret_cast<double2 *>(c->ws + c->off_qdisp) : nullptr;
+        P.uegd = c->q9_moving ? reinterpret_cast<float4 *>(c->ws + c->off_uegd) : nullptr;
         {
             const std::pair<size_t, std::pair<const void *, size_t>> up[] = {
                 {c->off_qflag, {c->qflag.data(), c->qflag.size()}},
@@ -1413,7 +1447,8 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
             if (which == 0 && c->topo == FSI_TOPO_Q9)
                 e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, stg,
                                              c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
-                                             c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->stream);
+                                             c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->inst.qdisp,
+                                             c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
                                                c->cut, 0);

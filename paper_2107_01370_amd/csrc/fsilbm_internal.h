@@ -139,6 +139,9 @@ struct Inst {
     const int *qw_eB;         // [n_qw] element holding the point B
     const float2 *qw_xyB;     // [n_qw] local coordinates of B there
     float2 *qw_prev;          // [n_qw] (rho, T) of the completed wall node, previous level
+    // a moving body on a Q9 mesh (null: fixed)
+    double2 *qdisp;           // [2][n_nodes] blended displacement at levels n, n+1
+    float4 *uegd;             // [n_elems][9] derivatives of the level-(n+1) displacement
 };
 
 // nodes per block of the LDS-staged interpolation
@@ -173,7 +176,11 @@ hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_wor
 hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
                                float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
-                               int eu16, hipStream_t s);
+                               int eu16, const double2 *disp0, hipStream_t s);
+// a moving body on a Q9 mesh: node displacements of levels n and n+1, and
+// (relocate) the departure points on the moving mesh
+hipError_t launch_unstructured_motion(const Inst *inst, long long n_nodes, long long n_elems, int relocate,
+                                      hipStream_t s);
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s);
 hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int storage, hipStream_t s);
 // far field, wall targets, Grad populations and traction (phase 1), or

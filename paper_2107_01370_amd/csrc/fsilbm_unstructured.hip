@@ -66,7 +66,8 @@ __device__ __forceinline__ float dlag_at(int p, int x) {
 // each line sum to zero) make the derivative of a constant field exactly zero.
 __global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ pinst,
                                                        const float2 *__restrict__ v,
-                                                       float2 *__restrict__ eg) {
+                                                       float2 *__restrict__ eg,
+                                                       const double2 *__restrict__ disp) {
     const Inst &P = *pinst;
     for (long long e = xcd_block() * blockDim.x + threadIdx.x; e < P.n_elems;
          e += (long long)gridDim.x * blockDim.x) {
@@ -75,6 +76,17 @@ __global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ 
         for (int s = 0; s < 9; ++s) {
             val[s] = v[P.elems[9 * e + s]];
             rel[s] = P.erel[9 * e + s];
+        }
+        if (disp) {
+            // the deformed element: offsets from the centre node plus the
+            // displacement differences (formed in FP64, rounded once)
+            const double2 dc = disp[P.elems[9 * e + 8]];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const double2 ds = disp[P.elems[9 * e + s]];
+                rel[s].x += (float)(ds.x - dc.x);
+                rel[s].y += (float)(ds.y - dc.y);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
@@ -216,13 +228,102 @@ __global__ void __launch_bounds__(U_THREADS) k_u_collide(const Inst *__restrict_
     if (err) atomicOr(P.err, err);
 }
 
-// Departure points of a static mesh: for every node and moving direction the
-// element of the node's patch whose corner (first-order) map holds
-// X - dt c_k, and the local coordinates there (Newton from the node's own
-// position, FP32 offsets from the element's centre node).  Run once when the
-// workspace is bound; ERR_CFL if a point lies outside every element of the
-// patch.
-__global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__ pinst) {
+// Mesh motion of a moving body (Sec. II.D): the blended displacement
+// (1 - r)(G'(X) - X) of every node at levels n and n+1 (FP64), for the
+// departure points, the deformed elements and the wall.
+__global__ void __launch_bounds__(U_THREADS) k_u_motion(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const long long n = *P.step;
+    const BodySlot s0 = P.slots[(n % 3) * MAX_BODIES], s1 = P.slots[((n + 1) % 3) * MAX_BODIES];
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const double2 X = P.X[idx];
+        const double om = 1.0 - blend_factor(P, 0, idx, X.x, X.y);
+        double d0x, d0y, d1x, d1y;
+        rigid_disp(P.body[0], s0, X.x, X.y, d0x, d0y);
+        rigid_disp(P.body[0], s1, X.x, X.y, d1x, d1y);
+        P.qdisp[idx] = make_double2(om * d0x, om * d0y);
+        P.qdisp[P.n_nodes + idx] = make_double2(om * d1x, om * d1y);
+    }
+}
+
+// Element pass of the displacement's derivatives on the undeformed mesh at
+// level n+1, at each element node: (d dx/dX, d dx/dY, d dy/dX, d dy/dY)
+__global__ void __launch_bounds__(U_THREADS) k_u_dgrad(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const double2 *d1 = P.qdisp + P.n_nodes;
+    for (long long e = xcd_block() * blockDim.x + threadIdx.x; e < P.n_elems;
+         e += (long long)gridDim.x * blockDim.x) {
+        double2 dv[9];
+        float2 rel[9];
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            dv[s] = d1[P.elems[9 * e + s]];
+            rel[s] = P.erel[9 * e + s];
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int pa = q9_p(a), qa = q9_q(a);
+            float axi = 0.0f, aeta = 0.0f, bxi = 0.0f, beta = 0.0f;
+            float xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
+#pragma unroll
+            for (int m = -1; m <= 1; ++m) {
+                if (m != pa) {
+                    const int si = q9_node(m, qa);
+                    const float w = dlag_at(m, pa);
+                    axi += w * (float)(dv[si].x - dv[a].x);
+                    bxi += w * (float)(dv[si].y - dv[a].y);
+                    xxi += w * (rel[si].x - rel[a].x);
+                    yxi += w * (rel[si].y - rel[a].y);
+                }
+                if (m != qa) {
+                    const int sj = q9_node(pa, m);
+                    const float w = dlag_at(m, qa);
+                    aeta += w * (float)(dv[sj].x - dv[a].x);
+                    beta += w * (float)(dv[sj].y - dv[a].y);
+                    xeta += w * (rel[sj].x - rel[a].x);
+                    yeta += w * (rel[sj].y - rel[a].y);
+                }
+            }
+            const float idet = 1.0f / (xxi * yeta - yxi * xeta);
+            P.uegd[9 * e + a] = make_float4(idet * (yeta * axi - yxi * aeta), idet * (-xeta * axi + xxi * aeta),
+                                            idet * (yeta * bxi - yxi * beta), idet * (-xeta * bxi + xxi * beta));
+        }
+    }
+}
+
+// Local coordinates of the point at offset (px, py) from local node a of
+// element e under the element's corner map (Newton in FP32 from (u, v))
+__device__ __forceinline__ void q9_corner_newton(const Inst &P, long long e, int a, float px, float py,
+                                                 int iters, float &u, float &v) {
+    const float2 *rel = P.erel + 9 * e;
+    const float2 c0 = rel[0], c1 = rel[1], c2 = rel[2], c3 = rel[3], ra = rel[a];
+    px += ra.x;
+    py += ra.y;
+    for (int it = 0; it < iters; ++it) {
+        const float n0 = (1 - u) * (1 - v), n1 = (1 + u) * (1 - v);
+        const float n2 = (1 + u) * (1 + v), n3 = (1 - u) * (1 + v);
+        const float rx = 0.25f * (n0 * c0.x + n1 * c1.x + n2 * c2.x + n3 * c3.x) - px;
+        const float ry = 0.25f * (n0 * c0.y + n1 * c1.y + n2 * c2.y + n3 * c3.y) - py;
+        const float ja = 0.25f * (-(1 - v) * c0.x + (1 - v) * c1.x + (1 + v) * c2.x - (1 + v) * c3.x);
+        const float jb = 0.25f * (-(1 - u) * c0.x - (1 + u) * c1.x + (1 + u) * c2.x + (1 - u) * c3.x);
+        const float jc = 0.25f * (-(1 - v) * c0.y + (1 - v) * c1.y + (1 + v) * c2.y - (1 + v) * c3.y);
+        const float jd = 0.25f * (-(1 - u) * c0.y - (1 + u) * c1.y + (1 + u) * c2.y + (1 - u) * c3.y);
+        const float id = 1.0f / (ja * jd - jb * jc);
+        u -= id * (jd * rx - jb * ry);
+        v -= id * (-jc * rx + ja * ry);
+    }
+}
+
+// Departure points: for every node and moving direction the element of the
+// node's patch whose corner (first-order) map holds X - dt c_hat_k in the
+// undeformed frame, and the local coordinates there (Newton in FP32 offsets
+// from the element's centre node).  moving == 0: a static mesh (c_hat = c),
+// once when the workspace is bound, Newton from the node's own position;
+// moving == 1: every step of a moving body, c_hat = g^{-1}(c - V_G), the
+// previous step's element tried first from its local coordinates.  ERR_CFL
+// if an interior node's point lies outside every element of its patch.
+__global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__ pinst, int moving) {
     const Inst &P = *pinst;
     const float dt = P.dt;
     unsigned err = 0;
@@ -230,29 +331,56 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
          idx += (long long)gridDim.x * blockDim.x) {
         const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
         const bool bnd = P.n_qw + P.n_qf > 0 && P.qflag[idx] != 0;
+        // moving mesh: c_hat = g^{-1}(c - V_G), g = I + dd/dX (nodal mean of
+        // the element derivatives), V_G = (d^{n+1} - d^n) / dt
+        float g00 = 1.0f, g01 = 0.0f, g10 = 0.0f, g11 = 1.0f, vgx = 0.0f, vgy = 0.0f;
+        if (moving) {
+            float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
+            for (int q = b; q < e_end; ++q) {
+                const int ent = P.patch_ent[q];
+                const float4 dg = P.uegd[9 * (long long)(ent >> 4) + (ent & 15)];
+                s00 += dg.x;
+                s01 += dg.y;
+                s10 += dg.z;
+                s11 += dg.w;
+            }
+            const float inv = 1.0f / (float)(e_end - b);
+            g00 += s00 * inv;
+            g01 += s01 * inv;
+            g10 += s10 * inv;
+            g11 += s11 * inv;
+            const double2 d0 = P.qdisp[idx], d1 = P.qdisp[P.n_nodes + idx];
+            vgx = (float)((d1.x - d0.x) / P.dt_d);
+            vgy = (float)((d1.y - d0.y) / P.dt_d);
+        }
+        const float idg = 1.0f / (g00 * g11 - g01 * g10);
         for (int k = 1; k < 9; ++k) {
-            const float dx = -dt * (float)CXK(k), dy = -dt * (float)CYK(k);
+            const float ax = (float)CXK(k) - vgx, ay = (float)CYK(k) - vgy;
+            const float dx = -dt * idg * (g11 * ax - g01 * ay);
+            const float dy = -dt * idg * (-g10 * ax + g00 * ay);
             int e_found = -1;
             float xi = 0.0f, eta = 0.0f;
+            // the previous step's element first (from its local coordinates)
+            const int e_prev = moving ? P.dep_e[(k - 1) * P.n_nodes + idx] : -1;
+            if (e_prev >= 0) {
+                int a = -1;
+                for (int q = b; q < e_end; ++q)
+                    if ((P.patch_ent[q] >> 4) == e_prev) a = P.patch_ent[q] & 15;
+                if (a >= 0) {
+                    const float2 prev = P.dep_xy[(k - 1) * P.n_nodes + idx];
+                    float u = prev.x, v = prev.y;
+                    q9_corner_newton(P, e_prev, a, dx, dy, 4, u, v);
+                    if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
+                        e_found = e_prev;
+                        xi = u;
+                        eta = v;
+                    }
+                }
+            }
             for (int q = b; q < e_end && e_found < 0; ++q) {
                 const int ent = P.patch_ent[q], e = ent >> 4, a = ent & 15;
-                const float2 *rel = P.erel + 9 * (long long)e;
-                const float2 c0 = rel[0], c1 = rel[1], c2 = rel[2], c3 = rel[3], ra = rel[a];
-                const float px = ra.x + dx, py = ra.y + dy;
                 float u = (float)q9_p(a), v = (float)q9_q(a);
-                for (int it = 0; it < 8; ++it) {
-                    const float n0 = (1 - u) * (1 - v), n1 = (1 + u) * (1 - v);
-                    const float n2 = (1 + u) * (1 + v), n3 = (1 - u) * (1 + v);
-                    const float rx = 0.25f * (n0 * c0.x + n1 * c1.x + n2 * c2.x + n3 * c3.x) - px;
-                    const float ry = 0.25f * (n0 * c0.y + n1 * c1.y + n2 * c2.y + n3 * c3.y) - py;
-                    const float ja = 0.25f * (-(1 - v) * c0.x + (1 - v) * c1.x + (1 + v) * c2.x - (1 + v) * c3.x);
-                    const float jb = 0.25f * (-(1 - u) * c0.x - (1 + u) * c1.x + (1 + u) * c2.x + (1 - u) * c3.x);
-                    const float jc = 0.25f * (-(1 - v) * c0.y + (1 - v) * c1.y + (1 + v) * c2.y - (1 + v) * c3.y);
-                    const float jd = 0.25f * (-(1 - u) * c0.y - (1 + u) * c1.y + (1 + u) * c2.y + (1 - u) * c3.y);
-                    const float id = 1.0f / (ja * jd - jb * jc);
-                    u -= id * (jd * rx - jb * ry);
-                    v -= id * (-jc * rx + ja * ry);
-                }
+                q9_corner_newton(P, e, a, dx, dy, 8, u, v);
                 if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
                     e_found = e;
                     xi = u;
@@ -523,14 +651,22 @@ __global__ void __launch_bounds__(64) k_u_wall_targets(const Inst *__restrict__ 
     P.wall_tgt[k] = make_float4(rho_t, 0.0f, 0.0f, T_t);
 }
 
+// mesh velocity V_G = (d^{n+1} - d^n) / dt of node v (moving body)
+__device__ __forceinline__ float2 q9_mesh_velocity(const Inst &P, long long v) {
+    const double2 d0 = P.qdisp[v], d1 = P.qdisp[P.n_nodes + v];
+    return make_float2((float)((d1.x - d0.x) / P.dt_d), (float)((d1.y - d0.y) / P.dt_d));
+}
+
 // (u_x, u_y, T, E) of node v for a wall node's gradient: the target at wall
-// nodes (fixed body: u = 0), the moments of the new populations elsewhere
+// nodes (the wall's mesh velocity, zero for a fixed body), the moments of the
+// new populations elsewhere
 template <int STORE>
 __device__ float4 q9_wall_field(const Inst &P, const void *buf, long long v) {
     const int wi = P.qw_idx[v];
     if (wi >= 0) {
         const float T = P.wall_tgt[wi].w;
-        return make_float4(0.0f, 0.0f, T, P.Cv * T);
+        const float2 u = P.qdisp ? q9_mesh_velocity(P, v) : make_float2(0.0f, 0.0f);
+        return make_float4(u.x, u.y, T, P.Cv * T + 0.5f * (u.x * u.x + u.y * u.y));
     }
     float f[9], g[9];
 #pragma unroll
@@ -574,14 +710,18 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
     for (int q = 1; q < 9; ++q)
         if (P.dep_e[(q - 1) * P.n_nodes + w] < 0) miss |= 1u << q;
     const float4 t0 = P.wall_tgt[k];
-    const float T_t = t0.w, E_t = P.Cv * T_t;
+    const bool mv = P.qdisp != nullptr;
+    // the wall's mesh velocity (no slip), the displacements of the level
+    const float2 uw = mv && phase ? q9_mesh_velocity(P, w) : make_float2(0.0f, 0.0f);
+    const double2 *dL = mv ? P.qdisp + (phase ? P.n_nodes : 0) : nullptr;
+    const float T_t = t0.w, E_t = P.Cv * T_t + 0.5f * (uw.x * uw.x + uw.y * uw.y);
     const bool fill = phase && miss;
     if (fill) {
         // nodal derivative: mean over the node's elements of the element
         // derivative at the node (the nodes on its two element lines), the
         // wall nodes at their targets
         const int b = P.patch_off[w], e_end = P.patch_off[w + 1];
-        const float4 Ca = make_float4(0.0f, 0.0f, T_t, E_t);
+        const float4 Ca = make_float4(uw.x, uw.y, T_t, E_t);
         float acc[4][2] = {};
         for (int base = b; base < e_end; base += U_WALL_ENT) {
             const int cnt = min(U_WALL_ENT, e_end - base);
@@ -605,7 +745,12 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
                     wall_line_node(a, r, sn, wt);
                     const float4 C = sval[t][r];
                     const float dC[4] = {C.x - Ca.x, C.y - Ca.y, C.z - Ca.z, C.w - Ca.w};
-                    const float dx = rel[sn].x - rel[a].x, dy = rel[sn].y - rel[a].y;
+                    float dx = rel[sn].x - rel[a].x, dy = rel[sn].y - rel[a].y;
+                    if (mv) {                 // the deformed element of the new level
+                        const double2 ds = dL[P.elems[9 * (long long)e + sn]], da = dL[P.elems[9 * (long long)e + a]];
+                        dx += (float)(ds.x - da.x);
+                        dy += (float)(ds.y - da.y);
+                    }
                     if (r < 2) {
                         for (int c = 0; c < 4; ++c) ax[c] += wt * dC[c];
                         xxi += wt * dx;
@@ -647,7 +792,7 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
         g[q] = pop_load<STORE>(P, buf, Q + q, w);
     }
     if (fill) {
-        grad_populations(P, miss, t0.x, 0.0f, 0.0f, T_t, E_t, sgrad[0][0], sgrad[0][1], sgrad[1][0],
+        grad_populations(P, miss, t0.x, uw.x, uw.y, T_t, E_t, sgrad[0][0], sgrad[0][1], sgrad[1][0],
                          sgrad[1][1], sgrad[2][0], sgrad[2][1], sgrad[3][0], sgrad[3][1], f, g);
 #pragma unroll
         for (int q = 1; q < 9; ++q) {
@@ -662,7 +807,17 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
     // traction of the complete wall node; its (rho, T) for the next targets
     double sxx, sxy, syy;
     const bool ok = wall_stress(P, f, g, sxx, sxy, syy);
-    const double4 geo = P.qw_geo[k];
+    double4 geo = P.qw_geo[k];
+    if (mv) {
+        // lumped normal and moment arm on the mesh of the level
+        const int nw = P.n_qw;
+        const long long vm = P.qw_nodes[(k + nw - 1) % nw], vp = P.qw_nodes[(k + 1) % nw];
+        const double2 Xm = P.X[vm], Xp = P.X[vp], Xw = P.X[w];
+        const double2 dm = dL[vm], dp = dL[vp], dw = dL[w];
+        const double h = P.slots[((phase ? n + 1 : n) % 3) * MAX_BODIES].h;
+        geo = make_double4(-0.5 * ((Xp.y + dp.y) - (Xm.y + dm.y)), 0.5 * ((Xp.x + dp.x) - (Xm.x + dm.x)),
+                           Xw.x + dw.x - P.body[0].ex, Xw.y + dw.y - (P.body[0].ey + h));
+    }
     const double Fx = sxx * geo.x + sxy * geo.y;
     const double Fy = sxy * geo.x + syy * geo.y;
     P.wall_force[k] = make_double4(Fx, Fy, geo.z * Fy - geo.w * Fx, 0.0);
@@ -676,7 +831,7 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
 // ---------------------------------------------------------------------------
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s) {
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
-    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst);
+    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst, 0);
     return hipGetLastError();
 }
 
@@ -688,14 +843,14 @@ hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int 
 
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
                                float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
-                               int eu16, hipStream_t s) {
+                               int eu16, const double2 *disp0, hipStream_t s) {
     // multiples of the XCD count (see xcd_block)
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
     const long long e64 = ((n_elems + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
     const dim3 grid((unsigned)(g64 > 0 ? g64 : 8)), egrid((unsigned)(e64 > 0 ? e64 : 8)), block(U_THREADS);
-    hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, uq, ueg);
+    hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, uq, ueg, disp0);
     hipLaunchKernelGGL(k_u_nodeD, grid, block, 0, s, inst);
-    hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, ud, ueg);
+    hipLaunchKernelGGL(k_u_egrad, egrid, block, 0, s, inst, ud, ueg, disp0);
     if (n_blocks > 0) {
         // a multiple of the XCD count; the kernel maps slots to blocks
         const unsigned g = (unsigned)(((n_blocks + 7) / 8) * 8);
@@ -715,6 +870,18 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
     } else {
         FSI_DISPATCH(storage, k_u_collide, grid, block, s, inst);
         FSI_DISPATCH(storage, k_u_stream, grid, block, s, inst);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unstructured_motion(const Inst *inst, long long n_nodes, long long n_elems, int relocate,
+                                      hipStream_t s) {
+    const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    const long long e64 = ((n_elems + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    hipLaunchKernelGGL(k_u_motion, dim3((unsigned)g64), dim3(U_THREADS), 0, s, inst);
+    if (relocate) {
+        hipLaunchKernelGGL(k_u_dgrad, dim3((unsigned)e64), dim3(U_THREADS), 0, s, inst);
+        hipLaunchKernelGGL(k_u_locate, dim3((unsigned)g64), dim3(U_THREADS), 0, s, inst, 1);
     }
     return hipGetLastError();
 }

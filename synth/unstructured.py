@@ -383,9 +383,11 @@ def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: 
                   symmetric: bool = False):
     """A cylinder on the unstructured mesh of `cylinder_q9_mesh` in gas at
     rest, moving along y: prescribed heave h = A sin(w t) (dof 0; A = amp_D D,
-    peak speed Ma_body times the speed of sound), or released from h0 = A on a
-    spring (dof 1, mass ratio mstar, reduced velocity ustar against the same
-    speed).  Blending: rigid out to R + D/4, blended out to R + 2D.
+    peak speed Ma_body times the speed of sound), or released at h0 = A with
+    that peak speed on a spring (dof 1, mass ratio mstar, reduced velocity
+    ustar against the same speed; the initial speed makes the fluid's load
+    large against the rounding of single-precision populations, which a body
+    released from rest feels only at that level in the first steps).  Blending: rigid out to R + D/4, blended out to R + 2D.
     symmetric: the mesh is its own mirror image about the y axis (the line of
     the motion).
     dt = (smallest patch reach) / (3 sqrt 2).  Returns (mesh, fluid, body,
@@ -405,6 +407,6 @@ def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: 
     body = BodyParams(dof=dof, m=m, k_h=k_h, center=(0.0, 0.0), ea=(0.0, 0.0),
                       r_rigid=R + 0.25 * D, r_blend=R + 2.0 * D,
                       heave_amp=A if dof == 0 else 0.0, heave_freq=w / (2.0 * np.pi) if dof == 0 else 0.0,
-                      h0=A if dof == 1 else 0.0)
+                      h0=A if dof == 1 else 0.0, hd0=U if dof == 1 else 0.0)
     N = mesh.n_nodes
     return mesh, fluid, body, (np.ones(N), np.zeros(N), np.zeros(N), np.full(N, T0))
