@@ -118,6 +118,11 @@ WORKLOADS = {
                                         "elements (2,103,296 nodes) round a fixed cylinder (D 640, "
                                         "far field 8 D), Ma 0.2, Re 1000, Grad wall, free-stream "
                                         "far field",
+    "unstructured_cylinder_heave_q9_2103296": "the same unstructured mesh round a cylinder in "
+                                              "prescribed heave (0.1 D, St 0.2) in the same "
+                                              "stream, blended mesh motion (rigid to R + D/4, "
+                                              "blended to R + 2 D), departure points located "
+                                              "every step",
 }
 
 
@@ -138,6 +143,8 @@ def workload_case(name: str, storage: int):
         return unstructured_case(256, storage)
     if name == "unstructured_cylinder_q9_2103296":
         return unstructured_cylinder_case(512, 640.0, storage)
+    if name == "unstructured_cylinder_heave_q9_2103296":
+        return unstructured_cylinder_case(512, 640.0, storage, heave_D=0.1)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -149,12 +156,14 @@ def unstructured_case(m: int, storage: int):
                 T[None])
 
 
-def unstructured_cylinder_case(n_theta: int, D: float, storage: int):
+def unstructured_cylinder_case(n_theta: int, D: float, storage: int, heave_D: float = 0.0):
     from synth.configs import Case
     from synth.unstructured import q9_cylinder_case
     mesh, fluid, body, (rho, ux, uy, T) = q9_cylinder_case(n_theta, D, 8.0, seed=1, Ma=0.2,
-                                                          Re=1000.0, storage=storage)
-    return Case(f"unstructured_cylinder_q9_{mesh.n_nodes}", mesh, fluid, [body], rho[None],
+                                                          Re=1000.0, storage=storage,
+                                                          heave_D=heave_D)
+    kind = "cylinder_heave" if heave_D > 0.0 else "cylinder"
+    return Case(f"unstructured_{kind}_q9_{mesh.n_nodes}", mesh, fluid, [body], rho[None],
                 ux[None], uy[None], T[None])
 
 
@@ -286,7 +295,8 @@ def cpu_baseline_unstructured(target_s: float = 20.0, m: int = 48):
             "sample": sample}, accuracy
 
 
-def cpu_baseline_unstructured_cylinder(target_s: float = 20.0, n_theta: int = 64):
+def cpu_baseline_unstructured_cylinder(target_s: float = 20.0, n_theta: int = 64,
+                                       heave_D: float = 0.0):
     """Oracle (plain FP64 NumPy) timed on a smaller mesh of the same
     construction round the same body shape and physics (n_theta = 64,
     D = 80), started from the populations the GPU path initialises; returns
@@ -294,7 +304,7 @@ def cpu_baseline_unstructured_cylinder(target_s: float = 20.0, n_theta: int = 64
     from oracle.unstructured import UnstructuredWallSolver
     from paper_2107_01370_amd.fsilbm import Simulation
 
-    case = unstructured_cylinder_case(n_theta, 80.0, 0)
+    case = unstructured_cylinder_case(n_theta, 80.0, 0, heave_D=heave_D)
     mesh, fluid, body = case.mesh, case.fluid, case.bodies[0]
     rho, ux, uy, T = case.rho[0], case.ux[0], case.uy[0], case.T[0]
     sim = Simulation(mesh, fluid, [body], device="cuda:0")
@@ -522,7 +532,9 @@ def main():
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
             out["cpu_baseline"], out["accuracy"] = (
-                cpu_baseline_unstructured_cylinder() if args.workload.startswith("unstructured_cyl")
+                cpu_baseline_unstructured_cylinder(
+                    heave_D=0.1 if "heave" in args.workload else 0.0)
+                if args.workload.startswith("unstructured_cyl")
                 else cpu_baseline_unstructured() if args.workload.startswith("unstructured")
                 else cpu_baseline(case))
     print(json.dumps(out), flush=True)

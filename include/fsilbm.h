@@ -111,21 +111,31 @@ typedef struct {
  *              be 2).  Junction copies merge and slit copies are kept
  *              single-valued as on a C-grid.
  *   Q9:        unstructured mesh of 9-node quadrilateral elements (the
- *              paper's own discretisation, Sec. II.B), static: periodic
+ *              paper's own discretisation, Sec. II.B): periodic and static
  *              (period shift_i[0] along x, shift_j[1] along y, shifts used by
- *              `elem_shifts`), or bounded, round one fixed body
- *              (FSI_DOF_FIXED): `wall_nodes` the body polygon, clockwise (a
- *              +90 degree rotation of its tangent points into the fluid),
- *              `far_nodes` the outer boundary.  A boundary node's population
- *              whose departure point lies in none of the node's elements is
- *              missing: far-field nodes take the free-stream equilibrium, wall
- *              nodes Grad's populations (u = 0; rho, T interpolated at
- *              B = x + dt n in the element of the node that holds it, the
- *              wall nodes there at their previous values; gradients by the
- *              nodal finite-element derivative with the wall nodes at their
- *              targets).  The force is sigma . (n ds) summed over the wall
- *              polygon, (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2, the moment
- *              about the body's `ea`.  ni = number of nodes, nj = 1; X holds the
+ *              `elem_shifts`), or bounded, round one body: `wall_nodes` the
+ *              body polygon, clockwise (a +90 degree rotation of its tangent
+ *              points into the fluid), `far_nodes` the outer boundary.  A
+ *              boundary node's population whose departure point lies in none
+ *              of the node's elements is missing: far-field nodes take the
+ *              free-stream equilibrium, wall nodes Grad's populations (u = the
+ *              wall node's mesh velocity, 0 for FSI_DOF_FIXED; rho, T
+ *              interpolated at B = X + dt n in the undeformed element of the
+ *              node that holds it, the wall nodes there at their previous
+ *              values; gradients by the nodal finite-element derivative on the
+ *              mesh of the new level with the wall nodes at their targets).
+ *              The force is sigma . (n ds) summed over the wall polygon,
+ *              (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2 on the mesh of the
+ *              level, the moment about the body's displaced `ea`.  A moving
+ *              body (any dof but FSI_DOF_FIXED) blends radially (blend_mode
+ *              0) and its rigid zone must hold every element at the wall
+ *              (FSI_E_ARG otherwise); nodes move by the blending of Sec. II.D
+ *              and each step locates the departure points
+ *              X - dt g^{-1}(c - V_G) anew among the node's undeformed
+ *              elements (g = dx/dX, V_G the node's mesh velocity), trying the
+ *              previous step's element first; an interior point outside its
+ *              elements is reported as FSI_E_CFL at the next synchronising
+ *              call.  ni = number of nodes, nj = 1; X holds the
  *              node coordinates; `elems` [n_elems][9] the nodes of each
  *              element in the order corners (-1,-1), (1,-1), (1,1), (-1,1),
  *              edge midpoints (0,-1), (1,0), (0,1), (-1,0), centre (0,0),
@@ -222,8 +232,9 @@ fsi_status fsi_workspace_bytes(const fsi_ctx *ctx, size_t *bytes);
 
 /* Lend `bytes` of device memory at `dev_ptr` (256-byte aligned) to the
  * context and upload the static data.  Synchronises the stream.  Q9 meshes:
- * also locates every departure point of the static mesh once; FSI_E_CFL if
- * one lies outside the elements of its node (dt too large for the mesh). */
+ * also locates every departure point of the undeformed mesh once (a moving
+ * body relocates them every step); FSI_E_CFL if one lies outside the
+ * elements of its node (dt too large for the mesh). */
 fsi_status fsi_bind_workspace(fsi_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Initial populations = equilibria (f^eq, g^eq with Psi) of the given host

@@ -366,6 +366,21 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
                 }
             }
         }
+        // nodes the blending moves (Q9_MOVES: closer to the centre than
+        // r_blend, with a margin far above rounding) and nodes whose patch
+        // holds one (Q9_PATCH_MOVES); the departure points of the others keep
+        // their values of the undeformed mesh
+        const int N = c->ni;
+        const double reach = b.r_blend * (1.0 + 1e-9);
+        for (int v = 0; v < N; ++v)
+            if (hypot(c->X[2 * (size_t)v] - b.center[0], c->X[2 * (size_t)v + 1] - b.center[1]) < reach)
+                c->qflag[v] |= fsi::Q9_MOVES;
+        for (int v = 0; v < N; ++v)
+            for (int q = c->patch_off[v]; q < c->patch_off[v + 1]; ++q) {
+                const int e = c->patch_ent[q] >> 4;
+                for (int a = 0; a < 9; ++a)
+                    if (c->qflag[c->elems[9 * (size_t)e + a]] & fsi::Q9_MOVES) c->qflag[v] |= fsi::Q9_PATCH_MOVES;
+            }
     }
     const double dt = c->fluid.dt;
     for (int k = 0; k < nw; ++k) {
@@ -432,7 +447,7 @@ fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
         const int v = wall ? mesh->wall_nodes[q] : mesh->far_nodes[q - mesh->n_wall_nodes];
         if (v < 0 || v >= N || c->qflag[v])
             return fail(c, FSI_E_MESH, "Q9 boundary node out of range or listed twice");
-        c->qflag[v] = wall ? 1 : 2;
+        c->qflag[v] = wall ? fsi::Q9_WALL : fsi::Q9_FAR;
         if (wall) {
             c->qw_idx[v] = q;
             c->qw_nodes.push_back(v);

@@ -23,6 +23,11 @@ constexpr int HIST_CAP = 1 << 16;   // force / displacement history records kept
 constexpr unsigned ERR_CFL = 1u;    // departure point outside the node's cells
 constexpr unsigned ERR_STATE = 2u;  // rho<=0, T<=0, T>=1, Phi_0<=0, NaN
 constexpr unsigned ERR_MESH = 4u;   // det(dx/dxi) <= 0 after blending
+// node flags of bounded Q9 meshes
+constexpr uint8_t Q9_WALL = 1, Q9_FAR = 2;              // boundary nodes
+constexpr uint8_t Q9_BOUNDARY = Q9_WALL | Q9_FAR;
+constexpr uint8_t Q9_MOVES = 4;                         // the body's blending moves the node
+constexpr uint8_t Q9_PATCH_MOVES = 8;                   // a node of its elements moves
 
 enum Dof { DOF_PRESCRIBED = 0, DOF_HEAVE = 1, DOF_PITCH_PLUNGE = 2, DOF_FIXED = 3 };
 
@@ -131,7 +136,7 @@ struct Inst {
     uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
     // unstructured meshes round a fixed body: wall and far-field nodes
     int n_qw, n_qf;
-    const uint8_t *qflag;     // [n_nodes] 1 wall node, 2 far-field node, 0 interior
+    const uint8_t *qflag;     // [n_nodes] Q9_WALL, Q9_FAR (else interior), Q9_MOVES, Q9_PATCH_MOVES
     const int *qw_nodes;      // [n_qw] wall polygon, clockwise
     const int *qw_idx;        // [n_nodes] position in qw_nodes, -1 elsewhere
     const int *qf_nodes;      // [n_qf]

@@ -8,8 +8,9 @@ namespace fsi {
 
 // ---------------------------------------------------------------------------
 // Unstructured meshes of 9-node quadrilateral elements (Sec. II.B on the
-// paper's own finite-element meshes), static and periodic.  Node-wise
-// kernels, data reached through the element connectivity:
+// paper's own finite-element meshes): periodic, or bounded round one body,
+// fixed or moving.  Node-wise kernels, data reached through the element
+// connectivity:
 //   k_u_egrad    element derivatives at the element's nine nodes (of delta Q_a,
 //                which the previous step's interpolation formed with mu/p)
 //   k_u_nodeD    D_a = (mu/p) d_a delta Q_a at every node (nodal means)
@@ -23,6 +24,9 @@ namespace fsi {
 //                elements with the corner (first-order) map; then delta Q_a
 //                and mu/p of the new populations for the next step
 //                (k_u_moments forms them when the host sets populations)
+// and, for a moving body, before them: k_u_motion (blended displacements of
+// levels n and n+1), k_u_dgrad (their element derivatives) and k_u_relocate
+// (the departure points on the mesh of the new level, every step).
 // A nodal derivative is the mean over the node's elements of the element
 // derivative J^{-T} sum_s C_s grad_xi N_s at the node's own local position,
 // where only the three nodes on each of the node's element lines contribute
@@ -254,11 +258,24 @@ __global__ void __launch_bounds__(U_THREADS) k_u_dgrad(const Inst *__restrict__ 
     const double2 *d1 = P.qdisp + P.n_nodes;
     for (long long e = xcd_block() * blockDim.x + threadIdx.x; e < P.n_elems;
          e += (long long)gridDim.x * blockDim.x) {
+        int nd[9];
+        bool moves = false;
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            nd[s] = P.elems[9 * e + s];
+            moves |= (P.qflag[nd[s]] & Q9_MOVES) != 0;
+        }
+        if (!moves) {
+            // no node of the element moves: the derivatives are zero
+#pragma unroll
+            for (int a = 0; a < 9; ++a) P.uegd[9 * e + a] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            continue;
+        }
         double2 dv[9];
         float2 rel[9];
 #pragma unroll
         for (int s = 0; s < 9; ++s) {
-            dv[s] = d1[P.elems[9 * e + s]];
+            dv[s] = d1[nd[s]];
             rel[s] = P.erel[9 * e + s];
         }
 #pragma unroll
@@ -315,101 +332,203 @@ __device__ __forceinline__ void q9_corner_newton(const Inst &P, long long e, int
     }
 }
 
-// Departure points: for every node and moving direction the element of the
-// node's patch whose corner (first-order) map holds X - dt c_hat_k in the
-// undeformed frame, and the local coordinates there (Newton in FP32 offsets
-// from the element's centre node).  moving == 0: a static mesh (c_hat = c),
-// once when the workspace is bound, Newton from the node's own position;
-// moving == 1: every step of a moving body, c_hat = g^{-1}(c - V_G), the
-// previous step's element tried first from its local coordinates.  ERR_CFL
-// if an interior node's point lies outside every element of its patch.
-__global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__ pinst, int moving) {
+// The first element of a node's patch whose corner map holds the point at
+// offset (dx, dy) from the node (Newton from the node's own local position);
+// e = -1 if none does
+__device__ __forceinline__ void u_patch_search(const Inst &P, int b, int e_end, float dx, float dy, int &e,
+                                               float &xi, float &eta) {
+    for (int q = b; q < e_end && e < 0; ++q) {
+        const int ent = P.patch_ent[q], el = ent >> 4, a = ent & 15;
+        float u = (float)q9_p(a), v = (float)q9_q(a);
+        q9_corner_newton(P, el, a, dx, dy, 8, u, v);
+        if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
+            e = el;
+            xi = u;
+            eta = v;
+        }
+    }
+}
+
+// Departure table entry of node idx, direction k: element, local coordinates
+// and, with node blocks, the element's position in the block's ascending
+// element list (it holds every element of the node's patch); `changed` false
+// keeps the element entries (the point stayed in the same element)
+__device__ __forceinline__ void u_dep_store(const Inst &P, long long idx, int k, int e, float xi, float eta,
+                                            bool changed) {
+    const long long at = (long long)(k - 1) * P.n_nodes + idx;
+    P.dep_xy[at] = make_float2(xi, eta);
+    if (!changed) return;
+    P.dep_e[at] = e;
+    if (P.be_off && e < 0) {
+        P.dep_le[at] = U_MISSING;
+    } else if (P.be_off) {
+        const long long blk = idx / U_BLOCK;
+        int lo = P.be_off[blk], hi = P.be_off[blk + 1];
+        const int first = lo;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (P.be_elem[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        P.dep_le[at] = (uint16_t)(lo - first);
+    }
+}
+
+// Departure points of a static mesh, once when the workspace is bound: for
+// every node and moving direction the element of the node's patch whose
+// corner (first-order) map holds X - dt c_k, and the local coordinates there
+// (Newton in FP32 offsets from the element's centre node).  ERR_CFL if an
+// interior node's point lies outside every element of its patch; a boundary
+// node's point outside them lies outside the mesh: the population is missing
+// (set by the boundary kernels).
+__global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
     const float dt = P.dt;
     unsigned err = 0;
     for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
         const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
-        const bool bnd = P.n_qw + P.n_qf > 0 && P.qflag[idx] != 0;
-        // moving mesh: c_hat = g^{-1}(c - V_G), g = I + dd/dX (nodal mean of
-        // the element derivatives), V_G = (d^{n+1} - d^n) / dt
-        float g00 = 1.0f, g01 = 0.0f, g10 = 0.0f, g11 = 1.0f, vgx = 0.0f, vgy = 0.0f;
-        if (moving) {
-            float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
-            for (int q = b; q < e_end; ++q) {
-                const int ent = P.patch_ent[q];
-                const float4 dg = P.uegd[9 * (long long)(ent >> 4) + (ent & 15)];
+        const bool bnd = P.n_qw + P.n_qf > 0 && (P.qflag[idx] & Q9_BOUNDARY) != 0;
+        for (int k = 1; k < 9; ++k) {
+            int e = -1;
+            float xi = 0.0f, eta = 0.0f;
+            u_patch_search(P, b, e_end, -dt * (float)CXK(k), -dt * (float)CYK(k), e, xi, eta);
+            if (e < 0 && !bnd) {
+                err |= ERR_CFL;
+                e = P.patch_ent[b] >> 4;
+            }
+            u_dep_store(P, idx, k, e, xi, eta, true);
+        }
+    }
+    if (err) atomicOr(P.err, err);
+}
+
+// patch entries of a node held in registers by k_u_relocate (larger patches
+// take the rest from memory)
+constexpr int U_PATCH_REG = 8;
+
+// Departure points of a moving body, every step: X - dt g^{-1}(c_k - V_G) in
+// the undeformed frame, g = I + dd/dX at level n+1 (the nodal mean of the
+// element derivatives), V_G = (d^{n+1} - d^n) / dt; the previous step's
+// element is tried first, by Newton from its local coordinates, then the
+// patch in order as for a static mesh.  Two threads per node (neighbouring
+// lanes, directions 1-4 and 5-8), each issuing all loads it needs before
+// their first use (previous table entries, patch, element derivatives, then
+// the corners of the previous elements), so a thread waits on a few memory
+// round trips rather than one per direction.
+constexpr int U_REL_DIRS = 4;   // directions per thread
+__global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    const float dt = P.dt;
+    const long long N = P.n_nodes;
+    unsigned err = 0;
+    for (long long tid = xcd_block() * blockDim.x + threadIdx.x; tid < 2 * N;
+         tid += (long long)gridDim.x * blockDim.x) {
+        const long long idx = tid >> 1;
+        const int k0 = 1 + U_REL_DIRS * (int)(tid & 1);
+        // a patch the blending leaves in place keeps the undeformed mesh's
+        // departure points
+        const uint8_t flag = P.qflag[idx];
+        if (!(flag & Q9_PATCH_MOVES)) continue;
+        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1], cnt = e_end - b;
+        int ep[U_REL_DIRS];
+        float2 pxy[U_REL_DIRS];
+#pragma unroll
+        for (int j = 0; j < U_REL_DIRS; ++j) {
+            ep[j] = P.dep_e[(k0 - 1 + j) * N + idx];
+            pxy[j] = P.dep_xy[(k0 - 1 + j) * N + idx];
+        }
+        const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
+        const bool bnd = (flag & Q9_BOUNDARY) != 0;
+        int ent[U_PATCH_REG];
+#pragma unroll
+        for (int j = 0; j < U_PATCH_REG; ++j) ent[j] = j < cnt ? P.patch_ent[b + j] : 0;
+        float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < U_PATCH_REG; ++j) {
+            if (j < cnt) {
+                const float4 dg = P.uegd[9 * (long long)(ent[j] >> 4) + (ent[j] & 15)];
                 s00 += dg.x;
                 s01 += dg.y;
                 s10 += dg.z;
                 s11 += dg.w;
             }
-            const float inv = 1.0f / (float)(e_end - b);
-            g00 += s00 * inv;
-            g01 += s01 * inv;
-            g10 += s10 * inv;
-            g11 += s11 * inv;
-            const double2 d0 = P.qdisp[idx], d1 = P.qdisp[P.n_nodes + idx];
-            vgx = (float)((d1.x - d0.x) / P.dt_d);
-            vgy = (float)((d1.y - d0.y) / P.dt_d);
         }
+        for (int q = b + U_PATCH_REG; q < e_end; ++q) {
+            const int en = P.patch_ent[q];
+            const float4 dg = P.uegd[9 * (long long)(en >> 4) + (en & 15)];
+            s00 += dg.x;
+            s01 += dg.y;
+            s10 += dg.z;
+            s11 += dg.w;
+        }
+        // the node's local index in each previous element
+        int la[U_REL_DIRS];
+#pragma unroll
+        for (int j = 0; j < U_REL_DIRS; ++j) {
+            la[j] = -1;
+#pragma unroll
+            for (int i = 0; i < U_PATCH_REG; ++i)
+                if (i < cnt && (ent[i] >> 4) == ep[j]) la[j] = ent[i] & 15;
+            for (int q = b + U_PATCH_REG; q < e_end; ++q)
+                if ((P.patch_ent[q] >> 4) == ep[j]) la[j] = P.patch_ent[q] & 15;
+        }
+        float2 c0[U_REL_DIRS], c1[U_REL_DIRS], c2[U_REL_DIRS], c3[U_REL_DIRS], ra[U_REL_DIRS];
+#pragma unroll
+        for (int j = 0; j < U_REL_DIRS; ++j) {
+            const float2 *rel = P.erel + 9 * (long long)(la[j] >= 0 ? ep[j] : 0);
+            c0[j] = rel[0];
+            c1[j] = rel[1];
+            c2[j] = rel[2];
+            c3[j] = rel[3];
+            ra[j] = rel[la[j] >= 0 ? la[j] : 0];
+        }
+        const float inv = 1.0f / (float)cnt;
+        const float g00 = 1.0f + s00 * inv, g01 = s01 * inv, g10 = s10 * inv, g11 = 1.0f + s11 * inv;
+        const float vgx = (float)((d1.x - d0.x) / P.dt_d), vgy = (float)((d1.y - d0.y) / P.dt_d);
         const float idg = 1.0f / (g00 * g11 - g01 * g10);
-        for (int k = 1; k < 9; ++k) {
+#pragma unroll
+        for (int j = 0; j < U_REL_DIRS; ++j) {
+            const int k = k0 + j;
             const float ax = (float)CXK(k) - vgx, ay = (float)CYK(k) - vgy;
             const float dx = -dt * idg * (g11 * ax - g01 * ay);
             const float dy = -dt * idg * (-g10 * ax + g00 * ay);
-            int e_found = -1;
+            int e = -1;
             float xi = 0.0f, eta = 0.0f;
-            // the previous step's element first (from its local coordinates)
-            const int e_prev = moving ? P.dep_e[(k - 1) * P.n_nodes + idx] : -1;
-            if (e_prev >= 0) {
-                int a = -1;
-                for (int q = b; q < e_end; ++q)
-                    if ((P.patch_ent[q] >> 4) == e_prev) a = P.patch_ent[q] & 15;
-                if (a >= 0) {
-                    const float2 prev = P.dep_xy[(k - 1) * P.n_nodes + idx];
-                    float u = prev.x, v = prev.y;
-                    q9_corner_newton(P, e_prev, a, dx, dy, 4, u, v);
-                    if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
-                        e_found = e_prev;
-                        xi = u;
-                        eta = v;
-                    }
+            if (la[j] >= 0) {
+                // Newton on the previous element's corner map, written as
+                // x(u, v) = A + B u + C v + D u v, from the previous local
+                // coordinates; the point moves little from step to step, so
+                // it stops once an update falls below 1e-6 (at most 4)
+                const float2 C0 = c0[j], C1 = c1[j], C2 = c2[j], C3 = c3[j];
+                const float Ax = 0.25f * (C0.x + C1.x + C2.x + C3.x) - (dx + ra[j].x);
+                const float Ay = 0.25f * (C0.y + C1.y + C2.y + C3.y) - (dy + ra[j].y);
+                const float Bx = 0.25f * (-C0.x + C1.x + C2.x - C3.x), By = 0.25f * (-C0.y + C1.y + C2.y - C3.y);
+                const float Cx = 0.25f * (-C0.x - C1.x + C2.x + C3.x), Cy = 0.25f * (-C0.y - C1.y + C2.y + C3.y);
+                const float Dx = 0.25f * (C0.x - C1.x + C2.x - C3.x), Dy = 0.25f * (C0.y - C1.y + C2.y - C3.y);
+                float u = pxy[j].x, v = pxy[j].y;
+                for (int it = 0; it < 4; ++it) {
+                    const float rx = Ax + Bx * u + (Cx + Dx * u) * v;
+                    const float ry = Ay + By * u + (Cy + Dy * u) * v;
+                    const float ja = Bx + Dx * v, jb = Cx + Dx * u, jc = By + Dy * v, jd = Cy + Dy * u;
+                    const float id = 1.0f / (ja * jd - jb * jc);
+                    const float du = id * (jd * rx - jb * ry), dv = id * (-jc * rx + ja * ry);
+                    u -= du;
+                    v -= dv;
+                    if (fabsf(du) + fabsf(dv) < 1e-6f) break;
                 }
-            }
-            for (int q = b; q < e_end && e_found < 0; ++q) {
-                const int ent = P.patch_ent[q], e = ent >> 4, a = ent & 15;
-                float u = (float)q9_p(a), v = (float)q9_q(a);
-                q9_corner_newton(P, e, a, dx, dy, 8, u, v);
                 if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
-                    e_found = e;
+                    e = ep[j];
                     xi = u;
                     eta = v;
                 }
             }
-            // a boundary node's point outside its elements lies outside the
-            // mesh: the population is missing (set by the boundary kernels)
-            if (e_found < 0 && !bnd) {
+            if (e < 0) u_patch_search(P, b, e_end, dx, dy, e, xi, eta);
+            if (e < 0 && !bnd) {
                 err |= ERR_CFL;
-                e_found = P.patch_ent[b] >> 4;
+                e = P.patch_ent[b] >> 4;
             }
-            P.dep_e[(k - 1) * P.n_nodes + idx] = e_found;
-            P.dep_xy[(k - 1) * P.n_nodes + idx] = make_float2(xi, eta);
-            if (P.be_off && e_found < 0) {
-                P.dep_le[(k - 1) * P.n_nodes + idx] = U_MISSING;
-            } else if (P.be_off) {
-                // its position in the block's ascending element list (it holds
-                // every element of the node's patch)
-                const long long blk = idx / U_BLOCK;
-                int lo = P.be_off[blk], hi = P.be_off[blk + 1];
-                const int first = lo;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (P.be_elem[mid] <= e_found) lo = mid;
-                    else hi = mid;
-                }
-                P.dep_le[(k - 1) * P.n_nodes + idx] = (uint16_t)(lo - first);
-            }
+            u_dep_store(P, idx, k, e, xi, eta, e != ep[j]);
         }
     }
     if (err) atomicOr(P.err, err);
@@ -831,7 +950,7 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
 // ---------------------------------------------------------------------------
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s) {
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
-    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst, 0);
+    hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst);
     return hipGetLastError();
 }
 
@@ -881,7 +1000,9 @@ hipError_t launch_unstructured_motion(const Inst *inst, long long n_nodes, long 
     hipLaunchKernelGGL(k_u_motion, dim3((unsigned)g64), dim3(U_THREADS), 0, s, inst);
     if (relocate) {
         hipLaunchKernelGGL(k_u_dgrad, dim3((unsigned)e64), dim3(U_THREADS), 0, s, inst);
-        hipLaunchKernelGGL(k_u_locate, dim3((unsigned)g64), dim3(U_THREADS), 0, s, inst, 1);
+        // two threads per node
+        const long long r64 = ((2 * n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+        hipLaunchKernelGGL(k_u_relocate, dim3((unsigned)r64), dim3(U_THREADS), 0, s, inst);
     }
     return hipGetLastError();
 }

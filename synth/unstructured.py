@@ -347,23 +347,29 @@ def cylinder_q9_mesh(n_theta: int = 64, D: float = 80.0, far_D: float = 8.0, see
 def q9_cylinder_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: int = 1,
                      Ma: float = 0.2, Re: float = 100.0, T0: float = 1.0 / 3.0,
                      gamma: float = 1.4, Pr: float = 0.71, storage: int = 0,
-                     mirror: bool = False):
-    """Flow past a fixed cylinder on the unstructured mesh of
-    `cylinder_q9_mesh`: free stream along +x at Mach Ma, Re = rho U D / mu,
-    started from potential flow times tanh((r - R) / delta) (delta = D / 8),
-    uniform density and temperature; dt = (smallest patch reach) / (3 sqrt 2).
+                     mirror: bool = False, heave_D: float = 0.0, heave_St: float = 0.2):
+    """Flow past a cylinder on the unstructured mesh of `cylinder_q9_mesh`:
+    free stream along +x at Mach Ma, Re = rho U D / mu, started from
+    potential flow times tanh((r - R) / delta) (delta = D / 8), uniform
+    density and temperature; dt = (smallest patch reach) / (3 sqrt 2).
     Returns (mesh, fluid, body, (rho, ux, uy, T)); the body is fixed
-    (elastic axis at the centre)."""
-    from .configs import DOF_FIXED, BodyParams, FluidParams, sound_speed
+    (elastic axis at the centre), or with heave_D > 0 in prescribed heave
+    h = heave_D D sin(2 pi f t), f = heave_St U / D, rigid out to R + D/4 and
+    blended out to R + 2D."""
+    from .configs import DOF_FIXED, DOF_PRESCRIBED, BodyParams, FluidParams, sound_speed
     mesh = cylinder_q9_mesh(n_theta, D, far_D, seed=seed, mirror=mirror)
     U = Ma * sound_speed(gamma, T0)
     mu = 1.0 * U * D / Re
     dt = smallest_patch_reach(mesh) / (3.0 * np.sqrt(2.0))
     fluid = FluidParams(gamma=gamma, Pr=Pr, mu=mu, rho_inf=1.0, T_inf=T0, u_inf=(U, 0.0), dt=dt,
                         storage=storage)
-    body = BodyParams(dof=DOF_FIXED, center=(0.0, 0.0), ea=(0.0, 0.0), r_rigid=0.5 * D,
-                      r_blend=D)
     R = 0.5 * D
+    if heave_D > 0.0:
+        body = BodyParams(dof=DOF_PRESCRIBED, center=(0.0, 0.0), ea=(0.0, 0.0),
+                          r_rigid=R + 0.25 * D, r_blend=R + 2.0 * D, heave_amp=heave_D * D,
+                          heave_freq=heave_St * U / D)
+    else:
+        body = BodyParams(dof=DOF_FIXED, center=(0.0, 0.0), ea=(0.0, 0.0), r_rigid=R, r_blend=D)
     r = np.hypot(mesh.X, mesh.Y)
     c, s = mesh.X / r, mesh.Y / r
     a = (R / r) ** 2
