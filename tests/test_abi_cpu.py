@@ -382,11 +382,19 @@ def test_q9_mesh_round_a_body_is_accepted_and_validated(F):
     with pytest.raises(F.FsiError) as e:
         F.fsi_create(fl, ccw, [body], None)
     assert e.value.status == -2 and "clockwise" in str(e.value)
-    # one fixed body, and only with a wall polygon
-    for bodies in ([], [R(body, dof=1)], [body, body]):
+    # one body, and only with a wall polygon
+    for bodies in ([], [body, body]):
         with pytest.raises(F.FsiError) as e:
             F.fsi_create(fl, mesh, bodies, None)
         assert e.value.status == -1
+    # a moving body: radial blending whose rigid zone holds every element at the wall
+    moving = R(body, dof=1, m=1.0, k_h=1.0, r_rigid=12.5, r_blend=40.0)
+    F.fsi_destroy(F.fsi_create(fl, mesh, [moving], None))
+    for bad, what in ((R(moving, r_rigid=10.0), "rigid zone"), (R(moving, blend_mode=1), "radially"),
+                      (R(moving, link=0), "link")):
+        with pytest.raises(F.FsiError) as e:
+            F.fsi_create(fl, mesh, [bad], None)
+        assert e.value.status == -1 and what in str(e.value)
     dup = R(mesh, far_nodes=np.concatenate([mesh.far_nodes, mesh.wall_nodes[:1]]))
     with pytest.raises(F.FsiError) as e:
         F.fsi_create(fl, dup, [body], None)
