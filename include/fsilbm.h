@@ -278,7 +278,10 @@ fsi_status fsi_get_populations(fsi_ctx *ctx, float *f, float *g);
 fsi_status fsi_set_populations(fsi_ctx *ctx, const float *f, const float *g);
 
 /* Checkpoint: populations (storage precision), body states, step counter and
- * parameters.  fsi_state_bytes() gives the buffer size. */
+ * parameters; with a moving body on a Q9 mesh also the departure table
+ * (element and local coordinates per node and direction) that each step's
+ * relocation starts from, so that a restart repeats the run bitwise.
+ * fsi_state_bytes() gives the buffer size. */
 fsi_status fsi_state_bytes(const fsi_ctx *ctx, size_t *bytes);
 fsi_status fsi_save(fsi_ctx *ctx, void *host_buf, size_t bytes);
 fsi_status fsi_load(fsi_ctx *ctx, const void *host_buf, size_t bytes);

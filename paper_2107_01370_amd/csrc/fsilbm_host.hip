@@ -1382,7 +1382,10 @@ fsi_status fsi_state_bytes(const fsi_ctx *c, size_t *bytes) {
     if (!c || !bytes) return FSI_E_ARG;
     const size_t N = (size_t)c->ni * c->nj;
     const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
-    *bytes = 8 * 6 + 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot) + fsi::NPOP * N * bpp;
+    // a moving body on a Q9 mesh: the departure table (element, local
+    // coordinates), from which each step's relocation starts
+    const size_t dep = c->q9_moving ? 8 * N * (sizeof(int) + sizeof(float2)) : 0;
+    *bytes = 8 * 6 + 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot) + fsi::NPOP * N * bpp + dep;
     return FSI_OK;
 }
 
@@ -1404,6 +1407,12 @@ fsi_status fsi_save(fsi_ctx *c, void *host_buf, size_t bytes) {
                          hipMemcpyDeviceToHost));
     p += 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot);
     HIP_TRY(c, hipMemcpy(p, c->ws + c->off_pop[c->host_step & 1], fsi::NPOP * N * bpp, hipMemcpyDeviceToHost));
+    p += fsi::NPOP * N * bpp;
+    if (c->q9_moving) {
+        HIP_TRY(c, hipMemcpy(p, c->ws + c->off_dep_e, 8 * N * sizeof(int), hipMemcpyDeviceToHost));
+        p += 8 * N * sizeof(int);
+        HIP_TRY(c, hipMemcpy(p, c->ws + c->off_dep_xy, 8 * N * sizeof(float2), hipMemcpyDeviceToHost));
+    }
     return FSI_OK;
 }
 
@@ -1425,6 +1434,21 @@ fsi_status fsi_load(fsi_ctx *c, const void *host_buf, size_t bytes) {
                          hipMemcpyHostToDevice));
     p += 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot);
     HIP_TRY(c, hipMemcpy(c->ws + c->off_pop[step & 1], p, fsi::NPOP * N * bpp, hipMemcpyHostToDevice));
+    p += fsi::NPOP * N * bpp;
+    if (c->q9_moving) {
+        // the departure table the run continues from: elements and local
+        // coordinates (element ids checked on the host), then the block-list
+        // positions formed from them
+        std::vector<int> de(8 * N);
+        memcpy(de.data(), p, 8 * N * sizeof(int));
+        for (int e : de)
+            if (e < -1 || e >= c->n_elems) return fail(c, FSI_E_ARG, "checkpoint departure table out of range");
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_dep_e, de.data(), 8 * N * sizeof(int), hipMemcpyHostToDevice));
+        p += 8 * N * sizeof(int);
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_dep_xy, p, 8 * N * sizeof(float2), hipMemcpyHostToDevice));
+        if (!c->bh_off.empty())
+            HIP_TRY(c, fsi::launch_unstructured_dep_le(d_inst(c), (long long)N, c->stream));
+    }
     long long s = step;
     HIP_TRY(c, hipMemcpy(c->ws + c->off_step, &s, 8, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemset(c->ws + c->off_err, 0, 4));

@@ -184,6 +184,7 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
                                int eu16, const double2 *disp0, hipStream_t s);
 // a moving body on a Q9 mesh: node displacements of levels n and n+1, and
 // (relocate) the departure points on the moving mesh
+hipError_t launch_unstructured_dep_le(const Inst *inst, long long n_nodes, hipStream_t s);
 hipError_t launch_unstructured_motion(const Inst *inst, long long n_nodes, long long n_elems, int relocate,
                                       hipStream_t s);
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s);

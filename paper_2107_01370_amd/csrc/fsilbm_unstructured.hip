@@ -349,6 +349,21 @@ __device__ __forceinline__ void u_patch_search(const Inst &P, int b, int e_end, 
     }
 }
 
+// position of element e (-1: none) in the ascending element list of node
+// idx's block (it holds every element of the node's patch)
+__device__ __forceinline__ uint16_t u_block_pos(const Inst &P, long long idx, int e) {
+    if (e < 0) return U_MISSING;
+    const long long blk = idx / U_BLOCK;
+    int lo = P.be_off[blk], hi = P.be_off[blk + 1];
+    const int first = lo;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P.be_elem[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return (uint16_t)(lo - first);
+}
+
 // Departure table entry of node idx, direction k: element, local coordinates
 // and, with node blocks, the element's position in the block's ascending
 // element list (it holds every element of the node's patch); `changed` false
@@ -359,19 +374,19 @@ __device__ __forceinline__ void u_dep_store(const Inst &P, long long idx, int k,
     P.dep_xy[at] = make_float2(xi, eta);
     if (!changed) return;
     P.dep_e[at] = e;
-    if (P.be_off && e < 0) {
-        P.dep_le[at] = U_MISSING;
-    } else if (P.be_off) {
-        const long long blk = idx / U_BLOCK;
-        int lo = P.be_off[blk], hi = P.be_off[blk + 1];
-        const int first = lo;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (P.be_elem[mid] <= e) lo = mid;
-            else hi = mid;
+    if (P.be_off) P.dep_le[at] = u_block_pos(P, idx, e);
+}
+
+// the departure elements' positions in their node blocks' element lists,
+// from the element table (after a checkpoint has restored it)
+__global__ void __launch_bounds__(U_THREADS) k_u_dep_le(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
+    for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
+         idx += (long long)gridDim.x * blockDim.x)
+        for (int k = 0; k < 8; ++k) {
+            const long long at = (long long)k * P.n_nodes + idx;
+            P.dep_le[at] = u_block_pos(P, idx, P.dep_e[at]);
         }
-        P.dep_le[at] = (uint16_t)(lo - first);
-    }
 }
 
 // Departure points of a static mesh, once when the workspace is bound: for
@@ -951,6 +966,12 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
 hipError_t launch_unstructured_locate(const Inst *inst, long long n_nodes, hipStream_t s) {
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
     hipLaunchKernelGGL(k_u_locate, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unstructured_dep_le(const Inst *inst, long long n_nodes, hipStream_t s) {
+    const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
+    hipLaunchKernelGGL(k_u_dep_le, dim3((unsigned)(g64 > 0 ? g64 : 8)), dim3(U_THREADS), 0, s, inst);
     return hipGetLastError();
 }
 
