@@ -127,8 +127,8 @@ typedef struct {
  *              The force is sigma . (n ds) summed over the wall polygon,
  *              (n ds)_k = rot90(x_{k+1} - x_{k-1}) / 2 on the mesh of the
  *              level, the moment about the body's displaced `ea`.  A moving
- *              body (any dof but FSI_DOF_FIXED) blends radially (blend_mode
- *              0) and its rigid zone must hold every element at the wall
+ *              body (any dof but FSI_DOF_FIXED; radial or distance blending)
+ *              needs a rigid zone that holds every element at the wall
  *              (FSI_E_ARG otherwise); nodes move by the blending of Sec. II.D
  *              and each step locates the departure points
  *              X - dt g^{-1}(c - V_G) anew among the node's undeformed

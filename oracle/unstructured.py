@@ -302,7 +302,9 @@ class UnstructuredWallSolver(UnstructuredSolver):
       the mesh of the level, the moment about the body's displaced elastic
       axis (Sec. III);
     * a moving body (any dof but fixed): nodes move by the blending of
-      Sec. II.D, x = X + (1 - r)(G'(X) - X); the departure point of node X is
+      Sec. II.D, x = X + (1 - r)(G'(X) - X), r of the distance to the body's
+      centre or, with distance blending (the variant Sec. II.D suggests for
+      slender bodies), to the closed wall polygon; the departure point of node X is
       X - dt g^{-1}(c_i - V_G) in the undeformed frame (g = dx/dX at the new
       level by the nodal finite-element derivative on the undeformed mesh,
       V_G = (x^{n+1} - x^n)/dt), located among the node's undeformed
@@ -330,8 +332,11 @@ class UnstructuredWallSolver(UnstructuredSolver):
         self.Y = np.asarray(mesh.Y, dtype=np.float64)
         self.moving = body.dof != B.DOF_FIXED
         self.state = B.initial_state(body)
-        self.r = blend_factors(self.X, self.Y, [body])[0]
         self.wall = np.asarray(mesh.wall_nodes, dtype=np.int64)
+        # blending coordinate: distance to the centre, or (blend_mode 1) to the
+        # closed wall polygon in the undeformed frame
+        walls = [(self.X[self.wall], self.Y[self.wall])] if getattr(body, "blend_mode", 0) == 1 else None
+        self.r = blend_factors(self.X[None], self.Y[None], [body], walls)[0][0]
         self.far = np.asarray(mesh.far_nodes, dtype=np.int64)
         self.bnd = np.zeros(N, dtype=bool)
         self.bnd[self.wall] = True

@@ -349,9 +349,40 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
     const fsi_body_desc &b = c->bodies[0];
     if (b.link >= 0) return fail(c, FSI_E_ARG, "a body on a Q9 mesh has no link");
     c->q9_moving = b.dof != FSI_DOF_FIXED;
+    c->wall_dist.clear();
     if (c->q9_moving) {
-        if (b.blend_mode != 0 || !(b.r_blend > b.r_rigid))
-            return fail(c, FSI_E_ARG, "a moving body on a Q9 mesh blends radially (blend_mode 0, r_blend > r_rigid)");
+        if (!(b.r_blend > b.r_rigid) || !(b.r_rigid >= 0))
+            return fail(c, FSI_E_ARG, "a moving body on a Q9 mesh needs 0 <= r_rigid < r_blend");
+        if (b.blend_mode != 0 && b.blend_mode != 1) return fail(c, FSI_E_ARG, "unknown blend_mode");
+        const size_t N = (size_t)c->ni;
+        if (b.blend_mode == 1) {
+            // distance of every node to the closed wall polygon (undeformed frame)
+            if ((double)N * (double)nw > 4e9)
+                return fail(c, FSI_E_ARG, "distance blending: mesh too large for the direct "
+                                          "distance computation (nodes x wall edges > 4e9)");
+            c->wall_dist.assign(N, 0.0);
+            for (size_t q = 0; q < N; ++q) {
+                const double px = c->X[2 * q], py = c->X[2 * q + 1];
+                double best = INFINITY;
+                for (int e = 0; e < nw; ++e) {
+                    const double *a = &c->X[2 * (size_t)c->qw_nodes[e]];
+                    const double *bq = &c->X[2 * (size_t)c->qw_nodes[(e + 1) % nw]];
+                    const double ex = bq[0] - a[0], ey = bq[1] - a[1];
+                    const double ee = ex * ex + ey * ey;
+                    double t = ee > 0 ? ((px - a[0]) * ex + (py - a[1]) * ey) / ee : 0.0;
+                    t = t < 0 ? 0 : (t > 1 ? 1 : t);
+                    const double dx = px - (a[0] + t * ex), dy = py - (a[1] + t * ey);
+                    best = std::min(best, dx * dx + dy * dy);
+                }
+                c->wall_dist[q] = sqrt(best);
+            }
+        }
+        // the blending coordinate of node v: the distance to the centre or
+        // to the wall
+        auto dist = [&](size_t v) {
+            return b.blend_mode == 1 ? c->wall_dist[v]
+                                     : hypot(c->X[2 * v] - b.center[0], c->X[2 * v + 1] - b.center[1]);
+        };
         // the wall nodes' elements move rigidly with the body (B is placed
         // in the undeformed frame)
         for (int k = 0; k < nw; ++k) {
@@ -359,23 +390,22 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
             for (int q = c->patch_off[v]; q < c->patch_off[v + 1]; ++q) {
                 const int e = c->patch_ent[q] >> 4;
                 for (int a = 0; a < 9; ++a) {
-                    const int u = c->elems[9 * (size_t)e + a];
-                    if (blend_r(b, c->X[2 * (size_t)u], c->X[2 * (size_t)u + 1]) != 0.0)
+                    const size_t u = (size_t)c->elems[9 * (size_t)e + a];
+                    const double dw = b.blend_mode == 1 ? c->wall_dist[u] : 0.0;
+                    if (blend_r(b, c->X[2 * u], c->X[2 * u + 1], dw) != 0.0)
                         return fail(c, FSI_E_ARG, "the elements at the wall must lie in the moving body's rigid zone "
                                                   "(r_rigid too small)");
                 }
             }
         }
-        // nodes the blending moves (Q9_MOVES: closer to the centre than
-        // r_blend, with a margin far above rounding) and nodes whose patch
-        // holds one (Q9_PATCH_MOVES); the departure points of the others keep
-        // their values of the undeformed mesh
-        const int N = c->ni;
+        // nodes the blending moves (Q9_MOVES: nearer than r_blend, with a
+        // margin far above rounding) and nodes whose patch holds one
+        // (Q9_PATCH_MOVES); the departure points of the others keep their
+        // values of the undeformed mesh
         const double reach = b.r_blend * (1.0 + 1e-9);
-        for (int v = 0; v < N; ++v)
-            if (hypot(c->X[2 * (size_t)v] - b.center[0], c->X[2 * (size_t)v + 1] - b.center[1]) < reach)
-                c->qflag[v] |= fsi::Q9_MOVES;
-        for (int v = 0; v < N; ++v)
+        for (size_t v = 0; v < N; ++v)
+            if (dist(v) < reach) c->qflag[v] |= fsi::Q9_MOVES;
+        for (size_t v = 0; v < N; ++v)
             for (int q = c->patch_off[v]; q < c->patch_off[v + 1]; ++q) {
                 const int e = c->patch_ent[q] >> 4;
                 for (int a = 0; a < 9; ++a)

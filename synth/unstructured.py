@@ -386,7 +386,8 @@ def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: 
                   amp_D: float = 0.02, Ma_body: float = 0.05, T0: float = 1.0 / 3.0,
                   nu: float = 0.02, gamma: float = 1.4, Pr: float = 0.71, storage: int = 0,
                   dof: int = 0, mstar: float = 2.0, ustar: float = 5.0,
-                  symmetric: bool = False, pitch_deg: float = 0.0, ea_D: float = 0.0):
+                  symmetric: bool = False, pitch_deg: float = 0.0, ea_D: float = 0.0,
+                  distance_blend: bool = False):
     """A cylinder on the unstructured mesh of `cylinder_q9_mesh` in gas at
     rest, moving along y: prescribed heave h = A sin(w t) (dof 0; A = amp_D D,
     peak speed Ma_body times the speed of sound), or released at h0 = A with
@@ -397,7 +398,8 @@ def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: 
     pitch_deg > 0 (dof 0): also a prescribed pitch alpha = pitch_deg sin(w_a t)
     about the elastic axis (ea_D D, 0), the wall's peak pitching speed again
     Ma_body times the speed of sound.  Blending: rigid out to R + D/4 from the
-    centre, blended out to R + 2D.
+    centre, blended out to R + 2D; distance_blend: the same distances measured
+    from the wall polygon (D/4 and 2D).
     symmetric: the mesh is its own mirror image about the y axis (the line of
     the motion).
     dt = (smallest patch reach) / (3 sqrt 2).  Returns (mesh, fluid, body,
@@ -416,8 +418,9 @@ def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: 
     k_h = m * (2.0 * np.pi * U / (ustar * D)) ** 2
     a_amp = np.radians(pitch_deg) if dof == 0 else 0.0
     w_a = U / (a_amp * (R + abs(ea_D) * D)) if a_amp > 0 else 0.0
+    r0 = 0.0 if distance_blend else R
     body = BodyParams(dof=dof, m=m, k_h=k_h, center=(0.0, 0.0), ea=(ea_D * D, 0.0),
-                      r_rigid=R + 0.25 * D, r_blend=R + 2.0 * D,
+                      r_rigid=r0 + 0.25 * D, r_blend=r0 + 2.0 * D, blend_mode=1 if distance_blend else 0,
                       heave_amp=A if dof == 0 else 0.0, heave_freq=w / (2.0 * np.pi) if dof == 0 else 0.0,
                       pitch_amp=a_amp, pitch_freq=w_a / (2.0 * np.pi),
                       h0=A if dof == 1 else 0.0, hd0=U if dof == 1 else 0.0)

@@ -390,7 +390,10 @@ def test_q9_mesh_round_a_body_is_accepted_and_validated(F):
     # a moving body: radial blending whose rigid zone holds every element at the wall
     moving = R(body, dof=1, m=1.0, k_h=1.0, r_rigid=12.5, r_blend=40.0)
     F.fsi_destroy(F.fsi_create(fl, mesh, [moving], None))
-    for bad, what in ((R(moving, r_rigid=10.0), "rigid zone"), (R(moving, blend_mode=1), "radially"),
+    # distance blending measures from the wall polygon
+    F.fsi_destroy(F.fsi_create(fl, mesh, [R(moving, blend_mode=1, r_rigid=5.0, r_blend=30.0)], None))
+    for bad, what in ((R(moving, r_rigid=10.0), "rigid zone"), (R(moving, blend_mode=2), "blend_mode"),
+                      (R(moving, blend_mode=1, r_rigid=0.5, r_blend=30.0), "rigid zone"),
                       (R(moving, link=0), "link")):
         with pytest.raises(F.FsiError) as e:
             F.fsi_create(fl, mesh, [bad], None)

@@ -288,3 +288,21 @@ def test_moving_body_checkpoint_and_single_steps_keep_the_run():
     assert np.array_equal(a.forces(7, 21), b.forces(7, 21))
     a.close()
     b.close()
+
+
+def test_moving_body_with_distance_blending():
+    """Heave with the blending measured from the wall polygon (distances D/4
+    and 2D): fields, loads and motion against the oracle after 40 steps."""
+    from synth.unstructured import q9_heave_case
+    sim, ora = paired_moving(q9_heave_case(seed=7, distance_blend=True))
+    n = 40
+    sim.step(n)
+    ora.run(n)
+    rho, _, _, T = sim.macro()
+    r_o, _, _, _, T_o = ora.macroscopic()
+    assert np.max(np.abs(rho[0] - r_o) / r_o) <= 1e-5
+    assert np.max(np.abs(rho[0] * T[0] - r_o * T_o) / (r_o * T_o)) <= 1e-5
+    hist = sim.forces(0, n)
+    ho = np.array(ora.history)
+    fscale = np.max(np.hypot(ho[:, 1], ho[:, 2]))
+    assert np.max(np.abs(hist[:, 1:3] - ho[:, 1:3])) <= 1e-4 * fscale

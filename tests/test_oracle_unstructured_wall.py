@@ -169,3 +169,31 @@ def test_heaving_body_flow_is_mirror_symmetric():
     h = np.array(o.history)
     assert abs(h[-1, 2]) > 0.1 and h[-1, 4] != 0.0
     assert np.max(np.abs(h[:, 1])) < 1e-11 * abs(h[-1, 2])
+
+
+def test_distance_blending_measures_from_the_wall_polygon():
+    """Distance blending (Sec. II.D's variant for slender bodies) on the
+    cylinder mesh: the wall polygon is the n-gon through the wall points on
+    the circle, so the distance of an outside node to it lies between its
+    radial distance to the circle and that plus the polygon's sagitta
+    R (1 - cos(pi / n)); the blending factor, monotone in the distance, lies
+    between the factors of those two distances, and is 0 on the wall."""
+    from oracle.mesh import r5
+    from synth.unstructured import q9_heave_case
+    m, fl, b, (r, u, v, T) = q9_heave_case(16, 20.0, 4.0, distance_blend=True)
+    sol = UnstructuredWallSolver(m, fl, b, r, u, v, T)
+    R = 10.0
+    n = 16
+    sag = R * (1.0 - np.cos(np.pi / n))
+    d_rad = np.hypot(m.X, m.Y) - R
+
+    def factor(d):
+        s = (d - b.r_rigid) / (b.r_blend - b.r_rigid)
+        return np.where(s < 0.0, 0.0, np.where(s > 1.0, 1.0, r5(np.clip(s, 0.0, 1.0))))
+
+    assert np.all(sol.r >= factor(d_rad) - 1e-12)
+    assert np.all(sol.r <= factor(d_rad + sag) + 1e-12)
+    assert np.all(sol.r[m.wall_nodes] == 0.0)
+    # the band is narrow against the blending width: the two readings differ
+    assert sag < 0.05 * (b.r_blend - b.r_rigid)
+    assert np.max(np.abs(sol.r - factor(d_rad))) > 0.0
