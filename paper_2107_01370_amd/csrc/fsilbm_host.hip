@@ -31,6 +31,7 @@ struct fsi_ctx {
     std::vector<int> elems;         // [E][9]
     std::vector<float2> erel;       // [E][9] offsets from the element's centre node
     std::vector<int> patch_off, patch_ent;
+    std::vector<int> patch8;            // moving body: [N][8] first patch entries, -1 past the end
     // node blocks of the LDS-staged interpolation (empty: device-memory gathers)
     std::vector<int> bh_off, bh_nodes, be_off, be_elem;
     std::vector<uint16_t> be_nodes, uself;
@@ -54,7 +55,7 @@ struct fsi_ctx {
            off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0,
            off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
            off_uself = 0, off_dep_le = 0, off_qflag = 0, off_qw = 0, off_qwidx = 0, off_qf = 0,
-           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_uegd = 0,
+           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_uegd = 0, off_patch8 = 0,
            total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
@@ -411,6 +412,12 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
                 for (int a = 0; a < 9; ++a)
                     if (c->qflag[c->elems[9 * (size_t)e + a]] & fsi::Q9_MOVES) c->qflag[v] |= fsi::Q9_PATCH_MOVES;
             }
+        // each node's first eight patch entries at a fixed stride, so that
+        // the relocation reaches its elements in one memory round trip
+        c->patch8.assign(8 * N, -1);
+        for (size_t v = 0; v < N; ++v)
+            for (int j = 0; j < 8 && c->patch_off[v] + j < c->patch_off[v + 1]; ++j)
+                c->patch8[8 * v + j] = c->patch_ent[c->patch_off[v] + j];
     }
     const double dt = c->fluid.dt;
     for (int k = 0; k < nw; ++k) {
@@ -867,6 +874,7 @@ void layout(fsi_ctx *c) {
         if (c->q9_moving) {
             c->off_qdisp = take(2 * N * sizeof(double2));
             c->off_uegd = take(9 * (size_t)c->n_elems * sizeof(float4));
+            c->off_patch8 = take(c->patch8.size() * 4);
         }
         if (!c->bh_off.empty()) {
             c->off_bh_off = take(c->bh_off.size() * 4);
@@ -1131,6 +1139,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
         P.qdisp = c->q9_moving ? reinterpret_cast<double2 *>(c->ws + c->off_qdisp) : nullptr;
         P.uegd = c->q9_moving ? reinterpret_cast<float4 *>(c->ws + c->off_uegd) : nullptr;
+        P.patch8 = c->q9_moving ? reinterpret_cast<const int *>(c->ws + c->off_patch8) : nullptr;
         {
             const std::pair<size_t, std::pair<const void *, size_t>> up[] = {
                 {c->off_qflag, {c->qflag.data(), c->qflag.size()}},
@@ -1139,7 +1148,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                 {c->off_qf, {c->qf_nodes.data(), c->qf_nodes.size() * 4}},
                 {c->off_qwgeo, {c->qw_geo.data(), c->qw_geo.size() * sizeof(double4)}},
                 {c->off_qweB, {c->qw_eB.data(), c->qw_eB.size() * 4}},
-                {c->off_qwxyB, {c->qw_xyB.data(), c->qw_xyB.size() * sizeof(float2)}}};
+                {c->off_qwxyB, {c->qw_xyB.data(), c->qw_xyB.size() * sizeof(float2)}},
+                {c->off_patch8, {c->patch8.data(), c->patch8.size() * 4}}};
             for (const auto &u : up)
                 if (u.second.second)
                     HIP_TRY(c, hipMemcpyAsync(c->ws + u.first, u.second.first, u.second.second,

@@ -427,10 +427,10 @@ constexpr int U_PATCH_REG = 8;
 // element derivatives), V_G = (d^{n+1} - d^n) / dt; the previous step's
 // element is tried first, by Newton from its local coordinates, then the
 // patch in order as for a static mesh.  Two threads per node (neighbouring
-// lanes, directions 1-4 and 5-8), each issuing all loads it needs before
-// their first use (previous table entries, patch, element derivatives, then
-// the corners of the previous elements), so a thread waits on a few memory
-// round trips rather than one per direction.
+// lanes, directions 1-4 and 5-8), each issuing its loads in two round trips
+// (flag, previous table entries, displacements and the node's first eight
+// patch entries at a fixed stride; then the element derivatives and the
+// corners of the previous elements), rather than one per direction.
 constexpr int U_REL_DIRS = 4;   // directions per thread
 __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
@@ -441,11 +441,12 @@ __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict
          tid += (long long)gridDim.x * blockDim.x) {
         const long long idx = tid >> 1;
         const int k0 = 1 + U_REL_DIRS * (int)(tid & 1);
-        // a patch the blending leaves in place keeps the undeformed mesh's
-        // departure points
+        // every load of the node's first round trip, before the flag decides
+        // (a patch the blending leaves in place keeps the undeformed mesh's
+        // departure points)
         const uint8_t flag = P.qflag[idx];
-        if (!(flag & Q9_PATCH_MOVES)) continue;
-        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1], cnt = e_end - b;
+        const int4 pa = reinterpret_cast<const int4 *>(P.patch8)[2 * idx];
+        const int4 pb = reinterpret_cast<const int4 *>(P.patch8)[2 * idx + 1];
         int ep[U_REL_DIRS];
         float2 pxy[U_REL_DIRS];
 #pragma unroll
@@ -454,10 +455,20 @@ __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict
             pxy[j] = P.dep_xy[(k0 - 1 + j) * N + idx];
         }
         const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
+        if (!(flag & Q9_PATCH_MOVES)) continue;
         const bool bnd = (flag & Q9_BOUNDARY) != 0;
-        int ent[U_PATCH_REG];
+        const int ent[U_PATCH_REG] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
+        // patch size: the entries held, or from the patch offsets for a node
+        // with more than eight elements
+        int b = 0, e_end = 0, cnt = 0;
 #pragma unroll
-        for (int j = 0; j < U_PATCH_REG; ++j) ent[j] = j < cnt ? P.patch_ent[b + j] : 0;
+        for (int j = 0; j < U_PATCH_REG; ++j) cnt += ent[j] >= 0 ? 1 : 0;
+        const bool big = ent[U_PATCH_REG - 1] >= 0;
+        if (big) {
+            b = P.patch_off[idx];
+            e_end = P.patch_off[idx + 1];
+            cnt = e_end - b;
+        }
         float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
 #pragma unroll
         for (int j = 0; j < U_PATCH_REG; ++j) {
@@ -538,10 +549,14 @@ __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict
                     eta = v;
                 }
             }
-            if (e < 0) u_patch_search(P, b, e_end, dx, dy, e, xi, eta);
-            if (e < 0 && !bnd) {
-                err |= ERR_CFL;
-                e = P.patch_ent[b] >> 4;
+            if (e < 0) {
+                // left the previous element: the patch in order
+                const int pb0 = P.patch_off[idx], pe0 = P.patch_off[idx + 1];
+                u_patch_search(P, pb0, pe0, dx, dy, e, xi, eta);
+                if (e < 0 && !bnd) {
+                    err |= ERR_CFL;
+                    e = P.patch_ent[pb0] >> 4;
+                }
             }
             u_dep_store(P, idx, k, e, xi, eta, e != ep[j]);
         }
