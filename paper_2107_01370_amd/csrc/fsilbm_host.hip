@@ -31,7 +31,7 @@ struct fsi_ctx {
     std::vector<int> elems;         // [E][9]
     std::vector<float2> erel;       // [E][9] offsets from the element's centre node
     std::vector<int> patch_off, patch_ent;
-    std::vector<int> patch8;            // moving body: [N][8] first patch entries, -1 past the end
+    std::vector<int> patch8;            // [N][8] first patch entries, -1 past the end
     // node blocks of the LDS-staged interpolation (empty: device-memory gathers)
     std::vector<int> bh_off, bh_nodes, be_off, be_elem;
     std::vector<uint16_t> be_nodes, uself;
@@ -412,12 +412,6 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
                 for (int a = 0; a < 9; ++a)
                     if (c->qflag[c->elems[9 * (size_t)e + a]] & fsi::Q9_MOVES) c->qflag[v] |= fsi::Q9_PATCH_MOVES;
             }
-        // each node's first eight patch entries at a fixed stride, so that
-        // the relocation reaches its elements in one memory round trip
-        c->patch8.assign(8 * N, -1);
-        for (size_t v = 0; v < N; ++v)
-            for (int j = 0; j < 8 && c->patch_off[v] + j < c->patch_off[v + 1]; ++j)
-                c->patch8[8 * v + j] = c->patch_ent[c->patch_off[v] + j];
     }
     const double dt = c->fluid.dt;
     for (int k = 0; k < nw; ++k) {
@@ -499,6 +493,12 @@ fsi_status validate_q9(fsi_ctx *c, const fsi_mesh_desc *mesh) {
     std::vector<int> fill(c->patch_off.begin(), c->patch_off.end() - 1);
     for (int e = 0; e < E; ++e)
         for (int a = 0; a < 9; ++a) c->patch_ent[fill[c->elems[9 * (size_t)e + a]]++] = e * 16 + a;
+    // each node's first eight patch entries at a fixed stride, so that a
+    // nodal mean reaches its elements in one memory round trip
+    c->patch8.assign(8 * (size_t)N, -1);
+    for (int v = 0; v < N; ++v)
+        for (int j = 0; j < 8 && c->patch_off[v] + j < c->patch_off[v + 1]; ++j)
+            c->patch8[8 * (size_t)v + j] = c->patch_ent[c->patch_off[v] + j];
     // geometry: FP64 unwrapped coordinates, offsets from the centre node in FP32
     const int lp[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0}, lq[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
     auto dl = [](int p, int x) { return p < 0 ? x - 0.5 : (p == 0 ? -2.0 * x : x + 0.5); };
@@ -874,8 +874,8 @@ void layout(fsi_ctx *c) {
         if (c->q9_moving) {
             c->off_qdisp = take(2 * N * sizeof(double2));
             c->off_uegd = take(9 * (size_t)c->n_elems * sizeof(float4));
-            c->off_patch8 = take(c->patch8.size() * 4);
         }
+        c->off_patch8 = take(c->patch8.size() * 4);
         if (!c->bh_off.empty()) {
             c->off_bh_off = take(c->bh_off.size() * 4);
             c->off_bh_nodes = take(c->bh_nodes.size() * 4);
@@ -1139,7 +1139,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
         P.qdisp = c->q9_moving ? reinterpret_cast<double2 *>(c->ws + c->off_qdisp) : nullptr;
         P.uegd = c->q9_moving ? reinterpret_cast<float4 *>(c->ws + c->off_uegd) : nullptr;
-        P.patch8 = c->q9_moving ? reinterpret_cast<const int *>(c->ws + c->off_patch8) : nullptr;
+        P.patch8 = reinterpret_cast<const int *>(c->ws + c->off_patch8);
         {
             const std::pair<size_t, std::pair<const void *, size_t>> up[] = {
                 {c->off_qflag, {c->qflag.data(), c->qflag.size()}},

@@ -147,7 +147,7 @@ struct Inst {
     // a moving body on a Q9 mesh (null: fixed)
     double2 *qdisp;           // [2][n_nodes] blended displacement at levels n, n+1
     float4 *uegd;             // [n_elems][9] derivatives of the level-(n+1) displacement
-    const int *patch8;        // [n_nodes][8] first patch entries (moving body), -1 past the end
+    const int *patch8;        // [n_nodes][8] first patch entries (Q9 meshes), -1 past the end
 };
 
 // nodes per block of the LDS-staged interpolation

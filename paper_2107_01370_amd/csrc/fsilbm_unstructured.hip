@@ -127,15 +127,18 @@ __global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ 
 // (their loads in flight at once), a longer list continues one by one
 constexpr int U_PATCH = 8;
 __device__ __forceinline__ float2 node_mean(const Inst &P, const float2 *__restrict__ eg, long long idx) {
-    const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
-    const int cnt = e_end - b;
-    int ent[U_PATCH];
-#pragma unroll
-    for (int j = 0; j < U_PATCH; ++j) ent[j] = j < cnt ? P.patch_ent[b + j] : -1;
+    // the first U_PATCH entries from the fixed-stride table (one round trip);
+    // a full row may have more: then the CSR lists give the count and the rest
+    const int4 pa = reinterpret_cast<const int4 *>(P.patch8)[2 * idx];
+    const int4 pb = reinterpret_cast<const int4 *>(P.patch8)[2 * idx + 1];
+    const int ent[U_PATCH] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
     float2 d[U_PATCH];
 #pragma unroll
     for (int j = 0; j < U_PATCH; ++j)
         d[j] = ent[j] >= 0 ? eg[9 * (long long)(ent[j] >> 4) + (ent[j] & 15)] : make_float2(0.0f, 0.0f);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < U_PATCH; ++j) cnt += ent[j] >= 0 ? 1 : 0;
     float gx = 0.0f, gy = 0.0f;
 #pragma unroll
     for (int j = 0; j < U_PATCH; ++j) {
@@ -144,11 +147,15 @@ __device__ __forceinline__ float2 node_mean(const Inst &P, const float2 *__restr
             gy += d[j].y;
         }
     }
-    for (int k = b + U_PATCH; k < e_end; ++k) {
-        const int e2 = P.patch_ent[k];
-        const float2 d2 = eg[9 * (long long)(e2 >> 4) + (e2 & 15)];
-        gx += d2.x;
-        gy += d2.y;
+    if (ent[U_PATCH - 1] >= 0) {
+        const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
+        cnt = e_end - b;
+        for (int k = b + U_PATCH; k < e_end; ++k) {
+            const int e2 = P.patch_ent[k];
+            const float2 d2 = eg[9 * (long long)(e2 >> 4) + (e2 & 15)];
+            gx += d2.x;
+            gy += d2.y;
+        }
     }
     const float inv = 1.0f / (float)cnt;
     return make_float2(gx * inv, gy * inv);
