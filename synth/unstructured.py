@@ -426,3 +426,25 @@ def q9_heave_case(n_theta: int = 32, D: float = 40.0, far_D: float = 6.0, seed: 
                       h0=A if dof == 1 else 0.0, hd0=U if dof == 1 else 0.0)
     N = mesh.n_nodes
     return mesh, fluid, body, (np.ones(N), np.zeros(N), np.zeros(N), np.full(N, T0))
+
+
+def q9_comoving_case(n_theta: int = 16, D: float = 20.0, far_D: float = 4.0, seed: int = 1,
+                     Ma: float = 0.1, T0: float = 1.0 / 3.0, nu: float = 0.02, gamma: float = 1.4,
+                     Pr: float = 0.71, storage: int = 0):
+    """A cylinder carried along y by gas in uniform motion at Mach Ma: the
+    body on a spring-free heave equation with a mass far above the gas's
+    (1e30), started at the gas velocity, so that it keeps that velocity; the
+    mesh blends rigid out to R + D/4 and back to rest at R + 1.2 D (inside
+    the outer boundary).  Exactly, nothing changes but the body's position.
+    Returns (mesh, fluid, body, (rho, ux, uy, T))."""
+    from .configs import DOF_HEAVE, BodyParams, FluidParams, sound_speed
+    mesh = cylinder_q9_mesh(n_theta, D, far_D, seed=seed)
+    R = 0.5 * D
+    U = Ma * sound_speed(gamma, T0)
+    dt = smallest_patch_reach(mesh) / (3.0 * np.sqrt(2.0))
+    fluid = FluidParams(gamma=gamma, Pr=Pr, mu=nu, rho_inf=1.0, T_inf=T0, u_inf=(0.0, U), dt=dt,
+                        storage=storage)
+    body = BodyParams(dof=DOF_HEAVE, m=1e30, k_h=0.0, center=(0.0, 0.0), ea=(0.0, 0.0),
+                      r_rigid=R + 0.25 * D, r_blend=R + 1.2 * D, hd0=U)
+    N = mesh.n_nodes
+    return mesh, fluid, body, (np.ones(N), np.zeros(N), np.full(N, U), np.full(N, T0))

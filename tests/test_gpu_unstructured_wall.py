@@ -306,3 +306,25 @@ def test_moving_body_with_distance_blending():
     ho = np.array(ora.history)
     fscale = np.max(np.hypot(ho[:, 1], ho[:, 2]))
     assert np.max(np.abs(hist[:, 1:3] - ho[:, 1:3])) <= 1e-4 * fscale
+
+
+def test_body_carried_by_uniform_gas_changes_nothing_but_its_position():
+    """The Galilean check on the device: the gas stays uniform to FP32
+    rounding, the load stays at rounding level against p times the
+    perimeter, the body moves at the gas velocity, and the oracle agrees."""
+    from synth.unstructured import q9_comoving_case
+    sim, ora = paired_moving(q9_comoving_case())
+    mesh, fl = sim.mesh, ora.fluid
+    n = 30
+    sim.step(n)
+    ora.run(n)
+    rho, ux, uy, T = sim.macro()
+    U = fl.u_inf[1]
+    assert np.max(np.abs(rho[0] - 1.0)) <= 1e-6 and np.max(np.abs(ux[0])) <= 1e-6
+    assert np.max(np.abs(uy[0] - U)) <= 1e-6 and np.max(np.abs(T[0] - fl.T_inf)) <= 1e-6
+    hist = sim.forces(0, n)
+    perimeter = np.pi * 20.0
+    assert np.max(np.abs(hist[:, 1:3])) <= 1e-5 * fl.rho_inf * fl.T_inf * perimeter
+    assert abs(hist[-1, 4] - (n - 1) * fl.dt * U) <= 1e-9
+    ho = np.array(ora.history)
+    assert np.max(np.abs(hist[:, 4] - ho[:, 4])) <= 1e-12

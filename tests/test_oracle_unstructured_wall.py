@@ -197,3 +197,21 @@ def test_distance_blending_measures_from_the_wall_polygon():
     # the band is narrow against the blending width: the two readings differ
     assert sag < 0.05 * (b.r_blend - b.r_rigid)
     assert np.max(np.abs(sol.r - factor(d_rad))) > 0.0
+
+
+def test_body_carried_by_uniform_gas_changes_nothing_but_its_position():
+    """Galilean check of the moving mesh: a body moving with gas in uniform
+    motion (the wall's mesh velocity equals the gas velocity) leaves the gas
+    uniform to rounding and feels no force; the wall condition of a fixed body
+    (u_t = 0) or a wrong sign of V_G would disturb it at the first step."""
+    from synth.unstructured import q9_comoving_case
+    m, fl, b, (r, u, v, T) = q9_comoving_case()
+    o = UnstructuredWallSolver(m, fl, b, r, u, v, T)
+    o.run(30)
+    rr, ux, uy, E, Tt = o.macroscopic()
+    U = v[0]
+    assert np.max(np.abs(rr - 1.0)) < 1e-13 and np.max(np.abs(ux)) < 1e-13
+    assert np.max(np.abs(uy - U)) < 1e-13 and np.max(np.abs(Tt - T[0])) < 1e-13
+    h = np.array(o.history)
+    assert np.max(np.abs(h[:, 1:4])) < 1e-11
+    assert abs(h[-1, 4] - 29 * fl.dt * U) < 1e-12
