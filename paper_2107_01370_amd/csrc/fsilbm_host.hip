@@ -32,6 +32,7 @@ struct fsi_ctx {
     std::vector<float2> erel;       // [E][9] offsets from the element's centre node
     std::vector<int> patch_off, patch_ent;
     std::vector<int> patch8;            // [N][8] first patch entries, -1 past the end
+    std::vector<float2> q9_dgr;         // moving body: [N][3] nodal derivatives of r, r X, r Y
     // node blocks of the LDS-staged interpolation (empty: device-memory gathers)
     std::vector<int> bh_off, bh_nodes, be_off, be_elem;
     std::vector<uint16_t> be_nodes, uself;
@@ -55,7 +56,7 @@ struct fsi_ctx {
            off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0,
            off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
            off_uself = 0, off_dep_le = 0, off_qflag = 0, off_qw = 0, off_qwidx = 0, off_qf = 0,
-           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_uegd = 0, off_patch8 = 0,
+           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_dgr = 0, off_patch8 = 0,
            total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
@@ -412,6 +413,62 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
                 for (int a = 0; a < 9; ++a)
                     if (c->qflag[c->elems[9 * (size_t)e + a]] & fsi::Q9_MOVES) c->qflag[v] |= fsi::Q9_PATCH_MOVES;
             }
+        // The displacement at level n+1 is (1 - r)(A X + b) with A = R(a) - I
+        // and b = (0, h) - A X_EA of that level's body state, so its nodal
+        // finite-element derivative (the mean over the node's elements of the
+        // element derivative at the node) is, by linearity and the exactness
+        // of that derivative for linear fields, A - A L[r X] - b (x) L[r] with
+        // L[F] the nodal derivative of the static field F.  L[r], L[r X] and
+        // L[r Y] are formed here once, in FP64 on the undeformed mesh.
+        {
+            const int lp[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0}, lq[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
+            auto dl = [](int p, int x) { return p < 0 ? x - 0.5 : (p == 0 ? -2.0 * x : x + 0.5); };
+            std::vector<double> rn(N), acc(6 * N, 0.0);
+            for (size_t v = 0; v < N; ++v)
+                rn[v] = blend_r(b, c->X[2 * v], c->X[2 * v + 1], b.blend_mode == 1 ? c->wall_dist[v] : 0.0);
+            for (int e = 0; e < c->n_elems; ++e) {
+                const double *xe = &c->ecoord[18 * (size_t)e];
+                double F[3][9];
+                for (int a = 0; a < 9; ++a) {
+                    const size_t v = (size_t)c->elems[9 * (size_t)e + a];
+                    F[0][a] = rn[v];
+                    F[1][a] = rn[v] * c->X[2 * v];
+                    F[2][a] = rn[v] * c->X[2 * v + 1];
+                }
+                for (int a = 0; a < 9; ++a) {
+                    double xxi = 0, yxi = 0, xeta = 0, yeta = 0, fxi[3] = {}, feta[3] = {};
+                    for (int m = -1; m <= 1; ++m) {
+                        int si = -1, sj = -1;
+                        for (int q = 0; q < 9; ++q) {
+                            if (lp[q] == m && lq[q] == lq[a]) si = q;
+                            if (lp[q] == lp[a] && lq[q] == m) sj = q;
+                        }
+                        const double wi = dl(m, lp[a]), wj = dl(m, lq[a]);
+                        xxi += wi * (xe[2 * si] - xe[2 * a]);
+                        yxi += wi * (xe[2 * si + 1] - xe[2 * a + 1]);
+                        xeta += wj * (xe[2 * sj] - xe[2 * a]);
+                        yeta += wj * (xe[2 * sj + 1] - xe[2 * a + 1]);
+                        for (int f = 0; f < 3; ++f) {
+                            fxi[f] += wi * (F[f][si] - F[f][a]);
+                            feta[f] += wj * (F[f][sj] - F[f][a]);
+                        }
+                    }
+                    const double idet = 1.0 / (xxi * yeta - yxi * xeta);
+                    const size_t v = (size_t)c->elems[9 * (size_t)e + a];
+                    for (int f = 0; f < 3; ++f) {
+                        acc[6 * v + 2 * f] += idet * (yeta * fxi[f] - yxi * feta[f]);
+                        acc[6 * v + 2 * f + 1] += idet * (-xeta * fxi[f] + xxi * feta[f]);
+                    }
+                }
+            }
+            c->q9_dgr.assign(3 * N, make_float2(0.0f, 0.0f));
+            for (size_t v = 0; v < N; ++v) {
+                const double inv = 1.0 / (double)(c->patch_off[v + 1] - c->patch_off[v]);
+                for (int f = 0; f < 3; ++f)
+                    c->q9_dgr[3 * v + f] = make_float2((float)(acc[6 * v + 2 * f] * inv),
+                                                       (float)(acc[6 * v + 2 * f + 1] * inv));
+            }
+        }
     }
     const double dt = c->fluid.dt;
     for (int k = 0; k < nw; ++k) {
@@ -873,7 +930,7 @@ void layout(fsi_ctx *c) {
         c->off_qwprev = take(c->qw_nodes.size() * sizeof(float2));
         if (c->q9_moving) {
             c->off_qdisp = take(2 * N * sizeof(double2));
-            c->off_uegd = take(9 * (size_t)c->n_elems * sizeof(float4));
+            c->off_dgr = take(c->q9_dgr.size() * sizeof(float2));
         }
         c->off_patch8 = take(c->patch8.size() * 4);
         if (!c->bh_off.empty()) {
@@ -1138,7 +1195,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.qw_xyB = reinterpret_cast<const float2 *>(c->ws + c->off_qwxyB);
         P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
         P.qdisp = c->q9_moving ? reinterpret_cast<double2 *>(c->ws + c->off_qdisp) : nullptr;
-        P.uegd = c->q9_moving ? reinterpret_cast<float4 *>(c->ws + c->off_uegd) : nullptr;
+        P.dgr = c->q9_moving ? reinterpret_cast<const float2 *>(c->ws + c->off_dgr) : nullptr;
         P.patch8 = reinterpret_cast<const int *>(c->ws + c->off_patch8);
         {
             const std::pair<size_t, std::pair<const void *, size_t>> up[] = {
@@ -1149,7 +1206,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                 {c->off_qwgeo, {c->qw_geo.data(), c->qw_geo.size() * sizeof(double4)}},
                 {c->off_qweB, {c->qw_eB.data(), c->qw_eB.size() * 4}},
                 {c->off_qwxyB, {c->qw_xyB.data(), c->qw_xyB.size() * sizeof(float2)}},
-                {c->off_patch8, {c->patch8.data(), c->patch8.size() * 4}}};
+                {c->off_patch8, {c->patch8.data(), c->patch8.size() * 4}},
+                {c->off_dgr, {c->q9_dgr.data(), c->q9_dgr.size() * sizeof(float2)}}};
             for (const auto &u : up)
                 if (u.second.second)
                     HIP_TRY(c, hipMemcpyAsync(c->ws + u.first, u.second.first, u.second.second,

@@ -146,7 +146,7 @@ struct Inst {
     float2 *qw_prev;          // [n_qw] (rho, T) of the completed wall node, previous level
     // a moving body on a Q9 mesh (null: fixed)
     double2 *qdisp;           // [2][n_nodes] blended displacement at levels n, n+1
-    float4 *uegd;             // [n_elems][9] derivatives of the level-(n+1) displacement
+    const float2 *dgr;        // [n_nodes][3] nodal derivatives of r, r X, r Y (moving body)
     const int *patch8;        // [n_nodes][8] first patch entries (Q9 meshes), -1 past the end
 };
 

@@ -25,8 +25,8 @@ namespace fsi {
 //                and mu/p of the new populations for the next step
 //                (k_u_moments forms them when the host sets populations)
 // and, for a moving body, before them: k_u_motion (blended displacements of
-// levels n and n+1), k_u_dgrad (their element derivatives) and k_u_relocate
-// (the departure points on the mesh of the new level, every step).
+// levels n and n+1) and k_u_relocate (the departure points on the mesh of the
+// new level, every step).
 // A nodal derivative is the mean over the node's elements of the element
 // derivative J^{-T} sum_s C_s grad_xi N_s at the node's own local position,
 // where only the three nodes on each of the node's element lines contribute
@@ -258,64 +258,6 @@ __global__ void __launch_bounds__(U_THREADS) k_u_motion(const Inst *__restrict__
     }
 }
 
-// Element pass of the displacement's derivatives on the undeformed mesh at
-// level n+1, at each element node: (d dx/dX, d dx/dY, d dy/dX, d dy/dY)
-__global__ void __launch_bounds__(U_THREADS) k_u_dgrad(const Inst *__restrict__ pinst) {
-    const Inst &P = *pinst;
-    const double2 *d1 = P.qdisp + P.n_nodes;
-    for (long long e = xcd_block() * blockDim.x + threadIdx.x; e < P.n_elems;
-         e += (long long)gridDim.x * blockDim.x) {
-        int nd[9];
-        bool moves = false;
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-            nd[s] = P.elems[9 * e + s];
-            moves |= (P.qflag[nd[s]] & Q9_MOVES) != 0;
-        }
-        if (!moves) {
-            // no node of the element moves: the derivatives are zero
-#pragma unroll
-            for (int a = 0; a < 9; ++a) P.uegd[9 * e + a] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            continue;
-        }
-        double2 dv[9];
-        float2 rel[9];
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-            dv[s] = d1[nd[s]];
-            rel[s] = P.erel[9 * e + s];
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int pa = q9_p(a), qa = q9_q(a);
-            float axi = 0.0f, aeta = 0.0f, bxi = 0.0f, beta = 0.0f;
-            float xxi = 0.0f, yxi = 0.0f, xeta = 0.0f, yeta = 0.0f;
-#pragma unroll
-            for (int m = -1; m <= 1; ++m) {
-                if (m != pa) {
-                    const int si = q9_node(m, qa);
-                    const float w = dlag_at(m, pa);
-                    axi += w * (float)(dv[si].x - dv[a].x);
-                    bxi += w * (float)(dv[si].y - dv[a].y);
-                    xxi += w * (rel[si].x - rel[a].x);
-                    yxi += w * (rel[si].y - rel[a].y);
-                }
-                if (m != qa) {
-                    const int sj = q9_node(pa, m);
-                    const float w = dlag_at(m, qa);
-                    aeta += w * (float)(dv[sj].x - dv[a].x);
-                    beta += w * (float)(dv[sj].y - dv[a].y);
-                    xeta += w * (rel[sj].x - rel[a].x);
-                    yeta += w * (rel[sj].y - rel[a].y);
-                }
-            }
-            const float idet = 1.0f / (xxi * yeta - yxi * xeta);
-            P.uegd[9 * e + a] = make_float4(idet * (yeta * axi - yxi * aeta), idet * (-xeta * axi + xxi * aeta),
-                                            idet * (yeta * bxi - yxi * beta), idet * (-xeta * bxi + xxi * beta));
-        }
-    }
-}
-
 // Local coordinates of the point at offset (px, py) from local node a of
 // element e under the element's corner map (Newton in FP32 from (u, v))
 __device__ __forceinline__ void q9_corner_newton(const Inst &P, long long e, int a, float px, float py,
@@ -431,18 +373,21 @@ constexpr int U_PATCH_REG = 8;
 
 // Departure points of a moving body, every step: X - dt g^{-1}(c_k - V_G) in
 // the undeformed frame, g = I + dd/dX at level n+1 (the nodal mean of the
-// element derivatives), V_G = (d^{n+1} - d^n) / dt; the previous step's
+// element derivatives, formed from the static nodal derivatives of r, r X and
+// r Y and the body state), V_G = (d^{n+1} - d^n) / dt; the previous step's
 // element is tried first, by Newton from its local coordinates, then the
 // patch in order as for a static mesh.  Two threads per node (neighbouring
 // lanes, directions 1-4 and 5-8), each issuing its loads in two round trips
 // (flag, previous table entries, displacements and the node's first eight
-// patch entries at a fixed stride; then the element derivatives and the
-// corners of the previous elements), rather than one per direction.
+// patch entries at a fixed stride; then the corners of the previous
+// elements), rather than one per direction.
 constexpr int U_REL_DIRS = 4;   // directions per thread
 __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
     const float dt = P.dt;
     const long long N = P.n_nodes;
+    const Body &body = P.body[0];
+    const BodySlot s1 = P.slots[((*P.step + 1) % 3) * MAX_BODIES];
     unsigned err = 0;
     for (long long tid = xcd_block() * blockDim.x + threadIdx.x; tid < 2 * N;
          tid += (long long)gridDim.x * blockDim.x) {
@@ -462,6 +407,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict
             pxy[j] = P.dep_xy[(k0 - 1 + j) * N + idx];
         }
         const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
+        const float2 Lr = P.dgr[3 * idx], LrX = P.dgr[3 * idx + 1], LrY = P.dgr[3 * idx + 2];
         if (!(flag & Q9_PATCH_MOVES)) continue;
         const bool bnd = (flag & Q9_BOUNDARY) != 0;
         const int ent[U_PATCH_REG] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
@@ -475,25 +421,6 @@ __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict
             b = P.patch_off[idx];
             e_end = P.patch_off[idx + 1];
             cnt = e_end - b;
-        }
-        float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
-#pragma unroll
-        for (int j = 0; j < U_PATCH_REG; ++j) {
-            if (j < cnt) {
-                const float4 dg = P.uegd[9 * (long long)(ent[j] >> 4) + (ent[j] & 15)];
-                s00 += dg.x;
-                s01 += dg.y;
-                s10 += dg.z;
-                s11 += dg.w;
-            }
-        }
-        for (int q = b + U_PATCH_REG; q < e_end; ++q) {
-            const int en = P.patch_ent[q];
-            const float4 dg = P.uegd[9 * (long long)(en >> 4) + (en & 15)];
-            s00 += dg.x;
-            s01 += dg.y;
-            s10 += dg.z;
-            s11 += dg.w;
         }
         // the node's local index in each previous element
         int la[U_REL_DIRS];
@@ -516,8 +443,16 @@ __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict
             c3[j] = rel[3];
             ra[j] = rel[la[j] >= 0 ? la[j] : 0];
         }
-        const float inv = 1.0f / (float)cnt;
-        const float g00 = 1.0f + s00 * inv, g01 = s01 * inv, g10 = s10 * inv, g11 = 1.0f + s11 * inv;
+        // g = I + A - A L[r X] - b (x) L[r] (the nodal derivative of the
+        // displacement (1 - r)(A X + b) of level n+1, A = R(a) - I,
+        // b = (0, h) - A X_EA)
+        const float A00 = (float)s1.cm1, A01 = (float)(-s1.sa), A10 = (float)s1.sa, A11 = (float)s1.cm1;
+        const float b0 = (float)(-(s1.cm1 * body.ex - s1.sa * body.ey));
+        const float b1 = (float)(s1.h - (s1.sa * body.ex + s1.cm1 * body.ey));
+        const float g00 = 1.0f + A00 - (A00 * LrX.x + A01 * LrY.x) - b0 * Lr.x;
+        const float g01 = A01 - (A00 * LrX.y + A01 * LrY.y) - b0 * Lr.y;
+        const float g10 = A10 - (A10 * LrX.x + A11 * LrY.x) - b1 * Lr.x;
+        const float g11 = 1.0f + A11 - (A10 * LrX.y + A11 * LrY.y) - b1 * Lr.y;
         const float vgx = (float)((d1.x - d0.x) / P.dt_d), vgy = (float)((d1.y - d0.y) / P.dt_d);
         const float idg = 1.0f / (g00 * g11 - g01 * g10);
 #pragma unroll
@@ -1039,10 +974,8 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
 hipError_t launch_unstructured_motion(const Inst *inst, long long n_nodes, long long n_elems, int relocate,
                                       hipStream_t s) {
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
-    const long long e64 = ((n_elems + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
     hipLaunchKernelGGL(k_u_motion, dim3((unsigned)g64), dim3(U_THREADS), 0, s, inst);
     if (relocate) {
-        hipLaunchKernelGGL(k_u_dgrad, dim3((unsigned)e64), dim3(U_THREADS), 0, s, inst);
         // two threads per node
         const long long r64 = ((2 * n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
         hipLaunchKernelGGL(k_u_relocate, dim3((unsigned)r64), dim3(U_THREADS), 0, s, inst);
