@@ -961,14 +961,16 @@ const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c
 fsi_status enqueue_fluid(fsi_ctx *c) {
     const int st = c->fluid.storage;
     if (c->topo == FSI_TOPO_Q9) {
-        // a moving body: the mesh of both levels and the departure points on it
+        // a moving body: the mesh of both levels and the departure points on
+        // it (relocated by the node-block kernel itself where it runs)
+        const bool fused = c->q9_moving && c->inst.u_nblk > 0;
         if (c->q9_moving)
-            HIP_TRY(c, fsi::launch_unstructured_motion(d_inst(c), (long long)c->ni, (long long)c->n_elems, 1,
-                                                       c->stream));
+            HIP_TRY(c, fsi::launch_unstructured_motion(d_inst(c), (long long)c->ni, (long long)c->n_elems,
+                                                       fused ? 0 : 1, c->stream));
         HIP_TRY(c, fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, st,
                                             c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
                                             c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->inst.qdisp,
-                                            c->stream));
+                                            fused ? 1 : 0, c->stream));
         if (!c->qw_nodes.empty() || !c->qf_nodes.empty())
             HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(),
                                                          (int)c->qf_nodes.size(), st, 1, c->stream));
@@ -1585,7 +1587,7 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                 e = fsi::launch_unstructured(d_inst(c), (long long)c->ni, (long long)c->n_elems, stg,
                                              c->inst.uq, c->inst.ud, c->inst.ueg, c->inst.u_nblk,
                                              c->inst.u_hmax, c->inst.u_lemax, c->inst.u_eu16, c->inst.qdisp,
-                                             c->stream);
+                                             0, c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
                                                c->cut, 0);

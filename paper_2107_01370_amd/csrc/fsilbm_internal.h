@@ -182,7 +182,7 @@ hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_wor
 hipError_t launch_body(const Inst *insts, int n_inst, int phase, hipStream_t s);
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
                                float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
-                               int eu16, const double2 *disp0, hipStream_t s);
+                               int eu16, const double2 *disp0, int relocate, hipStream_t s);
 // a moving body on a Q9 mesh: node displacements of levels n and n+1, and
 // (relocate) the departure points on the moving mesh
 hipError_t launch_unstructured_dep_le(const Inst *inst, long long n_nodes, hipStream_t s);

@@ -381,128 +381,132 @@ constexpr int U_PATCH_REG = 8;
 // (flag, previous table entries, displacements and the node's first eight
 // patch entries at a fixed stride; then the corners of the previous
 // elements), rather than one per direction.
-constexpr int U_REL_DIRS = 4;   // directions per thread
-__global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict__ pinst) {
-    const Inst &P = *pinst;
+constexpr int U_REL_DIRS = 4;   // directions per call
+__device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, int k0, const BodySlot &s1,
+                                                const Body &body, unsigned &err) {
     const float dt = P.dt;
     const long long N = P.n_nodes;
-    const Body &body = P.body[0];
+    // every load of the node's first round trip, before the flag decides
+    // (a patch the blending leaves in place keeps the undeformed mesh's
+    // departure points)
+    const uint8_t flag = P.qflag[idx];
+    const int4 pa = reinterpret_cast<const int4 *>(P.patch8)[2 * idx];
+    const int4 pb = reinterpret_cast<const int4 *>(P.patch8)[2 * idx + 1];
+    int ep[U_REL_DIRS];
+    float2 pxy[U_REL_DIRS];
+#pragma unroll
+    for (int j = 0; j < U_REL_DIRS; ++j) {
+        ep[j] = P.dep_e[(k0 - 1 + j) * N + idx];
+        pxy[j] = P.dep_xy[(k0 - 1 + j) * N + idx];
+    }
+    const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
+    const float2 Lr = P.dgr[3 * idx], LrX = P.dgr[3 * idx + 1], LrY = P.dgr[3 * idx + 2];
+    if (!(flag & Q9_PATCH_MOVES)) return;
+    const bool bnd = (flag & Q9_BOUNDARY) != 0;
+    const int ent[U_PATCH_REG] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
+    // patch size: the entries held, or from the patch offsets for a node
+    // with more than eight elements
+    int b = 0, e_end = 0, cnt = 0;
+#pragma unroll
+    for (int j = 0; j < U_PATCH_REG; ++j) cnt += ent[j] >= 0 ? 1 : 0;
+    const bool big = ent[U_PATCH_REG - 1] >= 0;
+    if (big) {
+        b = P.patch_off[idx];
+        e_end = P.patch_off[idx + 1];
+        cnt = e_end - b;
+    }
+    // the node's local index in each previous element
+    int la[U_REL_DIRS];
+#pragma unroll
+    for (int j = 0; j < U_REL_DIRS; ++j) {
+        la[j] = -1;
+#pragma unroll
+        for (int i = 0; i < U_PATCH_REG; ++i)
+            if (i < cnt && (ent[i] >> 4) == ep[j]) la[j] = ent[i] & 15;
+        for (int q = b + U_PATCH_REG; q < e_end; ++q)
+            if ((P.patch_ent[q] >> 4) == ep[j]) la[j] = P.patch_ent[q] & 15;
+    }
+    float2 c0[U_REL_DIRS], c1[U_REL_DIRS], c2[U_REL_DIRS], c3[U_REL_DIRS], ra[U_REL_DIRS];
+#pragma unroll
+    for (int j = 0; j < U_REL_DIRS; ++j) {
+        const float2 *rel = P.erel + 9 * (long long)(la[j] >= 0 ? ep[j] : 0);
+        c0[j] = rel[0];
+        c1[j] = rel[1];
+        c2[j] = rel[2];
+        c3[j] = rel[3];
+        ra[j] = rel[la[j] >= 0 ? la[j] : 0];
+    }
+    // g = I + A - A L[r X] - b (x) L[r] (the nodal derivative of the
+    // displacement (1 - r)(A X + b) of level n+1, A = R(a) - I,
+    // b = (0, h) - A X_EA)
+    const float A00 = (float)s1.cm1, A01 = (float)(-s1.sa), A10 = (float)s1.sa, A11 = (float)s1.cm1;
+    const float b0 = (float)(-(s1.cm1 * body.ex - s1.sa * body.ey));
+    const float b1 = (float)(s1.h - (s1.sa * body.ex + s1.cm1 * body.ey));
+    const float g00 = 1.0f + A00 - (A00 * LrX.x + A01 * LrY.x) - b0 * Lr.x;
+    const float g01 = A01 - (A00 * LrX.y + A01 * LrY.y) - b0 * Lr.y;
+    const float g10 = A10 - (A10 * LrX.x + A11 * LrY.x) - b1 * Lr.x;
+    const float g11 = 1.0f + A11 - (A10 * LrX.y + A11 * LrY.y) - b1 * Lr.y;
+    const float vgx = (float)((d1.x - d0.x) / P.dt_d), vgy = (float)((d1.y - d0.y) / P.dt_d);
+    const float idg = 1.0f / (g00 * g11 - g01 * g10);
+#pragma unroll
+    for (int j = 0; j < U_REL_DIRS; ++j) {
+        const int k = k0 + j;
+        const float ax = (float)CXK(k) - vgx, ay = (float)CYK(k) - vgy;
+        const float dx = -dt * idg * (g11 * ax - g01 * ay);
+        const float dy = -dt * idg * (-g10 * ax + g00 * ay);
+        int e = -1;
+        float xi = 0.0f, eta = 0.0f;
+        if (la[j] >= 0) {
+            // Newton on the previous element's corner map, written as
+            // x(u, v) = A + B u + C v + D u v, from the previous local
+            // coordinates; the point moves little from step to step, so
+            // it stops once an update falls below 1e-6 (at most 4)
+            const float2 C0 = c0[j], C1 = c1[j], C2 = c2[j], C3 = c3[j];
+            const float Ax = 0.25f * (C0.x + C1.x + C2.x + C3.x) - (dx + ra[j].x);
+            const float Ay = 0.25f * (C0.y + C1.y + C2.y + C3.y) - (dy + ra[j].y);
+            const float Bx = 0.25f * (-C0.x + C1.x + C2.x - C3.x), By = 0.25f * (-C0.y + C1.y + C2.y - C3.y);
+            const float Cx = 0.25f * (-C0.x - C1.x + C2.x + C3.x), Cy = 0.25f * (-C0.y - C1.y + C2.y + C3.y);
+            const float Dx = 0.25f * (C0.x - C1.x + C2.x - C3.x), Dy = 0.25f * (C0.y - C1.y + C2.y - C3.y);
+            float u = pxy[j].x, v = pxy[j].y;
+            for (int it = 0; it < 4; ++it) {
+                const float rx = Ax + Bx * u + (Cx + Dx * u) * v;
+                const float ry = Ay + By * u + (Cy + Dy * u) * v;
+                const float ja = Bx + Dx * v, jb = Cx + Dx * u, jc = By + Dy * v, jd = Cy + Dy * u;
+                const float id = 1.0f / (ja * jd - jb * jc);
+                const float du = id * (jd * rx - jb * ry), dv = id * (-jc * rx + ja * ry);
+                u -= du;
+                v -= dv;
+                if (fabsf(du) + fabsf(dv) < 1e-6f) break;
+            }
+            if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
+                e = ep[j];
+                xi = u;
+                eta = v;
+            }
+        }
+        if (e < 0) {
+            // left the previous element: the patch in order
+            const int pb0 = P.patch_off[idx], pe0 = P.patch_off[idx + 1];
+            u_patch_search(P, pb0, pe0, dx, dy, e, xi, eta);
+            if (e < 0 && !bnd) {
+                err |= ERR_CFL;
+                e = P.patch_ent[pb0] >> 4;
+            }
+        }
+        u_dep_store(P, idx, k, e, xi, eta, e != ep[j]);
+    }
+}
+
+// two threads per node (neighbouring lanes: directions 1-4 and 5-8); the
+// node-block interpolation kernel does the same for its own nodes when it
+// runs with the relocation folded in
+__global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict__ pinst) {
+    const Inst &P = *pinst;
     const BodySlot s1 = P.slots[((*P.step + 1) % 3) * MAX_BODIES];
     unsigned err = 0;
-    for (long long tid = xcd_block() * blockDim.x + threadIdx.x; tid < 2 * N;
-         tid += (long long)gridDim.x * blockDim.x) {
-        const long long idx = tid >> 1;
-        const int k0 = 1 + U_REL_DIRS * (int)(tid & 1);
-        // every load of the node's first round trip, before the flag decides
-        // (a patch the blending leaves in place keeps the undeformed mesh's
-        // departure points)
-        const uint8_t flag = P.qflag[idx];
-        const int4 pa = reinterpret_cast<const int4 *>(P.patch8)[2 * idx];
-        const int4 pb = reinterpret_cast<const int4 *>(P.patch8)[2 * idx + 1];
-        int ep[U_REL_DIRS];
-        float2 pxy[U_REL_DIRS];
-#pragma unroll
-        for (int j = 0; j < U_REL_DIRS; ++j) {
-            ep[j] = P.dep_e[(k0 - 1 + j) * N + idx];
-            pxy[j] = P.dep_xy[(k0 - 1 + j) * N + idx];
-        }
-        const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
-        const float2 Lr = P.dgr[3 * idx], LrX = P.dgr[3 * idx + 1], LrY = P.dgr[3 * idx + 2];
-        if (!(flag & Q9_PATCH_MOVES)) continue;
-        const bool bnd = (flag & Q9_BOUNDARY) != 0;
-        const int ent[U_PATCH_REG] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
-        // patch size: the entries held, or from the patch offsets for a node
-        // with more than eight elements
-        int b = 0, e_end = 0, cnt = 0;
-#pragma unroll
-        for (int j = 0; j < U_PATCH_REG; ++j) cnt += ent[j] >= 0 ? 1 : 0;
-        const bool big = ent[U_PATCH_REG - 1] >= 0;
-        if (big) {
-            b = P.patch_off[idx];
-            e_end = P.patch_off[idx + 1];
-            cnt = e_end - b;
-        }
-        // the node's local index in each previous element
-        int la[U_REL_DIRS];
-#pragma unroll
-        for (int j = 0; j < U_REL_DIRS; ++j) {
-            la[j] = -1;
-#pragma unroll
-            for (int i = 0; i < U_PATCH_REG; ++i)
-                if (i < cnt && (ent[i] >> 4) == ep[j]) la[j] = ent[i] & 15;
-            for (int q = b + U_PATCH_REG; q < e_end; ++q)
-                if ((P.patch_ent[q] >> 4) == ep[j]) la[j] = P.patch_ent[q] & 15;
-        }
-        float2 c0[U_REL_DIRS], c1[U_REL_DIRS], c2[U_REL_DIRS], c3[U_REL_DIRS], ra[U_REL_DIRS];
-#pragma unroll
-        for (int j = 0; j < U_REL_DIRS; ++j) {
-            const float2 *rel = P.erel + 9 * (long long)(la[j] >= 0 ? ep[j] : 0);
-            c0[j] = rel[0];
-            c1[j] = rel[1];
-            c2[j] = rel[2];
-            c3[j] = rel[3];
-            ra[j] = rel[la[j] >= 0 ? la[j] : 0];
-        }
-        // g = I + A - A L[r X] - b (x) L[r] (the nodal derivative of the
-        // displacement (1 - r)(A X + b) of level n+1, A = R(a) - I,
-        // b = (0, h) - A X_EA)
-        const float A00 = (float)s1.cm1, A01 = (float)(-s1.sa), A10 = (float)s1.sa, A11 = (float)s1.cm1;
-        const float b0 = (float)(-(s1.cm1 * body.ex - s1.sa * body.ey));
-        const float b1 = (float)(s1.h - (s1.sa * body.ex + s1.cm1 * body.ey));
-        const float g00 = 1.0f + A00 - (A00 * LrX.x + A01 * LrY.x) - b0 * Lr.x;
-        const float g01 = A01 - (A00 * LrX.y + A01 * LrY.y) - b0 * Lr.y;
-        const float g10 = A10 - (A10 * LrX.x + A11 * LrY.x) - b1 * Lr.x;
-        const float g11 = 1.0f + A11 - (A10 * LrX.y + A11 * LrY.y) - b1 * Lr.y;
-        const float vgx = (float)((d1.x - d0.x) / P.dt_d), vgy = (float)((d1.y - d0.y) / P.dt_d);
-        const float idg = 1.0f / (g00 * g11 - g01 * g10);
-#pragma unroll
-        for (int j = 0; j < U_REL_DIRS; ++j) {
-            const int k = k0 + j;
-            const float ax = (float)CXK(k) - vgx, ay = (float)CYK(k) - vgy;
-            const float dx = -dt * idg * (g11 * ax - g01 * ay);
-            const float dy = -dt * idg * (-g10 * ax + g00 * ay);
-            int e = -1;
-            float xi = 0.0f, eta = 0.0f;
-            if (la[j] >= 0) {
-                // Newton on the previous element's corner map, written as
-                // x(u, v) = A + B u + C v + D u v, from the previous local
-                // coordinates; the point moves little from step to step, so
-                // it stops once an update falls below 1e-6 (at most 4)
-                const float2 C0 = c0[j], C1 = c1[j], C2 = c2[j], C3 = c3[j];
-                const float Ax = 0.25f * (C0.x + C1.x + C2.x + C3.x) - (dx + ra[j].x);
-                const float Ay = 0.25f * (C0.y + C1.y + C2.y + C3.y) - (dy + ra[j].y);
-                const float Bx = 0.25f * (-C0.x + C1.x + C2.x - C3.x), By = 0.25f * (-C0.y + C1.y + C2.y - C3.y);
-                const float Cx = 0.25f * (-C0.x - C1.x + C2.x + C3.x), Cy = 0.25f * (-C0.y - C1.y + C2.y + C3.y);
-                const float Dx = 0.25f * (C0.x - C1.x + C2.x - C3.x), Dy = 0.25f * (C0.y - C1.y + C2.y - C3.y);
-                float u = pxy[j].x, v = pxy[j].y;
-                for (int it = 0; it < 4; ++it) {
-                    const float rx = Ax + Bx * u + (Cx + Dx * u) * v;
-                    const float ry = Ay + By * u + (Cy + Dy * u) * v;
-                    const float ja = Bx + Dx * v, jb = Cx + Dx * u, jc = By + Dy * v, jd = Cy + Dy * u;
-                    const float id = 1.0f / (ja * jd - jb * jc);
-                    const float du = id * (jd * rx - jb * ry), dv = id * (-jc * rx + ja * ry);
-                    u -= du;
-                    v -= dv;
-                    if (fabsf(du) + fabsf(dv) < 1e-6f) break;
-                }
-                if (fabsf(u) <= 1.0f + 1e-5f && fabsf(v) <= 1.0f + 1e-5f) {
-                    e = ep[j];
-                    xi = u;
-                    eta = v;
-                }
-            }
-            if (e < 0) {
-                // left the previous element: the patch in order
-                const int pb0 = P.patch_off[idx], pe0 = P.patch_off[idx + 1];
-                u_patch_search(P, pb0, pe0, dx, dy, e, xi, eta);
-                if (e < 0 && !bnd) {
-                    err |= ERR_CFL;
-                    e = P.patch_ent[pb0] >> 4;
-                }
-            }
-            u_dep_store(P, idx, k, e, xi, eta, e != ep[j]);
-        }
-    }
+    for (long long tid = xcd_block() * blockDim.x + threadIdx.x; tid < 2 * P.n_nodes;
+         tid += (long long)gridDim.x * blockDim.x)
+        u_relocate_dirs(P, tid >> 1, 1 + U_REL_DIRS * (int)(tid & 1), s1, P.body[0], err);
     if (err) atomicOr(P.err, err);
 }
 
@@ -563,7 +567,7 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
 // compiler may fuse multiply-adds differently in the two kernels, so the paths
 // agree to FP32 rounding).  Blocks go to XCDs in
 // contiguous runs, so neighbouring blocks share their halo's lines in one L2.
-template <int STORE, int EU16>
+template <int STORE, int EU16, bool MOV>
 __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__restrict__ pinst) {
     extern __shared__ __align__(16) unsigned char u_lds[];
     const Inst &P = *pinst;
@@ -582,6 +586,18 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     const int e0 = P.be_off[b], ne = P.be_off[b + 1] - e0;
     const long long n0 = (long long)b * U_BLOCK;
     unsigned err = 0;
+    if constexpr (MOV) {
+        // a moving body: this block's departure points on the mesh of the new
+        // level first (their memory round trips overlap the halo collisions
+        // of the other blocks on the CU); the interpolation below reads them
+        // back in the same thread
+        const long long r = n0 + threadIdx.x;
+        if (r < P.n_nodes) {
+            const BodySlot s1 = P.slots[((n + 1) % 3) * MAX_BODIES];
+            u_relocate_dirs(P, r, 1, s1, P.body[0], err);
+            u_relocate_dirs(P, r, 1 + U_REL_DIRS, s1, P.body[0], err);
+        }
+    }
     for (int h = threadIdx.x; h < nh; h += U_BLOCK) {
         const long long v = P.bh_nodes[h0 + h];
         const float2 F = node_mean(P, P.ueg, v);
@@ -940,7 +956,7 @@ hipError_t launch_unstructured_moments(const Inst *inst, long long n_nodes, int 
 
 hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_elems, int storage,
                                float2 *uq, float2 *ud, float2 *ueg, int n_blocks, int hmax, int lemax,
-                               int eu16, const double2 *disp0, hipStream_t s) {
+                               int eu16, const double2 *disp0, int relocate, hipStream_t s) {
     // multiples of the XCD count (see xcd_block)
     const long long g64 = ((n_nodes + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
     const long long e64 = ((n_elems + 8 * U_THREADS - 1) / (8 * U_THREADS)) * 8;
@@ -952,8 +968,13 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
         // a multiple of the XCD count; the kernel maps slots to blocks
         const unsigned g = (unsigned)(((n_blocks + 7) / 8) * 8);
         const size_t lds = u_block_lds_bytes(hmax, lemax, eu16);
-#define FSI_U_BLK(ST, EU)                                                                     \
-    hipLaunchKernelGGL((k_u_collide_stream_blk<ST, EU>), dim3(g), dim3(U_BLOCK), lds, s, inst)
+#define FSI_U_BLK(ST, EU)                                                                          \
+    do {                                                                                           \
+        if (relocate)                                                                              \
+            hipLaunchKernelGGL((k_u_collide_stream_blk<ST, EU, true>), dim3(g), dim3(U_BLOCK), lds, s, inst); \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_u_collide_stream_blk<ST, EU, false>), dim3(g), dim3(U_BLOCK), lds, s, inst); \
+    } while (0)
         if (storage == 0) {
             if (eu16 == 16) FSI_U_BLK(0, 16);
             else if (eu16 == 12) FSI_U_BLK(0, 12);
