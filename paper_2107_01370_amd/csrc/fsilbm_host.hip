@@ -1616,6 +1616,10 @@ fsi_status fsi_set_coupling(fsi_ctx *c, int subiterations, double relaxation) {
     if (!c) return FSI_E_ARG;
     if (subiterations < 1 || subiterations > 64 || !(relaxation > 0.0 && relaxation <= 1.0))
         return fail(c, FSI_E_ARG, "coupling needs 1 <= subiterations <= 64 and 0 < relaxation <= 1");
+    // the unstructured step forms the next step's moments and the wall's
+    // previous-level values in place, so a pass cannot be repeated
+    if (c->topo == FSI_TOPO_Q9 && subiterations > 1)
+        return fail(c, FSI_E_ARG, "strong coupling (subiterations > 1) is not available on Q9 meshes");
     drop_graph(c);
     c->n_sub = subiterations;
     c->relax = relaxation;
