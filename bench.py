@@ -433,7 +433,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build.", file=sys.stderr)
+              "decomposition is described as a design and not implemented.", file=sys.stderr)
         sys.exit(2)
     storage = 1 if args.storage == "fp16" else 0
     if args.workload not in WORKLOADS:
