@@ -297,9 +297,10 @@ fsi_status fsi_load(fsi_ctx *ctx, const void *host_buf, size_t bytes);
  * to the solution; the last pass is accepted (populations and the body state
  * they were computed with).  1 sub-iteration = the staggered scheme (the
  * default).  Each pass costs one collision-streaming launch.  FSI_E_ARG unless
- * 1 <= subiterations <= 64 and 0 < relaxation <= 1, and for subiterations > 1
- * on a Q9 mesh (its step forms the next step's moments in place).
- * Invalidates the captured graph; the state is kept. */
+ * 1 <= subiterations <= 64 and 0 < relaxation <= 1.  On a Q9 mesh each pass
+ * after the first first forms again the level-n moments and wall values that
+ * the previous pass overwrote.  Invalidates the captured graph; the state is
+ * kept. */
 fsi_status fsi_set_coupling(fsi_ctx *ctx, int subiterations, double relaxation);
 
 /* Largest change |solution - estimate| of body `body`'s state components in

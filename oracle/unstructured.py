@@ -351,6 +351,9 @@ class UnstructuredWallSolver(UnstructuredSolver):
         nn = np.hypot(self.nds_x, self.nds_y)
         self.B = g.locate(fluid.dt * self.nds_x / nn, fluid.dt * self.nds_y / nn, nodes=self.wall)
         self.history = []
+        self.subiterations = 1
+        self.relaxation = 1.0
+        self.residuals = []
 
     @staticmethod
     def _nds(xw, yw):
@@ -375,17 +378,19 @@ class UnstructuredWallSolver(UnstructuredSolver):
         departure points on a moving mesh)."""
         return self.dep[i][0] < 0
 
-    def wall_force(self, x=None, y=None, state=None):
-        """(F_x, F_y, M_EA) on the body from the current populations on the
-        mesh (x, y) of the body state `state` (default: the current level)."""
+    def wall_force(self, x=None, y=None, state=None, f=None, gp=None):
+        """(F_x, F_y, M_EA) on the body from the populations (f, gp) (default:
+        the current ones) on the mesh (x, y) of the body state `state`
+        (default: the current level)."""
         from .forces import wall_stress
         if state is None:
             state = self.state
         if x is None:
             x, y = self.positions(state)
         fl = self.fluid
-        sxx, sxy, syy = wall_stress(self.f[:, self.wall], self.g[:, self.wall], fl.gamma, fl.mu,
-                                    fl.Pr, fl.dt)
+        f = self.f if f is None else f
+        gp = self.g if gp is None else gp
+        sxx, sxy, syy = wall_stress(f[:, self.wall], gp[:, self.wall], fl.gamma, fl.mu, fl.Pr, fl.dt)
         xw, yw = x[self.wall], y[self.wall]
         nx, ny = self._nds(xw, yw)
         Fx_k = sxx * nx + sxy * ny
@@ -400,9 +405,23 @@ class UnstructuredWallSolver(UnstructuredSolver):
             Mz += Mz_k[k]
         return Fx, Fy, Mz
 
+    def coupling(self, subiterations=1, relaxation=1.0):
+        """Strong coupling by sub-iterations, read as on the structured meshes
+        (Sec. III names it for low mass ratios without giving an algorithm):
+        the step starts from the staggered predictor; each sub-iteration
+        streams the post-collision populations of t^n onto the mesh of the
+        current body estimate and applies the boundary conditions, takes the
+        load of the result, re-solves the body over the step with the load
+        varying linearly from F^n to it, and relaxes the estimate towards that
+        solution by `relaxation`; the last sub-iteration is accepted.  The
+        change |solution - estimate| of each sub-iteration is kept in
+        `residuals`.  One sub-iteration is the staggered scheme."""
+        assert subiterations >= 1 and 0.0 < relaxation <= 1.0
+        self.subiterations = int(subiterations)
+        self.relaxation = float(relaxation)
+
     def step(self):
         from . import body as B
-        from .boundary import grad_populations
         fl = self.fluid
         g = self.grid
         dt = fl.dt
@@ -410,18 +429,6 @@ class UnstructuredWallSolver(UnstructuredSolver):
         Fx_b, Fy_b, Mz_b = self.wall_force(x0, y0, self.state)
         self.history.append([float(self.n), Fx_b, Fy_b, Mz_b, self.state[0], self.state[1]])
         new_state = B.advance(self.body, self.state, Fy_b, Mz_b, (self.n + 1) * dt, dt)
-        x1, y1 = self.positions(new_state)
-        VGx, VGy = (x1 - x0) / dt, (y1 - y0) / dt
-        if self.moving:
-            # departure points in the undeformed frame: X - dt g^{-1}(c - V_G)
-            gxx, gxy = g.grad(x1)
-            gyx, gyy = g.grad(y1)
-            det = gxx * gyy - gxy * gyx
-            for i in range(1, L.Q):
-                ax, ay = L.CX[i] - VGx, L.CY[i] - VGy
-                chx = (gyy * ax - gxy * ay) / det
-                chy = (-gyx * ax + gxx * ay) / det
-                self.dep[i] = g.locate(-dt * chx, -dt * chy, allow_missing=self.bnd)
         rho0, _, _, _, T0 = L.macroscopic(self.f[:, self.wall], self.g[:, self.wall], fl.gamma)
         if self.correction:
             W0 = self._operator(x0, y0)
@@ -437,6 +444,43 @@ class UnstructuredWallSolver(UnstructuredSolver):
         else:
             Fx = Fy = np.zeros(g.N)
         fpost, gpost = L.collide(self.f, self.g, fl.gamma, fl.mu, fl.Pr, dt, Fx, Fy)
+        # streaming and boundaries on the mesh of the body estimate; with
+        # strong coupling repeated with the structure re-solved against the
+        # new load (the reading of `coupling`)
+        self.residuals = []
+        for it in range(self.subiterations):
+            f_new, g_new, x1, y1 = self._fluid(fpost, gpost, x0, y0, rho0, T0, new_state)
+            if self.subiterations == 1:
+                break
+            _, Fy1, M1 = self.wall_force(x1, y1, new_state, f_new, g_new)
+            target = B.advance(self.body, self.state, Fy_b, Mz_b, (self.n + 1) * dt, dt, Fy1, M1)
+            self.residuals.append(float(np.max(np.abs(target - new_state))))
+            if it + 1 < self.subiterations:
+                new_state = new_state + self.relaxation * (target - new_state)
+        self.f, self.g = f_new, g_new
+        self.state = new_state
+        self.n += 1
+
+    def _fluid(self, fpost, gpost, x0, y0, rho0, T0, new_state):
+        """Streaming of the post-collision populations onto the mesh of body
+        state `new_state`, far field and wall: the populations of the new
+        level and that mesh."""
+        from .boundary import grad_populations
+        fl = self.fluid
+        g = self.grid
+        dt = fl.dt
+        x1, y1 = self.positions(new_state)
+        VGx, VGy = (x1 - x0) / dt, (y1 - y0) / dt
+        if self.moving:
+            # departure points in the undeformed frame: X - dt g^{-1}(c - V_G)
+            gxx, gxy = g.grad(x1)
+            gyx, gyy = g.grad(y1)
+            det = gxx * gyy - gxy * gyx
+            for i in range(1, L.Q):
+                ax, ay = L.CX[i] - VGx, L.CY[i] - VGy
+                chx = (gyy * ax - gxy * ay) / det
+                chy = (-gyx * ax + gxx * ay) / det
+                self.dep[i] = g.locate(-dt * chx, -dt * chy, allow_missing=self.bnd)
         f_new = np.full_like(fpost, np.nan)
         g_new = np.full_like(gpost, np.nan)
         f_new[0] = fpost[0]
@@ -487,6 +531,5 @@ class UnstructuredWallSolver(UnstructuredSolver):
             f_new[i, self.wall[m]] = fw[i, m]
             g_new[i, self.wall[m]] = gw[i, m]
         assert not np.any(np.isnan(f_new)) and not np.any(np.isnan(g_new))
-        self.f, self.g = f_new, g_new
-        self.state = new_state
-        self.n += 1
+        return f_new, g_new, x1, y1
+

@@ -998,6 +998,15 @@ fsi_status enqueue_step(fsi_ctx *c) {
     // without a body there is nothing to iterate on: one pass
     const int passes = c->bodies.empty() ? 1 : c->n_sub;
     for (int k = 0; k < passes; ++k) {
+        if (k > 0 && c->topo == FSI_TOPO_Q9) {
+            // an unstructured pass overwrote the moments of level n (the next
+            // step's, formed by its interpolation) and the wall nodes' (rho, T)
+            // of level n: form them again from the populations of level n
+            HIP_TRY(c, fsi::launch_unstructured_moments(d_inst(c), (long long)c->ni, c->fluid.storage, c->stream));
+            if (!c->qw_nodes.empty())
+                HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(), 0,
+                                                             c->fluid.storage, 0, c->stream));
+        }
         fsi_status st = enqueue_fluid(c);
         if (st != FSI_OK) return st;
         HIP_TRY(c, fsi::launch_body(d_inst(c), 1, k + 1 < passes ? 2 : 1, c->stream));
@@ -1616,10 +1625,6 @@ fsi_status fsi_set_coupling(fsi_ctx *c, int subiterations, double relaxation) {
     if (!c) return FSI_E_ARG;
     if (subiterations < 1 || subiterations > 64 || !(relaxation > 0.0 && relaxation <= 1.0))
         return fail(c, FSI_E_ARG, "coupling needs 1 <= subiterations <= 64 and 0 < relaxation <= 1");
-    // the unstructured step forms the next step's moments and the wall's
-    // previous-level values in place, so a pass cannot be repeated
-    if (c->topo == FSI_TOPO_Q9 && subiterations > 1)
-        return fail(c, FSI_E_ARG, "strong coupling (subiterations > 1) is not available on Q9 meshes");
     drop_graph(c);
     c->n_sub = subiterations;
     c->relax = relaxation;

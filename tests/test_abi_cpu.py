@@ -389,13 +389,7 @@ def test_q9_mesh_round_a_body_is_accepted_and_validated(F):
         assert e.value.status == -1
     # a moving body: radial blending whose rigid zone holds every element at the wall
     moving = R(body, dof=1, m=1.0, k_h=1.0, r_rigid=12.5, r_blend=40.0)
-    ctx = F.fsi_create(fl, mesh, [moving], None)
-    # no strong coupling on these meshes (the step forms the next moments in place)
-    F.fsi_set_coupling(ctx, 1, 1.0)
-    with pytest.raises(F.FsiError) as e:
-        F.fsi_set_coupling(ctx, 3, 0.7)
-    assert e.value.status == -1 and "Q9" in str(e.value)
-    F.fsi_destroy(ctx)
+    F.fsi_destroy(F.fsi_create(fl, mesh, [moving], None))
     # distance blending measures from the wall polygon
     F.fsi_destroy(F.fsi_create(fl, mesh, [R(moving, blend_mode=1, r_rigid=5.0, r_blend=30.0)], None))
     for bad, what in ((R(moving, r_rigid=10.0), "rigid zone"), (R(moving, blend_mode=2), "blend_mode"),
