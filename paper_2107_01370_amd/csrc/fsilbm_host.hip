@@ -33,6 +33,7 @@ struct fsi_ctx {
     std::vector<int> patch_off, patch_ent;
     std::vector<int> patch8;            // [N][8] first patch entries, -1 past the end
     std::vector<float2> q9_dgr;         // moving body: [N][3] nodal derivatives of r, r X, r Y
+    std::vector<uint8_t> q9_eflag;      // moving body: [E] Q9E_MOVES, Q9E_RIGID
     // node blocks of the LDS-staged interpolation (empty: device-memory gathers)
     std::vector<int> bh_off, bh_nodes, be_off, be_elem;
     std::vector<uint16_t> be_nodes, uself;
@@ -56,7 +57,7 @@ struct fsi_ctx {
            off_ud = 0, off_upost = 0, off_dep_e = 0, off_dep_xy = 0, off_us = 0, off_ueg = 0,
            off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
            off_uself = 0, off_dep_le = 0, off_qflag = 0, off_qw = 0, off_qwidx = 0, off_qf = 0,
-           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_dgr = 0, off_patch8 = 0,
+           off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_dgr = 0, off_eflag = 0, off_patch8 = 0,
            total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
@@ -460,6 +461,18 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
                         acc[6 * v + 2 * f + 1] += idet * (-xeta * fxi[f] + xxi * feta[f]);
                     }
                 }
+            }
+            // elements with a moving node, and elements wholly in the rigid
+            // zone (a translation moves their nodes alike)
+            c->q9_eflag.assign((size_t)c->n_elems, 0);
+            for (int e = 0; e < c->n_elems; ++e) {
+                bool moves = false, rigid = true;
+                for (int a = 0; a < 9; ++a) {
+                    const size_t v = (size_t)c->elems[9 * (size_t)e + a];
+                    moves |= (c->qflag[v] & fsi::Q9_MOVES) != 0;
+                    rigid &= rn[v] == 0.0;
+                }
+                c->q9_eflag[e] = (moves ? fsi::Q9E_MOVES : 0) | (rigid ? fsi::Q9E_RIGID : 0);
             }
             c->q9_dgr.assign(3 * N, make_float2(0.0f, 0.0f));
             for (size_t v = 0; v < N; ++v) {
@@ -931,6 +944,7 @@ void layout(fsi_ctx *c) {
         if (c->q9_moving) {
             c->off_qdisp = take(2 * N * sizeof(double2));
             c->off_dgr = take(c->q9_dgr.size() * sizeof(float2));
+            c->off_eflag = take(c->q9_eflag.size());
         }
         c->off_patch8 = take(c->patch8.size() * 4);
         if (!c->bh_off.empty()) {
@@ -1196,6 +1210,12 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_pent, c->patch_ent.data(), c->patch_ent.size() * 4,
                                   hipMemcpyHostToDevice, c->stream));
         P.n_qw = (int)c->qw_nodes.size();
+        {
+            const fsi_body_desc *bd = c->bodies.empty() ? nullptr : &c->bodies[0];
+            P.q9_rotates = c->q9_moving && bd &&
+                           (bd->dof == FSI_DOF_PITCH_PLUNGE || bd->a0 != 0.0 || bd->ad0 != 0.0 ||
+                            bd->pitch_amp != 0.0);
+        }
         P.n_qf = (int)c->qf_nodes.size();
         P.qflag = reinterpret_cast<const uint8_t *>(c->ws + c->off_qflag);
         P.qw_idx = reinterpret_cast<const int *>(c->ws + c->off_qwidx);
@@ -1207,6 +1227,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
         P.qdisp = c->q9_moving ? reinterpret_cast<double2 *>(c->ws + c->off_qdisp) : nullptr;
         P.dgr = c->q9_moving ? reinterpret_cast<const float2 *>(c->ws + c->off_dgr) : nullptr;
+        P.eflag = c->q9_moving ? reinterpret_cast<const uint8_t *>(c->ws + c->off_eflag) : nullptr;
         P.patch8 = reinterpret_cast<const int *>(c->ws + c->off_patch8);
         {
             const std::pair<size_t, std::pair<const void *, size_t>> up[] = {
@@ -1218,7 +1239,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                 {c->off_qweB, {c->qw_eB.data(), c->qw_eB.size() * 4}},
                 {c->off_qwxyB, {c->qw_xyB.data(), c->qw_xyB.size() * sizeof(float2)}},
                 {c->off_patch8, {c->patch8.data(), c->patch8.size() * 4}},
-                {c->off_dgr, {c->q9_dgr.data(), c->q9_dgr.size() * sizeof(float2)}}};
+                {c->off_dgr, {c->q9_dgr.data(), c->q9_dgr.size() * sizeof(float2)}},
+                {c->off_eflag, {c->q9_eflag.data(), c->q9_eflag.size()}}};
             for (const auto &u : up)
                 if (u.second.second)
                     HIP_TRY(c, hipMemcpyAsync(c->ws + u.first, u.second.first, u.second.second,

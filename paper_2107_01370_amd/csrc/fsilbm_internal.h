@@ -28,6 +28,9 @@ constexpr uint8_t Q9_WALL = 1, Q9_FAR = 2;              // boundary nodes
 constexpr uint8_t Q9_BOUNDARY = Q9_WALL | Q9_FAR;
 constexpr uint8_t Q9_MOVES = 4;                         // the body's blending moves the node
 constexpr uint8_t Q9_PATCH_MOVES = 8;                   // a node of its elements moves
+// element flags of a moving body on a Q9 mesh
+constexpr uint8_t Q9E_MOVES = 1;                        // a node of the element moves
+constexpr uint8_t Q9E_RIGID = 2;                        // every node in the rigid zone
 
 enum Dof { DOF_PRESCRIBED = 0, DOF_HEAVE = 1, DOF_PITCH_PLUNGE = 2, DOF_FIXED = 3 };
 
@@ -136,6 +139,8 @@ struct Inst {
     uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
     // unstructured meshes round a fixed body: wall and far-field nodes
     int n_qw, n_qf;
+    int q9_rotates;           // moving body whose rigid map may turn (else a translation)
+    const uint8_t *eflag;     // [n_elems] Q9E_MOVES, Q9E_RIGID (moving body), else null
     const uint8_t *qflag;     // [n_nodes] Q9_WALL, Q9_FAR (else interior), Q9_MOVES, Q9_PATCH_MOVES
     const int *qw_nodes;      // [n_qw] wall polygon, clockwise
     const int *qw_idx;        // [n_nodes] position in qw_nodes, -1 elsewhere

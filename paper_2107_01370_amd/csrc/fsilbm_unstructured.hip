@@ -81,9 +81,12 @@ __global__ void __launch_bounds__(U_THREADS) k_u_egrad(const Inst *__restrict__ 
             val[s] = v[P.elems[9 * e + s]];
             rel[s] = P.erel[9 * e + s];
         }
-        if (disp) {
-            // the deformed element: offsets from the centre node plus the
-            // displacement differences (formed in FP64, rounded once)
+        // the deformed element: offsets from the centre node plus the
+        // displacement differences (formed in FP64, rounded once); they are
+        // zero where no node moves, and where a translation moves all nodes
+        // of a rigid-zone element alike
+        const uint8_t ef = disp ? P.eflag[e] : 0;
+        if ((ef & Q9E_MOVES) && !((ef & Q9E_RIGID) && !P.q9_rotates)) {
             const double2 dc = disp[P.elems[9 * e + 8]];
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
