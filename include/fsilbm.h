@@ -313,7 +313,10 @@ fsi_status fsi_get_coupling_residual(fsi_ctx *ctx, int body, double *residual);
  * the two wall kernels and of the body kernel, at the current step (every
  * launch recomputes the same values, so the state is unchanged).  out_ms[4]
  * receives the mean milliseconds per launch, in that order (0 for kernels the
- * topology does not use).  Synchronises. */
+ * topology does not use).  On a Q9 mesh the first entry covers the element
+ * derivatives, nodal means and collision-interpolation of a step (without
+ * the mesh motion and relocation of a moving body, which are left alone);
+ * the moments of the next step are formed again afterwards.  Synchronises. */
 fsi_status fsi_time_kernels(fsi_ctx *ctx, int reps, double out_ms[4]);
 
 /* ---------------------------------------------------------------------------
