@@ -1,7 +1,7 @@
 """ALE semi-Lagrangian streaming in float64 (paper Sec. II.A and II.B).
 Test infrastructure only.
 
-For every node and every moving velocity c_i:
+For every node and every velocity c_i, the rest velocity c_0 = 0 included:
 
 1. transformed velocity  c^_i = g^{-1} (c_i - V_G), with g = dx/dX the
    Jacobian of the ALE map.  Reading of the printed "g^{-T} c_i - V_G": by the
@@ -16,6 +16,14 @@ For every node and every moving velocity c_i:
 4. the population at the node is the second-order (9-node) Lagrange
    interpolant of the post-collision populations at the departure point
    (Sec. II.B, Eq. for f_i(X, t)).
+
+The propagation holds for all nine populations.  The rest populations f_0,
+g_0 do not move in physical space, but on a moving mesh their transformed
+velocity c^_0 = -g^{-1} V_G is not zero, so they are interpolated at
+X + dt g^{-1} V_G like the others (and are missing at a wall node whose point
+lies in the body).  Where the mesh does not move (V_G = 0) the departure
+point is the node itself, whose offsets are exactly zero, and the
+interpolation returns the node's own value.
 
 Reading for the structured mesh: the 9-node element is the 3 x 3 block of
 nodes centred on the arriving node (shifted inward by one row on a wall or
@@ -114,6 +122,9 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
     """
     Pdx = -dt * chx                      # X_dp - X, relative to the node
     Pdy = -dt * chy
+    # a departure point on the node itself (a rest population where the mesh
+    # does not move) is a corner of every cell round the node: offsets 0
+    at_node = (Pdx == 0.0) & (Pdy == 0.0)
     a = np.full(X.shape, np.nan)
     b = np.full(X.shape, np.nan)
     found = np.zeros(X.shape, dtype=bool)
@@ -142,6 +153,10 @@ def departure_offsets(grid, X, Y, chx, chy, dt, wall_row=False):
             b = np.where(new, t, b)
             missing |= new
     missing &= ~found
+    a = np.where(at_node, 0.0, a)
+    b = np.where(at_node, 0.0, b)
+    found |= at_node
+    missing &= ~at_node
     bad = ~found & ~missing
     if np.any(bad):
         k = int(np.flatnonzero(bad.ravel())[0])
@@ -215,10 +230,6 @@ def stream(grid, X, Y, x1, y1, VGx, VGy, dt, fpost, gpost):
     active = ~boundary_nodes(grid)
     wall = bool(np.any(grid.wall_col))
     for i in range(Q):
-        if i == 0:
-            f_new[0] = fpost[0]
-            g_new[0] = gpost[0]
-            continue
         chx, chy = chat[i]
         # far-field nodes get a zero offset (never used) so they cannot raise
         chx = np.where(active, chx, 0.0)

@@ -308,8 +308,11 @@ class UnstructuredWallSolver(UnstructuredSolver):
       X - dt g^{-1}(c_i - V_G) in the undeformed frame (g = dx/dX at the new
       level by the nodal finite-element derivative on the undeformed mesh,
       V_G = (x^{n+1} - x^n)/dt), located among the node's undeformed
-      elements every step; the correction's derivatives are taken on the
-      mesh of level n.
+      elements every step, for the rest populations (c_0 = 0) too: their
+      point X + dt g^{-1} V_G is the node itself only where the mesh does not
+      move (there they keep their value); a wall node's rest population whose
+      point lies in the body is missing like any other; the correction's
+      derivatives are taken on the mesh of level n.
     """
 
     def __init__(self, mesh, fluid, body, rho=None, ux=None, uy=None, T=None, correction=True):
@@ -375,8 +378,11 @@ class UnstructuredWallSolver(UnstructuredSolver):
 
     def missing(self, i):
         """Mask of the nodes whose population i is missing (last step's
-        departure points on a moving mesh)."""
-        return self.dep[i][0] < 0
+        departure points on a moving mesh; a rest population is never missing
+        on a fixed mesh)."""
+        if self.dep[i] is None:
+            return np.zeros(self.grid.N, dtype=bool)
+        return self.dep[i][0] == -1
 
     def wall_force(self, x=None, y=None, state=None, f=None, gp=None):
         """(F_x, F_y, M_EA) on the body from the populations (f, gp) (default:
@@ -471,21 +477,31 @@ class UnstructuredWallSolver(UnstructuredSolver):
         dt = fl.dt
         x1, y1 = self.positions(new_state)
         VGx, VGy = (x1 - x0) / dt, (y1 - y0) / dt
+        f_new = np.full_like(fpost, np.nan)
+        g_new = np.full_like(gpost, np.nan)
+        # rest populations: their own value where the mesh does not move
+        still = (VGx == 0.0) & (VGy == 0.0)
+        f_new[0] = np.where(still, fpost[0], np.nan)
+        g_new[0] = np.where(still, gpost[0], np.nan)
         if self.moving:
-            # departure points in the undeformed frame: X - dt g^{-1}(c - V_G)
+            # departure points in the undeformed frame: X - dt g^{-1}(c - V_G),
+            # for the rest populations (c_0 = 0) at the nodes that move
             gxx, gxy = g.grad(x1)
             gyx, gyy = g.grad(y1)
             det = gxx * gyy - gxy * gyx
-            for i in range(1, L.Q):
+            for i in range(L.Q):
                 ax, ay = L.CX[i] - VGx, L.CY[i] - VGy
                 chx = (gyy * ax - gxy * ay) / det
                 chy = (-gyx * ax + gxx * ay) / det
-                self.dep[i] = g.locate(-dt * chx, -dt * chy, allow_missing=self.bnd)
-        f_new = np.full_like(fpost, np.nan)
-        g_new = np.full_like(gpost, np.nan)
-        f_new[0] = fpost[0]
-        g_new[0] = gpost[0]
-        for i in range(1, L.Q):
+                if i == 0:
+                    e, xi, eta = g.locate(-dt * chx, -dt * chy, allow_missing=self.bnd)
+                    e = np.where(still, -2, e)          # -2: kept, not missing
+                    self.dep[0] = (e, xi, eta)
+                else:
+                    self.dep[i] = g.locate(-dt * chx, -dt * chy, allow_missing=self.bnd)
+        for i in range(L.Q):
+            if self.dep[i] is None:
+                continue
             e, xi, eta = self.dep[i]
             ok = e >= 0
             Nw = shape(xi[ok], eta[ok])
@@ -526,7 +542,7 @@ class UnstructuredWallSolver(UnstructuredSolver):
             gx, gy = g.grad(F, W1)
             grads.append((gx[self.wall], gy[self.wall]))
         fw, gw = grad_populations(rho_t, ux_t, uy_t, T_t, E_t, *grads, fl.gamma, fl.mu, fl.Pr, dt)
-        for i in range(1, L.Q):
+        for i in range(L.Q):
             m = self.missing(i)[self.wall]
             f_new[i, self.wall[m]] = fw[i, m]
             g_new[i, self.wall[m]] = gw[i, m]

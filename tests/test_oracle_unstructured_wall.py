@@ -125,8 +125,11 @@ def test_moving_body_departures_in_the_rigid_zone():
     """A heaving body on the blended unstructured mesh: in the rigid zone
     (r = 0) the mesh translates with the body, g = dx/dX = I and the
     departure point in the undeformed frame is X - dt (c_i - V_G) with
-    V_G = (h^{n+1} - h^n) / dt along y; the located element and local
-    coordinates map back to that point."""
+    V_G = (h^{n+1} - h^n) / dt along y, for the rest populations (c_0 = 0)
+    too; the located element and local coordinates map back to that point.
+    A wall node's rest population is missing exactly where the wall moves
+    towards the fluid side of the node (its point X + dt V_G lies in the
+    body)."""
     from synth.unstructured import q9_heave_case
     m, fl, b, (r, u, v, T) = q9_heave_case(16, 20.0, 4.0)
     o = UnstructuredWallSolver(m, fl, b, r, u, v, T)
@@ -142,7 +145,7 @@ def test_moving_body_departures_in_the_rigid_zone():
     rigid = np.all(np.where(g.pm, rel[g.pe], True), axis=1)
     ex, ey = element_coords(m)
     checked = 0
-    for i in range(1, L.Q):
+    for i in range(L.Q):
         e, xi, eta = o.dep[i]
         ok = rigid & (e >= 0)
         Nw = shape(xi[ok], eta[ok])
@@ -152,6 +155,11 @@ def test_moving_body_departures_in_the_rigid_zone():
         assert np.max(np.abs(py - (m.Y[ok] - fl.dt * (L.CY[i] - vg)))) < 1e-10
         checked += ok.sum()
     assert checked > 500
+    # rest populations at the wall: missing where n . V_G < 0 (n into the fluid)
+    nvg = o.nds_y / np.hypot(o.nds_x, o.nds_y) * vg
+    miss0 = o.missing(0)[o.wall]
+    assert np.all(miss0[nvg < -0.1 * abs(vg)]) and not np.any(miss0[nvg > 0.0])
+    assert miss0.sum() > 0.3 * miss0.size
 
 
 def test_heaving_body_flow_is_mirror_symmetric():
