@@ -12,9 +12,11 @@
  *      V_G = (x^{n+1} - x^n) / dt;
  *   4. collision of f and g with the momentum correction phi and the energy
  *      correction Psi (Sec. II.C, kinetic equations);
- *   5. ALE semi-Lagrangian streaming: departure points X - dt c^ with
- *      c^ = (dx/dX)^{-1}(c - V_G), bilinear inverse map, 9-node quadratic
- *      Lagrange interpolation (Sec. II.A-B);
+ *   5. ALE semi-Lagrangian streaming of all nine populations: departure
+ *      points X - dt c^ with c^ = (dx/dX)^{-1}(c - V_G), bilinear inverse
+ *      map, 9-node quadratic Lagrange interpolation (Sec. II.A-B); the rest
+ *      populations (c = 0) move where the mesh moves (c^_0 = -(dx/dX)^{-1} V_G)
+ *      and keep their value where it does not;
  *   6. Grad wall populations and far-field equilibria (Sec. III.A).
  *
  * Conventions
@@ -131,7 +133,8 @@ typedef struct {
  *              needs a rigid zone that holds every element at the wall
  *              (FSI_E_ARG otherwise); nodes move by the blending of Sec. II.D
  *              and each step locates the departure points
- *              X - dt g^{-1}(c - V_G) anew among the node's undeformed
+ *              X - dt g^{-1}(c - V_G) (the rest direction c = 0 included,
+ *              where the node moves) anew among the node's undeformed
  *              elements (g = dx/dX, V_G the node's mesh velocity), trying the
  *              previous step's element first; an interior point outside its
  *              elements is reported as FSI_E_CFL at the next synchronising

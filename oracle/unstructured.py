@@ -31,6 +31,14 @@ from . import lattice as L
 LOCAL = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1],
                   [0, -1], [1, 0], [0, 1], [-1, 0], [0, 0]], dtype=np.float64)
 INSIDE_TOL = 1e-12
+# Reading (as on the structured wall line; the paper does not say how a point
+# on the boundary of the mesh is classified): a boundary node's departure point
+# that lies in none of its elements but less than EDGE_TOL (in local
+# coordinates) outside one of them counts as in it, so it is interpolated, not
+# missing.  This makes the decision independent of rounding for points that lie
+# on the boundary in exact arithmetic, or nearly so: the rest populations of a
+# wall node whose mesh velocity is tangential or very small.
+EDGE_TOL = 1e-4
 
 
 def lagrange(p, a):
@@ -133,7 +141,8 @@ class UGrid:
         (dx[n], dy[n]) from the node, and the local coordinates there.
         Returns (element, xi, eta).  A point in none of the node's elements
         raises ValueError, unless allow_missing[n] is set (a boundary node,
-        whose point then lies outside the mesh): element -1 there."""
+        whose point then lies outside the mesh: element -1 there, unless it
+        lies within EDGE_TOL of one of its elements, which then holds it)."""
         nodes = np.arange(self.N) if nodes is None else np.asarray(nodes, dtype=np.int64)
         M = nodes.size
         found = np.zeros(M, dtype=bool)
@@ -143,23 +152,26 @@ class UGrid:
         dx = np.broadcast_to(dx, (M,))
         dy = np.broadcast_to(dy, (M,))
         pm, pe, pa = self.pm[nodes], self.pe[nodes], self.pa[nodes]
-        for k in range(self.P):
-            # the k-th element of the patches of the nodes not yet placed
-            todo = np.flatnonzero(pm[:, k] & ~found)
-            if todo.size == 0:
-                continue
-            e = pe[todo, k]
-            a = pa[todo, k]
-            # coordinates relative to the node (well conditioned)
-            cx = self.ex[e, :4] - self.ex[e, a][:, None]
-            cy = self.ey[e, :4] - self.ey[e, a][:, None]
-            xi, eta = bilinear_local(cx, cy, dx[todo], dy[todo])
-            inside = (np.abs(xi) <= 1 + INSIDE_TOL) & (np.abs(eta) <= 1 + INSIDE_TOL)
-            hit = todo[inside]
-            elem[hit] = e[inside]
-            XI[hit] = xi[inside]
-            ETA[hit] = eta[inside]
-            found[hit] = True
+        edge = np.zeros(M, dtype=bool) if allow_missing is None else \
+            np.asarray(allow_missing)[nodes]
+        for tol, among in ((INSIDE_TOL, np.ones(M, dtype=bool)), (EDGE_TOL, edge)):
+            for k in range(self.P):
+                # the k-th element of the patches of the nodes not yet placed
+                todo = np.flatnonzero(pm[:, k] & ~found & among)
+                if todo.size == 0:
+                    continue
+                e = pe[todo, k]
+                a = pa[todo, k]
+                # coordinates relative to the node (well conditioned)
+                cx = self.ex[e, :4] - self.ex[e, a][:, None]
+                cy = self.ey[e, :4] - self.ey[e, a][:, None]
+                xi, eta = bilinear_local(cx, cy, dx[todo], dy[todo])
+                inside = (np.abs(xi) <= 1 + tol) & (np.abs(eta) <= 1 + tol)
+                hit = todo[inside]
+                elem[hit] = e[inside]
+                XI[hit] = xi[inside]
+                ETA[hit] = eta[inside]
+                found[hit] = True
         ok = found if allow_missing is None else (found | np.asarray(allow_missing)[nodes])
         if not np.all(ok):
             raise ValueError(f"departure point outside the patch of node {int(nodes[np.argmin(ok)])}")

@@ -43,6 +43,10 @@ struct fsi_ctx {
     std::vector<int> qw_nodes, qw_idx, qf_nodes, qw_eB;
     std::vector<double4> qw_geo;
     std::vector<float2> qw_xyB;
+    // per wall node: the corners of its elements (patch order) relative to the
+    // node in FP64, for the wall nodes' FP64 departure-point location
+    std::vector<int> qw_coff;       // [n_qw + 1] first patch entry of each wall node
+    std::vector<double2> qw_corner; // [entries][4]
     std::vector<double> ecoord;     // [E][9][2] unwrapped FP64 element node coordinates
     bool q9_moving = false;         // a moving body on a Q9 mesh
     hipStream_t stream = nullptr;
@@ -58,6 +62,7 @@ struct fsi_ctx {
            off_bh_off = 0, off_bh_nodes = 0, off_be_off = 0, off_be_elem = 0, off_be_nodes = 0,
            off_uself = 0, off_dep_le = 0, off_qflag = 0, off_qw = 0, off_qwidx = 0, off_qf = 0,
            off_qwgeo = 0, off_qweB = 0, off_qwxyB = 0, off_qwprev = 0, off_qdisp = 0, off_dgr = 0, off_eflag = 0, off_patch8 = 0,
+           off_qwcoff = 0, off_qwcorner = 0,
            total = 0;
     char *ws = nullptr;
     std::vector<float2> wallB;
@@ -249,6 +254,12 @@ fsi_status topology(fsi_ctx *c) {
 // list and rest populations do not fit 64 KiB of LDS, or if FSILBM_UNSTRUCTURED_GATHER is
 // set to "device" (k_u_collide and k_u_stream then go through device memory;
 // both paths agree to FP32 rounding).
+// planes of the departure tables: the eight moving directions, and with a
+// moving body the rest direction (its point X + dt g^{-1} V_G moves with the mesh)
+int q9_dep_planes(const fsi_ctx *c) {
+    return !c->bodies.empty() && c->bodies[0].dof != FSI_DOF_FIXED ? 9 : 8;
+}
+
 void build_q9_blocks(fsi_ctx *c) {
     c->bh_off.clear(); c->bh_nodes.clear(); c->be_off.clear(); c->be_elem.clear();
     c->be_nodes.clear(); c->uself.clear();
@@ -287,11 +298,13 @@ void build_q9_blocks(fsi_ctx *c) {
         hmax = std::max(hmax, (int)nodes.size());
         lemax = std::max(lemax, (int)els.size());
     }
-    // the widest element stride that keeps four blocks per CU, else the narrowest
+    // the widest element stride that keeps four blocks per CU, else the
+    // narrowest (a moving body stages the rest pair as a ninth plane)
+    const int planes = q9_dep_planes(c);
     int eu16 = 10;
     for (int w : {16, 12, 10})
-        if (fsi::u_block_lds_bytes(hmax, lemax, w) <= fsi::U_LDS_PER_BLOCK) { eu16 = w; break; }
-    if (fsi::u_block_lds_bytes(hmax, lemax, eu16) > 65536) return;
+        if (fsi::u_block_lds_bytes(hmax, lemax, w, planes) <= fsi::U_LDS_PER_BLOCK) { eu16 = w; break; }
+    if (fsi::u_block_lds_bytes(hmax, lemax, eu16, planes) > 65536) return;
     if (eu16 != 16) {
         std::vector<uint16_t> packed(be_nodes.size() / 16 * eu16, 0);
         for (size_t e = 0; e < be_nodes.size() / 16; ++e)
@@ -347,6 +360,8 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
     c->qw_geo.clear();
     c->qw_eB.clear();
     c->qw_xyB.clear();
+    c->qw_coff.assign(1, 0);
+    c->qw_corner.clear();
     c->n_seg = 0;
     if (nw == 0) return FSI_OK;
     const fsi_body_desc &b = c->bodies[0];
@@ -503,6 +518,13 @@ fsi_status q9_wall_geometry(fsi_ctx *c) {
                                        " lies outside its elements (is the wall clockwise?)");
         c->qw_eB.push_back(eB);
         c->qw_xyB.push_back(make_float2((float)xi, (float)eta));
+        for (int q = c->patch_off[v]; q < c->patch_off[v + 1]; ++q) {
+            const int e = c->patch_ent[q] >> 4, a = c->patch_ent[q] & 15;
+            const double *xy = c->ecoord.data() + 18 * (size_t)e;
+            for (int m = 0; m < 4; ++m)
+                c->qw_corner.push_back(make_double2(xy[2 * m] - xy[2 * a], xy[2 * m + 1] - xy[2 * a + 1]));
+        }
+        c->qw_coff.push_back((int)(c->qw_corner.size() / 4));
     }
     c->n_seg = 1;
     c->seg_i0[0] = 0;
@@ -908,7 +930,7 @@ void layout(fsi_ctx *c) {
     c->off_B = take(c->ni * 8);
     c->off_inflow = take(c->ff.size());
     c->off_ff = take(c->ff.size() * sizeof(int2));
-    c->off_cut = take((size_t)16 * c->inst.cut_n * sizeof(float));
+    c->off_cut = take((size_t)18 * c->inst.cut_n * sizeof(float));
     c->off_force = take(c->ni * 32);
     c->off_slots = take(3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot));
     c->off_hist = take((size_t)fsi::MAX_BODIES * fsi::HIST_CAP * 6 * 8);
@@ -930,9 +952,10 @@ void layout(fsi_ctx *c) {
         c->off_us = take(N * sizeof(float));
         c->off_ud = take(N * sizeof(float2));
         c->off_ueg = take(9 * (size_t)c->n_elems * sizeof(float2));
-        c->off_upost = take(16 * N * sizeof(float));
-        c->off_dep_e = take(8 * N * 4);
-        c->off_dep_xy = take(8 * N * sizeof(float2));
+        const size_t planes = (size_t)q9_dep_planes(c);
+        c->off_upost = take(2 * planes * N * sizeof(float));
+        c->off_dep_e = take(planes * N * 4);
+        c->off_dep_xy = take(planes * N * sizeof(float2));
         c->off_qflag = take(N);
         c->off_qwidx = take(N * 4);
         c->off_qw = take(c->qw_nodes.size() * 4);
@@ -940,6 +963,8 @@ void layout(fsi_ctx *c) {
         c->off_qwgeo = take(c->qw_geo.size() * sizeof(double4));
         c->off_qweB = take(c->qw_eB.size() * 4);
         c->off_qwxyB = take(c->qw_xyB.size() * sizeof(float2));
+        c->off_qwcoff = take(c->qw_coff.size() * 4);
+        c->off_qwcorner = take(c->qw_corner.size() * sizeof(double2));
         c->off_qwprev = take(c->qw_nodes.size() * sizeof(float2));
         if (c->q9_moving) {
             c->off_qdisp = take(2 * N * sizeof(double2));
@@ -954,7 +979,7 @@ void layout(fsi_ctx *c) {
             c->off_be_elem = take(c->be_elem.size() * 4);
             c->off_be_nodes = take(c->be_nodes.size() * 2);
             c->off_uself = take(c->uself.size() * 2);
-            c->off_dep_le = take(8 * N * 2);
+            c->off_dep_le = take(planes * N * 2);
         }
     }
     c->total = o;
@@ -1224,6 +1249,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
         P.qw_geo = reinterpret_cast<const double4 *>(c->ws + c->off_qwgeo);
         P.qw_eB = reinterpret_cast<const int *>(c->ws + c->off_qweB);
         P.qw_xyB = reinterpret_cast<const float2 *>(c->ws + c->off_qwxyB);
+        P.qw_coff = reinterpret_cast<const int *>(c->ws + c->off_qwcoff);
+        P.qw_corner = reinterpret_cast<const double2 *>(c->ws + c->off_qwcorner);
         P.qw_prev = reinterpret_cast<float2 *>(c->ws + c->off_qwprev);
         P.qdisp = c->q9_moving ? reinterpret_cast<double2 *>(c->ws + c->off_qdisp) : nullptr;
         P.dgr = c->q9_moving ? reinterpret_cast<const float2 *>(c->ws + c->off_dgr) : nullptr;
@@ -1238,6 +1265,8 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
                 {c->off_qwgeo, {c->qw_geo.data(), c->qw_geo.size() * sizeof(double4)}},
                 {c->off_qweB, {c->qw_eB.data(), c->qw_eB.size() * 4}},
                 {c->off_qwxyB, {c->qw_xyB.data(), c->qw_xyB.size() * sizeof(float2)}},
+                {c->off_qwcoff, {c->qw_coff.data(), c->qw_coff.size() * 4}},
+                {c->off_qwcorner, {c->qw_corner.data(), c->qw_corner.size() * sizeof(double2)}},
                 {c->off_patch8, {c->patch8.data(), c->patch8.size() * 4}},
                 {c->off_dgr, {c->q9_dgr.data(), c->q9_dgr.size() * sizeof(float2)}},
                 {c->off_eflag, {c->q9_eflag.data(), c->q9_eflag.size()}}};
@@ -1289,7 +1318,7 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_err, 0, 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_resid, 0, fsi::MAX_BODIES * sizeof(double), c->stream));
     if (!c->wk0.empty()) {
-        HIP_TRY(c, hipMemsetAsync(c->ws + c->off_cut, 0, (size_t)16 * c->inst.cut_n * 4, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->ws + c->off_cut, 0, (size_t)18 * c->inst.cut_n * 4, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk0, c->wk0.data(), c->wk0.size() * sizeof(int2),
                                   hipMemcpyHostToDevice, c->stream));
     }
@@ -1515,7 +1544,7 @@ fsi_status fsi_state_bytes(const fsi_ctx *c, size_t *bytes) {
     const size_t bpp = c->fluid.storage == FSI_STORE_FP16_SHIFTED ? 2 : 4;
     // a moving body on a Q9 mesh: the departure table (element, local
     // coordinates), from which each step's relocation starts
-    const size_t dep = c->q9_moving ? 8 * N * (sizeof(int) + sizeof(float2)) : 0;
+    const size_t dep = c->q9_moving ? 9 * N * (sizeof(int) + sizeof(float2)) : 0;
     *bytes = 8 * 6 + 3 * fsi::MAX_BODIES * sizeof(fsi::BodySlot) + fsi::NPOP * N * bpp + dep;
     return FSI_OK;
 }
@@ -1540,9 +1569,9 @@ fsi_status fsi_save(fsi_ctx *c, void *host_buf, size_t bytes) {
     HIP_TRY(c, hipMemcpy(p, c->ws + c->off_pop[c->host_step & 1], fsi::NPOP * N * bpp, hipMemcpyDeviceToHost));
     p += fsi::NPOP * N * bpp;
     if (c->q9_moving) {
-        HIP_TRY(c, hipMemcpy(p, c->ws + c->off_dep_e, 8 * N * sizeof(int), hipMemcpyDeviceToHost));
-        p += 8 * N * sizeof(int);
-        HIP_TRY(c, hipMemcpy(p, c->ws + c->off_dep_xy, 8 * N * sizeof(float2), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(p, c->ws + c->off_dep_e, 9 * N * sizeof(int), hipMemcpyDeviceToHost));
+        p += 9 * N * sizeof(int);
+        HIP_TRY(c, hipMemcpy(p, c->ws + c->off_dep_xy, 9 * N * sizeof(float2), hipMemcpyDeviceToHost));
     }
     return FSI_OK;
 }
@@ -1570,13 +1599,16 @@ fsi_status fsi_load(fsi_ctx *c, const void *host_buf, size_t bytes) {
         // the departure table the run continues from: elements and local
         // coordinates (element ids checked on the host), then the block-list
         // positions formed from them
-        std::vector<int> de(8 * N);
-        memcpy(de.data(), p, 8 * N * sizeof(int));
-        for (int e : de)
-            if (e < -1 || e >= c->n_elems) return fail(c, FSI_E_ARG, "checkpoint departure table out of range");
-        HIP_TRY(c, hipMemcpy(c->ws + c->off_dep_e, de.data(), 8 * N * sizeof(int), hipMemcpyHostToDevice));
-        p += 8 * N * sizeof(int);
-        HIP_TRY(c, hipMemcpy(c->ws + c->off_dep_xy, p, 8 * N * sizeof(float2), hipMemcpyHostToDevice));
+        std::vector<int> de(9 * N);
+        memcpy(de.data(), p, 9 * N * sizeof(int));
+        for (size_t q = 0; q < de.size(); ++q) {
+            // -1 missing; -2 (the rest plane only) the node itself
+            const int lo = q >= 8 * N ? -2 : -1;
+            if (de[q] < lo || de[q] >= c->n_elems) return fail(c, FSI_E_ARG, "checkpoint departure table out of range");
+        }
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_dep_e, de.data(), 9 * N * sizeof(int), hipMemcpyHostToDevice));
+        p += 9 * N * sizeof(int);
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_dep_xy, p, 9 * N * sizeof(float2), hipMemcpyHostToDevice));
         if (!c->bh_off.empty())
             HIP_TRY(c, fsi::launch_unstructured_dep_le(d_inst(c), (long long)N, c->stream));
     }

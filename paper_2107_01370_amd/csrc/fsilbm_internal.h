@@ -104,7 +104,7 @@ struct Inst {
     const float2 *wall_B;     // [ni] index offsets of point B from the wall node
     const int2 *ff;           // [n_ff] far-field node index, interior node an outlet copies
     const uint8_t *inflow;    // [n_ff] far-field node is an inlet
-    float *cutbuf;            // cut topologies: [16][cut_n] post-collision moving populations of row 1
+    float *cutbuf;            // cut topologies: [18][cut_n] post-collision populations of row 1 (f_1..8, g_1..8, f_0, g_0)
     double4 *wall_force;      // [ni] per-node (Fx, Fy, Mz, 0)
     const double *wall_dist;  // [nbody][nj][ni] distance to each body's wall (blend_mode 1), else null
     BodySlot *slots;          // [3][MAX_BODIES] body states at levels n % 3
@@ -124,9 +124,11 @@ struct Inst {
     float *us;                // [n_nodes] mu / p
     float2 *ud;               // [n_nodes] D_a = (mu / p) d_a delta Q_a
     float2 *ueg;              // [n_elems][9] element derivatives at the element's nodes
-    void *upost;              // [n_nodes][8][2] post-collision moving populations (f_k, g_k), FP32
-    int *dep_e;               // [8][n_nodes] element holding each departure point
-    float2 *dep_xy;           // [8][n_nodes] its local coordinates there
+    void *upost;              // [n_nodes][8][2] post-collision moving populations (f_k, g_k), FP32,
+                              // then (moving body) [n_nodes][2] the rest pair (f_0, g_0)
+    int *dep_e;               // [8 or 9][n_nodes] element holding each departure point (plane 8:
+                              // the rest direction of a moving body; -1 missing, -2 the node itself)
+    float2 *dep_xy;           // [8 or 9][n_nodes] its local coordinates there
     // node blocks of U_BLOCK consecutive nodes for the LDS-staged interpolation
     // (null bh_off: every block gathers from device memory instead)
     int u_nblk, u_hmax, u_lemax, u_eu16;
@@ -136,7 +138,7 @@ struct Inst {
     const int *be_elem;       // elements holding a node of the block, ascending
     const uint16_t *be_nodes; // [.][u_eu16] their nine nodes as halo positions (padded)
     const uint16_t *uself;    // [n_nodes] each node's own position in its block's halo
-    uint16_t *dep_le;         // [8][n_nodes] departure element as a position in the block's list
+    uint16_t *dep_le;         // [8 or 9][n_nodes] departure element as a position in the block's list
     // unstructured meshes round a fixed body: wall and far-field nodes
     int n_qw, n_qf;
     int q9_rotates;           // moving body whose rigid map may turn (else a translation)
@@ -149,6 +151,8 @@ struct Inst {
     const int *qw_eB;         // [n_qw] element holding the point B
     const float2 *qw_xyB;     // [n_qw] local coordinates of B there
     float2 *qw_prev;          // [n_qw] (rho, T) of the completed wall node, previous level
+    const int *qw_coff;       // [n_qw + 1] first patch entry of each wall node in qw_corner
+    const double2 *qw_corner; // [.][4] corners of each wall node's elements relative to the node (FP64)
     // a moving body on a Q9 mesh (null: fixed)
     double2 *qdisp;           // [2][n_nodes] blended displacement at levels n, n+1
     const float2 *dgr;        // [n_nodes][3] nodal derivatives of r, r X, r Y (moving body)
@@ -163,13 +167,14 @@ constexpr int U_BLOCK = 256;
 // widest whose block still lets four blocks share a CU's 160 KiB of LDS
 constexpr size_t U_LDS_PER_BLOCK = 40960;
 
-// LDS of one node block: 8 planes of (f_k, g_k) over the halo, the element
-// lists as halo positions, the block's rest populations (8-byte aligned)
+// LDS of one node block: 8 planes of (f_k, g_k) over the halo (9 with a
+// moving body: the rest pair too), the element lists as halo positions, the
+// block's rest populations (8-byte aligned)
 __host__ __device__ inline size_t u_block_elem_bytes(int lemax, int eu16) {
     return (((size_t)lemax * eu16 * 2 + 7) / 8) * 8;
 }
-__host__ __device__ inline size_t u_block_lds_bytes(int hmax, int lemax, int eu16) {
-    return (size_t)hmax * 8 * 8 + u_block_elem_bytes(lemax, eu16) + (size_t)U_BLOCK * 8;
+__host__ __device__ inline size_t u_block_lds_bytes(int hmax, int lemax, int eu16, int planes) {
+    return (size_t)hmax * planes * 8 + u_block_elem_bytes(lemax, eu16) + (size_t)U_BLOCK * 8;
 }
 
 }  // namespace fsi

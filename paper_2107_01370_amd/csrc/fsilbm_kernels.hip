@@ -46,6 +46,7 @@ namespace fsi {
 // integer grids stay exact.
 // ---------------------------------------------------------------------------
 constexpr int NMOV = 16;     // moving populations kept in LDS (f_1..8, g_1..8)
+constexpr int NFG = NMOV + 2; // and the rest pair (f_0, g_0) of a tile whose mesh moves
 // waves per SIMD the launch bounds ask for (16 waves per CU: two 512-thread or
 // four 256-thread workgroups), which caps the VGPRs at 128
 constexpr int kWavesPerSimd = 4;
@@ -74,7 +75,7 @@ struct K1Smem {
         struct {
             float Qx[G::R3N], Qy[G::R3N], S[G::R3N];
         } q;
-        float FG[NMOV][G::R1N];
+        float FG[NFG][G::R1N];   // f_1..8, g_1..8, then f_0, g_0
     } u;
 };
 
@@ -283,6 +284,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
 
     // populations of this thread's collision nodes, kept from phase 1
     float fk[R1_ROUNDS][9], gk[R1_ROUNDS][9];
+    int mv = 0;              // a node of this thread's phase-1 items moves
 
     // ---- phase 1: tile+3 --------------------------------------------------
 #pragma unroll
@@ -344,6 +346,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             }
         }
         float2 dn = make_float2((float)(-Drx), (float)(-Dry)), dd = make_float2(0.0f, 0.0f);
+        mv |= moved ? 1 : 0;
         if (moved) {
             dn = make_float2((float)(a0x - Drx), (float)(a0y - Dry));
             dd = make_float2((float)a1x, (float)a1y);
@@ -383,7 +386,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         sm.u.q.Qy[e] = jy * (one3T - uy * uy);
         sm.u.q.S[e] = P.mu * rcpf(rho * T);       // (1/omega - 1/2) dt = mu / p
     }
-    __syncthreads();
+    // Rest populations (c_0 = 0) have the transformed velocity -g^{-1} V_G:
+    // on a tile whose mesh moves they are interpolated like the others; on a
+    // tile where no node moves their departure point is the node itself and
+    // they are stored as collided.
+    const bool tile_moves = __syncthreads_or(mv) != 0;
 
     // ---- phase 2: tile+2: D_a = (mu/p) d_{x_a} dQ_a --------------------------
     for (int e = t; e < R2N; e += K1_THREADS) {
@@ -424,6 +431,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 if (slot >= 0) {
 #pragma unroll
                     for (int k = 0; k < NMOV; ++k) sm.u.FG[k][e] = P.cutbuf[k * P.cut_n + slot];
+                    if (tile_moves) {
+                        sm.u.FG[NMOV][e] = P.cutbuf[NMOV * P.cut_n + slot];
+                        sm.u.FG[NMOV + 1][e] = P.cutbuf[(NMOV + 1) * P.cut_n + slot];
+                    }
                 }
             }
             continue;
@@ -456,6 +467,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             sm.u.FG[k - 1][e] = f[k];
             sm.u.FG[7 + k][e] = g[k];
         }
+        if (tile_moves) {
+            sm.u.FG[NMOV][e] = f[0];
+            sm.u.FG[NMOV + 1][e] = g[0];
+        }
         const bool own = u1 >= 1 && u1 <= TILE_X && v1 >= 1 && v1 <= TILE_Y &&
                          i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
         if constexpr (EXPORT) {
@@ -467,9 +482,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                     P.cutbuf[(k - 1) * P.cut_n + slot] = f[k];
                     P.cutbuf[(7 + k) * P.cut_n + slot] = g[k];
                 }
+                P.cutbuf[NMOV * P.cut_n + slot] = f[0];
+                P.cutbuf[(NMOV + 1) * P.cut_n + slot] = g[0];
             }
-        } else if (own) {
-            // rest populations do not move: store them for the tile's own nodes
+        } else if (own && !tile_moves) {
+            // no node of the tile moves: the rest populations stay at their node
             const int off = pop_off<STORE>(jg * ni + wrap(ig, ni));
             pop_st<STORE>(P, dst, 0, off, f[0]);
             pop_st<STORE>(P, dst, Q, off, g[0]);
@@ -538,7 +555,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const int off = pop_off<STORE>(jg * ni + ig);
         uint16_t miss = 0, amb = 0;
 #pragma unroll
-        for (int k = 1; k < 9; ++k) {
+        for (int k = 0; k < 9; ++k) {
+            if (k == 0 && !tile_moves) continue;     // stored in phase 3
             const float cx = (float)CXK(k), cy = (float)CYK(k);
             const float deta = a21 * cx + a22 * cy + B0y;
             const float Px = p11 * cx + p12 * cy + P0x;
@@ -591,7 +609,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             float outv[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const float *F = sm.u.FG[h * 8 + k - 1];
+                const float *F = k == 0 ? sm.u.FG[NMOV + h] : sm.u.FG[h * 8 + k - 1];
                 float row[3];
 #pragma unroll
                 for (int dj = -1; dj <= 1; ++dj) {
@@ -798,7 +816,7 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
         const uint16_t amb = P.wall_amb[ig];
         if (amb) {
             uint16_t miss = P.wall_mask[ig];
-            for (int k = 1; k < 9; ++k)
+            for (int k = 0; k < 9; ++k)
                 if ((amb & (1u << k)) && wall_departure_v(P, ig, k, n) < -1e-4) miss |= (uint16_t)(1u << k);
             P.wall_mask[ig] = miss;
         }

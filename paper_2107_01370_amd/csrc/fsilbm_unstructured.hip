@@ -37,6 +37,15 @@ namespace fsi {
 constexpr int U_THREADS = 256;
 // departure element of a missing population (block positions)
 constexpr uint16_t U_MISSING = 0xffff;
+// departure "element" of a rest population whose node does not move: the
+// point is the node itself and the population keeps its value (element table
+// entry -2; -1 marks a missing population)
+constexpr uint16_t U_SELF = 0xfffe;
+constexpr int DEP_SELF = -2;
+
+// plane of direction k in the departure tables: the moving directions
+// 1..8 in planes 0..7, the rest direction (moving bodies only) in plane 8
+__device__ __forceinline__ int dep_plane(int k) { return k == 0 ? 8 : k - 1; }
 
 // Workgroup slot -> block of consecutive nodes (or elements), so that each of
 // the 8 XCDs takes a contiguous run of blocks (dispatch slot b goes to XCD
@@ -228,9 +237,14 @@ __global__ void __launch_bounds__(U_THREADS) k_u_collide(const Inst *__restrict_
             g[k] = pop_load<STORE>(P, src, Q + k, idx);
         }
         collide(f, g, F.x, F.y, P, err);
-        // rest populations do not move
-        pop_store<STORE>(P, dst, 0, idx, f[0]);
-        pop_store<STORE>(P, dst, Q, idx, g[0]);
+        // rest populations: in place on a fixed mesh; with a moving body after
+        // the moving ones (the interpolation moves them where the node moves)
+        if (P.qdisp) {
+            reinterpret_cast<float2 *>(P.upost)[8 * P.n_nodes + idx] = make_float2(f[0], g[0]);
+        } else {
+            pop_store<STORE>(P, dst, 0, idx, f[0]);
+            pop_store<STORE>(P, dst, Q, idx, g[0]);
+        }
         // the 16 moving ones node by node (f_k and g_k of a node side by side,
         // one 64-byte line per node), FP32: the interpolation gathers them
         float4 *up = reinterpret_cast<float4 *>(P.upost) + 4 * idx;
@@ -301,10 +315,69 @@ __device__ __forceinline__ void u_patch_search(const Inst &P, int b, int e_end, 
     }
 }
 
+// A wall node's departure point, at offset (dx, dy) from the node, located in
+// FP64 among the node's elements with their corner (first-order) maps, from
+// the FP64 corner coordinates relative to the node: the first element (in
+// patch order) that holds it to 1e-12 in local coordinates, else the first
+// that holds it to 1e-4 (a point that close to the mesh's boundary counts as
+// in the mesh, so that points on the boundary in exact arithmetic, such as the
+// rest populations' points of a wall moving along itself, are not decided by
+// rounding); e = -1 if none (the population is missing).  Newton from the
+// element's centre, stopped once an update falls below 1e-13.
+__device__ void q9_wall_locate(const Inst &P, long long idx, double dx, double dy, int &e, float &xi,
+                               float &eta) {
+    const int b = P.patch_off[idx], cnt = P.patch_off[idx + 1] - b;
+    const double2 *cr = P.qw_corner + 4 * (long long)P.qw_coff[P.qw_idx[idx]];
+    int e_near = -1;
+    double u_near = 0.0, v_near = 0.0;
+    e = -1;
+    for (int q = 0; q < cnt; ++q) {
+        const double2 c0 = cr[4 * q], c1 = cr[4 * q + 1], c2 = cr[4 * q + 2], c3 = cr[4 * q + 3];
+        double u = 0.0, v = 0.0;
+        bool settled = false;
+        for (int it = 0; it < 25; ++it) {
+            const double n0 = (1 - u) * (1 - v) * 0.25, n1 = (1 + u) * (1 - v) * 0.25;
+            const double n2 = (1 + u) * (1 + v) * 0.25, n3 = (1 - u) * (1 + v) * 0.25;
+            const double rx = n0 * c0.x + n1 * c1.x + n2 * c2.x + n3 * c3.x - dx;
+            const double ry = n0 * c0.y + n1 * c1.y + n2 * c2.y + n3 * c3.y - dy;
+            const double ja = 0.25 * (-(1 - v) * c0.x + (1 - v) * c1.x + (1 + v) * c2.x - (1 + v) * c3.x);
+            const double jb = 0.25 * (-(1 - u) * c0.x - (1 + u) * c1.x + (1 + u) * c2.x + (1 - u) * c3.x);
+            const double jc = 0.25 * (-(1 - v) * c0.y + (1 - v) * c1.y + (1 + v) * c2.y - (1 + v) * c3.y);
+            const double jd = 0.25 * (-(1 - u) * c0.y - (1 + u) * c1.y + (1 + u) * c2.y + (1 - u) * c3.y);
+            const double det = ja * jd - jb * jc;
+            const double du = (jd * rx - jb * ry) / det, dv = (-jc * rx + ja * ry) / det;
+            u -= du;
+            v -= dv;
+            if (fabs(du) + fabs(dv) < 1e-13) {
+                settled = true;
+                break;
+            }
+        }
+        if (!settled) continue;
+        const double m = fmax(fabs(u), fabs(v));
+        if (m <= 1.0 + 1e-12) {
+            e = P.patch_ent[b + q] >> 4;
+            xi = (float)u;
+            eta = (float)v;
+            return;
+        }
+        if (e_near < 0 && m <= 1.0 + 1e-4) {
+            e_near = P.patch_ent[b + q] >> 4;
+            u_near = u;
+            v_near = v;
+        }
+    }
+    if (e_near >= 0) {
+        e = e_near;
+        xi = (float)u_near;
+        eta = (float)v_near;
+    }
+}
+
 // position of element e (-1: none) in the ascending element list of node
 // idx's block (it holds every element of the node's patch)
 __device__ __forceinline__ uint16_t u_block_pos(const Inst &P, long long idx, int e) {
-    if (e < 0) return U_MISSING;
+    if (e < 0) return e == DEP_SELF ? U_SELF : U_MISSING;
     const long long blk = idx / U_BLOCK;
     int lo = P.be_off[blk], hi = P.be_off[blk + 1];
     const int first = lo;
@@ -322,7 +395,7 @@ __device__ __forceinline__ uint16_t u_block_pos(const Inst &P, long long idx, in
 // keeps the element entries (the point stayed in the same element)
 __device__ __forceinline__ void u_dep_store(const Inst &P, long long idx, int k, int e, float xi, float eta,
                                             bool changed) {
-    const long long at = (long long)(k - 1) * P.n_nodes + idx;
+    const long long at = (long long)dep_plane(k) * P.n_nodes + idx;
     P.dep_xy[at] = make_float2(xi, eta);
     if (!changed) return;
     P.dep_e[at] = e;
@@ -333,9 +406,10 @@ __device__ __forceinline__ void u_dep_store(const Inst &P, long long idx, int k,
 // from the element table (after a checkpoint has restored it)
 __global__ void __launch_bounds__(U_THREADS) k_u_dep_le(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
+    const int planes = P.qdisp ? 9 : 8;
     for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x)
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < planes; ++k) {
             const long long at = (long long)k * P.n_nodes + idx;
             P.dep_le[at] = u_block_pos(P, idx, P.dep_e[at]);
         }
@@ -347,7 +421,9 @@ __global__ void __launch_bounds__(U_THREADS) k_u_dep_le(const Inst *__restrict__
 // (Newton in FP32 offsets from the element's centre node).  ERR_CFL if an
 // interior node's point lies outside every element of its patch; a boundary
 // node's point outside them lies outside the mesh: the population is missing
-// (set by the boundary kernels).
+// (set by the boundary kernels).  With a moving body the rest direction's
+// entry starts as the node itself (the relocation replaces it where the node
+// moves).
 __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
     const float dt = P.dt;
@@ -356,16 +432,21 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
          idx += (long long)gridDim.x * blockDim.x) {
         const int b = P.patch_off[idx], e_end = P.patch_off[idx + 1];
         const bool bnd = P.n_qw + P.n_qf > 0 && (P.qflag[idx] & Q9_BOUNDARY) != 0;
+        const bool wallnode = P.n_qw > 0 && (P.qflag[idx] & Q9_WALL) != 0;
         for (int k = 1; k < 9; ++k) {
             int e = -1;
             float xi = 0.0f, eta = 0.0f;
-            u_patch_search(P, b, e_end, -dt * (float)CXK(k), -dt * (float)CYK(k), e, xi, eta);
+            if (wallnode)
+                q9_wall_locate(P, idx, -P.dt_d * (double)CXK(k), -P.dt_d * (double)CYK(k), e, xi, eta);
+            else
+                u_patch_search(P, b, e_end, -dt * (float)CXK(k), -dt * (float)CYK(k), e, xi, eta);
             if (e < 0 && !bnd) {
                 err |= ERR_CFL;
                 e = P.patch_ent[b] >> 4;
             }
             u_dep_store(P, idx, k, e, xi, eta, true);
         }
+        if (P.qdisp) u_dep_store(P, idx, 0, DEP_SELF, 0.0f, 0.0f, true);
     }
     if (err) atomicOr(P.err, err);
 }
@@ -374,8 +455,43 @@ __global__ void __launch_bounds__(U_THREADS) k_u_locate(const Inst *__restrict__
 // take the rest from memory)
 constexpr int U_PATCH_REG = 8;
 
+// Departure points of a wall node of a moving body, directions k0 .. k0+nd-1,
+// in FP64 (the decision whether a population is missing): g and V_G as in
+// u_relocate_dirs, from the FP64 body state and displacements, then
+// q9_wall_locate.
+__device__ void q9_wall_relocate(const Inst &P, long long idx, int k0, int nd, const BodySlot &s1,
+                                 const Body &body) {
+    const long long N = P.n_nodes;
+    const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
+    const float2 Lr = P.dgr[3 * idx], LrX = P.dgr[3 * idx + 1], LrY = P.dgr[3 * idx + 2];
+    const double A00 = s1.cm1, A01 = -s1.sa, A10 = s1.sa, A11 = s1.cm1;
+    const double b0 = -(s1.cm1 * body.ex - s1.sa * body.ey);
+    const double b1 = s1.h - (s1.sa * body.ex + s1.cm1 * body.ey);
+    const double g00 = 1.0 + A00 - (A00 * LrX.x + A01 * LrY.x) - b0 * Lr.x;
+    const double g01 = A01 - (A00 * LrX.y + A01 * LrY.y) - b0 * Lr.y;
+    const double g10 = A10 - (A10 * LrX.x + A11 * LrY.x) - b1 * Lr.x;
+    const double g11 = 1.0 + A11 - (A10 * LrX.y + A11 * LrY.y) - b1 * Lr.y;
+    const double vgx = (d1.x - d0.x) / P.dt_d, vgy = (d1.y - d0.y) / P.dt_d;
+    const double det = g00 * g11 - g01 * g10;
+    for (int j = 0; j < nd; ++j) {
+        const int k = k0 + j;
+        if (k == 0 && vgx == 0.0 && vgy == 0.0) {
+            u_dep_store(P, idx, 0, DEP_SELF, 0.0f, 0.0f, true);
+            continue;
+        }
+        const double ax = (double)CXK(k) - vgx, ay = (double)CYK(k) - vgy;
+        const double dx = -P.dt_d * (g11 * ax - g01 * ay) / det;
+        const double dy = -P.dt_d * (-g10 * ax + g00 * ay) / det;
+        int e = -1;
+        float xi = 0.0f, eta = 0.0f;
+        q9_wall_locate(P, idx, dx, dy, e, xi, eta);
+        u_dep_store(P, idx, k, e, xi, eta, true);
+    }
+}
+
 // Departure points of a moving body, every step: X - dt g^{-1}(c_k - V_G) in
-// the undeformed frame, g = I + dd/dX at level n+1 (the nodal mean of the
+// the undeformed frame (k = 0 included: the rest populations' point is
+// X + dt g^{-1} V_G, the node itself where V_G = 0), g = I + dd/dX at level n+1 (the nodal mean of the
 // element derivatives, formed from the static nodal derivatives of r, r X and
 // r Y and the body state), V_G = (d^{n+1} - d^n) / dt; the previous step's
 // element is tried first, by Newton from its local coordinates, then the
@@ -384,7 +500,8 @@ constexpr int U_PATCH_REG = 8;
 // (flag, previous table entries, displacements and the node's first eight
 // patch entries at a fixed stride; then the corners of the previous
 // elements), rather than one per direction.
-constexpr int U_REL_DIRS = 4;   // directions per call
+constexpr int U_REL_DIRS = 4;   // moving directions per call
+template <int ND = U_REL_DIRS>
 __device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, int k0, const BodySlot &s1,
                                                 const Body &body, unsigned &err) {
     const float dt = P.dt;
@@ -395,16 +512,20 @@ __device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, in
     const uint8_t flag = P.qflag[idx];
     const int4 pa = reinterpret_cast<const int4 *>(P.patch8)[2 * idx];
     const int4 pb = reinterpret_cast<const int4 *>(P.patch8)[2 * idx + 1];
-    int ep[U_REL_DIRS];
-    float2 pxy[U_REL_DIRS];
+    int ep[ND];
+    float2 pxy[ND];
 #pragma unroll
-    for (int j = 0; j < U_REL_DIRS; ++j) {
-        ep[j] = P.dep_e[(k0 - 1 + j) * N + idx];
-        pxy[j] = P.dep_xy[(k0 - 1 + j) * N + idx];
+    for (int j = 0; j < ND; ++j) {
+        ep[j] = P.dep_e[dep_plane(k0 + j) * N + idx];
+        pxy[j] = P.dep_xy[dep_plane(k0 + j) * N + idx];
     }
     const double2 d0 = P.qdisp[idx], d1 = P.qdisp[N + idx];
     const float2 Lr = P.dgr[3 * idx], LrX = P.dgr[3 * idx + 1], LrY = P.dgr[3 * idx + 2];
     if (!(flag & Q9_PATCH_MOVES)) return;
+    if (flag & Q9_WALL) {
+        q9_wall_relocate(P, idx, k0, ND, s1, body);
+        return;
+    }
     const bool bnd = (flag & Q9_BOUNDARY) != 0;
     const int ent[U_PATCH_REG] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
     // patch size: the entries held, or from the patch offsets for a node
@@ -419,9 +540,9 @@ __device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, in
         cnt = e_end - b;
     }
     // the node's local index in each previous element
-    int la[U_REL_DIRS];
+    int la[ND];
 #pragma unroll
-    for (int j = 0; j < U_REL_DIRS; ++j) {
+    for (int j = 0; j < ND; ++j) {
         la[j] = -1;
 #pragma unroll
         for (int i = 0; i < U_PATCH_REG; ++i)
@@ -429,9 +550,9 @@ __device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, in
         for (int q = b + U_PATCH_REG; q < e_end; ++q)
             if ((P.patch_ent[q] >> 4) == ep[j]) la[j] = P.patch_ent[q] & 15;
     }
-    float2 c0[U_REL_DIRS], c1[U_REL_DIRS], c2[U_REL_DIRS], c3[U_REL_DIRS], ra[U_REL_DIRS];
+    float2 c0[ND], c1[ND], c2[ND], c3[ND], ra[ND];
 #pragma unroll
-    for (int j = 0; j < U_REL_DIRS; ++j) {
+    for (int j = 0; j < ND; ++j) {
         const float2 *rel = P.erel + 9 * (long long)(la[j] >= 0 ? ep[j] : 0);
         c0[j] = rel[0];
         c1[j] = rel[1];
@@ -452,8 +573,13 @@ __device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, in
     const float vgx = (float)((d1.x - d0.x) / P.dt_d), vgy = (float)((d1.y - d0.y) / P.dt_d);
     const float idg = 1.0f / (g00 * g11 - g01 * g10);
 #pragma unroll
-    for (int j = 0; j < U_REL_DIRS; ++j) {
+    for (int j = 0; j < ND; ++j) {
         const int k = k0 + j;
+        if (k == 0 && vgx == 0.0f && vgy == 0.0f) {
+            // a rest population whose node does not move keeps its value
+            u_dep_store(P, idx, 0, DEP_SELF, 0.0f, 0.0f, ep[j] != DEP_SELF);
+            continue;
+        }
         const float ax = (float)CXK(k) - vgx, ay = (float)CYK(k) - vgy;
         const float dx = -dt * idg * (g11 * ax - g01 * ay);
         const float dy = -dt * idg * (-g10 * ax + g00 * ay);
@@ -500,16 +626,18 @@ __device__ __forceinline__ void u_relocate_dirs(const Inst &P, long long idx, in
     }
 }
 
-// two threads per node (neighbouring lanes: directions 1-4 and 5-8); the
-// node-block interpolation kernel does the same for its own nodes when it
-// runs with the relocation folded in
+// two threads per node (neighbouring lanes: directions 1-4, and 5-8 then
+// the rest direction); the node-block interpolation kernel does the same for
+// its own nodes when it runs with the relocation folded in
 __global__ void __launch_bounds__(U_THREADS) k_u_relocate(const Inst *__restrict__ pinst) {
     const Inst &P = *pinst;
     const BodySlot s1 = P.slots[((*P.step + 1) % 3) * MAX_BODIES];
     unsigned err = 0;
     for (long long tid = xcd_block() * blockDim.x + threadIdx.x; tid < 2 * P.n_nodes;
-         tid += (long long)gridDim.x * blockDim.x)
+         tid += (long long)gridDim.x * blockDim.x) {
         u_relocate_dirs(P, tid >> 1, 1 + U_REL_DIRS * (int)(tid & 1), s1, P.body[0], err);
+        if (tid & 1) u_relocate_dirs<1>(P, tid >> 1, 0, s1, P.body[0], err);
+    }
     if (err) atomicOr(P.err, err);
 }
 
@@ -523,30 +651,45 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
     void *dst = P.pop[(n + 1) & 1];
     for (long long idx = xcd_block() * blockDim.x + threadIdx.x; idx < P.n_nodes;
          idx += (long long)gridDim.x * blockDim.x) {
-        // the rest populations k_u_collide wrote, then the moving ones
+        // the rest populations k_u_collide wrote (fixed mesh), then the moving
+        // ones (and with a moving body the rest ones, from after them)
+        const bool mv = P.qdisp != nullptr;
+        const float2 *up = reinterpret_cast<const float2 *>(P.upost);
         float f[9], g[9];
-        f[0] = pop_load<STORE>(P, dst, 0, idx);
-        g[0] = pop_load<STORE>(P, dst, Q, idx);
+        if (!mv) {
+            f[0] = pop_load<STORE>(P, dst, 0, idx);
+            g[0] = pop_load<STORE>(P, dst, Q, idx);
+        }
 #pragma unroll
-        for (int k = 1; k < 9; ++k) {
+        for (int k = 0; k < 9; ++k) {
+            if (k == 0 && !mv) continue;
             // a missing population (boundary node) is interpolated in element 0
             // at (0, 0), a value the boundary kernels replace
-            const int e0 = P.dep_e[(k - 1) * P.n_nodes + idx];
+            const int e0 = P.dep_e[dep_plane(k) * P.n_nodes + idx];
+            // post-collision (f_k, g_k) of node v
+            auto fgk = [&](long long v) { return k == 0 ? up[8 * P.n_nodes + v] : up[8 * v + (k - 1)]; };
+            if (e0 == DEP_SELF) {
+                const float2 own = fgk(idx);
+                pop_store<STORE>(P, dst, k, idx, own.x);
+                pop_store<STORE>(P, dst, Q + k, idx, own.y);
+                f[k] = pop_round<STORE>(P, k, own.x);
+                g[k] = pop_round<STORE>(P, Q + k, own.y);
+                continue;
+            }
             const int e = e0 < 0 ? 0 : e0;
-            const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
+            const float2 d = P.dep_xy[dep_plane(k) * P.n_nodes + idx];
             const float xi = d.x, eta = d.y;
             const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
             const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
             const int *nodes = P.elems + 9 * (long long)e;
-            const float2 *up = reinterpret_cast<const float2 *>(P.upost);
-            const float2 fg0 = up[8 * idx + (k - 1)];
+            const float2 fg0 = fgk(idx);
             float vf = fg0.x, vg = fg0.y;
 #pragma unroll
             for (int qq = -1; qq <= 1; ++qq)
 #pragma unroll
                 for (int pp = -1; pp <= 1; ++pp) {
                     const float w = lx[pp + 1] * ly[qq + 1];
-                    const float2 fg = up[8 * (long long)nodes[q9_node(pp, qq)] + (k - 1)];
+                    const float2 fg = fgk(nodes[q9_node(pp, qq)]);
                     vf += w * (fg.x - fg0.x);
                     vg += w * (fg.y - fg0.y);
                 }
@@ -570,9 +713,14 @@ __global__ void __launch_bounds__(U_THREADS) k_u_stream(const Inst *__restrict__
 // compiler may fuse multiply-adds differently in the two kernels, so the paths
 // agree to FP32 rounding).  Blocks go to XCDs in
 // contiguous runs, so neighbouring blocks share their halo's lines in one L2.
+//
+// With a moving body (MOV) the rest populations form a ninth LDS plane and are
+// interpolated like the others where the node moves (a node that does not
+// move keeps its own value); on a fixed mesh they go straight to the output.
 template <int STORE, int EU16, bool MOV>
 __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__restrict__ pinst) {
     extern __shared__ __align__(16) unsigned char u_lds[];
+    constexpr int NPL = MOV ? 9 : 8;          // LDS planes of (f_k, g_k)
     const Inst &P = *pinst;
     const int nb = P.u_nblk, per_xcd = (nb + 7) / 8;
     const int b = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
@@ -581,8 +729,8 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     const void *src = P.pop[n & 1];
     void *dst = P.pop[(n + 1) & 1];
     const int H = P.u_hmax;
-    float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [8][H]
-    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)8 * H * sizeof(float2));  // [LE][EU16]
+    float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [NPL][H]
+    uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)NPL * H * sizeof(float2));  // [LE][EU16]
     float2 *rest = reinterpret_cast<float2 *>(reinterpret_cast<unsigned char *>(el) +
                                               u_block_elem_bytes(P.u_lemax, EU16));  // [U_BLOCK]
     const int h0 = P.bh_off[b], nh = P.bh_off[b + 1] - h0;
@@ -599,6 +747,7 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
             const BodySlot s1 = P.slots[((n + 1) % 3) * MAX_BODIES];
             u_relocate_dirs(P, r, 1, s1, P.body[0], err);
             u_relocate_dirs(P, r, 1 + U_REL_DIRS, s1, P.body[0], err);
+            u_relocate_dirs<1>(P, r, 0, s1, P.body[0], err);
         }
     }
     for (int h = threadIdx.x; h < nh; h += U_BLOCK) {
@@ -613,9 +762,10 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         collide(f, g, F.x, F.y, P, err);
 #pragma unroll
         for (int k = 1; k < 9; ++k) pl[(k - 1) * H + h] = make_float2(f[k], g[k]);
-        // the block's own nodes: rest populations (they do not move)
+        if constexpr (MOV) pl[8 * H + h] = make_float2(f[0], g[0]);
+        // fixed mesh, the block's own nodes: rest populations (they do not move)
         const long long own = v - n0;
-        if (own >= 0 && own < U_BLOCK) {
+        if (!MOV && own >= 0 && own < U_BLOCK) {
             pop_store<STORE>(P, dst, 0, v, f[0]);
             pop_store<STORE>(P, dst, Q, v, g[0]);
             rest[own] = make_float2(pop_round<STORE>(P, 0, f[0]), pop_round<STORE>(P, Q, g[0]));
@@ -631,15 +781,26 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     if (idx >= P.n_nodes) return;
     const int self = P.uself[idx];
     float f[9], g[9];
-    f[0] = rest[threadIdx.x].x;
-    g[0] = rest[threadIdx.x].y;
+    if constexpr (!MOV) {
+        f[0] = rest[threadIdx.x].x;
+        g[0] = rest[threadIdx.x].y;
+    }
 #pragma unroll
-    for (int k = 1; k < 9; ++k) {
+    for (int k = MOV ? 0 : 1; k < 9; ++k) {
+        const float2 *plk = pl + dep_plane(k) * H;
         // a missing population (boundary node) is interpolated in the block's
         // first element at (0, 0), a value the boundary kernels replace
-        const int le0 = P.dep_le[(k - 1) * P.n_nodes + idx];
+        const int le0 = P.dep_le[dep_plane(k) * P.n_nodes + idx];
+        if (k == 0 && le0 == U_SELF) {
+            const float2 own = plk[self];
+            pop_store<STORE>(P, dst, 0, idx, own.x);
+            pop_store<STORE>(P, dst, Q, idx, own.y);
+            f[0] = pop_round<STORE>(P, 0, own.x);
+            g[0] = pop_round<STORE>(P, Q, own.y);
+            continue;
+        }
         const int le = le0 == U_MISSING ? 0 : le0;
-        const float2 d = P.dep_xy[(k - 1) * P.n_nodes + idx];
+        const float2 d = P.dep_xy[dep_plane(k) * P.n_nodes + idx];
         const float xi = d.x, eta = d.y;
         const float lx[3] = {0.5f * xi * (xi - 1.0f), 1.0f - xi * xi, 0.5f * xi * (xi + 1.0f)};
         const float ly[3] = {0.5f * eta * (eta - 1.0f), 1.0f - eta * eta, 0.5f * eta * (eta + 1.0f)};
@@ -659,7 +820,6 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         const int nodes[9] = {(int)(w0 & 0xffffu), (int)(w0 >> 16), (int)(w1 & 0xffffu),
                               (int)(w1 >> 16),     (int)(w2 & 0xffffu), (int)(w2 >> 16),
                               (int)(w3 & 0xffffu), (int)(w3 >> 16),     n8};
-        const float2 *plk = pl + (k - 1) * H;
         const float2 fg0 = plk[self];
         float vf = fg0.x, vg = fg0.y;
 #pragma unroll
@@ -816,11 +976,13 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
     const long long n = *P.step;
     void *buf = P.pop[(phase ? n + 1 : n) & 1];
     const long long w = P.qw_nodes[k];
-    unsigned miss = 0;
-    for (int q = 1; q < 9; ++q)
-        if (P.dep_e[(q - 1) * P.n_nodes + w] < 0) miss |= 1u << q;
-    const float4 t0 = P.wall_tgt[k];
     const bool mv = P.qdisp != nullptr;
+    // missing populations: departure point outside the mesh (the rest
+    // populations only with a moving body)
+    unsigned miss = 0;
+    for (int q = mv ? 0 : 1; q < 9; ++q)
+        if (P.dep_e[dep_plane(q) * P.n_nodes + w] == -1) miss |= 1u << q;
+    const float4 t0 = P.wall_tgt[k];
     // the wall's mesh velocity (no slip), the displacements of the level
     const float2 uw = mv && phase ? q9_mesh_velocity(P, w) : make_float2(0.0f, 0.0f);
     const double2 *dL = mv ? P.qdisp + (phase ? P.n_nodes : 0) : nullptr;
@@ -905,7 +1067,7 @@ __global__ void __launch_bounds__(64) k_u_wall(const Inst *__restrict__ pinst, i
         grad_populations(P, miss, t0.x, uw.x, uw.y, T_t, E_t, sgrad[0][0], sgrad[0][1], sgrad[1][0],
                          sgrad[1][1], sgrad[2][0], sgrad[2][1], sgrad[3][0], sgrad[3][1], f, g);
 #pragma unroll
-        for (int q = 1; q < 9; ++q) {
+        for (int q = 0; q < 9; ++q) {
             if (!(miss & (1u << q))) continue;
             pop_store<STORE>(P, buf, q, w, f[q]);
             pop_store<STORE>(P, buf, Q + q, w, g[q]);
@@ -970,7 +1132,7 @@ hipError_t launch_unstructured(const Inst *inst, long long n_nodes, long long n_
     if (n_blocks > 0) {
         // a multiple of the XCD count; the kernel maps slots to blocks
         const unsigned g = (unsigned)(((n_blocks + 7) / 8) * 8);
-        const size_t lds = u_block_lds_bytes(hmax, lemax, eu16);
+        const size_t lds = u_block_lds_bytes(hmax, lemax, eu16, relocate ? 9 : 8);
 #define FSI_U_BLK(ST, EU)                                                                          \
     do {                                                                                           \
         if (relocate)                                                                              \
