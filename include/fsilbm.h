@@ -252,6 +252,24 @@ fsi_status fsi_init_equilibrium(fsi_ctx *ctx, const double *rho, const double *u
  * Asynchronous. */
 fsi_status fsi_step(fsi_ctx *ctx, int nsteps);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same `nsteps` coupled
+ * steps as fsi_step, with the same kernels and results, but launched directly
+ * on the context's stream (no graph is captured or instantiated, nothing is
+ * allocated, no memset is recorded).  The step's temporaries (wall masks,
+ * wall targets, per-node tractions, cut staging: 52 * ni bytes plus
+ * 72 * (cut columns) bytes, each part rounded up to 256) live in a static
+ * device array of 1 MiB per GPU, held until the process ends, instead of the
+ * workspace; its address on the device current at fsi_bind_workspace is
+ * looked up there.  Structured meshes only (FSI_E_ARG for 9-node meshes and
+ * for meshes whose temporaries exceed 1 MiB).  Every call on one GPU shares
+ * the array: calls on different contexts that overlap in time on one GPU
+ * race (serialise them, e.g. on one stream).  No entry of the array needs to
+ * start at zero (each step writes every entry before reading it).
+ * Asynchronous, like fsi_step; the inputs and outputs are the context's bound
+ * state. */
+fsi_status fsi_step_noalloc(fsi_ctx *ctx, int nsteps);
+
 /* Wait for the stream and report the sticky device error word
  * (FSI_E_CFL, FSI_E_STATE, FSI_E_MESH). */
 fsi_status fsi_synchronize(fsi_ctx *ctx);

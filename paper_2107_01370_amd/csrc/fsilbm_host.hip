@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -14,6 +15,15 @@
 #include "fsilbm_internal.h"
 
 using fsi::Inst;
+
+// Per-step scratch of fsi_step_noalloc (callers that cannot allocate): the
+// wall masks, wall targets, per-node tractions and cut staging of one step,
+// which fsi_step keeps in the caller's workspace.  One copy per GPU, held
+// until the process ends; every call on a GPU shares it, so calls that
+// overlap on one GPU race.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (noalloc_scratch below).
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 struct fsi_ctx {
     fsi_fluid_params fluid{};
@@ -70,6 +80,11 @@ struct fsi_ctx {
     std::vector<uint8_t> inflow;        // per far-field list entry
     std::vector<int2> ff;               // far-field (node, interior node)
     std::vector<int2> wk0, wk1, wbnd, wwall;
+    // fsi_step_noalloc: a second device copy of the instance whose per-step
+    // scratch pointers lead into the static scratch array of the bound device
+    size_t off_inst_na = 0;
+    size_t na_bytes = 0;            // scratch the step needs (0: not supported)
+    bool na_ready = false;          // the copy is uploaded
     // captured steps: [0] one step, [1] kGraphSteps steps (fewer graph launches)
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -98,6 +113,41 @@ fsi_status hip_fail(fsi_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Device address of the static scratch array on the current device, looked up
+// once per device (each GPU holds its own copy at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+hipError_t noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// byte offsets of the per-step scratch inside the static array: wall masks
+// (missing, ambiguous), wall targets, tractions, cut staging; the total
+size_t na_layout(const fsi_ctx *c, size_t off[5]) {
+    size_t o = 0;
+    const size_t sz[5] = {(size_t)c->ni * 4, (size_t)c->ni * 16, (size_t)c->ni * 32,
+                          (size_t)18 * c->inst.cut_n * sizeof(float), 0};
+    for (int k = 0; k < 5; ++k) {
+        off[k] = o;
+        o += align_up(sz[k]);
+    }
+    return o;
+}
 
 int wrapi(int a, int n) { return ((a % n) + n) % n; }
 
@@ -937,6 +987,7 @@ void layout(fsi_ctx *c) {
     c->off_step = take(8);
     c->off_err = take(4);
     c->off_inst = take(sizeof(Inst));
+    c->off_inst_na = take(sizeof(Inst));
     c->off_wk1 = take(c->wk1.size() * sizeof(int2));
     c->off_wbnd = take(c->wbnd.size() * sizeof(int2));
     c->off_wwall = take(c->wwall.size() * sizeof(int2));
@@ -993,11 +1044,38 @@ fsi_status check_ready(fsi_ctx *c, bool need_init) {
 }
 
 const Inst *d_inst(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c->off_inst); }
+const Inst *d_inst_na(fsi_ctx *c) { return reinterpret_cast<const Inst *>(c->ws + c->off_inst_na); }
+
+// The instance copy of fsi_step_noalloc: the bound instance with its per-step
+// scratch (wall masks, targets, tractions, cut staging) in the static scratch
+// array of the current device.  Structured meshes whose scratch fits the
+// array only (else na_bytes stays 0 and the entry point refuses).
+fsi_status upload_inst_na(fsi_ctx *c) {
+    c->na_ready = false;
+    c->na_bytes = 0;
+    if (c->topo == FSI_TOPO_Q9) return FSI_OK;
+    size_t off[5];
+    const size_t need = na_layout(c, off);
+    if (need > kNoAllocScratchBytes) return FSI_OK;
+    void *base = nullptr;
+    HIP_TRY(c, noalloc_scratch(&base));
+    char *sb = static_cast<char *>(base);
+    Inst P = c->inst;
+    P.wall_mask = reinterpret_cast<uint16_t *>(sb + off[0]);
+    P.wall_amb = P.wall_mask + c->ni;
+    P.wall_tgt = reinterpret_cast<float4 *>(sb + off[1]);
+    P.wall_force = reinterpret_cast<double4 *>(sb + off[2]);
+    P.cutbuf = reinterpret_cast<float *>(sb + off[3]);
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst_na, &P, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+    c->na_bytes = need;
+    c->na_ready = true;
+    return FSI_OK;
+}
 
 // one pass of the fluid part of a step on the populations of level n: the cut
 // pre-pass, collision-streaming, wall targets and far field, Grad populations
 // and traction of the new level
-fsi_status enqueue_fluid(fsi_ctx *c) {
+fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di) {
     const int st = c->fluid.storage;
     if (c->topo == FSI_TOPO_Q9) {
         // a moving body: the mesh of both levels and the departure points on
@@ -1016,14 +1094,14 @@ fsi_status enqueue_fluid(fsi_ctx *c) {
         return FSI_OK;
     }
     if (!c->wk0.empty())
-        HIP_TRY(c, fsi::launch_cut_export(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
+        HIP_TRY(c, fsi::launch_cut_export(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
-    HIP_TRY(c, fsi::launch_collide_stream(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
+    HIP_TRY(c, fsi::launch_collide_stream(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
                                           (int)c->wk1.size(), st, c->stream, 0, c->cut, 0));
     if (c->has_wall) {
-        HIP_TRY(c, fsi::launch_wall_targets(d_inst(c), reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
+        HIP_TRY(c, fsi::launch_wall_targets(di, reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
-        HIP_TRY(c, fsi::launch_wall_grad_force(d_inst(c),
+        HIP_TRY(c, fsi::launch_wall_grad_force(di,
                                                reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
                                                (int)c->wwall.size(), st, 1, c->stream));
     }
@@ -1033,7 +1111,8 @@ fsi_status enqueue_fluid(fsi_ctx *c) {
 // one coupled step: with strong coupling, n_sub - 1 sub-iterations (fluid pass,
 // structure re-solved and relaxed) before the final pass, which the body
 // kernel accepts and records
-fsi_status enqueue_step(fsi_ctx *c) {
+fsi_status enqueue_step(fsi_ctx *c, const Inst *di = nullptr) {
+    if (!di) di = d_inst(c);
     // without a body there is nothing to iterate on: one pass
     const int passes = c->bodies.empty() ? 1 : c->n_sub;
     for (int k = 0; k < passes; ++k) {
@@ -1046,9 +1125,9 @@ fsi_status enqueue_step(fsi_ctx *c) {
                 HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(), 0,
                                                              c->fluid.storage, 0, c->stream));
         }
-        fsi_status st = enqueue_fluid(c);
+        fsi_status st = enqueue_fluid(c, di);
         if (st != FSI_OK) return st;
-        HIP_TRY(c, fsi::launch_body(d_inst(c), 1, k + 1 < passes ? 2 : 1, c->stream));
+        HIP_TRY(c, fsi::launch_body(di, 1, k + 1 < passes ? 2 : 1, c->stream));
     }
     return FSI_OK;
 }
@@ -1336,6 +1415,10 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk1, c->wk1.data(), c->wk1.size() * sizeof(int2),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+    {
+        fsi_status sn = upload_inst_na(c);
+        if (sn != FSI_OK) return sn;
+    }
     // static unstructured mesh: the departure points once
     if (c->topo == FSI_TOPO_Q9)
         HIP_TRY(c, fsi::launch_unstructured_locate(d_inst(c), (long long)c->ni, c->stream));
@@ -1417,6 +1500,29 @@ fsi_status fsi_step(fsi_ctx *c, int nsteps) {
         }
         for (int k = 0; k < nlong; ++k) HIP_TRY(c, hipGraphLaunch(c->graph_exec[1], c->stream));
         for (int k = 0; k < nshort; ++k) HIP_TRY(c, hipGraphLaunch(c->graph_exec[0], c->stream));
+    }
+    c->host_step += nsteps;
+    return FSI_OK;
+}
+
+fsi_status fsi_step_noalloc(fsi_ctx *c, int nsteps) {
+    fsi_status st = check_ready(c, true);
+    if (st != FSI_OK) return st;
+    if (nsteps < 0) return fail(c, FSI_E_ARG, "nsteps < 0");
+    if (c->topo == FSI_TOPO_Q9) return fail(c, FSI_E_ARG, "fsi_step_noalloc: structured meshes only");
+    if (!c->na_ready) {
+        size_t off[5];
+        return fail(c, FSI_E_ARG, "fsi_step_noalloc: the step needs " + std::to_string(na_layout(c, off)) +
+                                      " bytes of scratch, more than the " +
+                                      std::to_string(kNoAllocScratchBytes) + " the library holds");
+    }
+    // the kernels of each step, launched directly (no graph, no memset): the
+    // same kernels as fsi_step with the per-step scratch in the static array;
+    // every scratch entry a step reads is written earlier in the same step, so
+    // nothing has to be cleared between calls
+    for (int k = 0; k < nsteps; ++k) {
+        st = enqueue_step(c, d_inst_na(c));
+        if (st != FSI_OK) return st;
     }
     c->host_step += nsteps;
     return FSI_OK;
@@ -1687,6 +1793,8 @@ fsi_status fsi_set_coupling(fsi_ctx *c, int subiterations, double relaxation) {
     if (c->ws) {
         HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice,
                                   c->stream));
+        fsi_status sn = upload_inst_na(c);
+        if (sn != FSI_OK) return sn;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     return FSI_OK;

@@ -21,7 +21,7 @@ FSI_OK = 0
 STATUS_NAMES = {0: "FSI_OK", -1: "FSI_E_ARG", -2: "FSI_E_MESH", -3: "FSI_E_CFL",
                 -4: "FSI_E_STATE", -5: "FSI_E_HIP", -6: "FSI_E_NOMEM", -7: "FSI_E_UNBOUND"}
 EXPORTED = ("fsi_create", "fsi_workspace_bytes", "fsi_bind_workspace", "fsi_init_equilibrium",
-            "fsi_step", "fsi_synchronize", "fsi_get_step", "fsi_get_forces",
+            "fsi_step", "fsi_step_noalloc", "fsi_synchronize", "fsi_get_step", "fsi_get_forces",
             "fsi_history_capacity", "fsi_get_body_state", "fsi_dump_macro",
             "fsi_get_populations", "fsi_set_populations", "fsi_state_bytes", "fsi_save",
             "fsi_load", "fsi_time_kernels", "fsi_set_coupling", "fsi_get_coupling_residual",
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "fsi_bind_workspace": (ctypes.c_int, [P, P, ctypes.c_size_t]),
         "fsi_init_equilibrium": (ctypes.c_int, [P, dp, dp, dp, dp]),
         "fsi_step": (ctypes.c_int, [P, ctypes.c_int]),
+        "fsi_step_noalloc": (ctypes.c_int, [P, ctypes.c_int]),
         "fsi_synchronize": (ctypes.c_int, [P]),
         "fsi_get_step": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64)]),
         "fsi_get_forces": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, dp]),
@@ -235,6 +236,10 @@ def fsi_init_equilibrium(ctx, shape, rho=None, ux=None, uy=None, T=None):
 
 def fsi_step(ctx, nsteps):
     _check(ctx, _lib.fsi_step(ctx, int(nsteps)))
+
+
+def fsi_step_noalloc(ctx, nsteps):
+    _check(ctx, _lib.fsi_step_noalloc(ctx, int(nsteps)))
 
 
 def fsi_synchronize(ctx):
@@ -483,6 +488,9 @@ class Simulation:
 
     def step(self, nsteps=1):
         fsi_step(self.ctx, nsteps)
+
+    def step_noalloc(self, nsteps=1):
+        fsi_step_noalloc(self.ctx, nsteps)
 
     def synchronize(self):
         fsi_synchronize(self.ctx)
