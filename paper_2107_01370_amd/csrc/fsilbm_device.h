@@ -66,7 +66,12 @@ __device__ __forceinline__ double blend_factor(const Inst &P, int k, long long i
         d = P.wall_dist[k * P.n_nodes + idx];
     } else {
         const double dx = X - b.cx, dy = Y - b.cy;
-        d = sqrt(dx * dx + dy * dy);
+        const double d2 = dx * dx + dy * dy;
+        // outside the region of influence, or in the rigid zone, without the
+        // root (r_5 is flat to third order at both ends)
+        if (d2 >= b.r_blend2) return 1.0;
+        if (d2 <= b.r_rigid2) return 0.0;
+        d = sqrt(d2);
     }
     const double s = (d - b.r_rigid) * b.inv_width;
     if (s <= 0.0) return 0.0;
@@ -251,60 +256,71 @@ __device__ __forceinline__ void pop_st(const Inst &P, const PopBuf &b, int q, in
 // with q^* - q^eq = 2 u . (P - P^eq).
 __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float Fy, const Inst &P,
                                         unsigned &err) {
-    const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    // moments from sums and differences of opposite populations
+    const float s13 = f[1] + f[3], d13 = f[1] - f[3];
+    const float s24 = f[2] + f[4], d24 = f[2] - f[4];
+    const float s56 = f[5] + f[6], d56 = f[5] - f[6];
+    const float s78 = f[7] + f[8], d78 = f[7] - f[8];
+    const float sd = s56 + s78;                        // the four diagonal populations
+    const float rho = (f[0] + s13) + (s24 + sd);
+    const float jx = d13 + (d56 - d78);
+    const float jy = d24 + (s56 - s78);
+    const float Pxx = s13 + sd, Pyy = s24 + sd, Pxy = d56 + d78;
     const float G = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
     const float ir = rcpf(rho);
     const float ux = jx * ir, uy = jy * ir;
+    const float uxx = ux * ux, uyy = uy * uy;
     const float E = 0.5f * G * ir;
-    const float T = (E - 0.5f * (ux * ux + uy * uy)) * (P.gamma - 1.0f);
+    const float T = (E - 0.5f * (uxx + uyy)) * (P.gamma - 1.0f);
     if (!state_ok(rho, ux, uy, T)) err |= ERR_STATE;
-    const float Pxx = (f[1] + f[3]) + (f[5] + f[6]) + (f[7] + f[8]);
-    const float Pyy = (f[2] + f[4]) + (f[5] + f[6]) + (f[7] + f[8]);
-    const float Pxy = (f[5] - f[6]) + (f[7] - f[8]);
     // omega from mu = (1/omega - 1/2) p dt; Pr = (1/omega - 1/2)/(1/omega_1 - 1/2)
     const float a = P.mu * rcpf(rho * T * P.dt);
     const float omega = rcpf(a + 0.5f);
     const float omega1 = rcpf(a * rcpf(P.Pr) + 0.5f);
     const float invT = rcpf(T);
-    // equilibria (product-form f^eq; g^eq with Psi)
-    const float px[3] = {0.5f * (-ux + ux * ux + T), 1.0f - (ux * ux + T), 0.5f * (ux + ux * ux + T)};
-    const float py[3] = {0.5f * (-uy + uy * uy + T), 1.0f - (uy * uy + T), 0.5f * (uy + uy * uy + T)};
-    const float w[3] = {0.5f * T, 1.0f - T, 0.5f * T};
+    // lattice weights: axis (1 - T) T/2, diagonal (T/2)^2 (the rest population's
+    // equilibria follow from the closure below)
+    const float wh = 0.5f * T, w1 = 1.0f - T;
+    const float Wa = w1 * wh, Wd = wh * wh;
+    // product-form f^eq = rho px[cx] py[cy], px[+-1] = (u^2 + T +- u)/2, px[0] = 1 - u^2 - T
+    const float hx = 0.5f * (uxx + T), hy = 0.5f * (uyy + T);
+    const float rpm = rho * (hx - 0.5f * ux), rpp = rho * (hx + 0.5f * ux), rp0 = rho * (1.0f - 2.0f * hx);
+    const float pym = hy - 0.5f * uy, pyp = hy + 0.5f * uy, py0 = 1.0f - 2.0f * hy;
+    float feq[9];
+    feq[0] = rp0 * py0;
+    feq[1] = rpp * py0;
+    feq[2] = rp0 * pyp;
+    feq[3] = rpm * py0;
+    feq[4] = rp0 * pym;
+    feq[5] = rpp * pyp;
+    feq[6] = rpm * pyp;
+    feq[7] = rpm * pym;
+    feq[8] = rpp * pym;
+    // g^eq (with Psi): W_i [2 rho E + q^eq.c_i/T + A:(c_i c_i - T I)/(2T^2)] + Psi_i,
+    // q^eq = 2 rho u H, H = E + T; A = 2 rho [(E + 2T) u u + T^2 I]
     const float inv2T2 = 0.5f * invT * invT;
     const float H = E + T;
-    const float qx = 2.0f * rho * ux * H, qy = 2.0f * rho * uy * H;
+    const float qxT = 2.0f * rho * ux * H * invT, qyT = 2.0f * rho * uy * H * invT;
     const float e2 = E + 2.0f * T;
-    const float Axx = 2.0f * rho * (e2 * ux * ux + T * T);
-    const float Ayy = 2.0f * rho * (e2 * uy * uy + T * T);
+    const float Axx = 2.0f * rho * (e2 * uxx + T * T);
+    const float Ayy = 2.0f * rho * (e2 * uyy + T * T);
     const float Axy = 2.0f * rho * e2 * ux * uy;
+    // Psi: delta R_a = rho (1 - 3T)(T^2 + 2 u_a^2 T + E u_a^2) / T
     const float c13 = rho * (1.0f - 3.0f * T) * invT;
-    const float dRx = c13 * (T * T + (2.0f * T + E) * ux * ux);
-    const float dRy = c13 * (T * T + (2.0f * T + E) * uy * uy);
+    const float dRx = c13 * (T * T + (2.0f * T + E) * uxx);
+    const float dRy = c13 * (T * T + (2.0f * T + E) * uyy);
     const float two_rho_E = 2.0f * rho * E;
     const float trA = T * (Axx + Ayy);
-    const float dPxx = Pxx - rho * (T + ux * ux);
-    const float dPyy = Pyy - rho * (T + uy * uy);
-    const float dPxy = Pxy - rho * ux * uy;
-    const float dqx = 2.0f * (ux * dPxx + uy * dPxy);
-    const float dqy = 2.0f * (ux * dPxy + uy * dPyy);
-    // per-direction vectors: f gets -dt F/T, g gets (omega_1 - omega) dq/T + q^eq/T
-    const float cf = -P.dt * invT, cg = (omega1 - omega) * invT;
-    const float vfx = cf * Fx, vfy = cf * Fy;
-    const float vgx = cg * dqx, vgy = cg * dqy;
-    const float qxT = qx * invT, qyT = qy * invT;
-    float feq[9], geq[9];
+    const float w[3] = {wh, w1, wh};
+    float geq[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 1; k < 9; ++k) {
         const int cx = CXK(k), cy = CYK(k);
         const float W = w[cx + 1] * w[cy + 1];
-        feq[k] = rho * px[cx + 1] * py[cy + 1];
         const float contr = Axx * (float)(cx * cx) + Ayy * (float)(cy * cy) +
                             2.0f * Axy * (float)(cx * cy) - trA;
         float psi = 0.0f;
-        if (k == 0) psi = dRx + dRy;
-        else if (cy == 0) psi = -0.5f * dRx;
+        if (cy == 0) psi = -0.5f * dRx;
         else if (cx == 0) psi = -0.5f * dRy;
         geq[k] = W * (two_rho_E + qxT * (float)cx + qyT * (float)cy + contr * inv2T2) + psi;
     }
@@ -316,12 +332,24 @@ __device__ __forceinline__ void collide(float f[9], float g[9], float Fx, float 
     feq[2] = jy + ((feq[4] + feq[7] + feq[8]) - (feq[5] + feq[6]));
     feq[0] = rho - (((feq[1] + feq[2]) + (feq[3] + feq[4])) + ((feq[5] + feq[6]) + (feq[7] + feq[8])));
     geq[0] = G - (((geq[1] + geq[2]) + (geq[3] + geq[4])) + ((geq[5] + geq[6]) + (geq[7] + geq[8])));
+    // Collision (Sec. II.C, kinetic equations), the forcing terms by direction:
+    //   f* = f + omega (f^eq - f) + dt phi,  phi_i = -(W_i/T) c_i . F
+    //   g* = g + omega_1 (g^eq - g) + (omega_1 - omega) W_i (q^* - q^eq) . c_i / T,
+    //   q^* - q^eq = 2 u . (P - P^eq)
+    const float dPxx = Pxx - rho * (T + uxx);
+    const float dPyy = Pyy - rho * (T + uyy);
+    const float dPxy = Pxy - rho * ux * uy;
+    const float cf = -P.dt * invT, cgm = 2.0f * (omega1 - omega) * invT;
+    const float vfx = cf * Fx, vfy = cf * Fy;
+    const float vgx = cgm * (ux * dPxx + uy * dPxy), vgy = cgm * (ux * dPxy + uy * dPyy);
+    const float tfx = Wa * vfx, tfy = Wa * vfy, tfp = Wd * (vfx + vfy), tfm = Wd * (vfx - vfy);
+    const float tgx = Wa * vgx, tgy = Wa * vgy, tgp = Wd * (vgx + vgy), tgm = Wd * (vgx - vgy);
+    const float tf[9] = {0.0f, tfx, tfy, -tfx, -tfy, tfp, -tfm, -tfp, tfm};
+    const float tg[9] = {0.0f, tgx, tgy, -tgx, -tgy, tgp, -tgm, -tgp, tgm};
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int cx = CXK(k), cy = CYK(k);
-        const float W = w[cx + 1] * w[cy + 1];
-        f[k] = f[k] + omega * (feq[k] - f[k]) + W * (vfx * (float)cx + vfy * (float)cy);
-        g[k] = g[k] + omega1 * (geq[k] - g[k]) + W * (vgx * (float)cx + vgy * (float)cy);
+        f[k] = f[k] + omega * (feq[k] - f[k]) + tf[k];
+        g[k] = g[k] + omega1 * (geq[k] - g[k]) + tg[k];
     }
 }
 

@@ -930,6 +930,8 @@ void fill_params(fsi_ctx *c) {
         B.cx = b.center[0]; B.cy = b.center[1]; B.ex = bm.ea[0]; B.ey = bm.ea[1];
         B.r_rigid = b.r_rigid;
         B.inv_width = 1.0 / (b.r_blend - b.r_rigid);
+        B.r_rigid2 = b.r_rigid > 0.0 ? b.r_rigid * b.r_rigid : -1.0;
+        B.r_blend2 = b.r_blend * b.r_blend;
         B.heave_amp = bm.heave_amp; B.heave_omega = 2.0 * M_PI * bm.heave_freq;
         B.pitch_amp = bm.pitch_amp; B.pitch_omega = 2.0 * M_PI * bm.pitch_freq;
         B.release_time = bm.release_time;

@@ -45,6 +45,7 @@ struct Body {
     double ex, ey;            // rotation centre of its rigid map: its elastic axis, or
                               // the axis of the body it is linked to
     double r_rigid, inv_width;// 1 / (r_blend - r_rigid)
+    double r_rigid2, r_blend2;// squared radii (r_rigid2 < 0 if r_rigid <= 0)
     double heave_amp, heave_omega, pitch_amp, pitch_omega;
     double release_time;      // > 0: prescribed motion until then (1DOF / 2DOF)
     int blend_mode;           // 0: radial from (cx, cy); 1: per-node wall distance

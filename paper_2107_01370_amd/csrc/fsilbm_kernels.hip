@@ -308,11 +308,15 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 valid = jg < nj;
             }
         } else {
-            while (ig < 0) { ig += ni; --wi; }
-            while (ig >= ni) { ig -= ni; ++wi; }
+            if (ig < 0 || ig >= ni) {        // meshes narrower than the halo wrap more than once
+                while (ig < 0) { ig += ni; --wi; }
+                while (ig >= ni) { ig -= ni; ++wi; }
+            }
             if (P.periodic_j) {
-                while (jg < 0) { jg += nj; --wj; }
-                while (jg >= nj) { jg -= nj; ++wj; }
+                if (jg < 0 || jg >= nj) {
+                    while (jg < 0) { jg += nj; --wj; }
+                    while (jg >= nj) { jg -= nj; ++wj; }
+                }
             } else {
                 valid = (jg >= 0 && jg < nj);
             }
@@ -351,8 +355,12 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             dn = make_float2((float)(a0x - Drx), (float)(a0y - Dry));
             dd = make_float2((float)a1x, (float)a1y);
         }
-        sm.Xu[e] = make_float2((float)(Xr.x - Xrx + ((double)wi * P.shift_ix + (double)wj * P.shift_jx)),
-                               (float)(Xr.y - Xry + ((double)wi * P.shift_iy + (double)wj * P.shift_jy)));
+        double sx = Xr.x - Xrx, sy = Xr.y - Xry;
+        if (wi | wj) {            // seen across a periodic seam
+            sx += (double)wi * P.shift_ix + (double)wj * P.shift_jx;
+            sy += (double)wi * P.shift_iy + (double)wj * P.shift_jy;
+        }
+        sm.Xu[e] = make_float2((float)sx, (float)sy);
         sm.dn[e] = dn;
         sm.dd[e] = dd;
         float f[9], g[9];
@@ -486,8 +494,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 P.cutbuf[(NMOV + 1) * P.cut_n + slot] = g[0];
             }
         } else if (own && !tile_moves) {
-            // no node of the tile moves: the rest populations stay at their node
-            const int off = pop_off<STORE>(jg * ni + wrap(ig, ni));
+            // no node of the tile moves: the rest populations stay at their
+            // node (a node of the tile itself: 0 <= ig < ni)
+            const int off = pop_off<STORE>(jg * ni + ig);
             pop_st<STORE>(P, dst, 0, off, f[0]);
             pop_st<STORE>(P, dst, Q, off, g[0]);
         }
@@ -554,6 +563,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
         const int off = pop_off<STORE>(jg * ni + ig);
         uint16_t miss = 0, amb = 0;
+        float cfl = 0.0f;          // largest |index offset| of the departure points
+        bool unsettled = false;    // a bilinear solve that did not settle
+        // the wave holds a wall node (wave-uniform): the wall decision below
+        const bool wall_wave = __any(wall);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             if (k == 0 && !tile_moves) continue;     // stored in phase 3
@@ -583,24 +596,50 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             const float pu = im * (ejy * Px - ejx * Py), pv = im * (eix * Py - eiy * Px);
             const float tu = im * (ejy * twx - ejx * twy), tv = im * (eix * twy - eiy * twx);
             // u + tu u v = pu, v + tv u v = pv: fixed point from the linear
-            // solution (the twist is small for smooth cells)
+            // solution (the twist is small for smooth cells), until an update
+            // falls below 1e-6 of a cell: three rounds, a fourth whose update
+            // is checked, and where it still moved the point (strongly
+            // distorted cells; NaN never settles) up to 20 in all
             float uu = pu, vv = pv;
 #pragma unroll
-            for (int it = 0; it < 4; ++it) {
+            for (int it = 0; it < 3; ++it) {
                 const float uv = uu * vv;
                 uu = pu - tu * uv;
                 vv = pv - tv * uv;
             }
+            {
+                const float uv = uu * vv;
+                const float nu = pu - tu * uv, nv = pv - tv * uv;
+                bool moving = !(fabsf(nu - uu) + fabsf(nv - vv) <= 1e-6f);
+                uu = nu;
+                vv = nv;
+                if (__any(moving)) {
+                    for (int it = 4; it < 20 && __any(moving); ++it) {
+                        const float uv2 = uu * vv;
+                        const float nu2 = pu - tu * uv2, nv2 = pv - tv * uv2;
+                        moving = !(fabsf(nu2 - uu) + fabsf(nv2 - vv) <= 1e-6f);
+                        uu = nu2;
+                        vv = nv2;
+                    }
+                    unsettled = unsettled || moving;
+                }
+            }
             const float a = li ? -uu : uu;
             float bb = lj ? -vv : vv;
-            // a point more than 1e-4 of the cell below the wall line lies in
-            // the body (nearer, it counts as on the line).  Within 1e-5 of that
-            // line (several times the FP32 error of vv) the population is
-            // interpolated here and the wall kernel decides in FP64.
-            const bool near = wall && vv < -0.9e-4f;
-            amb |= near ? (uint16_t)(1u << k) : (uint16_t)0;
-            if (wall && vv < -1.1e-4f) { miss |= (uint16_t)(1u << k); continue; }
-            if (!(fabsf(a) <= 1.0f + 1e-4f) || !(fabsf(bb) <= 1.0f + 1e-4f)) err |= ERR_CFL;
+            if (wall_wave) {
+                // a point more than 1e-4 of the cell below the wall line lies
+                // in the body (nearer, it counts as on the line).  Within 1e-5
+                // of that line (several times the FP32 error of vv) the
+                // population is interpolated here and the wall kernel decides
+                // in FP64.
+                const bool near = wall && vv < -0.9e-4f;
+                amb |= near ? (uint16_t)(1u << k) : (uint16_t)0;
+                if (wall && vv < -1.1e-4f) {
+                    miss |= (uint16_t)(1u << k);
+                    continue;
+                }
+            }
+            cfl = fmaxf(cfl, fmaxf(fabsf(a), fabsf(bb)));
             bb -= (float)vc;
             const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
             const float wbm = 0.5f * bb * (bb - 1.0f), wbp = 0.5f * bb * (bb + 1.0f);
@@ -622,6 +661,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             pop_st<STORE>(P, dst, k, off, outv[0]);
             pop_st<STORE>(P, dst, Q + k, off, outv[1]);
         }
+        // a departure point beyond the node's cells (NaN sets `unsettled`), or
+        // a bilinear solve that did not settle in 20 rounds
+        if (!(cfl <= 1.0f + 1e-4f) || unsettled) err |= ERR_CFL;
         if (wall) {
             P.wall_mask[ig] = miss;
             P.wall_amb[ig] = amb & (uint16_t)~miss;
