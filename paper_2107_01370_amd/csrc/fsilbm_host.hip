@@ -886,6 +886,7 @@ void fill_params(fsi_ctx *c) {
     P.shift_jx = c->shift_j[0];
     P.shift_jy = c->shift_j[1];
     P.dt_d = fl.dt;
+    P.gm1_d = fl.gamma - 1.0;
     P.gamma = (float)fl.gamma;
     const double Cv = 1.0 / (fl.gamma - 1.0);
     P.Cv = (float)Cv;

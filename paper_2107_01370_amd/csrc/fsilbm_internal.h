@@ -90,6 +90,7 @@ struct Inst {
     long long n_nodes;
     double shift_ix, shift_iy, shift_jx, shift_jy;
     double dt_d;
+    double gm1_d;             // gamma - 1 in FP64 (the FP64 initialisation and field output)
     float gamma, Cv, Cp, mu, Pr, dt;
     float rho_inf, T_inf, ux_inf, uy_inf;
     float ref[NPOP];          // FP16 shifted storage: reference populations

@@ -1267,7 +1267,7 @@ __global__ void k_init_equilibrium(const Inst *__restrict__ pinst, const double 
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N;
          idx += (long long)gridDim.x * blockDim.x) {
         const double rho = macro[idx], ux = macro[N + idx], uy = macro[2 * N + idx], T = macro[3 * N + idx];
-        const double Cv = 1.0 / ((double)P.gamma - 1.0);
+        const double Cv = 1.0 / P.gm1_d;
         const double E = Cv * T + 0.5 * (ux * ux + uy * uy);
         double feq[9], geq[9];
         equilibria<double>(rho, ux, uy, T, E, feq, geq);
@@ -1297,7 +1297,7 @@ __global__ void k_dump_macro(const Inst *__restrict__ pinst, int side, double *_
         }
         const double ux = jx / rho, uy = jy / rho;
         const double E = 0.5 * G / rho;
-        const double T = (E - 0.5 * (ux * ux + uy * uy)) * ((double)P.gamma - 1.0);
+        const double T = (E - 0.5 * (ux * ux + uy * uy)) * P.gm1_d;
         out[idx] = rho;
         out[N + idx] = ux;
         out[2 * N + idx] = uy;

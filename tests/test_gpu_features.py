@@ -185,7 +185,10 @@ def test_unit_cfl_conserves_mass_momentum_energy():
         r, u, v, T = s.macro()
         E = T / 0.4 + 0.5 * (u * u + v * v)
         q = [r, r * u, r * v, r * E]
-        # momenta are measured against the total mass times the lattice speed
+        # Momenta are measured against the total mass times the lattice speed:
+        # rho u is a difference of populations of size ~rho W_i, so its FP32
+        # rounding at a node is ~2^-24 rho |c| whatever u is (the sum of
+        # |rho u| vanishes for gas at rest, the rounding does not)
         scale = [r.sum(), r.sum(), r.sum(), np.abs(r * E).sum()]
         return np.array([x.sum() for x in q]), np.array(scale)
 
@@ -223,12 +226,15 @@ def strip_case(case, j0, j1):
     return mesh
 
 
-@pytest.mark.parametrize("storage", [0])
+@pytest.mark.parametrize("storage", [0, 1])
 def test_large_workload_one_step_sampled_parity(storage):
     """One step of the 8.4M-node heaving-cylinder workload in the benchmark's
     launch configuration, compared on three bands of rows (wall, middle, far
     field) with the oracle stepping strips of the same mesh that contain each
-    band plus a three-row margin (the reach of one step)."""
+    band plus a three-row margin (the reach of one step).  FP32 storage:
+    populations within 1e-6 of their scale; FP16 shifted storage (the oracle
+    starts from the decoded populations): density and pressure within 2e-3,
+    populations within 1e-3 of their scale."""
     case = synth.large_heave_case(storage=storage)
     sim = Sim(case.mesh, case.fluid, case.bodies)
     sim.init_equilibrium(case.rho, case.ux, case.uy, case.T)
@@ -249,8 +255,16 @@ def test_large_workload_one_step_sampled_parity(storage):
         rows = slice(c0, c1)
         scale_f = np.max(np.abs(ora.f[:, rows]))
         scale_g = np.max(np.abs(ora.g[:, rows]))
-        assert np.max(np.abs(f1[:, j0:j1][:, rows] - ora.f[:, rows])) <= 1e-6 * scale_f, (j0, j1)
-        assert np.max(np.abs(g1[:, j0:j1][:, rows] - ora.g[:, rows])) <= 1e-6 * scale_g, (j0, j1)
+        bound = 1e-6 if storage == 0 else 1e-3
+        assert np.max(np.abs(f1[:, j0:j1][:, rows] - ora.f[:, rows])) <= bound * scale_f, (j0, j1)
+        assert np.max(np.abs(g1[:, j0:j1][:, rows] - ora.g[:, rows])) <= bound * scale_g, (j0, j1)
+        if storage == 1:
+            from oracle import lattice as L
+            r_g, _, _, _, T_g = L.macroscopic(f1[:, j0:j1][:, rows].astype(np.float64),
+                                             g1[:, j0:j1][:, rows].astype(np.float64), case.fluid.gamma)
+            r_o, _, _, _, T_o = L.macroscopic(ora.f[:, rows], ora.g[:, rows], case.fluid.gamma)
+            assert np.max(np.abs(r_g - r_o) / r_o) <= 2e-3
+            assert np.max(np.abs(r_g * T_g - r_o * T_o) / (r_o * T_o)) <= 2e-3
 
 
 def sim_state_at(case, n):

@@ -41,7 +41,10 @@ def test_one_step_parity_periodic_pulse():
     f, g = sim.populations()
     scale = np.max(np.abs(ora.f))
     assert np.max(np.abs(f - ora.f)) <= 1e-6 * scale
-    assert np.max(np.abs(g - ora.g)) <= 1e-6 * np.max(np.abs(ora.g))
+    # every g equilibrium carries the FP32 rounding of the energy moment
+    # G = sum g = 2 rho E (about 1.7 here, ulp 1.2e-7), amplified by omega_1:
+    # the scale of g's one-step error is G, not its largest population
+    assert np.max(np.abs(g - ora.g)) <= 1e-6 * np.max(np.sum(np.abs(ora.g), axis=0))
 
 
 def test_acoustic_pulse_100_steps_rho_p():
