@@ -45,8 +45,8 @@ namespace fsi {
 // of a cell), on meshes with large absolute coordinates and displacements;
 // integer grids stay exact.
 // ---------------------------------------------------------------------------
-constexpr int NMOV = 16;     // moving populations kept in LDS (f_1..8, g_1..8)
-constexpr int NFG = NMOV + 2; // and the rest pair (f_0, g_0) of a tile whose mesh moves
+constexpr int NMOV = 16;     // moving populations in the row-1 export (f_1..8, g_1..8) ...
+constexpr int NFG = NMOV + 2; // ... and the rest pair (f_0, g_0)
 // waves per SIMD the launch bounds ask for (16 waves per CU: two 512-thread or
 // four 256-thread workgroups), which caps the VGPRs at 128
 constexpr int kWavesPerSimd = 4;
@@ -75,7 +75,11 @@ struct K1Smem {
         struct {
             float Qx[G::R3N], Qy[G::R3N], S[G::R3N];
         } q;
-        float FG[NFG][G::R1N];   // f_1..8, g_1..8, then f_0, g_0
+        // post-collision pair (f_k, g_k) of direction k = 0..8 (the rest
+        // pair only on a tile whose mesh moves): one 8-byte read per stencil
+        // tap serves both populations, and the nine taps of a plane lie within
+        // the reach of one base address
+        float2 FG[9][G::R1N];
     } u;
 };
 
@@ -97,6 +101,15 @@ __device__ __forceinline__ Sten forward_sten(int dir) {
     Sten s;
     s.centred = false; s.o1 = dir; s.o2 = 2 * dir; s.w1 = 2.0f * (float)dir; s.w2 = -0.5f * (float)dir;
     return s;
+}
+
+// a cx + b cy + c for lattice velocity components cx, cy in {-1, 0, 1} (known
+// once a loop over the directions is unrolled: no products, no terms for 0)
+__device__ __forceinline__ float affine(int cx, int cy, float a, float b, float c) {
+    float r = c;
+    if (cx != 0) r = cx > 0 ? r + a : r - a;
+    if (cy != 0) r = cy > 0 ? r + b : r - b;
+    return r;
 }
 
 // column across the cut from column i (cut topologies)
@@ -438,11 +451,12 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 const int slot = cut_slot(P, mirror_col(P, P.exits ? ig : wrap(ig, ni)));
                 if (slot >= 0) {
 #pragma unroll
-                    for (int k = 0; k < NMOV; ++k) sm.u.FG[k][e] = P.cutbuf[k * P.cut_n + slot];
-                    if (tile_moves) {
-                        sm.u.FG[NMOV][e] = P.cutbuf[NMOV * P.cut_n + slot];
-                        sm.u.FG[NMOV + 1][e] = P.cutbuf[(NMOV + 1) * P.cut_n + slot];
-                    }
+                    for (int k = 1; k < 9; ++k)
+                        sm.u.FG[k][e] = make_float2(P.cutbuf[(k - 1) * P.cut_n + slot],
+                                                    P.cutbuf[(7 + k) * P.cut_n + slot]);
+                    if (tile_moves)
+                        sm.u.FG[0][e] = make_float2(P.cutbuf[NMOV * P.cut_n + slot],
+                                                    P.cutbuf[(NMOV + 1) * P.cut_n + slot]);
                 }
             }
             continue;
@@ -471,14 +485,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         }
         collide(f, g, Fx, Fy, P, err);
 #pragma unroll
-        for (int k = 1; k < 9; ++k) {
-            sm.u.FG[k - 1][e] = f[k];
-            sm.u.FG[7 + k][e] = g[k];
-        }
-        if (tile_moves) {
-            sm.u.FG[NMOV][e] = f[0];
-            sm.u.FG[NMOV + 1][e] = g[0];
-        }
+        for (int k = 1; k < 9; ++k) sm.u.FG[k][e] = make_float2(f[k], g[k]);
+        if (tile_moves) sm.u.FG[0][e] = make_float2(f[0], g[0]);
         const bool own = u1 >= 1 && u1 <= TILE_X && v1 >= 1 && v1 <= TILE_Y &&
                          i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
         if constexpr (EXPORT) {
@@ -570,10 +578,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             if (k == 0 && !tile_moves) continue;     // stored in phase 3
-            const float cx = (float)CXK(k), cy = (float)CYK(k);
-            const float deta = a21 * cx + a22 * cy + B0y;
-            const float Px = p11 * cx + p12 * cy + P0x;
-            const float Py = p21 * cx + p22 * cy + P0y;
+            const float deta = affine(CXK(k), CYK(k), a21, a22, B0y);
+            const float Px = affine(CXK(k), CYK(k), p11, p12, P0x);
+            const float Py = affine(CXK(k), CYK(k), p21, p22, P0y);
             // quadrant (cell) holding X_dp, decided by which side of the straight
             // cell edges through the node the target lies on (the linear estimate
             // only seeds the choice); on the wall row only cells above exist
@@ -596,13 +603,15 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             const float pu = im * (ejy * Px - ejx * Py), pv = im * (eix * Py - eiy * Px);
             const float tu = im * (ejy * twx - ejx * twy), tv = im * (eix * twy - eiy * twx);
             // u + tu u v = pu, v + tv u v = pv: fixed point from the linear
-            // solution (the twist is small for smooth cells), until an update
-            // falls below 1e-6 of a cell: three rounds, a fourth whose update
-            // is checked, and where it still moved the point (strongly
-            // distorted cells; NaN never settles) up to 20 in all
+            // solution, until an update falls below 1e-6 of a cell.  Each round
+            // multiplies the error by about |t| |(u, v)|, the twist relative to
+            // the cell (1e-3 on smooth meshes, where the third round's update is
+            // at FP32 round-off): two rounds, a third whose update is checked,
+            // and where it still moved the point (strongly distorted cells; NaN
+            // never settles) up to 20 in all
             float uu = pu, vv = pv;
 #pragma unroll
-            for (int it = 0; it < 3; ++it) {
+            for (int it = 0; it < 2; ++it) {
                 const float uv = uu * vv;
                 uu = pu - tu * uv;
                 vv = pv - tv * uv;
@@ -614,7 +623,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 uu = nu;
                 vv = nv;
                 if (__any(moving)) {
-                    for (int it = 4; it < 20 && __any(moving); ++it) {
+#pragma unroll 1
+                    for (int it = 3; it < 20 && __any(moving); ++it) {
                         const float uv2 = uu * vv;
                         const float nu2 = pu - tu * uv2, nv2 = pv - tv * uv2;
                         moving = !(fabsf(nu2 - uu) + fabsf(nv2 - vv) <= 1e-6f);
@@ -641,25 +651,25 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             }
             cfl = fmaxf(cfl, fmaxf(fabsf(a), fabsf(bb)));
             bb -= (float)vc;
-            const float wam = 0.5f * a * (a - 1.0f), wap = 0.5f * a * (a + 1.0f);
-            const float wbm = 0.5f * bb * (bb - 1.0f), wbp = 0.5f * bb * (bb + 1.0f);
+            // weights of the nodes -1 and +1: a (a - 1) / 2 and a (a + 1) / 2
+            const float ha = 0.5f * a, hb = 0.5f * bb;
+            const float wam = fmaf(ha, a, -ha), wap = wam + a;
+            const float wbm = fmaf(hb, bb, -hb), wbp = wbm + bb;
             // tensor-product quadratic Lagrange, as centre + weighted differences
             // so that constants are reproduced exactly
-            float outv[2];
+            const float2 *F = sm.u.FG[k];
+            float2 row[3];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const float *F = k == 0 ? sm.u.FG[NMOV + h] : sm.u.FG[h * 8 + k - 1];
-                float row[3];
-#pragma unroll
-                for (int dj = -1; dj <= 1; ++dj) {
-                    const int cc = c1 + dj * R1X;
-                    const float fc = F[cc];
-                    row[dj + 1] = fc + wam * (F[cc - 1] - fc) + wap * (F[cc + 1] - fc);
-                }
-                outv[h] = row[1] + wbm * (row[0] - row[1]) + wbp * (row[2] - row[1]);
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int cc = c1 + dj * R1X;
+                const float2 fc = F[cc], fm = F[cc - 1], fp = F[cc + 1];
+                row[dj + 1].x = fc.x + wam * (fm.x - fc.x) + wap * (fp.x - fc.x);
+                row[dj + 1].y = fc.y + wam * (fm.y - fc.y) + wap * (fp.y - fc.y);
             }
-            pop_st<STORE>(P, dst, k, off, outv[0]);
-            pop_st<STORE>(P, dst, Q + k, off, outv[1]);
+            const float outf = row[1].x + wbm * (row[0].x - row[1].x) + wbp * (row[2].x - row[1].x);
+            const float outg = row[1].y + wbm * (row[0].y - row[1].y) + wbp * (row[2].y - row[1].y);
+            pop_st<STORE>(P, dst, k, off, outf);
+            pop_st<STORE>(P, dst, Q + k, off, outg);
         }
         // a departure point beyond the node's cells (NaN sets `unsettled`), or
         // a bilinear solve that did not settle in 20 rounds

@@ -14,6 +14,7 @@ from .meshes import (  # noqa: F401
     ogrid_mesh,
     cgrid_mesh,
     twin_mesh,
+    skewed_twisted_mesh,
     geometric_ratio,
 )
 from .configs import (  # noqa: F401

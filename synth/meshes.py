@@ -97,6 +97,31 @@ def periodic_sine_mesh(n: int = 64, amp: float = 0.05, ni: int | None = None,
                     info={"kind": "periodic_sine", "amp": amp})
 
 
+def skewed_twisted_mesh(n: int = 32, skew_deg: float = 60.0, twist: float = 0.3,
+                        wavelength: int = 8) -> MeshSpec:
+    """Doubly periodic mesh of strongly skewed, twisted cells.
+
+    x = i + tan(skew) j + twist sin(k i) sin(k j), y = j, with k = 2 pi /
+    wavelength: the j lines lean by ``skew_deg`` from the normal to the i
+    lines, and each cell is twisted (its fourth corner leaves the
+    parallelogram of the other three) by up to 4 twist sin^2(k / 2) cells
+    (0.15 with the defaults, on the nodes); dx/di stays between 1 - twist k
+    and 1 + twist k.
+    """
+    if n % wavelength:
+        raise ValueError("the wavelength must divide n")
+    sh = float(np.tan(np.radians(skew_deg)))
+    k = 2.0 * np.pi / wavelength
+    jj, ii = np.meshgrid(np.arange(n, dtype=np.float64),
+                         np.arange(n, dtype=np.float64), indexing="ij")
+    X = ii + sh * jj + twist * np.sin(k * ii) * np.sin(k * jj)
+    Y = jj.copy()
+    return MeshSpec(n, n, TOPO_PERIODIC2, X, Y,
+                    shift_i=(float(n), 0.0), shift_j=(sh * n, float(n)),
+                    info={"kind": "skewed_twisted", "skew_deg": skew_deg, "twist": twist,
+                          "wavelength": wavelength})
+
+
 def geometric_ratio(n_cells: int, first: float, span: float) -> float:
     """Ratio q with first * (q**n_cells - 1) / (q - 1) == span (bisection)."""
     if abs(first * n_cells - span) < 1e-12 * span:
