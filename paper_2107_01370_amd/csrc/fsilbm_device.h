@@ -238,6 +238,36 @@ __device__ __forceinline__ float pop_decode(const Inst &P, int q, unsigned raw) 
     }
 }
 
+// A byte offset beyond every buffer resource here (population arrays and X
+// are below 2^31 bytes): loads at it return zeros without touching memory.
+constexpr int kOutside = (int)0x80000000u;
+
+// The undeformed coordinates X as a buffer resource: node idx at byte offset
+// 16 idx, one 16-byte load per node.
+struct XBuf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ XBuf x_buf(const Inst &P) {
+    XBuf b;
+    b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double2 *>(P.X), (short)0,
+                                            (int)(P.n_nodes * 16), kBufDword3);
+    return b;
+}
+
+__device__ __forceinline__ double2 x_ld(const XBuf &b, int off) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, 0);
+    return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+}
+
+// Load of a wave-uniform value through the scalar cache, for device memory
+// that only earlier kernels write (the step counter, body states, coordinates)
+template <class T>
+__device__ __forceinline__ T sload(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 template <int STORE>
 __device__ __forceinline__ void pop_st(const Inst &P, const PopBuf &b, int q, int off, float v) {
     if constexpr (STORE == 0) {

@@ -75,11 +75,12 @@ struct K1Smem {
         struct {
             float Qx[G::R3N], Qy[G::R3N], S[G::R3N];
         } q;
-        // post-collision pair (f_k, g_k) of direction k = 0..8 (the rest
-        // pair only on a tile whose mesh moves): one 8-byte read per stencil
-        // tap serves both populations, and the nine taps of a plane lie within
-        // the reach of one base address
-        float2 FG[9][G::R1N];
+        // post-collision pairs (f_k, g_k), k = 0..8, of each tile+1 node (the
+        // rest pair only on a tile whose mesh moves), node-major: one 8-byte
+        // read per stencil tap serves both populations, and the three taps of
+        // a stencil row, for all nine directions, lie within the reach of one
+        // base address (consecutive lanes 72 bytes apart: no bank conflicts)
+        float2 FG[G::R1N][9];
     } u;
 };
 
@@ -196,6 +197,56 @@ __device__ __forceinline__ float2 pos_diff(const K1Smem<G> &sm, int a, int b, bo
     return d;
 }
 
+// lane mask of a per-lane condition over the active lanes, and a lane's bit of
+// a wave-uniform mask (selects on such bits take the mask as their condition)
+__device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// rigid-map terms of ring level l (0, 1 or 2; wave-uniform) as a body slot
+__device__ __forceinline__ BodySlot level_slot(int l, double h0, double c0, double s0, double h1,
+                                               double c1, double s1, double h2, double c2,
+                                               double s2) {
+    BodySlot b;
+    b.h = l == 0 ? h0 : (l == 1 ? h1 : h2);
+    b.cm1 = l == 0 ? c0 : (l == 1 ? c1 : c2);
+    b.sa = l == 0 ? s0 : (l == 1 ? s1 : s2);
+    b.a = 0.0; b.hd = 0.0; b.ad = 0.0; b.pad0 = 0.0; b.pad1 = 0.0;
+    return b;
+}
+
+// an opaque register copy: the value is computed where it is defined and
+// kept, not re-derived from its inputs at each later use
+__device__ __forceinline__ void keep(float &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void keep(float3 &v) { keep(v.x); keep(v.y); keep(v.z); }
+
+// undeformed position of R3 entry a relative to Xc
+template <class G>
+__device__ __forceinline__ float2 rel_pos(const K1Smem<G> &sm, int a, float2 Xc) {
+    return make_float2(sm.Xu[a].x - Xc.x, sm.Xu[a].y - Xc.y);
+}
+
+// coefficients (of c_x, of c_y, constant) of E x P for a target P = M c + P0
+__device__ __forceinline__ float3 side_coef(float2 E, float m11, float m12, float m21, float m22,
+                                            float P0x, float P0y) {
+    return make_float3(E.x * m21 - E.y * m11, E.x * m22 - E.y * m12, E.x * P0y - E.y * P0x);
+}
+
+// inverse data of a bilinear cell X(u, v) = u e_i + v e_j + u v tw spanned from
+// the node by the edges e_i, e_j with far corner K: 1/(e_i x e_j) and the twist
+// coefficients tu = (tw x e_j)/(e_i x e_j), tv = (e_i x tw)/(e_i x e_j)
+struct CellInv {
+    float im, tu, tv;
+};
+
+__device__ __forceinline__ CellInv cell_inv(float2 ei, float2 ej, float2 K) {
+    const float twx = K.x - ei.x - ej.x, twy = K.y - ei.y - ej.y;
+    CellInv c;
+    c.im = rcpf(ei.x * ej.y - ei.y * ej.x);
+    c.tu = c.im * (twx * ej.y - twy * ej.x);
+    c.tv = c.im * (ei.x * twy - ei.y * twx);
+    return c;
+}
+
 // metric (x_xi, x_eta, y_xi, y_eta) at R3 entry c
 template <class G>
 __device__ __forceinline__ void metric(const K1Smem<G> &sm, int c, const Sten &is, const Sten &js,
@@ -267,30 +318,55 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     const int ti = tile % tiles_i, tj = tile / tiles_i;
     const int i0 = ti * TILE_X, j0 = tj * TILE_Y;
     const int ni = P.ni, nj = P.nj;
-    const long long n = uniform(*P.step);
-    const PopBuf src = pop_buf<STORE>(P, P.pop[n & 1]);
-    const PopBuf dst = pop_buf<STORE>(P, P.pop[(n + 1) & 1]);
+    const int t = threadIdx.x;
+    unsigned err = 0;
+    // The tile's state of the step, requested in one round: the step counter,
+    // the body states of all three ring levels (the pair the step needs is
+    // picked once the counter is in), both population buffers and the FP64
+    // reference node (all written by earlier kernels only, so read through
+    // the scalar cache)
+    const long long iref = (long long)min(j0, nj - 1) * ni + i0;
+    const long long *const stepp = P.step;
+    const BodySlot *const slots = P.slots;
+    const double2 *const Xp = P.X;
+    void *const pop0 = P.pop[0], *const pop1 = P.pop[1];
+    const long long nraw = sload(stepp);
+    // rigid-map terms (h, cos a - 1, sin a) of every body at the three levels
+    double rh[3][NB], rc[3][NB], rs[3][NB];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const BodySlot *sl = slots + l * MAX_BODIES + k;
+            rh[l][k] = sload(&sl->h);
+            rc[l][k] = sload(&sl->cm1);
+            rs[l][k] = sload(&sl->sa);
+        }
+    const double2 Xref = sload(Xp + iref);
+    const Body *const bd = P.body;
+    const long long n = uniform(nraw);
+    const int l0 = (int)(n % 3), l1 = l0 == 2 ? 0 : l0 + 1;
     BodySlot sn[NB], sn1[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        sn[k] = uniform(P.slots[(n % 3) * MAX_BODIES + k]);
-        sn1[k] = uniform(P.slots[((n + 1) % 3) * MAX_BODIES + k]);
+        sn[k] = level_slot(l0, rh[0][k], rc[0][k], rs[0][k], rh[1][k], rc[1][k], rs[1][k],
+                           rh[2][k], rc[2][k], rs[2][k]);
+        sn1[k] = level_slot(l1, rh[0][k], rc[0][k], rs[0][k], rh[1][k], rc[1][k], rs[1][k],
+                            rh[2][k], rc[2][k], rs[2][k]);
     }
+    const PopBuf src = pop_buf<STORE>(P, (n & 1) ? pop1 : pop0);
+    const PopBuf dst = pop_buf<STORE>(P, (n & 1) ? pop0 : pop1);
     const int nbody = min(P.nbody, NB);
-    const int t = threadIdx.x;
-    unsigned err = 0;
 
     // FP64 references of the tile: position and displacement of its first node
-    const long long iref = (long long)min(j0, nj - 1) * ni + i0;
-    const double2 Xref = P.X[iref];
-    const double Xrx = uniform(Xref.x), Xry = uniform(Xref.y);
+    const double Xrx = Xref.x, Xry = Xref.y;
     double Drx = 0.0, Dry = 0.0;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        if (k >= nbody || !P.body[k].present) continue;
+        if (k >= nbody || !bd[k].present) continue;
         const double r = uniform(blend_factor(P, k, iref, Xrx, Xry));
         double dx, dy;
-        rigid_disp(P.body[k], sn[k], Xrx, Xry, dx, dy);
+        rigid_disp(bd[k], sn[k], Xrx, Xry, dx, dy);
         Drx += (1.0 - r) * dx;
         Dry += (1.0 - r) * dy;
     }
@@ -300,25 +376,31 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     int mv = 0;              // a node of this thread's phase-1 items moves
 
     // ---- phase 1: tile+3 --------------------------------------------------
+    // This thread's items (two rounds): entries, node indices and periodic
+    // shifts first, then every load of both items in flight together (a
+    // missing item's loads fall outside their buffers: no traffic, zeros)
+    constexpr int P1 = (R3N + K1_THREADS - 1) / K1_THREADS;
+    static_assert(P1 == R1_ROUNDS, "phase-1 rounds hand populations to phase 3");
+    int p1e[P1], p1idx[P1], p1wi[P1], p1wj[P1];
+    bool p1ok[P1];
 #pragma unroll
-    for (int rd = 0; rd < (R3N + K1_THREADS - 1) / K1_THREADS; ++rd) {
+    for (int rd = 0; rd < P1; ++rd) {
         const int p = rd * K1_THREADS + t;
-        if (p >= R3N) break;
-        const int e = phase1_entry<G>(p);
+        const int e = phase1_entry<G>(min(p, R3N - 1));
         const int u = e % R3X, v = e / R3X;
         int ig = i0 - 3 + u, jg = j0 - 3 + v;
         // wrap into the mesh; a node seen across a periodic seam has its
         // coordinates shifted by the period; on a cut topology node (i, -m) is
         // node (mirror - i, m) across the cut (no shifts on these meshes)
         int wi = 0, wj = 0;
-        bool valid = true;
+        bool valid = p < R3N;
         if (cg) {
             if (jg < 0) { ig = P.mirror - ig; jg = -jg; }
             if (P.exits) {
-                valid = ig >= 0 && ig < ni && jg < nj;
+                valid = valid && ig >= 0 && ig < ni && jg < nj;
             } else {
                 ig = wrap(ig, ni);
-                valid = jg < nj;
+                valid = valid && jg < nj;
             }
         } else {
             if (ig < 0 || ig >= ni) {        // meshes narrower than the halo wrap more than once
@@ -331,29 +413,49 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                     while (jg >= nj) { jg -= nj; ++wj; }
                 }
             } else {
-                valid = (jg >= 0 && jg < nj);
+                valid = valid && (jg >= 0 && jg < nj);
             }
         }
-        if (!valid) {
+        p1e[rd] = e;
+        p1idx[rd] = valid ? jg * ni + ig : 0;
+        p1wi[rd] = wi;
+        p1wj[rd] = wj;
+        p1ok[rd] = valid;
+    }
+    const XBuf xb = x_buf(P);
+    unsigned raw[P1][NPOP];
+    double2 Xr[P1];
+#pragma unroll
+    for (int rd = 0; rd < P1; ++rd) {
+        const int off = p1ok[rd] ? pop_off<STORE>(p1idx[rd]) : kOutside;
+#pragma unroll
+        for (int q = 0; q < NPOP; ++q) raw[rd][q] = pop_ld_raw<STORE>(src, q, off);
+        Xr[rd] = x_ld(xb, p1ok[rd] ? p1idx[rd] * 16 : kOutside);
+    }
+#pragma unroll
+    for (int rd = 0; rd < P1; ++rd) {
+        const int p = rd * K1_THREADS + t;
+        if (p >= R3N) break;
+        const int e = p1e[rd];
+        if (!p1ok[rd]) {
             sm.Xu[e] = make_float2(0.0f, 0.0f);
             sm.dn[e] = make_float2(0.0f, 0.0f); sm.dd[e] = make_float2(0.0f, 0.0f);
             sm.u.q.Qx[e] = 0.0f; sm.u.q.Qy[e] = 0.0f; sm.u.q.S[e] = 0.0f;
             continue;
         }
-        const int idx = jg * ni + ig;
-        const double2 Xr = gld(P.X + idx);
+        const int idx = p1idx[rd];
         // blending factors and displacements from the unshifted node: every
         // body moves the nodes of its own region of influence
         double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
         bool moved = false;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            if (k >= nbody || !P.body[k].present) continue;
-            const double r = blend_factor(P, k, idx, Xr.x, Xr.y);
+            if (k >= nbody || !bd[k].present) continue;
+            const double r = blend_factor(P, k, idx, Xr[rd].x, Xr[rd].y);
             if (r < 1.0) {
                 double d0x, d0y, d1x, d1y;
-                rigid_disp(P.body[k], sn[k], Xr.x, Xr.y, d0x, d0y);
-                rigid_disp(P.body[k], sn1[k], Xr.x, Xr.y, d1x, d1y);
+                rigid_disp(bd[k], sn[k], Xr[rd].x, Xr[rd].y, d0x, d0y);
+                rigid_disp(bd[k], sn1[k], Xr[rd].x, Xr[rd].y, d1x, d1y);
                 const double om = 1.0 - r;
                 a0x += om * d0x;
                 a0y += om * d0y;
@@ -368,7 +470,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             dn = make_float2((float)(a0x - Drx), (float)(a0y - Dry));
             dd = make_float2((float)a1x, (float)a1y);
         }
-        double sx = Xr.x - Xrx, sy = Xr.y - Xry;
+        double sx = Xr[rd].x - Xrx, sy = Xr[rd].y - Xry;
+        const int wi = p1wi[rd], wj = p1wj[rd];
         if (wi | wj) {            // seen across a periodic seam
             sx += (double)wi * P.shift_ix + (double)wj * P.shift_jx;
             sy += (double)wi * P.shift_iy + (double)wj * P.shift_jy;
@@ -377,15 +480,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         sm.dn[e] = dn;
         sm.dd[e] = dd;
         float f[9], g[9];
-        const int off = pop_off<STORE>(idx);
-        // all 18 loads in flight before the first use
-        unsigned raw[NPOP];
-#pragma unroll
-        for (int q = 0; q < NPOP; ++q) raw[q] = pop_ld_raw<STORE>(src, q, off);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_decode<STORE>(P, k, raw[k]);
-            g[k] = pop_decode<STORE>(P, Q + k, raw[Q + k]);
+            f[k] = pop_decode<STORE>(P, k, raw[rd][k]);
+            g[k] = pop_decode<STORE>(P, Q + k, raw[rd][Q + k]);
         }
         if (rd < R1_ROUNDS && p < R1N) {
 #pragma unroll
@@ -452,10 +550,10 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 if (slot >= 0) {
 #pragma unroll
                     for (int k = 1; k < 9; ++k)
-                        sm.u.FG[k][e] = make_float2(P.cutbuf[(k - 1) * P.cut_n + slot],
+                        sm.u.FG[e][k] = make_float2(P.cutbuf[(k - 1) * P.cut_n + slot],
                                                     P.cutbuf[(7 + k) * P.cut_n + slot]);
                     if (tile_moves)
-                        sm.u.FG[0][e] = make_float2(P.cutbuf[NMOV * P.cut_n + slot],
+                        sm.u.FG[e][0] = make_float2(P.cutbuf[NMOV * P.cut_n + slot],
                                                     P.cutbuf[(NMOV + 1) * P.cut_n + slot]);
                 }
             }
@@ -485,8 +583,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         }
         collide(f, g, Fx, Fy, P, err);
 #pragma unroll
-        for (int k = 1; k < 9; ++k) sm.u.FG[k][e] = make_float2(f[k], g[k]);
-        if (tile_moves) sm.u.FG[0][e] = make_float2(f[0], g[0]);
+        for (int k = 1; k < 9; ++k) sm.u.FG[e][k] = make_float2(f[k], g[k]);
+        if (tile_moves) sm.u.FG[e][0] = make_float2(f[0], g[0]);
         const bool own = u1 >= 1 && u1 <= TILE_X && v1 >= 1 && v1 <= TILE_Y &&
                          i0 + u1 - 1 < ni && j0 + v1 - 1 < nj;
         if constexpr (EXPORT) {
@@ -534,27 +632,21 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const float det = J[0] * J[3] - J[2] * J[1];
         if (!(det > 0.0f)) err |= ERR_MESH;
         const float idet = rcpf(det);
-        // undeformed neighbourhood relative to the node: R[dj+1][di+1]
-        float RX[3][3], RY[3][3];
+        // undeformed neighbourhood relative to the node: the four edges out of
+        // it (+i, -i, +j, -j) and the far corners of its four cells
         const float2 Xc = sm.Xu[c3];
-#pragma unroll
-        for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-            for (int di = -1; di <= 1; ++di) {
-                const int ee = c3 + dj * R3X + di;
-                RX[dj + 1][di + 1] = sm.Xu[ee].x - Xc.x;
-                RY[dj + 1][di + 1] = sm.Xu[ee].y - Xc.y;
-            }
+        const float2 Epi = rel_pos(sm, c3 + 1, Xc), Emi = rel_pos(sm, c3 - 1, Xc);
+        const float2 Epj = rel_pos(sm, c3 + R3X, Xc), Emj = rel_pos(sm, c3 - R3X, Xc);
         // centred metric of X (one-sided into the fluid on the wall row)
-        const float BXxi = 0.5f * (RX[1][2] - RX[1][0]), BYxi = 0.5f * (RY[1][2] - RY[1][0]);
+        const float BXxi = 0.5f * (Epi.x - Emi.x), BYxi = 0.5f * (Epi.y - Emi.y);
         float BXeta, BYeta;
         if (wall) {
-            const int e2 = c3 + 2 * R3X;
-            BXeta = 2.0f * RX[2][1] - 0.5f * (sm.Xu[e2].x - Xc.x);
-            BYeta = 2.0f * RY[2][1] - 0.5f * (sm.Xu[e2].y - Xc.y);
+            const float2 E2 = rel_pos(sm, c3 + 2 * R3X, Xc);
+            BXeta = 2.0f * Epj.x - 0.5f * E2.x;
+            BYeta = 2.0f * Epj.y - 0.5f * E2.y;
         } else {
-            BXeta = 0.5f * (RX[2][1] - RX[0][1]);
-            BYeta = 0.5f * (RY[2][1] - RY[0][1]);
+            BXeta = 0.5f * (Epj.x - Emj.x);
+            BYeta = 0.5f * (Epj.y - Emj.y);
         }
         // mesh velocity V_G = (x^{n+1} - x^n)/dt
         const float VGx = sm.dd[c3].x * inv_dt, VGy = sm.dd[c3].y * inv_dt;
@@ -567,6 +659,24 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const float p11 = BXxi * a11 + BXeta * a21, p12 = BXxi * a12 + BXeta * a22;
         const float p21 = BYxi * a11 + BYeta * a21, p22 = BYxi * a12 + BYeta * a22;
         const float P0x = BXxi * B0x + BXeta * B0y, P0y = BYxi * B0x + BYeta * B0y;
+        // Side of each edge E on which the target lies: E x (X_dp - X), also
+        // affine in c_i (the same coefficients serve all nine directions)
+        float3 Spi = side_coef(Epi, p11, p12, p21, p22, P0x, P0y);
+        float3 Smi = side_coef(Emi, p11, p12, p21, p22, P0x, P0y);
+        float3 Spj = side_coef(Epj, p11, p12, p21, p22, P0x, P0y);
+        float3 Smj = side_coef(Emj, p11, p12, p21, p22, P0x, P0y);
+        // formed once here for all directions (not re-derived per direction)
+        keep(Spi); keep(Smi); keep(Spj); keep(Smj);
+        // the four cells round the node as first-order (bilinear) elements
+        // X(u, v) = u e_i + v e_j + u v tw, (u, v) in [0,1]^2, with e_i, e_j
+        // the edges along which the cell extends: 1/(e_i x e_j) and the twist
+        // terms of the inverse map, once per node.  Cell (li, lj) extends to
+        // -i if li and to -j if lj (on the wall row only cells above exist:
+        // the lower pair is formed from placeholder entries and never chosen).
+        const CellInv q00 = cell_inv(Epi, Epj, rel_pos(sm, c3 + R3X + 1, Xc));
+        const CellInv q10 = cell_inv(Emi, Epj, rel_pos(sm, c3 + R3X - 1, Xc));
+        const CellInv q11 = cell_inv(Emi, Emj, rel_pos(sm, c3 - R3X - 1, Xc));
+        const CellInv q01 = cell_inv(Epi, Emj, rel_pos(sm, c3 - R3X + 1, Xc));
         const int vc = wall ? 1 : 0;                   // stencil centre row offset
         const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
         const int off = pop_off<STORE>(jg * ni + ig);
@@ -574,45 +684,44 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         float cfl = 0.0f;          // largest |index offset| of the departure points
         bool unsettled = false;    // a bilinear solve that did not settle
         // the wave holds a wall node (wave-uniform): the wall decision below
-        const bool wall_wave = __any(wall);
+        const uint64_t wall_m = ballot(wall);
+        const bool wall_wave = wall_m != 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             if (k == 0 && !tile_moves) continue;     // stored in phase 3
-            const float deta = affine(CXK(k), CYK(k), a21, a22, B0y);
-            const float Px = affine(CXK(k), CYK(k), p11, p12, P0x);
-            const float Py = affine(CXK(k), CYK(k), p21, p22, P0y);
-            // quadrant (cell) holding X_dp, decided by which side of the straight
-            // cell edges through the node the target lies on (the linear estimate
-            // only seeds the choice); on the wall row only cells above exist
-            const bool ljg = !wall && deta < 0.0f;
-            float djx = ljg ? -RX[0][1] : RX[2][1], djy = ljg ? -RY[0][1] : RY[2][1];
-            bool li = djx * Py - djy * Px > 0.0f;
-            const float dix = li ? -RX[1][0] : RX[1][2], diy = li ? -RY[1][0] : RY[1][2];
-            const bool lj = !wall && (dix * Py - diy * Px < 0.0f);
-            djx = lj ? -RX[0][1] : RX[2][1];
-            djy = lj ? -RY[0][1] : RY[2][1];
-            li = djx * Py - djy * Px > 0.0f;
-            // bilinear first-order element of that cell: X(u,v) = u e_i + v e_j
-            // + u v tw with (u, v) in [0,1]^2
-            const float eix = li ? RX[1][0] : RX[1][2], eiy = li ? RY[1][0] : RY[1][2];
-            const float ejx = lj ? RX[0][1] : RX[2][1], ejy = lj ? RY[0][1] : RY[2][1];
-            const float ckx = lj ? (li ? RX[0][0] : RX[0][2]) : (li ? RX[2][0] : RX[2][2]);
-            const float cky = lj ? (li ? RY[0][0] : RY[0][2]) : (li ? RY[2][0] : RY[2][2]);
-            const float twx = ckx - eix - ejx, twy = cky - eiy - ejy;
-            const float im = rcpf(eix * ejy - eiy * ejx);
-            const float pu = im * (ejy * Px - ejx * Py), pv = im * (eix * Py - eiy * Px);
-            const float tu = im * (ejy * twx - ejx * twy), tv = im * (eix * twy - eiy * twx);
-            // u + tu u v = pu, v + tv u v = pv: fixed point from the linear
-            // solution, until an update falls below 1e-6 of a cell.  Each round
-            // multiplies the error by about |t| |(u, v)|, the twist relative to
-            // the cell (1e-3 on smooth meshes, where the third round's update is
-            // at FP32 round-off): two rounds, a third whose update is checked,
-            // and where it still moved the point (strongly distorted cells; NaN
-            // never settles) up to 20 in all
-            float uu = pu, vv = pv;
-#pragma unroll
-            for (int it = 0; it < 2; ++it) {
-                const float uv = uu * vv;
+            const int cx = CXK(k), cy = CYK(k);
+            const float spi = affine(cx, cy, Spi.x, Spi.y, Spi.z);
+            const float smi = affine(cx, cy, Smi.x, Smi.y, Smi.z);
+            const float spj = affine(cx, cy, Spj.x, Spj.y, Spj.z);
+            const float smj = affine(cx, cy, Smj.x, Smj.y, Smj.z);
+            // The edges split the plane round the node into four sectors, one
+            // per cell; the target lies counter-clockwise of the sector's first
+            // edge and clockwise of its second: (+i, +j) cell 00, (+j, -i) 10,
+            // (-i, -j) 11, (-j, +i) 01.  On the wall row the cell above on the
+            // target's side of the +j edge is taken (a point below the wall
+            // line then has v < 0).
+            // (the sector logic on the wave's lane masks: scalar instructions)
+            const uint64_t sa = ballot(spi > 0.0f), sb = ballot(spj > 0.0f);
+            const uint64_t sc = ballot(smi > 0.0f), sd = ballot(smj > 0.0f);
+            const uint64_t s3 = sc & ~sd;
+            const bool li = lane_bit((wall_m & sb) | (~wall_m & ((sb & ~sc) | s3)));
+            const bool lj = lane_bit(~wall_m & (s3 | (sd & ~sa)));
+            // bilinear inverse in that cell: u + tu u v = pu, v + tv u v = pv
+            // with pu = (X_dp - X) x e_j / (e_i x e_j), pv = e_i x (X_dp - X) / (e_i x e_j)
+            const CellInv cq = lj ? (li ? q11 : q01) : (li ? q10 : q00);
+            const float pu = -cq.im * (lj ? smj : spj);
+            const float pv = cq.im * (li ? smi : spi);
+            const float tu = cq.tu, tv = cq.tv;
+            // Fixed point from the linear solution, until an update falls below
+            // 1e-6 of a cell.  Each round multiplies the error by about
+            // |t| |(u, v)|, the twist relative to the cell (1e-3 on smooth
+            // meshes, where the second round's update is already below the
+            // bound and leaves an error at FP32 round-off): one round, a second
+            // whose update is checked, and where it still moved the point
+            // (strongly distorted cells; NaN never settles) up to 20 in all
+            float uu, vv;
+            {
+                const float uv = pu * pv;
                 uu = pu - tu * uv;
                 vv = pv - tv * uv;
             }
@@ -624,7 +733,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                 vv = nv;
                 if (__any(moving)) {
 #pragma unroll 1
-                    for (int it = 3; it < 20 && __any(moving); ++it) {
+                    for (int it = 2; it < 20 && __any(moving); ++it) {
                         const float uv2 = uu * vv;
                         const float nu2 = pu - tu * uv2, nv2 = pv - tv * uv2;
                         moving = !(fabsf(nu2 - uu) + fabsf(nv2 - vv) <= 1e-6f);
@@ -657,12 +766,11 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             const float wbm = fmaf(hb, bb, -hb), wbp = wbm + bb;
             // tensor-product quadratic Lagrange, as centre + weighted differences
             // so that constants are reproduced exactly
-            const float2 *F = sm.u.FG[k];
             float2 row[3];
 #pragma unroll
             for (int dj = -1; dj <= 1; ++dj) {
-                const int cc = c1 + dj * R1X;
-                const float2 fc = F[cc], fm = F[cc - 1], fp = F[cc + 1];
+                const float2 *F = sm.u.FG[c1 + dj * R1X - 1] + k;
+                const float2 fm = F[0], fc = F[9], fp = F[18];
                 row[dj + 1].x = fc.x + wam * (fm.x - fc.x) + wap * (fp.x - fc.x);
                 row[dj + 1].y = fc.y + wam * (fm.y - fc.y) + wap * (fp.y - fc.y);
             }
