@@ -365,9 +365,10 @@ fsi_status fsi_batch_init_equilibrium(fsi_batch *b, int k, const double *rho, co
  * one per work item; otherwise a persistent grid, rounded to a multiple of 8),
  * `order` of the work items (0: instance after instance, 1: instances by
  * decreasing size) and the tile `shape` of the arrival nodes one workgroup owns
- * (0: 32 x 16, 1: 64 x 8, 2: 16 x 32, 3: 16 x 16 with 256-thread workgroups; a
- * batch holding a C-grid or TWIN instance uses 0).  Invalidates the captured graph.
- * FSI_E_ARG on values out of range. */
+ * (0: 32 x 16, the default, 1: 64 x 8, 2: 16 x 32, 3: 16 x 16 with 256-thread
+ * workgroups).  The shape applies to the instances without a cut; C-grid, TWIN
+ * and two-body instances always run on 32 x 16 tiles, in a launch of their own.
+ * Invalidates the captured graph.  FSI_E_ARG on values out of range. */
 fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape);
 /* Time candidate schedules on the current state and keep the fastest: after
  * warm-up launches, each (shape, order, grid) candidate is timed twice over

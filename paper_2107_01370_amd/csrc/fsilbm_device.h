@@ -207,9 +207,11 @@ template <int STORE>
 __device__ __forceinline__ PopBuf pop_buf(const Inst &P, const void *base) {
     constexpr int B = STORE == 0 ? 4 : 2;
     PopBuf b;
-    b.plane = (int)P.n_nodes * B;
-    b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, NPOP * b.plane,
-                                            kBufDword3);
+    // base and size through readfirstlane: the descriptor is wave-uniform by
+    // construction and stays in scalar registers wherever it is carried
+    b.plane = uniform((int)P.n_nodes * B);
+    void *const ub = reinterpret_cast<void *>(uniform(reinterpret_cast<long long>(base)));
+    b.r = __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, NPOP * b.plane, kBufDword3);
     return b;
 }
 
@@ -250,8 +252,8 @@ struct XBuf {
 
 __device__ __forceinline__ XBuf x_buf(const Inst &P) {
     XBuf b;
-    b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double2 *>(P.X), (short)0,
-                                            (int)(P.n_nodes * 16), kBufDword3);
+    void *const ub = reinterpret_cast<void *>(uniform(reinterpret_cast<long long>(P.X)));
+    b.r = __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, uniform((int)(P.n_nodes * 16)), kBufDword3);
     return b;
 }
 
@@ -266,6 +268,10 @@ __device__ __forceinline__ double2 x_ld(const XBuf &b, int off) {
 template <class T>
 __device__ __forceinline__ T sload(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
+}
+__device__ __forceinline__ double2 sload(const double2 *p) {
+    const double *q = reinterpret_cast<const double *>(p);
+    return make_double2(sload(q), sload(q + 1));
 }
 
 template <int STORE>

@@ -30,6 +30,7 @@ struct fsi_ctx {
     int ni = 0, nj = 0, topo = 0, n_wake = 0, n_wall2 = 0;
     bool has_wall = false;      // O-grid, C-grid or twin O-grid
     bool cut = false;           // C-grid or twin O-grid
+    int shape = 0;              // work-item shape of the fused kernel (fsi::TILE_SHAPES)
     int cut_a = 0, cut_b = 0, mirror = 0;
     int seg_i0[fsi::MAX_BODIES] = {}, seg_n[fsi::MAX_BODIES] = {}, seg_dup[fsi::MAX_BODIES] = {};
     int n_seg = 0;
@@ -877,8 +878,17 @@ void fill_params(fsi_ctx *c) {
     P.relax = c->relax;
     P.storage = fl.storage;
     P.n_elems = c->n_elems;
-    P.tiles_i = (c->ni + fsi::TILE_X - 1) / fsi::TILE_X;
-    P.tiles_j = (c->nj + fsi::TILE_Y - 1) / fsi::TILE_Y;
+    // 64 x 8 tiles for meshes without a cut and with at most one body whose
+    // step streams more than the Infinity Cache holds; 32 x 16 otherwise
+    {
+        const long long pop_bytes = fl.storage == FSI_STORE_FP32 ? 4 : 2;
+        const long long step_bytes = (long long)c->ni * c->nj * (2 * fsi::NPOP * pop_bytes + 16);
+        c->shape = (!c->cut && c->bodies.size() <= 1 && step_bytes > fsi::CACHE_BYTES)
+                       ? fsi::WIDE_SHAPE : 0;
+    }
+    const int sx = fsi::TILE_SHAPES[c->shape][0], sy = fsi::TILE_SHAPES[c->shape][1];
+    P.tiles_i = (c->ni + sx - 1) / sx;
+    P.tiles_j = (c->nj + sy - 1) / sy;
     P.tile_base = 0;
     P.n_nodes = (long long)c->ni * c->nj;
     P.shift_ix = c->shift_i[0];
@@ -1100,7 +1110,7 @@ fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di) {
         HIP_TRY(c, fsi::launch_cut_export(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
     HIP_TRY(c, fsi::launch_collide_stream(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
-                                          (int)c->wk1.size(), st, c->stream, 0, c->cut, 0));
+                                          (int)c->wk1.size(), st, c->stream, 0, c->cut, c->shape));
     if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(di, reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
@@ -1762,7 +1772,7 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                                              0, c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
-                                               c->cut, 0);
+                                               c->cut, c->shape);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
             // phase 0 of the wall kernel (traction only) and of the body kernel
             // recompute the current level without advancing it
@@ -1841,7 +1851,9 @@ struct fsi_batch {
     std::vector<int2> wk0, wk1, wbnd, wwall;
     int grid = 0, order = 0, shape = 0;
     int n_sub = 1;                  // coupling sub-iterations per step (all instances)
-    bool any_cut = false;
+    bool any_cut = false;           // an instance needs the cut build (a cut or two bodies)
+    bool any_plain = false;         // an instance does not
+    int n_cut_items = 0;            // wk1 holds these instances' 32 x 16 tiles first
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     std::string err;
@@ -1870,6 +1882,9 @@ void batch_drop_graph(fsi_batch *b) {
     }
 }
 
+// instances the fused kernel's cut build serves (a cut, or two bodies)
+bool needs_cut_build(const fsi_ctx *c) { return c->cut || c->bodies.size() > 1; }
+
 void batch_lists(fsi_batch *b) {
     const int n = (int)b->ctx.size();
     std::vector<int> ord(n);
@@ -1882,11 +1897,18 @@ void batch_lists(fsi_batch *b) {
     b->wk1.clear();
     b->wbnd.clear();
     b->wwall.clear();
-    const int tx = fsi::TILE_SHAPES[b->shape][0], ty = fsi::TILE_SHAPES[b->shape][1];
-    for (int k : ord) {
-        const fsi_ctx *c = b->ctx[k];
-        const int ntiles = ((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
-        for (int t = 0; t < ntiles; ++t) b->wk1.push_back(make_int2(k, t));
+    // instances that need the cut build run on 32 x 16 tiles (the only shape
+    // of that build), the others on the scheduled shape
+    for (int pass = 0; pass < 2; ++pass) {
+        const int sh = pass == 0 ? 0 : b->shape;
+        const int tx = fsi::TILE_SHAPES[sh][0], ty = fsi::TILE_SHAPES[sh][1];
+        for (int k : ord) {
+            const fsi_ctx *c = b->ctx[k];
+            if (needs_cut_build(c) != (pass == 0)) continue;
+            const int ntiles = ((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
+            for (int t = 0; t < ntiles; ++t) b->wk1.push_back(make_int2(k, t));
+        }
+        if (pass == 0) b->n_cut_items = (int)b->wk1.size();
     }
     // the per-instance lists, re-labelled with the instance index
     for (int k = 0; k < n; ++k) {
@@ -1918,9 +1940,14 @@ fsi_status batch_enqueue_k1(fsi_batch *b) {
     if (!b->wk0.empty())
         BHIP_TRY(b, fsi::launch_cut_export(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk0),
                                            (int)b->wk0.size(), b->storage, b->stream));
-    BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), reinterpret_cast<const int2 *>(b->ws + b->off_wk1),
-                                           (int)b->wk1.size(), b->storage, b->stream, b->grid,
-                                           b->any_cut, b->shape));
+    const int2 *wk1 = reinterpret_cast<const int2 *>(b->ws + b->off_wk1);
+    const int n_plain = (int)b->wk1.size() - b->n_cut_items;
+    if (b->n_cut_items > 0)
+        BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), wk1, b->n_cut_items, b->storage, b->stream,
+                                               b->grid, true, 0));
+    if (n_plain > 0)
+        BHIP_TRY(b, fsi::launch_collide_stream(b_insts(b), wk1 + b->n_cut_items, n_plain, b->storage,
+                                               b->stream, b->grid, false, b->shape));
     return FSI_OK;
 }
 
@@ -1990,18 +2017,24 @@ fsi_status fsi_batch_create(int n, const fsi_fluid_params *fluids, const fsi_mes
         if (k == 0) b->storage = c->fluid.storage;
         if (c->fluid.storage != b->storage) return bfail(b, FSI_E_ARG, "mixed storage precisions");
         if (c->has_wall) b->any_wall = true;
-        if (c->cut) b->any_cut = true;
+        if (needs_cut_build(c)) b->any_cut = true;
+        else b->any_plain = true;
     }
+    // the default of the instances without a cut (those with one always use
+    // 32 x 16): 32 x 16 too; the autotuner picks the fastest
     batch_lists(b);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
     b->off_insts = take(n * sizeof(Inst));
     b->off_wk0 = take(b->wk0.size() * sizeof(int2));
-    size_t max_items = 0;                 // the largest work list over the tile shapes
+    size_t max_items = 0;                 // the largest work list over the shapes
     for (int sh = 0; sh < fsi::N_TILE_SHAPES; ++sh) {
         size_t items = 0;
-        const int tx = fsi::TILE_SHAPES[sh][0], ty = fsi::TILE_SHAPES[sh][1];
-        for (fsi_ctx *c : b->ctx) items += (size_t)((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
+        for (fsi_ctx *c : b->ctx) {
+            const int s2 = needs_cut_build(c) ? 0 : sh;
+            const int tx = fsi::TILE_SHAPES[s2][0], ty = fsi::TILE_SHAPES[s2][1];
+            items += (size_t)((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
+        }
         max_items = std::max(max_items, items);
     }
     b->off_wk1 = take(max_items * sizeof(int2));
@@ -2047,8 +2080,6 @@ fsi_status fsi_batch_set_schedule(fsi_batch *b, int grid, int order, int shape) 
     if (!b) return FSI_E_ARG;
     if (grid < 0 || (order != 0 && order != 1) || shape < 0 || shape >= fsi::N_TILE_SHAPES)
         return bfail(b, FSI_E_ARG, "bad schedule");
-    if (shape != 0 && b->any_cut)
-        return bfail(b, FSI_E_ARG, "a batch with C-grid or twin O-grid instances uses tile shape 0");
     batch_drop_graph(b);
     b->grid = grid;
     if (order != b->order || shape != b->shape) {
@@ -2177,7 +2208,7 @@ fsi_status fsi_batch_autotune(fsi_batch *b, int reps, double best[4]) {
     const int grids[] = {0, 4096, 2048, 1024, 512};
     double best_ms = 1e30;
     int best_grid = 0, best_order = 0, best_shape = 0;
-    const int n_shapes = b->any_cut ? 1 : fsi::N_TILE_SHAPES;
+    const int n_shapes = b->any_plain ? fsi::N_TILE_SHAPES : 1;
     // warm-up launches first (clocks ramp up over the first milliseconds),
     // then each candidate timed twice and its faster pass kept
     {

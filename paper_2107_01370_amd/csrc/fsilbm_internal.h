@@ -12,11 +12,18 @@ constexpr int Q = 9;
 constexpr int NPOP = 18;            // f_0..f_8 then g_0..g_8
 constexpr int TILE_X = 32;          // nodes along i per tile (default shape)
 constexpr int TILE_Y = 16;          // nodes along j per tile (default shape)
-// tile shapes of the fused kernel (the batch autotuner chooses among them;
-// launches over cut topologies use shape 0)
-// (one thread per arrival node: 512-thread workgroups, 256 for 16 x 16)
+// Tile shapes of the fused kernel, one thread per arrival node (512-thread
+// workgroups, 256 for 16 x 16); the batch autotuner chooses among them.
+// Instances with a cut (or two bodies) run the cut-capable build, which exists
+// for shape 0 only.  A single instance without a cut whose step streams more
+// than the 256 MiB Infinity Cache holds (populations read and written, and X)
+// runs on WIDE_SHAPE: each tile row of a population plane is then a DRAM run of
+// 70 consecutive nodes instead of 38; smaller working sets stay in the cache
+// and keep 32 x 16.
 constexpr int N_TILE_SHAPES = 4;
 constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}, {16, 16}};
+constexpr int WIDE_SHAPE = 1;
+constexpr long long CACHE_BYTES = 256ll << 20;
 constexpr int HIST_CAP = 1 << 16;   // force / displacement history records kept
 
 // error bits of the device error word

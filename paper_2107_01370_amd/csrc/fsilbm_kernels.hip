@@ -37,7 +37,7 @@ namespace fsi {
 //                     interpolation from LDS, store f^{n+1}, g^{n+1}
 //
 // Geometry in LDS, all FP32 and relative to FP64 references of the tile (its
-// first node's undeformed position and blended displacement at t^n): the
+// centre node's undeformed position and blended displacement at t^n): the
 // undeformed coordinates X - X_ref (with periodic shifts), the displacement at
 // t^n minus D_ref (dn) and the increment over the step (dd), each formed in
 // FP64 and rounded once.  Coordinate differences inside a tile are then single
@@ -274,6 +274,185 @@ __device__ __forceinline__ void metric(const K1Smem<G> &sm, int c, const Sten &i
     }
 }
 
+// Undeformed neighbourhood, mesh metric at t^{n+1} and mesh velocity of one
+// arrival node, gathered by the caller from its LDS layout.
+struct NodeGeo {
+    float J[4];                       // dx^{n+1}/dxi: x_xi, x_eta, y_xi, y_eta
+    float2 Epi, Emi, Epj, Emj;        // X of the neighbours +i, -i, +j, -j minus X
+    float2 Kpp, Kmp, Kmm, Kpm;        // far corners of the cells (+i+j, -i+j, -i-j, +i-j)
+    float2 E2;                        // X two rows up minus X (wall row only)
+    float VGx, VGy;                   // V_G = (x^{n+1} - x^n)/dt
+};
+
+// ALE semi-Lagrangian streaming of one arrival node (Sec. II.A-B): for each
+// population (the rest pair only if `rest`), the departure point
+// X - dt g^{-1}(c_i - V_G), its cell and local coordinates in the undeformed
+// mesh (bilinear element), and the 9-node quadratic Lagrange interpolation of
+// the post-collision pairs FG (node-major, FGX nodes per row; cn: the node's own
+// entry).  Stores the new populations at byte offset `off` or, DEFER, leaves
+// them in out[] (f_0..8, g_0..8) for the caller to store; on a wall node the
+// missing (miss) and near-line (amb) populations are flagged instead.
+template <int STORE, int FGX, bool DEFER = false>
+__device__ __forceinline__ void node_stream(const Inst &P, const PopBuf &dst, int off,
+                                            const NodeGeo &ng, bool wall, bool rest,
+                                            const float2 (*FG)[9], int cn, float dtf,
+                                            uint16_t &miss, uint16_t &amb, unsigned &err,
+                                            float *out = nullptr) {
+    const float2 Epi = ng.Epi, Emi = ng.Emi, Epj = ng.Epj, Emj = ng.Emj;
+    // centred metric of X (one-sided into the fluid on the wall row)
+    const float BXxi = 0.5f * (Epi.x - Emi.x), BYxi = 0.5f * (Epi.y - Emi.y);
+    float BXeta, BYeta;
+    if (wall) {
+        BXeta = 2.0f * Epj.x - 0.5f * ng.E2.x;
+        BYeta = 2.0f * Epj.y - 0.5f * ng.E2.y;
+    } else {
+        BXeta = 0.5f * (Epj.x - Emj.x);
+        BYeta = 0.5f * (Epj.y - Emj.y);
+    }
+    const float VGx = ng.VGx, VGy = ng.VGy;
+    const float *J = ng.J;
+    const float det = J[0] * J[3] - J[2] * J[1];
+    if (!(det > 0.0f)) err |= ERR_MESH;
+    const float idet = rcpf(det);
+    // linear departure offsets are affine in c_i:
+    //   dxi_i = -dt (dx^{n+1}/dxi)^{-1} (c_i - V_G) = A c_i + B0,
+    // and so is the target X_dp - X = (dX/dxi) dxi_i = (B A) c_i + B B0
+    const float a11 = -dtf * idet * J[3], a12 = dtf * idet * J[1];
+    const float a21 = dtf * idet * J[2], a22 = -dtf * idet * J[0];
+    const float B0x = -(a11 * VGx + a12 * VGy), B0y = -(a21 * VGx + a22 * VGy);
+    const float p11 = BXxi * a11 + BXeta * a21, p12 = BXxi * a12 + BXeta * a22;
+    const float p21 = BYxi * a11 + BYeta * a21, p22 = BYxi * a12 + BYeta * a22;
+    const float P0x = BXxi * B0x + BXeta * B0y, P0y = BYxi * B0x + BYeta * B0y;
+    // Side of each edge E on which the target lies: E x (X_dp - X), also
+    // affine in c_i (the same coefficients serve all nine directions)
+    float3 Spi = side_coef(Epi, p11, p12, p21, p22, P0x, P0y);
+    float3 Smi = side_coef(Emi, p11, p12, p21, p22, P0x, P0y);
+    float3 Spj = side_coef(Epj, p11, p12, p21, p22, P0x, P0y);
+    float3 Smj = side_coef(Emj, p11, p12, p21, p22, P0x, P0y);
+    // formed once here for all directions (not re-derived per direction)
+    keep(Spi); keep(Smi); keep(Spj); keep(Smj);
+    // the four cells round the node as first-order (bilinear) elements
+    // X(u, v) = u e_i + v e_j + u v tw, (u, v) in [0,1]^2, with e_i, e_j
+    // the edges along which the cell extends: 1/(e_i x e_j) and the twist
+    // terms of the inverse map, once per node.  Cell (li, lj) extends to
+    // -i if li and to -j if lj (on the wall row only cells above exist:
+    // the lower pair is formed from placeholder entries and never chosen).
+    const CellInv q00 = cell_inv(Epi, Epj, ng.Kpp);
+    const CellInv q10 = cell_inv(Emi, Epj, ng.Kmp);
+    const CellInv q11 = cell_inv(Emi, Emj, ng.Kmm);
+    const CellInv q01 = cell_inv(Epi, Emj, ng.Kpm);
+    const int vc = wall ? 1 : 0;                   // stencil centre row offset
+    const int c1 = cn + vc * FGX;                  // stencil centre
+    float cfl = 0.0f;          // largest |index offset| of the departure points
+    bool unsettled = false;    // a bilinear solve that did not settle
+    // the wave holds a wall node (wave-uniform): the wall decision below
+    const uint64_t wall_m = ballot(wall);
+    const bool wall_wave = wall_m != 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        if (k == 0 && !rest) continue;           // the caller stores it
+        const int cx = CXK(k), cy = CYK(k);
+        const float spi = affine(cx, cy, Spi.x, Spi.y, Spi.z);
+        const float smi = affine(cx, cy, Smi.x, Smi.y, Smi.z);
+        const float spj = affine(cx, cy, Spj.x, Spj.y, Spj.z);
+        const float smj = affine(cx, cy, Smj.x, Smj.y, Smj.z);
+        // The edges split the plane round the node into four sectors, one
+        // per cell; the target lies counter-clockwise of the sector's first
+        // edge and clockwise of its second: (+i, +j) cell 00, (+j, -i) 10,
+        // (-i, -j) 11, (-j, +i) 01.  On the wall row the cell above on the
+        // target's side of the +j edge is taken (a point below the wall
+        // line then has v < 0).
+        // (the sector logic on the wave's lane masks: scalar instructions)
+        const uint64_t sa = ballot(spi > 0.0f), sb = ballot(spj > 0.0f);
+        const uint64_t sc = ballot(smi > 0.0f), sd = ballot(smj > 0.0f);
+        const uint64_t s3 = sc & ~sd;
+        const bool li = lane_bit((wall_m & sb) | (~wall_m & ((sb & ~sc) | s3)));
+        const bool lj = lane_bit(~wall_m & (s3 | (sd & ~sa)));
+        // bilinear inverse in that cell: u + tu u v = pu, v + tv u v = pv
+        // with pu = (X_dp - X) x e_j / (e_i x e_j), pv = e_i x (X_dp - X) / (e_i x e_j)
+        const CellInv cq = lj ? (li ? q11 : q01) : (li ? q10 : q00);
+        const float pu = -cq.im * (lj ? smj : spj);
+        const float pv = cq.im * (li ? smi : spi);
+        const float tu = cq.tu, tv = cq.tv;
+        // Fixed point from the linear solution, until an update falls below
+        // 1e-6 of a cell.  Each round multiplies the error by about
+        // |t| |(u, v)|, the twist relative to the cell (1e-3 on smooth
+        // meshes, where the second round's update is already below the
+        // bound and leaves an error at FP32 round-off): one round, a second
+        // whose update is checked, and where it still moved the point
+        // (strongly distorted cells; NaN never settles) up to 20 in all
+        float uu, vv;
+        {
+            const float uv = pu * pv;
+            uu = pu - tu * uv;
+            vv = pv - tv * uv;
+        }
+        {
+            const float uv = uu * vv;
+            const float nu = pu - tu * uv, nv = pv - tv * uv;
+            bool moving = !(fabsf(nu - uu) + fabsf(nv - vv) <= 1e-6f);
+            uu = nu;
+            vv = nv;
+            if (__any(moving)) {
+#pragma unroll 1
+                for (int it = 2; it < 20 && __any(moving); ++it) {
+                    const float uv2 = uu * vv;
+                    const float nu2 = pu - tu * uv2, nv2 = pv - tv * uv2;
+                    moving = !(fabsf(nu2 - uu) + fabsf(nv2 - vv) <= 1e-6f);
+                    uu = nu2;
+                    vv = nv2;
+                }
+                unsettled = unsettled || moving;
+            }
+        }
+        const float a = li ? -uu : uu;
+        float bb = lj ? -vv : vv;
+        if (wall_wave) {
+            // a point more than 1e-4 of the cell below the wall line lies
+            // in the body (nearer, it counts as on the line).  Within 1e-5
+            // of that line (several times the FP32 error of vv) the
+            // population is interpolated here and the wall kernel decides
+            // in FP64.
+            const bool near = wall && vv < -0.9e-4f;
+            amb |= near ? (uint16_t)(1u << k) : (uint16_t)0;
+            if (wall && vv < -1.1e-4f) {
+                miss |= (uint16_t)(1u << k);
+                continue;
+            }
+        }
+        cfl = fmaxf(cfl, fmaxf(fabsf(a), fabsf(bb)));
+        bb -= (float)vc;
+        // weights of the nodes -1 and +1: a (a - 1) / 2 and a (a + 1) / 2
+        const float ha = 0.5f * a, hb = 0.5f * bb;
+        const float wam = fmaf(ha, a, -ha), wap = wam + a;
+        const float wbm = fmaf(hb, bb, -hb), wbp = wbm + bb;
+        // tensor-product quadratic Lagrange, as centre + weighted differences
+        // so that constants are reproduced exactly
+        float2 row[3];
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            const float2 *F = FG[c1 + dj * FGX - 1] + k;
+            const float2 fm = F[0], fc = F[9], fp = F[18];
+            row[dj + 1].x = fc.x + wam * (fm.x - fc.x) + wap * (fp.x - fc.x);
+            row[dj + 1].y = fc.y + wam * (fm.y - fc.y) + wap * (fp.y - fc.y);
+        }
+        const float outf = row[1].x + wbm * (row[0].x - row[1].x) + wbp * (row[2].x - row[1].x);
+        const float outg = row[1].y + wbm * (row[0].y - row[1].y) + wbp * (row[2].y - row[1].y);
+        if constexpr (DEFER) {
+            out[k] = outf;
+            out[Q + k] = outg;
+        } else {
+            pop_st<STORE>(P, dst, k, off, outf);
+            pop_st<STORE>(P, dst, Q + k, off, outg);
+        }
+    }
+    // a departure point beyond the node's cells (NaN sets `unsettled`), or
+    // a bilinear solve that did not settle in 20 rounds
+    // a departure point beyond the node's cells (NaN sets `unsettled`), or
+    // a bilinear solve that did not settle in 20 rounds
+    if (!(cfl <= 1.0f + 1e-4f) || unsettled) err |= ERR_CFL;
+}
+
 // Phase-1 work item p -> R3 entry: the tile+1 region first (row-major), then
 // the ring of tile+3 outside it, so that a thread's phase-1 items below R1N
 // are exactly its phase-3 collision nodes (their populations stay in
@@ -325,7 +504,9 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     // picked once the counter is in), both population buffers and the FP64
     // reference node (all written by earlier kernels only, so read through
     // the scalar cache)
-    const long long iref = (long long)min(j0, nj - 1) * ni + i0;
+    // (the tile's centre node: the largest coordinate relative to it, and so
+    // the FP32 rounding of the LDS geometry, is half that from a corner)
+    const long long iref = (long long)min(j0 + TY / 2, nj - 1) * ni + min(i0 + TX / 2, ni - 1);
     const long long *const stepp = P.step;
     const BodySlot *const slots = P.slots;
     const double2 *const Xp = P.X;
@@ -358,7 +539,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     const PopBuf dst = pop_buf<STORE>(P, (n & 1) ? pop0 : pop1);
     const int nbody = min(P.nbody, NB);
 
-    // FP64 references of the tile: position and displacement of its first node
+    // FP64 references of the tile: position and displacement of its centre node
     const double Xrx = Xref.x, Xry = Xref.y;
     double Drx = 0.0, Dry = 0.0;
 #pragma unroll
@@ -626,162 +807,27 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         const int c3 = (vt + 3) * R3X + (ut + 3);
         const bool wall = !P.periodic_j && jg == 0 && wall_col(P, ig, cg);
         const Sten js = jstencil(P, ig, jg, cg);
-        // metric of the mesh at t^{n+1} and its inverse
-        float J[4];
-        metric(sm, c3, centred_sten(), js, true, J);
-        const float det = J[0] * J[3] - J[2] * J[1];
-        if (!(det > 0.0f)) err |= ERR_MESH;
-        const float idet = rcpf(det);
+        NodeGeo ng;
+        // metric of the mesh at t^{n+1}
+        metric(sm, c3, centred_sten(), js, true, ng.J);
         // undeformed neighbourhood relative to the node: the four edges out of
         // it (+i, -i, +j, -j) and the far corners of its four cells
         const float2 Xc = sm.Xu[c3];
-        const float2 Epi = rel_pos(sm, c3 + 1, Xc), Emi = rel_pos(sm, c3 - 1, Xc);
-        const float2 Epj = rel_pos(sm, c3 + R3X, Xc), Emj = rel_pos(sm, c3 - R3X, Xc);
-        // centred metric of X (one-sided into the fluid on the wall row)
-        const float BXxi = 0.5f * (Epi.x - Emi.x), BYxi = 0.5f * (Epi.y - Emi.y);
-        float BXeta, BYeta;
-        if (wall) {
-            const float2 E2 = rel_pos(sm, c3 + 2 * R3X, Xc);
-            BXeta = 2.0f * Epj.x - 0.5f * E2.x;
-            BYeta = 2.0f * Epj.y - 0.5f * E2.y;
-        } else {
-            BXeta = 0.5f * (Epj.x - Emj.x);
-            BYeta = 0.5f * (Epj.y - Emj.y);
-        }
+        ng.Epi = rel_pos(sm, c3 + 1, Xc);
+        ng.Emi = rel_pos(sm, c3 - 1, Xc);
+        ng.Epj = rel_pos(sm, c3 + R3X, Xc);
+        ng.Emj = rel_pos(sm, c3 - R3X, Xc);
+        ng.Kpp = rel_pos(sm, c3 + R3X + 1, Xc);
+        ng.Kmp = rel_pos(sm, c3 + R3X - 1, Xc);
+        ng.Kmm = rel_pos(sm, c3 - R3X - 1, Xc);
+        ng.Kpm = rel_pos(sm, c3 - R3X + 1, Xc);
+        ng.E2 = wall ? rel_pos(sm, c3 + 2 * R3X, Xc) : make_float2(0.0f, 0.0f);
         // mesh velocity V_G = (x^{n+1} - x^n)/dt
-        const float VGx = sm.dd[c3].x * inv_dt, VGy = sm.dd[c3].y * inv_dt;
-        // linear departure offsets are affine in c_i:
-        //   dxi_i = -dt (dx^{n+1}/dxi)^{-1} (c_i - V_G) = A c_i + B0,
-        // and so is the target X_dp - X = (dX/dxi) dxi_i = (B A) c_i + B B0
-        const float a11 = -dtf * idet * J[3], a12 = dtf * idet * J[1];
-        const float a21 = dtf * idet * J[2], a22 = -dtf * idet * J[0];
-        const float B0x = -(a11 * VGx + a12 * VGy), B0y = -(a21 * VGx + a22 * VGy);
-        const float p11 = BXxi * a11 + BXeta * a21, p12 = BXxi * a12 + BXeta * a22;
-        const float p21 = BYxi * a11 + BYeta * a21, p22 = BYxi * a12 + BYeta * a22;
-        const float P0x = BXxi * B0x + BXeta * B0y, P0y = BYxi * B0x + BYeta * B0y;
-        // Side of each edge E on which the target lies: E x (X_dp - X), also
-        // affine in c_i (the same coefficients serve all nine directions)
-        float3 Spi = side_coef(Epi, p11, p12, p21, p22, P0x, P0y);
-        float3 Smi = side_coef(Emi, p11, p12, p21, p22, P0x, P0y);
-        float3 Spj = side_coef(Epj, p11, p12, p21, p22, P0x, P0y);
-        float3 Smj = side_coef(Emj, p11, p12, p21, p22, P0x, P0y);
-        // formed once here for all directions (not re-derived per direction)
-        keep(Spi); keep(Smi); keep(Spj); keep(Smj);
-        // the four cells round the node as first-order (bilinear) elements
-        // X(u, v) = u e_i + v e_j + u v tw, (u, v) in [0,1]^2, with e_i, e_j
-        // the edges along which the cell extends: 1/(e_i x e_j) and the twist
-        // terms of the inverse map, once per node.  Cell (li, lj) extends to
-        // -i if li and to -j if lj (on the wall row only cells above exist:
-        // the lower pair is formed from placeholder entries and never chosen).
-        const CellInv q00 = cell_inv(Epi, Epj, rel_pos(sm, c3 + R3X + 1, Xc));
-        const CellInv q10 = cell_inv(Emi, Epj, rel_pos(sm, c3 + R3X - 1, Xc));
-        const CellInv q11 = cell_inv(Emi, Emj, rel_pos(sm, c3 - R3X - 1, Xc));
-        const CellInv q01 = cell_inv(Epi, Emj, rel_pos(sm, c3 - R3X + 1, Xc));
-        const int vc = wall ? 1 : 0;                   // stencil centre row offset
-        const int c1 = (vt + 1 + vc) * R1X + (ut + 1); // R1 index of the stencil centre
-        const int off = pop_off<STORE>(jg * ni + ig);
+        ng.VGx = sm.dd[c3].x * inv_dt;
+        ng.VGy = sm.dd[c3].y * inv_dt;
         uint16_t miss = 0, amb = 0;
-        float cfl = 0.0f;          // largest |index offset| of the departure points
-        bool unsettled = false;    // a bilinear solve that did not settle
-        // the wave holds a wall node (wave-uniform): the wall decision below
-        const uint64_t wall_m = ballot(wall);
-        const bool wall_wave = wall_m != 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            if (k == 0 && !tile_moves) continue;     // stored in phase 3
-            const int cx = CXK(k), cy = CYK(k);
-            const float spi = affine(cx, cy, Spi.x, Spi.y, Spi.z);
-            const float smi = affine(cx, cy, Smi.x, Smi.y, Smi.z);
-            const float spj = affine(cx, cy, Spj.x, Spj.y, Spj.z);
-            const float smj = affine(cx, cy, Smj.x, Smj.y, Smj.z);
-            // The edges split the plane round the node into four sectors, one
-            // per cell; the target lies counter-clockwise of the sector's first
-            // edge and clockwise of its second: (+i, +j) cell 00, (+j, -i) 10,
-            // (-i, -j) 11, (-j, +i) 01.  On the wall row the cell above on the
-            // target's side of the +j edge is taken (a point below the wall
-            // line then has v < 0).
-            // (the sector logic on the wave's lane masks: scalar instructions)
-            const uint64_t sa = ballot(spi > 0.0f), sb = ballot(spj > 0.0f);
-            const uint64_t sc = ballot(smi > 0.0f), sd = ballot(smj > 0.0f);
-            const uint64_t s3 = sc & ~sd;
-            const bool li = lane_bit((wall_m & sb) | (~wall_m & ((sb & ~sc) | s3)));
-            const bool lj = lane_bit(~wall_m & (s3 | (sd & ~sa)));
-            // bilinear inverse in that cell: u + tu u v = pu, v + tv u v = pv
-            // with pu = (X_dp - X) x e_j / (e_i x e_j), pv = e_i x (X_dp - X) / (e_i x e_j)
-            const CellInv cq = lj ? (li ? q11 : q01) : (li ? q10 : q00);
-            const float pu = -cq.im * (lj ? smj : spj);
-            const float pv = cq.im * (li ? smi : spi);
-            const float tu = cq.tu, tv = cq.tv;
-            // Fixed point from the linear solution, until an update falls below
-            // 1e-6 of a cell.  Each round multiplies the error by about
-            // |t| |(u, v)|, the twist relative to the cell (1e-3 on smooth
-            // meshes, where the second round's update is already below the
-            // bound and leaves an error at FP32 round-off): one round, a second
-            // whose update is checked, and where it still moved the point
-            // (strongly distorted cells; NaN never settles) up to 20 in all
-            float uu, vv;
-            {
-                const float uv = pu * pv;
-                uu = pu - tu * uv;
-                vv = pv - tv * uv;
-            }
-            {
-                const float uv = uu * vv;
-                const float nu = pu - tu * uv, nv = pv - tv * uv;
-                bool moving = !(fabsf(nu - uu) + fabsf(nv - vv) <= 1e-6f);
-                uu = nu;
-                vv = nv;
-                if (__any(moving)) {
-#pragma unroll 1
-                    for (int it = 2; it < 20 && __any(moving); ++it) {
-                        const float uv2 = uu * vv;
-                        const float nu2 = pu - tu * uv2, nv2 = pv - tv * uv2;
-                        moving = !(fabsf(nu2 - uu) + fabsf(nv2 - vv) <= 1e-6f);
-                        uu = nu2;
-                        vv = nv2;
-                    }
-                    unsettled = unsettled || moving;
-                }
-            }
-            const float a = li ? -uu : uu;
-            float bb = lj ? -vv : vv;
-            if (wall_wave) {
-                // a point more than 1e-4 of the cell below the wall line lies
-                // in the body (nearer, it counts as on the line).  Within 1e-5
-                // of that line (several times the FP32 error of vv) the
-                // population is interpolated here and the wall kernel decides
-                // in FP64.
-                const bool near = wall && vv < -0.9e-4f;
-                amb |= near ? (uint16_t)(1u << k) : (uint16_t)0;
-                if (wall && vv < -1.1e-4f) {
-                    miss |= (uint16_t)(1u << k);
-                    continue;
-                }
-            }
-            cfl = fmaxf(cfl, fmaxf(fabsf(a), fabsf(bb)));
-            bb -= (float)vc;
-            // weights of the nodes -1 and +1: a (a - 1) / 2 and a (a + 1) / 2
-            const float ha = 0.5f * a, hb = 0.5f * bb;
-            const float wam = fmaf(ha, a, -ha), wap = wam + a;
-            const float wbm = fmaf(hb, bb, -hb), wbp = wbm + bb;
-            // tensor-product quadratic Lagrange, as centre + weighted differences
-            // so that constants are reproduced exactly
-            float2 row[3];
-#pragma unroll
-            for (int dj = -1; dj <= 1; ++dj) {
-                const float2 *F = sm.u.FG[c1 + dj * R1X - 1] + k;
-                const float2 fm = F[0], fc = F[9], fp = F[18];
-                row[dj + 1].x = fc.x + wam * (fm.x - fc.x) + wap * (fp.x - fc.x);
-                row[dj + 1].y = fc.y + wam * (fm.y - fc.y) + wap * (fp.y - fc.y);
-            }
-            const float outf = row[1].x + wbm * (row[0].x - row[1].x) + wbp * (row[2].x - row[1].x);
-            const float outg = row[1].y + wbm * (row[0].y - row[1].y) + wbp * (row[2].y - row[1].y);
-            pop_st<STORE>(P, dst, k, off, outf);
-            pop_st<STORE>(P, dst, Q + k, off, outg);
-        }
-        // a departure point beyond the node's cells (NaN sets `unsettled`), or
-        // a bilinear solve that did not settle in 20 rounds
-        if (!(cfl <= 1.0f + 1e-4f) || unsettled) err |= ERR_CFL;
+        node_stream<STORE, R1X>(P, dst, pop_off<STORE>(jg * ni + ig), ng, wall, tile_moves,
+                                sm.u.FG, (vt + 1) * R1X + (ut + 1), dtf, miss, amb, err);
         if (wall) {
             P.wall_mask[ig] = miss;
             P.wall_amb[ig] = amb & (uint16_t)~miss;

@@ -384,7 +384,11 @@ def fsi_batch_init_equilibrium(b, k, shape, rho=None, ux=None, uy=None, T=None):
     _bcheck(b, _lib.fsi_batch_init_equilibrium(b, int(k), *[_dptr(a) for a in arrs]))
 
 
-def fsi_batch_set_schedule(b, grid, order, shape=0):
+# default tile shape of a batch's instances (32 x 16; see fsi_batch_set_schedule)
+DEFAULT_SHAPE = 0
+
+
+def fsi_batch_set_schedule(b, grid, order, shape=DEFAULT_SHAPE):
     _bcheck(b, _lib.fsi_batch_set_schedule(b, int(grid), int(order), int(shape)))
 
 
@@ -577,7 +581,7 @@ class Batch:
     def init_equilibrium(self, k, rho=None, ux=None, uy=None, T=None):
         fsi_batch_init_equilibrium(self.b, k, self.shapes[k], rho, ux, uy, T)
 
-    def set_schedule(self, grid, order, shape=0):
+    def set_schedule(self, grid, order, shape=DEFAULT_SHAPE):
         fsi_batch_set_schedule(self.b, grid, order, shape)
 
     def autotune(self, reps=5):

@@ -59,18 +59,23 @@ def _compare(b, cases, ref, nsteps, exact=True):
             assert np.array_equal(b.body_state(k), ref[k][3]), k
 
 
+# the default tile shape of these instances: 32 x 16
+DEFAULT = 0
+
+
 @pytest.mark.parametrize("grid,order,shape", [(0, 0, 0), (0, 1, 0), (16, 0, 0), (64, 1, 0),
                                               (0, 0, 1), (24, 1, 2), (0, 0, 3), (40, 1, 3)])
 def test_batch_equals_instances_run_alone(reference, grid, order, shape):
-    """Bitwise equal to the instances run alone for the default tile shape; the
-    other tile shapes change only which tile computes a halo node's collision
-    (and its FP32 tile-relative rounding), so over 12 steps they agree to 1e-5."""
+    """Bitwise equal to the instances run alone for their default tile shape;
+    the other shapes change only which tile computes a halo node's collision
+    (and its FP32 rounding relative to the tile's reference node), so over 12
+    steps they agree to 1e-5."""
     cases, ref = reference
     b = _batch(cases)
     b.set_schedule(grid, order, shape)
     b.step(12)
     b.synchronize()
-    _compare(b, cases, ref, 12, exact=(shape == 0))
+    _compare(b, cases, ref, 12, exact=(shape == DEFAULT))
     b.close()
 
 
@@ -80,7 +85,7 @@ def test_autotune_keeps_the_state(reference):
     b.step(5)
     grid, order, shape, ms = b.autotune(reps=2)
     assert grid >= 0 and order in (0, 1) and shape in (0, 1, 2, 3) and ms > 0
-    b.set_schedule(0, 0, 0)              # the reference runs used the default shape
+    b.set_schedule(0, 0, DEFAULT)        # the reference runs used the default shape
     kms = b.time_kernels(2)
     assert kms[0] > 0
     b.step(7)
