@@ -54,9 +54,17 @@ def algorithmic_bytes_per_node(storage: int, unstructured: bool = False) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of what a counter summary of the collision-streaming kernel depends
+    on: its source, the shared device and layout headers, and the host routine
+    that orders its tiles (the order decides which halo reads hit in L2)."""
     h = hashlib.sha256()
-    with open(os.path.join(CSRC, "fsilbm_device.h"), "rb") as fh:
-        h.update(fh.read())
+    for name in ("fsilbm_device.h", "fsilbm_internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(CSRC, "fsilbm_host.hip"), encoding="utf-8") as fh:
+        text = fh.read()
+    a = text.index("void append_tiles(")
+    h.update(text[a:text.index("\n}\n", a)].encode())
     with open(os.path.join(CSRC, "fsilbm_kernels.hip"), encoding="utf-8") as fh:
         text = fh.read()
     a = text.index(K1_SECTION[0])

@@ -853,6 +853,18 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
     return FSI_OK;
 }
 
+// The fused kernel's tiles of an ni x nj instance on tile shape `shape`, as
+// (instance, tile) work items in visiting order: column strips of
+// STRIP_NODES, each strip row by row (row order for instances no wider).
+void append_tiles(std::vector<int2> &out, int inst, int ni, int nj, int shape) {
+    const int tx = fsi::TILE_SHAPES[shape][0], ty = fsi::TILE_SHAPES[shape][1];
+    const int tiles_i = (ni + tx - 1) / tx, tiles_j = (nj + ty - 1) / ty;
+    const int w = std::max(1, fsi::STRIP_NODES / tx);
+    for (int s0 = 0; s0 < tiles_i; s0 += w)
+        for (int tj = 0; tj < tiles_j; ++tj)
+            for (int ti = s0; ti < std::min(s0 + w, tiles_i); ++ti) out.push_back(make_int2(inst, tj * tiles_i + ti));
+}
+
 void fill_params(fsi_ctx *c) {
     Inst &P = c->inst;
     const fsi_fluid_params &fl = c->fluid;
@@ -949,9 +961,8 @@ void fill_params(fsi_ctx *c) {
         B.blend_mode = b.blend_mode;
     }
     // work lists
-    const int ntiles = c->topo == FSI_TOPO_Q9 ? 0 : P.tiles_i * P.tiles_j;
-    c->wk1.resize(ntiles);
-    for (int t = 0; t < ntiles; ++t) c->wk1[t] = make_int2(0, t);
+    c->wk1.clear();
+    if (c->topo != FSI_TOPO_Q9) append_tiles(c->wk1, 0, c->ni, c->nj, c->shape);
     c->wbnd.clear();
     c->wwall.clear();
     c->wk0.clear();
@@ -1901,12 +1912,10 @@ void batch_lists(fsi_batch *b) {
     // of that build), the others on the scheduled shape
     for (int pass = 0; pass < 2; ++pass) {
         const int sh = pass == 0 ? 0 : b->shape;
-        const int tx = fsi::TILE_SHAPES[sh][0], ty = fsi::TILE_SHAPES[sh][1];
         for (int k : ord) {
             const fsi_ctx *c = b->ctx[k];
             if (needs_cut_build(c) != (pass == 0)) continue;
-            const int ntiles = ((c->ni + tx - 1) / tx) * ((c->nj + ty - 1) / ty);
-            for (int t = 0; t < ntiles; ++t) b->wk1.push_back(make_int2(k, t));
+            append_tiles(b->wk1, k, c->ni, c->nj, sh);
         }
         if (pass == 0) b->n_cut_items = (int)b->wk1.size();
     }
