@@ -854,12 +854,12 @@ fsi_status validate_and_precompute(fsi_ctx *c) {
 }
 
 // The fused kernel's tiles of an ni x nj instance on tile shape `shape`, as
-// (instance, tile) work items in visiting order: column strips of
-// STRIP_NODES, each strip row by row (row order for instances no wider).
-void append_tiles(std::vector<int2> &out, int inst, int ni, int nj, int shape) {
+// (instance, tile) work items in visiting order: `strips` column strips of
+// equal width (the last one narrower), each strip row by row.
+void append_tiles(std::vector<int2> &out, int inst, int ni, int nj, int shape, int strips) {
     const int tx = fsi::TILE_SHAPES[shape][0], ty = fsi::TILE_SHAPES[shape][1];
     const int tiles_i = (ni + tx - 1) / tx, tiles_j = (nj + ty - 1) / ty;
-    const int w = std::max(1, fsi::STRIP_NODES / tx);
+    const int w = (tiles_i + strips - 1) / strips;
     for (int s0 = 0; s0 < tiles_i; s0 += w)
         for (int tj = 0; tj < tiles_j; ++tj)
             for (int ti = s0; ti < std::min(s0 + w, tiles_i); ++ti) out.push_back(make_int2(inst, tj * tiles_i + ti));
@@ -962,7 +962,7 @@ void fill_params(fsi_ctx *c) {
     }
     // work lists
     c->wk1.clear();
-    if (c->topo != FSI_TOPO_Q9) append_tiles(c->wk1, 0, c->ni, c->nj, c->shape);
+    if (c->topo != FSI_TOPO_Q9) append_tiles(c->wk1, 0, c->ni, c->nj, c->shape, fsi::N_XCD);
     c->wbnd.clear();
     c->wwall.clear();
     c->wk0.clear();
@@ -1909,13 +1909,14 @@ void batch_lists(fsi_batch *b) {
     b->wbnd.clear();
     b->wwall.clear();
     // instances that need the cut build run on 32 x 16 tiles (the only shape
-    // of that build), the others on the scheduled shape
+    // of that build), the others on the scheduled shape; each instance's
+    // tiles in row order (an XCD's run of the list spans several instances)
     for (int pass = 0; pass < 2; ++pass) {
         const int sh = pass == 0 ? 0 : b->shape;
         for (int k : ord) {
             const fsi_ctx *c = b->ctx[k];
             if (needs_cut_build(c) != (pass == 0)) continue;
-            append_tiles(b->wk1, k, c->ni, c->nj, sh);
+            append_tiles(b->wk1, k, c->ni, c->nj, sh, 1);
         }
         if (pass == 0) b->n_cut_items = (int)b->wk1.size();
     }

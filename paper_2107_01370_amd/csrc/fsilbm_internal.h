@@ -24,11 +24,13 @@ constexpr int N_TILE_SHAPES = 4;
 constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}, {16, 16}};
 constexpr int WIDE_SHAPE = 1;
 constexpr long long CACHE_BYTES = 256ll << 20;
-// Visiting order of the fused kernel's tiles: column strips STRIP_NODES wide,
-// each strip row by row from j = 0.  The kernel gives each XCD a contiguous
-// run of the list, so a tile's lower neighbour follows it one strip width of
-// tiles later, while the halo rows they share are still in that XCD's L2.
-constexpr int STRIP_NODES = 512;
+// Visiting order of a single instance's tiles: N_XCD column strips, each
+// strip row by row from j = 0.  The kernel gives each XCD a contiguous run of
+// the list, i.e. one strip: a tile's lower neighbour follows it one strip
+// width of tiles later, while the halo rows they share are still in that
+// XCD's L2, and the XCDs, walking down their strips together, read whole rows
+// of each population plane between them.
+constexpr int N_XCD = 8;
 constexpr int HIST_CAP = 1 << 16;   // force / displacement history records kept
 
 // error bits of the device error word

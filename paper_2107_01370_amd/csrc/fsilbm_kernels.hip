@@ -920,16 +920,18 @@ __device__ __forceinline__ bool wall_block(const Inst &P, int blk, int &seg, int
     return false;
 }
 
-// FP64 bilinear coordinate v (in units of the first cell row, 0 on the wall
-// line) of the departure point of population k at wall node ig, from the
-// undeformed coordinates and the body states of levels n and n+1: the same
-// steps as the collision-streaming kernel's FP32 evaluation (metric of
-// x^{n+1} centred along the wall and one-sided into the fluid, V_G, the
-// linear departure offset mapped to the undeformed frame, bilinear inverse
-// of the first-row cell whose i-range holds the point), in absolute FP64
-// coordinates.  Used for the populations whose FP32 v lies within reach of
-// the line at which a population counts as missing.
-__device__ double wall_departure_v(const Inst &P, int ig, int k, long long n) {
+// FP64 geometry of wall node ig for the departure points of its populations
+// at level n: the metric of x^{n+1} (centred along the wall, one-sided into
+// the fluid) and of X, the mesh velocity, and the edges and twist of the two
+// first-row cells (toward i - 1 and toward i + 1), in absolute FP64
+// coordinates.  The same steps as the collision-streaming kernel's FP32
+// evaluation; formed once per node for all its populations.
+struct WallDepGeo {
+    double idet, j11, j21, j12, j22, b11, b21, b12, b22, vgx, vgy;
+    double ejx, ejy, eix[2], eiy[2], twx[2], twy[2];
+};
+
+__device__ WallDepGeo wall_departure_geo(const Inst &P, int ig, long long n) {
     const int ni = P.ni;
     const int im = P.exits ? ig - 1 : wrap(ig - 1, ni), ip = P.exits ? ig + 1 : wrap(ig + 1, ni);
     const BodySlot *s0 = P.slots + (n % 3) * MAX_BODIES, *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES;
@@ -943,25 +945,45 @@ __device__ double wall_departure_v(const Inst &P, int ig, int k, long long n) {
     node_pos(P, ig, s0, x0n, y0n);
     const double2 X0 = P.X[ig], Xm = P.X[im], Xp = P.X[ip], X1 = P.X[i1], X2 = P.X[i2];
     const double2 Xm1 = P.X[(long long)ni + im], Xp1 = P.X[(long long)ni + ip];
-    // metric of x^{n+1} and of X
-    const double j11 = 0.5 * (xp - xm), j21 = 0.5 * (yp - ym);
-    const double j12 = 2.0 * (x1 - x0) - 0.5 * (x2 - x0), j22 = 2.0 * (y1 - y0) - 0.5 * (y2 - y0);
-    const double b11 = 0.5 * (Xp.x - Xm.x), b21 = 0.5 * (Xp.y - Xm.y);
-    const double b12 = 2.0 * (X1.x - X0.x) - 0.5 * (X2.x - X0.x);
-    const double b22 = 2.0 * (X1.y - X0.y) - 0.5 * (X2.y - X0.y);
-    const double vgx = (x0 - x0n) / P.dt_d, vgy = (y0 - y0n) / P.dt_d;
-    const double wx = (double)CXK(k) - vgx, wy = (double)CYK(k) - vgy;
-    const double idet = 1.0 / (j11 * j22 - j12 * j21);
-    const double ax = -P.dt_d * idet * (j22 * wx - j12 * wy);
-    const double ay = -P.dt_d * idet * (-j21 * wx + j11 * wy);
-    const double px = b11 * ax + b12 * ay, py = b21 * ax + b22 * ay;
-    // the two first-row cells: toward i - 1 and toward i + 1
-    double v_best = 0.0, u_err = 1e300;
+    WallDepGeo w;
+    w.j11 = 0.5 * (xp - xm);
+    w.j21 = 0.5 * (yp - ym);
+    w.j12 = 2.0 * (x1 - x0) - 0.5 * (x2 - x0);
+    w.j22 = 2.0 * (y1 - y0) - 0.5 * (y2 - y0);
+    w.b11 = 0.5 * (Xp.x - Xm.x);
+    w.b21 = 0.5 * (Xp.y - Xm.y);
+    w.b12 = 2.0 * (X1.x - X0.x) - 0.5 * (X2.x - X0.x);
+    w.b22 = 2.0 * (X1.y - X0.y) - 0.5 * (X2.y - X0.y);
+    w.vgx = (x0 - x0n) / P.dt_d;
+    w.vgy = (y0 - y0n) / P.dt_d;
+    w.idet = 1.0 / (w.j11 * w.j22 - w.j12 * w.j21);
+    w.ejx = X1.x - X0.x;
+    w.ejy = X1.y - X0.y;
     for (int side = 0; side < 2; ++side) {
         const double2 Xs = side ? Xp : Xm, Xs1 = side ? Xp1 : Xm1;
-        const double eix = Xs.x - X0.x, eiy = Xs.y - X0.y;
-        const double ejx = X1.x - X0.x, ejy = X1.y - X0.y;
-        const double twx = (Xs1.x - X0.x) - eix - ejx, twy = (Xs1.y - X0.y) - eiy - ejy;
+        w.eix[side] = Xs.x - X0.x;
+        w.eiy[side] = Xs.y - X0.y;
+        w.twx[side] = (Xs1.x - X0.x) - w.eix[side] - w.ejx;
+        w.twy[side] = (Xs1.y - X0.y) - w.eiy[side] - w.ejy;
+    }
+    return w;
+}
+
+// FP64 bilinear coordinate v (in units of the first cell row, 0 on the wall
+// line) of the departure point of population k at the wall node of `w`: the
+// linear departure offset mapped to the undeformed frame, then the bilinear
+// inverse of the first-row cell whose i-range holds the point.  Used for the
+// populations whose FP32 v lies within reach of the line at which a population
+// counts as missing.
+__device__ double wall_departure_v(const Inst &P, const WallDepGeo &w, int k) {
+    const double wx = (double)CXK(k) - w.vgx, wy = (double)CYK(k) - w.vgy;
+    const double ax = -P.dt_d * w.idet * (w.j22 * wx - w.j12 * wy);
+    const double ay = -P.dt_d * w.idet * (-w.j21 * wx + w.j11 * wy);
+    const double px = w.b11 * ax + w.b12 * ay, py = w.b21 * ax + w.b22 * ay;
+    double v_best = 0.0, u_err = 1e300;
+    for (int side = 0; side < 2; ++side) {
+        const double eix = w.eix[side], eiy = w.eiy[side], ejx = w.ejx, ejy = w.ejy;
+        const double twx = w.twx[side], twy = w.twy[side];
         double u = 0.0, v = 0.0;
         for (int it = 0; it < 30; ++it) {   // Newton on u e_i + v e_j + u v tw = p
             const double rx = u * eix + v * ejx + u * v * twx - px;
@@ -1006,27 +1028,41 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
         int seg, i0;
         if (!wall_block(P, blk, seg, i0)) return;
         const int iend = P.seg_i0[seg] + P.seg_n[seg];
-        for (int e = t; e < 3 * (BND + 2); e += BND) {
+        const int ig = i0 + t, igc = min(ig, iend - 1);
+        // this node's inputs, requested with the element's populations: the
+        // rows 0 (previous level), 1 and 2 of columns i0 - 1 .. i0 + BND, every
+        // load of this thread's items in flight together (the lanes past the
+        // end repeat the last item)
+        const uint16_t amb = P.wall_amb[igc];
+        const float2 B = P.wall_B[igc];
+        const double2 X = P.X[igc];
+        constexpr int NS = 3 * (BND + 2), NE = (NS + BND - 1) / BND;
+        float fe[NE][9], ge[NE][9];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = min(t + q * BND, NS - 1);
             const int r = e / (BND + 2), c = e % (BND + 2);
-            const int ig = wrap(i0 - 1 + c, ni);
-            float f[9], g[9];
-            load_node<STORE>(P, r == 0 ? src : dst, (long long)r * ni + ig, f, g);
-            const Moments m = moments(f, g, P.Cv);
-            s_rho[r][c] = m.rho;
-            s_T[r][c] = m.T;
+            load_node<STORE>(P, r == 0 ? src : dst, (long long)r * ni + wrap(i0 - 1 + c, ni), fe[q], ge[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = t + q * BND;
+            if (e < NS) {
+                const Moments m = moments(fe[q], ge[q], P.Cv);
+                s_rho[e / (BND + 2)][e % (BND + 2)] = m.rho;
+                s_T[e / (BND + 2)][e % (BND + 2)] = m.T;
+            }
         }
         __syncthreads();
-        const int ig = i0 + t;
         if (ig >= iend) return;
         // missing or not, decided in FP64 where the FP32 evaluation was too close to call
-        const uint16_t amb = P.wall_amb[ig];
         if (amb) {
             uint16_t miss = P.wall_mask[ig];
+            const WallDepGeo wd = wall_departure_geo(P, ig, n);
             for (int k = 0; k < 9; ++k)
-                if ((amb & (1u << k)) && wall_departure_v(P, ig, k, n) < -1e-4) miss |= (uint16_t)(1u << k);
+                if ((amb & (1u << k)) && wall_departure_v(P, wd, k) < -1e-4) miss |= (uint16_t)(1u << k);
             P.wall_mask[ig] = miss;
         }
-        const float2 B = P.wall_B[ig];
         const float a = B.x, b = B.y - 1.0f;   // offsets from the element centre (i, 1)
         float rho_t = 0.0f, T_t = 0.0f;
 #pragma unroll
@@ -1038,7 +1074,6 @@ __global__ void __launch_bounds__(BND) k_wall_targets(const Inst *__restrict__ i
                 T_t += w * s_T[q + 1][t + 1 + p];
             }
         double vx = 0.0, vy = 0.0;
-        const double2 X = P.X[ig];
         const BodySlot *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES, *s0 = P.slots + (n % 3) * MAX_BODIES;
         for (int k = 0; k < P.nbody; ++k) {
             const double r = blend_factor(P, k, ig, X.x, X.y);
@@ -1145,41 +1180,73 @@ __device__ void grad_fill(const Inst &P, const void *buf, const BodySlot *sL, in
 // P^(1) = sum (f - f^eq) c c; (n ds)_k = 1/2 rot_{+90}(x_{k+1} - x_{k-1}) with
 // k +- 1 the polygon neighbours).  A wall segment that ends on a second copy
 // of its first point (a C-grid's trailing edge, a twin O-grid's junctions):
-// the thread of the first copy also fills the second and stores one merged
+// both copies are filled, and the thread of the first copy stores one merged
 // state in both: population by population the streamed value of the copy that
-// found its departure point, else the mean of the two copies.
+// found its departure point, else the mean of the two copies.  Blocks of two
+// waves: the first takes BND wall nodes; the second, in the block that holds
+// the first copy of a duplicated point, fills the second copy meanwhile.
 template <int STORE>
-__global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict__ insts,
-                                                         const int2 *__restrict__ work, int n_work,
-                                                         int phase) {
+__global__ void __launch_bounds__(2 * BND) k_wall_grad_force(const Inst *__restrict__ insts,
+                                                             const int2 *__restrict__ work, int n_work,
+                                                             int phase) {
+    __shared__ float s_fu[9], s_gu[9];        // second copy, Grad-filled
     if ((int)blockIdx.x >= n_work) return;
     const int2 item = work[blockIdx.x];
     const Inst &P = insts[item.x];
     int seg, c0;
     if (!wall_block(P, item.y, seg, c0)) return;
-    const int ig = c0 + threadIdx.x;
     const int w0 = P.seg_i0[seg], dup = P.seg_dup[seg];
-    if (ig >= w0 + P.seg_n[seg]) return;
     const int te_up = w0 + P.seg_n[seg] - 1;
-    if (dup && ig == te_up) return;           // handled with the first copy
+    const bool pair = phase && dup && c0 == w0;   // the same for the whole block
     const long long n = *P.step;
     const long long L = phase ? n + 1 : n;
     void *buf = P.pop[L & 1];
     const BodySlot *sL = P.slots + (L % 3) * MAX_BODIES;
+    if (threadIdx.x >= BND) {
+        if (pair) {
+            if (threadIdx.x == BND) {
+                float fu[9], gu[9];
+                load_node<STORE>(P, buf, te_up, fu, gu);
+                grad_fill<STORE>(P, buf, sL, te_up, fu, gu);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    s_fu[k] = fu[k];
+                    s_gu[k] = gu[k];
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const int ig = c0 + threadIdx.x;
+    // a node of this block (the second copy goes with the first)
+    const bool live = ig < w0 + P.seg_n[seg] && !(dup && ig == te_up);
+    if (!live && !pair) return;
+    // positions for the traction's normal (polygon neighbours), formed while
+    // the populations load
+    const int fn = P.seg_n[seg] - dup;       // distinct nodes of the polygon
+    const int fm = ig == w0 ? w0 + fn - 1 : ig - 1;
+    const int fp = ig == w0 + fn - 1 ? w0 : ig + 1;
+    double xm = 0.0, ym = 0.0, xp = 0.0, yp = 0.0, x0 = 0.0, y0 = 0.0;
     float f[9], g[9];
-    load_node<STORE>(P, buf, ig, f, g);
+    if (live) {
+        node_pos(P, fm, sL, xm, ym);
+        node_pos(P, fp, sL, xp, yp);
+        node_pos(P, ig, sL, x0, y0);
+        load_node<STORE>(P, buf, ig, f, g);
+        if (phase) grad_fill<STORE>(P, buf, sL, ig, f, g);
+    }
+    if (pair) __syncthreads();
+    if (!live) return;
     if (phase) {
-        grad_fill<STORE>(P, buf, sL, ig, f, g);
-        if (dup && ig == w0) {
-            float fu[9], gu[9];
-            load_node<STORE>(P, buf, te_up, fu, gu);
-            grad_fill<STORE>(P, buf, sL, te_up, fu, gu);
+        if (pair && ig == w0) {
             const unsigned ml = P.wall_mask[ig], mu = P.wall_mask[te_up];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
+                const float fu = s_fu[k], gu = s_gu[k];
                 const bool lo_miss = ml & (1u << k), up_miss = mu & (1u << k);
-                f[k] = (lo_miss && !up_miss) ? fu[k] : ((up_miss && !lo_miss) ? f[k] : 0.5f * (f[k] + fu[k]));
-                g[k] = (lo_miss && !up_miss) ? gu[k] : ((up_miss && !lo_miss) ? g[k] : 0.5f * (g[k] + gu[k]));
+                f[k] = (lo_miss && !up_miss) ? fu : ((up_miss && !lo_miss) ? f[k] : 0.5f * (f[k] + fu));
+                g[k] = (lo_miss && !up_miss) ? gu : ((up_miss && !lo_miss) ? g[k] : 0.5f * (g[k] + gu));
             }
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
@@ -1205,13 +1272,6 @@ __global__ void __launch_bounds__(BND) k_wall_grad_force(const Inst *__restrict_
     }
     // traction of the complete wall node, with the moments formed in FP64
     // from the stored populations; normals from the polygon neighbours
-    const int fn = P.seg_n[seg] - dup;       // distinct nodes of the polygon
-    const int fm = ig == w0 ? w0 + fn - 1 : ig - 1;
-    const int fp = ig == w0 + fn - 1 ? w0 : ig + 1;
-    double xm, ym, xp, yp, x0, y0;
-    node_pos(P, fm, sL, xm, ym);
-    node_pos(P, fp, sL, xp, yp);
-    node_pos(P, ig, sL, x0, y0);
     double sxx, sxy, syy;
     const bool ok = wall_stress(P, f, g, sxx, sxy, syy);
     const double nx = -0.5 * (yp - ym), ny = 0.5 * (xp - xm);
@@ -1254,9 +1314,11 @@ __device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, do
         o.ad = b.pitch_amp * b.pitch_omega * cos(b.pitch_omega * t_next);
     } else if (b.present && (b.dof == DOF_HEAVE || b.dof == DOF_PITCH_PLUNGE)) {
         double y[4] = {s.h, s.a, s.hd, s.ad}, k[4][4];
+#pragma unroll
         for (int st = 0; st < 4; ++st) {
             const double c = st == 0 ? 0.0 : (st == 3 ? dt : 0.5 * dt);
             double z[4];
+#pragma unroll
             for (int q = 0; q < 4; ++q) z[q] = st == 0 ? y[q] : y[q] + c * k[st - 1][q];
             double hdd, add;
             body_accel(b, z[0], z[1], Fy + c / dt * (Fy1 - Fy), M + c / dt * (M1 - M), hdd, add);
@@ -1278,147 +1340,209 @@ __device__ BodySlot body_advance(const Body &b, const BodySlot &s, double Fy, do
 
 constexpr int BODY_THREADS = 1024;
 
+// Row 0 of the cut: the mirror copy of each primary cut node (columns
+// cut_a < c < cut_b) takes its populations (stored words copied as they are),
+// on the body kernel's threads t >= 0 of MIRROR_THREADS.  The primary and
+// mirror columns are distinct, so every thread issues the loads of eight
+// items before any of their stores.
+constexpr int MIRROR_THREADS = BODY_THREADS - 64 * MAX_BODIES;
+
+template <typename W>
+__device__ void mirror_cut_row(const Inst &P, W *buf, int t) {
+    constexpr int U = 8;
+    const int np = P.cut_b - P.cut_a - 1, total = NPOP * np;
+    for (int e0 = t; e0 < total; e0 += U * MIRROR_THREADS) {
+        W v[U];
+        long long to[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = min(e0 + u * MIRROR_THREADS, total - 1);
+            const int q = e / np, c = P.cut_a + 1 + e % np;
+            const int m = P.exits ? P.mirror - c : wrap(P.mirror - c, P.ni);
+            v[u] = buf[(long long)q * P.n_nodes + c];
+            to[u] = (long long)q * P.n_nodes + m;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * MIRROR_THREADS < total) buf[to[u]] = v[u];
+    }
+}
+
 __global__ void __launch_bounds__(BODY_THREADS) k_body(const Inst *__restrict__ insts, int phase) {
     constexpr int NW = BODY_THREADS / 64;
-    __shared__ double sx[NW], sy[NW], sz[NW];
+    __shared__ double sx[MAX_BODIES][NW], sy[MAX_BODIES][NW], sz[MAX_BODIES][NW];
     const Inst &P = insts[blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const long long n = *P.step;
     const long long L = phase ? n + 1 : n;
     // the load of every body: the traction sum over its wall polygon, in a
     // fixed order (per thread a stride of the polygon, loads issued four at a
-    // time; then the lanes of each wave pairwise; then the waves in order)
-    double F[MAX_BODIES][3] = {};
-    for (int k = 0; k < P.n_seg; ++k) {
-        double fx = 0.0, fy = 0.0, mz = 0.0;
-        const int fn = P.seg_n[k] - P.seg_dup[k];
-        const double4 *wf = P.wall_force + P.seg_i0[k];
-        for (int i0 = t; i0 < fn; i0 += 4 * BODY_THREADS) {
-            double4 v[4];
+    // time for every polygon together; then the lanes of each wave pairwise;
+    // then the waves in order)
+    const int nseg = min(P.n_seg, MAX_BODIES);
+    int fn[MAX_BODIES], fn_max = 0;
+    const double4 *wf[MAX_BODIES];
+#pragma unroll
+    for (int k = 0; k < MAX_BODIES; ++k) {
+        fn[k] = k < nseg ? P.seg_n[k] - P.seg_dup[k] : 0;
+        wf[k] = P.wall_force + (k < nseg ? P.seg_i0[k] : 0);
+        fn_max = max(fn_max, fn[k]);
+    }
+    double fx[MAX_BODIES] = {}, fy[MAX_BODIES] = {}, mz[MAX_BODIES] = {};
+    for (int i0 = t; i0 < fn_max; i0 += 4 * BODY_THREADS) {
+        double4 v[MAX_BODIES][4];
+#pragma unroll
+        for (int k = 0; k < MAX_BODIES; ++k)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * BODY_THREADS;
-                v[u] = i < fn ? wf[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+                v[k][u] = i < fn[k] ? wf[k][i] : make_double4(0.0, 0.0, 0.0, 0.0);
             }
+#pragma unroll
+        for (int k = 0; k < MAX_BODIES; ++k)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                fx += v[u].x;
-                fy += v[u].y;
-                mz += v[u].z;
+                fx[k] += v[k][u].x;
+                fy[k] += v[k][u].y;
+                mz[k] += v[k][u].z;
             }
-        }
+    }
+#pragma unroll
+    for (int k = 0; k < MAX_BODIES; ++k) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            fx += __shfl_down(fx, o, 64);
-            fy += __shfl_down(fy, o, 64);
-            mz += __shfl_down(mz, o, 64);
+            fx[k] += __shfl_down(fx[k], o, 64);
+            fy[k] += __shfl_down(fy[k], o, 64);
+            mz[k] += __shfl_down(mz[k], o, 64);
         }
         if (lane == 0) {
-            sx[wv] = fx;
-            sy[wv] = fy;
-            sz[wv] = mz;
+            sx[k][wv] = fx[k];
+            sy[k][wv] = fy[k];
+            sz[k][wv] = mz[k];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    double F[MAX_BODIES][3] = {};
+#pragma unroll
+    for (int k = 0; k < MAX_BODIES; ++k) {
+        if (k >= nseg) break;
         double ax = 0.0, ay = 0.0, az = 0.0;
         for (int w = 0; w < NW; ++w) {
-            ax += sx[w];
-            ay += sy[w];
-            az += sz[w];
+            ax += sx[k][w];
+            ay += sy[k][w];
+            az += sz[k][w];
         }
         F[k][0] = ax;
         F[k][1] = ay;
         F[k][2] = az;
-        __syncthreads();
     }
-    if (phase == 1 && P.cut) {
-        // one state per cut point: the mirror copy of each primary cut node
-        // takes its populations (duplicated wall points are merged at the wall)
-        void *buf = P.pop[(n + 1) & 1];
-        const size_t bpp = P.storage ? 2 : 4;
-        const int np = P.cut_b - P.cut_a - 1;
-        for (int e = t; e < NPOP * np; e += BODY_THREADS) {
-            const int q = e / np, c = P.cut_a + 1 + e % np;
-            const int m = P.exits ? P.mirror - c : wrap(P.mirror - c, P.ni);
-            char *base = static_cast<char *>(buf) + (size_t)q * P.n_nodes * bpp;
-            if (bpp == 4)
-                reinterpret_cast<float *>(base)[m] = reinterpret_cast<const float *>(base)[c];
+    if (wv >= MAX_BODIES) {
+        if (phase == 1 && P.cut) {
+            // one state per cut point: the mirror copy of each primary cut
+            // node takes its populations (duplicated wall points are merged at
+            // the wall); the waves that do not advance a body
+            void *buf = P.pop[(n + 1) & 1];
+            if (P.storage)
+                mirror_cut_row<uint16_t>(P, static_cast<uint16_t *>(buf), t - 64 * MAX_BODIES);
             else
-                reinterpret_cast<uint16_t *>(base)[m] = reinterpret_cast<const uint16_t *>(base)[c];
+                mirror_cut_row<uint32_t>(P, static_cast<uint32_t *>(buf), t - 64 * MAX_BODIES);
         }
+        return;
     }
-    if (t != 0) return;
     const int nrec = P.nbody > 0 ? P.nbody : 1;
     if (phase == 2 || (phase == 1 && P.n_sub > 1)) {
-        // strong coupling: the structure re-solved over step n -> n+1 with the
-        // load varying linearly from F^n (the record of level n) to the load of
-        // the new populations; a sub-iteration relaxes the estimate of level
-        // n+1 towards it, the last one only measures the remaining change
-        const BodySlot *sn = P.slots + (n % 3) * MAX_BODIES;
-        BodySlot *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES;
-        BodySlot target[MAX_BODIES];
-        for (int m = 0; m < nrec; ++m) {
-            if (P.body[m].master != m) continue;
-            double fy0 = 0.0, mz0 = 0.0, fy1 = 0.0, mz1 = 0.0;
-            for (int k = 0; k < nrec; ++k) {
-                if (P.body[k].master != m) continue;
-                const double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(n % HIST_CAP)) * 6;
-                fy0 += rec[2];
-                mz0 += rec[3];
-                fy1 += F[k][1];
-                mz1 += F[k][2];
-            }
-            target[m] = body_advance(P.body[m], sn[m], fy0, mz0, fy1, mz1, (double)(n + 1) * P.dt_d,
-                                     P.dt_d);
-        }
-        for (int k = 0; k < nrec; ++k) {
-            const BodySlot &tg = target[P.body[k].master];
-            const BodySlot &cur = s1[k];
-            P.resid[k] = fmax(fmax(fabs(tg.h - cur.h), fabs(tg.a - cur.a)),
-                              fmax(fabs(tg.hd - cur.hd), fabs(tg.ad - cur.ad)));
-        }
-        if (phase == 2) {
-            for (int m = 0; m < nrec; ++m) {
+        // strong coupling (thread 0): the structure re-solved over step
+        // n -> n+1 with the load varying linearly from F^n (the record of
+        // level n) to the load of the new populations; a sub-iteration relaxes
+        // the estimate of level n+1 towards it, the last one only measures the
+        // remaining change
+        if (t == 0) {
+            const BodySlot *sn = P.slots + (n % 3) * MAX_BODIES;
+            BodySlot *s1 = P.slots + ((n + 1) % 3) * MAX_BODIES;
+            BodySlot target[MAX_BODIES];
+#pragma unroll
+            for (int m = 0; m < MAX_BODIES; ++m) {
+                if (m >= nrec) break;
                 if (P.body[m].master != m) continue;
-                BodySlot o = s1[m];
-                const BodySlot &tg = target[m];
-                const double w = P.relax;
-                o.h += w * (tg.h - o.h);
-                o.a += w * (tg.a - o.a);
-                o.hd += w * (tg.hd - o.hd);
-                o.ad += w * (tg.ad - o.ad);
-                const double sh = sin(0.5 * o.a);
-                o.cm1 = -2.0 * sh * sh;
-                o.sa = sin(o.a);
-                s1[m] = o;
+                double fy0 = 0.0, mz0 = 0.0, fy1 = 0.0, mz1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < MAX_BODIES; ++k) {
+                    if (k >= nrec) break;
+                    if (P.body[k].master != m) continue;
+                    const double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(n % HIST_CAP)) * 6;
+                    fy0 += rec[2];
+                    mz0 += rec[3];
+                    fy1 += F[k][1];
+                    mz1 += F[k][2];
+                }
+                target[m] = body_advance(P.body[m], sn[m], fy0, mz0, fy1, mz1, (double)(n + 1) * P.dt_d,
+                                         P.dt_d);
             }
-            for (int k = 0; k < nrec; ++k)
-                if (P.body[k].master != k) s1[k] = s1[P.body[k].master];
-            return;
+#pragma unroll
+            for (int k = 0; k < MAX_BODIES; ++k) {
+                if (k >= nrec) break;
+                BodySlot tg = target[0];          // target of its master (a register select)
+#pragma unroll
+                for (int q = 1; q < MAX_BODIES; ++q)
+                    if (P.body[k].master == q) tg = target[q];
+                const BodySlot &cur = s1[k];
+                P.resid[k] = fmax(fmax(fabs(tg.h - cur.h), fabs(tg.a - cur.a)),
+                                  fmax(fabs(tg.hd - cur.hd), fabs(tg.ad - cur.ad)));
+            }
+            if (phase == 2) {
+#pragma unroll
+                for (int m = 0; m < MAX_BODIES; ++m) {
+                    if (m >= nrec) break;
+                    if (P.body[m].master != m) continue;
+                    BodySlot o = s1[m];
+                    const BodySlot &tg = target[m];
+                    const double w = P.relax;
+                    o.h += w * (tg.h - o.h);
+                    o.a += w * (tg.a - o.a);
+                    o.hd += w * (tg.hd - o.hd);
+                    o.ad += w * (tg.ad - o.ad);
+                    const double sh = sin(0.5 * o.a);
+                    o.cm1 = -2.0 * sh * sh;
+                    o.sa = sin(o.a);
+                    s1[m] = o;
+                }
+                for (int k = 0; k < nrec; ++k)
+                    if (P.body[k].master != k) s1[k] = s1[P.body[k].master];
+            }
         }
+        if (phase == 2) return;
     }
+    // record k on the first lane of wave k: its history entry, and its state
+    // at the next level, that of its master body, which takes its own load
+    // plus those of the bodies linked to it (frozen over the next step: the
+    // staggered scheme, and the predictor of strong coupling); a linked body
+    // forms its master's state itself, from the same inputs
+    if (lane != 0 || wv >= nrec) return;
+    const int k = wv;
     const BodySlot *cur = P.slots + (L % 3) * MAX_BODIES;
     BodySlot *nxt = P.slots + ((L + 1) % 3) * MAX_BODIES;
-    for (int k = 0; k < nrec; ++k) {
-        double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(L % HIST_CAP)) * 6;
-        rec[0] = (double)L; rec[1] = F[k][0]; rec[2] = F[k][1]; rec[3] = F[k][2];
-        rec[4] = cur[k].h; rec[5] = cur[k].a;
-    }
-    // each body with an equation of its own takes its load plus those of the
-    // bodies linked to it (frozen over the next step: the staggered scheme,
-    // and the predictor of strong coupling); linked bodies then take its state
-    for (int m = 0; m < nrec; ++m) {
-        if (P.body[m].master != m) continue;
-        double fy = 0.0, mz = 0.0;
-        for (int k = 0; k < nrec; ++k) {
-            if (P.body[k].master != m) continue;
-            fy += F[k][1];
-            mz += F[k][2];
+    double Fk[3] = {F[0][0], F[0][1], F[0][2]};
+#pragma unroll
+    for (int q = 1; q < MAX_BODIES; ++q)
+        if (k == q) {
+            Fk[0] = F[q][0];
+            Fk[1] = F[q][1];
+            Fk[2] = F[q][2];
         }
-        nxt[m] = body_advance(P.body[m], cur[m], fy, mz, fy, mz, (double)(L + 1) * P.dt_d, P.dt_d);
+    double *rec = P.history + ((size_t)k * HIST_CAP + (size_t)(L % HIST_CAP)) * 6;
+    rec[0] = (double)L; rec[1] = Fk[0]; rec[2] = Fk[1]; rec[3] = Fk[2];
+    rec[4] = cur[k].h; rec[5] = cur[k].a;
+    const int m = P.body[k].master;
+    double fys = 0.0, mzs = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAX_BODIES; ++j) {
+        if (j >= nrec) break;
+        if (P.body[j].master != m) continue;
+        fys += F[j][1];
+        mzs += F[j][2];
     }
-    for (int k = 0; k < nrec; ++k)
-        if (P.body[k].master != k) nxt[k] = nxt[P.body[k].master];
-    if (phase) *P.step = n + 1;
+    nxt[k] = body_advance(P.body[m], cur[m], fys, mzs, fys, mzs, (double)(L + 1) * P.dt_d, P.dt_d);
+    if (phase && k == 0) *P.step = n + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1540,7 +1664,7 @@ hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, 
 
 hipError_t launch_wall_grad_force(const Inst *insts, const int2 *work, int n_work, int storage,
                                   int phase, hipStream_t s) {
-    FSI_DISPATCH(storage, k_wall_grad_force, dim3(n_work), dim3(BND), s, insts, work, n_work, phase);
+    FSI_DISPATCH(storage, k_wall_grad_force, dim3(n_work), dim3(2 * BND), s, insts, work, n_work, phase);
     return hipGetLastError();
 }
 
