@@ -1189,8 +1189,9 @@ fsi_status sync_check(fsi_ctx *c) {
 
 void drop_graph(fsi_ctx *c) {
     for (int q = 0; q < 2; ++q) {
-        if (c->graph_exec[q]) hipGraphExecDestroy(c->graph_exec[q]);
-        if (c->graph[q]) hipGraphDestroy(c->graph[q]);
+        // teardown: a failure here leaves nothing to undo
+        if (c->graph_exec[q]) (void)hipGraphExecDestroy(c->graph_exec[q]);
+        if (c->graph[q]) (void)hipGraphDestroy(c->graph[q]);
         c->graph_exec[q] = nullptr;
         c->graph[q] = nullptr;
     }
@@ -1208,7 +1209,7 @@ fsi_status capture_steps(fsi_ctx *c, int q, int count) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != FSI_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);   // the capture's own error is reported
         return st;
     }
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
@@ -1886,8 +1887,8 @@ fsi_status bfail(fsi_batch *b, fsi_status st, const std::string &msg) {
 
 void batch_drop_graph(fsi_batch *b) {
     for (int q = 0; q < 2; ++q) {
-        if (b->graph_exec[q]) hipGraphExecDestroy(b->graph_exec[q]);
-        if (b->graph[q]) hipGraphDestroy(b->graph[q]);
+        if (b->graph_exec[q]) (void)hipGraphExecDestroy(b->graph_exec[q]);
+        if (b->graph[q]) (void)hipGraphDestroy(b->graph[q]);
         b->graph_exec[q] = nullptr;
         b->graph[q] = nullptr;
     }
@@ -2121,7 +2122,7 @@ fsi_status fsi_batch_step(fsi_batch *b, int nsteps) {
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(b->stream, &g);
             if (st != FSI_OK) {
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 return st;
             }
             if (e != hipSuccess) return bfail(b, FSI_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
