@@ -274,14 +274,21 @@ __device__ __forceinline__ double2 sload(const double2 *p) {
     return make_double2(sload(q), sload(q + 1));
 }
 
-template <int STORE>
+// Store of a new population.  NT: non-temporal (cache policy bit 1), for a
+// step that streams more than the Infinity Cache holds: the new populations
+// are then read again only from HBM, and keeping them out of the caches leaves
+// L2 to the halo rows that later tiles of the same XCD read.  (Smaller working
+// sets stay in the Infinity Cache from one step to the next, which
+// non-temporal stores would forgo.)
+template <int STORE, bool NT = false>
 __device__ __forceinline__ void pop_st(const Inst &P, const PopBuf &b, int q, int off, float v) {
+    constexpr int aux = NT ? 2 : 0;
     if constexpr (STORE == 0) {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), b.r, off, q * b.plane, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), b.r, off, q * b.plane, aux);
     } else {
         const unsigned short h =
             __half_as_ushort(__float2half_rn((v - P.ref[q]) * P.inv_scale[q >= Q]));
-        __builtin_amdgcn_raw_buffer_store_b16(h, b.r, off, q * b.plane, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(h, b.r, off, q * b.plane, aux);
     }
 }
 

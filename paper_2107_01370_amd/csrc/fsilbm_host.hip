@@ -31,6 +31,7 @@ struct fsi_ctx {
     bool has_wall = false;      // O-grid, C-grid or twin O-grid
     bool cut = false;           // C-grid or twin O-grid
     int shape = 0;              // work-item shape of the fused kernel (fsi::TILE_SHAPES)
+    bool stream_out = false;    // the step streams more than the Infinity Cache holds
     int cut_a = 0, cut_b = 0, mirror = 0;
     int seg_i0[fsi::MAX_BODIES] = {}, seg_n[fsi::MAX_BODIES] = {}, seg_dup[fsi::MAX_BODIES] = {};
     int n_seg = 0;
@@ -890,13 +891,14 @@ void fill_params(fsi_ctx *c) {
     P.relax = c->relax;
     P.storage = fl.storage;
     P.n_elems = c->n_elems;
-    // 64 x 8 tiles for meshes without a cut and with at most one body whose
-    // step streams more than the Infinity Cache holds; 32 x 16 otherwise
+    // 64 x 8 tiles and non-temporal population stores for meshes without a
+    // cut and with at most one body whose step streams more than the
+    // Infinity Cache holds; 32 x 16 otherwise
     {
         const long long pop_bytes = fl.storage == FSI_STORE_FP32 ? 4 : 2;
         const long long step_bytes = (long long)c->ni * c->nj * (2 * fsi::NPOP * pop_bytes + 16);
-        c->shape = (!c->cut && c->bodies.size() <= 1 && step_bytes > fsi::CACHE_BYTES)
-                       ? fsi::WIDE_SHAPE : 0;
+        c->stream_out = !c->cut && c->bodies.size() <= 1 && step_bytes > fsi::CACHE_BYTES;
+        c->shape = c->stream_out ? fsi::WIDE_SHAPE : 0;
     }
     const int sx = fsi::TILE_SHAPES[c->shape][0], sy = fsi::TILE_SHAPES[c->shape][1];
     P.tiles_i = (c->ni + sx - 1) / sx;
@@ -1121,7 +1123,8 @@ fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di) {
         HIP_TRY(c, fsi::launch_cut_export(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
     HIP_TRY(c, fsi::launch_collide_stream(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
-                                          (int)c->wk1.size(), st, c->stream, 0, c->cut, c->shape));
+                                          (int)c->wk1.size(), st, c->stream, 0, c->cut, c->shape,
+                                          c->stream_out));
     if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(di, reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
@@ -1784,7 +1787,7 @@ fsi_status fsi_time_kernels(fsi_ctx *c, int reps, double out_ms[4]) {
                                              0, c->stream);
             else if (which == 0)
                 e = fsi::launch_collide_stream(d_inst(c), wk1, (int)c->wk1.size(), stg, c->stream, 0,
-                                               c->cut, c->shape);
+                                               c->cut, c->shape, c->stream_out);
             if (which == 1) e = fsi::launch_wall_targets(d_inst(c), wbnd, (int)c->wbnd.size(), stg, c->stream);
             // phase 0 of the wall kernel (traction only) and of the body kernel
             // recompute the current level without advancing it

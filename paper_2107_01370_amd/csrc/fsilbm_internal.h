@@ -17,9 +17,9 @@ constexpr int TILE_Y = 16;          // nodes along j per tile (default shape)
 // Instances with a cut (or two bodies) run the cut-capable build, which exists
 // for shape 0 only.  A single instance without a cut whose step streams more
 // than the 256 MiB Infinity Cache holds (populations read and written, and X)
-// runs on WIDE_SHAPE: each tile row of a population plane is then a DRAM run of
-// 70 consecutive nodes instead of 38; smaller working sets stay in the cache
-// and keep 32 x 16.
+// runs on WIDE_SHAPE, with non-temporal population stores: each tile row of a
+// population plane is then a DRAM run of 70 consecutive nodes instead of 38;
+// smaller working sets stay in the cache and keep 32 x 16.
 constexpr int N_TILE_SHAPES = 4;
 constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{32, 16}, {64, 8}, {16, 32}, {16, 16}};
 constexpr int WIDE_SHAPE = 1;
@@ -197,8 +197,10 @@ __host__ __device__ inline size_t u_block_lds_bytes(int hmax, int lemax, int eu1
 
 namespace fsi {
 // host-callable launchers (fsilbm_kernels.hip)
+// stream_out: the launch's step streams more than the Infinity Cache holds
+// (non-temporal population stores; the wide shape only)
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid, bool cut, int shape);
+                                 hipStream_t s, int grid, bool cut, int shape, bool stream_out = false);
 hipError_t launch_cut_export(const Inst *insts, const int2 *work, int n_work, int storage,
                              hipStream_t s);
 hipError_t launch_wall_targets(const Inst *insts, const int2 *work, int n_work, int storage,

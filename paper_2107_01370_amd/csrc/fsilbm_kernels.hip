@@ -292,7 +292,7 @@ struct NodeGeo {
 // entry).  Stores the new populations at byte offset `off` or, DEFER, leaves
 // them in out[] (f_0..8, g_0..8) for the caller to store; on a wall node the
 // missing (miss) and near-line (amb) populations are flagged instead.
-template <int STORE, int FGX, bool DEFER = false>
+template <int STORE, int FGX, bool DEFER = false, bool NT = false>
 __device__ __forceinline__ void node_stream(const Inst &P, const PopBuf &dst, int off,
                                             const NodeGeo &ng, bool wall, bool rest,
                                             const float2 (*FG)[9], int cn, float dtf,
@@ -442,8 +442,8 @@ __device__ __forceinline__ void node_stream(const Inst &P, const PopBuf &dst, in
             out[k] = outf;
             out[Q + k] = outg;
         } else {
-            pop_st<STORE>(P, dst, k, off, outf);
-            pop_st<STORE>(P, dst, Q + k, off, outg);
+            pop_st<STORE, NT>(P, dst, k, off, outf);
+            pop_st<STORE, NT>(P, dst, Q + k, off, outg);
         }
     }
     // a departure point beyond the node's cells (NaN sets `unsettled`), or
@@ -479,7 +479,7 @@ __device__ __forceinline__ int phase1_entry(int p) {
 // them as their row -1 instead of colliding there: a node below the cut seen
 // from the other side has different neighbours on row 0 next to the trailing
 // edge, so its collision cannot be formed in the mirrored frame).
-template <int STORE, bool EXPORT, bool CG, int TX, int TY>
+template <int STORE, bool EXPORT, bool CG, int TX, int TY, bool NT = false>
 __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
                                                     const Inst *__restrict__ insts, const int2 item) {
     using G = Geo<TX, TY>;
@@ -784,8 +784,8 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
             // no node of the tile moves: the rest populations stay at their
             // node (a node of the tile itself: 0 <= ig < ni)
             const int off = pop_off<STORE>(jg * ni + ig);
-            pop_st<STORE>(P, dst, 0, off, f[0]);
-            pop_st<STORE>(P, dst, Q, off, g[0]);
+            pop_st<STORE, NT>(P, dst, 0, off, f[0]);
+            pop_st<STORE, NT>(P, dst, Q, off, g[0]);
         }
     }
     if constexpr (EXPORT) {
@@ -826,7 +826,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         ng.VGx = sm.dd[c3].x * inv_dt;
         ng.VGy = sm.dd[c3].y * inv_dt;
         uint16_t miss = 0, amb = 0;
-        node_stream<STORE, R1X>(P, dst, pop_off<STORE>(jg * ni + ig), ng, wall, tile_moves,
+        node_stream<STORE, R1X, false, NT>(P, dst, pop_off<STORE>(jg * ni + ig), ng, wall, tile_moves,
                                 sm.u.FG, (vt + 1) * R1X + (ut + 1), dtf, miss, amb, err);
         if (wall) {
             P.wall_mask[ig] = miss;
@@ -836,7 +836,7 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
     if (err) atomicOr(P.err, err);
 }
 
-template <int STORE, bool CG, int TX, int TY>
+template <int STORE, bool CG, int TX, int TY, bool NT = false>
 __global__ void __launch_bounds__(TX * TY, kWavesPerSimd)
 k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, int n_work) {
     __shared__ K1Smem<Geo<TX, TY>> sm;
@@ -850,7 +850,7 @@ k_collide_stream(const Inst *__restrict__ insts, const int2 *__restrict__ work, 
         const int wk = xcd * per_xcd + li;
         if (wk >= n_work) break;
         const int2 w = work[wk];
-        collide_stream_tile<STORE, false, CG, TX, TY>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
+        collide_stream_tile<STORE, false, CG, TX, TY, NT>(sm, insts, make_int2(uniform(w.x), uniform(w.y)));
         __syncthreads();                      // LDS is reused by the next item
     }
 }
@@ -1619,7 +1619,7 @@ __global__ void k_encode(const Inst *__restrict__ pinst, int side, int q0, const
 // host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work, int storage,
-                                 hipStream_t s, int grid, bool cut, int shape) {
+                                 hipStream_t s, int grid, bool cut, int shape, bool stream_out) {
     // one workgroup per item unless a smaller (persistent) grid is requested;
     // always a multiple of the XCD count
     const int all = ((n_work + 7) / 8) * 8;
@@ -1633,7 +1633,16 @@ hipError_t launch_collide_stream(const Inst *insts, const int2 *work, int n_work
     const dim3 G(g), B(TILE_SHAPES[shape][0] * TILE_SHAPES[shape][1]);
 #define FSI_K1(ST, CGV, TXV, TYV) \
     hipLaunchKernelGGL((k_collide_stream<ST, CGV, TXV, TYV>), G, B, 0, s, insts, work, n_work)
-    if (storage == 0) {
+    // non-temporal population stores: built for the wide shape only, the
+    // shape of the instances whose step streams more than the cache holds
+    static_assert(TILE_SHAPES[WIDE_SHAPE][0] == 64 && TILE_SHAPES[WIDE_SHAPE][1] == 8, "wide shape");
+    const bool nt = stream_out && !cut && shape == WIDE_SHAPE;
+    if (nt) {
+        if (storage == 0)
+            hipLaunchKernelGGL((k_collide_stream<0, false, 64, 8, true>), G, B, 0, s, insts, work, n_work);
+        else
+            hipLaunchKernelGGL((k_collide_stream<1, false, 64, 8, true>), G, B, 0, s, insts, work, n_work);
+    } else if (storage == 0) {
         if (cut) FSI_K1(0, true, TILE_X, TILE_Y);
         else if (shape == 1) FSI_K1(0, false, 64, 8);
         else if (shape == 2) FSI_K1(0, false, 16, 32);
