@@ -62,6 +62,18 @@ struct fsi_ctx {
     std::vector<double> ecoord;     // [E][9][2] unwrapped FP64 element node coordinates
     bool q9_moving = false;         // a moving body on a Q9 mesh
     hipStream_t stream = nullptr;
+    // O-grids: wk1s holds the fused kernel's tiles with a row the boundary
+    // kernels read or write (rows 0..2, nj-2, nj-1) first (n_near of them),
+    // then the others, which do not depend on the boundary kernels of their
+    // step: fsi_step runs them on a second stream beside the near tiles and
+    // the boundary kernels, joining before the body kernel (which advances the
+    // step).  wk1 keeps every tile in one list for single launches.
+    std::vector<int2> wk1s;
+    size_t off_wk1s = 0;
+    int n_near = 0;
+    bool split = false;
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int n_sub = 1;                  // coupling sub-iterations per step
     double relax = 1.0;
     Inst inst{};
@@ -965,6 +977,24 @@ void fill_params(fsi_ctx *c) {
     // work lists
     c->wk1.clear();
     if (c->topo != FSI_TOPO_Q9) append_tiles(c->wk1, 0, c->ni, c->nj, c->shape, fsi::N_XCD);
+    c->wk1s.clear();
+    c->n_near = 0;
+    if (c->topo == FSI_TOPO_OGRID) {
+        const int ty = fsi::TILE_SHAPES[c->shape][1];
+        auto near = [&](int2 w) {
+            const int j0 = (w.y / P.tiles_i) * ty, j1 = std::min(j0 + ty, c->nj) - 1;
+            return j0 <= 2 || j1 >= c->nj - 2;
+        };
+        for (int2 w : c->wk1)
+            if (near(w)) c->wk1s.push_back(w);
+        c->n_near = (int)c->wk1s.size();
+        // the interior tiles in strip order: one strip per XCD as before
+        std::vector<int2> far;
+        append_tiles(far, 0, c->ni, c->nj, c->shape, fsi::N_XCD);
+        for (int2 w : far)
+            if (!near(w)) c->wk1s.push_back(w);
+    }
+    c->split = c->n_near > 0 && c->n_near < (int)c->wk1s.size();
     c->wbnd.clear();
     c->wwall.clear();
     c->wk0.clear();
@@ -1015,6 +1045,7 @@ void layout(fsi_ctx *c) {
     c->off_inst = take(sizeof(Inst));
     c->off_inst_na = take(sizeof(Inst));
     c->off_wk1 = take(c->wk1.size() * sizeof(int2));
+    c->off_wk1s = take(c->wk1s.size() * sizeof(int2));
     c->off_wbnd = take(c->wbnd.size() * sizeof(int2));
     c->off_wwall = take(c->wwall.size() * sizeof(int2));
     c->off_wk0 = take(c->wk0.size() * sizeof(int2));
@@ -1101,7 +1132,7 @@ fsi_status upload_inst_na(fsi_ctx *c) {
 // one pass of the fluid part of a step on the populations of level n: the cut
 // pre-pass, collision-streaming, wall targets and far field, Grad populations
 // and traction of the new level
-fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di) {
+fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di, bool split) {
     const int st = c->fluid.storage;
     if (c->topo == FSI_TOPO_Q9) {
         // a moving body: the mesh of both levels and the departure points on
@@ -1122,9 +1153,22 @@ fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di) {
     if (!c->wk0.empty())
         HIP_TRY(c, fsi::launch_cut_export(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk0),
                                           (int)c->wk0.size(), st, c->stream));
-    HIP_TRY(c, fsi::launch_collide_stream(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
-                                          (int)c->wk1.size(), st, c->stream, 0, c->cut, c->shape,
-                                          c->stream_out));
+    if (split) {
+        // interior tiles on the second stream, from the state the step starts
+        // from; they read and write nothing the boundary kernels touch
+        const int2 *wk1s = reinterpret_cast<const int2 *>(c->ws + c->off_wk1s);
+        HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+        HIP_TRY(c, fsi::launch_collide_stream(di, wk1s + c->n_near, (int)c->wk1s.size() - c->n_near, st,
+                                              c->stream2, 0, c->cut, c->shape, c->stream_out));
+        HIP_TRY(c, hipEventRecord(c->ev_join, c->stream2));
+        HIP_TRY(c, fsi::launch_collide_stream(di, wk1s, c->n_near, st, c->stream, 0, c->cut, c->shape,
+                                              c->stream_out));
+    } else {
+        HIP_TRY(c, fsi::launch_collide_stream(di, reinterpret_cast<const int2 *>(c->ws + c->off_wk1),
+                                              (int)c->wk1.size(), st, c->stream, 0, c->cut, c->shape,
+                                              c->stream_out));
+    }
     if (c->has_wall) {
         HIP_TRY(c, fsi::launch_wall_targets(di, reinterpret_cast<const int2 *>(c->ws + c->off_wbnd),
                                             (int)c->wbnd.size(), st, c->stream));
@@ -1132,13 +1176,15 @@ fsi_status enqueue_fluid(fsi_ctx *c, const Inst *di) {
                                                reinterpret_cast<const int2 *>(c->ws + c->off_wwall),
                                                (int)c->wwall.size(), st, 1, c->stream));
     }
+    // every tile has read the step counter before the body kernel advances it
+    if (split) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     return FSI_OK;
 }
 
 // one coupled step: with strong coupling, n_sub - 1 sub-iterations (fluid pass,
 // structure re-solved and relaxed) before the final pass, which the body
 // kernel accepts and records
-fsi_status enqueue_step(fsi_ctx *c, const Inst *di = nullptr) {
+fsi_status enqueue_step(fsi_ctx *c, const Inst *di = nullptr, bool split = false) {
     if (!di) di = d_inst(c);
     // without a body there is nothing to iterate on: one pass
     const int passes = c->bodies.empty() ? 1 : c->n_sub;
@@ -1152,7 +1198,7 @@ fsi_status enqueue_step(fsi_ctx *c, const Inst *di = nullptr) {
                 HIP_TRY(c, fsi::launch_unstructured_boundary(d_inst(c), (int)c->qw_nodes.size(), 0,
                                                              c->fluid.storage, 0, c->stream));
         }
-        fsi_status st = enqueue_fluid(c, di);
+        fsi_status st = enqueue_fluid(c, di, split);
         if (st != FSI_OK) return st;
         HIP_TRY(c, fsi::launch_body(di, 1, k + 1 < passes ? 2 : 1, c->stream));
     }
@@ -1208,7 +1254,7 @@ constexpr int kGraphSteps = 16;
 fsi_status capture_steps(fsi_ctx *c, int q, int count) {
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     fsi_status st = FSI_OK;
-    for (int k = 0; k < count && st == FSI_OK; ++k) st = enqueue_step(c);
+    for (int k = 0; k < count && st == FSI_OK; ++k) st = enqueue_step(c, nullptr, c->stream2 != nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != FSI_OK) {
@@ -1442,6 +1488,9 @@ fsi_status fsi_bind_workspace(fsi_ctx *c, void *dev_ptr, size_t bytes) {
     }
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk1, c->wk1.data(), c->wk1.size() * sizeof(int2),
                               hipMemcpyHostToDevice, c->stream));
+    if (!c->wk1s.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_wk1s, c->wk1s.data(), c->wk1s.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
     {
         fsi_status sn = upload_inst_na(c);
@@ -1517,6 +1566,12 @@ fsi_status fsi_step(fsi_ctx *c, int nsteps) {
             if (st != FSI_OK) return st;
         }
     } else {
+        if (c->split && !c->stream2) {
+            // the second stream of the split step (default priority), once
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        }
         const int nlong = nsteps / kGraphSteps, nshort = nsteps % kGraphSteps;
         if (nlong && !c->graph_exec[1]) {
             st = capture_steps(c, 1, kGraphSteps);
@@ -1847,6 +1902,12 @@ void fsi_destroy(fsi_ctx *c) {
     // the caller frees the workspace after this returns: drain queued work first
     if (c->ws) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
+    if (c->stream2) {
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamDestroy(c->stream2);
+        (void)hipEventDestroy(c->ev_fork);
+        (void)hipEventDestroy(c->ev_join);
+    }
     delete c;
 }
 
