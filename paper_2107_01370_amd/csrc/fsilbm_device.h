@@ -240,6 +240,18 @@ __device__ __forceinline__ float pop_decode(const Inst &P, int q, unsigned raw) 
     }
 }
 
+// The same decoding with the scale held in a vector register (`scale`, the
+// value of P.scale[q >= Q]): the fused multiply-add then takes only one
+// scalar operand (the reference) and needs no copy of it per population.
+template <int STORE>
+__device__ __forceinline__ float pop_decode(const Inst &P, int q, unsigned raw, float scale) {
+    if constexpr (STORE == 0) {
+        return __uint_as_float(raw);
+    } else {
+        return fmaf(scale, __half2float(__ushort_as_half((unsigned short)raw)), P.ref[q]);
+    }
+}
+
 // A byte offset beyond every buffer resource here (population arrays and X
 // are below 2^31 bytes): loads at it return zeros without touching memory.
 constexpr int kOutside = (int)0x80000000u;

@@ -661,10 +661,17 @@ __device__ __forceinline__ void collide_stream_tile(K1Smem<Geo<TX, TY>> &sm,
         sm.dn[e] = dn;
         sm.dd[e] = dd;
         float f[9], g[9];
+        float sf = 0.0f, sg = 0.0f;            // FP16 scales of f and g, in vector registers
+        if constexpr (STORE != 0) {
+            sf = P.scale[0];
+            sg = P.scale[1];
+            keep(sf);
+            keep(sg);
+        }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = pop_decode<STORE>(P, k, raw[rd][k]);
-            g[k] = pop_decode<STORE>(P, Q + k, raw[rd][Q + k]);
+            f[k] = pop_decode<STORE>(P, k, raw[rd][k], sf);
+            g[k] = pop_decode<STORE>(P, Q + k, raw[rd][Q + k], sg);
         }
         if (rd < R1_ROUNDS && p < R1N) {
 #pragma unroll

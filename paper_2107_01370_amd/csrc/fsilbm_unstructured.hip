@@ -745,9 +745,10 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         const long long r = n0 + threadIdx.x;
         if (r < P.n_nodes) {
             const BodySlot s1 = P.slots[((n + 1) % 3) * MAX_BODIES];
-            u_relocate_dirs(P, r, 1, s1, P.body[0], err);
+            // the rest direction with 1-4, then 5-8: two calls, each with its
+            // loads in two memory round trips
+            u_relocate_dirs<U_REL_DIRS + 1>(P, r, 0, s1, P.body[0], err);
             u_relocate_dirs(P, r, 1 + U_REL_DIRS, s1, P.body[0], err);
-            u_relocate_dirs<1>(P, r, 0, s1, P.body[0], err);
         }
     }
     for (int h = threadIdx.x; h < nh; h += U_BLOCK) {
