@@ -65,9 +65,10 @@ struct fsi_ctx {
     // O-grids: wk1s holds the fused kernel's tiles with a row the boundary
     // kernels read or write (rows 0..2, nj-2, nj-1) first (n_near of them),
     // then the others, which do not depend on the boundary kernels of their
-    // step: fsi_step runs them on a second stream beside the near tiles and
-    // the boundary kernels, joining before the body kernel (which advances the
-    // step).  wk1 keeps every tile in one list for single launches.
+    // step: on a large instance fsi_step runs them on a second stream beside
+    // the near tiles and the boundary kernels, joining before the body kernel
+    // (which advances the step).  wk1 keeps every tile in one list for single
+    // launches.
     std::vector<int2> wk1s;
     size_t off_wk1s = 0;
     int n_near = 0;
@@ -994,7 +995,11 @@ void fill_params(fsi_ctx *c) {
         for (int2 w : far)
             if (!near(w)) c->wk1s.push_back(w);
     }
-    c->split = c->n_near > 0 && c->n_near < (int)c->wk1s.size();
+    // only where the interior launch outlasts the boundary kernels by far: a
+    // step that streams more than the Infinity Cache (a small instance's step
+    // is launch-bound, and the second stream's fork and join would cost more
+    // than the overlap saves)
+    c->split = c->stream_out && c->n_near > 0 && c->n_near < (int)c->wk1s.size();
     c->wbnd.clear();
     c->wwall.clear();
     c->wk0.clear();

@@ -55,6 +55,19 @@ def test_noalloc_step_equals_step_on_two_calls_second_smaller():
     assert np.max(np.abs(a2[2][:, 2])) > 0
 
 
+def test_noalloc_step_equals_the_split_step():
+    """An O-grid whose step streams more than the Infinity Cache (1024 x 2048
+    nodes, 64 x 8 tiles): fsi_step runs its interior tiles on a second stream
+    beside the near-boundary tiles and the boundary kernels; the
+    no-allocation step launches every tile at once.  The two must agree
+    exactly."""
+    c = synth.large_heave_case(n_r=1024, n_theta=2048, D=800.0)
+    assert c.mesh.ni * c.mesh.nj * 160 > 256 << 20
+    r, a = run_both(c, 24)
+    check_equal(r, a)
+    assert np.max(np.abs(a[2][:, 2])) > 0
+
+
 def test_noalloc_step_refuses_what_it_cannot_hold():
     from paper_2107_01370_amd.fsilbm import FsiError, Simulation
     from synth.unstructured import q9_heave_case
