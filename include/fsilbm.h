@@ -33,7 +33,11 @@
  *     much, fsi_bind_workspace() lends it to the context.  It must stay
  *     allocated, and untouched by the caller, until fsi_destroy().
  *   - Host outputs go to caller-owned buffers of the stated sizes.
- *   - All device work is enqueued on the HIP stream given at creation.
+ *   - All device work is enqueued on the HIP stream given at creation
+ *     (fsi_step() on an O-grid whose step streams more than the 256 MiB
+ *     Infinity Cache also forks a second stream of the library's own inside
+ *     its captured graph and joins it back before the step ends, so work the
+ *     caller enqueues after it on the given stream still follows the step).
  *     fsi_step() is asynchronous; a sticky device error word is checked and
  *     reported by the next synchronising call (fsi_synchronize, fsi_get_*,
  *     fsi_dump_macro, fsi_save).
@@ -249,14 +253,20 @@ fsi_status fsi_init_equilibrium(fsi_ctx *ctx, const double *rho, const double *u
 
 /* Enqueue `nsteps` coupled steps: replays of a captured HIP graph of 16
  * steps, then of one step for the remainder (both captured on first use).
- * Asynchronous. */
+ * Asynchronous.  On an O-grid whose step streams more than the Infinity
+ * Cache, the first call creates a second stream (and two events) of the
+ * context's own, released by fsi_destroy(): each captured step runs the
+ * interior tiles of the collision-streaming kernel there, beside the tiles
+ * next to the wall and the far field and the boundary kernels, and joins
+ * before the body kernel (results are those of one launch, bit for bit). */
 fsi_status fsi_step(fsi_ctx *ctx, int nsteps);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same `nsteps` coupled
  * steps as fsi_step, with the same kernels and results, but launched directly
  * on the context's stream (no graph is captured or instantiated, nothing is
- * allocated, no memset is recorded).  The step's temporaries (wall masks,
+ * allocated, no memset is recorded, no second stream: the collision-streaming
+ * kernel runs as one launch over every tile).  The step's temporaries (wall masks,
  * wall targets, per-node tractions, cut staging: 52 * ni bytes plus
  * 72 * (cut columns) bytes, each part rounded up to 256) live in a static
  * device array of 1 MiB per GPU, held until the process ends, instead of the
