@@ -16,6 +16,11 @@ fields and steps the plain FP64 oracle (oracle/solver.py):
       0.2 D at frequency 0.2 U / D) at 64 x 128 nodes with D = 50, 1000 steps:
       the body history and the density and temperature fields after 100 and
       after 1000 steps.
+  cylinder_viv_256x512_200
+      the single-cylinder workload at its own size (256 x 512 O-grid, first
+      cell 0.005 D, far field 30 D, blending to 10 D; Ma 0.2, Re 100, m* 10,
+      U* 5), 200 steps: the body history and the density and temperature of
+      the rows listed in ROWS (wall, near-wall and every octave outward).
 
 Usage: python tests/golden/make_oracle_runs.py [name ...]
 """
@@ -50,10 +55,19 @@ def heave_case():
     return c
 
 
+def cylinder_viv_256x512_case():
+    c = synth.cylinder_viv_case()
+    c.steps = 200
+    return c
+
+
 RUNS = {
     "force_protocol_cylinder_64x128": force_protocol_case,
     "heave_cylinder_64x128_1000": heave_case,
+    "cylinder_viv_256x512_200": cylinder_viv_256x512_case,
 }
+# runs whose final fields are stored on these rows (radial index j) only
+ROWS = {"cylinder_viv_256x512_200": (0, 1, 2, 4, 8, 16, 32, 64, 128, 192, 255)}
 # intermediate levels whose fields are stored too
 SNAPSHOTS = {"heave_cylinder_64x128_1000": (100,)}
 
@@ -88,6 +102,10 @@ def main(names):
                 "dt": c.fluid.dt, "snapshots": sorted(snaps),
                 "info": {k: float(v) for k, v in c.info.items() if isinstance(v, (int, float))}}
         extra = {}
+        if name in ROWS:
+            rows = np.array(ROWS[name], dtype=np.int64)
+            rho, T = rho[rows], T[rows]
+            extra["rows"] = rows
         for m, (r, t) in snaps.items():
             extra[f"rho_{m}"] = r
             extra[f"T_{m}"] = t

@@ -207,6 +207,45 @@ def test_force_protocol_2000_steps():
     assert errs["rho"] <= 1e-4 and errs["p"] <= 1e-4, errs
 
 
+# ---- the single-cylinder workload at its own size --------------------------------
+
+def test_cylinder_viv_256x512_200_steps():
+    """The single-cylinder workload at its own size (256 x 512 O-grid, first
+    cell 0.005 D, far field 30 D; Ma 0.2, Re 100, m* 10, U* 5), 200 steps from
+    the oracle's own equilibria, against the stored FP64 oracle run: drag
+    within 1e-4 of its peak, lift within 1e-4 of the peak force, density and
+    pressure on the stored rows (the wall, the near-wall rows and every
+    octave outward) within 1e-5 (measured 6.4e-7, 5.0e-7, 6.8e-6 and
+    8.9e-6)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_oracle_runs",
+                                                  os.path.join(GOLDEN, "make_oracle_runs.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    name = "cylinder_viv_256x512_200"
+    gold = load_golden(name)
+    c = mk.RUNS[name]()
+    n = int(json.loads(str(gold["meta"]))["steps"])
+    s = Sim(c.mesh, c.fluid, c.bodies)
+    s.init_equilibrium(c.rho, c.ux, c.uy, c.T)
+    print(f"cylinder VIV: {c.mesh.ni}x{c.mesh.nj}, {n} steps", flush=True)
+    s.step(n)
+    hist = s.forces(0, n)
+    ho = gold["history"]
+    assert np.array_equal(hist[:, 0], ho[:, 0])
+    errs = {}
+    errs["drag"] = float(np.max(np.abs(hist[:, 1] - ho[:, 1])) / np.max(np.abs(ho[:, 1])))
+    errs["lift_vs_peak_force"] = float(np.max(np.abs(hist[:, 2] - ho[:, 2])) /
+                                       np.max(np.hypot(ho[:, 1], ho[:, 2])))
+    rows = gold["rows"]
+    rho, ux, uy, T = s.macro()
+    errs["rho"] = rel(rho[rows], gold["rho"])
+    errs["p"] = rel(rho[rows] * T[rows], gold["rho"] * gold["T"])
+    print("cylinder VIV errors:", errs, flush=True)
+    assert errs["drag"] <= 1e-4 and errs["lift_vs_peak_force"] <= 1e-4, errs
+    assert errs["rho"] <= 1e-5 and errs["p"] <= 1e-5, errs
+
+
 # ---- FP32 and FP16 storage over a long horizon ---------------------------------
 
 @pytest.mark.parametrize("storage,bound100,bound1000", [(0, 1e-5, 1e-4), (1, 4e-3, 1.5e-2)])
