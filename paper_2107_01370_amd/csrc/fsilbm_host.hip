@@ -903,6 +903,11 @@ void fill_params(fsi_ctx *c) {
     P.n_sub = c->n_sub;
     P.relax = c->relax;
     P.storage = fl.storage;
+    // 9-node meshes: non-temporal population stores where the step streams
+    // more than the Infinity Cache holds (populations read and written, and
+    // about 40 B per node of coordinates and departure data)
+    P.stream_out = c->topo == FSI_TOPO_Q9 &&
+                   (long long)c->ni * (2 * fsi::NPOP * (fl.storage == FSI_STORE_FP32 ? 4 : 2) + 40) > fsi::CACHE_BYTES;
     P.n_elems = c->n_elems;
     // 64 x 8 tiles and non-temporal population stores for meshes without a
     // cut and with at most one body whose step streams more than the

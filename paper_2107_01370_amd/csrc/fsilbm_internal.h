@@ -87,6 +87,8 @@ struct Inst {
     int ni, nj;
     int periodic_j;           // 1: PERIODIC2 topology, 0: wall + far field
     int storage;              // 0 FP32, 1 FP16 shifted
+    int stream_out;           // 9-node meshes: the step streams more than the Infinity
+                              // Cache holds (non-temporal population stores)
     int tiles_i, tiles_j;     // tile grid of the fused kernel
     int tile_base;            // first work item of this instance in a batch
     int cut;                  // C-grid or twin O-grid: row 0 has a cut

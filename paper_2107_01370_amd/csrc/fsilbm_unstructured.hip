@@ -728,6 +728,18 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
     const long long n = *P.step;
     const void *src = P.pop[n & 1];
     void *dst = P.pop[(n + 1) & 1];
+    // the new populations, through a buffer resource: non-temporal where the
+    // step streams more than the Infinity Cache holds (a uniform choice; the
+    // cache policy is an immediate of each store, so the two stay distinct)
+    const bool nt = P.stream_out != 0;
+    const PopBuf db = pop_buf<STORE>(P, dst);
+    auto store = [&](int q, long long i, float v) {
+        const int off = pop_off<STORE>((int)i);
+        if (nt)
+            pop_st<STORE, true>(P, db, q, off, v);
+        else
+            pop_st<STORE, false>(P, db, q, off, v);
+    };
     const int H = P.u_hmax;
     float2 *pl = reinterpret_cast<float2 *>(u_lds);                                  // [NPL][H]
     uint16_t *el = reinterpret_cast<uint16_t *>(u_lds + (size_t)NPL * H * sizeof(float2));  // [LE][EU16]
@@ -767,8 +779,8 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         // fixed mesh, the block's own nodes: rest populations (they do not move)
         const long long own = v - n0;
         if (!MOV && own >= 0 && own < U_BLOCK) {
-            pop_store<STORE>(P, dst, 0, v, f[0]);
-            pop_store<STORE>(P, dst, Q, v, g[0]);
+            store(0, v, f[0]);
+            store(Q, v, g[0]);
             rest[own] = make_float2(pop_round<STORE>(P, 0, f[0]), pop_round<STORE>(P, Q, g[0]));
         }
     }
@@ -794,8 +806,8 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
         const int le0 = P.dep_le[dep_plane(k) * P.n_nodes + idx];
         if (k == 0 && le0 == U_SELF) {
             const float2 own = plk[self];
-            pop_store<STORE>(P, dst, 0, idx, own.x);
-            pop_store<STORE>(P, dst, Q, idx, own.y);
+            store(0, idx, own.x);
+            store(Q, idx, own.y);
             f[0] = pop_round<STORE>(P, 0, own.x);
             g[0] = pop_round<STORE>(P, Q, own.y);
             continue;
@@ -832,8 +844,8 @@ __global__ void __launch_bounds__(U_BLOCK) k_u_collide_stream_blk(const Inst *__
                 vf += w * (fg.x - fg0.x);
                 vg += w * (fg.y - fg0.y);
             }
-        pop_store<STORE>(P, dst, k, idx, vf);
-        pop_store<STORE>(P, dst, Q + k, idx, vg);
+        store(k, idx, vf);
+        store(Q + k, idx, vg);
         f[k] = pop_round<STORE>(P, k, vf);
         g[k] = pop_round<STORE>(P, Q + k, vg);
     }
