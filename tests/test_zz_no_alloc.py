@@ -55,14 +55,17 @@ def test_noalloc_step_equals_step_on_two_calls_second_smaller():
     assert np.max(np.abs(a2[2][:, 2])) > 0
 
 
-def test_noalloc_step_equals_the_split_step():
-    """An O-grid whose step streams more than the Infinity Cache (1024 x 2048
-    nodes, 64 x 8 tiles): fsi_step runs its interior tiles on a second stream
-    beside the near-boundary tiles and the boundary kernels; the
-    no-allocation step launches every tile at once.  The two must agree
-    exactly."""
-    c = synth.large_heave_case(n_r=1024, n_theta=2048, D=800.0)
-    assert c.mesh.ni * c.mesh.nj * 160 > 256 << 20
+@pytest.mark.parametrize("storage,n_r,n_theta", [(0, 1024, 2048), (1, 2048, 2048)])
+def test_noalloc_step_equals_the_split_step(storage, n_r, n_theta):
+    """An O-grid whose step streams more than the Infinity Cache (FP32: 1024 x
+    2048 nodes; FP16 shifted storage, half the bytes per node: 2048 x 2048),
+    on 64 x 8 tiles with non-temporal population stores: fsi_step runs its
+    interior tiles on a second stream beside the near-boundary tiles and the
+    boundary kernels; the no-allocation step launches every tile at once.
+    The two must agree exactly."""
+    c = synth.large_heave_case(n_r=n_r, n_theta=n_theta, D=800.0 * n_theta / 2048, storage=storage)
+    per_node = 2 * 18 * (4 if storage == 0 else 2) + 16
+    assert c.mesh.ni * c.mesh.nj * per_node > 256 << 20
     r, a = run_both(c, 24)
     check_equal(r, a)
     assert np.max(np.abs(a[2][:, 2])) > 0
