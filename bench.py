@@ -175,6 +175,26 @@ def unstructured_cylinder_case(n_theta: int, D: float, storage: int, heave_D: fl
                 ux[None], uy[None], T[None])
 
 
+def copy_ceiling_gbs(reps: int = 5) -> dict:
+    """A measured bandwidth ceiling beside the vendor peak: a plain 1 GiB
+    device-to-device copy (torch), bytes read plus bytes written per second."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBs": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1),
+            "how": "1 GiB device-to-device copy (torch copy_), read + write bytes per second"}
+
+
 def time_gpu(case, steps: int, warmup: int, kernel_reps: int = 20, subiterations: int = 1,
              relaxation: float = 1.0):
     import torch
@@ -473,6 +493,7 @@ def main():
     k1_ms = float(kms[0])
     achieved = bpn * N / (k1_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, storage, N)
+    copy_ceiling = copy_ceiling_gbs()
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -510,6 +531,8 @@ def main():
             "algorithmic_bytes_per_node": bpn,
             "valu_issue": (None if args.workload.startswith("unstructured")
                            else measured_valu(args.workload, storage, N, k1_ms)),
+            "copy_ceiling": copy_ceiling,
+            "frac_of_copy": round(achieved / copy_ceiling["GBs"], 4),
         },
     }
     if not args.no_variants and args.workload == "cylinder_heave_2048x4096" and storage == 0:
@@ -565,6 +588,7 @@ def main_batched(args, storage: int):
     bpn = algorithmic_bytes_per_node(storage)
     k1_ms = float(kms[0])
     achieved = bpn * N / (k1_ms * 1e-3) / 1e9
+    copy_ceiling = copy_ceiling_gbs()
     out = {
         "metric": METRIC,
         "value": round(N * args.steps / (total_ms * 1e-3) / 1e6, 1),
@@ -599,6 +623,8 @@ def main_batched(args, storage: int):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
             "algorithmic_bytes_per_node": bpn,
+            "copy_ceiling": copy_ceiling,
+            "frac_of_copy": round(achieved / copy_ceiling["GBs"], 4),
         },
     }
     print(json.dumps(out), flush=True)
